@@ -1,0 +1,207 @@
+"""ctypes binding of the plain-C FP64 oracle (rom_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: argument marshalling for numpy arrays; all arithmetic is in C.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rom_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.c_int64
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build() -> str:
+    """Compile rom_oracle.c with gcc: strict IEEE FP64 (no contraction into FMA)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-std=c99", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    lib.orc_nonlinear_dense.argtypes = [_i64, _d, _d, _d]
+    lib.orc_nonlinear_dense_rows.argtypes = [_i64, _d, _d, _i64, ctypes.POINTER(_i64), _d]
+    lib.orc_nonlinear_cp.argtypes = [_i64, _i64, _d, _d, _d, _d, _d, _d]
+    lib.orc_reconstruct.argtypes = [_i64, _i64, _d, _d, _d, _d, _d]
+    lib.orc_cholesky.argtypes = [_i64, _d, _d]
+    lib.orc_cholesky.restype = ctypes.c_int
+    lib.orc_chol_solve.argtypes = [_i64, _d, _d, _d]
+    lib.orc_energy.argtypes = [_i64, _d]
+    lib.orc_energy.restype = ctypes.c_double
+    lib.orc_run.argtypes = [_i64, ctypes.c_double, ctypes.c_double, _d, _d, _i64, _d, _d, _d,
+                            _d, _i64, _d, _d, _i64, _d, _d, ctypes.POINTER(_i64)]
+    lib.orc_run.restype = ctypes.c_int
+    lib.orc_round_f32.argtypes = [_i64, _d, _d]
+    lib.orc_round_bf16.argtypes = [_i64, _d, _d]
+    lib.orc_split_bf16x3.argtypes = [_i64, _d, _d, _d]
+    _lib = lib
+    return lib
+
+
+def _c(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return ctypes.cast(None, _d)
+    return a.ctypes.data_as(_d)
+
+
+def nonlinear_dense(C, u) -> np.ndarray:
+    """y = C(u)u for u of shape [N] or [B][N]."""
+    lib = _load()
+    C = _c(C)
+    u = _c(u)
+    N = C.shape[0]
+    uu = u.reshape(-1, N)
+    y = np.empty_like(uu)
+    for b in range(uu.shape[0]):
+        ub = np.ascontiguousarray(uu[b])
+        yb = np.empty(N)
+        lib.orc_nonlinear_dense(N, _p(C), _p(ub), _p(yb))
+        y[b] = yb
+    return y.reshape(u.shape)
+
+
+def nonlinear_dense_rows(C, u, rows) -> np.ndarray:
+    """y_i for i in rows (u of shape [N])."""
+    lib = _load()
+    C = np.asarray(C)
+    if not (C.dtype == np.float64 and C.flags.c_contiguous):
+        C = _c(C)
+    u = _c(u)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty(rows.shape[0])
+    lib.orc_nonlinear_dense_rows(C.shape[0], _p(C), _p(u), rows.shape[0],
+                                 rows.ctypes.data_as(ctypes.POINTER(_i64)), _p(out))
+    return out
+
+
+def nonlinear_cp(lam, Af, Bf, Cf, u) -> np.ndarray:
+    lib = _load()
+    lam, Af, Bf, Cf, u = map(_c, (lam, Af, Bf, Cf, u))
+    N, R = Af.shape
+    uu = u.reshape(-1, N)
+    y = np.empty_like(uu)
+    for b in range(uu.shape[0]):
+        ub = np.ascontiguousarray(uu[b])
+        yb = np.empty(N)
+        lib.orc_nonlinear_cp(N, R, _p(lam), _p(Af), _p(Bf), _p(Cf), _p(ub), _p(yb))
+        y[b] = yb
+    return y.reshape(u.shape)
+
+
+def reconstruct(lam, Af, Bf, Cf) -> np.ndarray:
+    lib = _load()
+    lam, Af, Bf, Cf = map(_c, (lam, Af, Bf, Cf))
+    N, R = Af.shape
+    T = np.empty((N, N, N))
+    lib.orc_reconstruct(N, R, _p(lam), _p(Af), _p(Bf), _p(Cf), _p(T))
+    return T
+
+
+def cholesky(H):
+    lib = _load()
+    H = _c(H)
+    L = np.empty_like(H)
+    rc = lib.orc_cholesky(H.shape[0], _p(H), _p(L))
+    if rc != 0:
+        raise np.linalg.LinAlgError("matrix is not positive definite")
+    return L
+
+
+def chol_solve(L, b):
+    lib = _load()
+    L = _c(L)
+    b = _c(b)
+    x = np.empty_like(b)
+    lib.orc_chol_solve(L.shape[0], _p(L), _p(b), _p(x))
+    return x
+
+
+def energy(u) -> float:
+    lib = _load()
+    u = _c(u)
+    return float(lib.orc_energy(u.shape[0], _p(u)))
+
+
+def run(N, nu, dt, A, nsteps, *, u0=None, C=None, lam=None, Af=None, Bf=None, Cf=None,
+        step0: int = 0, uh=None, yh=None, traj: bool = False) -> dict:
+    """Integrate one trajectory for nsteps BDF3/EXT3 steps (with the BDF1/BDF2 ramp).
+
+    Either u0 (start at step 0) or the history (step0, uh [3][N], yh [2][N]) is given.
+    Returns dict(u_hist, y_hist, step, E [nsteps+1], traj [nsteps+1][N] or None,
+    status, first_bad).
+    """
+    lib = _load()
+    A = _c(A)
+    if uh is None:
+        uh = np.zeros((3, N))
+        uh[0] = _c(u0).reshape(N)
+        yh = np.zeros((2, N))
+    uh = _c(uh).copy()
+    yh = _c(yh).copy()
+    E = np.empty(nsteps + 1)
+    T = np.empty((nsteps + 1, N)) if traj else None
+    fb = _i64(-1)
+    if C is not None:
+        C = np.asarray(C)
+        if not (C.dtype == np.float64 and C.flags.c_contiguous):
+            C = _c(C)
+        R = 0
+        args = (_p(C), 0, _p(None), _p(None), _p(None), _p(None))
+    else:
+        lam, Af, Bf, Cf = map(_c, (lam, Af, Bf, Cf))
+        R = Af.shape[1]
+        args = (_p(None), R, _p(lam), _p(Af), _p(Bf), _p(Cf))
+    st = lib.orc_run(N, float(nu), float(dt), _p(A), *args, int(step0), _p(uh), _p(yh),
+                     int(nsteps), _p(E), _p(T), ctypes.byref(fb))
+    return dict(u_hist=uh, y_hist=yh, step=step0 + nsteps, E=E, traj=T, status=int(st),
+                first_bad=int(fb.value))
+
+
+def round_f32(x) -> np.ndarray:
+    lib = _load()
+    x = _c(x)
+    out = np.empty_like(x)
+    lib.orc_round_f32(x.size, _p(x), _p(out))
+    return out
+
+
+def round_bf16(x) -> np.ndarray:
+    lib = _load()
+    x = _c(x)
+    out = np.empty_like(x)
+    lib.orc_round_bf16(x.size, _p(x), _p(out))
+    return out
+
+
+def split_bf16x3(x):
+    lib = _load()
+    x = _c(x)
+    hi = np.empty_like(x)
+    lo = np.empty_like(x)
+    lib.orc_split_bf16x3(x.size, _p(x), _p(hi), _p(lo))
+    return hi, lo

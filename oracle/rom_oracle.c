@@ -1,0 +1,344 @@
+/*
+ * rom_oracle.c -- plain FP64 CPU oracle for the online stage of a Galerkin
+ * reduced-order model whose advection tensor may be given in CP form
+ * (arXiv 2311.03694, "Accelerating Galerkin Reduced-Order Models for Turbulent
+ * Flows with Tensor Decomposition").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this file's library.  The product path never links,
+ * calls or includes it, and it shares no code with the HIP sources.
+ *
+ * Every routine is a single-threaded loop nest written in the order of the
+ * definition it cites, in IEEE FP64 (built with -ffp-contract=off, no fast-math).
+ *
+ * Storage (row-major, 0-based):
+ *   C[i][j][k]  = the paper's C_{i k j} with output row i; the pair (j, k) is the pair
+ *                 of advecting/advected coefficients.  The contraction is symmetric in
+ *                 j and k, so y_i = sum_j sum_k C[i][j][k] u_j u_k  (Sec. 2, eq. Cu).
+ *   Af,Bf,Cf    = [N][R] CP factors for tensor positions 1, 2, 3; lam = [R] weights.
+ *   A           = [N][N] reduced stiffness; the mass matrix is the identity.
+ *
+ * Parity status: every function below is pinned by a CPU test (closed forms,
+ * invariants, brute force, library routines); none is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ contractions */
+
+/* Dense advection term of the G-ROM (Sec. 2, eq. Cu and the C(u)u term of eq. nse_d1):
+ *   y_i = sum_{j} u_j * ( sum_{k} C[i][j][k] * u_k ),  2 N^3 flops. */
+void orc_nonlinear_dense(int64_t N, const double *C, const double *u, double *y)
+{
+    for (int64_t i = 0; i < N; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            const double *row = C + (i * N + j) * N;
+            double t = 0.0;
+            for (int64_t k = 0; k < N; ++k)
+                t += row[k] * u[k];
+            s += u[j] * t;
+        }
+        y[i] = s;
+    }
+}
+
+/* The same definition for a chosen subset of output rows (used at sizes where the
+ * full N^3 contraction is too slow for a test): y_out[q] = y_{rows[q]}. */
+void orc_nonlinear_dense_rows(int64_t N, const double *C, const double *u,
+                              int64_t nrows, const int64_t *rows, double *y_out)
+{
+    for (int64_t q = 0; q < nrows; ++q) {
+        int64_t i = rows[q];
+        double s = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            const double *row = C + (i * N + j) * N;
+            double t = 0.0;
+            for (int64_t k = 0; k < N; ++k)
+                t += row[k] * u[k];
+            s += u[j] * t;
+        }
+        y_out[q] = s;
+    }
+}
+
+/* CP contraction (Sec. 3.1, eq. tc_ap), with the weight vector lam:
+ *   s_r = sum_k Bf[k][r] u_k,   t_r = sum_j Cf[j][r] u_j,
+ *   y_i = sum_r Af[i][r] * (lam_r * s_r * t_r).               6 N R flops. */
+void orc_nonlinear_cp(int64_t N, int64_t R, const double *lam, const double *Af,
+                      const double *Bf, const double *Cf, const double *u, double *y)
+{
+    double *s = (double *)malloc(sizeof(double) * (size_t)(R > 0 ? R : 1));
+    double *t = (double *)malloc(sizeof(double) * (size_t)(R > 0 ? R : 1));
+    for (int64_t r = 0; r < R; ++r) {
+        double sr = 0.0, tr = 0.0;
+        for (int64_t k = 0; k < N; ++k)
+            sr += Bf[k * R + r] * u[k];
+        for (int64_t j = 0; j < N; ++j)
+            tr += Cf[j * R + r] * u[j];
+        s[r] = sr;
+        t[r] = tr;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        double acc = 0.0;
+        for (int64_t r = 0; r < R; ++r)
+            acc += Af[i * R + r] * (lam[r] * s[r] * t[r]);
+        y[i] = acc;
+    }
+    free(s);
+    free(t);
+}
+
+/* Kruskal tensor (Sec. 2.2, eq. cpd, with weights):
+ *   T[i][j][k] = sum_r lam_r Af[i][r] Bf[j][r] Cf[k][r]. */
+void orc_reconstruct(int64_t N, int64_t R, const double *lam, const double *Af,
+                     const double *Bf, const double *Cf, double *T)
+{
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < N; ++j)
+            for (int64_t k = 0; k < N; ++k) {
+                double acc = 0.0;
+                for (int64_t r = 0; r < R; ++r)
+                    acc += lam[r] * Af[i * R + r] * Bf[j * R + r] * Cf[k * R + r];
+                T[(i * N + j) * N + k] = acc;
+            }
+}
+
+/* ------------------------------------------------------------------ linear algebra */
+
+/* Cholesky factor H = L L^T of a symmetric positive definite matrix (textbook
+ * column-by-column form).  L is written lower-triangular, zeros above.
+ * Returns 0, or -1 if a pivot is not positive. */
+int orc_cholesky(int64_t N, const double *H, double *L)
+{
+    memset(L, 0, sizeof(double) * (size_t)(N * N));
+    for (int64_t j = 0; j < N; ++j) {
+        double d = H[j * N + j];
+        for (int64_t m = 0; m < j; ++m)
+            d -= L[j * N + m] * L[j * N + m];
+        if (!(d > 0.0))
+            return -1;
+        double ljj = sqrt(d);
+        L[j * N + j] = ljj;
+        for (int64_t i = j + 1; i < N; ++i) {
+            double v = H[i * N + j];
+            for (int64_t m = 0; m < j; ++m)
+                v -= L[i * N + m] * L[j * N + m];
+            L[i * N + j] = v / ljj;
+        }
+    }
+    return 0;
+}
+
+/* Solve L L^T x = b: forward substitution, then back substitution. */
+void orc_chol_solve(int64_t N, const double *L, const double *b, double *x)
+{
+    double *z = (double *)malloc(sizeof(double) * (size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        double v = b[i];
+        for (int64_t m = 0; m < i; ++m)
+            v -= L[i * N + m] * z[m];
+        z[i] = v / L[i * N + i];
+    }
+    for (int64_t i = N - 1; i >= 0; --i) {
+        double v = z[i];
+        for (int64_t m = i + 1; m < N; ++m)
+            v -= L[m * N + i] * x[m];
+        x[i] = v / L[i * N + i];
+    }
+    free(z);
+}
+
+/* ------------------------------------------------------------------ energy */
+
+/* Kinetic energy of the reduced state with identity mass matrix (eq. ene_fluc,
+ * first quantity): E = 1/2 sum_i u_i^2. */
+double orc_energy(int64_t N, const double *u)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        s += u[i] * u[i];
+    return 0.5 * s;
+}
+
+/* ------------------------------------------------------------------ BDFk / EXTk */
+
+/* Coefficients of the k-th order backward difference (beta) and extrapolation
+ * (alpha) used by the semi-implicit scheme of eq. nse_d1.  beta[0] multiplies the
+ * new level on the left; beta[q], alpha[q-1] (q = 1..k) multiply level n+1-q on the
+ * right.  They follow from differentiating (BDF) and evaluating (EXT) at t^{n+1} the
+ * Lagrange polynomial through the last k (EXT) or k+1 (BDF) equispaced levels. */
+static void bdf_ext(int k, double beta[4], double alpha[3])
+{
+    memset(beta, 0, 4 * sizeof(double));
+    memset(alpha, 0, 3 * sizeof(double));
+    if (k == 1) {
+        beta[0] = 1.0;  beta[1] = -1.0;
+        alpha[0] = 1.0;
+    } else if (k == 2) {
+        beta[0] = 1.5;  beta[1] = -2.0; beta[2] = 0.5;
+        alpha[0] = 2.0; alpha[1] = -1.0;
+    } else {
+        beta[0] = 11.0 / 6.0; beta[1] = -3.0; beta[2] = 1.5; beta[3] = -1.0 / 3.0;
+        alpha[0] = 3.0; alpha[1] = -3.0; alpha[2] = 1.0;
+    }
+}
+
+/* Time integration of  du/dt = -C(u)u - nu A u  (eq. nse_ode with B = I and the
+ * zeroth-mode terms dropped) by the semi-implicit BDFk/EXTk scheme of eq. nse_d1:
+ *
+ *   (beta0/dt I + nu A) u^{n+1} = - sum_{q=1..k} alpha_q y^{n+1-q}
+ *                                 - (1/dt) sum_{q=1..k} beta_q u^{n+1-q},
+ *   y^m = C(u^m) u^m,
+ *
+ * with k = min(n+1, 3): the first step is BDF1/EXT1, the second BDF2/EXT2, then
+ * BDF3/EXT3.
+ *
+ * State (in/out): step n, uh = [u^n, u^{n-1}, u^{n-2}] ([3][N]), yh = [y^{n-1},
+ * y^{n-2}] ([2][N]); levels that do not exist yet are ignored.  The advection term is
+ * the dense contraction if C != NULL, else the CP contraction.
+ * Outputs (optional): E[0..nsteps] = energies of u^{n}..u^{n+nsteps};
+ * traj[(s)][N] = u^{n+s}.
+ * Returns 0 ok, 1 if a Helmholtz matrix is not SPD, 2 on allocation failure,
+ * 4 if a state became non-finite (first_bad = that step index, integration stops). */
+int orc_run(int64_t N, double nu, double dt, const double *A, const double *C, int64_t R,
+            const double *lam, const double *Af, const double *Bf, const double *Cf,
+            int64_t step0, double *uh, double *yh, int64_t nsteps, double *E, double *traj,
+            int64_t *first_bad)
+{
+    size_t nn = (size_t)(N * N);
+    double *L[3] = {NULL, NULL, NULL};
+    double *H = (double *)malloc(sizeof(double) * nn);
+    double *y = (double *)malloc(sizeof(double) * (size_t)N);
+    double *rhs = (double *)malloc(sizeof(double) * (size_t)N);
+    double *un = (double *)malloc(sizeof(double) * (size_t)N);
+    int status = 0;
+    if (first_bad)
+        *first_bad = -1;
+    if (!H || !y || !rhs || !un) {
+        status = 2;
+        goto done;
+    }
+    if (E)
+        E[0] = orc_energy(N, uh);
+    if (traj)
+        memcpy(traj, uh, sizeof(double) * (size_t)N);
+
+    for (int64_t s = 0; s < nsteps; ++s) {
+        int64_t n = step0 + s;
+        int k = (int)(n + 1 < 3 ? n + 1 : 3);
+        double beta[4], alpha[3];
+        bdf_ext(k, beta, alpha);
+
+        if (!L[k - 1]) {
+            L[k - 1] = (double *)malloc(sizeof(double) * nn);
+            if (!L[k - 1]) {
+                status = 2;
+                goto done;
+            }
+            for (int64_t i = 0; i < N; ++i)
+                for (int64_t j = 0; j < N; ++j)
+                    H[i * N + j] = nu * A[i * N + j] + (i == j ? beta[0] / dt : 0.0);
+            if (orc_cholesky(N, H, L[k - 1]) != 0) {
+                status = 1;
+                goto done;
+            }
+        }
+
+        /* y^n */
+        if (C)
+            orc_nonlinear_dense(N, C, uh, y);
+        else
+            orc_nonlinear_cp(N, R, lam, Af, Bf, Cf, uh, y);
+
+        /* right-hand side: levels n, n-1, n-2 are uh[0..2] and y, yh[0], yh[1] */
+        for (int64_t i = 0; i < N; ++i) {
+            const double *ylev[3] = {y, yh, yh + N};
+            double v = 0.0;
+            for (int q = 1; q <= k; ++q)
+                v -= alpha[q - 1] * ylev[q - 1][i];
+            for (int q = 1; q <= k; ++q)
+                v -= (beta[q] / dt) * uh[(size_t)(q - 1) * N + i];
+            rhs[i] = v;
+        }
+        orc_chol_solve(N, L[k - 1], rhs, un);
+
+        /* shift histories */
+        memcpy(uh + 2 * N, uh + N, sizeof(double) * (size_t)N);
+        memcpy(uh + N, uh, sizeof(double) * (size_t)N);
+        memcpy(uh, un, sizeof(double) * (size_t)N);
+        memcpy(yh + N, yh, sizeof(double) * (size_t)N);
+        memcpy(yh, y, sizeof(double) * (size_t)N);
+
+        double e = orc_energy(N, uh);
+        if (E)
+            E[s + 1] = e;
+        if (traj)
+            memcpy(traj + (size_t)(s + 1) * N, uh, sizeof(double) * (size_t)N);
+        if (!isfinite(e)) {
+            if (first_bad)
+                *first_bad = n + 1;
+            status = 4;
+            goto done;
+        }
+    }
+done:
+    for (int q = 0; q < 3; ++q)
+        free(L[q]);
+    free(H);
+    free(y);
+    free(rhs);
+    free(un);
+    return status;
+}
+
+/* ------------------------------------------------------------------ storage rounding */
+
+/* FP64 -> FP32, round to nearest even (the C conversion in the default rounding mode). */
+void orc_round_f32(int64_t n, const double *x, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = (double)(float)x[i];
+}
+
+/* FP32 -> BF16 (1 sign, 8 exponent, 7 stored fraction bits), round to nearest, ties to
+ * even, by comparing the 16 dropped bits with one half unit in the last place. */
+static float bf16_of_f32(float f)
+{
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    if ((b & 0x7f800000u) == 0x7f800000u) {            /* inf or NaN: keep, quiet NaN */
+        if (b & 0x007fffffu)
+            b |= 0x00400000u;
+        b &= 0xffff0000u;
+    } else {
+        uint32_t low = b & 0xffffu;
+        uint32_t high = b & 0xffff0000u;
+        int up = (low > 0x8000u) || (low == 0x8000u && (high & 0x10000u));
+        b = up ? high + 0x10000u : high;                  /* carry may reach inf: correct */
+    }
+    float r;
+    memcpy(&r, &b, 4);
+    return r;
+}
+
+/* FP64 -> FP32 -> BF16, each step round-to-nearest-even. */
+void orc_round_bf16(int64_t n, const double *x, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = (double)bf16_of_f32((float)x[i]);
+}
+
+/* Split into two BF16 words: hi = bf16(fp32(x)), lo = bf16(fp32(x) - hi). */
+void orc_split_bf16x3(int64_t n, const double *x, double *hi, double *lo)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float f = (float)x[i];
+        float h = bf16_of_f32(f);
+        float l = bf16_of_f32(f - h);
+        hi[i] = (double)h;
+        lo[i] = (double)l;
+    }
+}

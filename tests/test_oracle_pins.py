@@ -1,0 +1,291 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: hand-worked exact
+rationals (tests/golden), closed forms, invariants, library routines, or a
+convergence order.  Together they catch a dropped term, a wrong sign or index, a
+transposed operand or a wrong scheme coefficient anywhere in rom_oracle.c.
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import romsynth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    vals = {}
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = (s.strip() for s in line.split("="))
+            vals[k] = Fraction(v)
+    return vals
+
+
+# ---------------------------------------------------------------- contraction
+
+def test_worked_example_contraction(orc):
+    g = _golden("n2_worked_example.txt")
+    C = np.zeros((2, 2, 2))
+    C[0, 0, 1] = float(g["a"])
+    C[0, 1, 1] = float(g["b"])
+    C[1, 0, 0] = -float(g["a"])
+    C[1, 1, 0] = -float(g["b"])
+    u = np.array([float(g["u0_0"]), float(g["u0_1"])])
+    y = orc.nonlinear_dense(C, u)
+    assert y[0] == float(g["y0_0"]) and y[1] == float(g["y0_1"])
+
+
+def test_unit_tensor_index_positions(orc):
+    """A tensor with one non-zero entry selects exactly one product u_j u_k into row i.
+    This fixes which position is the output and which two are contracted."""
+    N = 4
+    u = np.array([1.0, 2.0, 3.0, 5.0])
+    for (i, j, k) in [(0, 1, 2), (3, 0, 0), (2, 3, 1), (1, 2, 3)]:
+        C = np.zeros((N, N, N))
+        C[i, j, k] = 1.0
+        y = orc.nonlinear_dense(C, u)
+        expect = np.zeros(N)
+        expect[i] = u[j] * u[k]
+        assert np.array_equal(y, expect)
+
+
+def test_unit_factors_cp_positions(orc):
+    """Rank-1 CP with unit vectors: only row i of y is non-zero, equal to lam*u_j*u_k,
+    where i, j, k index the non-zeros of the first, second and third factor."""
+    N = 5
+    u = np.array([1.0, -2.0, 3.0, 0.5, 7.0])
+    for (i, j, k) in [(0, 1, 2), (4, 3, 3), (2, 0, 4)]:
+        Af = np.zeros((N, 1)); Af[i, 0] = 1.0
+        Bf = np.zeros((N, 1)); Bf[j, 0] = 1.0
+        Cf = np.zeros((N, 1)); Cf[k, 0] = 1.0
+        lam = np.array([0.25])
+        y = orc.nonlinear_cp(lam, Af, Bf, Cf, u)
+        expect = np.zeros(N)
+        expect[i] = 0.25 * u[j] * u[k]
+        assert np.array_equal(y, expect)
+        T = orc.reconstruct(lam, Af, Bf, Cf)
+        Texp = np.zeros((N, N, N))
+        Texp[i, j, k] = 0.25
+        assert np.array_equal(T, Texp)
+
+
+def test_energy_identity_skew(orc):
+    """Skew symmetry in positions 1 and 3 (Sec. 3.2) makes u . C(u)u vanish."""
+    for N, seed in [(16, 0), (33, 1)]:
+        C = romsynth.dense_rough(N, seed, cfg=7)
+        u = romsynth.initial_u(N, [seed], cfg=7)[0]
+        y = orc.nonlinear_dense(C, u)
+        scale = np.einsum("ijk,i,j,k->", np.abs(C), np.abs(u), np.abs(u), np.abs(u))
+        assert abs(u @ y) <= 1e-14 * scale
+        # a non-skew tensor does not satisfy it (the check has teeth)
+        y2 = orc.nonlinear_dense(C + np.abs(C), u)
+        assert abs(u @ y2) > 1e-6 * scale
+
+
+def test_homogeneity_and_symmetry_in_pair(orc):
+    N = 12
+    rng = np.random.default_rng(3)
+    C = rng.standard_normal((N, N, N))
+    u = rng.standard_normal(N)
+    y = orc.nonlinear_dense(C, u)
+    assert np.array_equal(orc.nonlinear_dense(C, 2.0 * u), 4.0 * y)
+    # positions 2 and 3 enter symmetrically
+    y_sw = orc.nonlinear_dense(np.ascontiguousarray(C.transpose(0, 2, 1)), u)
+    assert np.allclose(y, y_sw, rtol=1e-13, atol=1e-13)
+
+
+def test_cp_equals_dense_of_reconstruction(orc):
+    rng = np.random.default_rng(11)
+    N, R = 9, 7
+    lam = rng.standard_normal(R)
+    Af, Bf, Cf = (rng.standard_normal((N, R)) for _ in range(3))
+    u = rng.standard_normal(N)
+    T = orc.reconstruct(lam, Af, Bf, Cf)
+    y_cp = orc.nonlinear_cp(lam, Af, Bf, Cf, u)
+    y_d = orc.nonlinear_dense(T, u)
+    assert np.allclose(y_cp, y_d, rtol=1e-12, atol=1e-12 * np.abs(y_d).max())
+
+
+def test_skew_paired_factors_give_skew_tensor(orc):
+    """Sec. 3.3: with A(1) = [A1 A2], A(2) = [B1 B1], A(3) = [A2 -A1] the Kruskal
+    tensor is skew in positions 1 and 3; the generator's interleaved pairs are that
+    structure up to a column permutation."""
+    lam, Af, Bf, Cf = romsynth.skew_cp_factors(7, 4, seed=2, cfg=9)
+    T = orc.reconstruct(lam, Af, Bf, Cf)
+    assert np.allclose(T, -T.transpose(2, 1, 0), rtol=0, atol=1e-15)
+    # and the generator's vectorised dense build agrees with the oracle's loops
+    D = romsynth.dense_from_skew_cp(7, 4, eps=0.0, seed=2, cfg=9)
+    assert np.allclose(D, T, rtol=0, atol=1e-14)
+
+
+def test_rows_variant_matches_full(orc):
+    C = romsynth.dense_rough(10, 4, cfg=5)
+    u = romsynth.initial_u(10, [4], cfg=5)[0]
+    y = orc.nonlinear_dense(C, u)
+    rows = np.array([0, 3, 9, 3])
+    assert np.array_equal(orc.nonlinear_dense_rows(C, u, rows), y[rows])
+
+
+# ---------------------------------------------------------------- linear algebra, energy
+
+def test_cholesky_against_numpy(orc):
+    rng = np.random.default_rng(5)
+    G = rng.standard_normal((20, 20))
+    H = G @ G.T + 20 * np.eye(20)
+    L = orc.cholesky(H)
+    assert np.allclose(L, np.linalg.cholesky(H), rtol=1e-13, atol=1e-13)
+    b = rng.standard_normal(20)
+    assert np.allclose(orc.chol_solve(L, b), np.linalg.solve(H, b), rtol=1e-12, atol=1e-13)
+    with pytest.raises(np.linalg.LinAlgError):
+        orc.cholesky(-H)
+
+
+def test_energy_closed_form(orc):
+    assert orc.energy(np.array([3.0, 4.0])) == 12.5
+
+
+# ---------------------------------------------------------------- time stepping
+
+def test_worked_example_two_steps(orc):
+    g = _golden("n2_worked_example.txt")
+    C = np.zeros((2, 2, 2))
+    C[0, 0, 1] = float(g["a"]); C[0, 1, 1] = float(g["b"])
+    C[1, 0, 0] = -float(g["a"]); C[1, 1, 0] = -float(g["b"])
+    A = np.diag([float(g["A_0"]), float(g["A_1"])])
+    u0 = np.array([float(g["u0_0"]), float(g["u0_1"])])
+    r = orc.run(2, float(g["nu"]), float(g["dt"]), A, 2, u0=u0, C=C, traj=True)
+    assert r["status"] == 0
+    T = r["traj"]
+    for n, name in [(1, "u1"), (2, "u2")]:
+        for i in range(2):
+            assert T[n, i] == pytest.approx(float(g[f"{name}_{i}"]), rel=1e-15, abs=0)
+    for n in range(3):
+        assert r["E"][n] == pytest.approx(float(g[f"E{n}"]), rel=1e-15)
+    # history bookkeeping: y_hist = (y^1, y^0)
+    assert r["y_hist"][0][0] == pytest.approx(float(g["y1_0"]), rel=1e-15)
+    assert r["y_hist"][0][1] == pytest.approx(float(g["y1_1"]), rel=1e-15)
+    assert r["y_hist"][1][0] == float(g["y0_0"])
+
+
+def _closed_form_modes(mu, nu, dt, z0, nsteps):
+    """Linear test equation z' = -nu*mu*z under BDFk with the 1,2,3 ramp.
+
+    For n >= 2 each level obeys (11/6 + h) z^{n+1} = 3 z^n - 3/2 z^{n-1} + 1/3 z^{n-2}
+    (h = dt*nu*mu), whose solution is sum_q c_q xi_q^n with xi_q the roots of the
+    characteristic cubic; z^1 = z^0/(1+h) and z^2 = (2 z^1 - z^0/2)/(3/2+h) start it."""
+    h = dt * nu * mu
+    z1 = z0 / (1 + h)
+    z2 = (2 * z1 - 0.5 * z0) / (1.5 + h)
+    xi = np.roots([11.0 / 6.0 + h, -3.0, 1.5, -1.0 / 3.0])
+    V = np.array([[x ** n for x in xi] for n in range(3)], dtype=complex)
+    c = np.linalg.solve(V, np.array([z0, z1, z2], dtype=complex))
+    n = np.arange(nsteps + 1)
+    return np.real(sum(c[q] * xi[q] ** n for q in range(3)))
+
+
+def test_linear_closed_form_diag(orc):
+    N, nu, dt, steps = 6, 0.7, 0.01, 60
+    A = romsynth.stiffness_diag(N)
+    u0 = romsynth.initial_u(N, [1], cfg=8)[0]
+    r = orc.run(N, nu, dt, A, steps, u0=u0, C=np.zeros((N, N, N)), traj=True)
+    mu = np.diag(A)
+    for i in range(N):
+        z = _closed_form_modes(mu[i], nu, dt, u0[i], steps)
+        assert np.allclose(r["traj"][:, i], z, rtol=1e-11, atol=1e-14)
+
+
+def test_linear_closed_form_spd(orc):
+    N, nu, dt, steps = 8, 0.3, 0.02, 40
+    A = romsynth.stiffness_spd(N, seed=1, cfg=8, norm=2.0)
+    u0 = romsynth.initial_u(N, [2], cfg=8)[0]
+    r = orc.run(N, nu, dt, A, steps, u0=u0, C=np.zeros((N, N, N)), traj=True)
+    w, Q = np.linalg.eigh(A)
+    z0 = Q.T @ u0
+    Z = np.stack([_closed_form_modes(w[q], nu, dt, z0[q], steps) for q in range(N)], axis=1)
+    assert np.allclose(r["traj"], Z @ Q.T, rtol=1e-10, atol=1e-13)
+
+
+def test_inviscid_linear_is_constant(orc):
+    """nu = 0, C = 0: the BDF weights sum to zero, so every level equals u^0."""
+    N = 5
+    u0 = romsynth.initial_u(N, [3], cfg=8)[0]
+    r = orc.run(N, 0.0, 0.1, romsynth.stiffness_diag(N), 25, u0=u0, C=np.zeros((N, N, N)),
+                traj=True)
+    assert np.allclose(r["traj"], u0[None, :], rtol=1e-14, atol=0)
+
+
+def _logistic_exact(t, u0, a, c):
+    # u' = -c u^2 - a u  (Bernoulli):  1/u = (1/u0 + c/a) e^{a t} - c/a
+    return 1.0 / ((1.0 / u0 + c / a) * np.exp(a * t) - c / a)
+
+
+def test_third_order_convergence(orc):
+    """N = 1: y = c u^2, A = [a].  Started from exact levels, BDF3/EXT3 must converge
+    with order 3; a wrong BDF or EXT weight lowers the order or breaks consistency."""
+    a, c, u0, T = 1.0, 1.0, 0.5, 1.0
+    errs = []
+    for n in (50, 100, 200):
+        dt = T / n
+        ex = [_logistic_exact(m * dt, u0, a, c) for m in range(3)]
+        uh = np.array([[ex[2]], [ex[1]], [ex[0]]])
+        yh = np.array([[c * ex[1] ** 2], [c * ex[0] ** 2]])
+        r = orc.run(1, 1.0, dt, np.array([[a]]), n - 2, C=np.array([[[c]]]), step0=2,
+                    uh=uh, yh=yh)
+        errs.append(abs(r["u_hist"][0][0] - _logistic_exact(T, u0, a, c)))
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(7.0 < q < 9.0 for q in ratios), (errs, ratios)
+
+
+def test_nonfinite_and_not_spd_status(orc):
+    N = 3
+    C = np.zeros((N, N, N))
+    u0 = np.array([1.0, np.nan, 0.0])
+    r = orc.run(N, 1.0, 0.1, np.eye(N), 5, u0=u0, C=C)
+    assert r["status"] == 4 and r["first_bad"] == 1
+    r = orc.run(N, 1.0, 0.1, -100.0 * np.eye(N), 5, u0=np.ones(N), C=C)
+    assert r["status"] == 1
+
+
+def test_config0_energy_decays(orc):
+    """Config 0 (N=32): with skew C and SPD A the continuous energy decays as
+    dE/dt = -nu u.A u; the discrete run follows it monotonically."""
+    p = romsynth.make_config(0)
+    r = orc.run(p.N, p.nu, p.dt, p.A, 200, u0=p.u0[0], C=p.C)
+    assert r["status"] == 0
+    assert np.all(np.diff(r["E"]) < 0)
+
+
+# ---------------------------------------------------------------- storage rounding
+
+def test_bf16_rounding_special_values(orc):
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -8 + 2.0 ** -20,
+                  -(1.0 + 3 * 2.0 ** -8), 3.4e38, np.inf, 0.0])
+    expect = np.array([1.0, 1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7, -(1.0 + 2.0 ** -6), np.inf,
+                       np.inf, 0.0])
+    assert np.array_equal(orc.round_bf16(x), expect)
+    assert np.isnan(orc.round_bf16(np.array([np.nan]))[0])
+
+
+def test_bf16_rounding_matches_torch(orc):
+    import torch
+    x = np.random.default_rng(0).standard_normal(100000) * 10.0 ** np.random.default_rng(1).uniform(-20, 20, 100000)
+    ref = torch.from_numpy(x).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(orc.round_bf16(x), ref)
+    ref32 = torch.from_numpy(x).to(torch.float32).to(torch.float64).numpy()
+    assert np.array_equal(orc.round_f32(x), ref32)
+
+
+def test_bf16x3_split(orc):
+    x = np.random.default_rng(2).standard_normal(10000)
+    hi, lo = orc.split_bf16x3(x)
+    assert np.array_equal(hi, orc.round_bf16(x))
+    x32 = orc.round_f32(x)
+    assert np.all(np.abs(x32 - hi - lo) <= 2.0 ** -16 * np.abs(x32))
+    assert np.array_equal(orc.round_bf16(lo), lo)
