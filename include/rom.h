@@ -1,0 +1,159 @@
+/*
+ * rom.h -- C ABI of librom.so: the online stage of a Galerkin reduced-order model
+ * (ROM) on one AMD Instinct MI355X (gfx950), with the advection tensor either dense
+ * (the standard G-ROM) or in CP form (the CPD-ROM), following arXiv 2311.03694.
+ *
+ * The model (Sec. 2, eq. nse_ode, identity mass matrix, core tensor without the
+ * zeroth mode) is
+ *     du/dt = -C(u)u - nu A u,   [C(u)u]_i = sum_{j,k} C[i][j][k] u_j u_k,
+ * integrated by the semi-implicit BDFk/EXTk scheme of eq. nse_d1: the viscous term is
+ * implicit, the advection term is extrapolated, k = 1, 2 for the first two steps and
+ * k = 3 afterwards.  In CP form (Sec. 3.1, eqs. approx_tensor and tc_ap)
+ *     C[i][j][k] ~ sum_r lam_r Af[i][r] Bf[j][r] Cf[k][r],
+ *     C(u)u      = Af (lam .* (Bf^T u) .* (Cf^T u)).
+ *
+ * Conventions for every call:
+ *  - Host arrays are FP64, row-major, 0-based; the library deep-copies what it keeps,
+ *    so the caller may free its buffers after the call returns.
+ *  - Device arrays named *_dev are caller-owned device memory (e.g. torch tensors);
+ *    the library reads/writes them on the context's stream and never frees them.
+ *  - Work is asynchronous on the context's stream unless a call says it synchronizes.
+ *  - No call aborts or throws; each returns a rom_status and, on failure, leaves a
+ *    message for rom_last_error() (thread-local, valid until the next call on the
+ *    same thread).
+ *  - Contexts and states are independent; one context must not be used from two
+ *    threads at once.
+ */
+#ifndef ROM_H
+#define ROM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rom_ctx_s *rom_ctx;     /* device operators, Helmholtz inverses, kernels  */
+typedef struct rom_state_s *rom_state; /* batch of trajectories: FP64 histories, energy  */
+
+typedef enum {
+    ROM_OK = 0,
+    ROM_E_INVALID = 1,     /* bad argument, or a Helmholtz matrix that is not SPD        */
+    ROM_E_NOMEM = 2,       /* device or host allocation failed                           */
+    ROM_E_DEVICE = 3,      /* a HIP runtime call failed                                  */
+    ROM_E_NONFINITE = 4,   /* a trajectory produced Inf/NaN (Sec. 4.3's unstable ROMs)   */
+    ROM_E_UNSUPPORTED = 5  /* valid request this build does not implement                */
+} rom_status;
+
+/* Arithmetic of the advection contraction.  The state update, the Helmholtz solve and
+ * the energy are always FP64.
+ *   ROM_FP64   : FP64 operator, FP64 arithmetic.
+ *   ROM_FP32   : FP32 operator and coefficients, FP32 accumulation.
+ *   ROM_BF16   : BF16 operator and BF16 coefficients (round to nearest even from FP32),
+ *                exact products, FP32 accumulation.
+ *   ROM_BF16X3 : operator and coefficients split x = hi + lo into two BF16 words;
+ *                products hi*hi + hi*lo + lo*hi, FP32 accumulation. */
+typedef enum { ROM_FP64 = 0, ROM_FP32 = 1, ROM_BF16 = 2, ROM_BF16X3 = 3 } rom_dtype;
+
+/* Problem description handed to rom_create (Sec. 2, eqs. nse_ode / nse_d1).
+ *   N         number of modes, 1 <= N.
+ *   nu        viscosity, the paper's 1/Re (>= 0).
+ *   dt        time step (> 0).
+ *   A         host [N][N] symmetric stiffness; nu*A + (beta0/dt)*I must be SPD for
+ *             beta0 in {1, 3/2, 11/6}.  A diagonal A is detected and solved by division.
+ *   C         host [N][N][N] dense advection tensor, C[i][j][k] multiplies u_j*u_k in
+ *             row i; or NULL to use the CP factors below.
+ *   R         CP rank (columns), >= 1 when C is NULL.
+ *   lambda    host [R] weights; Af, Bf, Cf host [N][R] factors of tensor positions 1,2,3.
+ *   dtype     rom_dtype of the contraction.
+ *   max_batch largest batch a state of this context may hold (>= 1).
+ *   stream    hipStream_t for all work of this context; NULL = the null stream. */
+typedef struct rom_desc {
+    int32_t N;
+    int32_t R;
+    double nu;
+    double dt;
+    const double *A;
+    const double *C;
+    const double *lambda;
+    const double *Af;
+    const double *Bf;
+    const double *Cf;
+    int32_t dtype;
+    int32_t max_batch;
+    void *stream;
+} rom_desc;
+
+/* Stage the operators on the device (a conversion to the contraction dtype), form the
+ * three FP64 Helmholtz inverses (one Cholesky factorisation and triangular solves per
+ * BDF order, on the device) and size the workspaces.  Synchronizes.
+ * Errors: ROM_E_INVALID (sizes, nu < 0, dt <= 0, missing operator, non-SPD Helmholtz
+ * matrix), ROM_E_NOMEM, ROM_E_DEVICE. */
+rom_status rom_create(const rom_desc *d, rom_ctx *out);
+void rom_destroy(rom_ctx ctx);
+
+/* y = C(u)u for `batch` coefficient vectors (Sec. 2, eq. Cu; CP form: eq. tc_ap).
+ * u_dev, y_dev: device FP64 [batch][N], caller-owned; 1 <= batch <= max_batch.
+ * The contraction runs in the context's dtype; y is returned in FP64.  Asynchronous. */
+rom_status rom_nonlinear(rom_ctx ctx, int32_t batch, const double *u_dev, double *y_dev);
+
+/* A batch of trajectories at step 0 with initial coefficients u0_host [batch][N].
+ * Synchronizes (one upload). */
+rom_status rom_state_create(rom_ctx ctx, int32_t batch, const double *u0_host,
+                            rom_state *out);
+void rom_state_destroy(rom_state st);
+
+/* Advance every trajectory of the state by nsteps BDFk/EXTk steps (eq. nse_d1 with
+ * the 1-2-3 start-up ramp) and log the energy E = |u|^2/2 after each step.  Runs on the
+ * context's stream, in graph-captured chunks; synchronizes once at the end to read the
+ * health flag.  Returns ROM_E_NONFINITE if any trajectory became non-finite, with the
+ * first such step number in *first_bad_step (nullable; -1 if none). */
+rom_status rom_step(rom_ctx ctx, rom_state st, int64_t nsteps, int64_t *first_bad_step);
+
+/* Enqueue nsteps without the final synchronization; rom_step_sync later waits and
+ * reports the health flag exactly as rom_step does. */
+rom_status rom_step_async(rom_ctx ctx, rom_state st, int64_t nsteps);
+rom_status rom_step_sync(rom_ctx ctx, rom_state st, int64_t *first_bad_step);
+
+/* Energies (eq. ene_fluc, first quantity, with identity mass matrix).  Synchronizes.
+ * E_host [batch] (nullable): energy of the current level of each trajectory.
+ * Elog_host (nullable): [steps+1][batch], level 0..steps of the state's step counter. */
+rom_status rom_energy(rom_ctx ctx, rom_state st, double *E_host, double *Elog_host);
+
+/* Checkpoint/resume.  u_hist [3][batch][N] = levels n, n-1, n-2; y_hist [2][batch][N] =
+ * C(u)u at levels n-1, n-2; *step = n.  Levels below 0 are zero.  rom_state_set
+ * restarts at step n from the given history (the energy log restarts at level n).
+ * Both synchronize. */
+rom_status rom_state_get(rom_ctx ctx, rom_state st, double *u_hist, double *y_hist,
+                         int64_t *step);
+rom_status rom_state_set(rom_ctx ctx, rom_state st, const double *u_hist,
+                         const double *y_hist, int64_t step);
+
+/* Copy the current coefficients u^n [batch][N] into caller device memory.  Async. */
+rom_status rom_state_u(rom_ctx ctx, rom_state st, double *u_dev);
+
+/* Several (context, state) pairs of possibly different N, R and dtype advanced
+ * together: each step of all pairs is issued as one fused launch per kernel phase over
+ * a device work table, on the stream of ctxs[0], so trajectories of uneven size share
+ * the device.  nsteps applies to every pair.  Results equal those of rom_step on each
+ * pair alone within the dtype's tolerance.  Synchronizes at the end. */
+rom_status rom_step_multi(int32_t n, const rom_ctx *ctxs, const rom_state *states,
+                          int64_t nsteps, int64_t *first_bad_step);
+
+/* Introspection.  what: 0 = device bytes held by the context, 1 = device bytes held by
+ * the state, 2 = N, 3 = R (0 if dense), 4 = dtype, 5 = state batch, 6 = state step. */
+rom_status rom_query(rom_ctx ctx, rom_state st, int32_t what, int64_t *value);
+
+/* Kernel tile selection (the autotuner's knob).  kind: 0 = dense single-trajectory
+ * streaming contraction, 1 = dense batched MFMA contraction, 2 = CP projections,
+ * 3 = CP scatter.  value: an index into that kernel's variant table (see
+ * rom_tile_count); -1 restores the built-in heuristic.  Applies to later launches. */
+rom_status rom_set_tile(rom_ctx ctx, int32_t kind, int32_t value);
+int32_t rom_tile_count(int32_t kind);
+
+const char *rom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ROM_H */

@@ -1,0 +1,326 @@
+// k_bdf.hip -- FP64 parts of the time step and their one-time setup:
+//   * the semi-implicit BDFk/EXTk right-hand side and update (eq. nse_d1, identity
+//     mass matrix), the energy E = |u|^2/2 per trajectory and level (eq. ene_fluc)
+//     and the non-finite health flag;
+//   * the Helmholtz operators (beta0_k/dt) I + nu A for k = 1, 2, 3: reciprocals of
+//     the diagonal, or for a dense stiffness a Cholesky factorisation, the inverse of
+//     the factor by triangular solves, and the explicit SPD inverse;
+//   * storage conversions of the operators (round to nearest even).
+#include <climits>
+
+#include "kstep.h"
+
+namespace rom {
+
+// ============================================================== update kernels
+
+// y^n from contraction partials part[c][b][i] (summed over c in order), then either
+// the diagonal-stiffness update u^{n+1} = rhs / H_ii with energy and finalize, or the
+// right-hand side for the dense solve.  Grid: (ceil(N/256), B), 256 threads.
+template <class ACC, bool DIAG>
+__global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __restrict__ part,
+                                                      int nchunk, int pbstride) {
+    __shared__ double red[4];
+    const long long n = *a.step;
+    const int k = bdf_order(n);
+    const BdfCoef c = bdf_coef(k);
+    const int b = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (i < a.N) {
+        double y = 0.0;
+        for (int q = 0; q < nchunk; ++q) y += (double)part[((size_t)q * pbstride + b) * a.N + i];
+        const double rhs = bdf_rhs_point(a, n, c, k, b, i, y);
+        if (DIAG) {
+            const double un = rhs * a.hdiag[(size_t)(k - 1) * a.N + i];
+            write_level(a, n + 1, b, i, un);
+            e = un * un;
+        } else {
+            a.rhs[(size_t)b * a.N + i] = rhs;
+        }
+    }
+    if (DIAG) {
+        const double s = block_sum(e, red);
+        if (threadIdx.x == 0) a.epart[(size_t)b * gridDim.x + blockIdx.x] = s;
+        finalize_step(a, n, gridDim.x, gridDim.x * gridDim.y);
+    }
+}
+
+// Dense stiffness, one trajectory: u^{n+1}_i = sum_m Hinv_k[i][m] rhs_m, one wavefront
+// per row, rhs staged in LDS.  Grid: ceil(N/4) blocks of 256 threads.
+__global__ __launch_bounds__(256) void k_helm_gemv(StepArgs a) {
+    extern __shared__ double sm[];
+    double* r = sm;            // [N]
+    double* red = sm + a.N;    // [4]
+    const long long n = *a.step;
+    const int k = bdf_order(n);
+    for (int m = threadIdx.x; m < a.N; m += blockDim.x) r[m] = a.rhs[m];
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int i = blockIdx.x * 4 + w;
+    double e = 0.0;
+    if (i < a.N) {
+        const double* h = a.hinv + ((size_t)(k - 1) * a.N + i) * a.N;
+        double s = 0.0;
+        for (int m = lane; m < a.N; m += kWave) s += h[m] * r[m];
+        s = wave_sum(s);
+        if (lane == 0) {
+            write_level(a, n + 1, 0, i, s);
+            e = s * s;
+        }
+    }
+    const double es = block_sum(e, red);
+    if (threadIdx.x == 0) a.epart[blockIdx.x] = es;
+    finalize_step(a, n, gridDim.x, gridDim.x);
+}
+
+// Dense stiffness, batch: U^{n+1}[b][i] = sum_m Hinv_k[i][m] rhs[b][m], FP64 register
+// tiles of 32 rows x 64 trajectories per block (each thread 2 x 4).  Grid:
+// (ceil(N/32), ceil(B/64)), 256 threads.  Energy partials per (b, row tile).
+__global__ __launch_bounds__(256) void k_helm_gemm(StepArgs a) {
+    __shared__ double Hs[32][33];
+    __shared__ double Rs[64][33];
+    __shared__ double ered[16][65];
+    const long long n = *a.step;
+    const int k = bdf_order(n);
+    const double* H = a.hinv + (size_t)(k - 1) * a.N * a.N;
+    const int i0 = blockIdx.x * 32, b0 = blockIdx.y * 64;
+    const int tr = threadIdx.x / 16, tb = threadIdx.x % 16;
+    double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    for (int m0 = 0; m0 < a.N; m0 += 32) {
+        for (int q = threadIdx.x; q < 32 * 32; q += 256) {
+            const int rr = q / 32, mm = q % 32;
+            const int gi = i0 + rr, gm = m0 + mm;
+            Hs[rr][mm] = (gi < a.N && gm < a.N) ? H[(size_t)gi * a.N + gm] : 0.0;
+        }
+        for (int q = threadIdx.x; q < 64 * 32; q += 256) {
+            const int bb = q / 32, mm = q % 32;
+            const int gb = b0 + bb, gm = m0 + mm;
+            Rs[bb][mm] = (gb < a.B && gm < a.N) ? a.rhs[(size_t)gb * a.N + gm] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int mm = 0; mm < 32; ++mm) {
+            const double h0 = Hs[tr * 2][mm], h1 = Hs[tr * 2 + 1][mm];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double rv = Rs[tb * 4 + q][mm];
+                acc[0][q] += h0 * rv;
+                acc[1][q] += h1 * rv;
+            }
+        }
+        __syncthreads();
+    }
+    double ep[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gi = i0 + tr * 2 + p, gb = b0 + tb * 4 + q;
+            if (gi < a.N && gb < a.B) {
+                write_level(a, n + 1, gb, gi, acc[p][q]);
+                ep[q] += acc[p][q] * acc[p][q];
+            }
+        }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ered[tr][tb * 4 + q] = ep[q];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int gb = b0 + threadIdx.x;
+        double s = 0.0;
+        for (int t = 0; t < 16; ++t) s += ered[t][threadIdx.x];
+        if (gb < a.B) a.epart[(size_t)gb * gridDim.x + blockIdx.x] = s;
+    }
+    finalize_step(a, n, gridDim.x, gridDim.x * gridDim.y);
+}
+
+// Batched coefficient copies of u (state creation / restart).  Grid (ceil(N/256), B).
+__global__ void k_prep_ucv(StepArgs a, const double* __restrict__ u) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+    if (i < a.N) write_level(a, 0, b, i, u[(size_t)b * a.N + i]);
+}
+
+template <class ACC>
+__global__ void k_sum_partials(const ACC* __restrict__ part, int nchunk, int B, int N,
+                               double* __restrict__ y, int pbstride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+    if (i >= N) return;
+    double s = 0.0;
+    for (int q = 0; q < nchunk; ++q) s += (double)part[((size_t)q * pbstride + b) * N + i];
+    y[(size_t)b * N + i] = s;
+}
+
+// ============================================================== launchers
+
+void launch_bdf_from_partials(const StepArgs& a, int acc_f64, const void* part, int nchunk,
+                              int pb, int diag, hipStream_t s) {
+    dim3 grid((a.N + 255) / 256, a.B);
+    if (acc_f64) {
+        if (diag) hipLaunchKernelGGL((k_bdf_partials<double, true>), grid, dim3(256), 0, s, a, (const double*)part, nchunk, pb);
+        else hipLaunchKernelGGL((k_bdf_partials<double, false>), grid, dim3(256), 0, s, a, (const double*)part, nchunk, pb);
+    } else {
+        if (diag) hipLaunchKernelGGL((k_bdf_partials<float, true>), grid, dim3(256), 0, s, a, (const float*)part, nchunk, pb);
+        else hipLaunchKernelGGL((k_bdf_partials<float, false>), grid, dim3(256), 0, s, a, (const float*)part, nchunk, pb);
+    }
+}
+
+void launch_helm_apply(const StepArgs& a, hipStream_t s) {
+    if (a.B == 1) {
+        const size_t lds = sizeof(double) * (a.N + 4);
+        hipLaunchKernelGGL(k_helm_gemv, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
+    } else {
+        hipLaunchKernelGGL(k_helm_gemm, dim3((a.N + 31) / 32, (a.B + 63) / 64), dim3(256), 0, s, a);
+    }
+}
+
+void launch_prep_ucv(const StepArgs& a, const double* u_src, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep_ucv, dim3((a.N + 255) / 256, a.B), dim3(256), 0, s, a, u_src);
+}
+
+void launch_sum_partials(int acc_f64, const void* part, int nchunk, int pb, int B, int N,
+                         double* y, hipStream_t s) {
+    dim3 grid((N + 255) / 256, B);
+    if (acc_f64) hipLaunchKernelGGL(k_sum_partials<double>, grid, dim3(256), 0, s, (const double*)part, nchunk, B, N, y, pb);
+    else hipLaunchKernelGGL(k_sum_partials<float>, grid, dim3(256), 0, s, (const float*)part, nchunk, B, N, y, pb);
+}
+
+// ============================================================== Helmholtz setup
+
+__global__ void k_build_h(int N, double nu, double diag, const double* __restrict__ A,
+                          double* __restrict__ H) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (size_t)N * N) return;
+    const int i = (int)(q / N), m = (int)(q % N);
+    H[q] = nu * A[q] + (i == m ? diag : 0.0);
+}
+
+// Left-looking Cholesky, column j: one wavefront per row i >= j.
+//   L_jj = sqrt(H_jj - sum_{m<j} L_jm^2),  L_ij = (H_ij - sum_{m<j} L_im L_jm) / L_jj.
+__global__ __launch_bounds__(256) void k_chol_col(int N, int j, const double* __restrict__ H,
+                                                  double* __restrict__ L, int* info) {
+    const int lane = threadIdx.x % kWave;
+    const int i = j + blockIdx.x * 4 + threadIdx.x / kWave;
+    if (i >= N) return;
+    const double* Lj = L + (size_t)j * N;
+    const double* Li = L + (size_t)i * N;
+    double d = 0.0, s = 0.0;
+    for (int m = lane; m < j; m += kWave) {
+        d += Lj[m] * Lj[m];
+        s += Li[m] * Lj[m];
+    }
+    d = wave_sum(d);
+    s = wave_sum(s);
+    const double piv = H[(size_t)j * N + j] - d;
+    if (lane == 0) {
+        if (!(piv > 0.0)) {
+            if (i == j) atomicMax(info, 1);
+        }
+        const double ljj = sqrt(piv);
+        L[(size_t)i * N + j] = (i == j) ? ljj : (H[(size_t)i * N + j] - s) / ljj;
+    }
+}
+
+// X = L^{-1} column by column (one wavefront per column c, values kept in LDS):
+//   X_cc = 1/L_cc,  X_rc = -(sum_{c<=m<r} L_rm X_mc) / L_rr  for r > c.
+__global__ __launch_bounds__(64) void k_trinv_col(int N, const double* __restrict__ L,
+                                                  double* __restrict__ X) {
+    extern __shared__ double x[];
+    const int c = blockIdx.x, lane = threadIdx.x;
+    for (int r = lane; r < N; r += kWave) x[r] = 0.0;
+    __syncthreads();
+    for (int r = c; r < N; ++r) {
+        const double* Lr = L + (size_t)r * N;
+        double s = 0.0;
+        for (int m = c + lane; m < r; m += kWave) s += Lr[m] * x[m];
+        s = wave_sum(s);
+        const double v = ((r == c ? 1.0 : 0.0) - s) / Lr[r];
+        __syncthreads();
+        if (lane == 0) x[r] = v;
+        __syncthreads();
+    }
+    for (int r = lane; r < N; r += kWave) X[(size_t)r * N + c] = x[r];
+}
+
+// Hinv = X^T X (X lower triangular): Hinv_im = sum_{r >= max(i,m)} X_ri X_rm.
+__global__ void k_gram(int N, const double* __restrict__ X, double* __restrict__ Hinv) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (m >= N) return;
+    double s = 0.0;
+    for (int r = (i > m ? i : m); r < N; ++r) s += X[(size_t)r * N + i] * X[(size_t)r * N + m];
+    Hinv[(size_t)i * N + m] = s;
+}
+
+__global__ void k_hdiag(int N, double nu, double inv_dt, const double* __restrict__ A,
+                        double* __restrict__ hd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double b0[3] = {1.0, 1.5, 11.0 / 6.0};
+    for (int k = 0; k < 3; ++k) hd[(size_t)k * N + i] = 1.0 / (b0[k] * inv_dt + nu * A[(size_t)i * N + i]);
+}
+
+int helm_setup_dense(int N, double nu, double dt, const double* A_dev, double* hinv_dev,
+                     double* work_dev, int* info_dev, hipStream_t s) {
+    // work_dev: 3 N^2 doubles (H, L, X)
+    double* H = work_dev;
+    double* L = work_dev + (size_t)N * N;
+    double* X = work_dev + 2 * (size_t)N * N;
+    const double b0[3] = {1.0, 1.5, 11.0 / 6.0};
+    const size_t nn = (size_t)N * N;
+    for (int k = 0; k < 3; ++k) {
+        hipLaunchKernelGGL(k_build_h, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, nu, b0[k] / dt, A_dev, H);
+        hipMemsetAsync(L, 0, nn * sizeof(double), s);
+        for (int j = 0; j < N; ++j)
+            hipLaunchKernelGGL(k_chol_col, dim3((N - j + 3) / 4), dim3(256), 0, s, N, j, H, L, info_dev);
+        hipLaunchKernelGGL(k_trinv_col, dim3(N), dim3(64), sizeof(double) * N, s, N, L, X);
+        hipLaunchKernelGGL(k_gram, dim3((N + 255) / 256, N), dim3(256), 0, s, N, X, hinv_dev + k * nn);
+    }
+    return 0;
+}
+
+void helm_setup_diag(int N, double nu, double dt, const double* A_dev, double* hdiag_dev,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_hdiag, dim3((N + 255) / 256), dim3(256), 0, s, N, nu, 1.0 / dt, A_dev, hdiag_dev);
+}
+
+// ============================================================== storage conversion
+
+__global__ void k_cvt(int dt, const double* __restrict__ src, void* dst, void* dst_lo, long long n) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long p = q; p < n; p += stride) {
+        const double v = src[p];
+        if (dt == DT_F64) {
+            reinterpret_cast<double*>(dst)[p] = v;
+        } else if (dt == DT_F32) {
+            reinterpret_cast<float*>(dst)[p] = (float)v;
+        } else {
+            const float f = (float)v;
+            const unsigned short h = bf16_bits(f);
+            reinterpret_cast<unsigned short*>(dst)[p] = h;
+            if (dt == DT_BF16X3) reinterpret_cast<unsigned short*>(dst_lo)[p] = bf16_bits(f - bf16_f(h));
+        }
+    }
+}
+
+// CP weights: FP64 for DT_F64, BF16-rounded FP32 values for DT_BF16, FP32 otherwise.
+__global__ void k_cvt_lambda(int dt, const double* __restrict__ src, void* dst, long long n) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (dt == DT_F64) reinterpret_cast<double*>(dst)[p] = src[p];
+    else if (dt == DT_BF16) reinterpret_cast<float*>(dst)[p] = bf16_f(bf16_bits((float)src[p]));
+    else reinterpret_cast<float*>(dst)[p] = (float)src[p];
+}
+
+void launch_cvt_f64_to(int dt, const double* src, void* dst, void* dst_lo, long long n,
+                       hipStream_t s) {
+    long long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_cvt, dim3((unsigned)blocks), dim3(256), 0, s, dt, src, dst, dst_lo, n);
+}
+
+void launch_cvt_lambda(int dt, const double* src, void* dst, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cvt_lambda, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dt, src, dst, n);
+}
+
+}  // namespace rom

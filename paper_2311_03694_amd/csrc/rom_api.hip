@@ -1,0 +1,712 @@
+// rom_api.hip -- the C ABI of librom.so (include/rom.h): contexts (device operators,
+// Helmholtz inverses, workspaces), states (trajectory histories, energy log), and the
+// step sequencer that issues each BDF3/EXT3 step as a short chain of kernels and
+// replays chunks of steps as captured HIP graphs.
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rom.h"
+#include "rom_dev.h"
+
+using namespace rom;
+
+// ============================================================== errors
+
+static thread_local std::string g_err;
+
+static rom_status fail(rom_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static rom_status fail(rom_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? ROM_E_NOMEM : ROM_E_DEVICE,          \
+                        "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                        \
+    } while (0)
+
+extern "C" const char* rom_last_error(void) { return g_err.c_str(); }
+
+// ============================================================== objects
+
+namespace {
+
+constexpr int kGraphChunk = 64;   // steps per captured graph
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct rom_ctx_s {
+    int N = 0, R = 0, dtype = 0, max_batch = 1;
+    double nu = 0, dt = 0;
+    bool dense = true, diagA = true;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // operators in the contraction format
+    void *C = nullptr, *Clo = nullptr;         // dense [N][N][N]
+    void *BCt = nullptr, *BCt_lo = nullptr;    // CP [2R][N]: rows Bf^T then Cf^T
+    void *Af = nullptr, *Af_lo = nullptr;      // CP [N][R]
+    void* lam = nullptr;                        // CP [R] (FP64 or FP32)
+    double* hdiag = nullptr;                    // [3][N]
+    double* hinv = nullptr;                     // [3][N][N]
+    // workspaces (shared by every state of the context; one stream serializes use)
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int ws_gen = 0;
+    // tiles (-1 = heuristic)
+    int tile[4] = {-1, -1, -1, -1};
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+};
+
+struct rom_state_s {
+    rom_ctx ctx = nullptr;
+    int B = 0, Bpad = 0;
+    StepArgs a{};
+    long long h_step = 0;
+    long long elog_base = 0;
+    hipGraphExec_t graph = nullptr;
+    int graph_gen = -1;
+    double* graph_elog = nullptr;
+    bool pending = false;
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+};
+
+static rom_status dmalloc(void** p, size_t bytes, size_t* acct, std::vector<void*>* list) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? ROM_E_NOMEM : ROM_E_DEVICE,
+                    "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    *acct += bytes;
+    list->push_back(*p);
+    return ROM_OK;
+}
+
+static size_t elem_bytes(int dt) { return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2; }
+static int acc_f64(int dt) { return dt == DT_F64 ? 1 : 0; }
+static size_t acc_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
+
+// ============================================================== workspace sizing
+
+namespace {
+
+GemvTile gemv_tile(rom_ctx c) { return dense_gemv_variant(c->tile[0] < 0 ? 0 : c->tile[0]); }
+
+// Bytes of contraction workspace a batch of B needs, and its layout offsets.
+struct WsPlan {
+    size_t part_off = 0, part_bytes = 0;   // contraction partial sums
+    size_t st_off = 0, st_bytes = 0;       // CP projections
+    size_t total = 0;
+    int nchunk = 0;
+};
+
+WsPlan plan_ws(rom_ctx c, int B) {
+    WsPlan p;
+    const size_t ab = acc_bytes(c->dtype);
+    if (c->dense) {
+        if (B == 1) {
+            p.nchunk = dense_gemv_nchunk(c->N, gemv_tile(c));
+            p.part_bytes = (size_t)p.nchunk * c->N * ab;
+        }
+    } else {
+        if (B == 1) p.st_bytes = 2 * (size_t)c->R * ab;
+    }
+    p.part_off = 0;
+    p.st_off = (p.part_bytes + 255) & ~(size_t)255;
+    p.total = p.st_off + p.st_bytes + 256;
+    return p;
+}
+
+rom_status ensure_ws(rom_ctx c, size_t bytes) {
+    if (bytes <= c->ws_bytes) return ROM_OK;
+    if (c->ws) {
+        hipStreamSynchronize(c->stream);
+        hipFree(c->ws);
+        c->bytes -= c->ws_bytes;
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&c->ws, bytes);
+    if (e != hipSuccess) {
+        c->ws = nullptr;
+        return fail(ROM_E_NOMEM, "workspace hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->ws_bytes = bytes;
+    c->bytes += bytes;
+    c->ws_gen++;
+    return ROM_OK;
+}
+
+}  // namespace
+
+// ============================================================== create / destroy
+
+static rom_status upload_convert(rom_ctx c, const double* host, size_t n, void* dst, void* dst_lo,
+                                 double* stage, size_t stage_elems) {
+    const size_t eb = elem_bytes(c->dtype);
+    for (size_t off = 0; off < n; off += stage_elems) {
+        const size_t cnt = (n - off < stage_elems) ? n - off : stage_elems;
+        HIPCHK(hipMemcpyAsync(stage, host + off, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        launch_cvt_f64_to(c->dtype, stage, (char*)dst + off * eb, dst_lo ? (char*)dst_lo + off * 2 : nullptr,
+                          (long long)cnt, c->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return ROM_OK;
+}
+
+extern "C" void rom_destroy(rom_ctx c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    for (void* p : c->allocs) hipFree(p);
+    if (c->ws) hipFree(c->ws);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
+    if (!out) return fail(ROM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(ROM_E_INVALID, "desc is NULL");
+    if (d->N < 1) return fail(ROM_E_INVALID, "N must be >= 1 (got %d)", d->N);
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(ROM_E_INVALID, "dt must be > 0");
+    if (!(d->nu >= 0.0) || !std::isfinite(d->nu)) return fail(ROM_E_INVALID, "nu must be >= 0");
+    if (!d->A) return fail(ROM_E_INVALID, "stiffness A is NULL");
+    if (d->dtype < ROM_FP64 || d->dtype > ROM_BF16X3) return fail(ROM_E_INVALID, "unknown dtype %d", d->dtype);
+    if (d->max_batch < 1) return fail(ROM_E_INVALID, "max_batch must be >= 1");
+    if (!d->C) {
+        if (d->R < 1) return fail(ROM_E_INVALID, "CP rank R must be >= 1 when C is NULL");
+        if (!d->lambda || !d->Af || !d->Bf || !d->Cf)
+            return fail(ROM_E_INVALID, "CP mode needs lambda, Af, Bf and Cf");
+    }
+    const long long N = d->N;
+    if (d->C && N > 4096) return fail(ROM_E_UNSUPPORTED, "dense tensors are limited to N <= 4096");
+    if (N > 16384) return fail(ROM_E_UNSUPPORTED, "N > 16384 is not supported");
+    if (!d->C && (long long)d->R * (d->dtype == ROM_FP64 ? 8 : 4) > 65536)
+        return fail(ROM_E_UNSUPPORTED, "CP rank %d exceeds the 64 KB LDS staging of the scatter kernel", d->R);
+
+    rom_ctx c = new rom_ctx_s();
+    c->N = d->N;
+    c->R = d->C ? 0 : d->R;
+    c->dtype = d->dtype;
+    c->nu = d->nu;
+    c->dt = d->dt;
+    c->max_batch = d->max_batch;
+    c->dense = d->C != nullptr;
+    c->stream = (hipStream_t)d->stream;
+    rom_status st = ROM_OK;
+#define TRY(x)                          \
+    do {                                \
+        st = (x);                       \
+        if (st != ROM_OK) {             \
+            rom_destroy(c);             \
+            return st;                  \
+        }                               \
+    } while (0)
+#define HTRY(x)                                                                           \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) {                                                           \
+            st = fail(e_ == hipErrorOutOfMemory ? ROM_E_NOMEM : ROM_E_DEVICE, "%s: %s",  \
+                      #x, hipGetErrorString(e_));                                         \
+            rom_destroy(c);                                                               \
+            return st;                                                                    \
+        }                                                                                 \
+    } while (0)
+    if (!c->stream) {
+        HTRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+
+    // ---- stiffness: diagonal detection, Helmholtz data
+    bool diag = true;
+    for (long long i = 0; i < N && diag; ++i)
+        for (long long m = 0; m < N; ++m)
+            if (i != m && d->A[i * N + m] != 0.0) {
+                diag = false;
+                break;
+            }
+    c->diagA = diag;
+    if (!diag && N > 4096) {
+        st = fail(ROM_E_UNSUPPORTED, "a non-diagonal stiffness is limited to N <= 4096");
+        rom_destroy(c);
+        return st;
+    }
+    const size_t stage_elems = (size_t)1 << 25;   // 256 MB of FP64 per upload chunk
+    double* stage = nullptr;
+    const size_t nn = (size_t)N * N;
+    HTRY(hipMalloc((void**)&stage, sizeof(double) * (nn > stage_elems ? nn : stage_elems)));
+    struct StageGuard {
+        double* p;
+        ~StageGuard() { if (p) hipFree(p); }
+    } guard{stage};
+    HTRY(hipMemcpyAsync(stage, d->A, sizeof(double) * nn, hipMemcpyHostToDevice, c->stream));
+    if (diag) {
+        TRY(dmalloc((void**)&c->hdiag, sizeof(double) * 3 * N, &c->bytes, &c->allocs));
+        helm_setup_diag((int)N, d->nu, d->dt, stage, c->hdiag, c->stream);
+        HTRY(hipGetLastError());
+        // SPD check of the three diagonal Helmholtz matrices
+        for (long long i = 0; i < N; ++i) {
+            const double h = 1.0 / d->dt + d->nu * d->A[i * N + i];
+            if (!(h > 0.0)) {
+                st = fail(ROM_E_INVALID, "Helmholtz matrix not positive definite (row %lld)", i);
+                rom_destroy(c);
+                return st;
+            }
+        }
+    } else {
+        double* work = nullptr;
+        int* info = nullptr;
+        TRY(dmalloc((void**)&c->hinv, sizeof(double) * 3 * nn, &c->bytes, &c->allocs));
+        HTRY(hipMalloc((void**)&work, sizeof(double) * 3 * nn));
+        HTRY(hipMalloc((void**)&info, sizeof(int)));
+        HTRY(hipMemsetAsync(info, 0, sizeof(int), c->stream));
+        helm_setup_dense((int)N, d->nu, d->dt, stage, c->hinv, work, info, c->stream);
+        hipError_t le = hipGetLastError();
+        int hinfo = 0;
+        hipError_t se = hipStreamSynchronize(c->stream);
+        if (le == hipSuccess && se == hipSuccess)
+            se = hipMemcpy(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost);
+        hipFree(work);
+        hipFree(info);
+        if (le != hipSuccess || se != hipSuccess) {
+            st = fail(ROM_E_DEVICE, "Helmholtz setup failed: %s", hipGetErrorString(le != hipSuccess ? le : se));
+            rom_destroy(c);
+            return st;
+        }
+        if (hinfo != 0) {
+            st = fail(ROM_E_INVALID, "Helmholtz matrix (beta0/dt) I + nu A is not positive definite");
+            rom_destroy(c);
+            return st;
+        }
+    }
+    HTRY(hipStreamSynchronize(c->stream));
+
+    // ---- advection operator
+    const int dt = c->dtype;
+    const size_t eb = elem_bytes(dt);
+    const bool lo = dt == DT_BF16X3;
+    if (c->dense) {
+        const size_t n3 = nn * N;
+        TRY(dmalloc(&c->C, n3 * eb, &c->bytes, &c->allocs));
+        if (lo) TRY(dmalloc(&c->Clo, n3 * 2, &c->bytes, &c->allocs));
+        TRY(upload_convert(c, d->C, n3, c->C, c->Clo, stage, stage_elems));
+    } else {
+        const size_t R = c->R;
+        TRY(dmalloc(&c->BCt, 2 * R * N * eb, &c->bytes, &c->allocs));
+        TRY(dmalloc(&c->Af, R * N * eb, &c->bytes, &c->allocs));
+        if (lo) {
+            TRY(dmalloc(&c->BCt_lo, 2 * R * N * 2, &c->bytes, &c->allocs));
+            TRY(dmalloc(&c->Af_lo, R * N * 2, &c->bytes, &c->allocs));
+        }
+        TRY(dmalloc(&c->lam, R * acc_bytes(dt), &c->bytes, &c->allocs));
+        // [Bf | Cf]^T as [2R][N] (host transpose of the caller's [N][R] factors)
+        std::vector<double> t(2 * R * (size_t)N);
+        for (size_t n = 0; n < (size_t)N; ++n)
+            for (size_t r = 0; r < R; ++r) {
+                t[r * N + n] = d->Bf[n * R + r];
+                t[(R + r) * N + n] = d->Cf[n * R + r];
+            }
+        TRY(upload_convert(c, t.data(), t.size(), c->BCt, c->BCt_lo, stage, stage_elems));
+        TRY(upload_convert(c, d->Af, R * N, c->Af, c->Af_lo, stage, stage_elems));
+        HTRY(hipMemcpyAsync(stage, d->lambda, sizeof(double) * R, hipMemcpyHostToDevice, c->stream));
+        launch_cvt_lambda(dt, stage, c->lam, (long long)R, c->stream);
+        HTRY(hipGetLastError());
+    }
+    HTRY(hipStreamSynchronize(c->stream));
+    *out = c;
+#undef TRY
+#undef HTRY
+    return ROM_OK;
+}
+
+// ============================================================== contraction dispatch
+
+// Enqueue y = C(u)u for a batch of one whose coefficients sit at u_base (+ ring slot of
+// *stepp when stepp != NULL).  The CP path returns through the scatter kernel's
+// epilogue (mode 0: y_out; 1, 2: fused BDF update), the dense path through partials.
+static rom_status enqueue_step(rom_ctx c, rom_state s) {
+    const StepArgs& a = s->a;
+    const WsPlan p = plan_ws(c, s->B);
+    char* ws = (char*)c->ws;
+    if (s->B != 1) return fail(ROM_E_UNSUPPORTED, "batched states are not available in this build");
+    if (c->dense) {
+        launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, a.uring, a.step, (long long)s->B * c->N,
+                          ws + p.part_off, p.nchunk, gemv_tile(c), c->stream);
+        launch_bdf_from_partials(a, acc_f64(c->dtype), ws + p.part_off, p.nchunk, 1, c->diagA ? 1 : 0,
+                                 c->stream);
+    } else {
+        launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->R, a.uring, a.step, (long long)s->B * c->N,
+                        ws + p.st_off, c->stream);
+        launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->R, ws + p.st_off, nullptr, &a,
+                           c->diagA ? 1 : 2, c->stream);
+    }
+    if (!c->diagA) launch_helm_apply(a, c->stream);
+    HIPCHK(hipGetLastError());
+    return ROM_OK;
+}
+
+extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_dev, double* y_dev) {
+    if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
+    if (batch < 1 || batch > c->max_batch) return fail(ROM_E_INVALID, "batch %d outside [1, %d]", batch, c->max_batch);
+    if (!u_dev || !y_dev) return fail(ROM_E_INVALID, "u_dev / y_dev is NULL");
+    if (batch != 1) return fail(ROM_E_UNSUPPORTED, "batched evaluation is not available in this build");
+    const WsPlan p = plan_ws(c, 1);
+    rom_status st = ensure_ws(c, p.total);
+    if (st != ROM_OK) return st;
+    char* ws = (char*)c->ws;
+    if (c->dense) {
+        launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, u_dev, nullptr, 0, ws + p.part_off, p.nchunk,
+                          gemv_tile(c), c->stream);
+        launch_sum_partials(acc_f64(c->dtype), ws + p.part_off, p.nchunk, 1, 1, c->N, y_dev, c->stream);
+    } else {
+        launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->R, u_dev, nullptr, 0, ws + p.st_off, c->stream);
+        launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->R, ws + p.st_off, y_dev, nullptr, 0,
+                           c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    return ROM_OK;
+}
+
+// ============================================================== states
+
+namespace {
+
+__global__ void k_energy_level(StepArgs a, long long level) {
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const double* u = a.uring + ((size_t)(((level % 3) + 3) % 3) * a.B + b) * a.N;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < a.N; i += blockDim.x) s += u[i] * u[i];
+    s += __shfl_xor(s, 32, 64);
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 8, 64);
+    s += __shfl_xor(s, 4, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 1, 64);
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double e = 0.5 * (red[0] + red[1] + red[2] + red[3]);
+        a.elog[(size_t)level * a.B + b] = e;
+        if (!isfinite(e)) atomicMin(a.bad, level);
+    }
+}
+
+__global__ void k_fill(double* p, size_t n, double v) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) p[q] = v;
+}
+
+rom_status ensure_elog(rom_state s, long long levels_needed) {
+    if (levels_needed <= s->a.elog_cap) return ROM_OK;
+    long long cap = s->a.elog_cap > 0 ? s->a.elog_cap : 1024;
+    while (cap < levels_needed) cap *= 2;
+    double* nl = nullptr;
+    hipError_t e = hipMalloc((void**)&nl, sizeof(double) * cap * s->B);
+    if (e != hipSuccess) return fail(ROM_E_NOMEM, "energy log hipMalloc failed: %s", hipGetErrorString(e));
+    rom_ctx c = s->ctx;
+    const size_t total = (size_t)cap * s->B;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream, nl, total,
+                       std::nan(""));
+    if (s->a.elog) {
+        HIPCHK(hipMemcpyAsync(nl, s->a.elog, sizeof(double) * s->a.elog_cap * s->B, hipMemcpyDeviceToDevice,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        hipFree(s->a.elog);
+        s->bytes -= sizeof(double) * s->a.elog_cap * s->B;
+    }
+    s->a.elog = nl;
+    s->a.elog_cap = cap;
+    s->bytes += sizeof(double) * cap * s->B;
+    return ROM_OK;
+}
+
+rom_status reset_counters(rom_state s, long long step) {
+    rom_ctx c = s->ctx;
+    const long long big = LLONG_MAX;
+    HIPCHK(hipMemcpyAsync(s->a.step, &step, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(s->a.bad, &big, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemsetAsync(s->a.ticket, 0, sizeof(unsigned), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ROM_OK;
+}
+
+}  // namespace
+
+extern "C" void rom_state_destroy(rom_state s) {
+    if (!s) return;
+    if (s->ctx && s->ctx->stream) hipStreamSynchronize(s->ctx->stream);
+    if (s->graph) hipGraphExecDestroy(s->graph);
+    for (void* p : s->allocs) hipFree(p);
+    if (s->a.elog) hipFree(s->a.elog);
+    delete s;
+}
+
+extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u0_host, rom_state* out) {
+    if (!out) return fail(ROM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
+    if (batch < 1 || batch > c->max_batch) return fail(ROM_E_INVALID, "batch %d outside [1, %d]", batch, c->max_batch);
+    if (!u0_host) return fail(ROM_E_INVALID, "u0_host is NULL");
+    if (batch != 1) return fail(ROM_E_UNSUPPORTED, "batched states are not available in this build");
+    rom_state s = new rom_state_s();
+    s->ctx = c;
+    s->B = batch;
+    s->Bpad = (batch + 15) / 16 * 16;
+    const size_t N = c->N, B = batch, BN = B * N;
+    rom_status st;
+#define TRY(x)                      \
+    do {                            \
+        st = (x);                   \
+        if (st != ROM_OK) {         \
+            rom_state_destroy(s);   \
+            return st;              \
+        }                           \
+    } while (0)
+    StepArgs& a = s->a;
+    a.N = c->N;
+    a.B = batch;
+    a.Bpad = s->Bpad;
+    a.inv_dt = 1.0 / c->dt;
+    a.dtype = c->dtype;
+    a.batched = batch > 1 ? 1 : 0;
+    a.hdiag = c->hdiag;
+    a.hinv = c->hinv;
+    TRY(dmalloc((void**)&a.uring, sizeof(double) * 3 * BN, &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.yring, sizeof(double) * 3 * BN, &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.rhs, sizeof(double) * BN, &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.epart, sizeof(double) * B * ((N + 3) / 4 + 64), &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.step, sizeof(long long), &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.ticket, sizeof(unsigned), &s->bytes, &s->allocs));
+    if (hipMemsetAsync(a.uring, 0, sizeof(double) * 3 * BN, c->stream) != hipSuccess ||
+        hipMemsetAsync(a.yring, 0, sizeof(double) * 3 * BN, c->stream) != hipSuccess) {
+        rom_state_destroy(s);
+        return fail(ROM_E_DEVICE, "state clear failed");
+    }
+    if (hipMemcpyAsync(a.uring, u0_host, sizeof(double) * BN, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+        rom_state_destroy(s);
+        return fail(ROM_E_DEVICE, "upload of u0 failed");
+    }
+    TRY(reset_counters(s, 0));
+    TRY(ensure_elog(s, 1024));
+    hipLaunchKernelGGL(k_energy_level, dim3(batch), dim3(256), 0, c->stream, a, 0LL);
+    TRY(ensure_ws(c, plan_ws(c, batch).total));
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        rom_state_destroy(s);
+        return fail(ROM_E_DEVICE, "state setup failed");
+    }
+#undef TRY
+    *out = s;
+    return ROM_OK;
+}
+
+// ============================================================== stepping
+
+static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
+    rom_status st = ensure_ws(c, plan_ws(c, s->B).total);
+    if (st != ROM_OK) return st;
+    st = ensure_elog(s, s->h_step + nsteps + 1);
+    if (st != ROM_OK) return st;
+    int64_t left = nsteps;
+    if (left >= 2 * kGraphChunk) {
+        if (!s->graph || s->graph_gen != c->ws_gen || s->graph_elog != s->a.elog) {
+            if (s->graph) {
+                hipGraphExecDestroy(s->graph);
+                s->graph = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            rom_status cst = ROM_OK;
+            for (int q = 0; q < kGraphChunk && cst == ROM_OK; ++q) cst = enqueue_step(c, s);
+            hipError_t ee = hipStreamEndCapture(c->stream, &g);
+            if (cst != ROM_OK) {
+                if (g) hipGraphDestroy(g);
+                return cst;
+            }
+            if (ee != hipSuccess) return fail(ROM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ee));
+            hipError_t ie = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                s->graph = nullptr;
+                return fail(ROM_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+            }
+            s->graph_gen = c->ws_gen;
+            s->graph_elog = s->a.elog;
+        }
+        while (left >= kGraphChunk) {
+            HIPCHK(hipGraphLaunch(s->graph, c->stream));
+            left -= kGraphChunk;
+        }
+    }
+    for (; left > 0; --left) {
+        st = enqueue_step(c, s);
+        if (st != ROM_OK) return st;
+    }
+    s->h_step += nsteps;
+    s->pending = true;
+    return ROM_OK;
+}
+
+extern "C" rom_status rom_step_sync(rom_ctx c, rom_state s, int64_t* first_bad_step) {
+    if (!c || !s || s->ctx != c) return fail(ROM_E_INVALID, "bad ctx/state");
+    if (first_bad_step) *first_bad_step = -1;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    s->pending = false;
+    long long bad = LLONG_MAX;
+    HIPCHK(hipMemcpy(&bad, s->a.bad, sizeof(long long), hipMemcpyDeviceToHost));
+    if (bad != LLONG_MAX) {
+        if (first_bad_step) *first_bad_step = bad;
+        return fail(ROM_E_NONFINITE, "trajectory became non-finite at step %lld", bad);
+    }
+    return ROM_OK;
+}
+
+extern "C" rom_status rom_step_async(rom_ctx c, rom_state s, int64_t nsteps) {
+    if (!c || !s || s->ctx != c) return fail(ROM_E_INVALID, "bad ctx/state");
+    if (nsteps < 0) return fail(ROM_E_INVALID, "nsteps < 0");
+    return step_enqueue(c, s, nsteps);
+}
+
+extern "C" rom_status rom_step(rom_ctx c, rom_state s, int64_t nsteps, int64_t* first_bad_step) {
+    if (first_bad_step) *first_bad_step = -1;
+    rom_status st = rom_step_async(c, s, nsteps);
+    if (st != ROM_OK) return st;
+    return rom_step_sync(c, s, first_bad_step);
+}
+
+extern "C" rom_status rom_energy(rom_ctx c, rom_state s, double* E_host, double* Elog_host) {
+    if (!c || !s || s->ctx != c) return fail(ROM_E_INVALID, "bad ctx/state");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (E_host)
+        HIPCHK(hipMemcpy(E_host, s->a.elog + (size_t)s->h_step * s->B, sizeof(double) * s->B,
+                         hipMemcpyDeviceToHost));
+    if (Elog_host)
+        HIPCHK(hipMemcpy(Elog_host, s->a.elog, sizeof(double) * (size_t)(s->h_step + 1) * s->B,
+                         hipMemcpyDeviceToHost));
+    return ROM_OK;
+}
+
+extern "C" rom_status rom_state_get(rom_ctx c, rom_state s, double* u_hist, double* y_hist, int64_t* step) {
+    if (!c || !s || s->ctx != c) return fail(ROM_E_INVALID, "bad ctx/state");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const size_t BN = (size_t)s->B * c->N;
+    const long long n = s->h_step;
+    for (int q = 0; q < 3 && u_hist; ++q) {
+        const long long lev = n - q;
+        if (lev < 0) memset(u_hist + q * BN, 0, sizeof(double) * BN);
+        else HIPCHK(hipMemcpy(u_hist + q * BN, s->a.uring + (size_t)(lev % 3) * BN, sizeof(double) * BN,
+                              hipMemcpyDeviceToHost));
+    }
+    for (int q = 0; q < 2 && y_hist; ++q) {
+        const long long lev = n - 1 - q;
+        if (lev < 0) memset(y_hist + q * BN, 0, sizeof(double) * BN);
+        else HIPCHK(hipMemcpy(y_hist + q * BN, s->a.yring + (size_t)(lev % 3) * BN, sizeof(double) * BN,
+                              hipMemcpyDeviceToHost));
+    }
+    if (step) *step = n;
+    return ROM_OK;
+}
+
+extern "C" rom_status rom_state_set(rom_ctx c, rom_state s, const double* u_hist, const double* y_hist,
+                                    int64_t step) {
+    if (!c || !s || s->ctx != c) return fail(ROM_E_INVALID, "bad ctx/state");
+    if (!u_hist || !y_hist) return fail(ROM_E_INVALID, "u_hist / y_hist is NULL");
+    if (step < 0) return fail(ROM_E_INVALID, "step < 0");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const size_t BN = (size_t)s->B * c->N;
+    for (int q = 0; q < 3; ++q) {
+        const long long lev = step - q;
+        if (lev < 0) continue;
+        HIPCHK(hipMemcpy(s->a.uring + (size_t)(lev % 3) * BN, u_hist + q * BN, sizeof(double) * BN,
+                         hipMemcpyHostToDevice));
+    }
+    for (int q = 0; q < 2; ++q) {
+        const long long lev = step - 1 - q;
+        if (lev < 0) continue;
+        HIPCHK(hipMemcpy(s->a.yring + (size_t)(lev % 3) * BN, y_hist + q * BN, sizeof(double) * BN,
+                         hipMemcpyHostToDevice));
+    }
+    rom_status st = ensure_elog(s, step + 1024);
+    if (st != ROM_OK) return st;
+    const size_t total = (size_t)s->a.elog_cap * s->B;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream, s->a.elog, total,
+                       std::nan(""));
+    st = reset_counters(s, step);
+    if (st != ROM_OK) return st;
+    s->h_step = step;
+    hipLaunchKernelGGL(k_energy_level, dim3(s->B), dim3(256), 0, c->stream, s->a, (long long)step);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ROM_OK;
+}
+
+extern "C" rom_status rom_state_u(rom_ctx c, rom_state s, double* u_dev) {
+    if (!c || !s || s->ctx != c || !u_dev) return fail(ROM_E_INVALID, "bad arguments");
+    const size_t BN = (size_t)s->B * c->N;
+    HIPCHK(hipMemcpyAsync(u_dev, s->a.uring + (size_t)(s->h_step % 3) * BN, sizeof(double) * BN,
+                          hipMemcpyDeviceToDevice, c->stream));
+    return ROM_OK;
+}
+
+extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_state* states, int64_t nsteps,
+                                     int64_t* first_bad_step) {
+    (void)n; (void)ctxs; (void)states; (void)nsteps;
+    if (first_bad_step) *first_bad_step = -1;
+    return fail(ROM_E_UNSUPPORTED, "rom_step_multi is not available in this build");
+}
+
+extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* value) {
+    if (!value) return fail(ROM_E_INVALID, "value is NULL");
+    switch (what) {
+        case 0: if (!c) break; *value = (int64_t)c->bytes; return ROM_OK;
+        case 1: if (!s) break; *value = (int64_t)s->bytes; return ROM_OK;
+        case 2: if (!c) break; *value = c->N; return ROM_OK;
+        case 3: if (!c) break; *value = c->R; return ROM_OK;
+        case 4: if (!c) break; *value = c->dtype; return ROM_OK;
+        case 5: if (!s) break; *value = s->B; return ROM_OK;
+        case 6: if (!s) break; *value = s->h_step; return ROM_OK;
+        default: return fail(ROM_E_INVALID, "unknown query %d", what);
+    }
+    return fail(ROM_E_INVALID, "query %d needs a %s", what, what == 1 || what >= 5 ? "state" : "context");
+}
+
+extern "C" int32_t rom_tile_count(int32_t kind) {
+    switch (kind) {
+        case 0: return dense_gemv_variants();
+        default: return 0;
+    }
+}
+
+extern "C" rom_status rom_set_tile(rom_ctx c, int32_t kind, int32_t value) {
+    if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
+    if (kind < 0 || kind > 3) return fail(ROM_E_INVALID, "unknown kernel kind %d", kind);
+    if (value < -1 || value >= rom_tile_count(kind)) return fail(ROM_E_INVALID, "tile index %d out of range", value);
+    c->tile[kind] = value;
+    c->ws_gen++;   // captured graphs bake tile shapes: force a recapture
+    return ROM_OK;
+}

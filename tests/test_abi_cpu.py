@@ -1,0 +1,63 @@
+"""The C ABI library loads on a host without a GPU, exports every symbol that
+include/rom.h declares, and rejects invalid descriptions before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2311_03694_amd as rg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_header_symbols_are_exported():
+    hdr = open(os.path.join(ROOT, "include", "rom.h")).read()
+    declared = set(re.findall(r"\b(rom_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(rg.EXPORTS), declared ^ set(rg.EXPORTS)
+    L = rg.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_desc_layout_matches_header():
+    # rom_desc: int32 N, int32 R, double nu, double dt, 6 pointers, int32 dtype,
+    # int32 max_batch, void* stream  (x86-64 / LP64 layout)
+    assert ctypes.sizeof(rg.binding.rom_desc) == 4 + 4 + 8 + 8 + 6 * 8 + 4 + 4 + 8
+    assert rg.binding.rom_desc.stream.offset == 80
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(N=0), "N must be"),
+    (dict(dt=0.0), "dt must be"),
+    (dict(dt=float("nan")), "dt must be"),
+    (dict(nu=-1.0), "nu must be"),
+    (dict(dtype=7), "unknown dtype"),
+    (dict(max_batch=0), "max_batch"),
+    (dict(C=None), "CP rank"),
+    (dict(A=None), "stiffness A"),
+])
+def test_create_rejects_invalid(kw, msg):
+    N = 4
+    args = dict(N=N, nu=1e-3, dt=1e-3, A=np.eye(N), C=np.zeros((N, N, N)), dtype="fp32", max_batch=1)
+    args.update(kw)
+    dt = args.pop("dtype")
+    with pytest.raises(rg.RomError) as ei:
+        rg.rom_create(args.pop("N"), args.pop("nu"), args.pop("dt"), args.pop("A"), dtype=dt, **args)
+    assert ei.value.status == rg.binding.ROM_E_INVALID
+    assert msg in str(ei.value)
+
+
+def test_cp_without_factors_rejected():
+    N = 4
+    with pytest.raises(rg.RomError) as ei:
+        rg.rom_create(N, 1e-3, 1e-3, np.eye(N), lam=np.ones(2), Af=np.ones((N, 2)), dtype="fp32")
+    assert "needs lambda" in str(ei.value)
+
+
+def test_null_handles_rejected():
+    with pytest.raises(rg.RomError):
+        rg.rom_query(None, None, 0)
+    assert rg.rom_tile_count(0) >= 1
+    assert rg.rom_tile_count(99) == 0
