@@ -47,22 +47,49 @@ __global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __r
 }
 
 // Dense stiffness, one trajectory: u^{n+1}_i = sum_m Hinv_k[i][m] rhs_m, one wavefront
-// per row, rhs staged in LDS.  Grid: ceil(N/4) blocks of 256 threads.
+// per row.  Each lane issues its (up to 8) 16-byte loads of the row before rhs is
+// staged in LDS; rows longer than 1024 elements loop.  Grid: ceil(N/4) blocks of 256.
+template <bool EVEN>
 __global__ __launch_bounds__(256) void k_helm_gemv(StepArgs a) {
-    extern __shared__ double sm[];
-    double* r = sm;            // [N]
-    double* red = sm + a.N;    // [4]
+    extern __shared__ __attribute__((aligned(16))) double sm[];
+    double* r = sm;                       // [N]
+    __shared__ double red[4];
+    constexpr int V = EVEN ? 2 : 1, U = 8;
+    typedef typename RawT<8 * V>::T Raw;
     const long long n = *a.step;
     const int k = bdf_order(n);
-    for (int m = threadIdx.x; m < a.N; m += blockDim.x) r[m] = a.rhs[m];
-    __syncthreads();
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int i = blockIdx.x * 4 + w;
+    const bool live = i < a.N;
+    const double* h = a.hinv + ((size_t)(k - 1) * a.N + (live ? i : 0)) * a.N;
+    Raw hv[U];
+    int m0 = lane * V;
+    auto issue = [&](int mb) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int m = mb + q * kWave * V;
+            if (live && m < a.N) hv[q] = ld_plain<8 * V>(h + m);
+        }
+    };
+    issue(m0);
+    for (int m = threadIdx.x; m < a.N; m += blockDim.x) r[m] = a.rhs[m];
+    __syncthreads();
     double e = 0.0;
-    if (i < a.N) {
-        const double* h = a.hinv + ((size_t)(k - 1) * a.N + i) * a.N;
+    if (live) {
         double s = 0.0;
-        for (int m = lane; m < a.N; m += kWave) s += h[m] * r[m];
+        while (m0 < a.N) {
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int m = m0 + q * kWave * V;
+                if (m < a.N) {
+                    const double* hd = reinterpret_cast<const double*>(&hv[q]);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) s += hd[v] * r[m + v];
+                }
+            }
+            m0 += kWave * V * U;
+            if (m0 < a.N) issue(m0);
+        }
         s = wave_sum(s);
         if (lane == 0) {
             write_level(a, n + 1, 0, i, s);
@@ -134,10 +161,11 @@ __global__ __launch_bounds__(256) void k_helm_gemm(StepArgs a) {
     finalize_step(a, n, gridDim.x, gridDim.x * gridDim.y);
 }
 
-// Batched coefficient copies of u (state creation / restart).  Grid (ceil(N/256), B).
+// Batched coefficient copies of u [B][N] (state creation / restart, batched
+// rom_nonlinear).  Grid (ceil(N/256), B).
 __global__ void k_prep_ucv(StepArgs a, const double* __restrict__ u) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
-    if (i < a.N) write_level(a, 0, b, i, u[(size_t)b * a.N + i]);
+    if (i < a.N) write_ucv(a, b, i, u[(size_t)b * a.N + i]);
 }
 
 template <class ACC>
@@ -166,8 +194,9 @@ void launch_bdf_from_partials(const StepArgs& a, int acc_f64, const void* part, 
 
 void launch_helm_apply(const StepArgs& a, hipStream_t s) {
     if (a.B == 1) {
-        const size_t lds = sizeof(double) * (a.N + 4);
-        hipLaunchKernelGGL(k_helm_gemv, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
+        const size_t lds = sizeof(double) * a.N;
+        if (a.N % 2 == 0) hipLaunchKernelGGL(k_helm_gemv<true>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL(k_helm_gemv<false>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
     } else {
         hipLaunchKernelGGL(k_helm_gemm, dim3((a.N + 31) / 32, (a.B + 63) / 64), dim3(256), 0, s, a);
     }
@@ -284,20 +313,24 @@ void helm_setup_diag(int N, double nu, double dt, const double* A_dev, double* h
 
 // ============================================================== storage conversion
 
-__global__ void k_cvt(int dt, const double* __restrict__ src, void* dst, void* dst_lo, long long n) {
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_cvt(int dt, const double* __restrict__ src, void* dst, void* dst_lo, long long rows,
+                      int cols, int dpitch) {
+    const long long n = rows * cols;
+    const long long q0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long p = q; p < n; p += stride) {
+    for (long long p = q0; p < n; p += stride) {
+        const long long r = p / cols;
+        const long long d = r * dpitch + (p - r * cols);
         const double v = src[p];
         if (dt == DT_F64) {
-            reinterpret_cast<double*>(dst)[p] = v;
+            reinterpret_cast<double*>(dst)[d] = v;
         } else if (dt == DT_F32) {
-            reinterpret_cast<float*>(dst)[p] = (float)v;
+            reinterpret_cast<float*>(dst)[d] = (float)v;
         } else {
             const float f = (float)v;
             const unsigned short h = bf16_bits(f);
-            reinterpret_cast<unsigned short*>(dst)[p] = h;
-            if (dt == DT_BF16X3) reinterpret_cast<unsigned short*>(dst_lo)[p] = bf16_bits(f - bf16_f(h));
+            reinterpret_cast<unsigned short*>(dst)[d] = h;
+            if (dt == DT_BF16X3) reinterpret_cast<unsigned short*>(dst_lo)[d] = bf16_bits(f - bf16_f(h));
         }
     }
 }
@@ -311,12 +344,12 @@ __global__ void k_cvt_lambda(int dt, const double* __restrict__ src, void* dst, 
     else reinterpret_cast<float*>(dst)[p] = (float)src[p];
 }
 
-void launch_cvt_f64_to(int dt, const double* src, void* dst, void* dst_lo, long long n,
-                       hipStream_t s) {
-    long long blocks = (n + 255) / 256;
+void launch_cvt_f64_to(int dt, const double* src, void* dst, void* dst_lo, long long rows, int cols,
+                       int dpitch, hipStream_t s) {
+    long long blocks = (rows * cols + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_cvt, dim3((unsigned)blocks), dim3(256), 0, s, dt, src, dst, dst_lo, n);
+    hipLaunchKernelGGL(k_cvt, dim3((unsigned)blocks), dim3(256), 0, s, dt, src, dst, dst_lo, rows, cols, dpitch);
 }
 
 void launch_cvt_lambda(int dt, const double* src, void* dst, long long n, hipStream_t s) {

@@ -1,0 +1,449 @@
+// k_mfma.hip -- batched contractions on the matrix cores (MFMA), for B trajectories.
+//
+// One kernel shape serves three products, Out[b][m] over a row operand A and a
+// coefficient operand X ([Bpad][Kp], trajectory-major):
+//   dense (Sec. 2, eq. Cu, the G-ROM term; "KR" = Khatri-Rao form):
+//       Y[b][i] = sum_j S[b][j] * sum_k C[i][j][k] X[b][k],   S = X = u (per format),
+//     i.e. C_(1) [N x N^2] times the Khatri-Rao columns u_b (x) u_b, without ever
+//     forming u (x) u: the inner sum over k is an MFMA GEMM of the C slab at fixed j
+//     against u, and each finished slab is weighted by u_j per column;
+//   CP projections (Sec. 3.1, eq. tc_ap):  P[b][r] = sum_k [Bf|Cf]^T[r][k] X[b][k];
+//   CP scatter:  Y[b][i] = sum_r Af[i][r] W[b][r],  W = lam .* s .* t (FP32 / FP64).
+//
+// Tiling (gfx950, wave64): a block is 4 wavefronts stacked along rows; a wavefront
+// owns MW rows x BT columns as (MW/16) x (BT/16) tiles of 16x16 MFMA accumulators.
+// The X tile [BT][kc] of the block's k-chunk is staged once in LDS (16-byte rows of
+// odd stride: conflict-free fragment reads); A fragments stream from HBM straight
+// into registers through a PF-deep prefetch ring.  The grid is (row tiles, column
+// tiles, j-ranges x k-chunks); every block writes an FP32 (FP64) partial tile that the
+// consumer sums in a fixed order.  Rows and the contracted index are padded to
+// multiples of 8 with zeros, so every 16-byte lane vector is wholly inside or outside
+// the k range and the tail is handled by predicated zero loads.
+//
+// MFMA kinds: FP64 v_mfma_f64_16x16x4f64 (a lane holds 2 consecutive k, 2 issues per
+// k-step of 8), FP32 v_mfma_f32_16x16x4f32 (4 consecutive k, 4 issues per 16), BF16
+// v_mfma_f32_16x16x32_bf16 (8 consecutive k, 1 issue per 32) and BF16X3 (three BF16
+// issues hi*hi + hi*lo + lo*hi).  A and X use the same (lane group, element) -> k map,
+// so each issue pairs matching k.  Accumulator element v of lane l is column l%16 of
+// the 16x16 tile and row 4*(l/16) + v for the FP32-accumulating kinds, row
+// l/16 + 4*v for FP64 (layouts measured on gfx950 with a one-hot probe).
+#include "kcommon.h"
+
+namespace rom {
+
+enum MK { MK_F64 = 0, MK_F32 = 1, MK_BF16 = 2, MK_BF16X3 = 3 };
+
+template <int MKD> struct MfmaT;
+template <> struct MfmaT<MK_F64> {
+    typedef double X;          // LDS element
+    typedef f64x4 Acc4;
+    typedef double Acc;
+    typedef u32x4 Frag;        // double2 bit pattern
+    static constexpr int KS = 8, VEC = 2;
+};
+template <> struct MfmaT<MK_F32> {
+    typedef float X;
+    typedef f32x4 Acc4;
+    typedef float Acc;
+    typedef u32x4 Frag;        // float4 bit pattern
+    static constexpr int KS = 16, VEC = 4;
+};
+template <> struct MfmaT<MK_BF16> {
+    typedef unsigned short X;
+    typedef f32x4 Acc4;
+    typedef float Acc;
+    typedef u32x4 Frag;        // 8 bf16
+    static constexpr int KS = 32, VEC = 8;
+};
+template <> struct MfmaT<MK_BF16X3> : MfmaT<MK_BF16> {};
+
+// ---------------------------------------------------------------- fragment loads
+
+// A fragment: VEC consecutive k of one row, converted to the MFMA operand format.
+// ADT is the operator's storage format.
+template <int ADT, int MKD>
+__device__ __forceinline__ void load_a(const void* A, const unsigned short* Alo, size_t off, bool ok,
+                                       u32x4& hi, u32x4& lo) {
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    if (!ok) {
+        hi = zero;
+        lo = zero;
+        return;
+    }
+    if constexpr (MKD == MK_F64 || (MKD == MK_F32 && ADT == DT_F32) || MKD == MK_BF16) {
+        typedef typename Store<ADT>::T T;
+        hi = ld_stream<16>(reinterpret_cast<const T*>(A) + off);
+    } else if constexpr (MKD == MK_BF16X3) {
+        hi = ld_stream<16>(reinterpret_cast<const unsigned short*>(A) + off);
+        lo = ld_stream<16>(Alo + off);
+    } else {
+        // FP32 MFMA over a BF16 / BF16X3 operator: 4 words -> 4 floats (hi + lo exact)
+        const u32x2 h = ld_stream<8>(reinterpret_cast<const unsigned short*>(A) + off);
+        float f[4] = {bf16_lo_f(h[0]), bf16_hi_f(h[0]), bf16_lo_f(h[1]), bf16_hi_f(h[1])};
+        if constexpr (ADT == DT_BF16X3) {
+            const u32x2 l = ld_stream<8>(Alo + off);
+            f[0] += bf16_lo_f(l[0]);
+            f[1] += bf16_hi_f(l[0]);
+            f[2] += bf16_lo_f(l[1]);
+            f[3] += bf16_hi_f(l[1]);
+        }
+        hi[0] = __float_as_uint(f[0]);
+        hi[1] = __float_as_uint(f[1]);
+        hi[2] = __float_as_uint(f[2]);
+        hi[3] = __float_as_uint(f[3]);
+    }
+}
+
+template <int MKD>
+__device__ __forceinline__ void mfma_step(typename MfmaT<MKD>::Acc4& acc, const u32x4& a, const u32x4& al,
+                                          const u32x4& b, const u32x4& bl) {
+    if constexpr (MKD == MK_F64) {
+        const double* ad = reinterpret_cast<const double*>(&a);
+        const double* bd = reinterpret_cast<const double*>(&b);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[0], bd[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[1], bd[1], acc, 0, 0, 0);
+    } else if constexpr (MKD == MK_F32) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[e]), __uint_as_float(b[e]), acc, 0, 0, 0);
+    } else if constexpr (MKD == MK_BF16) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                      acc, 0, 0, 0);
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                      acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bl),
+                                                      acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, b),
+                                                      acc, 0, 0, 0);
+    }
+}
+
+// ---------------------------------------------------------------- the kernel
+
+struct MfmaArgs {
+    const void* A;                 // rows: [M][J][Kp] (KR) or [M][Kp]
+    const unsigned short* Alo;     // BF16X3 low words of A
+    const void* X;                 // [Bpad][Kp] in the MFMA operand format
+    const unsigned short* Xlo;     // BF16X3 low words of X
+    const void* S;                 // [Bpad][s_stride] j-weights (KR): FP64 for MK_F64, else FP32
+    void* part;                    // [nsplit][Bpad][M] partial sums (FP64 for MK_F64, else FP32)
+    long long a_rowstride, a_jstride;
+    int M, J, Kp, Bpad, s_stride;
+    int kc, jc, nkc;               // k-chunk length (multiple of KS), j-range length, k-chunks
+    int kcp;                       // LDS row stride (elements) of the X tile
+};
+
+template <int ADT, int MKD, int MW, int BT, bool KR>
+__global__ __launch_bounds__(256) void k_mfma_rows(MfmaArgs p) {
+    typedef MfmaT<MKD> Tr;
+    typedef typename Tr::X XT;
+    typedef typename Tr::Acc4 Acc4;
+    typedef typename Tr::Acc Acc;
+    constexpr int KS = Tr::KS, VEC = Tr::VEC;
+    constexpr int FM = MW / 16, FN = BT / 16, PF = 4;
+    constexpr bool X3 = (MKD == MK_BF16X3);
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    XT* xs = reinterpret_cast<XT*>(smem);
+    unsigned short* xsl = reinterpret_cast<unsigned short*>(smem + (size_t)BT * p.kcp * sizeof(XT));
+    Acc* ss = reinterpret_cast<Acc*>(smem + (size_t)BT * p.kcp * sizeof(XT) * (X3 ? 2 : 1));
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+    const int rowbase = (blockIdx.x * 4 + w) * MW;
+    const int b0 = blockIdx.y * BT;
+    const int jr = blockIdx.z / p.nkc, kci = blockIdx.z - jr * p.nkc;
+    const int kbeg = kci * p.kc;
+    const int kend = min(p.Kp, kbeg + p.kc);
+    const int jbeg = jr * p.jc;
+    const int jend = min(p.J, jbeg + p.jc);
+    const int klen = kend - kbeg;
+
+    // ---- stage the X tile (and the j-weights of this block's j-range) in LDS
+    {
+        const int vecs_per_row = p.kc / VEC;
+        for (int idx = threadIdx.x; idx < BT * vecs_per_row; idx += blockDim.x) {
+            const int col = idx / vecs_per_row, kv = (idx - col * vecs_per_row) * VEC;
+            const int k = kbeg + kv;
+            u32x4 v = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
+            if (k < kend) {
+                const size_t off = (size_t)(b0 + col) * p.Kp + k;
+                v = ld_plain<16>(reinterpret_cast<const XT*>(p.X) + off);
+                if constexpr (X3) vl = ld_plain<16>(p.Xlo + off);
+            }
+            *reinterpret_cast<u32x4*>(xs + (size_t)col * p.kcp + kv) = v;
+            if constexpr (X3) *reinterpret_cast<u32x4*>(xsl + (size_t)col * p.kcp + kv) = vl;
+        }
+        if constexpr (KR) {
+            const int nj = jend - jbeg;
+            for (int idx = threadIdx.x; idx < BT * nj; idx += blockDim.x) {
+                const int col = idx / nj, jj = idx - col * nj;
+                ss[col * p.jc + jj] = reinterpret_cast<const Acc*>(p.S)[(size_t)(b0 + col) * p.s_stride + jbeg + jj];
+            }
+        }
+    }
+
+    // ---- per-lane row pointers (rows past M are clamped for loads, never stored)
+    size_t rowoff[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+        int r = rowbase + f * 16 + c16;
+        r = r < p.M ? r : p.M - 1;
+        rowoff[f] = (size_t)r * p.a_rowstride;
+    }
+
+    Acc4 Y[FM][FN], Z[FM][FN];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int t = 0; t < FN; ++t) {
+            Y[f][t] = Acc4{0, 0, 0, 0};
+            Z[f][t] = Acc4{0, 0, 0, 0};
+        }
+
+    const int nks = (klen + KS - 1) / KS;             // k-steps per j
+    const int nsteps = (jend > jbeg && nks > 0) ? (jend - jbeg) * nks : 0;
+
+    // prefetch ring of A fragments, PF steps deep
+    u32x4 ah[PF][FM], al[PF][FM];
+    auto issue = [&](int s, u32x4* dh, u32x4* dl) {
+        const int jj = s / nks, ks = s - jj * nks;
+        const int k = kbeg + ks * KS + g * VEC;
+        const bool ok = (s < nsteps) && (k < kend);
+        const size_t base = (size_t)(jbeg + jj) * p.a_jstride + k;
+#pragma unroll
+        for (int f = 0; f < FM; ++f) load_a<ADT, MKD>(p.A, p.Alo, rowoff[f] + (ok ? base : 0), ok, dh[f], dl[f]);
+    };
+#pragma unroll
+    for (int d = 0; d < PF; ++d) issue(d, ah[d], al[d]);
+    __syncthreads();
+
+    for (int s0 = 0; s0 < nsteps; s0 += PF) {
+#pragma unroll
+        for (int d = 0; d < PF; ++d) {
+            const int s = s0 + d;
+            if (s < nsteps) {
+                const int jj = s / nks, ks = s - jj * nks;
+                const int kl = ks * KS + g * VEC;          // k offset inside the LDS tile
+                u32x4 bh[FN], bl[FN];
+#pragma unroll
+                for (int t = 0; t < FN; ++t) {
+                    bh[t] = *reinterpret_cast<const u32x4*>(xs + (size_t)(t * 16 + c16) * p.kcp + kl);
+                    if constexpr (X3) bl[t] = *reinterpret_cast<const u32x4*>(xsl + (size_t)(t * 16 + c16) * p.kcp + kl);
+                }
+#pragma unroll
+                for (int f = 0; f < FM; ++f)
+#pragma unroll
+                    for (int t = 0; t < FN; ++t) {
+                        if constexpr (KR) mfma_step<MKD>(Z[f][t], ah[d][f], al[d][f], bh[t], bl[t]);
+                        else mfma_step<MKD>(Y[f][t], ah[d][f], al[d][f], bh[t], bl[t]);
+                    }
+                issue(s + PF, ah[d], al[d]);
+                if constexpr (KR) {
+                    if (ks == nks - 1) {
+#pragma unroll
+                        for (int t = 0; t < FN; ++t) {
+                            const Acc sj = ss[(t * 16 + c16) * p.jc + jj];
+#pragma unroll
+                            for (int f = 0; f < FM; ++f) {
+                                Y[f][t] += sj * Z[f][t];
+                                Z[f][t] = Acc4{0, 0, 0, 0};
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- partial tile out: part[z][b][row]
+    Acc* out = reinterpret_cast<Acc*>(p.part) + (size_t)blockIdx.z * p.Bpad * p.M;
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int t = 0; t < FN; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rowbase + f * 16 + (MKD == MK_F64 ? g + 4 * v : 4 * g + v);
+                if (row < p.M) out[(size_t)(b0 + t * 16 + c16) * p.M + row] = Y[f][t][v];
+            }
+}
+
+// ---------------------------------------------------------------- CP Hadamard
+
+// W[b][r] = lam_r * s_r * t_r with s, t summed over the projection partials
+// P[z][b][r] (r < Rp) and P[z][b][Rp + r]; padding trajectories get zeros.
+template <class Acc>
+__global__ void k_hadamard(const Acc* __restrict__ P, int nz, int Bpad, int B, int Rp,
+                           const Acc* __restrict__ lam, Acc* __restrict__ W) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+    if (r >= Rp) return;
+    Acc s = 0, t = 0;
+    if (b < B) {
+        for (int z = 0; z < nz; ++z) {
+            const Acc* pz = P + ((size_t)z * Bpad + b) * 2 * Rp;
+            s += pz[r];
+            t += pz[Rp + r];
+        }
+    }
+    W[(size_t)b * Rp + r] = lam[r] * s * t;
+}
+
+// ---------------------------------------------------------------- planning, launch
+
+static const MfmaTile kMfmaTiles[] = {
+    // rows per wavefront, columns per block (cap), blocks in the grid (target)
+    {32, 64, 2048}, {16, 64, 2048}, {32, 32, 2048}, {32, 64, 1024},
+    {16, 32, 4096}, {32, 64, 4096}, {16, 16, 2048}, {32, 16, 2048},
+};
+
+int mfma_variants() { return (int)(sizeof(kMfmaTiles) / sizeof(kMfmaTiles[0])); }
+MfmaTile mfma_variant(int idx) {
+    if (idx < 0 || idx >= mfma_variants()) idx = 0;
+    return kMfmaTiles[idx];
+}
+
+static int mk_ks(int mk) { return mk == MK_F64 ? 8 : mk == MK_F32 ? 16 : 32; }
+static int mk_xbytes(int mk) { return mk == MK_F64 ? 8 : mk == MK_F32 ? 4 : 2; }
+
+MfmaPlan mfma_plan(int mk, int M, int J, int Kp, int Bpad, MfmaTile t) {
+    MfmaPlan pl{};
+    pl.mw = t.mw;
+    pl.bt = t.bt;
+    while (pl.bt > 16 && Bpad % pl.bt != 0) pl.bt /= 2;
+    const int KS = mk_ks(mk), eb = mk_xbytes(mk), xb = eb * (mk == MK_BF16X3 ? 2 : 1);
+    const int kp_r = (Kp + KS - 1) / KS * KS;
+    // k-chunk: the X tile gets at most 48 KB of LDS; chunks are balanced
+    int kc_max = (49152 / (pl.bt * xb)) / KS * KS;
+    if (kc_max < KS) kc_max = KS;
+    const long long gxy = (long long)((M + 4 * pl.mw - 1) / (4 * pl.mw)) * (Bpad / pl.bt);
+    const long long want = t.target > 0 ? t.target : 2048;     // blocks in the grid
+    long long splits = (want + gxy - 1) / gxy;
+    if (splits < 1) splits = 1;
+    long long nk = (kp_r + kc_max - 1) / kc_max;
+    if (J == 1 && splits > nk) {
+        // no j index to split: cut the contracted index finer
+        const long long nk_max = kp_r / KS;
+        nk = splits < nk_max ? splits : nk_max;
+    }
+    pl.kc = (int)(((kp_r / KS) + nk - 1) / nk) * KS;
+    pl.nkc = (Kp + pl.kc - 1) / pl.kc;
+    // j-ranges: enough splits for the block target; at most 16 KB of j-weights in LDS
+    const int jc_max = 16384 / (pl.bt * (mk == MK_F64 ? 8 : 4));
+    long long njr = (splits + pl.nkc - 1) / pl.nkc;
+    if (njr < 1) njr = 1;
+    if (njr > J) njr = J;
+    pl.jc = (int)((J + njr - 1) / njr);
+    if (J > 1 && pl.jc > jc_max) pl.jc = jc_max;
+    pl.njr = (J + pl.jc - 1) / pl.jc;
+    pl.nsplit = pl.njr * pl.nkc;
+    // LDS row stride: an odd number of 16-byte units (conflict-free fragment reads)
+    int units = (pl.kc * eb + 15) / 16;
+    if (units % 2 == 0) units += 1;
+    pl.kcp = units * 16 / eb;
+    pl.lds = (size_t)pl.bt * pl.kcp * eb * (mk == MK_BF16X3 ? 2 : 1) +
+             (J > 1 ? (size_t)pl.bt * pl.jc * (mk == MK_F64 ? 8 : 4) : 0);
+    pl.grid_x = (M + 4 * pl.mw - 1) / (4 * pl.mw);
+    pl.grid_y = Bpad / pl.bt;
+    return pl;
+}
+
+template <int ADT, int MKD, int MW, int BT, bool KR>
+static void go(const MfmaArgs& a, const MfmaPlan& pl, hipStream_t s) {
+    hipLaunchKernelGGL((k_mfma_rows<ADT, MKD, MW, BT, KR>), dim3(pl.grid_x, pl.grid_y, pl.nsplit), dim3(256),
+                       pl.lds, s, a);
+}
+
+template <int ADT, int MKD, bool KR>
+static void go_tile(const MfmaArgs& a, const MfmaPlan& pl, hipStream_t s) {
+    if (pl.mw == 16) {
+        if (pl.bt == 64) go<ADT, MKD, 16, 64, KR>(a, pl, s);
+        else if (pl.bt == 32) go<ADT, MKD, 16, 32, KR>(a, pl, s);
+        else go<ADT, MKD, 16, 16, KR>(a, pl, s);
+    } else {
+        if (pl.bt == 64) go<ADT, MKD, 32, 64, KR>(a, pl, s);
+        else if (pl.bt == 32) go<ADT, MKD, 32, 32, KR>(a, pl, s);
+        else go<ADT, MKD, 32, 16, KR>(a, pl, s);
+    }
+}
+
+static MfmaArgs fill_args(const MfmaPlan& pl, const void* A, const void* Alo, const void* X, const void* Xlo,
+                          const void* S, void* part, long long rowstride, long long jstride, int M, int J,
+                          int Kp, int Bpad, int s_stride) {
+    MfmaArgs a{};
+    a.A = A;
+    a.Alo = (const unsigned short*)Alo;
+    a.X = X;
+    a.Xlo = (const unsigned short*)Xlo;
+    a.S = S;
+    a.part = part;
+    a.a_rowstride = rowstride;
+    a.a_jstride = jstride;
+    a.M = M;
+    a.J = J;
+    a.Kp = Kp;
+    a.Bpad = Bpad;
+    a.s_stride = s_stride;
+    a.kc = pl.kc;
+    a.jc = pl.jc;
+    a.nkc = pl.nkc;
+    a.kcp = pl.kcp;
+    return a;
+}
+
+static int mk_of(int dt) { return dt == DT_F64 ? MK_F64 : dt == DT_F32 ? MK_F32 : dt == DT_BF16 ? MK_BF16 : MK_BF16X3; }
+
+MfmaPlan mfma_dense_plan(int dt, int N, int Np, int Bpad, MfmaTile t) { return mfma_plan(mk_of(dt), N, N, Np, Bpad, t); }
+
+void launch_mfma_dense(int dt, const MfmaPlan& pl, const void* C, const void* Clo, int N, int Np, int Bpad,
+                       const void* X, const void* Xlo, const void* S, void* part, hipStream_t s) {
+    const MfmaArgs a = fill_args(pl, C, Clo, X, Xlo, S, part, (long long)N * Np, Np, N, N, Np, Bpad, Np);
+    switch (dt) {
+        case DT_F64: go_tile<DT_F64, MK_F64, true>(a, pl, s); break;
+        case DT_F32: go_tile<DT_F32, MK_F32, true>(a, pl, s); break;
+        case DT_BF16: go_tile<DT_BF16, MK_BF16, true>(a, pl, s); break;
+        default: go_tile<DT_BF16X3, MK_BF16X3, true>(a, pl, s); break;
+    }
+}
+
+MfmaPlan mfma_proj_plan(int dt, int Np, int Rp, int Bpad, MfmaTile t) { return mfma_plan(mk_of(dt), 2 * Rp, 1, Np, Bpad, t); }
+
+void launch_mfma_proj(int dt, const MfmaPlan& pl, const void* BCt, const void* BCt_lo, int Np, int Rp, int Bpad,
+                      const void* X, const void* Xlo, void* part, hipStream_t s) {
+    const MfmaArgs a = fill_args(pl, BCt, BCt_lo, X, Xlo, nullptr, part, Np, 0, 2 * Rp, 1, Np, Bpad, 0);
+    switch (dt) {
+        case DT_F64: go_tile<DT_F64, MK_F64, false>(a, pl, s); break;
+        case DT_F32: go_tile<DT_F32, MK_F32, false>(a, pl, s); break;
+        case DT_BF16: go_tile<DT_BF16, MK_BF16, false>(a, pl, s); break;
+        default: go_tile<DT_BF16X3, MK_BF16X3, false>(a, pl, s); break;
+    }
+}
+
+// The scatter's coefficient operand W is FP32 (FP64 for the FP64 format): the BF16
+// formats contract their BF16 factor words against it with FP32 MFMA.
+MfmaPlan mfma_scatter_plan(int dt, int N, int Rp, int Bpad, MfmaTile t) {
+    return mfma_plan(dt == DT_F64 ? MK_F64 : MK_F32, N, 1, Rp, Bpad, t);
+}
+
+void launch_mfma_scatter(int dt, const MfmaPlan& pl, const void* Af, const void* Af_lo, int N, int Rp, int Bpad,
+                         const void* W, void* part, hipStream_t s) {
+    const MfmaArgs a = fill_args(pl, Af, Af_lo, W, nullptr, nullptr, part, Rp, 0, N, 1, Rp, Bpad, 0);
+    switch (dt) {
+        case DT_F64: go_tile<DT_F64, MK_F64, false>(a, pl, s); break;
+        case DT_F32: go_tile<DT_F32, MK_F32, false>(a, pl, s); break;
+        case DT_BF16: go_tile<DT_BF16, MK_F32, false>(a, pl, s); break;
+        default: go_tile<DT_BF16X3, MK_F32, false>(a, pl, s); break;
+    }
+}
+
+void launch_hadamard(int dt, const void* P, int nz, int Bpad, int B, int Rp, const void* lam, void* W,
+                     hipStream_t s) {
+    dim3 grid((Rp + 255) / 256, Bpad);
+    if (dt == DT_F64)
+        hipLaunchKernelGGL(k_hadamard<double>, grid, dim3(256), 0, s, (const double*)P, nz, Bpad, B, Rp,
+                           (const double*)lam, (double*)W);
+    else
+        hipLaunchKernelGGL(k_hadamard<float>, grid, dim3(256), 0, s, (const float*)P, nz, Bpad, B, Rp,
+                           (const float*)lam, (float*)W);
+}
+
+}  // namespace rom

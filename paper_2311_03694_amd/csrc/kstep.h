@@ -29,13 +29,9 @@ __device__ __forceinline__ double bdf_rhs_point(const StepArgs& a, long long n, 
     return v;
 }
 
-// Store level n+1 of trajectory b at row i, and its copies for the batched kernels.
-__device__ __forceinline__ void write_level(const StepArgs& a, long long n1, int b, int i,
-                                            double u) {
-    const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N + i;
-    a.uring[(size_t)slot_of(n1) * BN + off] = u;
-    if (!a.batched) return;
-    const size_t o = (size_t)b * a.N + i;
+// Coefficient copies for the batched contraction ([Bpad][Np] layout).
+__device__ __forceinline__ void write_ucv(const StepArgs& a, int b, int i, double u) {
+    const size_t o = (size_t)b * a.Np + i;
     if (a.dtype == DT_F64) {
         reinterpret_cast<double*>(a.ucv)[o] = u;
     } else {
@@ -57,12 +53,23 @@ __device__ __forceinline__ void write_level(const StepArgs& a, long long n1, int
     }
 }
 
+// Store level n+1 of trajectory b at row i, and its copies for the batched kernels.
+__device__ __forceinline__ void write_level(const StepArgs& a, long long n1, int b, int i,
+                                            double u) {
+    const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N + i;
+    a.uring[(size_t)slot_of(n1) * BN + off] = u;
+    if (a.batched) write_ucv(a, b, i, u);
+}
+
 // Last-arriving block of a grid of `nblk_total` blocks: sums the per-block energy
-// partials epart[b][0..nblk) in block order (deterministic), logs E^{n+1}, records the
+// partials epart[b][0..nblk) in a fixed order (deterministic), logs E^{n+1}, records the
 // first non-finite level and advances the step counter.  Returns true in the block
-// that finalized.  Must be called by every thread of every block.
+// that finalized.  Must be called by every thread of every block (blockDim.x <= 1024,
+// a multiple of 64).  One trajectory: the whole block reduces (strided partial sums,
+// then the wavefront/LDS tree); a batch: one thread per trajectory, loads unrolled.
 __device__ __forceinline__ bool finalize_step(const StepArgs& a, long long n, int nblk, unsigned nblk_total) {
     __shared__ int am_last;
+    __shared__ double fred[16];
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -72,13 +79,25 @@ __device__ __forceinline__ bool finalize_step(const StepArgs& a, long long n, in
     __syncthreads();
     if (!am_last) return false;
     __threadfence();
-    for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+    if (a.B == 1) {
         double s = 0.0;
-        const volatile double* ep = a.epart + (size_t)b * nblk;
-        for (int q = 0; q < nblk; ++q) s += ep[q];
-        const double e = 0.5 * s;
-        if (n + 1 < a.elog_cap) a.elog[(size_t)(n + 1) * a.B + b] = e;
-        if (!isfinite(e)) atomicMin(a.bad, n + 1);
+        for (int q = threadIdx.x; q < nblk; q += blockDim.x) s += a.epart[q];
+        s = block_sum(s, fred);
+        if (threadIdx.x == 0) {
+            const double e = 0.5 * s;
+            if (n + 1 < a.elog_cap) a.elog[n + 1] = e;
+            if (!isfinite(e)) atomicMin(a.bad, n + 1);
+        }
+    } else {
+        for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+            const double* ep = a.epart + (size_t)b * nblk;
+            double s = 0.0;
+#pragma unroll 8
+            for (int q = 0; q < nblk; ++q) s += ep[q];
+            const double e = 0.5 * s;
+            if (n + 1 < a.elog_cap) a.elog[(size_t)(n + 1) * a.B + b] = e;
+            if (!isfinite(e)) atomicMin(a.bad, n + 1);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -55,16 +55,17 @@ struct DevBuf {
 }  // namespace
 
 struct rom_ctx_s {
-    int N = 0, R = 0, dtype = 0, max_batch = 1;
+    int N = 0, Np = 0, R = 0, Rp = 0, dtype = 0, max_batch = 1;
     double nu = 0, dt = 0;
     bool dense = true, diagA = true;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     // operators in the contraction format
-    void *C = nullptr, *Clo = nullptr;         // dense [N][N][N]
-    void *BCt = nullptr, *BCt_lo = nullptr;    // CP [2R][N]: rows Bf^T then Cf^T
-    void *Af = nullptr, *Af_lo = nullptr;      // CP [N][R]
-    void* lam = nullptr;                        // CP [R] (FP64 or FP32)
+    // (contracted indices padded with zeros: Np, Rp = N, R rounded up to multiples of 8)
+    void *C = nullptr, *Clo = nullptr;         // dense [N][N][Np]
+    void *BCt = nullptr, *BCt_lo = nullptr;    // CP [2Rp][Np]: rows Bf^T then Cf^T
+    void *Af = nullptr, *Af_lo = nullptr;      // CP [N][Rp]
+    void* lam = nullptr;                        // CP [Rp] (FP64 or FP32)
     double* hdiag = nullptr;                    // [3][N]
     double* hinv = nullptr;                     // [3][N][N]
     // workspaces (shared by every state of the context; one stream serializes use)
@@ -114,29 +115,62 @@ static size_t acc_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
 namespace {
 
 GemvTile gemv_tile(rom_ctx c) { return dense_gemv_variant(c->tile[0] < 0 ? 0 : c->tile[0]); }
+MfmaTile mfma_tile(rom_ctx c, int kind) { return mfma_variant(c->tile[kind] < 0 ? 0 : c->tile[kind]); }
 
-// Bytes of contraction workspace a batch of B needs, and its layout offsets.
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Contraction workspace of a batch of B (shared by the states of a context and by
+// rom_nonlinear): layout and launch plans.
 struct WsPlan {
-    size_t part_off = 0, part_bytes = 0;   // contraction partial sums
-    size_t st_off = 0, st_bytes = 0;       // CP projections
+    int B = 1, Bpad = 16;
+    int nchunk = 0;                 // B = 1 dense: partial chunks per row
+    MfmaPlan pd{}, pp{}, ps{};      // B > 1: dense, CP projection, CP scatter
+    size_t part_off = 0;            // dense / scatter partials, or CP s,t (B = 1)
+    size_t part2_off = 0;           // CP projection partials (B > 1)
+    size_t w_off = 0;               // CP Hadamard products W [Bpad][Rp] (B > 1)
+    size_t ucv_off = 0, ucvlo_off = 0, usc_off = 0;   // rom_nonlinear operand copies (B > 1)
     size_t total = 0;
-    int nchunk = 0;
 };
 
 WsPlan plan_ws(rom_ctx c, int B) {
     WsPlan p;
+    p.B = B;
+    p.Bpad = (B + 15) / 16 * 16;
     const size_t ab = acc_bytes(c->dtype);
-    if (c->dense) {
-        if (B == 1) {
+    size_t off = 0;
+    if (B == 1) {
+        if (c->dense) {
             p.nchunk = dense_gemv_nchunk(c->N, gemv_tile(c));
-            p.part_bytes = (size_t)p.nchunk * c->N * ab;
+            p.part_off = off;
+            off = align256(off + (size_t)p.nchunk * c->N * ab);
+        } else {
+            p.part_off = off;
+            off = align256(off + 2 * (size_t)c->Rp * ab);
         }
     } else {
-        if (B == 1) p.st_bytes = 2 * (size_t)c->R * ab;
+        const size_t eb = elem_bytes(c->dtype);
+        if (c->dense) {
+            p.pd = mfma_dense_plan(c->dtype, c->N, c->Np, p.Bpad, mfma_tile(c, 1));
+            p.part_off = off;
+            off = align256(off + (size_t)p.pd.nsplit * p.Bpad * c->N * ab);
+        } else {
+            p.pp = mfma_proj_plan(c->dtype, c->Np, c->Rp, p.Bpad, mfma_tile(c, 2));
+            p.ps = mfma_scatter_plan(c->dtype, c->N, c->Rp, p.Bpad, mfma_tile(c, 3));
+            p.part2_off = off;
+            off = align256(off + (size_t)p.pp.nsplit * p.Bpad * 2 * c->Rp * ab);
+            p.w_off = off;
+            off = align256(off + (size_t)p.Bpad * c->Rp * ab);
+            p.part_off = off;
+            off = align256(off + (size_t)p.ps.nsplit * p.Bpad * c->N * ab);
+        }
+        p.ucv_off = off;
+        off = align256(off + (size_t)p.Bpad * c->Np * eb);
+        p.ucvlo_off = off;
+        off = align256(off + (c->dtype == DT_BF16X3 ? (size_t)p.Bpad * c->Np * 2 : 0));
+        p.usc_off = off;
+        off = align256(off + (size_t)p.Bpad * c->Np * 4);
     }
-    p.part_off = 0;
-    p.st_off = (p.part_bytes + 255) & ~(size_t)255;
-    p.total = p.st_off + p.st_bytes + 256;
+    p.total = off + 256;
     return p;
 }
 
@@ -154,6 +188,8 @@ rom_status ensure_ws(rom_ctx c, size_t bytes) {
         c->ws = nullptr;
         return fail(ROM_E_NOMEM, "workspace hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
+    // the operand copies of rom_nonlinear rely on zero padding
+    hipMemsetAsync(c->ws, 0, bytes, c->stream);
     c->ws_bytes = bytes;
     c->bytes += bytes;
     c->ws_gen++;
@@ -164,14 +200,20 @@ rom_status ensure_ws(rom_ctx c, size_t bytes) {
 
 // ============================================================== create / destroy
 
-static rom_status upload_convert(rom_ctx c, const double* host, size_t n, void* dst, void* dst_lo,
-                                 double* stage, size_t stage_elems) {
+// Upload `rows` rows of `cols` FP64 values and convert them into rows of pitch `dpitch`
+// elements of the context's format (the destination padding was zeroed beforehand).
+static rom_status upload_convert(rom_ctx c, const double* host, size_t rows, int cols, int dpitch, void* dst,
+                                 void* dst_lo, double* stage, size_t stage_elems) {
     const size_t eb = elem_bytes(c->dtype);
-    for (size_t off = 0; off < n; off += stage_elems) {
-        const size_t cnt = (n - off < stage_elems) ? n - off : stage_elems;
-        HIPCHK(hipMemcpyAsync(stage, host + off, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        launch_cvt_f64_to(c->dtype, stage, (char*)dst + off * eb, dst_lo ? (char*)dst_lo + off * 2 : nullptr,
-                          (long long)cnt, c->stream);
+    size_t rows_per = stage_elems / cols;
+    if (rows_per < 1) rows_per = 1;
+    for (size_t r0 = 0; r0 < rows; r0 += rows_per) {
+        const size_t nr = (rows - r0 < rows_per) ? rows - r0 : rows_per;
+        HIPCHK(hipMemcpyAsync(stage, host + r0 * cols, nr * cols * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
+        launch_cvt_f64_to(c->dtype, stage, (char*)dst + r0 * dpitch * eb,
+                          dst_lo ? (char*)dst_lo + r0 * dpitch * 2 : nullptr, (long long)nr, cols, dpitch,
+                          c->stream);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(c->stream));
     }
@@ -210,7 +252,9 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
 
     rom_ctx c = new rom_ctx_s();
     c->N = d->N;
+    c->Np = (d->N + 7) / 8 * 8;
     c->R = d->C ? 0 : d->R;
+    c->Rp = (c->R + 7) / 8 * 8;
     c->dtype = d->dtype;
     c->nu = d->nu;
     c->dt = d->dt;
@@ -305,33 +349,45 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
     }
     HTRY(hipStreamSynchronize(c->stream));
 
-    // ---- advection operator
+    // ---- advection operator (zero-padded along the contracted index)
     const int dt = c->dtype;
     const size_t eb = elem_bytes(dt);
     const bool lo = dt == DT_BF16X3;
+    const size_t Np = c->Np;
     if (c->dense) {
-        const size_t n3 = nn * N;
+        const size_t n3 = nn * Np;
         TRY(dmalloc(&c->C, n3 * eb, &c->bytes, &c->allocs));
-        if (lo) TRY(dmalloc(&c->Clo, n3 * 2, &c->bytes, &c->allocs));
-        TRY(upload_convert(c, d->C, n3, c->C, c->Clo, stage, stage_elems));
-    } else {
-        const size_t R = c->R;
-        TRY(dmalloc(&c->BCt, 2 * R * N * eb, &c->bytes, &c->allocs));
-        TRY(dmalloc(&c->Af, R * N * eb, &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->C, 0, n3 * eb, c->stream));
         if (lo) {
-            TRY(dmalloc(&c->BCt_lo, 2 * R * N * 2, &c->bytes, &c->allocs));
-            TRY(dmalloc(&c->Af_lo, R * N * 2, &c->bytes, &c->allocs));
+            TRY(dmalloc(&c->Clo, n3 * 2, &c->bytes, &c->allocs));
+            HTRY(hipMemsetAsync(c->Clo, 0, n3 * 2, c->stream));
         }
-        TRY(dmalloc(&c->lam, R * acc_bytes(dt), &c->bytes, &c->allocs));
-        // [Bf | Cf]^T as [2R][N] (host transpose of the caller's [N][R] factors)
-        std::vector<double> t(2 * R * (size_t)N);
+        TRY(upload_convert(c, d->C, nn, (int)N, (int)Np, c->C, c->Clo, stage, stage_elems));
+    } else {
+        const size_t R = c->R, Rp = c->Rp;
+        TRY(dmalloc(&c->BCt, 2 * Rp * Np * eb, &c->bytes, &c->allocs));
+        TRY(dmalloc(&c->Af, N * Rp * eb, &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->BCt, 0, 2 * Rp * Np * eb, c->stream));
+        HTRY(hipMemsetAsync(c->Af, 0, N * Rp * eb, c->stream));
+        if (lo) {
+            TRY(dmalloc(&c->BCt_lo, 2 * Rp * Np * 2, &c->bytes, &c->allocs));
+            TRY(dmalloc(&c->Af_lo, N * Rp * 2, &c->bytes, &c->allocs));
+            HTRY(hipMemsetAsync(c->BCt_lo, 0, 2 * Rp * Np * 2, c->stream));
+            HTRY(hipMemsetAsync(c->Af_lo, 0, N * Rp * 2, c->stream));
+        }
+        TRY(dmalloc(&c->lam, Rp * acc_bytes(dt), &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->lam, 0, Rp * acc_bytes(dt), c->stream));
+        // Bf^T into rows [0, R) and Cf^T into rows [Rp, Rp + R) (host transposes of the
+        // caller's [N][R] factors)
+        std::vector<double> t(R * (size_t)N);
         for (size_t n = 0; n < (size_t)N; ++n)
-            for (size_t r = 0; r < R; ++r) {
-                t[r * N + n] = d->Bf[n * R + r];
-                t[(R + r) * N + n] = d->Cf[n * R + r];
-            }
-        TRY(upload_convert(c, t.data(), t.size(), c->BCt, c->BCt_lo, stage, stage_elems));
-        TRY(upload_convert(c, d->Af, R * N, c->Af, c->Af_lo, stage, stage_elems));
+            for (size_t r = 0; r < R; ++r) t[r * N + n] = d->Bf[n * R + r];
+        TRY(upload_convert(c, t.data(), R, (int)N, (int)Np, c->BCt, c->BCt_lo, stage, stage_elems));
+        for (size_t n = 0; n < (size_t)N; ++n)
+            for (size_t r = 0; r < R; ++r) t[r * N + n] = d->Cf[n * R + r];
+        TRY(upload_convert(c, t.data(), R, (int)N, (int)Np, (char*)c->BCt + Rp * Np * eb,
+                           lo ? (char*)c->BCt_lo + Rp * Np * 2 : nullptr, stage, stage_elems));
+        TRY(upload_convert(c, d->Af, N, (int)R, (int)Rp, c->Af, c->Af_lo, stage, stage_elems));
         HTRY(hipMemcpyAsync(stage, d->lambda, sizeof(double) * R, hipMemcpyHostToDevice, c->stream));
         launch_cvt_lambda(dt, stage, c->lam, (long long)R, c->stream);
         HTRY(hipGetLastError());
@@ -345,24 +401,40 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
 
 // ============================================================== contraction dispatch
 
-// Enqueue y = C(u)u for a batch of one whose coefficients sit at u_base (+ ring slot of
-// *stepp when stepp != NULL).  The CP path returns through the scatter kernel's
-// epilogue (mode 0: y_out; 1, 2: fused BDF update), the dense path through partials.
+// Enqueue one BDF3/EXT3 step of state s: contraction (dense or CP, single-trajectory or
+// batched kernels), FP64 update and energy; dense stiffness adds the Helmholtz apply.
 static rom_status enqueue_step(rom_ctx c, rom_state s) {
     const StepArgs& a = s->a;
     const WsPlan p = plan_ws(c, s->B);
     char* ws = (char*)c->ws;
-    if (s->B != 1) return fail(ROM_E_UNSUPPORTED, "batched states are not available in this build");
-    if (c->dense) {
-        launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, a.uring, a.step, (long long)s->B * c->N,
-                          ws + p.part_off, p.nchunk, gemv_tile(c), c->stream);
-        launch_bdf_from_partials(a, acc_f64(c->dtype), ws + p.part_off, p.nchunk, 1, c->diagA ? 1 : 0,
-                                 c->stream);
+    const int accf = acc_f64(c->dtype);
+    const int diag = c->diagA ? 1 : 0;
+    if (s->B == 1) {
+        if (c->dense) {
+            launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, a.uring, a.step, (long long)c->N,
+                              ws + p.part_off, p.nchunk, gemv_tile(c), c->stream);
+            launch_bdf_from_partials(a, accf, ws + p.part_off, p.nchunk, 1, diag, c->stream);
+        } else {
+            launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N,
+                            ws + p.part_off, c->stream);
+            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, ws + p.part_off, nullptr, &a,
+                               diag ? 1 : 2, c->stream);
+        }
     } else {
-        launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->R, a.uring, a.step, (long long)s->B * c->N,
-                        ws + p.st_off, c->stream);
-        launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->R, ws + p.st_off, nullptr, &a,
-                           c->diagA ? 1 : 2, c->stream);
+        const void* S = c->dtype == DT_F64 ? a.ucv : (const void*)a.uscale;
+        if (c->dense) {
+            launch_mfma_dense(c->dtype, p.pd, c->C, c->Clo, c->N, c->Np, p.Bpad, a.ucv, a.ucv_lo, S,
+                              ws + p.part_off, c->stream);
+            launch_bdf_from_partials(a, accf, ws + p.part_off, p.pd.nsplit, p.Bpad, diag, c->stream);
+        } else {
+            launch_mfma_proj(c->dtype, p.pp, c->BCt, c->BCt_lo, c->Np, c->Rp, p.Bpad, a.ucv, a.ucv_lo,
+                             ws + p.part2_off, c->stream);
+            launch_hadamard(c->dtype, ws + p.part2_off, p.pp.nsplit, p.Bpad, s->B, c->Rp, c->lam, ws + p.w_off,
+                            c->stream);
+            launch_mfma_scatter(c->dtype, p.ps, c->Af, c->Af_lo, c->N, c->Rp, p.Bpad, ws + p.w_off,
+                                ws + p.part_off, c->stream);
+            launch_bdf_from_partials(a, accf, ws + p.part_off, p.ps.nsplit, p.Bpad, diag, c->stream);
+        }
     }
     if (!c->diagA) launch_helm_apply(a, c->stream);
     HIPCHK(hipGetLastError());
@@ -373,19 +445,49 @@ extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_de
     if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
     if (batch < 1 || batch > c->max_batch) return fail(ROM_E_INVALID, "batch %d outside [1, %d]", batch, c->max_batch);
     if (!u_dev || !y_dev) return fail(ROM_E_INVALID, "u_dev / y_dev is NULL");
-    if (batch != 1) return fail(ROM_E_UNSUPPORTED, "batched evaluation is not available in this build");
-    const WsPlan p = plan_ws(c, 1);
+    const WsPlan p = plan_ws(c, batch);
     rom_status st = ensure_ws(c, p.total);
     if (st != ROM_OK) return st;
     char* ws = (char*)c->ws;
-    if (c->dense) {
-        launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, u_dev, nullptr, 0, ws + p.part_off, p.nchunk,
-                          gemv_tile(c), c->stream);
-        launch_sum_partials(acc_f64(c->dtype), ws + p.part_off, p.nchunk, 1, 1, c->N, y_dev, c->stream);
+    const int accf = acc_f64(c->dtype);
+    if (batch == 1) {
+        if (c->dense) {
+            launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, u_dev, nullptr, 0, ws + p.part_off, p.nchunk,
+                              gemv_tile(c), c->stream);
+            launch_sum_partials(accf, ws + p.part_off, p.nchunk, 1, 1, c->N, y_dev, c->stream);
+        } else {
+            launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, u_dev, nullptr, 0, ws + p.part_off,
+                            c->stream);
+            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, ws + p.part_off, y_dev, nullptr, 0,
+                               c->stream);
+        }
     } else {
-        launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->R, u_dev, nullptr, 0, ws + p.st_off, c->stream);
-        launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->R, ws + p.st_off, y_dev, nullptr, 0,
-                           c->stream);
+        // operand copies of the caller's u in the contraction format
+        StepArgs a{};
+        a.N = c->N;
+        a.Np = c->Np;
+        a.B = batch;
+        a.Bpad = p.Bpad;
+        a.dtype = c->dtype;
+        a.batched = 1;
+        a.ucv = ws + p.ucv_off;
+        a.ucv_lo = ws + p.ucvlo_off;
+        a.uscale = (float*)(ws + p.usc_off);
+        launch_prep_ucv(a, u_dev, c->stream);
+        const void* S = c->dtype == DT_F64 ? a.ucv : (const void*)a.uscale;
+        if (c->dense) {
+            launch_mfma_dense(c->dtype, p.pd, c->C, c->Clo, c->N, c->Np, p.Bpad, a.ucv, a.ucv_lo, S,
+                              ws + p.part_off, c->stream);
+            launch_sum_partials(accf, ws + p.part_off, p.pd.nsplit, p.Bpad, batch, c->N, y_dev, c->stream);
+        } else {
+            launch_mfma_proj(c->dtype, p.pp, c->BCt, c->BCt_lo, c->Np, c->Rp, p.Bpad, a.ucv, a.ucv_lo,
+                             ws + p.part2_off, c->stream);
+            launch_hadamard(c->dtype, ws + p.part2_off, p.pp.nsplit, p.Bpad, batch, c->Rp, c->lam, ws + p.w_off,
+                            c->stream);
+            launch_mfma_scatter(c->dtype, p.ps, c->Af, c->Af_lo, c->N, c->Rp, p.Bpad, ws + p.w_off,
+                                ws + p.part_off, c->stream);
+            launch_sum_partials(accf, ws + p.part_off, p.ps.nsplit, p.Bpad, batch, c->N, y_dev, c->stream);
+        }
     }
     HIPCHK(hipGetLastError());
     return ROM_OK;
@@ -472,7 +574,6 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
     if (batch < 1 || batch > c->max_batch) return fail(ROM_E_INVALID, "batch %d outside [1, %d]", batch, c->max_batch);
     if (!u0_host) return fail(ROM_E_INVALID, "u0_host is NULL");
-    if (batch != 1) return fail(ROM_E_UNSUPPORTED, "batched states are not available in this build");
     rom_state s = new rom_state_s();
     s->ctx = c;
     s->B = batch;
@@ -489,6 +590,7 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     } while (0)
     StepArgs& a = s->a;
     a.N = c->N;
+    a.Np = c->Np;
     a.B = batch;
     a.Bpad = s->Bpad;
     a.inv_dt = 1.0 / c->dt;
@@ -503,6 +605,18 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(dmalloc((void**)&a.step, sizeof(long long), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.ticket, sizeof(unsigned), &s->bytes, &s->allocs));
+    if (a.batched) {
+        const size_t cells = (size_t)s->Bpad * c->Np;
+        TRY(dmalloc(&a.ucv, cells * elem_bytes(c->dtype), &s->bytes, &s->allocs));
+        TRY(dmalloc((void**)&a.uscale, cells * 4, &s->bytes, &s->allocs));
+        if (c->dtype == DT_BF16X3) TRY(dmalloc(&a.ucv_lo, cells * 2, &s->bytes, &s->allocs));
+        if (hipMemsetAsync(a.ucv, 0, cells * elem_bytes(c->dtype), c->stream) != hipSuccess ||
+            hipMemsetAsync(a.uscale, 0, cells * 4, c->stream) != hipSuccess ||
+            (a.ucv_lo && hipMemsetAsync(a.ucv_lo, 0, cells * 2, c->stream) != hipSuccess)) {
+            rom_state_destroy(s);
+            return fail(ROM_E_DEVICE, "state clear failed");
+        }
+    }
     if (hipMemsetAsync(a.uring, 0, sizeof(double) * 3 * BN, c->stream) != hipSuccess ||
         hipMemsetAsync(a.yring, 0, sizeof(double) * 3 * BN, c->stream) != hipSuccess) {
         rom_state_destroy(s);
@@ -515,6 +629,7 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(reset_counters(s, 0));
     TRY(ensure_elog(s, 1024));
     hipLaunchKernelGGL(k_energy_level, dim3(batch), dim3(256), 0, c->stream, a, 0LL);
+    if (a.batched) launch_prep_ucv(a, a.uring, c->stream);
     TRY(ensure_ws(c, plan_ws(c, batch).total));
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         rom_state_destroy(s);
@@ -660,6 +775,7 @@ extern "C" rom_status rom_state_set(rom_ctx c, rom_state s, const double* u_hist
     if (st != ROM_OK) return st;
     s->h_step = step;
     hipLaunchKernelGGL(k_energy_level, dim3(s->B), dim3(256), 0, c->stream, s->a, (long long)step);
+    if (s->a.batched) launch_prep_ucv(s->a, s->a.uring + (size_t)(step % 3) * BN, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     return ROM_OK;
@@ -698,6 +814,7 @@ extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* v
 extern "C" int32_t rom_tile_count(int32_t kind) {
     switch (kind) {
         case 0: return dense_gemv_variants();
+        case 1: case 2: case 3: return mfma_variants();
         default: return 0;
     }
 }

@@ -37,20 +37,22 @@ struct StepArgs {
     const double* hdiag;     // [3][N] 1/(beta0_k/dt + nu A_ii) (diagonal stiffness)
     const double* hinv;      // [3][N][N] (beta0_k/dt I + nu A)^-1 (dense stiffness)
     // coefficient copies in the contraction's number format for the batched kernels,
-    // laid out [Bpad][N] (padding rows stay zero); written by the update of each step
+    // laid out [Bpad][Np] (padding rows and columns stay zero); written by the update
+    // of each step
     void* ucv;               // FP64 / FP32 / BF16 words (BF16X3: high words)
     void* ucv_lo;            // BF16X3 low words
     float* uscale;           // FP32 (BF16: BF16-rounded) values used as the j-weight
-    int Bpad;
+    int Bpad, Np;
     int dtype;               // Dt of the contraction
     int batched;             // 1: write ucv/uscale for the batched contraction
 };
 
 // ---------------------------------------------------------------- launchers (k_*.hip)
 
-// Operator staging (a one-time conversion, round to nearest even).
-void launch_cvt_f64_to(int dt, const double* src, void* dst, void* dst_lo, long long n,
-                       hipStream_t s);
+// Operator staging (a one-time conversion, round to nearest even): `rows` rows of
+// `cols` FP64 values into rows of pitch `dpitch` elements (padding left untouched).
+void launch_cvt_f64_to(int dt, const double* src, void* dst, void* dst_lo, long long rows, int cols,
+                       int dpitch, hipStream_t s);
 // Scaled-weight copy: out[r] = lambda[r] rounded as the dtype prescribes.
 void launch_cvt_lambda(int dt, const double* src, void* dst, long long n, hipStream_t s);
 
@@ -60,21 +62,29 @@ struct GemvTile { int threads, unroll, chunk_target; };
 int dense_gemv_variants();
 GemvTile dense_gemv_variant(int idx);
 int dense_gemv_nchunk(int N, GemvTile t);
-int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, const double* u_base,
+int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
                       const long long* stepp, long long slot_stride, void* part, int nchunk,
                       GemvTile t, hipStream_t s);
 
 // Batched MFMA contraction (dense Khatri-Rao form, CP projections and CP scatter).
-struct MfmaTile { int mw, bt, kc, jc; };
+struct MfmaTile { int mw, bt, target; };
 int mfma_variants();
 MfmaTile mfma_variant(int idx);
+// Launch geometry of one batched contraction: wave rows, block columns, k-chunk, j-range,
+// splits (= partial tiles), LDS bytes and grid.
+struct MfmaPlan {
+    int mw, bt, kc, nkc, jc, njr, nsplit, kcp;
+    size_t lds;
+    int grid_x, grid_y;
+};
 
 // CP, one trajectory.
-int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, int N, int R,
+// st [2Rp]: s then t; factors padded to Np / Rp with zeros.
+int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, int N, int Np, int Rp,
                     const double* u_base, const long long* stepp, long long slot_stride,
                     void* st, hipStream_t s);
 int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, const void* lam, int N,
-                       int R, const void* st, double* y_out, const StepArgs* sa, int mode,
+                       int Rp, const void* st, double* y_out, const StepArgs* sa, int mode,
                        hipStream_t s);
 
 // BDF update from contraction partials part[c][b][i] (row stride pb trajectories) in
@@ -96,22 +106,22 @@ int helm_setup_dense(int N, double nu, double dt, const double* A_dev, double* h
 void helm_setup_diag(int N, double nu, double dt, const double* A_dev, double* hdiag_dev,
                      hipStream_t s);
 
-// Batched contraction launchers (k_mfma.hip).
-// dense: Y partials [nchunk][Bpad][N] FP32/FP64 from C [N][N][N] and ucv [Bpad][N].
-int mfma_dense_nchunk(int N, int Bpad, MfmaTile t);
-int launch_mfma_dense(int dt, const void* C, const void* Clo, int N, int Bpad,
-                      const StepArgs& a, const void* ucv_override, const void* ucvlo_override,
-                      const float* uscale_override, void* part, MfmaTile t, hipStream_t s);
-// CP projections ST partials [nchunk][Bpad][2R] from BCt [2R][N] and ucv [Bpad][N].
-int mfma_proj_nchunk(int N, int R, MfmaTile t);
-int launch_mfma_proj(int dt, const void* BCt, const void* BCt_lo, int N, int R, int Bpad,
-                     const void* ucv, const void* ucv_lo, void* part, MfmaTile t,
+// Batched contraction launchers (k_mfma.hip).  Partials are [nsplit][Bpad][M] in the
+// accumulation type (FP64 for DT_F64, FP32 otherwise).
+//   dense:   M = N rows of C [N][N][Np], X = u [Bpad][Np] and j-weights S [Bpad][Np]
+//   proj:    M = 2Rp rows of [Bf|Cf]^T [2Rp][Np], X = u [Bpad][Np]
+//   scatter: M = N rows of Af [N][Rp], X = W [Bpad][Rp] (FP32, FP64 for DT_F64)
+MfmaPlan mfma_dense_plan(int dt, int N, int Np, int Bpad, MfmaTile t);
+void launch_mfma_dense(int dt, const MfmaPlan& pl, const void* C, const void* Clo, int N, int Np, int Bpad,
+                       const void* X, const void* Xlo, const void* S, void* part, hipStream_t s);
+MfmaPlan mfma_proj_plan(int dt, int Np, int Rp, int Bpad, MfmaTile t);
+void launch_mfma_proj(int dt, const MfmaPlan& pl, const void* BCt, const void* BCt_lo, int Np, int Rp, int Bpad,
+                      const void* X, const void* Xlo, void* part, hipStream_t s);
+MfmaPlan mfma_scatter_plan(int dt, int N, int Rp, int Bpad, MfmaTile t);
+void launch_mfma_scatter(int dt, const MfmaPlan& pl, const void* Af, const void* Af_lo, int N, int Rp, int Bpad,
+                         const void* W, void* part, hipStream_t s);
+// W[b][r] = lam_r s_r t_r from projection partials P [nz][Bpad][2Rp].
+void launch_hadamard(int dt, const void* P, int nz, int Bpad, int B, int Rp, const void* lam, void* W,
                      hipStream_t s);
-// CP scatter partials [nchunk][Bpad][N] from Af [N][R] and W = lam .* S .* T, where
-// S, T are the reduced projections summed from the proj partials.
-int mfma_scatter_nchunk(int N, int R, MfmaTile t);
-int launch_mfma_scatter(int dt, const void* Af, const void* Af_lo, const void* lam, int N,
-                        int R, int Bpad, int B, const void* proj_part, int proj_nchunk,
-                        void* part, MfmaTile t, hipStream_t s);
 
 }  // namespace rom

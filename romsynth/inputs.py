@@ -8,6 +8,9 @@ Every array is FP64 numpy, row-major:
   Af,Bf,Cf [N][R]    CP factors for positions 1, 2, 3
   u0     [B][N]      initial coefficients, one row per trajectory
 
+If the environment variable ROMSYNTH_CACHE names a directory, large dense tensors are
+saved there once and memory-mapped on later calls (same seeds give the same file).
+
 Random streams come from numpy's PCG64 seeded with SeedSequence([config, stream, seed]);
 stream 0 = factors (or the rough tensor S), 1 = tensor noise, 2 = stiffness perturbation,
 3 = initial coefficients.  The draw order inside a stream is part of the recipe and
@@ -16,6 +19,7 @@ documented next to each draw.
 from __future__ import annotations
 
 import dataclasses
+import os
 from typing import Optional
 
 import numpy as np
@@ -102,6 +106,14 @@ def skew_cp_factors(N: int, pairs: int, seed: int = 0, cfg: int = 1):
     return lam, Af, Bf, Cf
 
 
+def _cache_path(tag: str) -> Optional[str]:
+    d = os.environ.get("ROMSYNTH_CACHE")
+    if not d:
+        return None
+    os.makedirs(d, exist_ok=True)
+    return os.path.join(d, tag + ".npy")
+
+
 def dense_from_skew_cp(N: int, pairs: int, eps: float, seed: int = 0, cfg: int = 1,
                        out: Optional[np.ndarray] = None) -> np.ndarray:
     """Dense tensor T - T^(13) with T = sum_p (1/p) a_p o b_p o c_p + eps*G.
@@ -111,6 +123,9 @@ def dense_from_skew_cp(N: int, pairs: int, eps: float, seed: int = 0, cfg: int =
     standard_normal((N, N), float32) call giving G[:, j, :].  Because the skew
     transposition swaps positions 1 and 3 only, slab j of the result is T_j - T_j^T.
     """
+    cache = _cache_path(f"dense_skewcp_N{N}_P{pairs}_e{eps!r}_s{seed}_c{cfg}") if out is None else None
+    if cache and os.path.exists(cache):
+        return np.load(cache, mmap_mode="r")
     lam, Af, Bf, Cf = skew_cp_factors(N, pairs, seed, cfg)
     a = Af[:, 0::2]
     b = Bf[:, 0::2]
@@ -125,6 +140,9 @@ def dense_from_skew_cp(N: int, pairs: int, eps: float, seed: int = 0, cfg: int =
         if eps != 0.0:
             Tj += eps * rng.standard_normal((N, N), dtype=np.float32).astype(np.float64)
         out[:, j, :] = Tj - Tj.T
+    if cache:
+        np.save(cache + ".tmp.npy", out)
+        os.replace(cache + ".tmp.npy", cache)
     return out
 
 

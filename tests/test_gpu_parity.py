@@ -10,7 +10,7 @@ import pytest
 import oracle as orc
 import paper_2311_03694_amd as rg
 import romsynth
-from helpers import EVAL_TOL, TRAJ_TOL, bf16_bound, rel, traj_rel
+from helpers import TRAJ_TOL, bf16_bound, check_eval, eval_bound_cp, eval_bound_dense, rel, traj_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_dense_nonlinear(torch_gpu, dt, N):
     y = _gpu_nonlinear(torch_gpu, rom, u)
     Cr, ur = _rounded_operands(dt, [C, u])
     y_ref = orc.nonlinear_dense(Cr, ur)
-    assert rel(y, y_ref) < EVAL_TOL[dt], (dt, N, rel(y, y_ref))
+    check_eval(dt, y, y_ref, eval_bound_dense(dt, C, u))
     if dt == "bf16":
         y_ex = orc.nonlinear_dense(C, u)
         assert np.all(np.abs(y - y_ex) <= bf16_bound(C, u))
@@ -73,7 +73,7 @@ def test_cp_nonlinear(torch_gpu, dt, N, pairs):
     y = _gpu_nonlinear(torch_gpu, rom, u)
     ops = _rounded_operands(dt, [lam, Af, Bf, Cf, u])
     y_ref = orc.nonlinear_cp(*ops)
-    assert rel(y, y_ref) < EVAL_TOL[dt], (dt, N, rel(y, y_ref))
+    check_eval(dt, y, y_ref, eval_bound_cp(dt, lam, Af, Bf, Cf, u))
 
 
 def test_unit_tensor_positions(torch_gpu):
