@@ -28,8 +28,19 @@ __global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __r
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     double e = 0.0;
     if (i < a.N) {
+        // partial sums added in chunk order; loads issued 8 at a time
         double y = 0.0;
-        for (int q = 0; q < nchunk; ++q) y += (double)part[((size_t)q * pbstride + b) * a.N + i];
+        const size_t cs = (size_t)pbstride * a.N;
+        const ACC* pp = part + (size_t)b * a.N + i;
+        int q = 0;
+        for (; q + 8 <= nchunk; q += 8) {
+            ACC v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = pp[(size_t)(q + e) * cs];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) y += (double)v[e];
+        }
+        for (; q < nchunk; ++q) y += (double)pp[(size_t)q * cs];
         const double rhs = bdf_rhs_point(a, n, c, k, b, i, y);
         if (DIAG) {
             const double un = rhs * a.hdiag[(size_t)(k - 1) * a.N + i];
@@ -174,7 +185,17 @@ __global__ void k_sum_partials(const ACC* __restrict__ part, int nchunk, int B, 
     const int i = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
     if (i >= N) return;
     double s = 0.0;
-    for (int q = 0; q < nchunk; ++q) s += (double)part[((size_t)q * pbstride + b) * N + i];
+    const size_t cs = (size_t)pbstride * N;
+    const ACC* pp = part + (size_t)b * N + i;
+    int q = 0;
+    for (; q + 8 <= nchunk; q += 8) {
+        ACC v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = pp[(size_t)(q + e) * cs];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += (double)v[e];
+    }
+    for (; q < nchunk; ++q) s += (double)pp[(size_t)q * cs];
     y[(size_t)b * N + i] = s;
 }
 

@@ -60,28 +60,31 @@ template <> struct MfmaT<MK_BF16X3> : MfmaT<MK_BF16> {};
 // ---------------------------------------------------------------- fragment loads
 
 // A fragment: VEC consecutive k of one row, converted to the MFMA operand format.
-// ADT is the operator's storage format.
-template <int ADT, int MKD>
-__device__ __forceinline__ void load_a(const void* A, const unsigned short* Alo, size_t off, bool ok,
-                                       u32x4& hi, u32x4& lo) {
-    const u32x4 zero = {0u, 0u, 0u, 0u};
-    if (!ok) {
-        hi = zero;
-        lo = zero;
-        return;
-    }
+// ADT is the operator's storage format.  Loads are never predicated (the caller keeps
+// every address inside the allocation), so the compiler can count them exactly.
+// NT: non-temporal (streamed once) loads; plain loads when sibling blocks of other
+// column tiles re-read the same rows through L2.
+template <int BYTES, bool NT>
+__device__ __forceinline__ typename RawT<BYTES>::T ld_a(const void* p) {
+    if constexpr (NT) return ld_stream<BYTES>(p);
+    else return ld_plain<BYTES>(p);
+}
+
+template <int ADT, int MKD, bool NT>
+__device__ __forceinline__ void load_a(const void* A, const unsigned short* Alo, size_t off, u32x4& hi,
+                                       u32x4& lo) {
     if constexpr (MKD == MK_F64 || (MKD == MK_F32 && ADT == DT_F32) || MKD == MK_BF16) {
         typedef typename Store<ADT>::T T;
-        hi = ld_stream<16>(reinterpret_cast<const T*>(A) + off);
+        hi = ld_a<16, NT>(reinterpret_cast<const T*>(A) + off);
     } else if constexpr (MKD == MK_BF16X3) {
-        hi = ld_stream<16>(reinterpret_cast<const unsigned short*>(A) + off);
-        lo = ld_stream<16>(Alo + off);
+        hi = ld_a<16, NT>(reinterpret_cast<const unsigned short*>(A) + off);
+        lo = ld_a<16, NT>(Alo + off);
     } else {
         // FP32 MFMA over a BF16 / BF16X3 operator: 4 words -> 4 floats (hi + lo exact)
-        const u32x2 h = ld_stream<8>(reinterpret_cast<const unsigned short*>(A) + off);
+        const u32x2 h = ld_a<8, NT>(reinterpret_cast<const unsigned short*>(A) + off);
         float f[4] = {bf16_lo_f(h[0]), bf16_hi_f(h[0]), bf16_lo_f(h[1]), bf16_hi_f(h[1])};
         if constexpr (ADT == DT_BF16X3) {
-            const u32x2 l = ld_stream<8>(Alo + off);
+            const u32x2 l = ld_a<8, NT>(Alo + off);
             f[0] += bf16_lo_f(l[0]);
             f[1] += bf16_hi_f(l[0]);
             f[2] += bf16_lo_f(l[1]);
@@ -130,28 +133,42 @@ struct MfmaArgs {
     void* part;                    // [nsplit][Bpad][M] partial sums (FP64 for MK_F64, else FP32)
     long long a_rowstride, a_jstride;
     int M, J, Kp, Bpad, s_stride;
-    int kc, jc, nkc;               // k-chunk length (multiple of KS), j-range length, k-chunks
+    int kc, jc, nkc;               // k-chunk length (multiple of 2 KS), j-range length, k-chunks
     int kcp;                       // LDS row stride (elements) of the X tile
+    int gx, gy, gz;                // work grid: row tiles, column tiles, splits
 };
 
-template <int ADT, int MKD, int MW, int BT, bool KR>
+template <int ADT, int MKD, int MW, int BT, bool KR, bool NT>
 __global__ __launch_bounds__(256) void k_mfma_rows(MfmaArgs p) {
     typedef MfmaT<MKD> Tr;
     typedef typename Tr::X XT;
     typedef typename Tr::Acc4 Acc4;
     typedef typename Tr::Acc Acc;
-    constexpr int KS = Tr::KS, VEC = Tr::VEC;
-    constexpr int FM = MW / 16, FN = BT / 16, PF = 4;
+    // A lane loads two 16-byte halves (VEC elements each) of 32 contiguous bytes per row
+    // and step, so the 16 rows of a fragment are read as whole 128-byte lines; half h
+    // feeds the h-th group of MFMA issues.  One step covers KS2 = 2 KS of k.
+    constexpr int KS = Tr::KS, VEC = Tr::VEC, VEC2 = 2 * VEC, KS2 = 2 * KS;
+    constexpr int FM = MW / 16, FN = BT / 16, PF = (FM == 1 ? 6 : 3);
     constexpr bool X3 = (MKD == MK_BF16X3);
     extern __shared__ __attribute__((aligned(16))) char smem[];
     XT* xs = reinterpret_cast<XT*>(smem);
     unsigned short* xsl = reinterpret_cast<unsigned short*>(smem + (size_t)BT * p.kcp * sizeof(XT));
     Acc* ss = reinterpret_cast<Acc*>(smem + (size_t)BT * p.kcp * sizeof(XT) * (X3 ? 2 : 1));
 
+    // XCD-aware decode of the linear block id: consecutive ids go round-robin to the 8
+    // XCDs, so ids q, q+8, q+16, ... (one XCD) take consecutive work items, and the
+    // column tiles of one (row tile, split) share that XCD's L2 for their C reads.
+    const int T = p.gx * p.gy * p.gz;
+    const int per = (T + 7) / 8;
+    const int wi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (wi >= T) return;
+    const int by = wi % p.gy, rest = wi / p.gy;
+    const int bx = rest % p.gx, bz = rest / p.gx;
+
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
-    const int rowbase = (blockIdx.x * 4 + w) * MW;
-    const int b0 = blockIdx.y * BT;
-    const int jr = blockIdx.z / p.nkc, kci = blockIdx.z - jr * p.nkc;
+    const int rowbase = (bx * 4 + w) * MW;
+    const int b0 = by * BT;
+    const int jr = bz / p.nkc, kci = bz - jr * p.nkc;
     const int kbeg = kci * p.kc;
     const int kend = min(p.Kp, kbeg + p.kc);
     const int jbeg = jr * p.jc;
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(256) void k_mfma_rows(MfmaArgs p) {
 
     // ---- stage the X tile (and the j-weights of this block's j-range) in LDS
     {
-        const int vecs_per_row = p.kc / VEC;
+        const int vecs_per_row = (p.kc + KS2) / VEC;     // the tile plus its zero region
         for (int idx = threadIdx.x; idx < BT * vecs_per_row; idx += blockDim.x) {
             const int col = idx / vecs_per_row, kv = (idx - col * vecs_per_row) * VEC;
             const int k = kbeg + kv;
@@ -200,63 +217,77 @@ __global__ __launch_bounds__(256) void k_mfma_rows(MfmaArgs p) {
             Z[f][t] = Acc4{0, 0, 0, 0};
         }
 
-    const int nks = (klen + KS - 1) / KS;             // k-steps per j
-    const int nsteps = (jend > jbeg && nks > 0) ? (jend - jbeg) * nks : 0;
+    const int nks = (klen + KS2 - 1) / KS2;           // steps per j
+    const int nj = jend - jbeg;
+    const int nsteps = (nj > 0 && nks > 0) ? nj * nks : 0;
+    const int nsteps_pad = (nsteps + PF - 1) / PF * PF;
 
-    // prefetch ring of A fragments, PF steps deep
-    u32x4 ah[PF][FM], al[PF][FM];
-    auto issue = [&](int s, u32x4* dh, u32x4* dl) {
-        const int jj = s / nks, ks = s - jj * nks;
-        const int k = kbeg + ks * KS + g * VEC;
-        const bool ok = (s < nsteps) && (k < kend);
-        const size_t base = (size_t)(jbeg + jj) * p.a_jstride + k;
+    // Prefetch ring of A fragments, PF steps deep.  Steps past the end (the padding up
+    // to a multiple of PF) reload the last valid step, which stays inside the
+    // allocation, and read the zero region [kc, kc + KS2) of the LDS tile, so they add
+    // nothing.  Lane vectors may run past kend inside a row (into the next row or the
+    // zeroed slack after the tensor): they meet zeros of the LDS tile.
+    u32x4 ah[PF][FM][2], al[PF][FM][2];
+    int pj = 0, pks = 0;                                // producer position
+    auto issue = [&](int d) {
+        int jj = pj, ks = pks;
+        if (jj >= nj) { jj = nj - 1; ks = nks - 1; }
+        const size_t base = (size_t)(jbeg + jj) * p.a_jstride + kbeg + ks * KS2 + g * VEC2;
 #pragma unroll
-        for (int f = 0; f < FM; ++f) load_a<ADT, MKD>(p.A, p.Alo, rowoff[f] + (ok ? base : 0), ok, dh[f], dl[f]);
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+                load_a<ADT, MKD, NT>(p.A, p.Alo, rowoff[f] + base + h * VEC, ah[d][f][h], al[d][f][h]);
+        if (++pks == nks) { pks = 0; ++pj; }
     };
+    if (nsteps > 0) {
 #pragma unroll
-    for (int d = 0; d < PF; ++d) issue(d, ah[d], al[d]);
+        for (int d = 0; d < PF; ++d) issue(d);
+    }
     __syncthreads();
 
-    for (int s0 = 0; s0 < nsteps; s0 += PF) {
+    int cj = 0, cks = 0;                                // consumer position
+    for (int s0 = 0; s0 < nsteps_pad; s0 += PF) {
 #pragma unroll
         for (int d = 0; d < PF; ++d) {
-            const int s = s0 + d;
-            if (s < nsteps) {
-                const int jj = s / nks, ks = s - jj * nks;
-                const int kl = ks * KS + g * VEC;          // k offset inside the LDS tile
+            const int kl = (cj < nj ? cks * KS2 : p.kc) + g * VEC2;   // padding: zero region
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
                 u32x4 bh[FN], bl[FN];
 #pragma unroll
                 for (int t = 0; t < FN; ++t) {
-                    bh[t] = *reinterpret_cast<const u32x4*>(xs + (size_t)(t * 16 + c16) * p.kcp + kl);
-                    if constexpr (X3) bl[t] = *reinterpret_cast<const u32x4*>(xsl + (size_t)(t * 16 + c16) * p.kcp + kl);
+                    const size_t o = (size_t)(t * 16 + c16) * p.kcp + kl + h * VEC;
+                    bh[t] = *reinterpret_cast<const u32x4*>(xs + o);
+                    if constexpr (X3) bl[t] = *reinterpret_cast<const u32x4*>(xsl + o);
                 }
 #pragma unroll
                 for (int f = 0; f < FM; ++f)
 #pragma unroll
                     for (int t = 0; t < FN; ++t) {
-                        if constexpr (KR) mfma_step<MKD>(Z[f][t], ah[d][f], al[d][f], bh[t], bl[t]);
-                        else mfma_step<MKD>(Y[f][t], ah[d][f], al[d][f], bh[t], bl[t]);
+                        if constexpr (KR) mfma_step<MKD>(Z[f][t], ah[d][f][h], al[d][f][h], bh[t], bl[t]);
+                        else mfma_step<MKD>(Y[f][t], ah[d][f][h], al[d][f][h], bh[t], bl[t]);
                     }
-                issue(s + PF, ah[d], al[d]);
-                if constexpr (KR) {
-                    if (ks == nks - 1) {
+            }
+            issue(d);
+            if constexpr (KR) {
+                if (cks == nks - 1 && cj < nj) {
 #pragma unroll
-                        for (int t = 0; t < FN; ++t) {
-                            const Acc sj = ss[(t * 16 + c16) * p.jc + jj];
+                    for (int t = 0; t < FN; ++t) {
+                        const Acc sj = ss[(t * 16 + c16) * p.jc + cj];
 #pragma unroll
-                            for (int f = 0; f < FM; ++f) {
-                                Y[f][t] += sj * Z[f][t];
-                                Z[f][t] = Acc4{0, 0, 0, 0};
-                            }
+                        for (int f = 0; f < FM; ++f) {
+                            Y[f][t] += sj * Z[f][t];
+                            Z[f][t] = Acc4{0, 0, 0, 0};
                         }
                     }
                 }
             }
+            if (++cks == nks) { cks = 0; ++cj; }
         }
     }
 
     // ---- partial tile out: part[z][b][row]
-    Acc* out = reinterpret_cast<Acc*>(p.part) + (size_t)blockIdx.z * p.Bpad * p.M;
+    Acc* out = reinterpret_cast<Acc*>(p.part) + (size_t)bz * p.Bpad * p.M;
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -292,8 +323,8 @@ __global__ void k_hadamard(const Acc* __restrict__ P, int nz, int Bpad, int B, i
 
 static const MfmaTile kMfmaTiles[] = {
     // rows per wavefront, columns per block (cap), blocks in the grid (target)
-    {32, 64, 2048}, {16, 64, 2048}, {32, 32, 2048}, {32, 64, 1024},
-    {16, 32, 4096}, {32, 64, 4096}, {16, 16, 2048}, {32, 16, 2048},
+    {32, 64, 1024}, {16, 64, 1024}, {32, 64, 512}, {16, 64, 512},
+    {32, 64, 2048}, {16, 64, 2048}, {32, 32, 1024}, {16, 32, 1024},
 };
 
 int mfma_variants() { return (int)(sizeof(kMfmaTiles) / sizeof(kMfmaTiles[0])); }
@@ -302,7 +333,8 @@ MfmaTile mfma_variant(int idx) {
     return kMfmaTiles[idx];
 }
 
-static int mk_ks(int mk) { return mk == MK_F64 ? 8 : mk == MK_F32 ? 16 : 32; }
+// k covered by one kernel step (two MFMA issue groups)
+static int mk_ks(int mk) { return 2 * (mk == MK_F64 ? 8 : mk == MK_F32 ? 16 : 32); }
 static int mk_xbytes(int mk) { return mk == MK_F64 ? 8 : mk == MK_F32 ? 4 : 2; }
 
 MfmaPlan mfma_plan(int mk, int M, int J, int Kp, int Bpad, MfmaTile t) {
@@ -312,8 +344,8 @@ MfmaPlan mfma_plan(int mk, int M, int J, int Kp, int Bpad, MfmaTile t) {
     while (pl.bt > 16 && Bpad % pl.bt != 0) pl.bt /= 2;
     const int KS = mk_ks(mk), eb = mk_xbytes(mk), xb = eb * (mk == MK_BF16X3 ? 2 : 1);
     const int kp_r = (Kp + KS - 1) / KS * KS;
-    // k-chunk: the X tile gets at most 48 KB of LDS; chunks are balanced
-    int kc_max = (49152 / (pl.bt * xb)) / KS * KS;
+    // k-chunk: the X tile gets at most 40 KB of LDS; chunks are balanced
+    int kc_max = (40960 / (pl.bt * xb)) / KS * KS;
     if (kc_max < KS) kc_max = KS;
     const long long gxy = (long long)((M + 4 * pl.mw - 1) / (4 * pl.mw)) * (Bpad / pl.bt);
     const long long want = t.target > 0 ? t.target : 2048;     // blocks in the grid
@@ -336,21 +368,25 @@ MfmaPlan mfma_plan(int mk, int M, int J, int Kp, int Bpad, MfmaTile t) {
     if (J > 1 && pl.jc > jc_max) pl.jc = jc_max;
     pl.njr = (J + pl.jc - 1) / pl.jc;
     pl.nsplit = pl.njr * pl.nkc;
-    // LDS row stride: an odd number of 16-byte units (conflict-free fragment reads)
-    int units = (pl.kc * eb + 15) / 16;
+    // LDS row stride: the chunk plus a zero region of one step, rounded to an odd number
+    // of 16-byte units (conflict-free fragment reads)
+    int units = ((pl.kc + KS) * eb + 15) / 16;
     if (units % 2 == 0) units += 1;
     pl.kcp = units * 16 / eb;
     pl.lds = (size_t)pl.bt * pl.kcp * eb * (mk == MK_BF16X3 ? 2 : 1) +
              (J > 1 ? (size_t)pl.bt * pl.jc * (mk == MK_F64 ? 8 : 4) : 0);
     pl.grid_x = (M + 4 * pl.mw - 1) / (4 * pl.mw);
     pl.grid_y = Bpad / pl.bt;
+    pl.blocks = (pl.grid_x * pl.grid_y * pl.nsplit + 7) / 8 * 8;
     return pl;
 }
 
 template <int ADT, int MKD, int MW, int BT, bool KR>
 static void go(const MfmaArgs& a, const MfmaPlan& pl, hipStream_t s) {
-    hipLaunchKernelGGL((k_mfma_rows<ADT, MKD, MW, BT, KR>), dim3(pl.grid_x, pl.grid_y, pl.nsplit), dim3(256),
-                       pl.lds, s, a);
+    if (pl.grid_y > 1)
+        hipLaunchKernelGGL((k_mfma_rows<ADT, MKD, MW, BT, KR, false>), dim3(pl.blocks), dim3(256), pl.lds, s, a);
+    else
+        hipLaunchKernelGGL((k_mfma_rows<ADT, MKD, MW, BT, KR, true>), dim3(pl.blocks), dim3(256), pl.lds, s, a);
 }
 
 template <int ADT, int MKD, bool KR>
@@ -387,6 +423,9 @@ static MfmaArgs fill_args(const MfmaPlan& pl, const void* A, const void* Alo, co
     a.jc = pl.jc;
     a.nkc = pl.nkc;
     a.kcp = pl.kcp;
+    a.gx = pl.grid_x;
+    a.gy = pl.grid_y;
+    a.gz = pl.nsplit;
     return a;
 }
 

@@ -354,26 +354,29 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
     const size_t eb = elem_bytes(dt);
     const bool lo = dt == DT_BF16X3;
     const size_t Np = c->Np;
+    // every operator allocation ends in kSlack zero bytes: the batched kernels' lane
+    // vectors may run up to one k-step past the last row (they meet zero weights)
+    const size_t kSlack = 256;
     if (c->dense) {
         const size_t n3 = nn * Np;
-        TRY(dmalloc(&c->C, n3 * eb, &c->bytes, &c->allocs));
-        HTRY(hipMemsetAsync(c->C, 0, n3 * eb, c->stream));
+        TRY(dmalloc(&c->C, n3 * eb + kSlack, &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->C, 0, n3 * eb + kSlack, c->stream));
         if (lo) {
-            TRY(dmalloc(&c->Clo, n3 * 2, &c->bytes, &c->allocs));
-            HTRY(hipMemsetAsync(c->Clo, 0, n3 * 2, c->stream));
+            TRY(dmalloc(&c->Clo, n3 * 2 + kSlack, &c->bytes, &c->allocs));
+            HTRY(hipMemsetAsync(c->Clo, 0, n3 * 2 + kSlack, c->stream));
         }
         TRY(upload_convert(c, d->C, nn, (int)N, (int)Np, c->C, c->Clo, stage, stage_elems));
     } else {
         const size_t R = c->R, Rp = c->Rp;
-        TRY(dmalloc(&c->BCt, 2 * Rp * Np * eb, &c->bytes, &c->allocs));
-        TRY(dmalloc(&c->Af, N * Rp * eb, &c->bytes, &c->allocs));
-        HTRY(hipMemsetAsync(c->BCt, 0, 2 * Rp * Np * eb, c->stream));
-        HTRY(hipMemsetAsync(c->Af, 0, N * Rp * eb, c->stream));
+        TRY(dmalloc(&c->BCt, 2 * Rp * Np * eb + kSlack, &c->bytes, &c->allocs));
+        TRY(dmalloc(&c->Af, N * Rp * eb + kSlack, &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->BCt, 0, 2 * Rp * Np * eb + kSlack, c->stream));
+        HTRY(hipMemsetAsync(c->Af, 0, N * Rp * eb + kSlack, c->stream));
         if (lo) {
-            TRY(dmalloc(&c->BCt_lo, 2 * Rp * Np * 2, &c->bytes, &c->allocs));
-            TRY(dmalloc(&c->Af_lo, N * Rp * 2, &c->bytes, &c->allocs));
-            HTRY(hipMemsetAsync(c->BCt_lo, 0, 2 * Rp * Np * 2, c->stream));
-            HTRY(hipMemsetAsync(c->Af_lo, 0, N * Rp * 2, c->stream));
+            TRY(dmalloc(&c->BCt_lo, 2 * Rp * Np * 2 + kSlack, &c->bytes, &c->allocs));
+            TRY(dmalloc(&c->Af_lo, N * Rp * 2 + kSlack, &c->bytes, &c->allocs));
+            HTRY(hipMemsetAsync(c->BCt_lo, 0, 2 * Rp * Np * 2 + kSlack, c->stream));
+            HTRY(hipMemsetAsync(c->Af_lo, 0, N * Rp * 2 + kSlack, c->stream));
         }
         TRY(dmalloc(&c->lam, Rp * acc_bytes(dt), &c->bytes, &c->allocs));
         HTRY(hipMemsetAsync(c->lam, 0, Rp * acc_bytes(dt), c->stream));

@@ -75,7 +75,7 @@ MfmaTile mfma_variant(int idx);
 struct MfmaPlan {
     int mw, bt, kc, nkc, jc, njr, nsplit, kcp;
     size_t lds;
-    int grid_x, grid_y;
+    int grid_x, grid_y, blocks;
 };
 
 // CP, one trajectory.
