@@ -16,16 +16,16 @@ namespace rom {
 
 // y^n from contraction partials part[c][b][i] (summed over c in order), then either
 // the diagonal-stiffness update u^{n+1} = rhs / H_ii with energy and finalize, or the
-// right-hand side for the dense solve.  Grid: (ceil(N/256), B), 256 threads.
+// right-hand side for the dense solve.  Block (bx, b) of an (nbx, B) grid of 256-thread
+// blocks covers rows 256 bx .. 256 bx + 255 of trajectory b.
 template <class ACC, bool DIAG>
-__global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __restrict__ part,
-                                                      int nchunk, int pbstride) {
+__device__ __forceinline__ void bdf_partials_body(const StepArgs& a, const ACC* __restrict__ part, int nchunk,
+                                                  int pbstride, int bx, int b, int nbx, int nblk_total) {
     __shared__ double red[4];
     const long long n = *a.step;
     const int k = bdf_order(n);
     const BdfCoef c = bdf_coef(k);
-    const int b = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = bx * blockDim.x + threadIdx.x;
     double e = 0.0;
     if (i < a.N) {
         // partial sums added in chunk order; loads issued 8 at a time
@@ -36,9 +36,9 @@ __global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __r
         for (; q + 8 <= nchunk; q += 8) {
             ACC v[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = pp[(size_t)(q + e) * cs];
+            for (int e2 = 0; e2 < 8; ++e2) v[e2] = pp[(size_t)(q + e2) * cs];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) y += (double)v[e];
+            for (int e2 = 0; e2 < 8; ++e2) y += (double)v[e2];
         }
         for (; q < nchunk; ++q) y += (double)pp[(size_t)q * cs];
         const double rhs = bdf_rhs_point(a, n, c, k, b, i, y);
@@ -52,16 +52,32 @@ __global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __r
     }
     if (DIAG) {
         const double s = block_sum(e, red);
-        if (threadIdx.x == 0) a.epart[(size_t)b * gridDim.x + blockIdx.x] = s;
-        finalize_step(a, n, gridDim.x, gridDim.x * gridDim.y);
+        if (threadIdx.x == 0) a.epart[(size_t)b * nbx + bx] = s;
+        finalize_step(a, n, nbx, (unsigned)nblk_total);
     }
+}
+
+template <class ACC, bool DIAG>
+__global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __restrict__ part,
+                                                      int nchunk, int pbstride) {
+    bdf_partials_body<ACC, DIAG>(a, part, nchunk, pbstride, blockIdx.x, blockIdx.y, gridDim.x,
+                                 gridDim.x * gridDim.y);
+}
+
+template <class ACC, bool DIAG>
+__global__ __launch_bounds__(256) void k_bdf_group(const BdfJob* __restrict__ jobs, int njobs) {
+    const int p = find_job(jobs, njobs, (int)blockIdx.x);
+    const BdfJob& jb = jobs[p];
+    bdf_partials_body<ACC, DIAG>(jb.a, reinterpret_cast<const ACC*>(jb.part), jb.nchunk, jb.pb,
+                                 (int)blockIdx.x - jb.blk0, 0, jb.nblk, jb.nblk);
 }
 
 // Dense stiffness, one trajectory: u^{n+1}_i = sum_m Hinv_k[i][m] rhs_m, one wavefront
 // per row.  Each lane issues its (up to 8) 16-byte loads of the row before rhs is
-// staged in LDS; rows longer than 1024 elements loop.  Grid: ceil(N/4) blocks of 256.
+// staged in LDS; rows longer than 1024 elements loop.  Block blk of nblk covers rows
+// 4 blk .. 4 blk + 3.
 template <bool EVEN>
-__global__ __launch_bounds__(256) void k_helm_gemv(StepArgs a) {
+__device__ __forceinline__ void helm_gemv_body(const StepArgs& a, int blk, int nblk) {
     extern __shared__ __attribute__((aligned(16))) double sm[];
     double* r = sm;                       // [N]
     __shared__ double red[4];
@@ -70,7 +86,7 @@ __global__ __launch_bounds__(256) void k_helm_gemv(StepArgs a) {
     const long long n = *a.step;
     const int k = bdf_order(n);
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    const int i = blockIdx.x * 4 + w;
+    const int i = blk * 4 + w;
     const bool live = i < a.N;
     const double* h = a.hinv + ((size_t)(k - 1) * a.N + (live ? i : 0)) * a.N;
     Raw hv[U];
@@ -108,8 +124,20 @@ __global__ __launch_bounds__(256) void k_helm_gemv(StepArgs a) {
         }
     }
     const double es = block_sum(e, red);
-    if (threadIdx.x == 0) a.epart[blockIdx.x] = es;
-    finalize_step(a, n, gridDim.x, gridDim.x);
+    if (threadIdx.x == 0) a.epart[blk] = es;
+    finalize_step(a, n, nblk, (unsigned)nblk);
+}
+
+template <bool EVEN>
+__global__ __launch_bounds__(256) void k_helm_gemv(StepArgs a) {
+    helm_gemv_body<EVEN>(a, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_helm_group(const HelmJob* __restrict__ jobs, int njobs) {
+    const int p = find_job(jobs, njobs, (int)blockIdx.x);
+    const HelmJob& jb = jobs[p];
+    if (jb.a.N % 2 == 0) helm_gemv_body<true>(jb.a, (int)blockIdx.x - jb.blk0, jb.nblk);
+    else helm_gemv_body<false>(jb.a, (int)blockIdx.x - jb.blk0, jb.nblk);
 }
 
 // Dense stiffness, batch: U^{n+1}[b][i] = sum_m Hinv_k[i][m] rhs[b][m], FP64 register
@@ -211,6 +239,20 @@ void launch_bdf_from_partials(const StepArgs& a, int acc_f64, const void* part, 
         if (diag) hipLaunchKernelGGL((k_bdf_partials<float, true>), grid, dim3(256), 0, s, a, (const float*)part, nchunk, pb);
         else hipLaunchKernelGGL((k_bdf_partials<float, false>), grid, dim3(256), 0, s, a, (const float*)part, nchunk, pb);
     }
+}
+
+void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s) {
+    if (acc_f64) {
+        if (diag) hipLaunchKernelGGL((k_bdf_group<double, true>), dim3(blocks), dim3(256), 0, s, jobs_dev, njobs);
+        else hipLaunchKernelGGL((k_bdf_group<double, false>), dim3(blocks), dim3(256), 0, s, jobs_dev, njobs);
+    } else {
+        if (diag) hipLaunchKernelGGL((k_bdf_group<float, true>), dim3(blocks), dim3(256), 0, s, jobs_dev, njobs);
+        else hipLaunchKernelGGL((k_bdf_group<float, false>), dim3(blocks), dim3(256), 0, s, jobs_dev, njobs);
+    }
+}
+
+void launch_helm_group(const HelmJob* jobs_dev, int njobs, int blocks, int Nmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_helm_group, dim3(blocks), dim3(256), sizeof(double) * Nmax, s, jobs_dev, njobs);
 }
 
 void launch_helm_apply(const StepArgs& a, hipStream_t s) {

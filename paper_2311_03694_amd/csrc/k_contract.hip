@@ -16,25 +16,21 @@ namespace rom {
 // Rp + r are Cf^T u).  One wavefront per row, four per block; each lane issues its U
 // row loads before u is staged in LDS.
 template <int DT, int V, int U>
-__global__ __launch_bounds__(256) void k_cp_proj1(const typename Store<DT>::T* __restrict__ BCt,
-                                                  const unsigned short* __restrict__ BCt_lo,
-                                                  int N, int Np, int R2, const double* __restrict__ u_base,
-                                                  const long long* __restrict__ stepp,
-                                                  long long slot_stride,
-                                                  typename Store<DT>::Acc* __restrict__ st) {
+__device__ __forceinline__ void cp_proj1_body(const Proj1Job& jb, int blk) {
     typedef typename Store<DT>::T T;
     typedef typename Store<DT>::Acc Acc;
     constexpr int BYTES = V * (int)sizeof(T);
     constexpr bool X3 = (DT == DT_BF16X3);
     typedef typename RawT<BYTES>::T Raw;
     extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int N = jb.N, Np = jb.Np;
     LdsU<DT> L;
     L.bind(smem, Np);
     const int lane = threadIdx.x % kWave;
-    const int r = blockIdx.x * 4 + threadIdx.x / kWave;
-    const bool live = r < R2;
-    const T* row = BCt + (size_t)(live ? r : 0) * Np;
-    const unsigned short* rowlo = X3 ? BCt_lo + (size_t)(live ? r : 0) * Np : nullptr;
+    const int r = blk * 4 + threadIdx.x / kWave;
+    const bool live = r < jb.R2;
+    const T* row = reinterpret_cast<const T*>(jb.BCt) + (size_t)(live ? r : 0) * Np;
+    const unsigned short* rowlo = X3 ? jb.BCt_lo + (size_t)(live ? r : 0) * Np : nullptr;
     Raw rv[U], rl[U];
     int k0 = lane * V;
     auto issue = [&](int kb) {
@@ -48,7 +44,7 @@ __global__ __launch_bounds__(256) void k_cp_proj1(const typename Store<DT>::T* _
         }
     };
     issue(k0);
-    L.fill(u_base + (stepp ? (size_t)slot_of(*stepp) * slot_stride : 0), N, Np);
+    L.fill(jb.u_base + (jb.stepp ? (size_t)slot_of(*jb.stepp) * jb.slot_stride : 0), N, Np);
     __syncthreads();
     if (!live) return;
     Acc z = 0;
@@ -62,20 +58,26 @@ __global__ __launch_bounds__(256) void k_cp_proj1(const typename Store<DT>::T* _
         if (k0 < Np) issue(k0);
     }
     z = wave_sum(z);
-    if (lane == 0) st[r] = z;
+    if (lane == 0) reinterpret_cast<Acc*>(jb.st)[r] = z;
+}
+
+template <int DT, int V, int U>
+__global__ __launch_bounds__(256) void k_cp_proj1(Proj1Job jb) {
+    cp_proj1_body<DT, V, U>(jb, blockIdx.x);
+}
+template <int DT, int V, int U>
+__global__ __launch_bounds__(256) void k_cp_proj1_group(const Proj1Job* __restrict__ jobs, int njobs) {
+    const int p = find_job(jobs, njobs, (int)blockIdx.x);
+    cp_proj1_body<DT, V, U>(jobs[p], (int)blockIdx.x - jobs[p].blk0);
 }
 
 // Hadamard-and-scatter: W_r = lam_r s_r t_r in LDS, then y_i = sum_r Af[i][r] W_r, one
-// wavefront per row (row loads issued before W is formed).  MODE 0 writes y (FP64);
-// MODE 1 applies the diagonal-stiffness BDF update with energy and finalize; MODE 2
-// writes the right-hand side for the dense Helmholtz solve.
+// wavefront per row (row loads issued before W is formed).  MODE 0 writes y (FP64,
+// to y_out); MODE 1 applies the diagonal-stiffness BDF update with energy and
+// finalize; MODE 2 writes the right-hand side for the dense Helmholtz solve.
 template <int DT, int V, int U, int MODE>
-__global__ __launch_bounds__(256) void k_cp_scatter1(const typename Store<DT>::T* __restrict__ Af,
-                                                     const unsigned short* __restrict__ Af_lo,
-                                                     const typename Store<DT>::Acc* __restrict__ lam,
-                                                     int N, int R,
-                                                     const typename Store<DT>::Acc* __restrict__ st,
-                                                     double* __restrict__ y_out, StepArgs a) {
+__device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __restrict__ y_out, int blk,
+                                                 int nblk) {
     typedef typename Store<DT>::T T;
     typedef typename Store<DT>::Acc Acc;
     constexpr int BYTES = V * (int)sizeof(T);
@@ -84,11 +86,15 @@ __global__ __launch_bounds__(256) void k_cp_scatter1(const typename Store<DT>::T
     extern __shared__ __attribute__((aligned(16))) char smem[];
     Acc* W = reinterpret_cast<Acc*>(smem);
     __shared__ double red[4];
+    const int N = jb.N, R = jb.Rp;
+    const StepArgs& a = jb.a;
+    const Acc* __restrict__ lam = reinterpret_cast<const Acc*>(jb.lam);
+    const Acc* __restrict__ st = reinterpret_cast<const Acc*>(jb.st);
     const int lane = threadIdx.x % kWave;
-    const int i = blockIdx.x * 4 + threadIdx.x / kWave;
+    const int i = blk * 4 + threadIdx.x / kWave;
     const bool live = i < N;
-    const T* row = Af + (size_t)(live ? i : 0) * R;
-    const unsigned short* rowlo = X3 ? Af_lo + (size_t)(live ? i : 0) * R : nullptr;
+    const T* row = reinterpret_cast<const T*>(jb.Af) + (size_t)(live ? i : 0) * R;
+    const unsigned short* rowlo = X3 ? jb.Af_lo + (size_t)(live ? i : 0) * R : nullptr;
     Raw rv[U], rl[U];
     int r0 = lane * V;
     auto issue = [&](int rb) {
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(256) void k_cp_scatter1(const typename Store<DT>::T
         }
     };
     issue(r0);
-    for (int r = threadIdx.x; r < R; r += blockDim.x) W[r] = lam[r] * st[r] * st[R + r];   // R = Rp here
+    for (int r = threadIdx.x; r < R; r += blockDim.x) W[r] = lam[r] * st[r] * st[R + r];
     __syncthreads();
     Acc z = 0;
     if (live) {
@@ -148,67 +154,113 @@ __global__ __launch_bounds__(256) void k_cp_scatter1(const typename Store<DT>::T
         }
         if constexpr (MODE == 1) {
             const double s = block_sum(e, red);
-            if (threadIdx.x == 0) a.epart[blockIdx.x] = s;
-            finalize_step(a, n, gridDim.x, gridDim.x);
+            if (threadIdx.x == 0) a.epart[blk] = s;
+            finalize_step(a, n, nblk, (unsigned)nblk);
         }
     }
 }
 
+template <int DT, int V, int U, int MODE>
+__global__ __launch_bounds__(256) void k_cp_scatter1(Scat1Job jb, double* y_out) {
+    cp_scatter1_body<DT, V, U, MODE>(jb, y_out, blockIdx.x, gridDim.x);
+}
+template <int DT, int V, int U, int MODE>
+__global__ __launch_bounds__(256) void k_cp_scatter1_group(const Scat1Job* __restrict__ jobs, int njobs) {
+    const int p = find_job(jobs, njobs, (int)blockIdx.x);
+    cp_scatter1_body<DT, V, U, MODE>(jobs[p], nullptr, (int)blockIdx.x - jobs[p].blk0, jobs[p].nblk);
+}
+
+// ---------------------------------------------------------------- launchers
+
 template <int DT>
-static void proj1_go(const void* BCt, const void* BCt_lo, int N, int Np, int Rp, const double* u,
-                     const long long* st, long long ss, void* out, hipStream_t s) {
-    typedef typename Store<DT>::T T;
-    typedef typename Store<DT>::Acc Acc;
-    constexpr int V = 16 / (int)sizeof(T);
-    const size_t lds = LdsU<DT>::bytes(Np);
-    hipLaunchKernelGGL((k_cp_proj1<DT, V, 4>), dim3((2 * Rp + 3) / 4), dim3(256), lds, s, (const T*)BCt,
-                       (const unsigned short*)BCt_lo, N, Np, 2 * Rp, u, st, ss, (Acc*)out);
+static void proj1_go(const Proj1Job& jb, const Proj1Job* jobs, int njobs, int blocks, int Npmax, hipStream_t s) {
+    constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
+    const size_t lds = LdsU<DT>::bytes(Npmax);
+    if (jobs) hipLaunchKernelGGL((k_cp_proj1_group<DT, V, 4>), dim3((unsigned)blocks), dim3(256), lds, s, jobs, njobs);
+    else hipLaunchKernelGGL((k_cp_proj1<DT, V, 4>), dim3((unsigned)jb.nblk), dim3(256), lds, s, jb);
+}
+
+static void proj1_dispatch(int dt, const Proj1Job& jb, const Proj1Job* jobs, int njobs, int blocks, int Npmax,
+                           hipStream_t s) {
+    switch (dt) {
+        case DT_F64: proj1_go<DT_F64>(jb, jobs, njobs, blocks, Npmax, s); break;
+        case DT_F32: proj1_go<DT_F32>(jb, jobs, njobs, blocks, Npmax, s); break;
+        case DT_BF16: proj1_go<DT_BF16>(jb, jobs, njobs, blocks, Npmax, s); break;
+        default: proj1_go<DT_BF16X3>(jb, jobs, njobs, blocks, Npmax, s); break;
+    }
 }
 
 int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, int N, int Np, int Rp,
                     const double* u_base, const long long* stepp, long long slot_stride,
                     void* st, hipStream_t s) {
-    switch (dt) {
-        case DT_F64: proj1_go<DT_F64>(BCt, BCt_lo, N, Np, Rp, u_base, stepp, slot_stride, st, s); break;
-        case DT_F32: proj1_go<DT_F32>(BCt, BCt_lo, N, Np, Rp, u_base, stepp, slot_stride, st, s); break;
-        case DT_BF16: proj1_go<DT_BF16>(BCt, BCt_lo, N, Np, Rp, u_base, stepp, slot_stride, st, s); break;
-        default: proj1_go<DT_BF16X3>(BCt, BCt_lo, N, Np, Rp, u_base, stepp, slot_stride, st, s); break;
-    }
+    Proj1Job jb{};
+    jb.BCt = BCt;
+    jb.BCt_lo = (const unsigned short*)BCt_lo;
+    jb.N = N;
+    jb.Np = Np;
+    jb.R2 = 2 * Rp;
+    jb.u_base = u_base;
+    jb.stepp = stepp;
+    jb.slot_stride = slot_stride;
+    jb.st = st;
+    jb.nblk = (2 * Rp + 3) / 4;
+    proj1_dispatch(dt, jb, nullptr, 0, 0, Np, s);
     return 0;
 }
 
+void launch_cp_proj1_group(int dt, const Proj1Job* jobs_dev, int njobs, int blocks, int Npmax, hipStream_t s) {
+    Proj1Job none{};
+    proj1_dispatch(dt, none, jobs_dev, njobs, blocks, Npmax, s);
+}
+
 template <int DT, int MODE>
-static void scat1_go(const void* Af, const void* Af_lo, const void* lam, int N, int Rp,
-                     const void* st, double* y, const StepArgs* sa, hipStream_t s) {
-    typedef typename Store<DT>::T T;
+static void scat1_go(const Scat1Job& jb, double* y, const Scat1Job* jobs, int njobs, int blocks, int Rpmax,
+                     hipStream_t s) {
     typedef typename Store<DT>::Acc Acc;
-    constexpr int V = 16 / (int)sizeof(T);
-    const size_t lds = sizeof(Acc) * Rp;
-    StepArgs a{};
-    if (sa) a = *sa;
-    hipLaunchKernelGGL((k_cp_scatter1<DT, V, 8, MODE>), dim3((N + 3) / 4), dim3(256), lds, s,
-                       (const T*)Af, (const unsigned short*)Af_lo, (const Acc*)lam, N, Rp,
-                       (const Acc*)st, y, a);
+    constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
+    const size_t lds = sizeof(Acc) * Rpmax;
+    if (jobs) hipLaunchKernelGGL((k_cp_scatter1_group<DT, V, 8, MODE>), dim3((unsigned)blocks), dim3(256), lds, s, jobs, njobs);
+    else hipLaunchKernelGGL((k_cp_scatter1<DT, V, 8, MODE>), dim3((unsigned)jb.nblk), dim3(256), lds, s, jb, y);
 }
 
 template <int DT>
-static void scat1_mode(int mode, const void* Af, const void* Af_lo, const void* lam, int N, int Rp,
-                       const void* st, double* y, const StepArgs* sa, hipStream_t s) {
-    if (mode == 0) scat1_go<DT, 0>(Af, Af_lo, lam, N, Rp, st, y, sa, s);
-    else if (mode == 1) scat1_go<DT, 1>(Af, Af_lo, lam, N, Rp, st, y, sa, s);
-    else scat1_go<DT, 2>(Af, Af_lo, lam, N, Rp, st, y, sa, s);
+static void scat1_mode(int mode, const Scat1Job& jb, double* y, const Scat1Job* jobs, int njobs, int blocks, int Rpmax,
+                       hipStream_t s) {
+    if (mode == 0) scat1_go<DT, 0>(jb, y, jobs, njobs, blocks, Rpmax, s);
+    else if (mode == 1) scat1_go<DT, 1>(jb, y, jobs, njobs, blocks, Rpmax, s);
+    else scat1_go<DT, 2>(jb, y, jobs, njobs, blocks, Rpmax, s);
+}
+
+static void scat1_dispatch(int dt, int mode, const Scat1Job& jb, double* y, const Scat1Job* jobs, int njobs,
+                           int blocks, int Rpmax, hipStream_t s) {
+    switch (dt) {
+        case DT_F64: scat1_mode<DT_F64>(mode, jb, y, jobs, njobs, blocks, Rpmax, s); break;
+        case DT_F32: scat1_mode<DT_F32>(mode, jb, y, jobs, njobs, blocks, Rpmax, s); break;
+        case DT_BF16: scat1_mode<DT_BF16>(mode, jb, y, jobs, njobs, blocks, Rpmax, s); break;
+        default: scat1_mode<DT_BF16X3>(mode, jb, y, jobs, njobs, blocks, Rpmax, s); break;
+    }
 }
 
 int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, const void* lam, int N,
                        int Rp, const void* st, double* y_out, const StepArgs* sa, int mode,
                        hipStream_t s) {
-    switch (dt) {
-        case DT_F64: scat1_mode<DT_F64>(mode, Af, Af_lo, lam, N, Rp, st, y_out, sa, s); break;
-        case DT_F32: scat1_mode<DT_F32>(mode, Af, Af_lo, lam, N, Rp, st, y_out, sa, s); break;
-        case DT_BF16: scat1_mode<DT_BF16>(mode, Af, Af_lo, lam, N, Rp, st, y_out, sa, s); break;
-        default: scat1_mode<DT_BF16X3>(mode, Af, Af_lo, lam, N, Rp, st, y_out, sa, s); break;
-    }
+    Scat1Job jb{};
+    jb.Af = Af;
+    jb.Af_lo = (const unsigned short*)Af_lo;
+    jb.lam = lam;
+    jb.N = N;
+    jb.Rp = Rp;
+    jb.st = st;
+    if (sa) jb.a = *sa;
+    jb.nblk = (N + 3) / 4;
+    scat1_dispatch(dt, mode, jb, y_out, nullptr, 0, 0, Rp, s);
     return 0;
+}
+
+void launch_cp_scatter1_group(int dt, int mode, const Scat1Job* jobs_dev, int njobs, int blocks, int Rpmax,
+                              hipStream_t s) {
+    Scat1Job none{};
+    scat1_dispatch(dt, mode, none, nullptr, jobs_dev, njobs, blocks, Rpmax, s);
 }
 
 }  // namespace rom

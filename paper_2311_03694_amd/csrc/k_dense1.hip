@@ -17,13 +17,7 @@
 namespace rom {
 
 template <int DT, int V, int UNR, int NT>
-__global__ __launch_bounds__(NT) void k_dense_gemv(const typename Store<DT>::T* __restrict__ C,
-                                                   const unsigned short* __restrict__ Clo, int N,
-                                                   int Np, const double* __restrict__ u_base,
-                                                   const long long* __restrict__ stepp,
-                                                   long long slot_stride,
-                                                   typename Store<DT>::Acc* __restrict__ part,
-                                                   int nchunk, long long chunk_len) {
+__device__ __forceinline__ void dense_gemv_body(const GemvJob& jb, int blk) {
     typedef typename Store<DT>::T T;
     typedef typename Store<DT>::Acc Acc;
     typedef typename RawT<V * (int)sizeof(T)>::T Raw;
@@ -31,16 +25,19 @@ __global__ __launch_bounds__(NT) void k_dense_gemv(const typename Store<DT>::T* 
     constexpr bool X3 = (DT == DT_BF16X3);
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ Acc red[NT / kWave];
+    const int N = jb.N, Np = jb.Np, nchunk = jb.nchunk;
+    const long long chunk_len = jb.chunk_len;
+    const T* __restrict__ C = reinterpret_cast<const T*>(jb.C);
     LdsU<DT> L;
     L.bind(smem, Np);
 
-    const int i = blockIdx.x / nchunk;
-    const int c = blockIdx.x - i * nchunk;
+    const int i = blk / nchunk;
+    const int c = blk - i * nchunk;
     const long long NN = (long long)N * Np;
     const long long m0 = (long long)c * chunk_len;
     const long long m1 = (m0 + chunk_len < NN) ? m0 + chunk_len : NN;
     const T* row = C + (size_t)i * NN;
-    const unsigned short* rowlo = X3 ? Clo + (size_t)i * NN : nullptr;
+    const unsigned short* rowlo = X3 ? jb.Clo + (size_t)i * NN : nullptr;
 
     constexpr int STEP = NT * V;
     const int dj = STEP / Np, dk = STEP - (STEP / Np) * Np;
@@ -66,7 +63,7 @@ __global__ __launch_bounds__(NT) void k_dense_gemv(const typename Store<DT>::T* 
     };
 
     if (m < m1) issue(m);
-    L.fill(u_base + (stepp ? (size_t)slot_of(*stepp) * slot_stride : 0), N, Np);
+    L.fill(jb.u_base + (jb.stepp ? (size_t)slot_of(*jb.stepp) * jb.slot_stride : 0), N, Np);
     __syncthreads();
 
     Acc acc = 0;
@@ -79,7 +76,20 @@ __global__ __launch_bounds__(NT) void k_dense_gemv(const typename Store<DT>::T* 
         if (m < m1) issue(m);
     }
     const Acc s = block_sum(acc, red);
-    if (threadIdx.x == 0) part[(size_t)c * N + i] = s;
+    if (threadIdx.x == 0) reinterpret_cast<Acc*>(jb.part)[(size_t)c * N + i] = s;
+}
+
+template <int DT, int V, int UNR, int NT>
+__global__ __launch_bounds__(NT) void k_dense_gemv(GemvJob jb) {
+    dense_gemv_body<DT, V, UNR, NT>(jb, blockIdx.x);
+}
+
+// Several contractions of different N in one launch: block q runs block
+// q - jobs[p].blk0 of the job p whose block range holds q.
+template <int DT, int V, int UNR, int NT>
+__global__ __launch_bounds__(NT) void k_dense_gemv_group(const GemvJob* __restrict__ jobs, int njobs) {
+    const int p = find_job(jobs, njobs, (int)blockIdx.x);
+    dense_gemv_body<DT, V, UNR, NT>(jobs[p], (int)blockIdx.x - jobs[p].blk0);
 }
 
 static const GemvTile kGemvTiles[] = {
@@ -100,43 +110,71 @@ int dense_gemv_nchunk(int N, GemvTile t) {
     return (int)nchunk;
 }
 
+static long long chunk_len_of(int dt, int N, int Np, int nchunk, GemvTile t) {
+    const int V = dt == DT_F64 ? 2 : dt == DT_F32 ? 4 : 8;
+    const long long NN = (long long)N * Np;
+    const long long step = (long long)t.threads * V;
+    // a multiple of threads*V covering the row in nchunk pieces (trailing pieces may be
+    // empty; their blocks write a zero partial)
+    long long len = (NN + nchunk - 1) / nchunk;
+    return ((len + step - 1) / step) * step;
+}
+
+GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
+                      const long long* stepp, long long slot_stride, void* part, int nchunk, GemvTile t) {
+    GemvJob jb{};
+    jb.C = C;
+    jb.Clo = (const unsigned short*)Clo;
+    jb.N = N;
+    jb.Np = Np;
+    jb.u_base = u_base;
+    jb.stepp = stepp;
+    jb.slot_stride = slot_stride;
+    jb.part = part;
+    jb.nchunk = nchunk;
+    jb.chunk_len = chunk_len_of(dt, N, Np, nchunk, t);
+    jb.blk0 = 0;
+    jb.nblk = N * nchunk;
+    return jb;
+}
+
 template <int DT, int UNR>
-static void gemv_go(const void* C, const void* Clo, int N, int Np, const double* u, const long long* st,
-                    long long ss, void* part, int nchunk, long long len, hipStream_t s) {
-    typedef typename Store<DT>::T T;
-    typedef typename Store<DT>::Acc Acc;
-    constexpr int V = 16 / (int)sizeof(T);
-    const size_t lds = LdsU<DT>::bytes(Np);
-    hipLaunchKernelGGL((k_dense_gemv<DT, V, UNR, 256>), dim3((unsigned)N * nchunk), dim3(256), lds, s,
-                       (const T*)C, (const unsigned short*)Clo, N, Np, u, st, ss, (Acc*)part, nchunk, len);
+static void gemv_go(const GemvJob& jb, const GemvJob* jobs, int njobs, int blocks, int Npmax, hipStream_t s) {
+    constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
+    const size_t lds = LdsU<DT>::bytes(Npmax);
+    if (jobs) hipLaunchKernelGGL((k_dense_gemv_group<DT, V, UNR, 256>), dim3((unsigned)blocks), dim3(256), lds, s, jobs, njobs);
+    else hipLaunchKernelGGL((k_dense_gemv<DT, V, UNR, 256>), dim3((unsigned)jb.nblk), dim3(256), lds, s, jb);
 }
 
 template <int DT>
-static int gemv_dt(int unr, const void* C, const void* Clo, int N, int Np, const double* u,
-                   const long long* st, long long ss, void* part, int nchunk, long long len,
-                   hipStream_t s) {
-    if (unr == 2) gemv_go<DT, 2>(C, Clo, N, Np, u, st, ss, part, nchunk, len, s);
-    else if (unr == 8) gemv_go<DT, 8>(C, Clo, N, Np, u, st, ss, part, nchunk, len, s);
-    else gemv_go<DT, 4>(C, Clo, N, Np, u, st, ss, part, nchunk, len, s);
-    return 0;
+static void gemv_dt(int unr, const GemvJob& jb, const GemvJob* jobs, int njobs, int blocks, int Npmax, hipStream_t s) {
+    if (unr == 2) gemv_go<DT, 2>(jb, jobs, njobs, blocks, Npmax, s);
+    else if (unr == 8) gemv_go<DT, 8>(jb, jobs, njobs, blocks, Npmax, s);
+    else gemv_go<DT, 4>(jb, jobs, njobs, blocks, Npmax, s);
+}
+
+static void gemv_dispatch(int dt, int unr, const GemvJob& jb, const GemvJob* jobs, int njobs, int blocks, int Npmax,
+                          hipStream_t s) {
+    switch (dt) {
+        case DT_F64: gemv_dt<DT_F64>(unr, jb, jobs, njobs, blocks, Npmax, s); break;
+        case DT_F32: gemv_dt<DT_F32>(unr, jb, jobs, njobs, blocks, Npmax, s); break;
+        case DT_BF16: gemv_dt<DT_BF16>(unr, jb, jobs, njobs, blocks, Npmax, s); break;
+        default: gemv_dt<DT_BF16X3>(unr, jb, jobs, njobs, blocks, Npmax, s); break;
+    }
 }
 
 int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
                       const long long* stepp, long long slot_stride, void* part, int nchunk,
                       GemvTile t, hipStream_t s) {
-    const int V = dt == DT_F64 ? 2 : dt == DT_F32 ? 4 : 8;
-    const long long NN = (long long)N * Np;
-    const long long step = (long long)t.threads * V;
-    // chunk length: a multiple of threads*V covering the row in nchunk pieces (the
-    // last pieces may be empty; their blocks write a zero partial)
-    long long len = (NN + nchunk - 1) / nchunk;
-    len = ((len + step - 1) / step) * step;
-    switch (dt) {
-        case DT_F64: return gemv_dt<DT_F64>(t.unroll, C, Clo, N, Np, u_base, stepp, slot_stride, part, nchunk, len, s);
-        case DT_F32: return gemv_dt<DT_F32>(t.unroll, C, Clo, N, Np, u_base, stepp, slot_stride, part, nchunk, len, s);
-        case DT_BF16: return gemv_dt<DT_BF16>(t.unroll, C, Clo, N, Np, u_base, stepp, slot_stride, part, nchunk, len, s);
-        default: return gemv_dt<DT_BF16X3>(t.unroll, C, Clo, N, Np, u_base, stepp, slot_stride, part, nchunk, len, s);
-    }
+    const GemvJob jb = make_gemv_job(dt, C, Clo, N, Np, u_base, stepp, slot_stride, part, nchunk, t);
+    gemv_dispatch(dt, t.unroll, jb, nullptr, 0, 0, Np, s);
+    return 0;
+}
+
+void launch_dense_gemv_group(int dt, const GemvJob* jobs_dev, int njobs, int blocks, int Npmax, GemvTile t,
+                             hipStream_t s) {
+    GemvJob none{};
+    gemv_dispatch(dt, t.unroll, none, jobs_dev, njobs, blocks, Npmax, s);
 }
 
 }  // namespace rom

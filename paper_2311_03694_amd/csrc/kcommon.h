@@ -103,6 +103,20 @@ __device__ __forceinline__ T block_sum(T v, T* scratch) {
     return s;
 }
 
+// ---------------------------------------------------------------- grouped launches
+
+// Job p with jobs[p].blk0 <= q < jobs[p+1].blk0 (jobs sorted by blk0, blk0[0] = 0).
+template <class J>
+__device__ __forceinline__ int find_job(const J* jobs, int n, int q) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].blk0 <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------- BDFk/EXTk weights
 
 // Row k-1 holds order k: beta0, beta_1..beta_3 (new level on the left, old levels

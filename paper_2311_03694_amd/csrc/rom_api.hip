@@ -84,9 +84,13 @@ struct rom_state_s {
     StepArgs a{};
     long long h_step = 0;
     long long elog_base = 0;
+    // single-trajectory states own their contraction scratch (partial sums or CP
+    // projections), so several states of one context can be stepped in one grouped launch
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int sgen = 0;                       // bumped when scratch or the energy log moves
     hipGraphExec_t graph = nullptr;
-    int graph_gen = -1;
-    double* graph_elog = nullptr;
+    int graph_gen = -1, graph_sgen = -1;
     bool pending = false;
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -404,42 +408,44 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
 
 // ============================================================== contraction dispatch
 
-// Enqueue one BDF3/EXT3 step of state s: contraction (dense or CP, single-trajectory or
-// batched kernels), FP64 update and energy; dense stiffness adds the Helmholtz apply.
-static rom_status enqueue_step(rom_ctx c, rom_state s) {
+// Enqueue one BDF3/EXT3 step of state s on `stream`: contraction (dense or CP,
+// single-trajectory or batched kernels), FP64 update and energy; dense stiffness adds
+// the Helmholtz apply.
+static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream) {
     const StepArgs& a = s->a;
     const WsPlan p = plan_ws(c, s->B);
-    char* ws = (char*)c->ws;
     const int accf = acc_f64(c->dtype);
     const int diag = c->diagA ? 1 : 0;
     if (s->B == 1) {
+        char* ws = (char*)s->scratch;
         if (c->dense) {
             launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, a.uring, a.step, (long long)c->N,
-                              ws + p.part_off, p.nchunk, gemv_tile(c), c->stream);
-            launch_bdf_from_partials(a, accf, ws + p.part_off, p.nchunk, 1, diag, c->stream);
+                              ws + p.part_off, p.nchunk, gemv_tile(c), stream);
+            launch_bdf_from_partials(a, accf, ws + p.part_off, p.nchunk, 1, diag, stream);
         } else {
             launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N,
-                            ws + p.part_off, c->stream);
+                            ws + p.part_off, stream);
             launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, ws + p.part_off, nullptr, &a,
-                               diag ? 1 : 2, c->stream);
+                               diag ? 1 : 2, stream);
         }
     } else {
+        char* ws = (char*)c->ws;
         const void* S = c->dtype == DT_F64 ? a.ucv : (const void*)a.uscale;
         if (c->dense) {
             launch_mfma_dense(c->dtype, p.pd, c->C, c->Clo, c->N, c->Np, p.Bpad, a.ucv, a.ucv_lo, S,
-                              ws + p.part_off, c->stream);
-            launch_bdf_from_partials(a, accf, ws + p.part_off, p.pd.nsplit, p.Bpad, diag, c->stream);
+                              ws + p.part_off, stream);
+            launch_bdf_from_partials(a, accf, ws + p.part_off, p.pd.nsplit, p.Bpad, diag, stream);
         } else {
             launch_mfma_proj(c->dtype, p.pp, c->BCt, c->BCt_lo, c->Np, c->Rp, p.Bpad, a.ucv, a.ucv_lo,
-                             ws + p.part2_off, c->stream);
+                             ws + p.part2_off, stream);
             launch_hadamard(c->dtype, ws + p.part2_off, p.pp.nsplit, p.Bpad, s->B, c->Rp, c->lam, ws + p.w_off,
-                            c->stream);
+                            stream);
             launch_mfma_scatter(c->dtype, p.ps, c->Af, c->Af_lo, c->N, c->Rp, p.Bpad, ws + p.w_off,
-                                ws + p.part_off, c->stream);
-            launch_bdf_from_partials(a, accf, ws + p.part_off, p.ps.nsplit, p.Bpad, diag, c->stream);
+                                ws + p.part_off, stream);
+            launch_bdf_from_partials(a, accf, ws + p.part_off, p.ps.nsplit, p.Bpad, diag, stream);
         }
     }
-    if (!c->diagA) launch_helm_apply(a, c->stream);
+    if (!c->diagA) launch_helm_apply(a, stream);
     HIPCHK(hipGetLastError());
     return ROM_OK;
 }
@@ -547,6 +553,30 @@ rom_status ensure_elog(rom_state s, long long levels_needed) {
     s->a.elog = nl;
     s->a.elog_cap = cap;
     s->bytes += sizeof(double) * cap * s->B;
+    s->sgen++;
+    return ROM_OK;
+}
+
+// Contraction scratch of a single-trajectory state (grows with the kernel tiles).
+rom_status ensure_scratch(rom_state s) {
+    if (s->B != 1) return ROM_OK;
+    const size_t need = plan_ws(s->ctx, 1).total;
+    if (need <= s->scratch_bytes) return ROM_OK;
+    if (s->scratch) {
+        hipStreamSynchronize(s->ctx->stream);
+        hipFree(s->scratch);
+        s->bytes -= s->scratch_bytes;
+        s->scratch = nullptr;
+        s->scratch_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&s->scratch, need);
+    if (e != hipSuccess) {
+        s->scratch = nullptr;
+        return fail(ROM_E_NOMEM, "state scratch hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
+    }
+    s->scratch_bytes = need;
+    s->bytes += need;
+    s->sgen++;
     return ROM_OK;
 }
 
@@ -568,6 +598,7 @@ extern "C" void rom_state_destroy(rom_state s) {
     if (s->graph) hipGraphExecDestroy(s->graph);
     for (void* p : s->allocs) hipFree(p);
     if (s->a.elog) hipFree(s->a.elog);
+    if (s->scratch) hipFree(s->scratch);
     delete s;
 }
 
@@ -634,6 +665,7 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     hipLaunchKernelGGL(k_energy_level, dim3(batch), dim3(256), 0, c->stream, a, 0LL);
     if (a.batched) launch_prep_ucv(a, a.uring, c->stream);
     TRY(ensure_ws(c, plan_ws(c, batch).total));
+    TRY(ensure_scratch(s));
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         rom_state_destroy(s);
         return fail(ROM_E_DEVICE, "state setup failed");
@@ -645,14 +677,20 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
 
 // ============================================================== stepping
 
-static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
+static rom_status prepare(rom_ctx c, rom_state s, int64_t nsteps) {
     rom_status st = ensure_ws(c, plan_ws(c, s->B).total);
     if (st != ROM_OK) return st;
-    st = ensure_elog(s, s->h_step + nsteps + 1);
+    st = ensure_scratch(s);
+    if (st != ROM_OK) return st;
+    return ensure_elog(s, s->h_step + nsteps + 1);
+}
+
+static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
+    rom_status st = prepare(c, s, nsteps);
     if (st != ROM_OK) return st;
     int64_t left = nsteps;
     if (left >= 2 * kGraphChunk) {
-        if (!s->graph || s->graph_gen != c->ws_gen || s->graph_elog != s->a.elog) {
+        if (!s->graph || s->graph_gen != c->ws_gen || s->graph_sgen != s->sgen) {
             if (s->graph) {
                 hipGraphExecDestroy(s->graph);
                 s->graph = nullptr;
@@ -660,7 +698,7 @@ static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             rom_status cst = ROM_OK;
-            for (int q = 0; q < kGraphChunk && cst == ROM_OK; ++q) cst = enqueue_step(c, s);
+            for (int q = 0; q < kGraphChunk && cst == ROM_OK; ++q) cst = enqueue_step(c, s, c->stream);
             hipError_t ee = hipStreamEndCapture(c->stream, &g);
             if (cst != ROM_OK) {
                 if (g) hipGraphDestroy(g);
@@ -674,7 +712,7 @@ static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
                 return fail(ROM_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
             }
             s->graph_gen = c->ws_gen;
-            s->graph_elog = s->a.elog;
+            s->graph_sgen = s->sgen;
         }
         while (left >= kGraphChunk) {
             HIPCHK(hipGraphLaunch(s->graph, c->stream));
@@ -682,7 +720,7 @@ static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
         }
     }
     for (; left > 0; --left) {
-        st = enqueue_step(c, s);
+        st = enqueue_step(c, s, c->stream);
         if (st != ROM_OK) return st;
     }
     s->h_step += nsteps;
@@ -792,11 +830,221 @@ extern "C" rom_status rom_state_u(rom_ctx c, rom_state s, double* u_dev) {
     return ROM_OK;
 }
 
+// ============================================================== uneven-N batching
+
+namespace {
+
+// Single-trajectory pairs that share a kernel family: dense/CP, number format, and
+// diagonal or dense stiffness.  Each phase of a step is one grouped launch over the
+// job table of the group.
+struct Group {
+    int dense = 0, dtype = 0, diag = 0;
+    std::vector<GemvJob> gemv;
+    std::vector<Proj1Job> proj;
+    std::vector<Scat1Job> scat;
+    std::vector<BdfJob> bdf;
+    std::vector<HelmJob> helm;
+    int b1 = 0, b2 = 0, b3 = 0;            // blocks of phase 1, 2, 3
+    int Npmax = 8, Rpmax = 8, Nmax = 1;
+    GemvTile tile{};
+    char* dev = nullptr;                   // device copies of the job tables
+    size_t off1 = 0, off2 = 0, off3 = 0;
+};
+
+template <class J>
+size_t put(std::vector<char>& blob, const std::vector<J>& v) {
+    size_t off = (blob.size() + 255) & ~(size_t)255;
+    blob.resize(off + sizeof(J) * v.size());
+    if (!v.empty()) memcpy(blob.data() + off, v.data(), sizeof(J) * v.size());
+    return off;
+}
+
+void enqueue_group(const Group& g, hipStream_t stream, int phase) {
+    if (phase == 1) {
+        if (g.dense)
+            launch_dense_gemv_group(g.dtype, (const GemvJob*)(g.dev + g.off1), (int)g.gemv.size(), g.b1, g.Npmax,
+                                    g.tile, stream);
+        else
+            launch_cp_proj1_group(g.dtype, (const Proj1Job*)(g.dev + g.off1), (int)g.proj.size(), g.b1, g.Npmax,
+                                  stream);
+    } else if (phase == 2) {
+        if (g.dense)
+            launch_bdf_group(acc_f64(g.dtype), g.diag, (const BdfJob*)(g.dev + g.off2), (int)g.bdf.size(), g.b2,
+                             stream);
+        else
+            launch_cp_scatter1_group(g.dtype, g.diag ? 1 : 2, (const Scat1Job*)(g.dev + g.off2),
+                                     (int)g.scat.size(), g.b2, g.Rpmax, stream);
+    } else if (!g.diag) {
+        launch_helm_group((const HelmJob*)(g.dev + g.off3), (int)g.helm.size(), g.b3, g.Nmax, stream);
+    }
+}
+
+}  // namespace
+
 extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_state* states, int64_t nsteps,
                                      int64_t* first_bad_step) {
-    (void)n; (void)ctxs; (void)states; (void)nsteps;
     if (first_bad_step) *first_bad_step = -1;
-    return fail(ROM_E_UNSUPPORTED, "rom_step_multi is not available in this build");
+    if (n < 1 || !ctxs || !states) return fail(ROM_E_INVALID, "rom_step_multi needs n >= 1 pairs");
+    if (nsteps < 0) return fail(ROM_E_INVALID, "nsteps < 0");
+    for (int q = 0; q < n; ++q) {
+        if (!ctxs[q] || !states[q] || states[q]->ctx != ctxs[q])
+            return fail(ROM_E_INVALID, "pair %d: state does not belong to its context", q);
+        for (int r = 0; r < q; ++r)
+            if (states[r] == states[q]) return fail(ROM_E_INVALID, "state listed twice (pairs %d and %d)", r, q);
+    }
+    hipStream_t stream = ctxs[0]->stream;
+    for (int q = 0; q < n; ++q) HIPCHK(hipStreamSynchronize(ctxs[q]->stream));
+    for (int q = 0; q < n; ++q) {
+        rom_status st = prepare(ctxs[q], states[q], nsteps);
+        if (st != ROM_OK) return st;
+    }
+    if (nsteps == 0) return ROM_OK;
+
+    // ---- job tables
+    std::vector<Group> groups;
+    std::vector<int> batched;
+    for (int q = 0; q < n; ++q) {
+        rom_ctx c = ctxs[q];
+        rom_state st = states[q];
+        if (st->B != 1) {
+            batched.push_back(q);
+            continue;
+        }
+        const int dense = c->dense ? 1 : 0, diag = c->diagA ? 1 : 0;
+        Group* g = nullptr;
+        for (auto& x : groups)
+            if (x.dense == dense && x.dtype == c->dtype && x.diag == diag) g = &x;
+        if (!g) {
+            groups.emplace_back();
+            g = &groups.back();
+            g->dense = dense;
+            g->dtype = c->dtype;
+            g->diag = diag;
+            g->tile = gemv_tile(c);
+        }
+        const WsPlan p = plan_ws(c, 1);
+        char* scr = (char*)st->scratch;
+        if (dense) {
+            GemvJob jb = make_gemv_job(c->dtype, c->C, c->Clo, c->N, c->Np, st->a.uring, st->a.step, c->N,
+                                       scr + p.part_off, p.nchunk, gemv_tile(c));
+            jb.blk0 = g->b1;
+            g->b1 += jb.nblk;
+            g->gemv.push_back(jb);
+            BdfJob bj{};
+            bj.a = st->a;
+            bj.part = scr + p.part_off;
+            bj.nchunk = p.nchunk;
+            bj.pb = 1;
+            bj.blk0 = g->b2;
+            bj.nblk = (c->N + 255) / 256;
+            g->b2 += bj.nblk;
+            g->bdf.push_back(bj);
+        } else {
+            Proj1Job pj{};
+            pj.BCt = c->BCt;
+            pj.BCt_lo = (const unsigned short*)c->BCt_lo;
+            pj.N = c->N;
+            pj.Np = c->Np;
+            pj.R2 = 2 * c->Rp;
+            pj.u_base = st->a.uring;
+            pj.stepp = st->a.step;
+            pj.slot_stride = c->N;
+            pj.st = scr + p.part_off;
+            pj.blk0 = g->b1;
+            pj.nblk = (2 * c->Rp + 3) / 4;
+            g->b1 += pj.nblk;
+            g->proj.push_back(pj);
+            Scat1Job sj{};
+            sj.Af = c->Af;
+            sj.Af_lo = (const unsigned short*)c->Af_lo;
+            sj.lam = c->lam;
+            sj.N = c->N;
+            sj.Rp = c->Rp;
+            sj.st = scr + p.part_off;
+            sj.a = st->a;
+            sj.blk0 = g->b2;
+            sj.nblk = (c->N + 3) / 4;
+            g->b2 += sj.nblk;
+            g->scat.push_back(sj);
+            if (c->Rp > g->Rpmax) g->Rpmax = c->Rp;
+        }
+        if (!diag) {
+            HelmJob hj{};
+            hj.a = st->a;
+            hj.blk0 = g->b3;
+            hj.nblk = (c->N + 3) / 4;
+            g->b3 += hj.nblk;
+            g->helm.push_back(hj);
+        }
+        if (c->Np > g->Npmax) g->Npmax = c->Np;
+        if (c->N > g->Nmax) g->Nmax = c->N;
+    }
+    std::vector<char> blob;
+    for (auto& g : groups) {
+        g.off1 = g.dense ? put(blob, g.gemv) : put(blob, g.proj);
+        g.off2 = g.dense ? put(blob, g.bdf) : put(blob, g.scat);
+        g.off3 = put(blob, g.helm);
+    }
+    char* dev = nullptr;
+    if (!blob.empty()) {
+        HIPCHK(hipMalloc((void**)&dev, blob.size()));
+        hipError_t e = hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(dev);
+            return fail(ROM_E_DEVICE, "job table upload failed: %s", hipGetErrorString(e));
+        }
+    }
+    for (auto& g : groups) g.dev = dev;
+
+    auto enqueue_all = [&]() -> rom_status {
+        for (int phase = 1; phase <= 3; ++phase)
+            for (const auto& g : groups) enqueue_group(g, stream, phase);
+        for (int q : batched) {
+            rom_status st = enqueue_step(ctxs[q], states[q], stream);
+            if (st != ROM_OK) return st;
+        }
+        HIPCHK(hipGetLastError());
+        return ROM_OK;
+    };
+
+    rom_status status = ROM_OK;
+    int64_t left = nsteps;
+    hipGraphExec_t gx = nullptr;
+    if (left >= 2 * kGraphChunk) {
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int q = 0; q < kGraphChunk && status == ROM_OK; ++q) status = enqueue_all();
+            e = hipStreamEndCapture(stream, &gr);
+            if (status == ROM_OK && e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
+            if (gr) hipGraphDestroy(gr);
+        }
+        if (status == ROM_OK && e != hipSuccess) status = fail(ROM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        while (status == ROM_OK && left >= kGraphChunk) {
+            e = hipGraphLaunch(gx, stream);
+            if (e != hipSuccess) status = fail(ROM_E_DEVICE, "graph launch failed: %s", hipGetErrorString(e));
+            left -= kGraphChunk;
+        }
+    }
+    for (; status == ROM_OK && left > 0; --left) status = enqueue_all();
+    hipError_t se = hipStreamSynchronize(stream);
+    if (gx) hipGraphExecDestroy(gx);
+    if (dev) hipFree(dev);
+    if (status != ROM_OK) return status;
+    if (se != hipSuccess) return fail(ROM_E_DEVICE, "rom_step_multi: %s", hipGetErrorString(se));
+    long long worst = LLONG_MAX;
+    for (int q = 0; q < n; ++q) {
+        states[q]->h_step += nsteps;
+        states[q]->pending = false;
+        long long bad = LLONG_MAX;
+        HIPCHK(hipMemcpy(&bad, states[q]->a.bad, sizeof(long long), hipMemcpyDeviceToHost));
+        if (bad < worst) worst = bad;
+    }
+    if (worst != LLONG_MAX) {
+        if (first_bad_step) *first_bad_step = worst;
+        return fail(ROM_E_NONFINITE, "a trajectory became non-finite at step %lld", worst);
+    }
+    return ROM_OK;
 }
 
 extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* value) {

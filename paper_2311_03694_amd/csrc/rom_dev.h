@@ -47,6 +47,52 @@ struct StepArgs {
     int batched;             // 1: write ucv/uscale for the batched contraction
 };
 
+// ---------------------------------------------------------------- grouped launches
+
+// A job is one kernel's work for one (context, state) pair; grouped launches run the
+// jobs of many pairs (uneven N, R) in one grid, job p owning blocks [blk0, blk0+nblk).
+struct GemvJob {           // dense contraction, one trajectory
+    const void* C;
+    const unsigned short* Clo;
+    int N, Np;
+    const double* u_base;
+    const long long* stepp;
+    long long slot_stride;
+    void* part;
+    int nchunk;
+    long long chunk_len;
+    int blk0, nblk;
+};
+struct Proj1Job {          // CP projections, one trajectory
+    const void* BCt;
+    const unsigned short* BCt_lo;
+    int N, Np, R2;
+    const double* u_base;
+    const long long* stepp;
+    long long slot_stride;
+    void* st;
+    int blk0, nblk;
+};
+struct Scat1Job {          // CP Hadamard-scatter with the fused BDF update
+    const void* Af;
+    const unsigned short* Af_lo;
+    const void* lam;
+    int N, Rp;
+    const void* st;
+    StepArgs a;
+    int blk0, nblk;
+};
+struct BdfJob {            // BDF update from contraction partials, one trajectory
+    StepArgs a;
+    const void* part;
+    int nchunk, pb;
+    int blk0, nblk;
+};
+struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory
+    StepArgs a;
+    int blk0, nblk;
+};
+
 // ---------------------------------------------------------------- launchers (k_*.hip)
 
 // Operator staging (a one-time conversion, round to nearest even): `rows` rows of
@@ -65,6 +111,18 @@ int dense_gemv_nchunk(int N, GemvTile t);
 int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
                       const long long* stepp, long long slot_stride, void* part, int nchunk,
                       GemvTile t, hipStream_t s);
+
+GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
+                      const long long* stepp, long long slot_stride, void* part, int nchunk, GemvTile t);
+void launch_dense_gemv_group(int dt, const GemvJob* jobs_dev, int njobs, int blocks, int Npmax, GemvTile t,
+                             hipStream_t s);
+// grouped single-trajectory CP and BDF kernels; scatter mode 1 = diagonal stiffness
+// (update fused), 2 = dense stiffness (right-hand side); bdf diag likewise
+void launch_cp_proj1_group(int dt, const Proj1Job* jobs_dev, int njobs, int blocks, int Npmax, hipStream_t s);
+void launch_cp_scatter1_group(int dt, int mode, const Scat1Job* jobs_dev, int njobs, int blocks, int Rpmax,
+                              hipStream_t s);
+void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s);
+void launch_helm_group(const HelmJob* jobs_dev, int njobs, int blocks, int Nmax, hipStream_t s);
 
 // Batched MFMA contraction (dense Khatri-Rao form, CP projections and CP scatter).
 struct MfmaTile { int mw, bt, target; };
