@@ -1,24 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark: online ROM steps on one MI355X, CP-ROM vs dense G-ROM at N = 1000.
 
-Workload (synthetic, seeded): N = 1000 modes, dense advection tensor built from a
-skew-preserving CP of rank 2000 (1000 skew pairs, weights 1/p, unit Gaussian factors)
-plus 1e-7 skew Gaussian noise; stiffness A = diag(k^2) + an SPD perturbation of
-spectral norm 0.1; nu = dt = 5e-4; BDF3/EXT3 with the 1-2-3 start-up ramp.  The
+Headline workload (synthetic, seeded): N = 1000 modes, dense advection tensor built
+from a skew-preserving CP of rank 2000 (1000 skew pairs, weights 1/p, unit Gaussian
+factors) plus 1e-7 skew Gaussian noise; stiffness A = diag(k^2) plus an SPD perturbation
+of spectral norm 0.1; nu = dt = 5e-4; BDF3/EXT3 with the 1-2-3 start-up ramp.  The
 CP-ROM uses the rank-2000 factors, the G-ROM the dense tensor, both with FP32
-contractions and FP64 state updates.
+contractions and FP64 state updates, one trajectory.
 
 One timed step = one BDF3/EXT3 step of the trajectory batch (contraction, FP64 right-hand
-side, FP64 Helmholtz solve, energy, health flag).  The headline value is CP-ROM
+side, FP64 Helmholtz solve, energy, health flag).  `value` is CP-ROM
 trajectory-steps/s; the dense G-ROM is timed the same way in the same run.  Inputs sit
-in HBM before the timed region opens.
+in HBM before a timed region opens; each region is bracketed by device
+synchronization and timed with HIP events on the library's stream.
 
-Also printed in the one JSON line:
-  roofline     the dense contraction kernel (HBM-bound), its average duration measured
-               with HIP events on the library's stream, against 8 TB/s
-  roofline_cp  the CP projection kernel, likewise
-  rel_err      max relative error of the GPU trajectories against the FP64 oracle
-  cpu_baseline the FP64 oracle (plain C, one thread) on a bounded sample of steps
+Also in the one JSON line:
+  dense / speedup_cp_vs_dense   the G-ROM beside it
+  roofline      dense contraction kernel (HBM-bound): algorithmic bytes N^3*4 per launch
+                over its event-timed average duration, against 8 TB/s
+  roofline_cp   CP projections + Hadamard-scatter (3NR*4 bytes per launch)
+  batched       N = 1000 with B = 16 and 64 trajectories (MFMA kernels), FP32 and BF16
+  config2       N = 400, B = 256, the dense Khatri-Rao MFMA GEMM (BF16, BF16x3, FP32)
+                and CP rank 400, with TFLOP/s against the dense MFMA peaks
+  serving       a bounded Poisson request stream through the continuous-batching loop
+  rel_err       GPU trajectories against the FP64 oracle (same operator)
+  cpu_baseline  the FP64 oracle (plain C, one thread) on a bounded sample of steps
 """
 from __future__ import annotations
 
@@ -36,6 +42,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ROM steps/s×trajectories at N=1000: CP vs dense G-ROM, rel err ≤1e-5 vs FP64"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}
 
 
 def parse():
@@ -45,12 +53,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64", "bf16", "bf16x3"])
     ap.add_argument("--R", type=int, default=2000)
-    ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--dense-steps", type=int, default=None,
                     help="timed steps of the dense G-ROM (default: min(steps, 2000))")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target length of the oracle sample (CPU baseline)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
+    ap.add_argument("--no-extra", action="store_true", help="headline only (no batched/config2/serving)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration)")
@@ -75,6 +83,24 @@ def _traffic(name, src):
     return rec.get("hbm_bytes_per_launch")
 
 
+class Timer:
+    """Events on the library's stream around enqueued work, bracketed by device syncs."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def __call__(self, fn):
+        torch = self.torch
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        fn()
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -85,87 +111,68 @@ def main():
     import torch
     import paper_2311_03694_amd as rg
     import romsynth
+    from paper_2311_03694_amd import tune
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    N, R, B, dt = 1000, args.R, args.batch, args.dtype
+    timer = Timer(torch, stream)
+    N, R, dt = 1000, args.R, args.dtype
     K, W = args.steps, args.warmup
     Kd = args.dense_steps if args.dense_steps is not None else min(K, 2000)
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
 
     t0 = time.time()
-    print(f"[bench] generating N={N} workload", file=sys.stderr, flush=True)
-    p = romsynth.make_config(3, R=R, batch=B)
-    print(f"[bench] generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-
-    def make(dense):
-        return rg.Rom.from_problem(p, dense=dense, dtype=dt, max_batch=B, stream=stream)
-
-    def timed_steps(rom, nsteps, warm):
-        s = rom.state(p.u0)
-        s.step(warm)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        t_host = time.perf_counter()
-        e0.record(stream)
-        s.step_async(nsteps)
-        e1.record(stream)
-        s.sync()
-        torch.cuda.synchronize()
-        t_host = time.perf_counter() - t_host
-        return s, e0.elapsed_time(e1) / 1e3, t_host
-
-    def kernel_avg(rom, reps):
-        """Average duration of the contraction alone: rom_nonlinear on the current state,
-        HIP events on the library stream around `reps` back-to-back launches."""
-        u = torch.tensor(p.u0, dtype=torch.float64, device=dev)
-        y = torch.empty_like(u)
-        with torch.cuda.stream(stream):
-            rg.rom_nonlinear(rom.handle, B, u, y)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            rg.rom_nonlinear(rom.handle, B, u, y)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3 / reps
+    log(f"generating N={N} workload")
+    p = romsynth.make_config(3, R=R, batch=1)
+    log(f"generated in {time.time() - t0:.1f}s")
 
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         torch.cuda.synchronize()
         b2 = a.clone()
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {a.numel() * 4} bytes done", file=sys.stderr, flush=True)
+        log(f"calibration copy of {a.numel() * 4} bytes done")
         del a, b2
 
-    # ---------------- CP-ROM (headline)
-    print("[bench] CP-ROM", file=sys.stderr, flush=True)
+    def make(dense, dtype=dt, batch=1):
+        return rg.Rom.from_problem(p, dense=dense, dtype=dtype, max_batch=batch, stream=stream)
+
+    def step_rate(rom, u0, nsteps, warm):
+        s = rom.state(u0)
+        s.step(warm)
+        t = timer(lambda: s.step_async(nsteps))
+        s.sync()
+        return s, t
+
+    def kernel_avg(rom, u, reps):
+        """Average duration of the contraction alone (rom_nonlinear, event-timed)."""
+        ud = torch.tensor(np.atleast_2d(u), dtype=torch.float64, device=dev)
+        yd = torch.empty_like(ud)
+        B = ud.shape[0]
+        rg.rom_nonlinear(rom.handle, B, ud, yd)
+        return timer(lambda: [rg.rom_nonlinear(rom.handle, B, ud, yd) for _ in range(reps)]) / reps
+
+    # ---------------- headline: CP-ROM and dense G-ROM, one trajectory
+    log("CP-ROM")
     rom_cp = make(False)
-    s_cp, t_cp, th_cp = timed_steps(rom_cp, K, W)
-    cp_kernel = kernel_avg(rom_cp, args.kernel_reps * 10)
-    print(f"[bench] CP {K} steps in {t_cp:.3f}s (host {th_cp:.3f}s)", file=sys.stderr, flush=True)
-
-    # ---------------- dense G-ROM
-    print("[bench] dense G-ROM", file=sys.stderr, flush=True)
+    s_cp, t_cp = step_rate(rom_cp, p.u0, K, W)
+    cp_kernel = kernel_avg(rom_cp, p.u0, args.kernel_reps * 10)
+    log(f"CP {K} steps in {t_cp:.3f}s")
+    log("dense G-ROM")
     rom_d = make(True)
-    s_d, t_d, th_d = timed_steps(rom_d, Kd, min(W, 20))
-    d_kernel = kernel_avg(rom_d, args.kernel_reps)
-    print(f"[bench] dense {Kd} steps in {t_d:.3f}s (host {th_d:.3f}s)", file=sys.stderr, flush=True)
+    s_d, t_d = step_rate(rom_d, p.u0, Kd, min(W, 20))
+    d_kernel = kernel_avg(rom_d, p.u0, args.kernel_reps)
+    log(f"dense {Kd} steps in {t_d:.3f}s")
 
-    es = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[dt]
-    cp_rate = K * B / t_cp
-    d_rate = Kd * B / t_d
-    d_bytes = float(N) ** 3 * es                     # algorithmic bytes per dense launch
-    cp_bytes = 2.0 * N * R * es                      # projection: [Bf|Cf]^T read once
-    # CP launch timed above = projection + scatter; split by bytes read (3NR total)
-    cp_proj_share = 2.0 / 3.0
-    src = os.path.join(ROOT, "paper_2311_03694_amd", "csrc", "k_contract.hip")
-
+    es = ELEM_BYTES[dt]
+    cp_rate = K / t_cp
+    d_rate = Kd / t_d
+    d_bytes = float(N) ** 3 * es
+    cp_bytes = 3.0 * N * R * es
+    src = os.path.join(ROOT, "paper_2311_03694_amd", "csrc", "k_dense1.hip")
     result = {
         "metric": METRIC,
         "value": cp_rate,
@@ -179,56 +186,128 @@ def main():
         "vs_baseline": None,
         "dtype": dt,
         "data": "synthetic (seeded skew-CP tensor, N=1000, rank 2000, eps 1e-7, SPD stiffness)",
-        "config": {"workload": f"N=1000 ROM, CP rank {R} vs dense G-ROM, BDF3/EXT3, batch {B}",
-                   "N": N, "R": R, "batch": B, "nu": p.nu, "dt": p.dt, "stiffness": "diag(k^2)+SPD(0.1)"},
-        "dense": {"value": d_rate, "unit": "trajectory-steps/s", "steps": Kd,
-                  "ms_per_step": t_d / Kd * 1e3},
+        "config": {"workload": f"N=1000 ROM, CP rank {R} vs dense G-ROM, BDF3/EXT3, one trajectory",
+                   "N": N, "R": R, "batch": 1, "nu": p.nu, "dt": p.dt, "stiffness": "diag(k^2)+SPD(0.1)"},
+        "dense": {"value": d_rate, "unit": "trajectory-steps/s", "steps": Kd, "ms_per_step": t_d / Kd * 1e3},
         "speedup_cp_vs_dense": cp_rate / d_rate,
-        "roofline": {"bound": "hbm", "kernel": "dense contraction (k_dense_gemv)",
+        "roofline": {"bound": "hbm", "kernel": "k_dense_gemv (dense contraction, one trajectory)",
                      "achieved": d_bytes / d_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": d_bytes / d_kernel / 1e9 / HBM_PEAK_GBS,
                      "traffic": _traffic(f"dense_gemv_n{N}_{dt}", src),
                      "avg_launch_us": d_kernel * 1e6, "algorithmic_bytes": d_bytes},
-        "roofline_cp": {"bound": "latency", "kernel": "CP projections + Hadamard-scatter",
-                        "achieved": 3.0 * N * R * es / cp_kernel / 1e9, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": 3.0 * N * R * es / cp_kernel / 1e9 / HBM_PEAK_GBS,
-                        "avg_launch_us": cp_kernel * 1e6, "algorithmic_bytes": 3.0 * N * R * es},
+        "roofline_cp": {"bound": "latency", "kernel": "k_cp_proj1 + k_cp_scatter1",
+                        "achieved": cp_bytes / cp_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": cp_bytes / cp_kernel / 1e9 / HBM_PEAK_GBS,
+                        "avg_launch_us": cp_kernel * 1e6, "algorithmic_bytes": cp_bytes},
     }
+    s_cp.close()
+    s_d.close()
+
+    if not args.no_extra:
+        tiles = tune.load()
+        # ---------------- batched trajectories at N = 1000 (MFMA kernels)
+        batched = {}
+        for B in (16, 64):
+            u0 = romsynth.initial_u(N, range(B), cfg=3)
+            for bdt in ("fp32", "bf16"):
+                entry = {}
+                for dense in (True, False):
+                    rom = make(dense, bdt, B)
+                    tune.apply(rom, B, dense=dense, R=0 if dense else R, table=tiles)
+                    steps = 100 if dense else 1000
+                    s, t = step_rate(rom, u0, steps, 5)
+                    name = "dense" if dense else "cp"
+                    entry[name] = {"traj_steps_per_s": steps * B / t, "us_per_step": t / steps * 1e6}
+                    if dense:
+                        tk = kernel_avg(rom, u0, 10)
+                        fl = 2.0 * N ** 3 * B
+                        entry[name]["contraction_us"] = tk * 1e6
+                        entry[name]["tflops"] = fl / tk / 1e12
+                        entry[name]["mfma_frac"] = fl / tk / 1e12 / MFMA_PEAK_TFLOPS[bdt]
+                        entry[name]["hbm_frac"] = N ** 3 * ELEM_BYTES[bdt] / tk / 1e9 / HBM_PEAK_GBS
+                    s.close()
+                    rom.close()
+                entry["speedup_cp_vs_dense"] = entry["cp"]["traj_steps_per_s"] / entry["dense"]["traj_steps_per_s"]
+                batched[f"B{B}_{bdt}"] = entry
+                log(f"batched B={B} {bdt}: dense {entry['dense']['traj_steps_per_s']:.0f} "
+                    f"cp {entry['cp']['traj_steps_per_s']:.0f} traj-steps/s")
+        result["batched"] = batched
+
+        # ---------------- config 2: N = 400, B = 256
+        log("config 2 (N=400, B=256)")
+        p2 = romsynth.make_config(2, R=400)
+        c2 = {}
+        for bdt in ("bf16", "bf16x3", "fp32"):
+            rom = rg.Rom.from_problem(p2, dense=True, dtype=bdt, max_batch=256, stream=stream)
+            tune.apply(rom, 256, dense=True, table=tiles)
+            s, t = step_rate(rom, p2.u0, 50, 5)
+            tk = kernel_avg(rom, p2.u0, 10)
+            fl = 2.0 * 400 ** 3 * 256 * (3 if bdt == "bf16x3" else 1)
+            c2[f"dense_{bdt}"] = {"traj_steps_per_s": 50 * 256 / t, "us_per_step": t / 50 * 1e6,
+                                  "contraction_us": tk * 1e6, "tflops": fl / tk / 1e12,
+                                  "mfma_frac": fl / tk / 1e12 / MFMA_PEAK_TFLOPS[bdt]}
+            s.close()
+            rom.close()
+        rom = rg.Rom.from_problem(p2, dense=False, dtype="fp32", max_batch=256, stream=stream)
+        tune.apply(rom, 256, dense=False, R=400, table=tiles)
+        s, t = step_rate(rom, p2.u0, 500, 20)
+        c2["cp_fp32_R400"] = {"traj_steps_per_s": 500 * 256 / t, "us_per_step": t / 500 * 1e6}
+        s.close()
+        rom.close()
+        result["config2"] = c2
+        result["roofline_mfma"] = {"bound": "mfma", "kernel": "k_mfma_rows (dense Khatri-Rao, N=400, B=256, BF16)",
+                                   "achieved": c2["dense_bf16"]["tflops"], "peak": MFMA_PEAK_TFLOPS["bf16"],
+                                   "unit": "TFLOP/s", "frac": c2["dense_bf16"]["mfma_frac"],
+                                   "avg_launch_us": c2["dense_bf16"]["contraction_us"],
+                                   "algorithmic_flops": 2.0 * 400 ** 3 * 256}
+
+        # ---------------- serving: bounded Poisson stream
+        from paper_2311_03694_amd.serve import RomBackend, Server, poisson_requests, summarize
+        log("serving")
+        reqs = poisson_requests(48, rate=200.0, Ns=(100, 200, 400, 700, 1000), dense_frac=0.25,
+                                dtypes=("fp32", "bf16x3"), steps_range=(1000, 10000), seeds=(0, 1), rng_seed=7)
+        for r in reqs:                      # dense operators above N = 400 are left to CP
+            if r.kind == "dense" and r.N > 400:
+                r.kind = "cp"
+        srv = Server(RomBackend(stream=stream), hbm_budget=64 << 30, max_slots=64, chunk=500)
+        t1 = time.perf_counter()
+        recs = srv.run(reqs)
+        wall = time.perf_counter() - t1
+        result["serving"] = dict(summarize(recs, wall), max_batch=max(srv.batches),
+                                 note="48 requests, N in {100..1000}, CP rank 2N or dense (N<=400), "
+                                      "fp32/bf16x3, 1e3-1e4 steps, Poisson 200/s; wall time includes "
+                                      "operator creation")
+        srv.close()
 
     # ---------------- accuracy and CPU baseline (oracle, FP64, one thread)
     if not args.no_cpu:
         import oracle as orc
-        # one oracle CP step ~ 6NR + 2N^2 flop; size the sample to ~cpu_seconds
         t1 = time.perf_counter()
-        r_probe = orc.run(N, p.nu, p.dt, p.A, 20, u0=p.u0[0], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
-        t_probe = time.perf_counter() - t1
-        per = max(t_probe / 20, 1e-6)
+        orc.run(N, p.nu, p.dt, p.A, 20, u0=p.u0[0], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
+        per = max((time.perf_counter() - t1) / 20, 1e-6)
         n_cpu = int(max(100, min(20000, args.cpu_seconds / per)))
         t1 = time.perf_counter()
         r_cp = orc.run(N, p.nu, p.dt, p.A, n_cpu, u0=p.u0[0], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
         t_cpu = time.perf_counter() - t1
-        # GPU FP32 trajectory over the same steps
         sg = rom_cp.state(p.u0)
         sg.step(n_cpu)
         ug = sg.get()[0][0][0]
         Eg = sg.energy()[1][:, 0]
         err_cp = float(np.linalg.norm(ug - r_cp["u_hist"][0]) / np.linalg.norm(r_cp["u_hist"][0]))
         errE_cp = float(np.max(np.abs(Eg - r_cp["E"]) / r_cp["E"]))
-        # dense: a few oracle steps (each ~1e9 multiply-adds)
         nd = 3
         t2 = time.perf_counter()
         r_d = orc.run(N, p.nu, p.dt, p.A, nd, u0=p.u0[0], C=p.C)
         t_cpu_d = time.perf_counter() - t2
         sd = rom_d.state(p.u0)
         sd.step(nd)
-        err_d = float(np.linalg.norm(sd.get()[0][0][0] - r_d["u_hist"][0]) /
-                      np.linalg.norm(r_d["u_hist"][0]))
+        err_d = float(np.linalg.norm(sd.get()[0][0][0] - r_d["u_hist"][0]) / np.linalg.norm(r_d["u_hist"][0]))
         result["rel_err"] = {"cp_traj": err_cp, "cp_energy": errE_cp, "cp_steps": n_cpu,
                              "dense_traj": err_d, "dense_steps": nd, "tol": 1e-5}
         result["cpu_baseline"] = {
             "value": n_cpu / t_cpu, "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_cpu} CP-ROM steps (N=1000, R={R}, FP64, one thread, incl. one-time "
-                      f"Cholesky); dense G-ROM: {nd} steps at {nd / t_cpu_d:.3f} steps/s",
+            "sample": f"{n_cpu} CP-ROM steps (N=1000, R={R}, FP64, one thread, incl. one-time Cholesky); "
+                      f"dense G-ROM: {nd} steps at {nd / t_cpu_d:.3f} steps/s",
             "dense_value": nd / t_cpu_d}
     print(json.dumps(result), flush=True)
 

@@ -61,6 +61,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"librom.so not found at {LIB_PATH}: build it with "
                            "`python -m paper_2311_03694_amd.build` (hipcc, gfx950)")
+    # Load PyTorch's HIP runtime first so that librom.so binds to the same runtime
+    # instance (PyTorch ships its own libamdhip64); two instances in one process do not
+    # share devices, streams or allocations.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     L.rom_create.argtypes = [ctypes.POINTER(rom_desc), ctypes.POINTER(_vp)]
     L.rom_destroy.argtypes = [_vp]

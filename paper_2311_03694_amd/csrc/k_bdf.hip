@@ -47,7 +47,7 @@ __device__ __forceinline__ void bdf_partials_body(const StepArgs& a, const ACC* 
             write_level(a, n + 1, b, i, un);
             e = un * un;
         } else {
-            a.rhs[(size_t)b * a.N + i] = rhs;
+            a.rhs[(size_t)b * a.Np + i] = rhs;
         }
     }
     if (DIAG) {
@@ -88,7 +88,7 @@ __device__ __forceinline__ void helm_gemv_body(const StepArgs& a, int blk, int n
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int i = blk * 4 + w;
     const bool live = i < a.N;
-    const double* h = a.hinv + ((size_t)(k - 1) * a.N + (live ? i : 0)) * a.N;
+    const double* h = a.hinv + ((size_t)(k - 1) * a.N + (live ? i : 0)) * a.Np;
     Raw hv[U];
     int m0 = lane * V;
     auto issue = [&](int mb) {
@@ -99,7 +99,7 @@ __device__ __forceinline__ void helm_gemv_body(const StepArgs& a, int blk, int n
         }
     };
     issue(m0);
-    for (int m = threadIdx.x; m < a.N; m += blockDim.x) r[m] = a.rhs[m];
+    staged_copy<8, double>(a.N, [&](int m) { return a.rhs[m]; }, [&](int m, double v) { r[m] = v; });
     __syncthreads();
     double e = 0.0;
     if (live) {
@@ -140,63 +140,34 @@ __global__ __launch_bounds__(256) void k_helm_group(const HelmJob* __restrict__ 
     else helm_gemv_body<false>(jb.a, (int)blockIdx.x - jb.blk0, jb.nblk);
 }
 
-// Dense stiffness, batch: U^{n+1}[b][i] = sum_m Hinv_k[i][m] rhs[b][m], FP64 register
-// tiles of 32 rows x 64 trajectories per block (each thread 2 x 4).  Grid:
-// (ceil(N/32), ceil(B/64)), 256 threads.  Energy partials per (b, row tile).
-__global__ __launch_bounds__(256) void k_helm_gemm(StepArgs a) {
-    __shared__ double Hs[32][33];
-    __shared__ double Rs[64][33];
-    __shared__ double ered[16][65];
+// Dense stiffness, batch: the FP64 MFMA kernel writes partial sums
+// part[z][b][i] of U^{n+1}[b][i] = sum_m Hinv_k[i][m] rhs[b][m]; this kernel adds them
+// in z order, stores level n+1, and reduces energies and the health flag.
+// Grid (ceil(N/256), B).
+__global__ __launch_bounds__(256) void k_helm_finish(StepArgs a, const double* __restrict__ part, int nsplit) {
+    __shared__ double red[4];
     const long long n = *a.step;
-    const int k = bdf_order(n);
-    const double* H = a.hinv + (size_t)(k - 1) * a.N * a.N;
-    const int i0 = blockIdx.x * 32, b0 = blockIdx.y * 64;
-    const int tr = threadIdx.x / 16, tb = threadIdx.x % 16;
-    double acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-    for (int m0 = 0; m0 < a.N; m0 += 32) {
-        for (int q = threadIdx.x; q < 32 * 32; q += 256) {
-            const int rr = q / 32, mm = q % 32;
-            const int gi = i0 + rr, gm = m0 + mm;
-            Hs[rr][mm] = (gi < a.N && gm < a.N) ? H[(size_t)gi * a.N + gm] : 0.0;
-        }
-        for (int q = threadIdx.x; q < 64 * 32; q += 256) {
-            const int bb = q / 32, mm = q % 32;
-            const int gb = b0 + bb, gm = m0 + mm;
-            Rs[bb][mm] = (gb < a.B && gm < a.N) ? a.rhs[(size_t)gb * a.N + gm] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int mm = 0; mm < 32; ++mm) {
-            const double h0 = Hs[tr * 2][mm], h1 = Hs[tr * 2 + 1][mm];
+    const int b = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double e = 0.0;
+    if (i < a.N) {
+        const size_t zs = (size_t)a.Bpad * a.N;
+        const double* pp = part + (size_t)b * a.N + i;
+        double u = 0.0;
+        int z = 0;
+        for (; z + 8 <= nsplit; z += 8) {
+            double v[8];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double rv = Rs[tb * 4 + q][mm];
-                acc[0][q] += h0 * rv;
-                acc[1][q] += h1 * rv;
-            }
+            for (int q = 0; q < 8; ++q) v[q] = pp[(size_t)(z + q) * zs];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u += v[q];
         }
-        __syncthreads();
+        for (; z < nsplit; ++z) u += pp[(size_t)z * zs];
+        write_level(a, n + 1, b, i, u);
+        e = u * u;
     }
-    double ep[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int gi = i0 + tr * 2 + p, gb = b0 + tb * 4 + q;
-            if (gi < a.N && gb < a.B) {
-                write_level(a, n + 1, gb, gi, acc[p][q]);
-                ep[q] += acc[p][q] * acc[p][q];
-            }
-        }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) ered[tr][tb * 4 + q] = ep[q];
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int gb = b0 + threadIdx.x;
-        double s = 0.0;
-        for (int t = 0; t < 16; ++t) s += ered[t][threadIdx.x];
-        if (gb < a.B) a.epart[(size_t)gb * gridDim.x + blockIdx.x] = s;
-    }
+    const double s = block_sum(e, red);
+    if (threadIdx.x == 0) a.epart[(size_t)b * gridDim.x + blockIdx.x] = s;
     finalize_step(a, n, gridDim.x, gridDim.x * gridDim.y);
 }
 
@@ -256,13 +227,13 @@ void launch_helm_group(const HelmJob* jobs_dev, int njobs, int blocks, int Nmax,
 }
 
 void launch_helm_apply(const StepArgs& a, hipStream_t s) {
-    if (a.B == 1) {
-        const size_t lds = sizeof(double) * a.N;
-        if (a.N % 2 == 0) hipLaunchKernelGGL(k_helm_gemv<true>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
-        else hipLaunchKernelGGL(k_helm_gemv<false>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
-    } else {
-        hipLaunchKernelGGL(k_helm_gemm, dim3((a.N + 31) / 32, (a.B + 63) / 64), dim3(256), 0, s, a);
-    }
+    const size_t lds = sizeof(double) * a.N;
+    if (a.N % 2 == 0) hipLaunchKernelGGL(k_helm_gemv<true>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL(k_helm_gemv<false>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
+}
+
+void launch_helm_finish(const StepArgs& a, const double* part, int nsplit, hipStream_t s) {
+    hipLaunchKernelGGL(k_helm_finish, dim3((a.N + 255) / 256, a.B), dim3(256), 0, s, a, part, nsplit);
 }
 
 void launch_prep_ucv(const StepArgs& a, const double* u_src, hipStream_t s) {
@@ -333,13 +304,14 @@ __global__ __launch_bounds__(64) void k_trinv_col(int N, const double* __restric
     for (int r = lane; r < N; r += kWave) X[(size_t)r * N + c] = x[r];
 }
 
-// Hinv = X^T X (X lower triangular): Hinv_im = sum_{r >= max(i,m)} X_ri X_rm.
-__global__ void k_gram(int N, const double* __restrict__ X, double* __restrict__ Hinv) {
+// Hinv = X^T X (X lower triangular): Hinv_im = sum_{r >= max(i,m)} X_ri X_rm, stored
+// with row pitch Np (padding columns stay zero).
+__global__ void k_gram(int N, int Np, const double* __restrict__ X, double* __restrict__ Hinv) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
     if (m >= N) return;
     double s = 0.0;
     for (int r = (i > m ? i : m); r < N; ++r) s += X[(size_t)r * N + i] * X[(size_t)r * N + m];
-    Hinv[(size_t)i * N + m] = s;
+    Hinv[(size_t)i * Np + m] = s;
 }
 
 __global__ void k_hdiag(int N, double nu, double inv_dt, const double* __restrict__ A,
@@ -350,7 +322,7 @@ __global__ void k_hdiag(int N, double nu, double inv_dt, const double* __restric
     for (int k = 0; k < 3; ++k) hd[(size_t)k * N + i] = 1.0 / (b0[k] * inv_dt + nu * A[(size_t)i * N + i]);
 }
 
-int helm_setup_dense(int N, double nu, double dt, const double* A_dev, double* hinv_dev,
+int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, double* hinv_dev,
                      double* work_dev, int* info_dev, hipStream_t s) {
     // work_dev: 3 N^2 doubles (H, L, X)
     double* H = work_dev;
@@ -364,7 +336,8 @@ int helm_setup_dense(int N, double nu, double dt, const double* A_dev, double* h
         for (int j = 0; j < N; ++j)
             hipLaunchKernelGGL(k_chol_col, dim3((N - j + 3) / 4), dim3(256), 0, s, N, j, H, L, info_dev);
         hipLaunchKernelGGL(k_trinv_col, dim3(N), dim3(64), sizeof(double) * N, s, N, L, X);
-        hipLaunchKernelGGL(k_gram, dim3((N + 255) / 256, N), dim3(256), 0, s, N, X, hinv_dev + k * nn);
+        hipLaunchKernelGGL(k_gram, dim3((N + 255) / 256, N), dim3(256), 0, s, N, Np, X,
+                           hinv_dev + (size_t)k * N * Np);
     }
     return 0;
 }

@@ -108,7 +108,10 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
         }
     };
     issue(r0);
-    for (int r = threadIdx.x; r < R; r += blockDim.x) W[r] = lam[r] * st[r] * st[R + r];
+    struct Trip { Acc l, a, b; };
+    staged_copy<8, Trip>(
+        R, [&](int r) { return Trip{lam[r], st[r], st[R + r]}; },
+        [&](int r, const Trip& t) { W[r] = t.l * t.a * t.b; });
     __syncthreads();
     Acc z = 0;
     if (live) {

@@ -136,6 +136,8 @@ struct MfmaArgs {
     int kc, jc, nkc;               // k-chunk length (multiple of 2 KS), j-range length, k-chunks
     int kcp;                       // LDS row stride (elements) of the X tile
     int gx, gy, gz;                // work grid: row tiles, column tiles, splits
+    const long long* kstep;        // non-null: A += (BDF order at *kstep - 1) * a_kstride
+    long long a_kstride;
 };
 
 template <int ADT, int MKD, int MW, int BT, bool KR, bool NT>
@@ -178,34 +180,51 @@ __global__ __launch_bounds__(256) void k_mfma_rows(MfmaArgs p) {
     // ---- stage the X tile (and the j-weights of this block's j-range) in LDS
     {
         const int vecs_per_row = (p.kc + KS2) / VEC;     // the tile plus its zero region
-        for (int idx = threadIdx.x; idx < BT * vecs_per_row; idx += blockDim.x) {
-            const int col = idx / vecs_per_row, kv = (idx - col * vecs_per_row) * VEC;
-            const int k = kbeg + kv;
-            u32x4 v = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
-            if (k < kend) {
-                const size_t off = (size_t)(b0 + col) * p.Kp + k;
-                v = ld_plain<16>(reinterpret_cast<const XT*>(p.X) + off);
-                if constexpr (X3) vl = ld_plain<16>(p.Xlo + off);
-            }
-            *reinterpret_cast<u32x4*>(xs + (size_t)col * p.kcp + kv) = v;
-            if constexpr (X3) *reinterpret_cast<u32x4*>(xsl + (size_t)col * p.kcp + kv) = vl;
-        }
+        struct V2 { u32x4 h, l; };
+        staged_copy<6, V2>(
+            BT * vecs_per_row,
+            [&](int idx) {
+                const int col = idx / vecs_per_row, kv = (idx - col * vecs_per_row) * VEC;
+                const int k = kbeg + kv;
+                V2 v;
+                v.h = u32x4{0u, 0u, 0u, 0u};
+                v.l = u32x4{0u, 0u, 0u, 0u};
+                if (k < kend) {
+                    const size_t off = (size_t)(b0 + col) * p.Kp + k;
+                    v.h = ld_plain<16>(reinterpret_cast<const XT*>(p.X) + off);
+                    if constexpr (X3) v.l = ld_plain<16>(p.Xlo + off);
+                }
+                return v;
+            },
+            [&](int idx, const V2& v) {
+                const int col = idx / vecs_per_row, kv = (idx - col * vecs_per_row) * VEC;
+                *reinterpret_cast<u32x4*>(xs + (size_t)col * p.kcp + kv) = v.h;
+                if constexpr (X3) *reinterpret_cast<u32x4*>(xsl + (size_t)col * p.kcp + kv) = v.l;
+            });
         if constexpr (KR) {
             const int nj = jend - jbeg;
-            for (int idx = threadIdx.x; idx < BT * nj; idx += blockDim.x) {
-                const int col = idx / nj, jj = idx - col * nj;
-                ss[col * p.jc + jj] = reinterpret_cast<const Acc*>(p.S)[(size_t)(b0 + col) * p.s_stride + jbeg + jj];
-            }
+            staged_copy<8, Acc>(
+                BT * nj,
+                [&](int idx) {
+                    const int col = idx / nj, jj = idx - col * nj;
+                    return reinterpret_cast<const Acc*>(p.S)[(size_t)(b0 + col) * p.s_stride + jbeg + jj];
+                },
+                [&](int idx, Acc v) {
+                    const int col = idx / nj, jj = idx - col * nj;
+                    ss[col * p.jc + jj] = v;
+                });
         }
     }
 
-    // ---- per-lane row pointers (rows past M are clamped for loads, never stored)
+    // ---- per-lane row pointers (rows past M are clamped for loads, never stored);
+    // an operator chosen by the BDF order of the current step starts at kbase
+    const size_t kbase = p.kstep ? (size_t)(bdf_order(*p.kstep) - 1) * p.a_kstride : 0;
     size_t rowoff[FM];
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
         int r = rowbase + f * 16 + c16;
         r = r < p.M ? r : p.M - 1;
-        rowoff[f] = (size_t)r * p.a_rowstride;
+        rowoff[f] = kbase + (size_t)r * p.a_rowstride;
     }
 
     Acc4 Y[FM][FN], Z[FM][FN];
@@ -310,10 +329,26 @@ __global__ void k_hadamard(const Acc* __restrict__ P, int nz, int Bpad, int B, i
     if (r >= Rp) return;
     Acc s = 0, t = 0;
     if (b < B) {
-        for (int z = 0; z < nz; ++z) {
-            const Acc* pz = P + ((size_t)z * Bpad + b) * 2 * Rp;
-            s += pz[r];
-            t += pz[Rp + r];
+        // partials added in z order; 8 pairs of loads in flight
+        const size_t zs = (size_t)Bpad * 2 * Rp;
+        const Acc* pb = P + (size_t)b * 2 * Rp + r;
+        int z = 0;
+        for (; z + 8 <= nz; z += 8) {
+            Acc vs[8], vt[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                vs[e] = pb[(size_t)(z + e) * zs];
+                vt[e] = pb[(size_t)(z + e) * zs + Rp];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                s += vs[e];
+                t += vt[e];
+            }
+        }
+        for (; z < nz; ++z) {
+            s += pb[(size_t)z * zs];
+            t += pb[(size_t)z * zs + Rp];
         }
     }
     W[(size_t)b * Rp + r] = lam[r] * s * t;
@@ -353,9 +388,12 @@ MfmaPlan mfma_plan(int mk, int M, int J, int Kp, int Bpad, MfmaTile t) {
     if (splits < 1) splits = 1;
     long long nk = (kp_r + kc_max - 1) / kc_max;
     if (J == 1 && splits > nk) {
-        // no j index to split: cut the contracted index finer
-        const long long nk_max = kp_r / KS;
+        // no j index to split: cut the contracted index finer, keeping at least four
+        // steps per block
+        long long nk_max = kp_r / (4 * KS);
+        if (nk_max < 1) nk_max = 1;
         nk = splits < nk_max ? splits : nk_max;
+        if (nk < (kp_r + kc_max - 1) / kc_max) nk = (kp_r + kc_max - 1) / kc_max;
     }
     pl.kc = (int)(((kp_r / KS) + nk - 1) / nk) * KS;
     pl.nkc = (Kp + pl.kc - 1) / pl.kc;
@@ -472,6 +510,16 @@ void launch_mfma_scatter(int dt, const MfmaPlan& pl, const void* Af, const void*
         case DT_BF16: go_tile<DT_BF16, MK_F32, false>(a, pl, s); break;
         default: go_tile<DT_BF16X3, MK_F32, false>(a, pl, s); break;
     }
+}
+
+MfmaPlan mfma_helm_plan(int N, int Np, int Bpad, MfmaTile t) { return mfma_plan(MK_F64, N, 1, Np, Bpad, t); }
+
+void launch_mfma_helm(const MfmaPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
+                      const long long* stepp, double* part, hipStream_t s) {
+    MfmaArgs a = fill_args(pl, hinv, nullptr, rhs, nullptr, nullptr, part, Np, 0, N, 1, Np, Bpad, 0);
+    a.kstep = stepp;
+    a.a_kstride = (long long)N * Np;
+    go_tile<DT_F64, MK_F64, false>(a, pl, s);
 }
 
 void launch_hadamard(int dt, const void* P, int nz, int Bpad, int B, int Rp, const void* lam, void* W,

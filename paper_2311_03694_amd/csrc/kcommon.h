@@ -103,6 +103,28 @@ __device__ __forceinline__ T block_sum(T v, T* scratch) {
     return s;
 }
 
+// ---------------------------------------------------------------- staging into LDS
+
+// Block-cooperative loop over q in [0, n): out(q, in(q)), with U loads per thread
+// issued before any store, so a staging pass costs one memory round trip per U
+// elements instead of one per element.
+template <int U, class T, class LoadF, class StoreF>
+__device__ __forceinline__ void staged_copy(int n, LoadF load, StoreF store) {
+    for (int base = threadIdx.x; base < n; base += U * (int)blockDim.x) {
+        T v[U];
+#pragma unroll
+        for (int e = 0; e < U; ++e) {
+            const int q = base + e * (int)blockDim.x;
+            if (q < n) v[e] = load(q);
+        }
+#pragma unroll
+        for (int e = 0; e < U; ++e) {
+            const int q = base + e * (int)blockDim.x;
+            if (q < n) store(q, v[e]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- grouped launches
 
 // Job p with jobs[p].blk0 <= q < jobs[p+1].blk0 (jobs sorted by blk0, blk0[0] = 0).

@@ -44,24 +44,25 @@ template <int DT> struct LdsU {
     // Convert u (FP64, N values) into an image of Np >= N entries, zero beyond N; call
     // with the whole block, then __syncthreads.
     __device__ void fill(const double* __restrict__ u, int N, int Np) {
-        for (int q = threadIdx.x; q < Np; q += blockDim.x) {
-            const double v = q < N ? u[q] : 0.0;
-            if constexpr (DT == DT_F64) {
-                uh[q] = v;
-            } else if constexpr (DT == DT_F32) {
-                uh[q] = (float)v;
-            } else if constexpr (DT == DT_BF16) {
-                const unsigned short h = bf16_bits((float)v);
-                uh[q] = h;
-                uw[q] = bf16_f(h);
-            } else {
-                const float f = (float)v;
-                const unsigned short h = bf16_bits(f);
-                uh[q] = h;
-                ul[q] = bf16_bits(f - bf16_f(h));
-                uw[q] = f;
-            }
-        }
+        staged_copy<8, double>(
+            Np, [&](int q) { return q < N ? u[q] : 0.0; },
+            [&](int q, double v) {
+                if constexpr (DT == DT_F64) {
+                    uh[q] = v;
+                } else if constexpr (DT == DT_F32) {
+                    uh[q] = (float)v;
+                } else if constexpr (DT == DT_BF16) {
+                    const unsigned short h = bf16_bits((float)v);
+                    uh[q] = h;
+                    uw[q] = bf16_f(h);
+                } else {
+                    const float f = (float)v;
+                    const unsigned short h = bf16_bits(f);
+                    uh[q] = h;
+                    ul[q] = bf16_bits(f - bf16_f(h));
+                    uw[q] = f;
+                }
+            });
     }
 };
 

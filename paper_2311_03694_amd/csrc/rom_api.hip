@@ -133,6 +133,8 @@ struct WsPlan {
     size_t part2_off = 0;           // CP projection partials (B > 1)
     size_t w_off = 0;               // CP Hadamard products W [Bpad][Rp] (B > 1)
     size_t ucv_off = 0, ucvlo_off = 0, usc_off = 0;   // rom_nonlinear operand copies (B > 1)
+    MfmaPlan ph{};                  // B > 1, dense stiffness: FP64 Helmholtz apply
+    size_t helm_off = 0;
     size_t total = 0;
 };
 
@@ -173,6 +175,11 @@ WsPlan plan_ws(rom_ctx c, int B) {
         off = align256(off + (c->dtype == DT_BF16X3 ? (size_t)p.Bpad * c->Np * 2 : 0));
         p.usc_off = off;
         off = align256(off + (size_t)p.Bpad * c->Np * 4);
+        if (!c->diagA) {
+            p.ph = mfma_helm_plan(c->N, c->Np, p.Bpad, mfma_variant(0));
+            p.helm_off = off;
+            off = align256(off + (size_t)p.ph.nsplit * p.Bpad * c->N * 8);
+        }
     }
     p.total = off + 256;
     return p;
@@ -328,11 +335,13 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
     } else {
         double* work = nullptr;
         int* info = nullptr;
-        TRY(dmalloc((void**)&c->hinv, sizeof(double) * 3 * nn, &c->bytes, &c->allocs));
+        const size_t hbytes = sizeof(double) * 3 * (size_t)N * c->Np + 256;
+        TRY(dmalloc((void**)&c->hinv, hbytes, &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->hinv, 0, hbytes, c->stream));
         HTRY(hipMalloc((void**)&work, sizeof(double) * 3 * nn));
         HTRY(hipMalloc((void**)&info, sizeof(int)));
         HTRY(hipMemsetAsync(info, 0, sizeof(int), c->stream));
-        helm_setup_dense((int)N, d->nu, d->dt, stage, c->hinv, work, info, c->stream);
+        helm_setup_dense((int)N, c->Np, d->nu, d->dt, stage, c->hinv, work, info, c->stream);
         hipError_t le = hipGetLastError();
         int hinfo = 0;
         hipError_t se = hipStreamSynchronize(c->stream);
@@ -445,7 +454,15 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream) {
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.ps.nsplit, p.Bpad, diag, stream);
         }
     }
-    if (!c->diagA) launch_helm_apply(a, stream);
+    if (!c->diagA) {
+        if (s->B == 1) {
+            launch_helm_apply(a, stream);
+        } else {
+            double* hp = (double*)((char*)c->ws + p.helm_off);
+            launch_mfma_helm(p.ph, c->hinv, c->N, c->Np, p.Bpad, a.rhs, a.step, hp, stream);
+            launch_helm_finish(a, hp, p.ph.nsplit, stream);
+        }
+    }
     HIPCHK(hipGetLastError());
     return ROM_OK;
 }
@@ -634,7 +651,7 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     a.hinv = c->hinv;
     TRY(dmalloc((void**)&a.uring, sizeof(double) * 3 * BN, &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.yring, sizeof(double) * 3 * BN, &s->bytes, &s->allocs));
-    TRY(dmalloc((void**)&a.rhs, sizeof(double) * BN, &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.rhs, sizeof(double) * s->Bpad * c->Np, &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.epart, sizeof(double) * B * ((N + 3) / 4 + 64), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.step, sizeof(long long), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
@@ -651,7 +668,8 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
             return fail(ROM_E_DEVICE, "state clear failed");
         }
     }
-    if (hipMemsetAsync(a.uring, 0, sizeof(double) * 3 * BN, c->stream) != hipSuccess ||
+    if (hipMemsetAsync(a.rhs, 0, sizeof(double) * s->Bpad * c->Np, c->stream) != hipSuccess ||
+        hipMemsetAsync(a.uring, 0, sizeof(double) * 3 * BN, c->stream) != hipSuccess ||
         hipMemsetAsync(a.yring, 0, sizeof(double) * 3 * BN, c->stream) != hipSuccess) {
         rom_state_destroy(s);
         return fail(ROM_E_DEVICE, "state clear failed");

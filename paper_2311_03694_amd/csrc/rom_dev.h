@@ -31,11 +31,11 @@ struct StepArgs {
     long long* bad;          // first non-finite level (LLONG_MAX: none)
     double* elog;            // [cap][B] energy per level
     long long elog_cap;
-    double* rhs;             // [B][N] right-hand sides (dense stiffness)
+    double* rhs;             // [Bpad][Np] right-hand sides (dense stiffness; padding zero)
     double* epart;           // [B][nblk] energy partial sums
     unsigned* ticket;        // arrival counter of the last-block reduction (0 at rest)
     const double* hdiag;     // [3][N] 1/(beta0_k/dt + nu A_ii) (diagonal stiffness)
-    const double* hinv;      // [3][N][N] (beta0_k/dt I + nu A)^-1 (dense stiffness)
+    const double* hinv;      // [3][N][Np] (beta0_k/dt I + nu A)^-1, row pitch Np (dense stiffness)
     // coefficient copies in the contraction's number format for the batched kernels,
     // laid out [Bpad][Np] (padding rows and columns stay zero); written by the update
     // of each step
@@ -150,8 +150,10 @@ int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, const void* la
 // stiffness (update, energy, finalize); diag = 0: right-hand side only.
 void launch_bdf_from_partials(const StepArgs& a, int acc_f64, const void* part, int nchunk,
                               int pb, int diag, hipStream_t s);
-// Dense stiffness: u^{n+1} = Hinv_k rhs, energy, finalize.
+// Dense stiffness, one trajectory: u^{n+1} = Hinv_k rhs, energy, finalize.
 void launch_helm_apply(const StepArgs& a, hipStream_t s);
+// Dense stiffness, batch: sum the FP64 MFMA partials of Hinv_k rhs, energy, finalize.
+void launch_helm_finish(const StepArgs& a, const double* part, int nsplit, hipStream_t s);
 // Write the batched coefficient copies from the current level (state create / set).
 void launch_prep_ucv(const StepArgs& a, const double* u_src, hipStream_t s);
 // Sum partials into FP64 y [B][N] (rom_nonlinear).
@@ -159,7 +161,7 @@ void launch_sum_partials(int acc_f64, const void* part, int nchunk, int pb, int 
                          double* y, hipStream_t s);
 
 // Helmholtz setup on the device: H = (beta0/dt) I + nu A, Cholesky, inverse.
-int helm_setup_dense(int N, double nu, double dt, const double* A_dev, double* hinv_dev,
+int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, double* hinv_dev,
                      double* work_dev, int* info_dev, hipStream_t s);
 void helm_setup_diag(int N, double nu, double dt, const double* A_dev, double* hdiag_dev,
                      hipStream_t s);
@@ -178,6 +180,11 @@ void launch_mfma_proj(int dt, const MfmaPlan& pl, const void* BCt, const void* B
 MfmaPlan mfma_scatter_plan(int dt, int N, int Rp, int Bpad, MfmaTile t);
 void launch_mfma_scatter(int dt, const MfmaPlan& pl, const void* Af, const void* Af_lo, int N, int Rp, int Bpad,
                          const void* W, void* part, hipStream_t s);
+// Batched Helmholtz apply: partials [nsplit][Bpad][N] (FP64) of Hinv_k rhs, with k read
+// from the device step counter; Hinv [3][N][Np], rhs [Bpad][Np].
+MfmaPlan mfma_helm_plan(int N, int Np, int Bpad, MfmaTile t);
+void launch_mfma_helm(const MfmaPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
+                      const long long* stepp, double* part, hipStream_t s);
 // W[b][r] = lam_r s_r t_r from projection partials P [nz][Bpad][2Rp].
 void launch_hadamard(int dt, const void* P, int nz, int Bpad, int B, int Rp, const void* lam, void* W,
                      hipStream_t s);
