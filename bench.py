@@ -59,26 +59,40 @@ def parse():
                     help="target length of the oracle sample (CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no batched/config2/serving)")
+    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "serving"],
+                    help="run one section only (profiling); the JSON line then holds that section")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
-def _file_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+CSRC = os.path.join(ROOT, "paper_2311_03694_amd", "csrc")
+# the sources each profiled kernel is compiled from (its counter record is valid only
+# while their combined hash is unchanged)
+KERNEL_SOURCES = {
+    "dense_gemv": ["k_dense1.hip", "kdot.h", "kcommon.h", "rom_dev.h"],
+    "mfma_rows": ["k_mfma.hip", "kcommon.h", "rom_dev.h"],
+}
 
 
-def _traffic(name, src):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if the kernel source
-    has not changed since they were taken; else None."""
+def sources_sha(kernel):
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _traffic(name, kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if the kernel's
+    sources have not changed since they were taken; else None."""
     path = os.path.join(ROOT, "profiles", f"{name}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha256") != _file_sha(src):
+    if rec.get("sources_sha256") != sources_sha(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -126,7 +140,7 @@ def main():
 
     t0 = time.time()
     log(f"generating N={N} workload")
-    p = romsynth.make_config(3, R=R, batch=1)
+    p = romsynth.make_config(3, R=R, batch=1, dense=args.section in ("all", "headline", "batched"))
     log(f"generated in {time.time() - t0:.1f}s")
 
     if args.calib_copy:
@@ -155,56 +169,65 @@ def main():
         rg.rom_nonlinear(rom.handle, B, ud, yd)
         return timer(lambda: [rg.rom_nonlinear(rom.handle, B, ud, yd) for _ in range(reps)]) / reps
 
-    # ---------------- headline: CP-ROM and dense G-ROM, one trajectory
-    log("CP-ROM")
-    rom_cp = make(False)
-    s_cp, t_cp = step_rate(rom_cp, p.u0, K, W)
-    cp_kernel = kernel_avg(rom_cp, p.u0, args.kernel_reps * 10)
-    log(f"CP {K} steps in {t_cp:.3f}s")
-    log("dense G-ROM")
-    rom_d = make(True)
-    s_d, t_d = step_rate(rom_d, p.u0, Kd, min(W, 20))
-    d_kernel = kernel_avg(rom_d, p.u0, args.kernel_reps)
-    log(f"dense {Kd} steps in {t_d:.3f}s")
+    sec = args.section
+    if sec not in ("all", "headline"):
+        args.no_cpu = True
+    result = {"metric": METRIC, "value": None, "unit": "trajectory-steps/s", "n_gpus": 1,
+              "section": sec}
+    if sec in ("all", "headline"):
+        # ---------------- headline: CP-ROM and dense G-ROM, one trajectory
+        log("CP-ROM")
+        rom_cp = make(False)
+        s_cp, t_cp = step_rate(rom_cp, p.u0, K, W)
+        cp_kernel = kernel_avg(rom_cp, p.u0, args.kernel_reps * 10)
+        log(f"CP {K} steps in {t_cp:.3f}s")
+        log("dense G-ROM")
+        rom_d = make(True)
+        s_d, t_d = step_rate(rom_d, p.u0, Kd, min(W, 20))
+        d_kernel = kernel_avg(rom_d, p.u0, args.kernel_reps)
+        log(f"dense {Kd} steps in {t_d:.3f}s")
 
-    es = ELEM_BYTES[dt]
-    cp_rate = K / t_cp
-    d_rate = Kd / t_d
-    d_bytes = float(N) ** 3 * es
-    cp_bytes = 3.0 * N * R * es
-    src = os.path.join(ROOT, "paper_2311_03694_amd", "csrc", "k_dense1.hip")
-    result = {
-        "metric": METRIC,
-        "value": cp_rate,
-        "unit": "trajectory-steps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": t_cp / K * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": dt,
-        "data": "synthetic (seeded skew-CP tensor, N=1000, rank 2000, eps 1e-7, SPD stiffness)",
-        "config": {"workload": f"N=1000 ROM, CP rank {R} vs dense G-ROM, BDF3/EXT3, one trajectory",
-                   "N": N, "R": R, "batch": 1, "nu": p.nu, "dt": p.dt, "stiffness": "diag(k^2)+SPD(0.1)"},
-        "dense": {"value": d_rate, "unit": "trajectory-steps/s", "steps": Kd, "ms_per_step": t_d / Kd * 1e3},
-        "speedup_cp_vs_dense": cp_rate / d_rate,
-        "roofline": {"bound": "hbm", "kernel": "k_dense_gemv (dense contraction, one trajectory)",
-                     "achieved": d_bytes / d_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": d_bytes / d_kernel / 1e9 / HBM_PEAK_GBS,
-                     "traffic": _traffic(f"dense_gemv_n{N}_{dt}", src),
-                     "avg_launch_us": d_kernel * 1e6, "algorithmic_bytes": d_bytes},
-        "roofline_cp": {"bound": "latency", "kernel": "k_cp_proj1 + k_cp_scatter1",
-                        "achieved": cp_bytes / cp_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": cp_bytes / cp_kernel / 1e9 / HBM_PEAK_GBS,
-                        "avg_launch_us": cp_kernel * 1e6, "algorithmic_bytes": cp_bytes},
-    }
-    s_cp.close()
-    s_d.close()
+        es = ELEM_BYTES[dt]
+        cp_rate = K / t_cp
+        d_rate = Kd / t_d
+        d_bytes = float(N) ** 3 * es
+        cp_bytes = 3.0 * N * R * es
+        result = {
+            "metric": METRIC,
+            "value": cp_rate,
+            "unit": "trajectory-steps/s",
+            "n_gpus": 1,
+            "steps": K,
+            "warmup": W,
+            "ms_per_step": t_cp / K * 1e3,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": dt,
+            "data": "synthetic (seeded skew-CP tensor, N=1000, rank 2000, eps 1e-7, SPD stiffness)",
+            "config": {"workload": f"N=1000 ROM, CP rank {R} vs dense G-ROM, BDF3/EXT3, one trajectory",
+                       "N": N, "R": R, "batch": 1, "nu": p.nu, "dt": p.dt, "stiffness": "diag(k^2)+SPD(0.1)"},
+            "dense": {"value": d_rate, "unit": "trajectory-steps/s", "steps": Kd, "ms_per_step": t_d / Kd * 1e3},
+            "speedup_cp_vs_dense": cp_rate / d_rate,
+            "roofline": {"bound": "hbm", "kernel": "k_dense_gemv (dense contraction, one trajectory)",
+                         "achieved": d_bytes / d_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": d_bytes / d_kernel / 1e9 / HBM_PEAK_GBS,
+                         "traffic": _traffic(f"dense_gemv_n{N}_{dt}", "dense_gemv"),
+                         "avg_launch_us": d_kernel * 1e6, "algorithmic_bytes": d_bytes},
+            "roofline_cp": {"bound": "latency", "kernel": "k_cp_proj1 + k_cp_scatter1",
+                            "achieved": cp_bytes / cp_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": cp_bytes / cp_kernel / 1e9 / HBM_PEAK_GBS,
+                            "avg_launch_us": cp_kernel * 1e6, "algorithmic_bytes": cp_bytes},
+        }
+        s_cp.close()
+        s_d.close()
 
+
+    if sec == "headline":
+        args.no_extra = True
     if not args.no_extra:
         tiles = tune.load()
+    if not args.no_extra and sec in ("all", "batched"):
         # ---------------- batched trajectories at N = 1000 (MFMA kernels)
         batched = {}
         for B in (16, 64):
@@ -233,6 +256,7 @@ def main():
                     f"cp {entry['cp']['traj_steps_per_s']:.0f} traj-steps/s")
         result["batched"] = batched
 
+    if not args.no_extra and sec in ("all", "config2"):
         # ---------------- config 2: N = 400, B = 256
         log("config 2 (N=400, B=256)")
         p2 = romsynth.make_config(2, R=400)
@@ -259,8 +283,10 @@ def main():
                                    "achieved": c2["dense_bf16"]["tflops"], "peak": MFMA_PEAK_TFLOPS["bf16"],
                                    "unit": "TFLOP/s", "frac": c2["dense_bf16"]["mfma_frac"],
                                    "avg_launch_us": c2["dense_bf16"]["contraction_us"],
-                                   "algorithmic_flops": 2.0 * 400 ** 3 * 256}
+                                   "algorithmic_flops": 2.0 * 400 ** 3 * 256,
+                                   "traffic": _traffic("mfma_dense_n400_b256_bf16", "mfma_rows")}
 
+    if not args.no_extra and sec in ("all", "serving"):
         # ---------------- serving: bounded Poisson stream
         from paper_2311_03694_amd.serve import RomBackend, Server, poisson_requests, summarize
         log("serving")

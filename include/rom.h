@@ -3,7 +3,7 @@
  * (ROM) on one AMD Instinct MI355X (gfx950), with the advection tensor either dense
  * (the standard G-ROM) or in CP form (the CPD-ROM), following arXiv 2311.03694.
  *
- * The model (Sec. 2, eq. nse_ode, identity mass matrix, core tensor without the
+ * The model (Sec. 2.2, eq. nse_ode, identity mass matrix, core tensor without the
  * zeroth mode) is
  *     du/dt = -C(u)u - nu A u,   [C(u)u]_i = sum_{j,k} C[i][j][k] u_j u_k,
  * integrated by the semi-implicit BDFk/EXTk scheme of eq. nse_d1: the viscous term is
@@ -55,7 +55,7 @@ typedef enum {
  *                products hi*hi + hi*lo + lo*hi, FP32 accumulation. */
 typedef enum { ROM_FP64 = 0, ROM_FP32 = 1, ROM_BF16 = 2, ROM_BF16X3 = 3 } rom_dtype;
 
-/* Problem description handed to rom_create (Sec. 2, eqs. nse_ode / nse_d1).
+/* Problem description handed to rom_create (Sec. 2.2, eqs. nse_ode / nse_d1).
  *   N         number of modes, 1 <= N.
  *   nu        viscosity, the paper's 1/Re (>= 0).
  *   dt        time step (> 0).
@@ -92,7 +92,7 @@ typedef struct rom_desc {
 rom_status rom_create(const rom_desc *d, rom_ctx *out);
 void rom_destroy(rom_ctx ctx);
 
-/* y = C(u)u for `batch` coefficient vectors (Sec. 2, eq. Cu; CP form: eq. tc_ap).
+/* y = C(u)u for `batch` coefficient vectors (Sec. 2.2, eq. Cu; CP form: eq. tc_ap).
  * u_dev, y_dev: device FP64 [batch][N], caller-owned; 1 <= batch <= max_batch.
  * The contraction runs in the context's dtype; y is returned in FP64.  Asynchronous. */
 rom_status rom_nonlinear(rom_ctx ctx, int32_t batch, const double *u_dev, double *y_dev);

@@ -14,7 +14,7 @@
  * Storage (row-major, 0-based):
  *   C[i][j][k]  = the paper's C_{i k j} with output row i; the pair (j, k) is the pair
  *                 of advecting/advected coefficients.  The contraction is symmetric in
- *                 j and k, so y_i = sum_j sum_k C[i][j][k] u_j u_k  (Sec. 2, eq. Cu).
+ *                 j and k, so y_i = sum_j sum_k C[i][j][k] u_j u_k  (Sec. 2.2, eq. Cu).
  *   Af,Bf,Cf    = [N][R] CP factors for tensor positions 1, 2, 3; lam = [R] weights.
  *   A           = [N][N] reduced stiffness; the mass matrix is the identity.
  *
@@ -28,7 +28,7 @@
 
 /* ------------------------------------------------------------------ contractions */
 
-/* Dense advection term of the G-ROM (Sec. 2, eq. Cu and the C(u)u term of eq. nse_d1):
+/* Dense advection term of the G-ROM (Sec. 2.2, eq. Cu and the C(u)u term of eq. nse_d1):
  *   y_i = sum_{j} u_j * ( sum_{k} C[i][j][k] * u_k ),  2 N^3 flops. */
 void orc_nonlinear_dense(int64_t N, const double *C, const double *u, double *y)
 {
@@ -91,7 +91,7 @@ void orc_nonlinear_cp(int64_t N, int64_t R, const double *lam, const double *Af,
     free(t);
 }
 
-/* Kruskal tensor (Sec. 2.2, eq. cpd, with weights):
+/* Kruskal tensor (Sec. 2.3, eq. cpd, with weights):
  *   T[i][j][k] = sum_r lam_r Af[i][r] Bf[j][r] Cf[k][r]. */
 void orc_reconstruct(int64_t N, int64_t R, const double *lam, const double *Af,
                      const double *Bf, const double *Cf, double *T)

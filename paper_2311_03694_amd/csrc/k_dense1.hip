@@ -1,4 +1,4 @@
-// k_dense1.hip -- dense advection contraction for one trajectory (Sec. 2, eq. Cu;
+// k_dense1.hip -- dense advection contraction for one trajectory (Sec. 2.2, eq. Cu;
 // the 2N^3-flop term of the G-ROM):
 //     y_i = sum_j u_j * sum_k C[i][j][k] u_k.
 //

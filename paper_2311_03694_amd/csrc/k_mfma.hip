@@ -2,7 +2,7 @@
 //
 // One kernel shape serves three products, Out[b][m] over a row operand A and a
 // coefficient operand X ([Bpad][Kp], trajectory-major):
-//   dense (Sec. 2, eq. Cu, the G-ROM term; "KR" = Khatri-Rao form):
+//   dense (Sec. 2.2, eq. Cu, the G-ROM term; "KR" = Khatri-Rao form):
 //       Y[b][i] = sum_j S[b][j] * sum_k C[i][j][k] X[b][k],   S = X = u (per format),
 //     i.e. C_(1) [N x N^2] times the Khatri-Rao columns u_b (x) u_b, without ever
 //     forming u (x) u: the inner sum over k is an MFMA GEMM of the C slab at fixed j
