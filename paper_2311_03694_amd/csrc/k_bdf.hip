@@ -172,10 +172,13 @@ __global__ __launch_bounds__(256) void k_helm_finish(StepArgs a, const double* _
 }
 
 // Batched coefficient copies of u [B][N] (state creation / restart, batched
-// rom_nonlinear).  Grid (ceil(N/256), B).
+// rom_nonlinear), padding included: trajectories b >= B and indices i >= N are written
+// as zeros, so the copies never depend on what their memory held before (the
+// contractions multiply the zero padding of the operators by these entries).
+// Grid (ceil(Np/256), Bpad).
 __global__ void k_prep_ucv(StepArgs a, const double* __restrict__ u) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
-    if (i < a.N) write_ucv(a, b, i, u[(size_t)b * a.N + i]);
+    if (i < a.Np) write_ucv(a, b, i, (b < a.B && i < a.N) ? u[(size_t)b * a.N + i] : 0.0);
 }
 
 template <class ACC>
@@ -237,7 +240,7 @@ void launch_helm_finish(const StepArgs& a, const double* part, int nsplit, hipSt
 }
 
 void launch_prep_ucv(const StepArgs& a, const double* u_src, hipStream_t s) {
-    hipLaunchKernelGGL(k_prep_ucv, dim3((a.N + 255) / 256, a.B), dim3(256), 0, s, a, u_src);
+    hipLaunchKernelGGL(k_prep_ucv, dim3((a.Np + 255) / 256, a.Bpad), dim3(256), 0, s, a, u_src);
 }
 
 void launch_sum_partials(int acc_f64, const void* part, int nchunk, int pb, int B, int N,

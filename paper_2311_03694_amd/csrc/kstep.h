@@ -31,24 +31,26 @@ __device__ __forceinline__ double bdf_rhs_point(const StepArgs& a, long long n, 
 
 // Coefficient copies for the batched contraction ([Bpad][Np] layout).
 __device__ __forceinline__ void write_ucv(const StepArgs& a, int b, int i, double u) {
-    const size_t o = (size_t)b * a.Np + i;
+    const size_t o = (size_t)b * a.Np + i, oj = (size_t)i * a.Bpad + b;
     if (a.dtype == DT_F64) {
         reinterpret_cast<double*>(a.ucv)[o] = u;
+        reinterpret_cast<double*>(a.uj)[oj] = u;
     } else {
         const float f = (float)u;
+        float* uj = reinterpret_cast<float*>(a.uj);
         if (a.dtype == DT_F32) {
             reinterpret_cast<float*>(a.ucv)[o] = f;
-            a.uscale[o] = f;
+            uj[oj] = f;
         } else if (a.dtype == DT_BF16) {
             const unsigned short h = bf16_bits(f);
             reinterpret_cast<unsigned short*>(a.ucv)[o] = h;
-            a.uscale[o] = bf16_f(h);
+            uj[oj] = bf16_f(h);
         } else {
             const unsigned short h = bf16_bits(f);
             const unsigned short l = bf16_bits(f - bf16_f(h));
             reinterpret_cast<unsigned short*>(a.ucv)[o] = h;
             reinterpret_cast<unsigned short*>(a.ucv_lo)[o] = l;
-            a.uscale[o] = f;
+            uj[oj] = f;
         }
     }
 }

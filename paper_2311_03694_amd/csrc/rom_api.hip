@@ -63,6 +63,7 @@ struct rom_ctx_s {
     // operators in the contraction format
     // (contracted indices padded with zeros: Np, Rp = N, R rounded up to multiples of 8)
     void *C = nullptr, *Clo = nullptr;         // dense [N][N][Np]
+    void *Ct = nullptr, *Ct_lo = nullptr;      // dense, max_batch > 1: tiled copy for k_kr
     void *BCt = nullptr, *BCt_lo = nullptr;    // CP [2Rp][Np]: rows Bf^T then Cf^T
     void *Af = nullptr, *Af_lo = nullptr;      // CP [N][Rp]
     void* lam = nullptr;                        // CP [Rp] (FP64 or FP32)
@@ -74,6 +75,7 @@ struct rom_ctx_s {
     int ws_gen = 0;
     // tiles (-1 = heuristic)
     int tile[4] = {-1, -1, -1, -1};
+    size_t lds_max = 65536;                     // dynamic LDS a batched kernel may take
     size_t bytes = 0;
     std::vector<void*> allocs;
 };
@@ -128,7 +130,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct WsPlan {
     int B = 1, Bpad = 16;
     int nchunk = 0;                 // B = 1 dense: partial chunks per row
-    MfmaPlan pd{}, pp{}, ps{};      // B > 1: dense, CP projection, CP scatter
+    DensePlan pd{};                 // B > 1: dense contraction
+    MfmaPlan pp{}, ps{};            // B > 1: CP projection, CP scatter
     size_t part_off = 0;            // dense / scatter partials, or CP s,t (B = 1)
     size_t part2_off = 0;           // CP projection partials (B > 1)
     size_t w_off = 0;               // CP Hadamard products W [Bpad][Rp] (B > 1)
@@ -156,7 +159,7 @@ WsPlan plan_ws(rom_ctx c, int B) {
     } else {
         const size_t eb = elem_bytes(c->dtype);
         if (c->dense) {
-            p.pd = mfma_dense_plan(c->dtype, c->N, c->Np, p.Bpad, mfma_tile(c, 1));
+            p.pd = dense_batched_plan(c->dtype, c->N, c->Np, p.Bpad, c->tile[1], c->lds_max);
             p.part_off = off;
             off = align256(off + (size_t)p.pd.nsplit * p.Bpad * c->N * ab);
         } else {
@@ -174,7 +177,7 @@ WsPlan plan_ws(rom_ctx c, int B) {
         p.ucvlo_off = off;
         off = align256(off + (c->dtype == DT_BF16X3 ? (size_t)p.Bpad * c->Np * 2 : 0));
         p.usc_off = off;
-        off = align256(off + (size_t)p.Bpad * c->Np * 4);
+        off = align256(off + (size_t)p.Bpad * c->Np * ab);
         if (!c->diagA) {
             p.ph = mfma_helm_plan(c->N, c->Np, p.Bpad, mfma_variant(0));
             p.helm_off = off;
@@ -199,7 +202,6 @@ rom_status ensure_ws(rom_ctx c, size_t bytes) {
         c->ws = nullptr;
         return fail(ROM_E_NOMEM, "workspace hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
-    // the operand copies of rom_nonlinear rely on zero padding
     hipMemsetAsync(c->ws, 0, bytes, c->stream);
     c->ws_bytes = bytes;
     c->bytes += bytes;
@@ -291,6 +293,20 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
             return st;                                                                    \
         }                                                                                 \
     } while (0)
+
+    // dynamic LDS the batched register kernel may request (the device limit, at most
+    // 120 KB; 64 KB if raising the per-kernel limit is refused)
+    {
+        int dev = 0, lds = 0;
+        HTRY(hipGetDevice(&dev));
+        HTRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        size_t want = lds > 122880 ? 122880 : (size_t)lds;
+        if (want > 65536 && kr_set_lds_limit(want) != hipSuccess) {
+            (void)hipGetLastError();
+            want = 65536;
+        }
+        c->lds_max = want;
+    }
     if (!c->stream) {
         HTRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         c->own_stream = true;
@@ -379,6 +395,17 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
             HTRY(hipMemsetAsync(c->Clo, 0, n3 * 2 + kSlack, c->stream));
         }
         TRY(upload_convert(c, d->C, nn, (int)N, (int)Np, c->C, c->Clo, stage, stage_elems));
+        if (c->max_batch > 1) {
+            // the batched kernel's tiled copy (a permutation of the converted words)
+            const size_t tb = kr_tiled_bytes(dt, (int)N, (int)eb);
+            TRY(dmalloc(&c->Ct, tb, &c->bytes, &c->allocs));
+            launch_kr_tile(dt, (int)eb, c->C, c->Ct, (int)N, (int)Np, c->stream);
+            if (lo) {
+                TRY(dmalloc(&c->Ct_lo, kr_tiled_bytes(dt, (int)N, 2), &c->bytes, &c->allocs));
+                launch_kr_tile(dt, 2, c->Clo, c->Ct_lo, (int)N, (int)Np, c->stream);
+            }
+            HTRY(hipGetLastError());
+        }
     } else {
         const size_t R = c->R, Rp = c->Rp;
         TRY(dmalloc(&c->BCt, 2 * Rp * Np * eb + kSlack, &c->bytes, &c->allocs));
@@ -439,10 +466,9 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream) {
         }
     } else {
         char* ws = (char*)c->ws;
-        const void* S = c->dtype == DT_F64 ? a.ucv : (const void*)a.uscale;
         if (c->dense) {
-            launch_mfma_dense(c->dtype, p.pd, c->C, c->Clo, c->N, c->Np, p.Bpad, a.ucv, a.ucv_lo, S,
-                              ws + p.part_off, stream);
+            launch_dense_batched(c->dtype, p.pd, c->C, c->Clo, c->Ct, c->Ct_lo, c->N, c->Np, p.Bpad, a.ucv,
+                                 a.ucv_lo, a.uj, ws + p.part_off, stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.pd.nsplit, p.Bpad, diag, stream);
         } else {
             launch_mfma_proj(c->dtype, p.pp, c->BCt, c->BCt_lo, c->Np, c->Rp, p.Bpad, a.ucv, a.ucv_lo,
@@ -498,12 +524,11 @@ extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_de
         a.batched = 1;
         a.ucv = ws + p.ucv_off;
         a.ucv_lo = ws + p.ucvlo_off;
-        a.uscale = (float*)(ws + p.usc_off);
+        a.uj = ws + p.usc_off;
         launch_prep_ucv(a, u_dev, c->stream);
-        const void* S = c->dtype == DT_F64 ? a.ucv : (const void*)a.uscale;
         if (c->dense) {
-            launch_mfma_dense(c->dtype, p.pd, c->C, c->Clo, c->N, c->Np, p.Bpad, a.ucv, a.ucv_lo, S,
-                              ws + p.part_off, c->stream);
+            launch_dense_batched(c->dtype, p.pd, c->C, c->Clo, c->Ct, c->Ct_lo, c->N, c->Np, p.Bpad, a.ucv,
+                                 a.ucv_lo, a.uj, ws + p.part_off, c->stream);
             launch_sum_partials(accf, ws + p.part_off, p.pd.nsplit, p.Bpad, batch, c->N, y_dev, c->stream);
         } else {
             launch_mfma_proj(c->dtype, p.pp, c->BCt, c->BCt_lo, c->Np, c->Rp, p.Bpad, a.ucv, a.ucv_lo,
@@ -659,10 +684,10 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     if (a.batched) {
         const size_t cells = (size_t)s->Bpad * c->Np;
         TRY(dmalloc(&a.ucv, cells * elem_bytes(c->dtype), &s->bytes, &s->allocs));
-        TRY(dmalloc((void**)&a.uscale, cells * 4, &s->bytes, &s->allocs));
+        TRY(dmalloc(&a.uj, cells * acc_bytes(c->dtype), &s->bytes, &s->allocs));
         if (c->dtype == DT_BF16X3) TRY(dmalloc(&a.ucv_lo, cells * 2, &s->bytes, &s->allocs));
         if (hipMemsetAsync(a.ucv, 0, cells * elem_bytes(c->dtype), c->stream) != hipSuccess ||
-            hipMemsetAsync(a.uscale, 0, cells * 4, c->stream) != hipSuccess ||
+            hipMemsetAsync(a.uj, 0, cells * acc_bytes(c->dtype), c->stream) != hipSuccess ||
             (a.ucv_lo && hipMemsetAsync(a.ucv_lo, 0, cells * 2, c->stream) != hipSuccess)) {
             rom_state_destroy(s);
             return fail(ROM_E_DEVICE, "state clear failed");
@@ -1083,7 +1108,8 @@ extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* v
 extern "C" int32_t rom_tile_count(int32_t kind) {
     switch (kind) {
         case 0: return dense_gemv_variants();
-        case 1: case 2: case 3: return mfma_variants();
+        case 1: return dense_batched_variants();
+        case 2: case 3: return mfma_variants();
         default: return 0;
     }
 }

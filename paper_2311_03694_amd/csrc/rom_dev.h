@@ -41,10 +41,11 @@ struct StepArgs {
     // of each step
     void* ucv;               // FP64 / FP32 / BF16 words (BF16X3: high words)
     void* ucv_lo;            // BF16X3 low words
-    float* uscale;           // FP32 (BF16: BF16-rounded) values used as the j-weight
+    void* uj;                // [Np][Bpad] j-weights in the accumulation type: FP64 (DT_F64),
+                             // else FP32 (the BF16-rounded value for DT_BF16)
     int Bpad, Np;
     int dtype;               // Dt of the contraction
-    int batched;             // 1: write ucv/uscale for the batched contraction
+    int batched;             // 1: write ucv/uj for the batched contraction
 };
 
 // ---------------------------------------------------------------- grouped launches
@@ -168,7 +169,7 @@ void helm_setup_diag(int N, double nu, double dt, const double* A_dev, double* h
 
 // Batched contraction launchers (k_mfma.hip).  Partials are [nsplit][Bpad][M] in the
 // accumulation type (FP64 for DT_F64, FP32 otherwise).
-//   dense:   M = N rows of C [N][N][Np], X = u [Bpad][Np] and j-weights S [Bpad][Np]
+//   dense:   M = N rows of C [N][N][Np], X = u [Bpad][Np] and j-weights S [Np][Bpad]
 //   proj:    M = 2Rp rows of [Bf|Cf]^T [2Rp][Np], X = u [Bpad][Np]
 //   scatter: M = N rows of Af [N][Rp], X = W [Bpad][Rp] (FP32, FP64 for DT_F64)
 MfmaPlan mfma_dense_plan(int dt, int N, int Np, int Bpad, MfmaTile t);
@@ -185,6 +186,40 @@ void launch_mfma_scatter(int dt, const MfmaPlan& pl, const void* Af, const void*
 MfmaPlan mfma_helm_plan(int N, int Np, int Bpad, MfmaTile t);
 void launch_mfma_helm(const MfmaPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
                       const long long* stepp, double* part, hipStream_t s);
+// Batched dense contraction with the coefficient fragments held in registers
+// (k_kr.hip).  Partials [nsplit][Bpad][N]; X = u [Bpad][Np], j-weights S [Np][Bpad];
+// the tensor comes from the tiled copy Ct [ceil(N/16)][N][Kt/VEC][16][VEC] made by
+// launch_kr_tile (Kt = kr_tiled_k, VEC = 16 bytes / element size).
+struct KrPlan {
+    int v, fn, kw, pf;             // variant and its shape
+    int ksteps, nkc, jc, njr;      // fragment steps, k-chunks, j per block, j-ranges
+    int gx, gy, nsplit, blocks;
+    size_t lds;
+};
+int kr_variants();
+int kr_tiled_k(int dt, int N);
+size_t kr_tiled_bytes(int dt, int N, int eb);
+void launch_kr_tile(int dt, int eb, const void* src, void* dst, int N, int Np, hipStream_t s);
+KrPlan kr_plan(int dt, int M, int J, int Kt, int Bpad, int variant, size_t lds_max);
+void launch_kr_dense(int dt, const KrPlan& pl, const void* Ct, const void* Ct_lo, int N, int Np, int Bpad,
+                     const void* X, const void* Xlo, const void* S, void* part, hipStream_t s);
+// Allow every variant up to `lds` bytes of dynamic LDS.
+hipError_t kr_set_lds_limit(size_t lds);
+
+// The batched dense contraction of a context: variants [0, kr_variants()) select the
+// register kernel, the following mfma_variants() the LDS-tile kernel; -1 = default.
+struct DensePlan {
+    int engine;                    // 0 = k_kr, 1 = k_mfma_rows
+    KrPlan k;
+    MfmaPlan m;
+    int nsplit;
+};
+int dense_batched_variants();
+DensePlan dense_batched_plan(int dt, int N, int Np, int Bpad, int variant, size_t lds_max);
+void launch_dense_batched(int dt, const DensePlan& pl, const void* C, const void* Clo, const void* Ct,
+                          const void* Ct_lo, int N, int Np, int Bpad, const void* X, const void* Xlo, const void* S,
+                          void* part, hipStream_t s);
+
 // W[b][r] = lam_r s_r t_r from projection partials P [nz][Bpad][2Rp].
 void launch_hadamard(int dt, const void* P, int nz, int Bpad, int B, int Rp, const void* lam, void* W,
                      hipStream_t s);

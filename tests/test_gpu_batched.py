@@ -57,6 +57,53 @@ def test_dense_batched_nonlinear(torch_gpu, dt, N, B):
 
 
 @pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("N,B", [(130, 40), (203, 17)])
+def test_dense_batched_every_variant(torch_gpu, dt, N, B):
+    """Every tile variant of the batched dense contraction (register kernel and LDS-tile
+    kernel) against the oracle: ragged rows, k-chunks, j-ranges and column tiles."""
+    C = romsynth.dense_rough(N, seed=N + 3, cfg=23)
+    U = romsynth.initial_u(N, range(B), cfg=23)
+    rom = rg.Rom(N, 1e-3, 1e-3, romsynth.stiffness_diag(N), C=C, dtype=dt, max_batch=B)
+    Cr, Ur = _round(dt, [C, U])
+    refs = [orc.nonlinear_dense(Cr, Ur[b]) for b in range(B)]
+    bounds = [eval_bound_dense(dt, C, U[b]) for b in range(B)]
+    for v in range(rg.rom_tile_count(1)):
+        _say(f"dense batched variant {v} N={N} B={B} {dt}")
+        rg.rom_set_tile(rom.handle, 1, v)
+        Y = _gpu_nonlinear(torch_gpu, rom, U)
+        for b in range(B):
+            check_eval(dt, Y[b], refs[b], bounds[b])
+
+
+@pytest.mark.parametrize("dense", [True, False])
+def test_nonlinear_after_workspace_layout_changes(torch_gpu, dense):
+    """rom_nonlinear with batch sizes that move the workspace regions between calls:
+    the operand copies are rebuilt with their zero padding every time, so stale
+    workspace bytes (which read as BF16 can be NaN) never reach the products."""
+    N, dt = 70, "bf16"
+    U = romsynth.initial_u(N, range(48), cfg=24)
+    if dense:
+        C = romsynth.dense_rough(N, seed=5, cfg=24)
+        rom = rg.Rom(N, 1e-3, 1e-3, romsynth.stiffness_diag(N), C=C, dtype=dt, max_batch=48)
+        Cr, Ur = _round(dt, [C, U])
+        refs = [orc.nonlinear_dense(Cr, Ur[b]) for b in range(48)]
+        bounds = [eval_bound_dense(dt, C, U[b]) for b in range(48)]
+    else:
+        lam, Af, Bf, Cf = romsynth.skew_cp_factors(N, 30, seed=5, cfg=24)
+        rom = rg.Rom(N, 1e-3, 1e-3, romsynth.stiffness_diag(N), lam=lam, Af=Af, Bf=Bf, Cf=Cf, dtype=dt,
+                     max_batch=48)
+        lr, Ar, Br, Crr, Ur = _round(dt, [lam, Af, Bf, Cf, U])
+        refs = [orc.nonlinear_cp(lr, Ar, Br, Crr, Ur[b]) for b in range(48)]
+        bounds = [eval_bound_cp(dt, lam, Af, Bf, Cf, U[b]) for b in range(48)]
+    for B in (40, 17, 48, 2, 33, 40):
+        _say(f"nonlinear after layout change dense={dense} B={B}")
+        Y = _gpu_nonlinear(torch_gpu, rom, U[:B])
+        assert np.all(np.isfinite(Y))
+        for b in range(B):
+            check_eval(dt, Y[b], refs[b], bounds[b])
+
+
+@pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("N,pairs,B", [(37, 25, 3), (100, 50, 20), (96, 160, 40)])
 def test_cp_batched_nonlinear(torch_gpu, dt, N, pairs, B):
     _say(f"cp batched nonlinear N={N} R={2 * pairs} B={B} {dt}")
