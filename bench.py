@@ -72,7 +72,7 @@ CSRC = os.path.join(ROOT, "paper_2311_03694_amd", "csrc")
 # while their combined hash is unchanged)
 KERNEL_SOURCES = {
     "dense_gemv": ["k_dense1.hip", "kdot.h", "kcommon.h", "rom_dev.h"],
-    "mfma_rows": ["k_mfma.hip", "kcommon.h", "rom_dev.h"],
+    "kr": ["k_kr.hip", "kmfma.h", "kcommon.h", "rom_dev.h"],
 }
 
 
@@ -279,12 +279,12 @@ def main():
         s.close()
         rom.close()
         result["config2"] = c2
-        result["roofline_mfma"] = {"bound": "mfma", "kernel": "k_mfma_rows (dense Khatri-Rao, N=400, B=256, BF16)",
+        result["roofline_mfma"] = {"bound": "mfma", "kernel": "k_kr (dense Khatri-Rao, X in registers, N=400, B=256, BF16)",
                                    "achieved": c2["dense_bf16"]["tflops"], "peak": MFMA_PEAK_TFLOPS["bf16"],
                                    "unit": "TFLOP/s", "frac": c2["dense_bf16"]["mfma_frac"],
                                    "avg_launch_us": c2["dense_bf16"]["contraction_us"],
                                    "algorithmic_flops": 2.0 * 400 ** 3 * 256,
-                                   "traffic": _traffic("mfma_dense_n400_b256_bf16", "mfma_rows")}
+                                   "traffic": _traffic("kr_dense_n400_b256_bf16", "kr")}
 
     if not args.no_extra and sec in ("all", "serving"):
         # ---------------- serving: bounded Poisson stream

@@ -53,8 +53,8 @@ __device__ __forceinline__ void bdf_partials_body(const StepArgs& a, const ACC* 
     if (DIAG) {
         const double s = block_sum(e, red);
         if (threadIdx.x == 0) a.epart[(size_t)b * nbx + bx] = s;
-        finalize_step(a, n, nbx, (unsigned)nblk_total);
     }
+    (void)nblk_total;
 }
 
 template <class ACC, bool DIAG>
@@ -125,7 +125,7 @@ __device__ __forceinline__ void helm_gemv_body(const StepArgs& a, int blk, int n
     }
     const double es = block_sum(e, red);
     if (threadIdx.x == 0) a.epart[blk] = es;
-    finalize_step(a, n, nblk, (unsigned)nblk);
+    (void)nblk;
 }
 
 template <bool EVEN>
@@ -168,7 +168,45 @@ __global__ __launch_bounds__(256) void k_helm_finish(StepArgs a, const double* _
     }
     const double s = block_sum(e, red);
     if (threadIdx.x == 0) a.epart[(size_t)b * gridDim.x + blockIdx.x] = s;
-    finalize_step(a, n, gridDim.x, gridDim.x * gridDim.y);
+}
+
+// Closes step n -> n+1 of a state after its update kernel: sums the per-block energy
+// partials epart[b][0..nblk) in a fixed order (deterministic), logs E^{n+1}, records the
+// first non-finite level and advances the step counter.  One 256-thread block per
+// state.  The kernel boundary before it makes the update kernel's partials visible, so
+// no block of the update kernel needs a device-wide fence (on gfx950 a fence at device
+// scope writes back and invalidates its XCD's whole L2).
+__device__ __forceinline__ void finalize_body(const StepArgs& a, int nblk) {
+    __shared__ double fred[4];
+    const long long n = *a.step;
+    if (a.B == 1) {
+        double s = 0.0;
+        for (int q = threadIdx.x; q < nblk; q += blockDim.x) s += a.epart[q];
+        s = block_sum(s, fred);
+        if (threadIdx.x == 0) {
+            const double e = 0.5 * s;
+            if (n + 1 < a.elog_cap) a.elog[n + 1] = e;
+            if (!isfinite(e)) atomicMin(a.bad, n + 1);
+        }
+    } else {
+        for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+            const double* ep = a.epart + (size_t)b * nblk;
+            double s = 0.0;
+#pragma unroll 8
+            for (int q = 0; q < nblk; ++q) s += ep[q];
+            const double e = 0.5 * s;
+            if (n + 1 < a.elog_cap) a.elog[(size_t)(n + 1) * a.B + b] = e;
+            if (!isfinite(e)) atomicMin(a.bad, n + 1);
+        }
+    }
+    __syncthreads();                      // every thread has read the step counter
+    if (threadIdx.x == 0) *a.step = n + 1;
+}
+
+__global__ __launch_bounds__(256) void k_finalize(StepArgs a, int nblk) { finalize_body(a, nblk); }
+
+__global__ __launch_bounds__(256) void k_finalize_group(const FinJob* __restrict__ jobs) {
+    finalize_body(jobs[blockIdx.x].a, jobs[blockIdx.x].nblk);
 }
 
 // Batched coefficient copies of u [B][N] (state creation / restart, batched
@@ -213,6 +251,15 @@ void launch_bdf_from_partials(const StepArgs& a, int acc_f64, const void* part, 
         if (diag) hipLaunchKernelGGL((k_bdf_partials<float, true>), grid, dim3(256), 0, s, a, (const float*)part, nchunk, pb);
         else hipLaunchKernelGGL((k_bdf_partials<float, false>), grid, dim3(256), 0, s, a, (const float*)part, nchunk, pb);
     }
+    if (diag) launch_finalize(a, (a.N + 255) / 256, s);
+}
+
+void launch_finalize(const StepArgs& a, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a, nblk);
+}
+
+void launch_finalize_group(const FinJob* jobs_dev, int njobs, hipStream_t s) {
+    if (njobs > 0) hipLaunchKernelGGL(k_finalize_group, dim3((unsigned)njobs), dim3(256), 0, s, jobs_dev);
 }
 
 void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s) {
@@ -233,10 +280,12 @@ void launch_helm_apply(const StepArgs& a, hipStream_t s) {
     const size_t lds = sizeof(double) * a.N;
     if (a.N % 2 == 0) hipLaunchKernelGGL(k_helm_gemv<true>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
     else hipLaunchKernelGGL(k_helm_gemv<false>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
+    launch_finalize(a, (a.N + 3) / 4, s);
 }
 
 void launch_helm_finish(const StepArgs& a, const double* part, int nsplit, hipStream_t s) {
     hipLaunchKernelGGL(k_helm_finish, dim3((a.N + 255) / 256, a.B), dim3(256), 0, s, a, part, nsplit);
+    launch_finalize(a, (a.N + 255) / 256, s);
 }
 
 void launch_prep_ucv(const StepArgs& a, const double* u_src, hipStream_t s) {

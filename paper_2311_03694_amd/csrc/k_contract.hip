@@ -158,7 +158,6 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
         if constexpr (MODE == 1) {
             const double s = block_sum(e, red);
             if (threadIdx.x == 0) a.epart[blk] = s;
-            finalize_step(a, n, nblk, (unsigned)nblk);
         }
     }
 }
@@ -257,6 +256,7 @@ int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, const void* la
     if (sa) jb.a = *sa;
     jb.nblk = (N + 3) / 4;
     scat1_dispatch(dt, mode, jb, y_out, nullptr, 0, 0, Rp, s);
+    if (mode == 1) launch_finalize(jb.a, jb.nblk, s);
     return 0;
 }
 

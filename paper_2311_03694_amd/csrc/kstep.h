@@ -63,51 +63,4 @@ __device__ __forceinline__ void write_level(const StepArgs& a, long long n1, int
     if (a.batched) write_ucv(a, b, i, u);
 }
 
-// Last-arriving block of a grid of `nblk_total` blocks: sums the per-block energy
-// partials epart[b][0..nblk) in a fixed order (deterministic), logs E^{n+1}, records the
-// first non-finite level and advances the step counter.  Returns true in the block
-// that finalized.  Must be called by every thread of every block (blockDim.x <= 1024,
-// a multiple of 64).  One trajectory: the whole block reduces (strided partial sums,
-// then the wavefront/LDS tree); a batch: one thread per trajectory, loads unrolled.
-__device__ __forceinline__ bool finalize_step(const StepArgs& a, long long n, int nblk, unsigned nblk_total) {
-    __shared__ int am_last;
-    __shared__ double fred[16];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(a.ticket, 1u);
-        am_last = (prev == nblk_total - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!am_last) return false;
-    __threadfence();
-    if (a.B == 1) {
-        double s = 0.0;
-        for (int q = threadIdx.x; q < nblk; q += blockDim.x) s += a.epart[q];
-        s = block_sum(s, fred);
-        if (threadIdx.x == 0) {
-            const double e = 0.5 * s;
-            if (n + 1 < a.elog_cap) a.elog[n + 1] = e;
-            if (!isfinite(e)) atomicMin(a.bad, n + 1);
-        }
-    } else {
-        for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
-            const double* ep = a.epart + (size_t)b * nblk;
-            double s = 0.0;
-#pragma unroll 8
-            for (int q = 0; q < nblk; ++q) s += ep[q];
-            const double e = 0.5 * s;
-            if (n + 1 < a.elog_cap) a.elog[(size_t)(n + 1) * a.B + b] = e;
-            if (!isfinite(e)) atomicMin(a.bad, n + 1);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        *a.step = n + 1;
-        *a.ticket = 0u;
-        __threadfence();
-    }
-    return true;
-}
-
 }  // namespace rom

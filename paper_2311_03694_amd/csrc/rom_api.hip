@@ -627,7 +627,6 @@ rom_status reset_counters(rom_state s, long long step) {
     const long long big = LLONG_MAX;
     HIPCHK(hipMemcpyAsync(s->a.step, &step, sizeof(long long), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(s->a.bad, &big, sizeof(long long), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemsetAsync(s->a.ticket, 0, sizeof(unsigned), c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return ROM_OK;
 }
@@ -680,7 +679,6 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(dmalloc((void**)&a.epart, sizeof(double) * B * ((N + 3) / 4 + 64), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.step, sizeof(long long), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
-    TRY(dmalloc((void**)&a.ticket, sizeof(unsigned), &s->bytes, &s->allocs));
     if (a.batched) {
         const size_t cells = (size_t)s->Bpad * c->Np;
         TRY(dmalloc(&a.ucv, cells * elem_bytes(c->dtype), &s->bytes, &s->allocs));
@@ -887,11 +885,12 @@ struct Group {
     std::vector<Scat1Job> scat;
     std::vector<BdfJob> bdf;
     std::vector<HelmJob> helm;
+    std::vector<FinJob> fin;               // phase 4: one step-close block per state
     int b1 = 0, b2 = 0, b3 = 0;            // blocks of phase 1, 2, 3
     int Npmax = 8, Rpmax = 8, Nmax = 1;
     GemvTile tile{};
     char* dev = nullptr;                   // device copies of the job tables
-    size_t off1 = 0, off2 = 0, off3 = 0;
+    size_t off1 = 0, off2 = 0, off3 = 0, off4 = 0;
 };
 
 template <class J>
@@ -917,8 +916,10 @@ void enqueue_group(const Group& g, hipStream_t stream, int phase) {
         else
             launch_cp_scatter1_group(g.dtype, g.diag ? 1 : 2, (const Scat1Job*)(g.dev + g.off2),
                                      (int)g.scat.size(), g.b2, g.Rpmax, stream);
-    } else if (!g.diag) {
-        launch_helm_group((const HelmJob*)(g.dev + g.off3), (int)g.helm.size(), g.b3, g.Nmax, stream);
+    } else if (phase == 3) {
+        if (!g.diag) launch_helm_group((const HelmJob*)(g.dev + g.off3), (int)g.helm.size(), g.b3, g.Nmax, stream);
+    } else {
+        launch_finalize_group((const FinJob*)(g.dev + g.off4), (int)g.fin.size(), stream);
     }
 }
 
@@ -1019,6 +1020,12 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
             g->b3 += hj.nblk;
             g->helm.push_back(hj);
         }
+        // the update kernel (phase 2 with a diagonal stiffness, else phase 3) leaves
+        // per-block energy partials; phase 4 closes the step
+        FinJob fj{};
+        fj.a = st->a;
+        fj.nblk = (diag && dense) ? (c->N + 255) / 256 : (c->N + 3) / 4;
+        g->fin.push_back(fj);
         if (c->Np > g->Npmax) g->Npmax = c->Np;
         if (c->N > g->Nmax) g->Nmax = c->N;
     }
@@ -1027,6 +1034,7 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
         g.off1 = g.dense ? put(blob, g.gemv) : put(blob, g.proj);
         g.off2 = g.dense ? put(blob, g.bdf) : put(blob, g.scat);
         g.off3 = put(blob, g.helm);
+        g.off4 = put(blob, g.fin);
     }
     char* dev = nullptr;
     if (!blob.empty()) {
@@ -1040,7 +1048,7 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
     for (auto& g : groups) g.dev = dev;
 
     auto enqueue_all = [&]() -> rom_status {
-        for (int phase = 1; phase <= 3; ++phase)
+        for (int phase = 1; phase <= 4; ++phase)
             for (const auto& g : groups) enqueue_group(g, stream, phase);
         for (int q : batched) {
             rom_status st = enqueue_step(ctxs[q], states[q], stream);

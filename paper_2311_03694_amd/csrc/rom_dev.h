@@ -33,7 +33,6 @@ struct StepArgs {
     long long elog_cap;
     double* rhs;             // [Bpad][Np] right-hand sides (dense stiffness; padding zero)
     double* epart;           // [B][nblk] energy partial sums
-    unsigned* ticket;        // arrival counter of the last-block reduction (0 at rest)
     const double* hdiag;     // [3][N] 1/(beta0_k/dt + nu A_ii) (diagonal stiffness)
     const double* hinv;      // [3][N][Np] (beta0_k/dt I + nu A)^-1, row pitch Np (dense stiffness)
     // coefficient copies in the contraction's number format for the batched kernels,
@@ -93,6 +92,10 @@ struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory
     StepArgs a;
     int blk0, nblk;
 };
+struct FinJob {            // step close (energy, health flag, counter), one state
+    StepArgs a;
+    int nblk;              // energy partials per trajectory written by the update
+};
 
 // ---------------------------------------------------------------- launchers (k_*.hip)
 
@@ -124,6 +127,10 @@ void launch_cp_scatter1_group(int dt, int mode, const Scat1Job* jobs_dev, int nj
                               hipStream_t s);
 void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s);
 void launch_helm_group(const HelmJob* jobs_dev, int njobs, int blocks, int Nmax, hipStream_t s);
+// Step close after an update kernel: energies of level n+1 from the per-block partials,
+// health flag, step counter (one block per state).
+void launch_finalize(const StepArgs& a, int nblk, hipStream_t s);
+void launch_finalize_group(const FinJob* jobs_dev, int njobs, hipStream_t s);
 
 // Batched MFMA contraction (dense Khatri-Rao form, CP projections and CP scatter).
 struct MfmaTile { int mw, bt, target; };

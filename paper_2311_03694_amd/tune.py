@@ -2,7 +2,7 @@
 
 For a context and a batch size it times every launch variant of the kernels that
 batch uses (rom_set_tile / rom_tile_count: 0 = single-trajectory dense stream,
-1 = batched dense MFMA, 2 = CP projections, 3 = CP scatter), keeps the fastest, and
+1 = batched dense contraction, 2 = CP projections, 3 = CP scatter), keeps the fastest, and
 caches the choice in a JSON table keyed by (kernel, N, R, B, dtype) so later contexts
 of the same shape start from it (apply()).  Timing is whole BDF steps on a scratch
 state, synchronized on the device, best of `reps`.
@@ -21,7 +21,7 @@ from . import binding as rb
 DEFAULT_CACHE = os.environ.get("ROM_TILE_CACHE",
                                os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles.json"))
 
-KIND_NAMES = {0: "dense1", 1: "dense_mfma", 2: "cp_proj_mfma", 3: "cp_scatter_mfma"}
+KIND_NAMES = {0: "dense1", 1: "dense_batched", 2: "cp_proj_mfma", 3: "cp_scatter_mfma"}
 
 
 def kinds_for(dense: bool, batch: int):
