@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librom.so")
-SOURCES = ["k_bdf.hip", "k_contract.hip", "k_dense1.hip", "k_kr.hip", "k_mfma.hip", "rom_api.hip"]
+SOURCES = ["k_bdf.hip", "k_contract.hip", "k_dense1.hip", "k_gemm.hip", "k_kr.hip", "k_mfma.hip", "rom_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -24,9 +24,10 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-# Per-source flags.  k_kr.hip keeps its MFMA accumulators in VGPRs (its per-j VALU fold
-# reads them every iteration; accumulators in AGPRs would need a copy each time).
-EXTRA = {"k_kr.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-source flags.  k_kr.hip and k_gemm.hip keep their MFMA accumulators in VGPRs (k_kr's
+# per-j VALU fold reads them every iteration; accumulators in AGPRs would need a copy
+# each time, and the ring registers k_gemm needs fit beside them).
+EXTRA = {"k_kr.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "k_gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:

@@ -1,0 +1,254 @@
+// k_gemm.hip -- skinny products of the batched path on the matrix cores:
+//   Y[b][m] = sum_k A[m][k] X[b][k]     (M rows, K contracted, Bpad <= a few hundred columns)
+// used for the CP projections [Bf|Cf]^T u and the CP scatter Af W (Sec. 3.1, eq. tc_ap)
+// and for the batched Helmholtz apply Hinv_k rhs (eq. nse_d1, dense stiffness).
+//
+// Block = 4 wavefronts over one 16-row tile of A and 16*FN columns, over the whole of K:
+// wavefront w takes the w-th quarter of the K steps (one step = one 16-byte lane vector
+// per lane: 32 k in BF16, 16 in FP32, 8 in FP64) and streams its A and X fragments
+// through a PF-deep register ring; the 4 partial tiles are added in LDS in a fixed
+// order and written straight to Y (no partial buffers, no second pass).  With one block
+// per output tile the grid is ceil(M/16) x (column tiles), which fills the device for
+// the shapes of this path; A is read once per column tile (column tiles of one row tile
+// run next to each other on one XCD and share its L2).
+#include "kmfma.h"
+
+namespace rom {
+
+struct GemmArgs {
+    const void* A;                 // [M][lda] rows in the operator's storage format
+    const unsigned short* Alo;     // BF16X3 low words of A
+    const void* X;                 // [Bpad][ldx] in the MFMA operand format
+    const unsigned short* Xlo;     // BF16X3 low words of X
+    void* Y;                       // [Bpad][M] (accumulation type)
+    int M, K, Bpad;
+    long long lda, ldx;
+    int gx, gy;                    // row tiles, column tiles
+    const long long* kstep;        // non-null: A += (BDF order at *kstep - 1) * a_kstride
+    long long a_kstride;
+};
+
+template <int ADT, int MKD, int FN, int PF>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
+    typedef MfmaT<MKD> Tr;
+    typedef typename Tr::X XT;
+    typedef typename Tr::Acc Acc;
+    typedef typename Tr::Acc4 Acc4;
+    constexpr int KS = Tr::KS, VEC = Tr::VEC;
+    constexpr bool X3 = (MKD == MK_BF16X3);
+    // a FP32 product over BF16 words (the CP scatter of the BF16 formats) reads 4 words
+    // per lane vector and converts them when the slot is consumed, not when it is
+    // loaded (a conversion at load time would wait for the load right away)
+    constexpr bool CVT = (MKD == MK_F32 && ADT != DT_F32);
+    constexpr int AV = CVT ? 4 : (int)(16 / sizeof(typename Store<ADT>::T));
+    static_assert(AV == VEC, "lane vectors of A and X must cover the same k");
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    Acc* red = reinterpret_cast<Acc*>(smem);             // [4][FN][4][64]
+
+    const int nwork = p.gx * p.gy;
+    const int per = (nwork + 7) / 8;
+    const int wi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (wi >= nwork) return;
+    const int by = wi % p.gy, bx = wi / p.gy;
+
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int rowbase = bx * 16, b0 = by * 16 * FN;
+    const int ksteps = (p.K + KS - 1) / KS;
+    const int wsb = ksteps / 4, wse = ksteps - wsb * 4;
+    const int ns = wsb + (w < wse ? 1 : 0);
+    const int s0 = w * wsb + (w < wse ? w : wse);
+
+    // the lane's row (rows past M are clamped for loads and never stored) and columns
+    int r = rowbase + c16;
+    r = r < p.M ? r : p.M - 1;
+    const size_t kbase = p.kstep ? (size_t)(bdf_order(*p.kstep) - 1) * p.a_kstride : 0;
+    const size_t arow = kbase + (size_t)r * p.lda;
+    size_t xrow[FN];
+#pragma unroll
+    for (int t = 0; t < FN; ++t) {
+        int b = b0 + t * 16 + c16;
+        b = b < p.Bpad ? b : p.Bpad - 1;
+        xrow[t] = (size_t)b * p.ldx;
+    }
+
+    Acc4 Z[FN];
+#pragma unroll
+    for (int t = 0; t < FN; ++t) Z[t] = Acc4{0, 0, 0, 0};
+
+    if (ns > 0) {                                        // wavefront-uniform
+        // Ring of PF steps.  Loads are unconditional: addresses past K are clamped to
+        // the last lane vector of the row and their X fragments selected to zero when
+        // consumed, so the loop has no branches and waits only for the slot it uses.
+        u32x4 ah[PF], al[PF], xh[PF][FN], xl[PF][FN];
+        int kq[PF];
+        int sp = 0;                                      // producer step
+        auto issue = [&](int d) {
+            const int st = s0 + (sp < ns ? sp : ns - 1);
+            int k = st * KS + g * VEC;
+            kq[d] = k;
+            k = k < p.K ? k : p.K - VEC;
+            if constexpr (CVT) {
+                const u32x2 h = ld_plain<8>(reinterpret_cast<const unsigned short*>(p.A) + arow + k);
+                u32x2 l = u32x2{0u, 0u};
+                if constexpr (ADT == DT_BF16X3) l = ld_plain<8>(p.Alo + arow + k);
+                ah[d] = u32x4{h[0], h[1], l[0], l[1]};
+            } else {
+                load_a<ADT, MKD, false>(p.A, p.Alo, arow + k, ah[d], al[d]);
+            }
+#pragma unroll
+            for (int t = 0; t < FN; ++t) {
+                xh[d][t] = ld_plain<16>(reinterpret_cast<const XT*>(p.X) + xrow[t] + k);
+                if constexpr (X3) xl[d][t] = ld_plain<16>(p.Xlo + xrow[t] + k);
+                else xl[d][t] = u32x4{0u, 0u, 0u, 0u};
+            }
+            ++sp;
+        };
+#pragma unroll
+        for (int d = 0; d < PF; ++d) {
+            issue(d);
+            __builtin_amdgcn_sched_barrier(0);           // slot order: slot 0 lands first
+        }
+        const int ns_pad = (ns + PF - 1) / PF * PF;
+        for (int q0 = 0; q0 < ns_pad; q0 += PF) {
+#pragma unroll
+            for (int d = 0; d < PF; ++d) {
+                const bool live = (q0 + d < ns) && (kq[d] < p.K);
+                const u32x4 z = u32x4{0u, 0u, 0u, 0u};
+                u32x4 av = ah[d];
+                if constexpr (CVT) {
+                    // 4 BF16 words (plus their low words) -> 4 FP32 values, hi + lo exact
+                    float f[4] = {bf16_lo_f(av[0]), bf16_hi_f(av[0]), bf16_lo_f(av[1]), bf16_hi_f(av[1])};
+                    if constexpr (ADT == DT_BF16X3) {
+                        f[0] += bf16_lo_f(av[2]);
+                        f[1] += bf16_hi_f(av[2]);
+                        f[2] += bf16_lo_f(av[3]);
+                        f[3] += bf16_hi_f(av[3]);
+                    }
+                    av = u32x4{__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]), __float_as_uint(f[3])};
+                }
+#pragma unroll
+                for (int t = 0; t < FN; ++t) {
+                    const u32x4 xv = live ? xh[d][t] : z;
+                    const u32x4 xlv = live ? xl[d][t] : z;
+                    mfma_step<MKD>(Z[t], av, al[d], xv, xlv);
+                }
+                issue(d);
+                // nothing crosses: later slots' arithmetic hoisted above these loads
+                // would push the loads to the end of the body and defeat the ring
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    // ---- add the 4 wavefront tiles (fixed order) and write Y
+#pragma unroll
+    for (int t = 0; t < FN; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((w * FN + t) * 4 + v) * 64 + lane] = Z[t][v];
+    __syncthreads();
+    Acc* out = reinterpret_cast<Acc*>(p.Y);
+    for (int e = threadIdx.x; e < 256 * FN; e += 256) {
+        const int cl = e >> 4, rr = e & 15;              // local column, local row
+        const int t = cl >> 4, cc = cl & 15;
+        const int gg = MKD == MK_F64 ? (rr & 3) : (rr >> 2);
+        const int v = MKD == MK_F64 ? (rr >> 2) : (rr & 3);
+        const int ln = gg * 16 + cc;
+        Acc sum = red[(t * 4 + v) * 64 + ln];
+#pragma unroll
+        for (int w2 = 1; w2 < 4; ++w2) sum += red[((w2 * FN + t) * 4 + v) * 64 + ln];
+        const int row = rowbase + rr, b = b0 + cl;
+        if (row < p.M && b < p.Bpad) out[(size_t)b * p.M + row] = sum;
+    }
+}
+
+// ---------------------------------------------------------------- planning, launch
+
+// Variant 0 picks the column-tile width from the shape; 1, 2, 3 force FN = 1, 2, 4.
+constexpr int kGemmVariants = 4;
+int gemm_variants() { return kGemmVariants; }
+
+static int gemm_fn(int M, int Bpad, int v) {
+    const int nct = Bpad / 16;
+    if (v == 1) return 1;
+    if (v == 2) return nct % 2 == 0 ? 2 : 1;
+    if (v == 3) return nct % 4 == 0 ? 4 : (nct % 2 == 0 ? 2 : 1);
+    // widest tile that still gives about one block per CU
+    const int gx = (M + 15) / 16;
+    for (int fn : {4, 2})
+        if (nct % fn == 0 && (long long)gx * (nct / fn) >= 224) return fn;
+    return 1;
+}
+
+GemmPlan gemm_plan(int M, int Bpad, int variant) {
+    GemmPlan pl{};
+    pl.fn = gemm_fn(M, Bpad, variant < 0 ? 0 : variant);
+    pl.gx = (M + 15) / 16;
+    pl.gy = Bpad / (16 * pl.fn);
+    pl.blocks = (pl.gx * pl.gy + 7) / 8 * 8;
+    return pl;
+}
+
+template <int ADT, int MKD>
+static void gemm_go(const GemmArgs& a, const GemmPlan& pl, hipStream_t s) {
+    const size_t lds = (size_t)1024 * pl.fn * sizeof(typename MfmaT<MKD>::Acc);
+    if (pl.fn == 4) hipLaunchKernelGGL((k_gemm<ADT, MKD, 4, 4>), dim3(pl.blocks), dim3(256), lds, s, a);
+    else if (pl.fn == 2) hipLaunchKernelGGL((k_gemm<ADT, MKD, 2, 6>), dim3(pl.blocks), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_gemm<ADT, MKD, 1, 8>), dim3(pl.blocks), dim3(256), lds, s, a);
+}
+
+static GemmArgs gemm_args(const GemmPlan& pl, const void* A, const void* Alo, long long lda, const void* X,
+                          const void* Xlo, long long ldx, void* Y, int M, int K, int Bpad) {
+    GemmArgs a{};
+    a.A = A;
+    a.Alo = (const unsigned short*)Alo;
+    a.X = X;
+    a.Xlo = (const unsigned short*)Xlo;
+    a.Y = Y;
+    a.M = M;
+    a.K = K;
+    a.Bpad = Bpad;
+    a.lda = lda;
+    a.ldx = ldx;
+    a.gx = pl.gx;
+    a.gy = pl.gy;
+    return a;
+}
+
+// CP projections: P[b][r] over the rows of [Bf|Cf]^T [2Rp][Np] (partials layout with one
+// split, in the accumulation type).
+void launch_gemm_proj(int dt, const GemmPlan& pl, const void* BCt, const void* BCt_lo, int Np, int Rp, int Bpad,
+                      const void* X, const void* Xlo, void* P, hipStream_t s) {
+    const GemmArgs a = gemm_args(pl, BCt, BCt_lo, Np, X, Xlo, Np, P, 2 * Rp, Np, Bpad);
+    switch (dt) {
+        case DT_F64: gemm_go<DT_F64, MK_F64>(a, pl, s); break;
+        case DT_F32: gemm_go<DT_F32, MK_F32>(a, pl, s); break;
+        case DT_BF16: gemm_go<DT_BF16, MK_BF16>(a, pl, s); break;
+        default: gemm_go<DT_BF16X3, MK_BF16X3>(a, pl, s); break;
+    }
+}
+
+// CP scatter: Y[b][i] = sum_r Af[i][r] W[b][r], W in FP32 (FP64 for DT_F64); the BF16
+// formats contract their factor words with FP32 MFMA.
+void launch_gemm_scatter(int dt, const GemmPlan& pl, const void* Af, const void* Af_lo, int N, int Rp, int Bpad,
+                         const void* W, void* Y, hipStream_t s) {
+    const GemmArgs a = gemm_args(pl, Af, Af_lo, Rp, W, nullptr, Rp, Y, N, Rp, Bpad);
+    switch (dt) {
+        case DT_F64: gemm_go<DT_F64, MK_F64>(a, pl, s); break;
+        case DT_F32: gemm_go<DT_F32, MK_F32>(a, pl, s); break;
+        case DT_BF16: gemm_go<DT_BF16, MK_F32>(a, pl, s); break;
+        default: gemm_go<DT_BF16X3, MK_F32>(a, pl, s); break;
+    }
+}
+
+// Batched Helmholtz apply: U[b][i] = sum_m Hinv_k[i][m] rhs[b][m] (FP64), k from the
+// device step counter; Hinv [3][N][Np], rhs [Bpad][Np].
+void launch_gemm_helm(const GemmPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
+                      const long long* stepp, double* Y, hipStream_t s) {
+    GemmArgs a = gemm_args(pl, hinv, nullptr, Np, rhs, nullptr, Np, Y, N, Np, Bpad);
+    a.kstep = stepp;
+    a.a_kstride = (long long)N * Np;
+    gemm_go<DT_F64, MK_F64>(a, pl, s);
+}
+
+}  // namespace rom

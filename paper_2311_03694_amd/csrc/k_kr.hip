@@ -141,7 +141,10 @@ __global__ __launch_bounds__(256) void k_kr(KrArgs p) {
     // Prologue: the ring's first loads (from HBM) go out first, then the X fragments
     // and the j-weights, so their round trips overlap instead of adding up.
 #pragma unroll
-    for (int d = 0; d < PF; ++d) issue(d);
+    for (int d = 0; d < PF; ++d) {
+        issue(d);
+        __builtin_amdgcn_sched_barrier(0);               // slot order: slot 0 lands first
+    }
     // ---- X fragments of the chunk for the lane's trajectories, zero past Kp, Bpad or
     // the chunk's last step.  The loads are unconditional (clamped addresses; the zero
     // selection waits until after the barrier): a load skipped on some lanes or paths

@@ -121,7 +121,34 @@ static size_t acc_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
 namespace {
 
 GemvTile gemv_tile(rom_ctx c) { return dense_gemv_variant(c->tile[0] < 0 ? 0 : c->tile[0]); }
-MfmaTile mfma_tile(rom_ctx c, int kind) { return mfma_variant(c->tile[kind] < 0 ? 0 : c->tile[kind]); }
+// kinds 2 (CP projections) and 3 (CP scatter): k_gemm variants first, then the LDS-tile
+// kernel's
+SkinnyPlan skinny_plan(rom_ctx c, int kind, int Bpad) {
+    SkinnyPlan sp{};
+    const int v = c->tile[kind];
+    const int M = kind == 2 ? 2 * c->Rp : c->N;
+    if (v >= gemm_variants()) {
+        sp.engine = 1;
+        const MfmaTile t = mfma_variant(v - gemm_variants());
+        sp.m = kind == 2 ? mfma_proj_plan(c->dtype, c->Np, c->Rp, Bpad, t) : mfma_scatter_plan(c->dtype, c->N, c->Rp, Bpad, t);
+        sp.nsplit = sp.m.nsplit;
+    } else {
+        sp.engine = 0;
+        sp.g = gemm_plan(M, Bpad, v);
+        sp.nsplit = 1;
+    }
+    return sp;
+}
+
+void launch_proj(rom_ctx c, const SkinnyPlan& sp, int Bpad, const void* X, const void* Xlo, void* P, hipStream_t s) {
+    if (sp.engine == 1) launch_mfma_proj(c->dtype, sp.m, c->BCt, c->BCt_lo, c->Np, c->Rp, Bpad, X, Xlo, P, s);
+    else launch_gemm_proj(c->dtype, sp.g, c->BCt, c->BCt_lo, c->Np, c->Rp, Bpad, X, Xlo, P, s);
+}
+
+void launch_scatter(rom_ctx c, const SkinnyPlan& sp, int Bpad, const void* W, void* Y, hipStream_t s) {
+    if (sp.engine == 1) launch_mfma_scatter(c->dtype, sp.m, c->Af, c->Af_lo, c->N, c->Rp, Bpad, W, Y, s);
+    else launch_gemm_scatter(c->dtype, sp.g, c->Af, c->Af_lo, c->N, c->Rp, Bpad, W, Y, s);
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -131,12 +158,12 @@ struct WsPlan {
     int B = 1, Bpad = 16;
     int nchunk = 0;                 // B = 1 dense: partial chunks per row
     DensePlan pd{};                 // B > 1: dense contraction
-    MfmaPlan pp{}, ps{};            // B > 1: CP projection, CP scatter
+    SkinnyPlan pp{}, ps{};          // B > 1: CP projection, CP scatter
     size_t part_off = 0;            // dense / scatter partials, or CP s,t (B = 1)
     size_t part2_off = 0;           // CP projection partials (B > 1)
     size_t w_off = 0;               // CP Hadamard products W [Bpad][Rp] (B > 1)
     size_t ucv_off = 0, ucvlo_off = 0, usc_off = 0;   // rom_nonlinear operand copies (B > 1)
-    MfmaPlan ph{};                  // B > 1, dense stiffness: FP64 Helmholtz apply
+    GemmPlan ph{};                  // B > 1, dense stiffness: FP64 Helmholtz apply
     size_t helm_off = 0;
     size_t total = 0;
 };
@@ -163,8 +190,8 @@ WsPlan plan_ws(rom_ctx c, int B) {
             p.part_off = off;
             off = align256(off + (size_t)p.pd.nsplit * p.Bpad * c->N * ab);
         } else {
-            p.pp = mfma_proj_plan(c->dtype, c->Np, c->Rp, p.Bpad, mfma_tile(c, 2));
-            p.ps = mfma_scatter_plan(c->dtype, c->N, c->Rp, p.Bpad, mfma_tile(c, 3));
+            p.pp = skinny_plan(c, 2, p.Bpad);
+            p.ps = skinny_plan(c, 3, p.Bpad);
             p.part2_off = off;
             off = align256(off + (size_t)p.pp.nsplit * p.Bpad * 2 * c->Rp * ab);
             p.w_off = off;
@@ -179,9 +206,9 @@ WsPlan plan_ws(rom_ctx c, int B) {
         p.usc_off = off;
         off = align256(off + (size_t)p.Bpad * c->Np * ab);
         if (!c->diagA) {
-            p.ph = mfma_helm_plan(c->N, c->Np, p.Bpad, mfma_variant(0));
+            p.ph = gemm_plan(c->N, p.Bpad, 0);
             p.helm_off = off;
-            off = align256(off + (size_t)p.ph.nsplit * p.Bpad * c->N * 8);
+            off = align256(off + (size_t)p.Bpad * c->N * 8);
         }
     }
     p.total = off + 256;
@@ -471,12 +498,10 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream) {
                                  a.ucv_lo, a.uj, ws + p.part_off, stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.pd.nsplit, p.Bpad, diag, stream);
         } else {
-            launch_mfma_proj(c->dtype, p.pp, c->BCt, c->BCt_lo, c->Np, c->Rp, p.Bpad, a.ucv, a.ucv_lo,
-                             ws + p.part2_off, stream);
+            launch_proj(c, p.pp, p.Bpad, a.ucv, a.ucv_lo, ws + p.part2_off, stream);
             launch_hadamard(c->dtype, ws + p.part2_off, p.pp.nsplit, p.Bpad, s->B, c->Rp, c->lam, ws + p.w_off,
                             stream);
-            launch_mfma_scatter(c->dtype, p.ps, c->Af, c->Af_lo, c->N, c->Rp, p.Bpad, ws + p.w_off,
-                                ws + p.part_off, stream);
+            launch_scatter(c, p.ps, p.Bpad, ws + p.w_off, ws + p.part_off, stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.ps.nsplit, p.Bpad, diag, stream);
         }
     }
@@ -485,8 +510,8 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream) {
             launch_helm_apply(a, stream);
         } else {
             double* hp = (double*)((char*)c->ws + p.helm_off);
-            launch_mfma_helm(p.ph, c->hinv, c->N, c->Np, p.Bpad, a.rhs, a.step, hp, stream);
-            launch_helm_finish(a, hp, p.ph.nsplit, stream);
+            launch_gemm_helm(p.ph, c->hinv, c->N, c->Np, p.Bpad, a.rhs, a.step, hp, stream);
+            launch_helm_finish(a, hp, 1, stream);
         }
     }
     HIPCHK(hipGetLastError());
@@ -531,12 +556,10 @@ extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_de
                                  a.ucv_lo, a.uj, ws + p.part_off, c->stream);
             launch_sum_partials(accf, ws + p.part_off, p.pd.nsplit, p.Bpad, batch, c->N, y_dev, c->stream);
         } else {
-            launch_mfma_proj(c->dtype, p.pp, c->BCt, c->BCt_lo, c->Np, c->Rp, p.Bpad, a.ucv, a.ucv_lo,
-                             ws + p.part2_off, c->stream);
+            launch_proj(c, p.pp, p.Bpad, a.ucv, a.ucv_lo, ws + p.part2_off, c->stream);
             launch_hadamard(c->dtype, ws + p.part2_off, p.pp.nsplit, p.Bpad, batch, c->Rp, c->lam, ws + p.w_off,
                             c->stream);
-            launch_mfma_scatter(c->dtype, p.ps, c->Af, c->Af_lo, c->N, c->Rp, p.Bpad, ws + p.w_off,
-                                ws + p.part_off, c->stream);
+            launch_scatter(c, p.ps, p.Bpad, ws + p.w_off, ws + p.part_off, c->stream);
             launch_sum_partials(accf, ws + p.part_off, p.ps.nsplit, p.Bpad, batch, c->N, y_dev, c->stream);
         }
     }
@@ -1117,7 +1140,7 @@ extern "C" int32_t rom_tile_count(int32_t kind) {
     switch (kind) {
         case 0: return dense_gemv_variants();
         case 1: return dense_batched_variants();
-        case 2: case 3: return mfma_variants();
+        case 2: case 3: return gemm_variants() + mfma_variants();
         default: return 0;
     }
 }

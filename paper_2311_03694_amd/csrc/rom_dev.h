@@ -227,6 +227,27 @@ void launch_dense_batched(int dt, const DensePlan& pl, const void* C, const void
                           const void* Ct_lo, int N, int Np, int Bpad, const void* X, const void* Xlo, const void* S,
                           void* part, hipStream_t s);
 
+// Skinny products of the batched path (k_gemm.hip): one block per output tile over the
+// whole contracted index; outputs in the partials layout with a single split.
+struct GemmPlan { int fn, gx, gy, blocks; };
+int gemm_variants();
+GemmPlan gemm_plan(int M, int Bpad, int variant);
+void launch_gemm_proj(int dt, const GemmPlan& pl, const void* BCt, const void* BCt_lo, int Np, int Rp, int Bpad,
+                      const void* X, const void* Xlo, void* P, hipStream_t s);
+void launch_gemm_scatter(int dt, const GemmPlan& pl, const void* Af, const void* Af_lo, int N, int Rp, int Bpad,
+                         const void* W, void* Y, hipStream_t s);
+void launch_gemm_helm(const GemmPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
+                      const long long* stepp, double* Y, hipStream_t s);
+
+// A batched CP product of a context: variants [0, gemm_variants()) select k_gemm, the
+// following mfma_variants() the LDS-tile kernel; -1 = default.
+struct SkinnyPlan {
+    int engine;                    // 0 = k_gemm, 1 = k_mfma_rows
+    GemmPlan g;
+    MfmaPlan m;
+    int nsplit;
+};
+
 // W[b][r] = lam_r s_r t_r from projection partials P [nz][Bpad][2Rp].
 void launch_hadamard(int dt, const void* P, int nz, int Bpad, int B, int Rp, const void* lam, void* W,
                      hipStream_t s);

@@ -21,7 +21,7 @@ from . import binding as rb
 DEFAULT_CACHE = os.environ.get("ROM_TILE_CACHE",
                                os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles.json"))
 
-KIND_NAMES = {0: "dense1", 1: "dense_batched", 2: "cp_proj_mfma", 3: "cp_scatter_mfma"}
+KIND_NAMES = {0: "dense1", 1: "dense_batched", 2: "cp_proj", 3: "cp_scatter"}
 
 
 def kinds_for(dense: bool, batch: int):

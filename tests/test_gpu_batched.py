@@ -118,6 +118,28 @@ def test_cp_batched_nonlinear(torch_gpu, dt, N, pairs, B):
         check_eval(dt, Y[b], yr, eval_bound_cp(dt, lam, Af, Bf, Cf, U[b]))
 
 
+@pytest.mark.parametrize("dt", DTS)
+def test_cp_batched_every_variant(torch_gpu, dt):
+    """Every tile variant of the batched CP projections and scatter (skinny-GEMM kernel
+    and LDS-tile kernel) against the oracle, with ragged rows, rank and batch."""
+    N, pairs, B = 130, 75, 40
+    lam, Af, Bf, Cf = romsynth.skew_cp_factors(N, pairs, seed=6, cfg=25)
+    U = romsynth.initial_u(N, range(B), cfg=25)
+    rom = rg.Rom(N, 1e-3, 1e-3, romsynth.stiffness_diag(N), lam=lam, Af=Af, Bf=Bf, Cf=Cf, dtype=dt, max_batch=B)
+    ops = _round(dt, [lam, Af, Bf, Cf])
+    Ur = _round(dt, [U])[0]
+    refs = [orc.nonlinear_cp(*ops, Ur[b]) for b in range(B)]
+    bounds = [eval_bound_cp(dt, lam, Af, Bf, Cf, U[b]) for b in range(B)]
+    for kind in (2, 3):
+        for v in range(rg.rom_tile_count(kind)):
+            _say(f"cp batched kind {kind} variant {v} {dt}")
+            rg.rom_set_tile(rom.handle, kind, v)
+            Y = _gpu_nonlinear(torch_gpu, rom, U)
+            for b in range(B):
+                check_eval(dt, Y[b], refs[b], bounds[b])
+        rg.rom_set_tile(rom.handle, kind, -1)
+
+
 def test_batched_unit_positions(torch_gpu):
     """One non-zero tensor entry / rank-1 unit factors, through the MFMA path: the
     output must land in row i of every trajectory with weight u_j u_k."""
