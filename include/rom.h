@@ -97,6 +97,17 @@ void rom_destroy(rom_ctx ctx);
  * The contraction runs in the context's dtype; y is returned in FP64.  Asynchronous. */
 rom_status rom_nonlinear(rom_ctx ctx, int32_t batch, const double *u_dev, double *y_dev);
 
+/* Measurement entry point: y = C(u)u exactly as rom_nonlinear computes it, but with the
+ * contraction kernels (dense: the stream or MFMA contraction; CP: projections, Hadamard
+ * product and scatter) captured `reps` >= 1 times into a HIP graph, launched once to warm
+ * up and once between two HIP events on the context's stream; *kernel_us receives their
+ * average duration per repetition (operand copies and the final sum of partial results
+ * are outside the events).  For profiling and roofline reports; the context's stream
+ * must not be capturing.  Synchronizes.  Errors as rom_nonlinear, plus ROM_E_INVALID for
+ * reps < 1 or a NULL kernel_us. */
+rom_status rom_nonlinear_timed(rom_ctx ctx, int32_t batch, const double *u_dev, double *y_dev,
+                               int32_t reps, double *kernel_us);
+
 /* A batch of trajectories at step 0 with initial coefficients u0_host [batch][N].
  * Synchronizes (one upload). */
 rom_status rom_state_create(rom_ctx ctx, int32_t batch, const double *u0_host,

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "ROM_OK", 1: "ROM_E_INVALID", 2: "ROM_E_NOMEM", 3: "ROM_E_DEV
                 4: "ROM_E_NONFINITE", 5: "ROM_E_UNSUPPORTED"}
 
 # every symbol declared in include/rom.h
-EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_state_create", "rom_state_destroy",
+EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_timed", "rom_state_create",
+           "rom_state_destroy",
            "rom_step", "rom_step_async", "rom_step_sync", "rom_energy", "rom_state_get",
            "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
            "rom_tile_count", "rom_last_error"]
@@ -73,6 +74,7 @@ def lib():
     L.rom_destroy.argtypes = [_vp]
     L.rom_destroy.restype = None
     L.rom_nonlinear.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+    L.rom_nonlinear_timed.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _d]
     L.rom_state_create.argtypes = [_vp, ctypes.c_int32, _d, ctypes.POINTER(_vp)]
     L.rom_state_destroy.argtypes = [_vp]
     L.rom_state_destroy.restype = None
@@ -91,7 +93,7 @@ def lib():
     L.rom_tile_count.restype = ctypes.c_int32
     L.rom_last_error.argtypes = []
     L.rom_last_error.restype = ctypes.c_char_p
-    for name in ("rom_create", "rom_nonlinear", "rom_state_create", "rom_step", "rom_step_async",
+    for name in ("rom_create", "rom_nonlinear", "rom_nonlinear_timed", "rom_state_create", "rom_step", "rom_step_async",
                  "rom_step_sync", "rom_energy", "rom_state_get", "rom_state_set", "rom_state_u",
                  "rom_step_multi", "rom_query", "rom_set_tile"):
         getattr(L, name).restype = ctypes.c_int
@@ -166,6 +168,15 @@ def rom_destroy(ctx: int):
 
 def rom_nonlinear(ctx: int, batch: int, u_dev, y_dev):
     _check(lib().rom_nonlinear(ctx, int(batch), _dev_ptr(u_dev), _dev_ptr(y_dev)))
+
+
+def rom_nonlinear_timed(ctx: int, batch: int, u_dev, y_dev, reps: int) -> float:
+    """rom_nonlinear with the contraction kernels launched `reps` times between two events;
+    returns their average duration in microseconds."""
+    us = ctypes.c_double(0.0)
+    _check(lib().rom_nonlinear_timed(ctx, int(batch), _dev_ptr(u_dev), _dev_ptr(y_dev), int(reps),
+                                     ctypes.byref(us)))
+    return float(us.value)
 
 
 def rom_state_create(ctx: int, u0) -> int:

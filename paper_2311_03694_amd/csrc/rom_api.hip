@@ -39,6 +39,13 @@ static rom_status fail(rom_status st, const char* fmt, ...) {
                         __LINE__);                                                        \
     } while (0)
 
+// propagate a rom_status
+#define TRYS(x)                        \
+    do {                               \
+        const rom_status s_ = (x);     \
+        if (s_ != ROM_OK) return s_;   \
+    } while (0)
+
 extern "C" const char* rom_last_error(void) { return g_err.c_str(); }
 
 // ============================================================== objects
@@ -518,7 +525,12 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream) {
     return ROM_OK;
 }
 
-extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_dev, double* y_dev) {
+// Shared body of rom_nonlinear and rom_nonlinear_timed: operand copies (batches), the
+// contraction kernels, and the sum of the partial results into y.  With kernel_us the
+// contraction is captured `reps` times into a HIP graph, launched once to warm up and
+// once between two events; *kernel_us is the average per repetition.
+static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, double* y_dev, int reps,
+                                 double* kernel_us) {
     if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
     if (batch < 1 || batch > c->max_batch) return fail(ROM_E_INVALID, "batch %d outside [1, %d]", batch, c->max_batch);
     if (!u_dev || !y_dev) return fail(ROM_E_INVALID, "u_dev / y_dev is NULL");
@@ -527,20 +539,9 @@ extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_de
     if (st != ROM_OK) return st;
     char* ws = (char*)c->ws;
     const int accf = acc_f64(c->dtype);
-    if (batch == 1) {
-        if (c->dense) {
-            launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, u_dev, nullptr, 0, ws + p.part_off, p.nchunk,
-                              gemv_tile(c), c->stream);
-            launch_sum_partials(accf, ws + p.part_off, p.nchunk, 1, 1, c->N, y_dev, c->stream);
-        } else {
-            launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, u_dev, nullptr, 0, ws + p.part_off,
-                            c->stream);
-            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, ws + p.part_off, y_dev, nullptr, 0,
-                               c->stream);
-        }
-    } else {
+    StepArgs a{};
+    if (batch > 1) {
         // operand copies of the caller's u in the contraction format
-        StepArgs a{};
         a.N = c->N;
         a.Np = c->Np;
         a.B = batch;
@@ -551,20 +552,78 @@ extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_de
         a.ucv_lo = ws + p.ucvlo_off;
         a.uj = ws + p.usc_off;
         launch_prep_ucv(a, u_dev, c->stream);
-        if (c->dense) {
-            launch_dense_batched(c->dtype, p.pd, c->C, c->Clo, c->Ct, c->Ct_lo, c->N, c->Np, p.Bpad, a.ucv,
-                                 a.ucv_lo, a.uj, ws + p.part_off, c->stream);
-            launch_sum_partials(accf, ws + p.part_off, p.pd.nsplit, p.Bpad, batch, c->N, y_dev, c->stream);
+    }
+    auto contract = [&]() {
+        if (batch == 1) {
+            if (c->dense) {
+                launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, u_dev, nullptr, 0, ws + p.part_off, p.nchunk,
+                                  gemv_tile(c), c->stream);
+            } else {
+                launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, u_dev, nullptr, 0, ws + p.part_off,
+                                c->stream);
+                launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, ws + p.part_off, y_dev, nullptr,
+                                   0, c->stream);
+            }
+        } else if (c->dense) {
+            launch_dense_batched(c->dtype, p.pd, c->C, c->Clo, c->Ct, c->Ct_lo, c->N, c->Np, p.Bpad, a.ucv, a.ucv_lo,
+                                 a.uj, ws + p.part_off, c->stream);
         } else {
             launch_proj(c, p.pp, p.Bpad, a.ucv, a.ucv_lo, ws + p.part2_off, c->stream);
             launch_hadamard(c->dtype, ws + p.part2_off, p.pp.nsplit, p.Bpad, batch, c->Rp, c->lam, ws + p.w_off,
                             c->stream);
             launch_scatter(c, p.ps, p.Bpad, ws + p.w_off, ws + p.part_off, c->stream);
-            launch_sum_partials(accf, ws + p.part_off, p.ps.nsplit, p.Bpad, batch, c->N, y_dev, c->stream);
         }
+    };
+    if (!kernel_us) {
+        contract();
+    } else {
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t gx = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int r = 0; r < reps; ++r) contract();
+            e = hipStreamEndCapture(c->stream, &gr);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = hipGraphLaunch(gx, c->stream);          // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) e = hipGraphLaunch(gx, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (gx) hipGraphExecDestroy(gx);
+        if (gr) hipGraphDestroy(gr);
+        if (e != hipSuccess) return fail(ROM_E_DEVICE, "timing the contraction failed: %s", hipGetErrorString(e));
+        *kernel_us = 1e3 * (double)ms / reps;
+    }
+    if (batch == 1) {
+        if (c->dense) launch_sum_partials(accf, ws + p.part_off, p.nchunk, 1, 1, c->N, y_dev, c->stream);
+    } else {
+        launch_sum_partials(accf, ws + p.part_off, c->dense ? p.pd.nsplit : p.ps.nsplit, p.Bpad, batch, c->N, y_dev,
+                            c->stream);
     }
     HIPCHK(hipGetLastError());
     return ROM_OK;
+}
+
+extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_dev, double* y_dev) {
+    return nonlinear_impl(c, batch, u_dev, y_dev, 1, nullptr);
+}
+
+extern "C" rom_status rom_nonlinear_timed(rom_ctx c, int32_t batch, const double* u_dev, double* y_dev, int32_t reps,
+                                          double* kernel_us) {
+    if (!kernel_us) return fail(ROM_E_INVALID, "kernel_us is NULL");
+    if (reps < 1) return fail(ROM_E_INVALID, "reps must be >= 1");
+    rom_status st = nonlinear_impl(c, batch, u_dev, y_dev, reps, kernel_us);
+    if (st == ROM_OK && hipStreamSynchronize(c->stream) != hipSuccess)
+        st = fail(ROM_E_DEVICE, "rom_nonlinear_timed: synchronize failed");
+    return st;
 }
 
 // ============================================================== states

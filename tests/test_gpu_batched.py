@@ -210,3 +210,30 @@ def test_batched_checkpoint_resume(torch_gpu):
     c.set(uh, yh, n)
     c.step(89)
     assert np.array_equal(a.get()[0], c.get()[0])
+
+
+@pytest.mark.parametrize("dense,B", [(True, 1), (True, 20), (False, 1), (False, 20)])
+def test_nonlinear_timed_matches(torch_gpu, dense, B):
+    """The measurement entry point returns the same y as rom_nonlinear (bit for bit),
+    a positive kernel time, and rejects reps < 1."""
+    _say(f"nonlinear_timed dense={dense} B={B}")
+    torch = torch_gpu
+    N = 64
+    U = romsynth.initial_u(N, range(B), cfg=26)
+    if dense:
+        rom = rg.Rom(N, 1e-3, 1e-3, romsynth.stiffness_diag(N), C=romsynth.dense_rough(N, seed=7, cfg=26),
+                     dtype="fp32", max_batch=max(B, 2))
+    else:
+        lam, Af, Bf, Cf = romsynth.skew_cp_factors(N, 20, seed=7, cfg=26)
+        rom = rg.Rom(N, 1e-3, 1e-3, romsynth.stiffness_diag(N), lam=lam, Af=Af, Bf=Bf, Cf=Cf, dtype="fp32",
+                     max_batch=max(B, 2))
+    ud = torch.tensor(U, dtype=torch.float64, device="cuda")
+    y1 = torch.empty_like(ud)
+    y2 = torch.empty_like(ud)
+    rg.rom_nonlinear(rom.handle, B, ud, y1)
+    us = rg.rom_nonlinear_timed(rom.handle, B, ud, y2, 3)
+    torch.cuda.synchronize()
+    assert us > 0
+    assert torch.equal(y1, y2)
+    with pytest.raises(rg.RomError):
+        rg.rom_nonlinear_timed(rom.handle, B, ud, y2, 0)
