@@ -28,9 +28,21 @@
 // contiguous in LDS.  The 4 wavefront tiles are added in LDS in a fixed order and the
 // block writes one partial tile part[split][b][i] (split = j-range * chunks + chunk),
 // which the consumer sums in a fixed order: results are deterministic.
+//
+// Prologue: the j-weights go straight from memory into LDS (global_load_lds) and the X
+// fragments into registers; only after the barrier that publishes the j-weights is
+// the tensor ring issued, so that barrier waits for small L2-resident loads rather
+// than for the ring's HBM traffic.  A chunk's steps rarely split evenly over the 4
+// wavefronts; a wavefront with one step fewer runs a copy of the loop with one
+// MFMA step fewer per j instead of multiplying zero fragments.
+#include <type_traits>
+
 #include "kmfma.h"
 
 namespace rom {
+
+typedef __attribute__((address_space(1))) void* gptr_t;   // global (HBM) pointer
+typedef __attribute__((address_space(3))) void* lptr_t;   // LDS pointer
 
 struct KrArgs {
     const void* C;                 // tiled [ceil(M/16)][J][Kt/VEC][16][VEC], storage format
@@ -71,6 +83,7 @@ __global__ __launch_bounds__(256) void k_kr(KrArgs p) {
     constexpr int KS = Tr::KS, VEC = Tr::VEC, NC = 16 * FN;
     constexpr int EV = 16 / (int)sizeof(Acc);
     constexpr bool X3 = (MKD == MK_BF16X3);
+    static_assert(1024 % (NC * (int)sizeof(Acc)) == 0, "a j-weight row must divide a 1 KB chunk");
     extern __shared__ __attribute__((aligned(16))) char smem[];
     Acc* sl = reinterpret_cast<Acc*>(smem);              // [jn + 1][NC] j-weights, row jn zero
 
@@ -115,41 +128,33 @@ __global__ __launch_bounds__(256) void k_kr(KrArgs p) {
     const int nq = jn;                                   // every wavefront walks all j's
     const int nq_pad = (nq + PF - 1) / PF * PF;
 
-    // Prefetch ring of PF iterations (one j each).  The loop body has no branches and
-    // its loads are never predicated (issues past the last j repeat it, steps past the
-    // chunk repeat its last step), so the compiler counts them exactly and waits only
-    // for the slot it consumes.  Padding iterations up to a multiple of PF take the
-    // zero j-weight row; steps past the chunk meet zero X fragments.
-    u32x4 ah[PF][KW], al[PF][KW];
-    int qp = 0;
-    auto issue = [&](int d) {
-        const int q = qp < nq ? qp : nq - 1;
-        const size_t o = abase + (size_t)q * jstep;
-#pragma unroll
-        for (int s = 0; s < KW; ++s) {
-            const size_t os = o + (size_t)(s < nsa ? s : nsa - 1) * sstep;
-            ah[d][s] = ld_plain<16>(reinterpret_cast<const AT*>(p.C) + os);
-            if constexpr (X3) al[d][s] = ld_plain<16>(p.Clo + os);
+    // ---- j-weights of the block's j's and trajectories, copied straight into LDS
+    // (global_load_lds: no registers, no wait until the barrier).  Wavefront w copies
+    // the 1 KB chunks w, w+4, ... of the [jn][NC] rows; lane l's 16 bytes land at
+    // byte 16 l of its chunk.  Lanes of rows past jn stay idle; columns past Bpad read
+    // a valid weight instead (their X fragments are zero, so it multiplies zeros in
+    // columns that are never stored).  Row jn (the weights of padding iterations) is
+    // written as zeros with ordinary LDS stores.
+    {
+        constexpr int rowb = NC * (int)sizeof(Acc);     // divides 1024
+        constexpr int rpc = 1024 / rowb;                 // rows per chunk
+        const int nch = (jn + rpc - 1) / rpc;
+        const int r_in = (lane * 16) / rowb, cb = (lane * 16) % rowb;
+        const int col = cb / (int)sizeof(Acc);
+        const int colc = b0 + col < p.Bpad ? col : 0;
+        for (int c = w; c < nch; c += 4) {
+            const int jj = c * rpc + r_in;
+            if (jj < jn) {
+                const Acc* src = reinterpret_cast<const Acc*>(p.S) + (size_t)(jbeg + jj) * p.Bpad + b0 + colc;
+                __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)(smem + (size_t)c * 1024), 16, 0, 0);
+            }
         }
-        ++qp;
-    };
-
-    Acc4 Y[FN];
-#pragma unroll
-    for (int t = 0; t < FN; ++t) Y[t] = Acc4{0, 0, 0, 0};
-
-    // Prologue: the ring's first loads (from HBM) go out first, then the X fragments
-    // and the j-weights, so their round trips overlap instead of adding up.
-#pragma unroll
-    for (int d = 0; d < PF; ++d) {
-        issue(d);
-        __builtin_amdgcn_sched_barrier(0);               // slot order: slot 0 lands first
+        for (int e = threadIdx.x; e < NC / EV; e += 256)
+            *reinterpret_cast<u32x4*>(sl + (size_t)jn * NC + e * EV) = u32x4{0u, 0u, 0u, 0u};
     }
+
     // ---- X fragments of the chunk for the lane's trajectories, zero past Kp, Bpad or
-    // the chunk's last step.  The loads are unconditional (clamped addresses; the zero
-    // selection waits until after the barrier): a load skipped on some lanes or paths
-    // would leave the number of loads in flight unknown and force a full wait inside
-    // the loop below.
+    // the chunk's last step (addresses clamped, zero selection after the barrier)
     u32x4 xh[KW][FN], xl[KW][FN];
     unsigned xok = 0;
 #pragma unroll
@@ -165,23 +170,10 @@ __global__ __launch_bounds__(256) void k_kr(KrArgs p) {
             else xl[s][t] = u32x4{0u, 0u, 0u, 0u};
         }
 
-    // ---- j-weights of the block's j's and trajectories; columns past Bpad and the
-    // extra row jn (weights of the padding iterations) read as zero
-    {
-        constexpr int vpr = NC / EV;                     // 16-byte vectors per row
-        staged_copy<16, u32x4>(
-            (jn + 1) * vpr,
-            [&](int idx) {
-                const int jj = idx / vpr, cc = (idx - jj * vpr) * EV;
-                u32x4 v = u32x4{0u, 0u, 0u, 0u};
-                if (jj < jn && b0 + cc < p.Bpad)
-                    v = ld_plain<16>(reinterpret_cast<const Acc*>(p.S) + (size_t)(jbeg + jj) * p.Bpad + b0 + cc);
-                return v;
-            },
-            [&](int idx, const u32x4& v) { *reinterpret_cast<u32x4*>(sl + (size_t)idx * EV) = v; });
-    }
-
-    __syncthreads();                                     // j-weights staged
+    // The copies above must land before any wavefront reads the j-weights; the
+    // tensor ring is issued after the barrier, so this wait covers only the small
+    // L2-resident loads and the ring's HBM traffic starts right behind it.
+    __syncthreads();
 #pragma unroll
     for (int s = 0; s < KW; ++s)
 #pragma unroll
@@ -191,27 +183,74 @@ __global__ __launch_bounds__(256) void k_kr(KrArgs p) {
                 xl[s][t] = u32x4{0u, 0u, 0u, 0u};
             }
 
-    for (int q0 = 0; q0 < nq_pad; q0 += PF) {
+    // Prefetch ring of PF iterations (one j each).  The loop body has no branches and
+    // its loads are never predicated (issues past the last j repeat it, steps past the
+    // wavefront's last step repeat that step), so the compiler counts them exactly and
+    // waits only for the slot it consumes.  Padding iterations up to a multiple of PF
+    // take the zero j-weight row.
+    u32x4 ah[PF][KW], al[PF][KW];
+    int qp = 0;
+    auto issue = [&](int d) {
+        const int q = qp < nq ? qp : nq - 1;
+        const size_t o = abase + (size_t)q * jstep;
 #pragma unroll
-        for (int d = 0; d < PF; ++d) {
-            const int q = q0 + d;
-            Acc4 Z[FN];
-#pragma unroll
-            for (int t = 0; t < FN; ++t) Z[t] = Acc4{0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < KW; ++s)
-#pragma unroll
-                for (int t = 0; t < FN; ++t) mfma_step<MKD>(Z[t], ah[d][s], al[d][s], xh[s][t], xl[s][t]);
-            Acc sv[FN];
-            const int jrow = q < nq ? q : jn;
-            lds_row<FN>(sl + (size_t)jrow * NC + c16 * FN, sv);
-#pragma unroll
-            for (int t = 0; t < FN; ++t) Y[t] += sv[t] * Z[t];
-            issue(d);
-            // keep this slot's loads ahead of the next iterations (arithmetic and LDS
-            // may move across, global loads may not)
-            __builtin_amdgcn_sched_barrier(0x78F);
+        for (int s = 0; s < KW; ++s) {
+            const size_t os = o + (size_t)(s < nsa ? s : nsa - 1) * sstep;
+            ah[d][s] = ld_plain<16>(reinterpret_cast<const AT*>(p.C) + os);
+            if constexpr (X3) al[d][s] = ld_plain<16>(p.Clo + os);
         }
+        ++qp;
+    };
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        issue(d);
+        __builtin_amdgcn_sched_barrier(0);               // slot order: slot 0 lands first
+    }
+
+    Acc4 Y[FN];
+#pragma unroll
+    for (int t = 0; t < FN; ++t) Y[t] = Acc4{0, 0, 0, 0};
+
+    // The loop issues NSC fragment steps per j.  A wavefront with one step fewer than
+    // KW (the chunk's steps do not split evenly) runs the NSC = KW - 1 copy instead of
+    // multiplying zero fragments; the rare other counts use the KW copy with zero
+    // fragments past their last step.
+    // The j-weights are read one iteration ahead, so the LDS latency overlaps the
+    // matrix work instead of stalling the fold.
+    auto run = [&](auto nsc) {
+        constexpr int NSC = decltype(nsc)::value;
+        Acc svn[FN];
+        lds_row<FN>(sl + c16 * FN, svn);                 // row 0 (jn >= 1)
+        for (int q0 = 0; q0 < nq_pad; q0 += PF) {
+#pragma unroll
+            for (int d = 0; d < PF; ++d) {
+                const int q = q0 + d;
+                Acc sv[FN];
+#pragma unroll
+                for (int t = 0; t < FN; ++t) sv[t] = svn[t];
+                const int jnext = q + 1 < nq ? q + 1 : jn;
+                lds_row<FN>(sl + (size_t)jnext * NC + c16 * FN, svn);
+                Acc4 Z[FN];
+#pragma unroll
+                for (int t = 0; t < FN; ++t) Z[t] = Acc4{0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < NSC; ++s)
+#pragma unroll
+                    for (int t = 0; t < FN; ++t) mfma_step<MKD>(Z[t], ah[d][s], al[d][s], xh[s][t], xl[s][t]);
+#pragma unroll
+                for (int t = 0; t < FN; ++t) Y[t] += sv[t] * Z[t];
+                issue(d);
+                // keep this slot's loads ahead of the next iterations (arithmetic and
+                // LDS may move across, global loads may not)
+                __builtin_amdgcn_sched_barrier(0x78F);
+            }
+        }
+    };
+    if constexpr (KW > 1) {
+        if (ns == KW - 1) run(std::integral_constant<int, KW - 1>{});
+        else run(std::integral_constant<int, KW>{});
+    } else {
+        run(std::integral_constant<int, KW>{});
     }
 
     // ---- add the 4 wavefront tiles in LDS (fixed order) and write the partial tile
