@@ -15,14 +15,13 @@ namespace rom {
 // ============================================================== update kernels
 
 // y^n from contraction partials part[c][b][i] (summed over c in order), then either
-// the diagonal-stiffness update u^{n+1} = rhs / H_ii with energy and finalize, or the
-// right-hand side for the dense solve.  Block (bx, b) of an (nbx, B) grid of 256-thread
-// blocks covers rows 256 bx .. 256 bx + 255 of trajectory b.
+// the diagonal-stiffness update u^{n+1} = rhs / H_ii with its energy partials, or the
+// right-hand side for the dense solve.  Block (bx, b) covers rows 256 bx .. 256 bx + 255
+// of trajectory b (nbx blocks per trajectory).
 template <class ACC, bool DIAG>
-__device__ __forceinline__ void bdf_partials_body(const StepArgs& a, const ACC* __restrict__ part, int nchunk,
-                                                  int pbstride, int bx, int b, int nbx, int nblk_total) {
+__device__ __forceinline__ void bdf_partials_body(const StepArgs& a, long long n, const ACC* __restrict__ part,
+                                                  int nchunk, int pbstride, int bx, int b, int nbx) {
     __shared__ double red[4];
-    const long long n = *a.step;
     const int k = bdf_order(n);
     const BdfCoef c = bdf_coef(k);
     const int i = bx * blockDim.x + threadIdx.x;
@@ -52,24 +51,39 @@ __device__ __forceinline__ void bdf_partials_body(const StepArgs& a, const ACC* 
     }
     if (DIAG) {
         const double s = block_sum(e, red);
-        if (threadIdx.x == 0) a.epart[(size_t)b * nbx + bx] = s;
+        if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * nbx + bx] = s;
     }
-    (void)nblk_total;
 }
 
+// Grid (nbx, B) for the right-hand side; with DIAG (the update kernel) one more row
+// whose block 0 closes the previous level and advances the counter (the rest of that
+// row exits at once).
 template <class ACC, bool DIAG>
 __global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __restrict__ part,
                                                       int nchunk, int pbstride) {
-    bdf_partials_body<ACC, DIAG>(a, part, nchunk, pbstride, blockIdx.x, blockIdx.y, gridDim.x,
-                                 gridDim.x * gridDim.y);
+    if constexpr (DIAG) {
+        if ((int)blockIdx.y == a.B) {
+            if (blockIdx.x == 0) close_and_advance(a, *a.step);
+            return;
+        }
+        bdf_partials_body<ACC, true>(a, *a.step, part, nchunk, pbstride, blockIdx.x, blockIdx.y, gridDim.x);
+    } else {
+        bdf_partials_body<ACC, false>(a, *a.step, part, nchunk, pbstride, blockIdx.x, blockIdx.y, gridDim.x);
+    }
 }
 
+// Grouped states (one trajectory each); with DIAG the first block of each job also
+// closes its state's previous level and advances its counter.
 template <class ACC, bool DIAG>
 __global__ __launch_bounds__(256) void k_bdf_group(const BdfJob* __restrict__ jobs, int njobs) {
     const int p = find_job(jobs, njobs, (int)blockIdx.x);
     const BdfJob& jb = jobs[p];
-    bdf_partials_body<ACC, DIAG>(jb.a, reinterpret_cast<const ACC*>(jb.part), jb.nchunk, jb.pb,
-                                 (int)blockIdx.x - jb.blk0, 0, jb.nblk, jb.nblk);
+    const int blk = (int)blockIdx.x - jb.blk0;
+    const long long n = *jb.a.step;
+    if constexpr (DIAG) {
+        if (blk == 0) close_and_advance(jb.a, n);
+    }
+    bdf_partials_body<ACC, DIAG>(jb.a, n, reinterpret_cast<const ACC*>(jb.part), jb.nchunk, jb.pb, blk, 0, jb.nblk);
 }
 
 // Dense stiffness, one trajectory: u^{n+1}_i = sum_m Hinv_k[i][m] rhs_m, one wavefront
@@ -77,13 +91,12 @@ __global__ __launch_bounds__(256) void k_bdf_group(const BdfJob* __restrict__ jo
 // staged in LDS; rows longer than 1024 elements loop.  Block blk of nblk covers rows
 // 4 blk .. 4 blk + 3.
 template <bool EVEN>
-__device__ __forceinline__ void helm_gemv_body(const StepArgs& a, int blk, int nblk) {
+__device__ __forceinline__ void helm_gemv_body(const StepArgs& a, long long n, int blk) {
     extern __shared__ __attribute__((aligned(16))) double sm[];
     double* r = sm;                       // [N]
     __shared__ double red[4];
     constexpr int V = EVEN ? 2 : 1, U = 8;
     typedef typename RawT<8 * V>::T Raw;
-    const long long n = *a.step;
     const int k = bdf_order(n);
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     const int i = blk * 4 + w;
@@ -124,28 +137,41 @@ __device__ __forceinline__ void helm_gemv_body(const StepArgs& a, int blk, int n
         }
     }
     const double es = block_sum(e, red);
-    if (threadIdx.x == 0) a.epart[blk] = es;
-    (void)nblk;
+    if (threadIdx.x == 0) epart_of(a, n + 1)[blk] = es;
 }
 
+// ceil(N/4) row blocks plus a last block that closes the previous level and advances
+// the counter.
 template <bool EVEN>
 __global__ __launch_bounds__(256) void k_helm_gemv(StepArgs a) {
-    helm_gemv_body<EVEN>(a, blockIdx.x, gridDim.x);
+    if (blockIdx.x == gridDim.x - 1) {
+        close_and_advance(a, *a.step);
+        return;
+    }
+    helm_gemv_body<EVEN>(a, *a.step, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_helm_group(const HelmJob* __restrict__ jobs, int njobs) {
     const int p = find_job(jobs, njobs, (int)blockIdx.x);
     const HelmJob& jb = jobs[p];
-    if (jb.a.N % 2 == 0) helm_gemv_body<true>(jb.a, (int)blockIdx.x - jb.blk0, jb.nblk);
-    else helm_gemv_body<false>(jb.a, (int)blockIdx.x - jb.blk0, jb.nblk);
+    const int blk = (int)blockIdx.x - jb.blk0;
+    const long long n = *jb.a.step;
+    if (blk == 0) close_and_advance(jb.a, n);
+    if (jb.a.N % 2 == 0) helm_gemv_body<true>(jb.a, n, blk);
+    else helm_gemv_body<false>(jb.a, n, blk);
 }
 
 // Dense stiffness, batch: the FP64 MFMA kernel writes partial sums
 // part[z][b][i] of U^{n+1}[b][i] = sum_m Hinv_k[i][m] rhs[b][m]; this kernel adds them
 // in z order, stores level n+1, and reduces energies and the health flag.
-// Grid (ceil(N/256), B).
+// Grid (ceil(N/256), B + 1): block 0 of the last row closes the previous level and
+// advances the counter.
 __global__ __launch_bounds__(256) void k_helm_finish(StepArgs a, const double* __restrict__ part, int nsplit) {
     __shared__ double red[4];
+    if ((int)blockIdx.y == a.B) {
+        if (blockIdx.x == 0) close_and_advance(a, *a.step);
+        return;
+    }
     const long long n = *a.step;
     const int b = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -167,46 +193,21 @@ __global__ __launch_bounds__(256) void k_helm_finish(StepArgs a, const double* _
         e = u * u;
     }
     const double s = block_sum(e, red);
-    if (threadIdx.x == 0) a.epart[(size_t)b * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * gridDim.x + blockIdx.x] = s;
 }
 
-// Closes step n -> n+1 of a state after its update kernel: sums the per-block energy
-// partials epart[b][0..nblk) in a fixed order (deterministic), logs E^{n+1}, records the
-// first non-finite level and advances the step counter.  One 256-thread block per
-// state.  The kernel boundary before it makes the update kernel's partials visible, so
-// no block of the update kernel needs a device-wide fence (on gfx950 a fence at device
-// scope writes back and invalidates its XCD's whole L2).
-__device__ __forceinline__ void finalize_body(const StepArgs& a, int nblk) {
-    __shared__ double fred[4];
-    const long long n = *a.step;
-    if (a.B == 1) {
-        double s = 0.0;
-        for (int q = threadIdx.x; q < nblk; q += blockDim.x) s += a.epart[q];
-        s = block_sum(s, fred);
-        if (threadIdx.x == 0) {
-            const double e = 0.5 * s;
-            if (n + 1 < a.elog_cap) a.elog[n + 1] = e;
-            if (!isfinite(e)) atomicMin(a.bad, n + 1);
-        }
-    } else {
-        for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
-            const double* ep = a.epart + (size_t)b * nblk;
-            double s = 0.0;
-#pragma unroll 8
-            for (int q = 0; q < nblk; ++q) s += ep[q];
-            const double e = 0.5 * s;
-            if (n + 1 < a.elog_cap) a.elog[(size_t)(n + 1) * a.B + b] = e;
-            if (!isfinite(e)) atomicMin(a.bad, n + 1);
-        }
-    }
-    __syncthreads();                      // every thread has read the step counter
-    if (threadIdx.x == 0) *a.step = n + 1;
+// Sums the energy of the newest level if it is still pending (the last level of a
+// sequence of steps; the update kernels close every earlier one).  One block per state.
+__device__ __forceinline__ void close_body(const StepArgs& a) {
+    close_level(a, *a.step);
+    __syncthreads();                      // every thread has read closep
+    if (threadIdx.x == 0) *a.closep = 0;
 }
 
-__global__ __launch_bounds__(256) void k_finalize(StepArgs a, int nblk) { finalize_body(a, nblk); }
+__global__ __launch_bounds__(256) void k_close(StepArgs a) { close_body(a); }
 
-__global__ __launch_bounds__(256) void k_finalize_group(const FinJob* __restrict__ jobs) {
-    finalize_body(jobs[blockIdx.x].a, jobs[blockIdx.x].nblk);
+__global__ __launch_bounds__(256) void k_close_group(const FinJob* __restrict__ jobs) {
+    close_body(jobs[blockIdx.x].a);
 }
 
 // Batched coefficient copies of u [B][N] (state creation / restart, batched
@@ -243,7 +244,7 @@ __global__ void k_sum_partials(const ACC* __restrict__ part, int nchunk, int B, 
 
 void launch_bdf_from_partials(const StepArgs& a, int acc_f64, const void* part, int nchunk,
                               int pb, int diag, hipStream_t s) {
-    dim3 grid((a.N + 255) / 256, a.B);
+    dim3 grid((a.N + 255) / 256, a.B + (diag ? 1 : 0));
     if (acc_f64) {
         if (diag) hipLaunchKernelGGL((k_bdf_partials<double, true>), grid, dim3(256), 0, s, a, (const double*)part, nchunk, pb);
         else hipLaunchKernelGGL((k_bdf_partials<double, false>), grid, dim3(256), 0, s, a, (const double*)part, nchunk, pb);
@@ -251,15 +252,14 @@ void launch_bdf_from_partials(const StepArgs& a, int acc_f64, const void* part, 
         if (diag) hipLaunchKernelGGL((k_bdf_partials<float, true>), grid, dim3(256), 0, s, a, (const float*)part, nchunk, pb);
         else hipLaunchKernelGGL((k_bdf_partials<float, false>), grid, dim3(256), 0, s, a, (const float*)part, nchunk, pb);
     }
-    if (diag) launch_finalize(a, (a.N + 255) / 256, s);
 }
 
-void launch_finalize(const StepArgs& a, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a, nblk);
+void launch_close(const StepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_close, dim3(1), dim3(256), 0, s, a);
 }
 
-void launch_finalize_group(const FinJob* jobs_dev, int njobs, hipStream_t s) {
-    if (njobs > 0) hipLaunchKernelGGL(k_finalize_group, dim3((unsigned)njobs), dim3(256), 0, s, jobs_dev);
+void launch_close_group(const FinJob* jobs_dev, int njobs, hipStream_t s) {
+    if (njobs > 0) hipLaunchKernelGGL(k_close_group, dim3((unsigned)njobs), dim3(256), 0, s, jobs_dev);
 }
 
 void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s) {
@@ -278,14 +278,13 @@ void launch_helm_group(const HelmJob* jobs_dev, int njobs, int blocks, int Nmax,
 
 void launch_helm_apply(const StepArgs& a, hipStream_t s) {
     const size_t lds = sizeof(double) * a.N;
-    if (a.N % 2 == 0) hipLaunchKernelGGL(k_helm_gemv<true>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL(k_helm_gemv<false>, dim3((a.N + 3) / 4), dim3(256), lds, s, a);
-    launch_finalize(a, (a.N + 3) / 4, s);
+    const unsigned blocks = (unsigned)((a.N + 3) / 4 + 1);
+    if (a.N % 2 == 0) hipLaunchKernelGGL(k_helm_gemv<true>, dim3(blocks), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL(k_helm_gemv<false>, dim3(blocks), dim3(256), lds, s, a);
 }
 
 void launch_helm_finish(const StepArgs& a, const double* part, int nsplit, hipStream_t s) {
-    hipLaunchKernelGGL(k_helm_finish, dim3((a.N + 255) / 256, a.B), dim3(256), 0, s, a, part, nsplit);
-    launch_finalize(a, (a.N + 255) / 256, s);
+    hipLaunchKernelGGL(k_helm_finish, dim3((a.N + 255) / 256, a.B + 1), dim3(256), 0, s, a, part, nsplit);
 }
 
 void launch_prep_ucv(const StepArgs& a, const double* u_src, hipStream_t s) {

@@ -73,11 +73,12 @@ __global__ __launch_bounds__(256) void k_cp_proj1_group(const Proj1Job* __restri
 
 // Hadamard-and-scatter: W_r = lam_r s_r t_r in LDS, then y_i = sum_r Af[i][r] W_r, one
 // wavefront per row (row loads issued before W is formed).  MODE 0 writes y (FP64,
-// to y_out); MODE 1 applies the diagonal-stiffness BDF update with energy and
-// finalize; MODE 2 writes the right-hand side for the dense Helmholtz solve.
+// to y_out); MODE 1 applies the diagonal-stiffness BDF update with its energy
+// partials; MODE 2 writes the right-hand side for the dense Helmholtz solve.  n is the
+// state's level (MODE 1 and 2).
 template <int DT, int V, int U, int MODE>
 __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __restrict__ y_out, int blk,
-                                                 int nblk) {
+                                                 long long n) {
     typedef typename Store<DT>::T T;
     typedef typename Store<DT>::Acc Acc;
     constexpr int BYTES = V * (int)sizeof(T);
@@ -141,7 +142,6 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
     if constexpr (MODE == 0) {
         if (live && lane == 0) y_out[i] = (double)z;
     } else {
-        const long long n = *a.step;
         const int k = bdf_order(n);
         const BdfCoef c = bdf_coef(k);
         double e = 0.0;
@@ -157,19 +157,36 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
         }
         if constexpr (MODE == 1) {
             const double s = block_sum(e, red);
-            if (threadIdx.x == 0) a.epart[blk] = s;
+            if (threadIdx.x == 0) epart_of(a, n + 1)[blk] = s;
         }
     }
 }
 
+// MODE 1 (the update kernel) runs one block more than there are row blocks: the last
+// one closes the previous level and advances the counter.
 template <int DT, int V, int U, int MODE>
 __global__ __launch_bounds__(256) void k_cp_scatter1(Scat1Job jb, double* y_out) {
-    cp_scatter1_body<DT, V, U, MODE>(jb, y_out, blockIdx.x, gridDim.x);
+    if constexpr (MODE == 1) {
+        if (blockIdx.x == gridDim.x - 1) {
+            close_and_advance(jb.a, *jb.a.step);
+            return;
+        }
+        cp_scatter1_body<DT, V, U, MODE>(jb, y_out, blockIdx.x, *jb.a.step);
+    } else {
+        cp_scatter1_body<DT, V, U, MODE>(jb, y_out, blockIdx.x, MODE == 0 ? 0LL : *jb.a.step);
+    }
 }
 template <int DT, int V, int U, int MODE>
 __global__ __launch_bounds__(256) void k_cp_scatter1_group(const Scat1Job* __restrict__ jobs, int njobs) {
     const int p = find_job(jobs, njobs, (int)blockIdx.x);
-    cp_scatter1_body<DT, V, U, MODE>(jobs[p], nullptr, (int)blockIdx.x - jobs[p].blk0, jobs[p].nblk);
+    const Scat1Job& jb = jobs[p];
+    const int blk = (int)blockIdx.x - jb.blk0;
+    long long n = 0;
+    if constexpr (MODE != 0) n = *jb.a.step;
+    if constexpr (MODE == 1) {
+        if (blk == 0) close_and_advance(jb.a, n);
+    }
+    cp_scatter1_body<DT, V, U, MODE>(jb, nullptr, blk, n);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -222,7 +239,8 @@ static void scat1_go(const Scat1Job& jb, double* y, const Scat1Job* jobs, int nj
     constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
     const size_t lds = sizeof(Acc) * Rpmax;
     if (jobs) hipLaunchKernelGGL((k_cp_scatter1_group<DT, V, 8, MODE>), dim3((unsigned)blocks), dim3(256), lds, s, jobs, njobs);
-    else hipLaunchKernelGGL((k_cp_scatter1<DT, V, 8, MODE>), dim3((unsigned)jb.nblk), dim3(256), lds, s, jb, y);
+    else hipLaunchKernelGGL((k_cp_scatter1<DT, V, 8, MODE>), dim3((unsigned)jb.nblk + (MODE == 1 ? 1u : 0u)), dim3(256),
+                            lds, s, jb, y);
 }
 
 template <int DT>
@@ -256,7 +274,6 @@ int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, const void* la
     if (sa) jb.a = *sa;
     jb.nblk = (N + 3) / 4;
     scat1_dispatch(dt, mode, jb, y_out, nullptr, 0, 0, Rp, s);
-    if (mode == 1) launch_finalize(jb.a, jb.nblk, s);
     return 0;
 }
 

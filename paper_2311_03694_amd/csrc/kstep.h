@@ -1,6 +1,6 @@
 // kstep.h -- per-point pieces of the BDFk/EXTk step shared by the update kernels and
-// the fused CP scatter kernel: right-hand side, level store, and the last-block
-// finalization (energy log, health flag, step counter).
+// the fused CP scatter kernel: right-hand side, level store, and the step close
+// (energy log, health flag, step counter).
 #pragma once
 
 #include "kcommon.h"
@@ -61,6 +61,67 @@ __device__ __forceinline__ void write_level(const StepArgs& a, long long n1, int
     const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N + i;
     a.uring[(size_t)slot_of(n1) * BN + off] = u;
     if (a.batched) write_ucv(a, b, i, u);
+}
+
+// ---------------------------------------------------------------- step close
+//
+// An update kernel writes level n+1.  Closing a step takes three things: advancing the
+// device step counter, summing the per-block energy partials into E^{n+1} (eq.
+// ene_fluc) and raising the health flag.  None of them needs a kernel of its own, nor
+// a device-wide fence (on gfx950 such a fence writes back and invalidates the XCD's
+// whole L2):
+//  * Counter: the counter has two slots; the kernels of the step of level n read slot
+//    n & 1 and one block of the update kernel stores n+1 into the other slot, which
+//    no kernel of this step reads (the host, which knows every level's parity, passes
+//    the slot pointers).  The next step reads it after the kernel boundary.
+//  * Energy: the partials of level n+1 are summed one step later, by that same block
+//    of the next update kernel, after the kernel boundary has made them visible.
+//    Partials alternate between two slots by level parity, so that block reads one
+//    slot while the kernel writes the other.  closep marks a level whose sum is still
+//    pending; a closing kernel sums the last level of a sequence of steps.
+
+// Energy partials of level n1: [B][enblk] in slot n1 & 1.
+__device__ __forceinline__ double* epart_of(const StepArgs& a, long long n1) {
+    return a.epart + (size_t)(n1 & 1) * a.B * a.enblk;
+}
+
+// Whole block: if level n's energy is pending, sum its partials in a fixed order
+// (deterministic), log E^n and record a non-finite level.
+__device__ __forceinline__ void close_level(const StepArgs& a, long long n) {
+    __shared__ double cred[4];
+    if (*a.closep == 0) return;
+    const double* ep = epart_of(a, n);
+    if (a.B == 1) {
+        double s = 0.0;
+        for (int q = threadIdx.x; q < a.enblk; q += blockDim.x) s += ep[q];
+        s = block_sum(s, cred);
+        if (threadIdx.x == 0) {
+            const double e = 0.5 * s;
+            if (n < a.elog_cap) a.elog[n] = e;
+            if (!isfinite(e)) atomicMin(a.bad, n);
+        }
+    } else {
+        for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+            const double* eb = ep + (size_t)b * a.enblk;
+            double s = 0.0;
+#pragma unroll 8
+            for (int q = 0; q < a.enblk; ++q) s += eb[q];
+            const double e = 0.5 * s;
+            if (n < a.elog_cap) a.elog[(size_t)n * a.B + b] = e;
+            if (!isfinite(e)) atomicMin(a.bad, n);
+        }
+    }
+}
+
+// One block of each update kernel (whole block): closes level n, marks level n+1 as
+// pending and advances the counter.
+__device__ __forceinline__ void close_and_advance(const StepArgs& a, long long n) {
+    close_level(a, n);
+    __syncthreads();                      // every thread has read closep
+    if (threadIdx.x == 0) {
+        *a.closep = 1;
+        *a.step_next = n + 1;
+    }
 }
 
 }  // namespace rom

@@ -98,8 +98,11 @@ struct rom_state_s {
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     int sgen = 0;                       // bumped when scratch or the energy log moves
-    hipGraphExec_t graph = nullptr;
-    int graph_gen = -1, graph_sgen = -1;
+    long long* cnt = nullptr;           // the two slots of the device step counter
+    // captured chunks of steps, one per parity of the first level (the kernels of a
+    // step take the counter slots of its level's parity)
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_gen[2] = {-1, -1}, graph_sgen[2] = {-1, -1};
     bool pending = false;
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -478,11 +481,20 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
 
 // ============================================================== contraction dispatch
 
-// Enqueue one BDF3/EXT3 step of state s on `stream`: contraction (dense or CP,
-// single-trajectory or batched kernels), FP64 update and energy; dense stiffness adds
-// the Helmholtz apply.
-static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream) {
-    const StepArgs& a = s->a;
+// The state's kernel arguments for the step from level n: the counter slot of n's
+// parity to read, the other one to advance.
+static StepArgs step_args(rom_state s, long long n) {
+    StepArgs a = s->a;
+    a.step = s->cnt + (n & 1);
+    a.step_next = s->cnt + ((n + 1) & 1);
+    return a;
+}
+
+// Enqueue one BDF3/EXT3 step of state s from level n on `stream`: contraction (dense
+// or CP, single-trajectory or batched kernels), FP64 update and energy; dense
+// stiffness adds the Helmholtz apply.
+static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long long n) {
+    const StepArgs a = step_args(s, n);
     const WsPlan p = plan_ws(c, s->B);
     const int accf = acc_f64(c->dtype);
     const int diag = c->diagA ? 1 : 0;
@@ -707,10 +719,23 @@ rom_status ensure_scratch(rom_state s) {
 rom_status reset_counters(rom_state s, long long step) {
     rom_ctx c = s->ctx;
     const long long big = LLONG_MAX;
-    HIPCHK(hipMemcpyAsync(s->a.step, &step, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    const long long both[2] = {step, step};
+    const int none = 0;
+    HIPCHK(hipMemcpyAsync(s->cnt, both, sizeof(both), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(s->a.bad, &big, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(s->a.closep, &none, sizeof(int), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return ROM_OK;
+}
+
+// Blocks per trajectory of the kernel that writes level n+1 of a state (the energy
+// partials it leaves): the diagonal update of the partial sums (256 rows a block),
+// the single-trajectory Helmholtz apply or fused CP update (4 rows a block), or the
+// batched Helmholtz finish (256 rows a block).
+int update_blocks(rom_ctx c, int B) {
+    if (B > 1) return (c->N + 255) / 256;
+    if (c->dense && c->diagA) return (c->N + 255) / 256;
+    return (c->N + 3) / 4;
 }
 
 }  // namespace
@@ -718,7 +743,8 @@ rom_status reset_counters(rom_state s, long long step) {
 extern "C" void rom_state_destroy(rom_state s) {
     if (!s) return;
     if (s->ctx && s->ctx->stream) hipStreamSynchronize(s->ctx->stream);
-    if (s->graph) hipGraphExecDestroy(s->graph);
+    for (auto g : s->graph)
+        if (g) hipGraphExecDestroy(g);
     for (void* p : s->allocs) hipFree(p);
     if (s->a.elog) hipFree(s->a.elog);
     if (s->scratch) hipFree(s->scratch);
@@ -758,9 +784,13 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(dmalloc((void**)&a.uring, sizeof(double) * 3 * BN, &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.yring, sizeof(double) * 3 * BN, &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.rhs, sizeof(double) * s->Bpad * c->Np, &s->bytes, &s->allocs));
-    TRY(dmalloc((void**)&a.epart, sizeof(double) * B * ((N + 3) / 4 + 64), &s->bytes, &s->allocs));
-    TRY(dmalloc((void**)&a.step, sizeof(long long), &s->bytes, &s->allocs));
+    a.enblk = update_blocks(c, batch);
+    TRY(dmalloc((void**)&a.epart, sizeof(double) * 2 * B * a.enblk, &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&s->cnt, 2 * sizeof(long long), &s->bytes, &s->allocs));
+    a.step = s->cnt;
+    a.step_next = s->cnt + 1;
     TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.closep, sizeof(int), &s->bytes, &s->allocs));
     if (a.batched) {
         const size_t cells = (size_t)s->Bpad * c->Np;
         TRY(dmalloc(&a.ucv, cells * elem_bytes(c->dtype), &s->bytes, &s->allocs));
@@ -811,41 +841,50 @@ static rom_status prepare(rom_ctx c, rom_state s, int64_t nsteps) {
 static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
     rom_status st = prepare(c, s, nsteps);
     if (st != ROM_OK) return st;
+    const long long n0 = s->h_step;
+    long long n = n0;
     int64_t left = nsteps;
     if (left >= 2 * kGraphChunk) {
-        if (!s->graph || s->graph_gen != c->ws_gen || s->graph_sgen != s->sgen) {
-            if (s->graph) {
-                hipGraphExecDestroy(s->graph);
-                s->graph = nullptr;
+        // kGraphChunk is even, so every launch of the chunk starts at n0's parity
+        const int par = (int)(n0 & 1);
+        hipGraphExec_t& gx = s->graph[par];
+        if (!gx || s->graph_gen[par] != c->ws_gen || s->graph_sgen[par] != s->sgen) {
+            if (gx) {
+                hipGraphExecDestroy(gx);
+                gx = nullptr;
             }
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             rom_status cst = ROM_OK;
-            for (int q = 0; q < kGraphChunk && cst == ROM_OK; ++q) cst = enqueue_step(c, s, c->stream);
+            for (int q = 0; q < kGraphChunk && cst == ROM_OK; ++q) cst = enqueue_step(c, s, c->stream, n0 + q);
             hipError_t ee = hipStreamEndCapture(c->stream, &g);
             if (cst != ROM_OK) {
                 if (g) hipGraphDestroy(g);
                 return cst;
             }
             if (ee != hipSuccess) return fail(ROM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ee));
-            hipError_t ie = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
+            hipError_t ie = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
             hipGraphDestroy(g);
             if (ie != hipSuccess) {
-                s->graph = nullptr;
+                gx = nullptr;
                 return fail(ROM_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
             }
-            s->graph_gen = c->ws_gen;
-            s->graph_sgen = s->sgen;
+            s->graph_gen[par] = c->ws_gen;
+            s->graph_sgen[par] = s->sgen;
         }
         while (left >= kGraphChunk) {
-            HIPCHK(hipGraphLaunch(s->graph, c->stream));
+            HIPCHK(hipGraphLaunch(gx, c->stream));
             left -= kGraphChunk;
+            n += kGraphChunk;
         }
     }
-    for (; left > 0; --left) {
-        st = enqueue_step(c, s, c->stream);
+    for (; left > 0; --left, ++n) {
+        st = enqueue_step(c, s, c->stream, n);
         if (st != ROM_OK) return st;
     }
+    // every update kernel closes the level before its own; the newest one is closed here
+    if (nsteps > 0) launch_close(step_args(s, n0 + nsteps), c->stream);
+    HIPCHK(hipGetLastError());
     s->h_step += nsteps;
     s->pending = true;
     return ROM_OK;
@@ -967,7 +1006,7 @@ struct Group {
     std::vector<Scat1Job> scat;
     std::vector<BdfJob> bdf;
     std::vector<HelmJob> helm;
-    std::vector<FinJob> fin;               // phase 4: one step-close block per state
+    std::vector<FinJob> fin;               // closing energy sum after the last step, per state
     int b1 = 0, b2 = 0, b3 = 0;            // blocks of phase 1, 2, 3
     int Npmax = 8, Rpmax = 8, Nmax = 1;
     GemvTile tile{};
@@ -1001,7 +1040,7 @@ void enqueue_group(const Group& g, hipStream_t stream, int phase) {
     } else if (phase == 3) {
         if (!g.diag) launch_helm_group((const HelmJob*)(g.dev + g.off3), (int)g.helm.size(), g.b3, g.Nmax, stream);
     } else {
-        launch_finalize_group((const FinJob*)(g.dev + g.off4), (int)g.fin.size(), stream);
+        launch_close_group((const FinJob*)(g.dev + g.off4), (int)g.fin.size(), stream);
     }
 }
 
@@ -1026,23 +1065,26 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
     }
     if (nsteps == 0) return ROM_OK;
 
-    // ---- job tables
-    std::vector<Group> groups;
+    // ---- job tables, one set per parity of the step index k (pair q's level is
+    // h_step + k, and its kernels take the counter slots of that level's parity)
+    std::vector<Group> groups[2];
     std::vector<int> batched;
+    for (int par = 0; par < 2; ++par)
     for (int q = 0; q < n; ++q) {
         rom_ctx c = ctxs[q];
         rom_state st = states[q];
         if (st->B != 1) {
-            batched.push_back(q);
+            if (par == 0) batched.push_back(q);
             continue;
         }
+        const StepArgs sa = step_args(st, st->h_step + par);
         const int dense = c->dense ? 1 : 0, diag = c->diagA ? 1 : 0;
         Group* g = nullptr;
-        for (auto& x : groups)
+        for (auto& x : groups[par])
             if (x.dense == dense && x.dtype == c->dtype && x.diag == diag) g = &x;
         if (!g) {
-            groups.emplace_back();
-            g = &groups.back();
+            groups[par].emplace_back();
+            g = &groups[par].back();
             g->dense = dense;
             g->dtype = c->dtype;
             g->diag = diag;
@@ -1051,13 +1093,13 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
         const WsPlan p = plan_ws(c, 1);
         char* scr = (char*)st->scratch;
         if (dense) {
-            GemvJob jb = make_gemv_job(c->dtype, c->C, c->Clo, c->N, c->Np, st->a.uring, st->a.step, c->N,
+            GemvJob jb = make_gemv_job(c->dtype, c->C, c->Clo, c->N, c->Np, sa.uring, sa.step, c->N,
                                        scr + p.part_off, p.nchunk, gemv_tile(c));
             jb.blk0 = g->b1;
             g->b1 += jb.nblk;
             g->gemv.push_back(jb);
             BdfJob bj{};
-            bj.a = st->a;
+            bj.a = sa;
             bj.part = scr + p.part_off;
             bj.nchunk = p.nchunk;
             bj.pb = 1;
@@ -1072,8 +1114,8 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
             pj.N = c->N;
             pj.Np = c->Np;
             pj.R2 = 2 * c->Rp;
-            pj.u_base = st->a.uring;
-            pj.stepp = st->a.step;
+            pj.u_base = sa.uring;
+            pj.stepp = sa.step;
             pj.slot_stride = c->N;
             pj.st = scr + p.part_off;
             pj.blk0 = g->b1;
@@ -1087,7 +1129,7 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
             sj.N = c->N;
             sj.Rp = c->Rp;
             sj.st = scr + p.part_off;
-            sj.a = st->a;
+            sj.a = sa;
             sj.blk0 = g->b2;
             sj.nblk = (c->N + 3) / 4;
             g->b2 += sj.nblk;
@@ -1096,44 +1138,49 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
         }
         if (!diag) {
             HelmJob hj{};
-            hj.a = st->a;
+            hj.a = sa;
             hj.blk0 = g->b3;
             hj.nblk = (c->N + 3) / 4;
             g->b3 += hj.nblk;
             g->helm.push_back(hj);
         }
-        // the update kernel (phase 2 with a diagonal stiffness, else phase 3) leaves
-        // per-block energy partials; phase 4 closes the step
+        // the update kernel (phase 2 with a diagonal stiffness, else phase 3) advances
+        // the step and closes the previous level; phase 4, after the last step, closes
+        // the newest one
         FinJob fj{};
-        fj.a = st->a;
-        fj.nblk = (diag && dense) ? (c->N + 255) / 256 : (c->N + 3) / 4;
+        fj.a = sa;
+        fj.nblk = sa.enblk;
         g->fin.push_back(fj);
         if (c->Np > g->Npmax) g->Npmax = c->Np;
         if (c->N > g->Nmax) g->Nmax = c->N;
     }
-    std::vector<char> blob;
-    for (auto& g : groups) {
-        g.off1 = g.dense ? put(blob, g.gemv) : put(blob, g.proj);
-        g.off2 = g.dense ? put(blob, g.bdf) : put(blob, g.scat);
-        g.off3 = put(blob, g.helm);
-        g.off4 = put(blob, g.fin);
-    }
-    char* dev = nullptr;
-    if (!blob.empty()) {
-        HIPCHK(hipMalloc((void**)&dev, blob.size()));
-        hipError_t e = hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            hipFree(dev);
-            return fail(ROM_E_DEVICE, "job table upload failed: %s", hipGetErrorString(e));
+    char* dev[2] = {nullptr, nullptr};
+    for (int par = 0; par < 2; ++par) {
+        std::vector<char> blob;
+        for (auto& g : groups[par]) {
+            g.off1 = g.dense ? put(blob, g.gemv) : put(blob, g.proj);
+            g.off2 = g.dense ? put(blob, g.bdf) : put(blob, g.scat);
+            g.off3 = put(blob, g.helm);
+            g.off4 = put(blob, g.fin);
         }
+        if (!blob.empty()) {
+            hipError_t e = hipMalloc((void**)&dev[par], blob.size());
+            if (e == hipSuccess) e = hipMemcpy(dev[par], blob.data(), blob.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                for (char* d : dev)
+                    if (d) hipFree(d);
+                return fail(ROM_E_DEVICE, "job table upload failed: %s", hipGetErrorString(e));
+            }
+        }
+        for (auto& g : groups[par]) g.dev = dev[par];
     }
-    for (auto& g : groups) g.dev = dev;
 
-    auto enqueue_all = [&]() -> rom_status {
-        for (int phase = 1; phase <= 4; ++phase)
-            for (const auto& g : groups) enqueue_group(g, stream, phase);
+    // step k of this call (levels h_step + k)
+    auto enqueue_all = [&](int64_t k) -> rom_status {
+        for (int phase = 1; phase <= 3; ++phase)
+            for (const auto& g : groups[k & 1]) enqueue_group(g, stream, phase);
         for (int q : batched) {
-            rom_status st = enqueue_step(ctxs[q], states[q], stream);
+            rom_status st = enqueue_step(ctxs[q], states[q], stream, states[q]->h_step + k);
             if (st != ROM_OK) return st;
         }
         HIPCHK(hipGetLastError());
@@ -1141,13 +1188,13 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
     };
 
     rom_status status = ROM_OK;
-    int64_t left = nsteps;
+    int64_t left = nsteps, k = 0;
     hipGraphExec_t gx = nullptr;
     if (left >= 2 * kGraphChunk) {
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            for (int q = 0; q < kGraphChunk && status == ROM_OK; ++q) status = enqueue_all();
+            for (int q = 0; q < kGraphChunk && status == ROM_OK; ++q) status = enqueue_all(q);
             e = hipStreamEndCapture(stream, &gr);
             if (status == ROM_OK && e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
             if (gr) hipGraphDestroy(gr);
@@ -1157,12 +1204,19 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
             e = hipGraphLaunch(gx, stream);
             if (e != hipSuccess) status = fail(ROM_E_DEVICE, "graph launch failed: %s", hipGetErrorString(e));
             left -= kGraphChunk;
+            k += kGraphChunk;
         }
     }
-    for (; status == ROM_OK && left > 0; --left) status = enqueue_all();
+    for (; status == ROM_OK && left > 0; --left, ++k) status = enqueue_all(k);
+    if (status == ROM_OK) {
+        // the newest level of every state is still to be closed
+        for (const auto& g : groups[nsteps & 1]) enqueue_group(g, stream, 4);
+        for (int q : batched) launch_close(step_args(states[q], states[q]->h_step + nsteps), stream);
+    }
     hipError_t se = hipStreamSynchronize(stream);
     if (gx) hipGraphExecDestroy(gx);
-    if (dev) hipFree(dev);
+    for (char* d : dev)
+        if (d) hipFree(d);
     if (status != ROM_OK) return status;
     if (se != hipSuccess) return fail(ROM_E_DEVICE, "rom_step_multi: %s", hipGetErrorString(se));
     long long worst = LLONG_MAX;

@@ -20,19 +20,24 @@ constexpr int kWave = 64;
 // ---------------------------------------------------------------- step state
 
 // Device pointers of one state (a batch of B trajectories of one context), plus the
-// context's Helmholtz data.  Levels are kept in rings of three slots: level n lives
-// in slot n % 3.  *step holds n, the level of the newest coefficients.
+// context's Helmholtz data, as passed to the kernels of the step from level n.  Levels
+// are kept in rings of three slots: level n lives in slot n % 3.  The step counter has
+// two slots; *step holds n, the level of the newest coefficients.
 struct StepArgs {
     int N, B;
     double inv_dt;           // 1/dt
     double* uring;           // [3][B][N] FP64 coefficients
     double* yring;           // [3][B][N] FP64 advection terms C(u)u
-    long long* step;         // newest level n
+    long long* step;         // counter slot holding the newest level n (slot n & 1)
+    long long* step_next;    // the other slot, where the update kernel stores n + 1
     long long* bad;          // first non-finite level (LLONG_MAX: none)
+    int* closep;             // 1: the energy of level n is still to be summed
     double* elog;            // [cap][B] energy per level
     long long elog_cap;
     double* rhs;             // [Bpad][Np] right-hand sides (dense stiffness; padding zero)
-    double* epart;           // [B][nblk] energy partial sums
+    double* epart;           // [2][B][enblk] per-block energy partials of a level,
+                             // parity slot (level & 1)
+    int enblk;               // blocks per trajectory of the state's update kernel
     const double* hdiag;     // [3][N] 1/(beta0_k/dt + nu A_ii) (diagonal stiffness)
     const double* hinv;      // [3][N][Np] (beta0_k/dt I + nu A)^-1, row pitch Np (dense stiffness)
     // coefficient copies in the contraction's number format for the batched kernels,
@@ -92,7 +97,7 @@ struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory
     StepArgs a;
     int blk0, nblk;
 };
-struct FinJob {            // step close (energy, health flag, counter), one state
+struct FinJob {            // closing energy sum of the newest level, one state
     StepArgs a;
     int nblk;              // energy partials per trajectory written by the update
 };
@@ -127,10 +132,10 @@ void launch_cp_scatter1_group(int dt, int mode, const Scat1Job* jobs_dev, int nj
                               hipStream_t s);
 void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s);
 void launch_helm_group(const HelmJob* jobs_dev, int njobs, int blocks, int Nmax, hipStream_t s);
-// Step close after an update kernel: energies of level n+1 from the per-block partials,
-// health flag, step counter (one block per state).
-void launch_finalize(const StepArgs& a, int nblk, hipStream_t s);
-void launch_finalize_group(const FinJob* jobs_dev, int njobs, hipStream_t s);
+// Closing energy sum of the newest level when it is still pending (after the last step
+// of a sequence; one block per state).
+void launch_close(const StepArgs& a, hipStream_t s);
+void launch_close_group(const FinJob* jobs_dev, int njobs, hipStream_t s);
 
 // Batched MFMA contraction (dense Khatri-Rao form, CP projections and CP scatter).
 struct MfmaTile { int mw, bt, target; };
