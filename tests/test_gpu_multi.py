@@ -95,3 +95,33 @@ def test_multi_rejects_bad_input(torch_gpu):
     p2, r2 = _build(SPECS[1], 61)
     with pytest.raises(rg.RomError):
         rg.rom_step_multi([r2.handle], [s.handle], 3)
+
+
+def test_multi_mixed_level_parities(torch_gpu):
+    """States whose levels have different parities share grouped launches: the kernels
+    of each step take the step-counter slots of each state's own level.  One step alone
+    for half of the states, then 131 steps together (a captured chunk launched twice,
+    then three eager steps), then one more step for the other half, must equal 132
+    steps alone, energies included."""
+    probs, roms = [], []
+    for q, spec in enumerate(SPECS):
+        p, r = _build(spec, 60 + q)
+        probs.append(p)
+        roms.append(r)
+    multi = [r.state(p.u0) for r, p in zip(roms, probs)]
+    for q in (0, 2, 4):
+        _say(f"pair {q}: one step alone (odd level)")
+        multi[q].step(1)
+    _say("rom_step_multi, 131 steps, levels of both parities")
+    rg.rom_step_multi([r.handle for r in roms], [s.handle for s in multi], 131)
+    for q in (1, 3, 5):
+        multi[q].step(1)
+    for q, (r, p) in enumerate(zip(roms, probs)):
+        _say(f"pair {q} alone, 132 steps")
+        a = r.state(p.u0)
+        a.step(132)
+        um, ym, nm = multi[q].get()
+        ua, ya, na = a.get()
+        assert nm == na == 132, (q, nm, na)
+        assert np.array_equal(um, ua), q
+        assert np.array_equal(multi[q].energy()[1], a.energy()[1]), q

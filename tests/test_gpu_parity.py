@@ -221,6 +221,30 @@ def test_not_spd_rejected(torch_gpu):
     assert ei.value.status == 1
 
 
+@pytest.mark.parametrize("dense,A,B", [(False, "diag", 1), (True, "spd", 1), (True, "diag", 1), (False, "spd", 3)])
+def test_step_splits_agree(torch_gpu, dense, A, B):
+    """The step counter has two slots and captured chunks are cached per parity of
+    their first level: 301 steps at once equal 1 + 130 + 3 + 167 steps (chunks that
+    start at odd and at even levels, eager steps between), energies included."""
+    _say(f"step splits dense={dense} A={A} B={B}")
+    p = romsynth.make_problem(40, pairs=20, eps=1e-6, nu=1e-3, dt=1e-3, A=A, batch=B, cfg=23,
+                              dense=dense, cp=not dense)
+    rom = rg.Rom.from_problem(p, dense=dense, dtype="fp64", max_batch=B)
+    a = rom.state(p.u0)
+    a.step(301)
+    b = rom.state(p.u0)
+    for k in (1, 130, 3, 167):
+        b.step(k)
+    ua, _, na = a.get()
+    ub, _, nb = b.get()
+    assert na == nb == 301
+    assert np.array_equal(ua, ub)
+    Ea, La = a.energy()
+    Eb, Lb = b.energy()
+    assert np.array_equal(La, Lb)
+    assert np.all(np.isfinite(La))
+
+
 def test_graph_and_eager_agree(torch_gpu):
     """A run that crosses graph-replay chunks equals a run of single eager steps."""
     _say("graph vs eager")
