@@ -11,6 +11,10 @@
 // per output tile the grid is ceil(M/16) x (column tiles), which fills the device for
 // the shapes of this path; A is read once per column tile (column tiles of one row tile
 // run next to each other on one XCD and share its L2).
+//
+// PAIR (the CP projections): a block takes row tile r of Bf^T and the same tile of Cf^T
+// (rows pair_off apart), so it holds s[b][r] and t[b][r] together and writes the
+// Hadamard product W[b][r] = lam_r s t (eq. tc_ap) instead of the projections.
 #include "kmfma.h"
 
 namespace rom {
@@ -26,9 +30,11 @@ struct GemmArgs {
     int gx, gy;                    // row tiles, column tiles
     const long long* kstep;        // non-null: A += (BDF order at *kstep - 1) * a_kstride
     long long a_kstride;
+    long long pair_off;            // PAIR: elements from a row of A to its partner row
+    const void* lam;               // PAIR: lam [M] (accumulation type)
 };
 
-template <int ADT, int MKD, int FN, int PF>
+template <int ADT, int MKD, int FN, int PF, bool PAIR>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     typedef MfmaT<MKD> Tr;
     typedef typename Tr::X XT;
@@ -42,8 +48,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     constexpr bool CVT = (MKD == MK_F32 && ADT != DT_F32);
     constexpr int AV = CVT ? 4 : (int)(16 / sizeof(typename Store<ADT>::T));
     static_assert(AV == VEC, "lane vectors of A and X must cover the same k");
+    constexpr int NA = PAIR ? 2 : 1;                     // A rows per lane (row and partner)
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    Acc* red = reinterpret_cast<Acc*>(smem);             // [4][FN][4][64]
+    Acc* red = reinterpret_cast<Acc*>(smem);             // [NA][4][FN][4][64]
 
     const int nwork = p.gx * p.gy;
     const int per = (nwork + 7) / 8;
@@ -72,15 +79,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
         xrow[t] = (size_t)b * p.ldx;
     }
 
-    Acc4 Z[FN];
+    Acc4 Z[NA][FN];
 #pragma unroll
-    for (int t = 0; t < FN; ++t) Z[t] = Acc4{0, 0, 0, 0};
+    for (int h = 0; h < NA; ++h)
+#pragma unroll
+        for (int t = 0; t < FN; ++t) Z[h][t] = Acc4{0, 0, 0, 0};
 
     if (ns > 0) {                                        // wavefront-uniform
         // Ring of PF steps.  Loads are unconditional: addresses past K are clamped to
         // the last lane vector of the row and their X fragments selected to zero when
         // consumed, so the loop has no branches and waits only for the slot it uses.
-        u32x4 ah[PF], al[PF], xh[PF][FN], xl[PF][FN];
+        u32x4 ah[NA][PF], al[NA][PF], xh[PF][FN], xl[PF][FN];
         int kq[PF];
         int sp = 0;                                      // producer step
         auto issue = [&](int d) {
@@ -88,13 +97,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
             int k = st * KS + g * VEC;
             kq[d] = k;
             k = k < p.K ? k : p.K - VEC;
-            if constexpr (CVT) {
-                const u32x2 h = ld_plain<8>(reinterpret_cast<const unsigned short*>(p.A) + arow + k);
-                u32x2 l = u32x2{0u, 0u};
-                if constexpr (ADT == DT_BF16X3) l = ld_plain<8>(p.Alo + arow + k);
-                ah[d] = u32x4{h[0], h[1], l[0], l[1]};
-            } else {
-                load_a<ADT, MKD, false>(p.A, p.Alo, arow + k, ah[d], al[d]);
+#pragma unroll
+            for (int h2 = 0; h2 < NA; ++h2) {
+                const size_t ar = arow + (h2 ? (size_t)p.pair_off : 0);
+                if constexpr (CVT) {
+                    const u32x2 h = ld_plain<8>(reinterpret_cast<const unsigned short*>(p.A) + ar + k);
+                    u32x2 l = u32x2{0u, 0u};
+                    if constexpr (ADT == DT_BF16X3) l = ld_plain<8>(p.Alo + ar + k);
+                    ah[h2][d] = u32x4{h[0], h[1], l[0], l[1]};
+                } else {
+                    load_a<ADT, MKD, false>(p.A, p.Alo, ar + k, ah[h2][d], al[h2][d]);
+                }
             }
 #pragma unroll
             for (int t = 0; t < FN; ++t) {
@@ -115,23 +128,27 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
             for (int d = 0; d < PF; ++d) {
                 const bool live = (q0 + d < ns) && (kq[d] < p.K);
                 const u32x4 z = u32x4{0u, 0u, 0u, 0u};
-                u32x4 av = ah[d];
-                if constexpr (CVT) {
-                    // 4 BF16 words (plus their low words) -> 4 FP32 values, hi + lo exact
-                    float f[4] = {bf16_lo_f(av[0]), bf16_hi_f(av[0]), bf16_lo_f(av[1]), bf16_hi_f(av[1])};
-                    if constexpr (ADT == DT_BF16X3) {
-                        f[0] += bf16_lo_f(av[2]);
-                        f[1] += bf16_hi_f(av[2]);
-                        f[2] += bf16_lo_f(av[3]);
-                        f[3] += bf16_hi_f(av[3]);
-                    }
-                    av = u32x4{__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]), __float_as_uint(f[3])};
-                }
 #pragma unroll
-                for (int t = 0; t < FN; ++t) {
-                    const u32x4 xv = live ? xh[d][t] : z;
-                    const u32x4 xlv = live ? xl[d][t] : z;
-                    mfma_step<MKD>(Z[t], av, al[d], xv, xlv);
+                for (int h2 = 0; h2 < NA; ++h2) {
+                    u32x4 av = ah[h2][d];
+                    if constexpr (CVT) {
+                        // 4 BF16 words (plus their low words) -> 4 FP32 values, hi + lo exact
+                        float f[4] = {bf16_lo_f(av[0]), bf16_hi_f(av[0]), bf16_lo_f(av[1]), bf16_hi_f(av[1])};
+                        if constexpr (ADT == DT_BF16X3) {
+                            f[0] += bf16_lo_f(av[2]);
+                            f[1] += bf16_hi_f(av[2]);
+                            f[2] += bf16_lo_f(av[3]);
+                            f[3] += bf16_hi_f(av[3]);
+                        }
+                        av = u32x4{__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]),
+                                   __float_as_uint(f[3])};
+                    }
+#pragma unroll
+                    for (int t = 0; t < FN; ++t) {
+                        const u32x4 xv = live ? xh[d][t] : z;
+                        const u32x4 xlv = live ? xl[d][t] : z;
+                        mfma_step<MKD>(Z[h2][t], av, al[h2][d], xv, xlv);
+                    }
                 }
                 issue(d);
                 // nothing crosses: later slots' arithmetic hoisted above these loads
@@ -141,11 +158,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
         }
     }
 
-    // ---- add the 4 wavefront tiles (fixed order) and write Y
+    // ---- add the 4 wavefront tiles (fixed order) and write Y (PAIR: W = lam s t)
+    constexpr int RS = 4 * FN * 4 * 64;                  // one A row set of red
 #pragma unroll
-    for (int t = 0; t < FN; ++t)
+    for (int h = 0; h < NA; ++h)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) red[((w * FN + t) * 4 + v) * 64 + lane] = Z[t][v];
+        for (int t = 0; t < FN; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[h * RS + ((w * FN + t) * 4 + v) * 64 + lane] = Z[h][t][v];
     __syncthreads();
     Acc* out = reinterpret_cast<Acc*>(p.Y);
     for (int e = threadIdx.x; e < 256 * FN; e += 256) {
@@ -154,11 +174,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
         const int gg = MKD == MK_F64 ? (rr & 3) : (rr >> 2);
         const int v = MKD == MK_F64 ? (rr >> 2) : (rr & 3);
         const int ln = gg * 16 + cc;
-        Acc sum = red[(t * 4 + v) * 64 + ln];
+        Acc sum[NA];
 #pragma unroll
-        for (int w2 = 1; w2 < 4; ++w2) sum += red[((w2 * FN + t) * 4 + v) * 64 + ln];
+        for (int h = 0; h < NA; ++h) {
+            sum[h] = red[h * RS + (t * 4 + v) * 64 + ln];
+#pragma unroll
+            for (int w2 = 1; w2 < 4; ++w2) sum[h] += red[h * RS + ((w2 * FN + t) * 4 + v) * 64 + ln];
+        }
         const int row = rowbase + rr, b = b0 + cl;
-        if (row < p.M && b < p.Bpad) out[(size_t)b * p.M + row] = sum;
+        if (row < p.M && b < p.Bpad) {
+            if constexpr (PAIR) out[(size_t)b * p.M + row] = reinterpret_cast<const Acc*>(p.lam)[row] * sum[0] * sum[1];
+            else out[(size_t)b * p.M + row] = sum[0];
+        }
     }
 }
 
@@ -189,12 +216,12 @@ GemmPlan gemm_plan(int M, int Bpad, int variant) {
     return pl;
 }
 
-template <int ADT, int MKD>
+template <int ADT, int MKD, bool PAIR = false>
 static void gemm_go(const GemmArgs& a, const GemmPlan& pl, hipStream_t s) {
-    const size_t lds = (size_t)1024 * pl.fn * sizeof(typename MfmaT<MKD>::Acc);
-    if (pl.fn == 4) hipLaunchKernelGGL((k_gemm<ADT, MKD, 4, 4>), dim3(pl.blocks), dim3(256), lds, s, a);
-    else if (pl.fn == 2) hipLaunchKernelGGL((k_gemm<ADT, MKD, 2, 6>), dim3(pl.blocks), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((k_gemm<ADT, MKD, 1, 8>), dim3(pl.blocks), dim3(256), lds, s, a);
+    const size_t lds = (size_t)1024 * pl.fn * sizeof(typename MfmaT<MKD>::Acc) * (PAIR ? 2 : 1);
+    if (pl.fn == 4) hipLaunchKernelGGL((k_gemm<ADT, MKD, 4, 4, PAIR>), dim3(pl.blocks), dim3(256), lds, s, a);
+    else if (pl.fn == 2) hipLaunchKernelGGL((k_gemm<ADT, MKD, 2, 6, PAIR>), dim3(pl.blocks), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_gemm<ADT, MKD, 1, 8, PAIR>), dim3(pl.blocks), dim3(256), lds, s, a);
 }
 
 static GemmArgs gemm_args(const GemmPlan& pl, const void* A, const void* Alo, long long lda, const void* X,
@@ -225,6 +252,27 @@ void launch_gemm_proj(int dt, const GemmPlan& pl, const void* BCt, const void* B
         case DT_F32: gemm_go<DT_F32, MK_F32>(a, pl, s); break;
         case DT_BF16: gemm_go<DT_BF16, MK_BF16>(a, pl, s); break;
         default: gemm_go<DT_BF16X3, MK_BF16X3>(a, pl, s); break;
+    }
+}
+
+// CP projections and their Hadamard product in one pass: W[b][r] = lam_r (Bf^T u_b)_r
+// (Cf^T u_b)_r over the row pairs (r, Rp + r) of [Bf|Cf]^T; W [Bpad][Rp] in the
+// accumulation type.  The plan's column-tile width is kept, its row tiles are those of
+// Rp rows.
+void launch_gemm_proj_pair(int dt, const GemmPlan& pl0, const void* BCt, const void* BCt_lo, int Np, int Rp,
+                           int Bpad, const void* X, const void* Xlo, const void* lam, void* W, hipStream_t s) {
+    GemmPlan pl = pl0;
+    pl.gx = (Rp + 15) / 16;
+    pl.gy = Bpad / (16 * pl.fn);
+    pl.blocks = (pl.gx * pl.gy + 7) / 8 * 8;
+    GemmArgs a = gemm_args(pl, BCt, BCt_lo, Np, X, Xlo, Np, W, Rp, Np, Bpad);
+    a.pair_off = (long long)Rp * Np;
+    a.lam = lam;
+    switch (dt) {
+        case DT_F64: gemm_go<DT_F64, MK_F64, true>(a, pl, s); break;
+        case DT_F32: gemm_go<DT_F32, MK_F32, true>(a, pl, s); break;
+        case DT_BF16: gemm_go<DT_BF16, MK_BF16, true>(a, pl, s); break;
+        default: gemm_go<DT_BF16X3, MK_BF16X3, true>(a, pl, s); break;
     }
 }
 

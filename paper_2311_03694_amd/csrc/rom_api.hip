@@ -160,6 +160,20 @@ void launch_scatter(rom_ctx c, const SkinnyPlan& sp, int Bpad, const void* W, vo
     else launch_gemm_scatter(c->dtype, sp.g, c->Af, c->Af_lo, c->N, c->Rp, Bpad, W, Y, s);
 }
 
+// Batched CP term Y = Af (lam . Bf^T U . Cf^T U) (eq. tc_ap).  On the skinny GEMM the
+// projection blocks pair the rows of Bf^T and Cf^T and write W themselves; the LDS-tile
+// engine leaves partial projections that a separate pass turns into W.
+void launch_cp_batched(rom_ctx c, const SkinnyPlan& pp, const SkinnyPlan& ps, int Bpad, int B, const void* X,
+                       const void* Xlo, void* P, void* W, void* Y, hipStream_t s) {
+    if (pp.engine == 0) {
+        launch_gemm_proj_pair(c->dtype, pp.g, c->BCt, c->BCt_lo, c->Np, c->Rp, Bpad, X, Xlo, c->lam, W, s);
+    } else {
+        launch_proj(c, pp, Bpad, X, Xlo, P, s);
+        launch_hadamard(c->dtype, P, pp.nsplit, Bpad, B, c->Rp, c->lam, W, s);
+    }
+    launch_scatter(c, ps, Bpad, W, Y, s);
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Contraction workspace of a batch of B (shared by the states of a context and by
@@ -517,10 +531,8 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
                                  a.ucv_lo, a.uj, ws + p.part_off, stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.pd.nsplit, p.Bpad, diag, stream);
         } else {
-            launch_proj(c, p.pp, p.Bpad, a.ucv, a.ucv_lo, ws + p.part2_off, stream);
-            launch_hadamard(c->dtype, ws + p.part2_off, p.pp.nsplit, p.Bpad, s->B, c->Rp, c->lam, ws + p.w_off,
-                            stream);
-            launch_scatter(c, p.ps, p.Bpad, ws + p.w_off, ws + p.part_off, stream);
+            launch_cp_batched(c, p.pp, p.ps, p.Bpad, s->B, a.ucv, a.ucv_lo, ws + p.part2_off, ws + p.w_off,
+                              ws + p.part_off, stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.ps.nsplit, p.Bpad, diag, stream);
         }
     }
@@ -580,10 +592,8 @@ static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, 
             launch_dense_batched(c->dtype, p.pd, c->C, c->Clo, c->Ct, c->Ct_lo, c->N, c->Np, p.Bpad, a.ucv, a.ucv_lo,
                                  a.uj, ws + p.part_off, c->stream);
         } else {
-            launch_proj(c, p.pp, p.Bpad, a.ucv, a.ucv_lo, ws + p.part2_off, c->stream);
-            launch_hadamard(c->dtype, ws + p.part2_off, p.pp.nsplit, p.Bpad, batch, c->Rp, c->lam, ws + p.w_off,
-                            c->stream);
-            launch_scatter(c, p.ps, p.Bpad, ws + p.w_off, ws + p.part_off, c->stream);
+            launch_cp_batched(c, p.pp, p.ps, p.Bpad, batch, a.ucv, a.ucv_lo, ws + p.part2_off, ws + p.w_off,
+                              ws + p.part_off, c->stream);
         }
     };
     if (!kernel_us) {
