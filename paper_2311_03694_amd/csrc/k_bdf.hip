@@ -51,7 +51,7 @@ __device__ __forceinline__ void bdf_partials_body(const StepArgs& a, long long n
     }
     if (DIAG) {
         const double s = block_sum(e, red);
-        if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * nbx + bx] = s;
+        if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * a.enmax + bx] = s;
     }
 }
 
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __r
                                                       int nchunk, int pbstride) {
     if constexpr (DIAG) {
         if ((int)blockIdx.y == a.B) {
-            if (blockIdx.x == 0) close_and_advance(a, *a.step);
+            if (blockIdx.x == 0) close_and_advance(a, *a.step, (int)gridDim.x);
             return;
         }
         bdf_partials_body<ACC, true>(a, *a.step, part, nchunk, pbstride, blockIdx.x, blockIdx.y, gridDim.x);
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_bdf_group(const BdfJob* __restrict__ jo
     const int blk = (int)blockIdx.x - jb.blk0;
     const long long n = *jb.a.step;
     if constexpr (DIAG) {
-        if (blk == 0) close_and_advance(jb.a, n);
+        if (blk == 0) close_and_advance(jb.a, n, jb.nblk);
     }
     bdf_partials_body<ACC, DIAG>(jb.a, n, reinterpret_cast<const ACC*>(jb.part), jb.nchunk, jb.pb, blk, 0, jb.nblk);
 }
@@ -145,7 +145,7 @@ __device__ __forceinline__ void helm_gemv_body(const StepArgs& a, long long n, i
 template <bool EVEN>
 __global__ __launch_bounds__(256) void k_helm_gemv(StepArgs a) {
     if (blockIdx.x == gridDim.x - 1) {
-        close_and_advance(a, *a.step);
+        close_and_advance(a, *a.step, (int)gridDim.x - 1);
         return;
     }
     helm_gemv_body<EVEN>(a, *a.step, blockIdx.x);
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_helm_group(const HelmJob* __restrict__ 
     const HelmJob& jb = jobs[p];
     const int blk = (int)blockIdx.x - jb.blk0;
     const long long n = *jb.a.step;
-    if (blk == 0) close_and_advance(jb.a, n);
+    if (blk == 0) close_and_advance(jb.a, n, jb.nblk);
     if (jb.a.N % 2 == 0) helm_gemv_body<true>(jb.a, n, blk);
     else helm_gemv_body<false>(jb.a, n, blk);
 }
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_helm_group(const HelmJob* __restrict__ 
 __global__ __launch_bounds__(256) void k_helm_finish(StepArgs a, const double* __restrict__ part, int nsplit) {
     __shared__ double red[4];
     if ((int)blockIdx.y == a.B) {
-        if (blockIdx.x == 0) close_and_advance(a, *a.step);
+        if (blockIdx.x == 0) close_and_advance(a, *a.step, (int)gridDim.x);
         return;
     }
     const long long n = *a.step;
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_helm_finish(StepArgs a, const double* _
         e = u * u;
     }
     const double s = block_sum(e, red);
-    if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * a.enmax + blockIdx.x] = s;
 }
 
 // Sums the energy of the newest level if it is still pending (the last level of a

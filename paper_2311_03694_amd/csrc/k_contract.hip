@@ -168,7 +168,7 @@ template <int DT, int V, int U, int MODE>
 __global__ __launch_bounds__(256) void k_cp_scatter1(Scat1Job jb, double* y_out) {
     if constexpr (MODE == 1) {
         if (blockIdx.x == gridDim.x - 1) {
-            close_and_advance(jb.a, *jb.a.step);
+            close_and_advance(jb.a, *jb.a.step, (int)gridDim.x - 1);
             return;
         }
         cp_scatter1_body<DT, V, U, MODE>(jb, y_out, blockIdx.x, *jb.a.step);
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_cp_scatter1_group(const Scat1Job* __res
     long long n = 0;
     if constexpr (MODE != 0) n = *jb.a.step;
     if constexpr (MODE == 1) {
-        if (blk == 0) close_and_advance(jb.a, n);
+        if (blk == 0) close_and_advance(jb.a, n, jb.nblk);
     }
     cp_scatter1_body<DT, V, U, MODE>(jb, nullptr, blk, n);
 }

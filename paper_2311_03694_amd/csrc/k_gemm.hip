@@ -12,10 +12,19 @@
 // the shapes of this path; A is read once per column tile (column tiles of one row tile
 // run next to each other on one XCD and share its L2).
 //
-// PAIR (the CP projections): a block takes row tile r of Bf^T and the same tile of Cf^T
-// (rows pair_off apart), so it holds s[b][r] and t[b][r] together and writes the
-// Hadamard product W[b][r] = lam_r s t (eq. tc_ap) instead of the projections.
+// Epilogues (EPI):
+//  * PLAIN writes Y.
+//  * PAIR (the CP projections): a block takes row tile r of Bf^T and the same tile of
+//    Cf^T (rows pair_off apart), so it holds s[b][r] and t[b][r] together and writes the
+//    Hadamard product W[b][r] = lam_r s t (eq. tc_ap) instead of the projections.
+//  * UPDATE / RHS (the CP scatter of a step): each output y^n[b][i] goes straight into
+//    the BDFk/EXTk right-hand side of eq. nse_d1; UPDATE (diagonal stiffness) also
+//    solves for u^{n+1}, stores it and leaves the energy of its 16 rows per trajectory,
+//    and one extra block closes the previous level and advances the step counter (this
+//    kernel is then the step's update kernel); RHS stores the right-hand side for the
+//    Helmholtz apply.
 #include "kmfma.h"
+#include "kstep.h"
 
 namespace rom {
 
@@ -32,10 +41,14 @@ struct GemmArgs {
     long long a_kstride;
     long long pair_off;            // PAIR: elements from a row of A to its partner row
     const void* lam;               // PAIR: lam [M] (accumulation type)
+    StepArgs st;                   // UPDATE, RHS: the state of the step (M = N rows)
 };
 
-template <int ADT, int MKD, int FN, int PF, bool PAIR>
+enum { EPI_PLAIN = 0, EPI_PAIR = 1, EPI_UPDATE = 2, EPI_RHS = 3 };
+
+template <int ADT, int MKD, int FN, int PF, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
+    constexpr bool PAIR = (EPI == EPI_PAIR);
     typedef MfmaT<MKD> Tr;
     typedef typename Tr::X XT;
     typedef typename Tr::Acc Acc;
@@ -52,10 +65,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     Acc* red = reinterpret_cast<Acc*>(smem);             // [NA][4][FN][4][64]
 
-    const int nwork = p.gx * p.gy;
+    const int nwork = p.gx * p.gy + (EPI == EPI_UPDATE ? 1 : 0);
     const int per = (nwork + 7) / 8;
     const int wi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (wi >= nwork) return;
+    if constexpr (EPI == EPI_UPDATE) {
+        if (wi == nwork - 1) {                           // the step-closing block
+            close_and_advance(p.st, *p.st.step, p.gx);
+            return;
+        }
+    }
+    const long long n = EPI >= EPI_UPDATE ? *p.st.step : 0;
     const int by = wi % p.gy, bx = wi / p.gy;
 
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
@@ -182,9 +202,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
             for (int w2 = 1; w2 < 4; ++w2) sum[h] += red[h * RS + ((w2 * FN + t) * 4 + v) * 64 + ln];
         }
         const int row = rowbase + rr, b = b0 + cl;
-        if (row < p.M && b < p.Bpad) {
-            if constexpr (PAIR) out[(size_t)b * p.M + row] = reinterpret_cast<const Acc*>(p.lam)[row] * sum[0] * sum[1];
-            else out[(size_t)b * p.M + row] = sum[0];
+        if constexpr (EPI <= EPI_PAIR) {
+            if (row < p.M && b < p.Bpad) {
+                if constexpr (PAIR) out[(size_t)b * p.M + row] = reinterpret_cast<const Acc*>(p.lam)[row] * sum[0] * sum[1];
+                else out[(size_t)b * p.M + row] = sum[0];
+            }
+        } else {
+            const StepArgs& a = p.st;
+            const int k = bdf_order(n);
+            const BdfCoef c = bdf_coef(k);
+            double ev = 0.0;
+            if (row < p.M && b < a.B) {
+                const double rhs = bdf_rhs_point(a, n, c, k, b, row, (double)sum[0]);
+                if constexpr (EPI == EPI_UPDATE) {
+                    const double un = rhs * a.hdiag[(size_t)(k - 1) * a.N + row];
+                    write_level(a, n + 1, b, row, un);
+                    ev = un * un;
+                } else {
+                    a.rhs[(size_t)b * a.Np + row] = rhs;
+                }
+            }
+            if constexpr (EPI == EPI_UPDATE) {
+                // the tile's 16 rows of trajectory b sit in 16 consecutive lanes
+                ev += __shfl_xor(ev, 8, 16);
+                ev += __shfl_xor(ev, 4, 16);
+                ev += __shfl_xor(ev, 2, 16);
+                ev += __shfl_xor(ev, 1, 16);
+                if (rr == 0 && b < a.B) epart_of(a, n + 1)[(size_t)b * a.enmax + bx] = ev;
+            }
         }
     }
 }
@@ -216,12 +261,12 @@ GemmPlan gemm_plan(int M, int Bpad, int variant) {
     return pl;
 }
 
-template <int ADT, int MKD, bool PAIR = false>
+template <int ADT, int MKD, int EPI = EPI_PLAIN>
 static void gemm_go(const GemmArgs& a, const GemmPlan& pl, hipStream_t s) {
-    const size_t lds = (size_t)1024 * pl.fn * sizeof(typename MfmaT<MKD>::Acc) * (PAIR ? 2 : 1);
-    if (pl.fn == 4) hipLaunchKernelGGL((k_gemm<ADT, MKD, 4, 4, PAIR>), dim3(pl.blocks), dim3(256), lds, s, a);
-    else if (pl.fn == 2) hipLaunchKernelGGL((k_gemm<ADT, MKD, 2, 6, PAIR>), dim3(pl.blocks), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((k_gemm<ADT, MKD, 1, 8, PAIR>), dim3(pl.blocks), dim3(256), lds, s, a);
+    const size_t lds = (size_t)1024 * pl.fn * sizeof(typename MfmaT<MKD>::Acc) * (EPI == EPI_PAIR ? 2 : 1);
+    if (pl.fn == 4) hipLaunchKernelGGL((k_gemm<ADT, MKD, 4, 4, EPI>), dim3(pl.blocks), dim3(256), lds, s, a);
+    else if (pl.fn == 2) hipLaunchKernelGGL((k_gemm<ADT, MKD, 2, 6, EPI>), dim3(pl.blocks), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_gemm<ADT, MKD, 1, 8, EPI>), dim3(pl.blocks), dim3(256), lds, s, a);
 }
 
 static GemmArgs gemm_args(const GemmPlan& pl, const void* A, const void* Alo, long long lda, const void* X,
@@ -269,10 +314,10 @@ void launch_gemm_proj_pair(int dt, const GemmPlan& pl0, const void* BCt, const v
     a.pair_off = (long long)Rp * Np;
     a.lam = lam;
     switch (dt) {
-        case DT_F64: gemm_go<DT_F64, MK_F64, true>(a, pl, s); break;
-        case DT_F32: gemm_go<DT_F32, MK_F32, true>(a, pl, s); break;
-        case DT_BF16: gemm_go<DT_BF16, MK_BF16, true>(a, pl, s); break;
-        default: gemm_go<DT_BF16X3, MK_BF16X3, true>(a, pl, s); break;
+        case DT_F64: gemm_go<DT_F64, MK_F64, EPI_PAIR>(a, pl, s); break;
+        case DT_F32: gemm_go<DT_F32, MK_F32, EPI_PAIR>(a, pl, s); break;
+        case DT_BF16: gemm_go<DT_BF16, MK_BF16, EPI_PAIR>(a, pl, s); break;
+        default: gemm_go<DT_BF16X3, MK_BF16X3, EPI_PAIR>(a, pl, s); break;
     }
 }
 
@@ -286,6 +331,32 @@ void launch_gemm_scatter(int dt, const GemmPlan& pl, const void* Af, const void*
         case DT_F32: gemm_go<DT_F32, MK_F32>(a, pl, s); break;
         case DT_BF16: gemm_go<DT_BF16, MK_F32>(a, pl, s); break;
         default: gemm_go<DT_BF16X3, MK_F32>(a, pl, s); break;
+    }
+}
+
+// CP scatter of a step: y^n = Af W goes straight into the BDF right-hand side; with a
+// diagonal stiffness (diag = 1) the kernel also solves for u^{n+1} and closes the step
+// (one extra block), else it stores the right-hand side for the Helmholtz apply.
+void launch_gemm_scatter_step(int dt, const GemmPlan& pl0, const void* Af, const void* Af_lo, int N, int Rp,
+                              int Bpad, const void* W, const StepArgs& st, int diag, hipStream_t s) {
+    GemmPlan pl = pl0;
+    if (diag) pl.blocks = (pl.gx * pl.gy + 1 + 7) / 8 * 8;
+    GemmArgs a = gemm_args(pl, Af, Af_lo, Rp, W, nullptr, Rp, nullptr, N, Rp, Bpad);
+    a.st = st;
+    if (diag) {
+        switch (dt) {
+            case DT_F64: gemm_go<DT_F64, MK_F64, EPI_UPDATE>(a, pl, s); break;
+            case DT_F32: gemm_go<DT_F32, MK_F32, EPI_UPDATE>(a, pl, s); break;
+            case DT_BF16: gemm_go<DT_BF16, MK_F32, EPI_UPDATE>(a, pl, s); break;
+            default: gemm_go<DT_BF16X3, MK_F32, EPI_UPDATE>(a, pl, s); break;
+        }
+    } else {
+        switch (dt) {
+            case DT_F64: gemm_go<DT_F64, MK_F64, EPI_RHS>(a, pl, s); break;
+            case DT_F32: gemm_go<DT_F32, MK_F32, EPI_RHS>(a, pl, s); break;
+            case DT_BF16: gemm_go<DT_BF16, MK_F32, EPI_RHS>(a, pl, s); break;
+            default: gemm_go<DT_BF16X3, MK_F32, EPI_RHS>(a, pl, s); break;
+        }
     }
 }
 

@@ -80,9 +80,10 @@ __device__ __forceinline__ void write_level(const StepArgs& a, long long n1, int
 //    slot while the kernel writes the other.  closep marks a level whose sum is still
 //    pending; a closing kernel sums the last level of a sequence of steps.
 
-// Energy partials of level n1: [B][enblk] in slot n1 & 1.
+// Energy partials of level n1: [B][enmax] in slot n1 & 1 (the first ecount[n1 & 1]
+// of each trajectory are written).
 __device__ __forceinline__ double* epart_of(const StepArgs& a, long long n1) {
-    return a.epart + (size_t)(n1 & 1) * a.B * a.enblk;
+    return a.epart + (size_t)(n1 & 1) * a.B * a.enmax;
 }
 
 // Whole block: if level n's energy is pending, sum its partials in a fixed order
@@ -91,9 +92,10 @@ __device__ __forceinline__ void close_level(const StepArgs& a, long long n) {
     __shared__ double cred[4];
     if (*a.closep == 0) return;
     const double* ep = epart_of(a, n);
+    const int cnt = a.ecount[n & 1];
     if (a.B == 1) {
         double s = 0.0;
-        for (int q = threadIdx.x; q < a.enblk; q += blockDim.x) s += ep[q];
+        for (int q = threadIdx.x; q < cnt; q += blockDim.x) s += ep[q];
         s = block_sum(s, cred);
         if (threadIdx.x == 0) {
             const double e = 0.5 * s;
@@ -102,10 +104,10 @@ __device__ __forceinline__ void close_level(const StepArgs& a, long long n) {
         }
     } else {
         for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
-            const double* eb = ep + (size_t)b * a.enblk;
+            const double* eb = ep + (size_t)b * a.enmax;
             double s = 0.0;
 #pragma unroll 8
-            for (int q = 0; q < a.enblk; ++q) s += eb[q];
+            for (int q = 0; q < cnt; ++q) s += eb[q];
             const double e = 0.5 * s;
             if (n < a.elog_cap) a.elog[(size_t)n * a.B + b] = e;
             if (!isfinite(e)) atomicMin(a.bad, n);
@@ -114,11 +116,13 @@ __device__ __forceinline__ void close_level(const StepArgs& a, long long n) {
 }
 
 // One block of each update kernel (whole block): closes level n, marks level n+1 as
-// pending and advances the counter.
-__device__ __forceinline__ void close_and_advance(const StepArgs& a, long long n) {
+// pending with the number of partials per trajectory its kernel writes, and advances
+// the counter.
+__device__ __forceinline__ void close_and_advance(const StepArgs& a, long long n, int nblk) {
     close_level(a, n);
     __syncthreads();                      // every thread has read closep
     if (threadIdx.x == 0) {
+        a.ecount[(n + 1) & 1] = nblk;
         *a.closep = 1;
         *a.step_next = n + 1;
     }

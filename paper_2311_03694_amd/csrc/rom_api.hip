@@ -162,16 +162,24 @@ void launch_scatter(rom_ctx c, const SkinnyPlan& sp, int Bpad, const void* W, vo
 
 // Batched CP term Y = Af (lam . Bf^T U . Cf^T U) (eq. tc_ap).  On the skinny GEMM the
 // projection blocks pair the rows of Bf^T and Cf^T and write W themselves; the LDS-tile
-// engine leaves partial projections that a separate pass turns into W.
-void launch_cp_batched(rom_ctx c, const SkinnyPlan& pp, const SkinnyPlan& ps, int Bpad, int B, const void* X,
-                       const void* Xlo, void* P, void* W, void* Y, hipStream_t s) {
+// engine leaves partial projections that a separate pass turns into W.  With step
+// arguments and the skinny GEMM for the scatter, the scatter also forms the step's
+// right-hand side (and with a diagonal stiffness the update and step close); the
+// return value says so.  Otherwise Y holds the scatter's partial sums.
+bool launch_cp_batched(rom_ctx c, const SkinnyPlan& pp, const SkinnyPlan& ps, int Bpad, int B, const void* X,
+                       const void* Xlo, void* P, void* W, void* Y, const StepArgs* sa, hipStream_t s) {
     if (pp.engine == 0) {
         launch_gemm_proj_pair(c->dtype, pp.g, c->BCt, c->BCt_lo, c->Np, c->Rp, Bpad, X, Xlo, c->lam, W, s);
     } else {
         launch_proj(c, pp, Bpad, X, Xlo, P, s);
         launch_hadamard(c->dtype, P, pp.nsplit, Bpad, B, c->Rp, c->lam, W, s);
     }
+    if (sa && ps.engine == 0) {
+        launch_gemm_scatter_step(c->dtype, ps.g, c->Af, c->Af_lo, c->N, c->Rp, Bpad, W, *sa, c->diagA ? 1 : 0, s);
+        return true;
+    }
     launch_scatter(c, ps, Bpad, W, Y, s);
+    return false;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -531,9 +539,9 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
                                  a.ucv_lo, a.uj, ws + p.part_off, stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.pd.nsplit, p.Bpad, diag, stream);
         } else {
-            launch_cp_batched(c, p.pp, p.ps, p.Bpad, s->B, a.ucv, a.ucv_lo, ws + p.part2_off, ws + p.w_off,
-                              ws + p.part_off, stream);
-            launch_bdf_from_partials(a, accf, ws + p.part_off, p.ps.nsplit, p.Bpad, diag, stream);
+            if (!launch_cp_batched(c, p.pp, p.ps, p.Bpad, s->B, a.ucv, a.ucv_lo, ws + p.part2_off, ws + p.w_off,
+                                   ws + p.part_off, &a, stream))
+                launch_bdf_from_partials(a, accf, ws + p.part_off, p.ps.nsplit, p.Bpad, diag, stream);
         }
     }
     if (!c->diagA) {
@@ -593,7 +601,7 @@ static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, 
                                  a.uj, ws + p.part_off, c->stream);
         } else {
             launch_cp_batched(c, p.pp, p.ps, p.Bpad, batch, a.ucv, a.ucv_lo, ws + p.part2_off, ws + p.w_off,
-                              ws + p.part_off, c->stream);
+                              ws + p.part_off, nullptr, c->stream);
         }
     };
     if (!kernel_us) {
@@ -733,20 +741,17 @@ rom_status reset_counters(rom_state s, long long step) {
     const int none = 0;
     HIPCHK(hipMemcpyAsync(s->cnt, both, sizeof(both), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(s->a.bad, &big, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    const int nocount[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(s->a.closep, &none, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(s->a.ecount, nocount, sizeof(nocount), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return ROM_OK;
 }
 
-// Blocks per trajectory of the kernel that writes level n+1 of a state (the energy
-// partials it leaves): the diagonal update of the partial sums (256 rows a block),
-// the single-trajectory Helmholtz apply or fused CP update (4 rows a block), or the
-// batched Helmholtz finish (256 rows a block).
-int update_blocks(rom_ctx c, int B) {
-    if (B > 1) return (c->N + 255) / 256;
-    if (c->dense && c->diagA) return (c->N + 255) / 256;
-    return (c->N + 3) / 4;
-}
+// Room for energy partials per trajectory: the most blocks per trajectory of any kernel
+// that can write level n+1 of a state (4 rows a block for one trajectory, 16 rows a
+// block for batches).
+int energy_slots(rom_ctx c, int B) { return B > 1 ? (c->N + 15) / 16 : (c->N + 3) / 4; }
 
 }  // namespace
 
@@ -794,8 +799,9 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(dmalloc((void**)&a.uring, sizeof(double) * 3 * BN, &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.yring, sizeof(double) * 3 * BN, &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.rhs, sizeof(double) * s->Bpad * c->Np, &s->bytes, &s->allocs));
-    a.enblk = update_blocks(c, batch);
-    TRY(dmalloc((void**)&a.epart, sizeof(double) * 2 * B * a.enblk, &s->bytes, &s->allocs));
+    a.enmax = energy_slots(c, batch);
+    TRY(dmalloc((void**)&a.epart, sizeof(double) * 2 * B * a.enmax, &s->bytes, &s->allocs));
+    TRY(dmalloc((void**)&a.ecount, 2 * sizeof(int), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&s->cnt, 2 * sizeof(long long), &s->bytes, &s->allocs));
     a.step = s->cnt;
     a.step_next = s->cnt + 1;
@@ -1159,7 +1165,7 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
         // the newest one
         FinJob fj{};
         fj.a = sa;
-        fj.nblk = sa.enblk;
+        fj.nblk = sa.enmax;
         g->fin.push_back(fj);
         if (c->Np > g->Npmax) g->Npmax = c->Np;
         if (c->N > g->Nmax) g->Nmax = c->N;

@@ -35,9 +35,10 @@ struct StepArgs {
     double* elog;            // [cap][B] energy per level
     long long elog_cap;
     double* rhs;             // [Bpad][Np] right-hand sides (dense stiffness; padding zero)
-    double* epart;           // [2][B][enblk] per-block energy partials of a level,
+    double* epart;           // [2][B][enmax] per-block energy partials of a level,
                              // parity slot (level & 1)
-    int enblk;               // blocks per trajectory of the state's update kernel
+    int* ecount;             // [2] partials per trajectory of a level, same parity slots
+    int enmax;               // capacity per trajectory (at least any update kernel's blocks)
     const double* hdiag;     // [3][N] 1/(beta0_k/dt + nu A_ii) (diagonal stiffness)
     const double* hinv;      // [3][N][Np] (beta0_k/dt I + nu A)^-1, row pitch Np (dense stiffness)
     // coefficient copies in the contraction's number format for the batched kernels,
@@ -241,6 +242,8 @@ void launch_gemm_proj(int dt, const GemmPlan& pl, const void* BCt, const void* B
                       const void* X, const void* Xlo, void* P, hipStream_t s);
 void launch_gemm_proj_pair(int dt, const GemmPlan& pl, const void* BCt, const void* BCt_lo, int Np, int Rp,
                            int Bpad, const void* X, const void* Xlo, const void* lam, void* W, hipStream_t s);
+void launch_gemm_scatter_step(int dt, const GemmPlan& pl, const void* Af, const void* Af_lo, int N, int Rp,
+                              int Bpad, const void* W, const StepArgs& st, int diag, hipStream_t s);
 void launch_gemm_scatter(int dt, const GemmPlan& pl, const void* Af, const void* Af_lo, int N, int Rp, int Bpad,
                          const void* W, void* Y, hipStream_t s);
 void launch_gemm_helm(const GemmPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
