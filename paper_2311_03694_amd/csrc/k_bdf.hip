@@ -161,41 +161,6 @@ __global__ __launch_bounds__(256) void k_helm_group(const HelmJob* __restrict__ 
     else helm_gemv_body<false>(jb.a, n, blk);
 }
 
-// Dense stiffness, batch: the FP64 MFMA kernel writes partial sums
-// part[z][b][i] of U^{n+1}[b][i] = sum_m Hinv_k[i][m] rhs[b][m]; this kernel adds them
-// in z order, stores level n+1, and reduces energies and the health flag.
-// Grid (ceil(N/256), B + 1): block 0 of the last row closes the previous level and
-// advances the counter.
-__global__ __launch_bounds__(256) void k_helm_finish(StepArgs a, const double* __restrict__ part, int nsplit) {
-    __shared__ double red[4];
-    if ((int)blockIdx.y == a.B) {
-        if (blockIdx.x == 0) close_and_advance(a, *a.step, (int)gridDim.x);
-        return;
-    }
-    const long long n = *a.step;
-    const int b = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double e = 0.0;
-    if (i < a.N) {
-        const size_t zs = (size_t)a.Bpad * a.N;
-        const double* pp = part + (size_t)b * a.N + i;
-        double u = 0.0;
-        int z = 0;
-        for (; z + 8 <= nsplit; z += 8) {
-            double v[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = pp[(size_t)(z + q) * zs];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) u += v[q];
-        }
-        for (; z < nsplit; ++z) u += pp[(size_t)z * zs];
-        write_level(a, n + 1, b, i, u);
-        e = u * u;
-    }
-    const double s = block_sum(e, red);
-    if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * a.enmax + blockIdx.x] = s;
-}
-
 // Sums the energy of the newest level if it is still pending (the last level of a
 // sequence of steps; the update kernels close every earlier one).  One block per state.
 __device__ __forceinline__ void close_body(const StepArgs& a) {
@@ -281,10 +246,6 @@ void launch_helm_apply(const StepArgs& a, hipStream_t s) {
     const unsigned blocks = (unsigned)((a.N + 3) / 4 + 1);
     if (a.N % 2 == 0) hipLaunchKernelGGL(k_helm_gemv<true>, dim3(blocks), dim3(256), lds, s, a);
     else hipLaunchKernelGGL(k_helm_gemv<false>, dim3(blocks), dim3(256), lds, s, a);
-}
-
-void launch_helm_finish(const StepArgs& a, const double* part, int nsplit, hipStream_t s) {
-    hipLaunchKernelGGL(k_helm_finish, dim3((a.N + 255) / 256, a.B + 1), dim3(256), 0, s, a, part, nsplit);
 }
 
 void launch_prep_ucv(const StepArgs& a, const double* u_src, hipStream_t s) {

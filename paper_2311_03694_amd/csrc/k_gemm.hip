@@ -23,6 +23,8 @@
 //    and one extra block closes the previous level and advances the step counter (this
 //    kernel is then the step's update kernel); RHS stores the right-hand side for the
 //    Helmholtz apply.
+//  * FINISH (the batched Helmholtz apply of a step): the outputs are u^{n+1}; they are
+//    stored with their energy partials, and one extra block closes the step.
 #include "kmfma.h"
 #include "kstep.h"
 
@@ -44,11 +46,12 @@ struct GemmArgs {
     StepArgs st;                   // UPDATE, RHS: the state of the step (M = N rows)
 };
 
-enum { EPI_PLAIN = 0, EPI_PAIR = 1, EPI_UPDATE = 2, EPI_RHS = 3 };
+enum { EPI_PLAIN = 0, EPI_PAIR = 1, EPI_UPDATE = 2, EPI_RHS = 3, EPI_FINISH = 4 };
 
 template <int ADT, int MKD, int FN, int PF, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     constexpr bool PAIR = (EPI == EPI_PAIR);
+    constexpr bool CLOSE = (EPI == EPI_UPDATE || EPI == EPI_FINISH);   // writes level n+1
     typedef MfmaT<MKD> Tr;
     typedef typename Tr::X XT;
     typedef typename Tr::Acc Acc;
@@ -65,11 +68,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     Acc* red = reinterpret_cast<Acc*>(smem);             // [NA][4][FN][4][64]
 
-    const int nwork = p.gx * p.gy + (EPI == EPI_UPDATE ? 1 : 0);
+    const int nwork = p.gx * p.gy + (CLOSE ? 1 : 0);
     const int per = (nwork + 7) / 8;
     const int wi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (wi >= nwork) return;
-    if constexpr (EPI == EPI_UPDATE) {
+    if constexpr (CLOSE) {
         if (wi == nwork - 1) {                           // the step-closing block
             close_and_advance(p.st, *p.st.step, p.gx);
             return;
@@ -209,20 +212,26 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
             }
         } else {
             const StepArgs& a = p.st;
-            const int k = bdf_order(n);
-            const BdfCoef c = bdf_coef(k);
             double ev = 0.0;
             if (row < p.M && b < a.B) {
-                const double rhs = bdf_rhs_point(a, n, c, k, b, row, (double)sum[0]);
-                if constexpr (EPI == EPI_UPDATE) {
-                    const double un = rhs * a.hdiag[(size_t)(k - 1) * a.N + row];
+                if constexpr (EPI == EPI_FINISH) {
+                    const double un = (double)sum[0];
                     write_level(a, n + 1, b, row, un);
                     ev = un * un;
                 } else {
-                    a.rhs[(size_t)b * a.Np + row] = rhs;
+                    const int k = bdf_order(n);
+                    const BdfCoef c = bdf_coef(k);
+                    const double rhs = bdf_rhs_point(a, n, c, k, b, row, (double)sum[0]);
+                    if constexpr (EPI == EPI_UPDATE) {
+                        const double un = rhs * a.hdiag[(size_t)(k - 1) * a.N + row];
+                        write_level(a, n + 1, b, row, un);
+                        ev = un * un;
+                    } else {
+                        a.rhs[(size_t)b * a.Np + row] = rhs;
+                    }
                 }
             }
-            if constexpr (EPI == EPI_UPDATE) {
+            if constexpr (CLOSE) {
                 // the tile's 16 rows of trajectory b sit in 16 consecutive lanes
                 ev += __shfl_xor(ev, 8, 16);
                 ev += __shfl_xor(ev, 4, 16);
@@ -361,13 +370,22 @@ void launch_gemm_scatter_step(int dt, const GemmPlan& pl0, const void* Af, const
 }
 
 // Batched Helmholtz apply: U[b][i] = sum_m Hinv_k[i][m] rhs[b][m] (FP64), k from the
-// device step counter; Hinv [3][N][Np], rhs [Bpad][Np].
-void launch_gemm_helm(const GemmPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
-                      const long long* stepp, double* Y, hipStream_t s) {
+// device step counter; Hinv [3][N][Np], rhs [Bpad][Np].  With step arguments (st) U is
+// u^{n+1}: stored into the state with its energy partials, and the step is closed (one
+// extra block); else U goes to Y.
+void launch_gemm_helm(const GemmPlan& pl0, const double* hinv, int N, int Np, int Bpad, const double* rhs,
+                      const long long* stepp, double* Y, const StepArgs* st, hipStream_t s) {
+    GemmPlan pl = pl0;
+    if (st) pl.blocks = (pl.gx * pl.gy + 1 + 7) / 8 * 8;
     GemmArgs a = gemm_args(pl, hinv, nullptr, Np, rhs, nullptr, Np, Y, N, Np, Bpad);
     a.kstep = stepp;
     a.a_kstride = (long long)N * Np;
-    gemm_go<DT_F64, MK_F64>(a, pl, s);
+    if (st) {
+        a.st = *st;
+        gemm_go<DT_F64, MK_F64, EPI_FINISH>(a, pl, s);
+    } else {
+        gemm_go<DT_F64, MK_F64>(a, pl, s);
+    }
 }
 
 }  // namespace rom

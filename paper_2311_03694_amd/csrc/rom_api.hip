@@ -196,7 +196,6 @@ struct WsPlan {
     size_t w_off = 0;               // CP Hadamard products W [Bpad][Rp] (B > 1)
     size_t ucv_off = 0, ucvlo_off = 0, usc_off = 0;   // rom_nonlinear operand copies (B > 1)
     GemmPlan ph{};                  // B > 1, dense stiffness: FP64 Helmholtz apply
-    size_t helm_off = 0;
     size_t total = 0;
 };
 
@@ -237,11 +236,7 @@ WsPlan plan_ws(rom_ctx c, int B) {
         off = align256(off + (c->dtype == DT_BF16X3 ? (size_t)p.Bpad * c->Np * 2 : 0));
         p.usc_off = off;
         off = align256(off + (size_t)p.Bpad * c->Np * ab);
-        if (!c->diagA) {
-            p.ph = gemm_plan(c->N, p.Bpad, 0);
-            p.helm_off = off;
-            off = align256(off + (size_t)p.Bpad * c->N * 8);
-        }
+        if (!c->diagA) p.ph = gemm_plan(c->N, p.Bpad, 0);
     }
     p.total = off + 256;
     return p;
@@ -548,9 +543,7 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
         if (s->B == 1) {
             launch_helm_apply(a, stream);
         } else {
-            double* hp = (double*)((char*)c->ws + p.helm_off);
-            launch_gemm_helm(p.ph, c->hinv, c->N, c->Np, p.Bpad, a.rhs, a.step, hp, stream);
-            launch_helm_finish(a, hp, 1, stream);
+            launch_gemm_helm(p.ph, c->hinv, c->N, c->Np, p.Bpad, a.rhs, a.step, nullptr, &a, stream);
         }
     }
     HIPCHK(hipGetLastError());

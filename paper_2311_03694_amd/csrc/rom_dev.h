@@ -161,13 +161,11 @@ int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, const void* la
 
 // BDF update from contraction partials part[c][b][i] (row stride pb trajectories) in
 // the accumulation type (FP64 for DT_F64, FP32 otherwise).  diag = 1: diagonal
-// stiffness (update, energy, finalize); diag = 0: right-hand side only.
+// stiffness (update, energy partials, step close); diag = 0: right-hand side only.
 void launch_bdf_from_partials(const StepArgs& a, int acc_f64, const void* part, int nchunk,
                               int pb, int diag, hipStream_t s);
-// Dense stiffness, one trajectory: u^{n+1} = Hinv_k rhs, energy, finalize.
+// Dense stiffness, one trajectory: u^{n+1} = Hinv_k rhs, energy partials, step close.
 void launch_helm_apply(const StepArgs& a, hipStream_t s);
-// Dense stiffness, batch: sum the FP64 MFMA partials of Hinv_k rhs, energy, finalize.
-void launch_helm_finish(const StepArgs& a, const double* part, int nsplit, hipStream_t s);
 // Write the batched coefficient copies from the current level (state create / set).
 void launch_prep_ucv(const StepArgs& a, const double* u_src, hipStream_t s);
 // Sum partials into FP64 y [B][N] (rom_nonlinear).
@@ -247,7 +245,7 @@ void launch_gemm_scatter_step(int dt, const GemmPlan& pl, const void* Af, const 
 void launch_gemm_scatter(int dt, const GemmPlan& pl, const void* Af, const void* Af_lo, int N, int Rp, int Bpad,
                          const void* W, void* Y, hipStream_t s);
 void launch_gemm_helm(const GemmPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
-                      const long long* stepp, double* Y, hipStream_t s);
+                      const long long* stepp, double* Y, const StepArgs* st, hipStream_t s);
 
 // A batched CP product of a context: variants [0, gemm_variants()) select k_gemm, the
 // following mfma_variants() the LDS-tile kernel; -1 = default.
