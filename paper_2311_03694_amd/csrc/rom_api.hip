@@ -1158,7 +1158,6 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
         // the newest one
         FinJob fj{};
         fj.a = sa;
-        fj.nblk = sa.enmax;
         g->fin.push_back(fj);
         if (c->Np > g->Npmax) g->Npmax = c->Np;
         if (c->N > g->Nmax) g->Nmax = c->N;

@@ -100,7 +100,6 @@ struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory
 };
 struct FinJob {            // closing energy sum of the newest level, one state
     StepArgs a;
-    int nblk;              // energy partials per trajectory written by the update
 };
 
 // ---------------------------------------------------------------- launchers (k_*.hip)
