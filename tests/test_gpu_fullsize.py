@@ -1,0 +1,208 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times
+(the tile table applied as bench.py applies it):
+
+* N=1000 with CP rank 2000 and with the 1e9-entry dense tensor, one trajectory (the
+  headline workload, FP32), and batches of 64 trajectories (FP32 and BF16);
+* N=400 with 256 trajectories (dense BF16, BF16x3, FP32 and CP rank 400 in FP32).
+
+The oracle evaluates sampled outputs one by one: sampled rows of one trajectory (row
+tiles, their boundaries and the ragged last tile of 8 rows at N=1000) and sampled
+trajectories of a batch (column-tile boundaries included)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2311_03694_amd as rg
+import romsynth
+from helpers import EPS_OP, EVAL_TOL, TRAJ_TOL, U_ACC, check_eval, eval_bound_cp, rel
+from paper_2311_03694_amd import tune
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def cfg3(torch_gpu):
+    _say("generating the N=1000 workload (dense tensor and CP rank 2000)")
+    return romsynth.make_config(3, batch=1, dense=True)
+
+
+@pytest.fixture(scope="module")
+def cfg2(torch_gpu):
+    _say("generating the N=400 workload (dense tensor and CP rank 400, 256 trajectories)")
+    return romsynth.make_config(2, R=400)
+
+
+def _rows(N, extra=24, seed=5):
+    """Row sample: the first and last rows, both sides of 16-row tile boundaries, the
+    ragged last tile, and random rows."""
+    fixed = [0, 1, 15, 16, 17, 255, 256, N // 2, N // 2 + 1]
+    tail = N - (N % 16 or 16)
+    fixed += [tail - 1, tail, N - 2, N - 1]
+    rng = np.random.default_rng(seed)
+    rows = set(r for r in fixed if 0 <= r < N) | set(rng.choice(N, size=extra, replace=False).tolist())
+    return np.array(sorted(rows), dtype=np.int64)
+
+
+def _abs_rows(C, u, rows):
+    """sum_jk |C_ijk| |u_j| |u_k| for the sampled rows."""
+    au = np.abs(u)
+    return np.array([au @ (np.abs(np.asarray(C[i])) @ au) for i in rows])
+
+
+def _check_rows(dt, y, y_ref, yabs, N):
+    """Norm-wise over the sampled rows: the operand error EPS_OP plus the accumulation
+    bound 4 N u of N^2-term sums, relative to sum |terms| (as eval_bound_dense)."""
+    bound = float(np.linalg.norm(yabs) * (EPS_OP[dt] + 4.0 * N * U_ACC[dt]))
+    check_eval(dt, y, y_ref, bound)
+
+
+def _check_rows_bf16(y, y_ref_exact, yabs, N):
+    """Elementwise: each product carries three BF16 roundings (2^-9 relative each) and
+    the FP32 sum of N^2 terms at most N^2 2^-24 relative to sum |terms|."""
+    g = (1 + 2.0 ** -8) ** 3 - 1 + N * N * 2.0 ** -24
+    err = np.abs(np.asarray(y) - np.asarray(y_ref_exact))
+    assert np.all(err <= g * yabs + 1e-300), float(np.max(err / (g * yabs + 1e-300)))
+
+
+def _nonlinear(torch, rom, U):
+    ud = torch.tensor(np.atleast_2d(U), dtype=torch.float64, device="cuda")
+    yd = torch.empty_like(ud)
+    torch.cuda.synchronize()
+    rg.rom_nonlinear(rom.handle, ud.shape[0], ud, yd)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def test_config3_cp_fp32(torch_gpu, cfg3):
+    """Headline workload, CP-ROM: the full y of one evaluation and 40 steps against the
+    oracle (coefficients at the last level and every energy)."""
+    p = cfg3
+    _say("N=1000 CP rank 2000 FP32: evaluation and 40 steps")
+    rom = rg.Rom.from_problem(p, dense=False, dtype="fp32", max_batch=1)
+    tune.apply(rom, 1, dense=False, R=p.Af.shape[1])
+    u = p.u0[0]
+    y = _nonlinear(torch_gpu, rom, u)[0]
+    check_eval("fp32", y, orc.nonlinear_cp(p.lam, p.Af, p.Bf, p.Cf, u),
+               eval_bound_cp("fp32", p.lam, p.Af, p.Bf, p.Cf, u))
+    s = rom.state(p.u0)
+    s.step(40)
+    uh, _, n = s.get()
+    _, Elog = s.energy()
+    ref = orc.run(p.N, p.nu, p.dt, p.A, 40, u0=u, lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
+    assert ref["status"] == 0 and n == 40
+    assert rel(uh[0][0], ref["u_hist"][0]) < TRAJ_TOL["fp32"]
+    assert float(np.max(np.abs(Elog.reshape(-1) - ref["E"]) / ref["E"])) < TRAJ_TOL["fp32"]
+    s.close()
+    rom.close()
+
+
+def test_config3_dense_fp32(torch_gpu, cfg3):
+    """Headline workload, dense G-ROM (the streaming contraction over 1e9 entries):
+    sampled rows of one evaluation, and the first two steps."""
+    p = cfg3
+    _say("N=1000 dense FP32: sampled rows and 2 steps")
+    rom = rg.Rom.from_problem(p, dense=True, dtype="fp32", max_batch=1)
+    tune.apply(rom, 1, dense=True)
+    u = p.u0[0]
+    rows = _rows(p.N)
+    y = _nonlinear(torch_gpu, rom, u)[0]
+    _check_rows("fp32", y[rows], orc.nonlinear_dense_rows(p.C, u, rows), _abs_rows(p.C, u, rows), p.N)
+    s = rom.state(p.u0)
+    s.step(2)
+    uh, _, n = s.get()
+    ref = orc.run(p.N, p.nu, p.dt, p.A, 2, u0=u, C=p.C)
+    assert ref["status"] == 0 and n == 2
+    assert rel(uh[0][0], ref["u_hist"][0]) < TRAJ_TOL["fp32"]
+    assert rel(uh[1][0], ref["u_hist"][1]) < TRAJ_TOL["fp32"]
+    s.close()
+    rom.close()
+
+
+@pytest.mark.parametrize("dt", ["fp32", "bf16"])
+def test_config3_batched_dense(torch_gpu, cfg3, dt):
+    """64 trajectories at N=1000 through the batched MFMA contraction: sampled rows of
+    sampled trajectories (column-tile boundaries among them)."""
+    p = cfg3
+    B = 64
+    _say(f"N=1000 dense batched B={B} {dt}")
+    U = romsynth.initial_u(p.N, range(B), cfg=3)
+    rom = rg.Rom.from_problem(p, dense=True, dtype=dt, max_batch=B)
+    tune.apply(rom, B, dense=True)
+    Y = _nonlinear(torch_gpu, rom, U)
+    rows = _rows(p.N, extra=8)
+    for b in (0, 15, 16, 31, 63):
+        _say(f"  trajectory {b}")
+        y_ref = orc.nonlinear_dense_rows(p.C, U[b], rows)
+        yabs = _abs_rows(p.C, U[b], rows)
+        if dt == "bf16":
+            _check_rows_bf16(Y[b][rows], y_ref, yabs, p.N)
+        else:
+            _check_rows(dt, Y[b][rows], y_ref, yabs, p.N)
+    rom.close()
+
+
+@pytest.mark.parametrize("dt", ["bf16", "bf16x3", "fp32"])
+def test_config2_batched_dense(torch_gpu, cfg2, dt):
+    """256 trajectories at N=400 (the MFMA workload): full outputs of sampled
+    trajectories; BF16 against the oracle on BF16-rounded operands."""
+    p = cfg2
+    B = p.u0.shape[0]
+    _say(f"N=400 dense batched B={B} {dt}")
+    rom = rg.Rom.from_problem(p, dense=True, dtype=dt, max_batch=B)
+    tune.apply(rom, B, dense=True)
+    Y = _nonlinear(torch_gpu, rom, p.u0)
+    if dt == "bf16":
+        Cr = orc.round_bf16(p.C).reshape(p.C.shape)
+    for b in (0, 1, 127, 128, 200, 255):
+        if dt == "bf16":
+            ur = orc.round_bf16(p.u0[b])
+            y_ref = orc.nonlinear_dense(Cr, ur)
+            bound = float(np.linalg.norm(np.einsum("ijk,j,k->i", np.abs(Cr), np.abs(ur), np.abs(ur)))
+                          * 4.0 * p.N * U_ACC[dt])
+        else:
+            y_ref = orc.nonlinear_dense(p.C, p.u0[b])
+            rows = np.arange(p.N)
+            bound = float(np.linalg.norm(_abs_rows(p.C, p.u0[b], rows)) * (EPS_OP[dt] + 4.0 * p.N * U_ACC[dt]))
+        check_eval(dt, Y[b], y_ref, bound)
+    rom.close()
+
+
+def test_config2_batched_cp(torch_gpu, cfg2):
+    """256 trajectories at N=400, CP rank 400 in FP32 (paired projections, scatter):
+    full outputs of sampled trajectories, then 30 steps of the same trajectories."""
+    p = cfg2
+    B = p.u0.shape[0]
+    _say(f"N=400 CP rank 400 batched B={B} fp32")
+    rom = rg.Rom.from_problem(p, dense=False, dtype="fp32", max_batch=B)
+    tune.apply(rom, B, dense=False, R=p.Af.shape[1])
+    Y = _nonlinear(torch_gpu, rom, p.u0)
+    sample = (0, 1, 127, 128, 200, 255)
+    for b in sample:
+        check_eval("fp32", Y[b], orc.nonlinear_cp(p.lam, p.Af, p.Bf, p.Cf, p.u0[b]),
+                   eval_bound_cp("fp32", p.lam, p.Af, p.Bf, p.Cf, p.u0[b]))
+    s = rom.state(p.u0)
+    s.step(30)
+    uh, _, n = s.get()
+    _, Elog = s.energy()
+    assert n == 30
+    for b in sample:
+        ref = orc.run(p.N, p.nu, p.dt, p.A, 30, u0=p.u0[b], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
+        assert rel(uh[0][b], ref["u_hist"][0]) < TRAJ_TOL["fp32"], b
+        assert float(np.max(np.abs(Elog[:, b] - ref["E"]) / ref["E"])) < TRAJ_TOL["fp32"], b
+    s.close()
+    rom.close()
