@@ -416,12 +416,15 @@ static hipError_t kr_attr(size_t lds) {
     return e;
 }
 
+hipError_t krs_set_lds_limit(size_t lds);
+
 hipError_t kr_set_lds_limit(size_t lds) {
     hipError_t e = hipSuccess, q;
     if ((q = kr_attr<DT_F64, MK_F64>(lds)) != hipSuccess) e = q;
     if ((q = kr_attr<DT_F32, MK_F32>(lds)) != hipSuccess) e = q;
     if ((q = kr_attr<DT_BF16, MK_BF16>(lds)) != hipSuccess) e = q;
     if ((q = kr_attr<DT_BF16X3, MK_BF16X3>(lds)) != hipSuccess) e = q;
+    if ((q = krs_set_lds_limit(lds)) != hipSuccess) e = q;
     return e;
 }
 
@@ -453,17 +456,396 @@ void launch_kr_dense(int dt, const KrPlan& pl, const void* Ct, const void* Ct_lo
     }
 }
 
+// ---------------------------------------------------------------- shared-tile variant
+//
+// k_krs: the same contraction with the tensor tile shared through LDS.  A block is 8
+// wavefronts over 16 rows, 4*16*FN trajectories, one k-chunk of at most KC fragment
+// steps and a range of j.  Wavefront w takes column group w%4 (16*FN trajectories)
+// and j parity w/4: in iteration it the block handles j = 2it and 2it+1, each half of
+// the wavefronts one of them.  Every wavefront holds the X fragments of its columns
+// over the whole chunk (KC steps), so the per-j weighting costs 4 FMAs per 16x16 tile
+// against KC MFMA steps.  The two tensor slabs of an iteration are read from HBM once
+// per block: each wavefront loads at most two 1 KB fragments of them into registers
+// P iterations ahead, stores them into one of two LDS slots after the barrier that
+// frees it, and all wavefronts read their A operands from LDS.  The two parities are
+// added in LDS at the end, in a fixed order, and the block writes one partial tile
+// part[split][b][i] like k_kr.
+struct KrsTile { int fn, kc, p; };
+constexpr int kKrsVariants = 4;
+template <int MKD> struct KrsTab;
+template <> struct KrsTab<MK_F64> {
+    static constexpr KrsTile t[kKrsVariants] = {{2, 7, 3}, {2, 8, 2}, {2, 4, 3}, {1, 8, 3}};
+};
+template <> struct KrsTab<MK_F32> {
+    static constexpr KrsTile t[kKrsVariants] = {{4, 7, 2}, {4, 8, 2}, {4, 4, 3}, {2, 8, 3}};
+};
+template <> struct KrsTab<MK_BF16> {
+    static constexpr KrsTile t[kKrsVariants] = {{4, 7, 2}, {4, 8, 2}, {4, 4, 3}, {2, 8, 3}};
+};
+template <> struct KrsTab<MK_BF16X3> {
+    static constexpr KrsTile t[kKrsVariants] = {{4, 3, 2}, {2, 7, 2}, {2, 4, 3}, {2, 8, 2}};
+};
+
+template <int ADT, int MKD, int FN, int KC, int P>
+__global__ __launch_bounds__(512) void k_krs(KrArgs p) {
+    typedef MfmaT<MKD> Tr;
+    typedef typename Tr::X XT;
+    typedef typename Tr::Acc Acc;
+    typedef typename Tr::Acc4 Acc4;
+    typedef typename Store<ADT>::T AT;
+    constexpr int KS = Tr::KS, VEC = Tr::VEC;
+    constexpr int NCW = 16 * FN, NCB = 4 * NCW;          // columns per wavefront, per block
+    constexpr int EV = 16 / (int)sizeof(Acc);
+    constexpr bool X3 = (MKD == MK_BF16X3);
+    constexpr int NH = X3 ? 2 : 1;                       // A words per element
+    constexpr int SLOT = 2 * KC * 1024 * NH;             // bytes of one ring slot
+    static_assert(1024 % (NCB * (int)sizeof(Acc)) == 0 || (NCB * (int)sizeof(Acc)) % 1024 == 0,
+                  "j-weight rows and 1 KB chunks must nest");
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    char* ring = smem;                                   // [2 slots][hi, lo][2 parities][KC][1 KB]
+    Acc* sl = reinterpret_cast<Acc*>(smem + 2 * SLOT);   // [jn + 1][NCB] j-weights, row jn zero
+
+    const int nwork = p.gx * p.gy * p.nkc * p.njr;
+    const int per = (nwork + 7) / 8;
+    const int wi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (wi >= nwork) return;
+    int rest = wi;
+    const int by = rest % p.gy;
+    rest /= p.gy;
+    const int kci = rest % p.nkc;
+    rest /= p.nkc;
+    const int bx = rest % p.gx;
+    const int jr = rest / p.gx;
+
+    const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int cg = w & 3, jp = w >> 2;
+    const int rowbase = bx * 16, b0 = by * NCB, cb0 = b0 + cg * NCW;
+    const int nsb = p.ksteps / p.nkc, nse = p.ksteps - nsb * p.nkc;
+    const int cs = nsb + (kci < nse ? 1 : 0);            // steps of this chunk (<= KC)
+    const int c0 = kci * nsb + (kci < nse ? kci : nse);
+    const int jbeg = jr * p.jc;
+    const int jn = min(p.J, jbeg + p.jc) - jbeg;
+    const int nit = (jn + 1) / 2;                        // iterations (pairs of j)
+
+    // ---- j-weights straight into LDS (rows [0, jn), 1 KB chunks over the 8
+    // wavefronts), row jn zero; columns past Bpad read a valid weight (their X
+    // fragments are zero and they are never stored)
+    {
+        constexpr int rowb = NCB * (int)sizeof(Acc);
+        const int nbytes = jn * rowb;
+        const int nch = (nbytes + 1023) / 1024;
+        for (int c = w; c < nch; c += 8) {
+            const int byte = c * 1024 + lane * 16;
+            const int jj = byte / rowb, col = (byte - jj * rowb) / (int)sizeof(Acc);
+            if (jj < jn) {
+                const int colc = b0 + col < p.Bpad ? col : 0;
+                const Acc* src = reinterpret_cast<const Acc*>(p.S) + (size_t)(jbeg + jj) * p.Bpad + b0 + colc;
+                __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)(reinterpret_cast<char*>(sl) + (size_t)c * 1024), 16,
+                                                 0, 0);
+            }
+        }
+        for (int e = threadIdx.x; e < NCB / EV; e += 512)
+            *reinterpret_cast<u32x4*>(sl + (size_t)jn * NCB + e * EV) = u32x4{0u, 0u, 0u, 0u};
+    }
+
+    // ---- X fragments of the wavefront's columns over the chunk
+    u32x4 xh[KC][FN], xl[KC][FN];
+    unsigned long long xok = 0;
+#pragma unroll
+    for (int s = 0; s < KC; ++s)
+#pragma unroll
+        for (int t = 0; t < FN; ++t) {
+            const int k = (c0 + s) * KS + g * VEC;
+            const int b = cb0 + c16 * FN + t;
+            if (s < cs && k < p.Kx && b < p.Bpad) xok |= 1ull << (s * FN + t);
+            const size_t o = (size_t)(b < p.Bpad ? b : p.Bpad - 1) * p.Kx + (k < p.Kx ? k : p.Kx - VEC);
+            xh[s][t] = ld_plain<16>(reinterpret_cast<const XT*>(p.X) + o);
+            if constexpr (X3) xl[s][t] = ld_plain<16>(p.Xlo + o);
+            else xl[s][t] = u32x4{0u, 0u, 0u, 0u};
+        }
+    __syncthreads();                                     // j-weights published
+#pragma unroll
+    for (int s = 0; s < KC; ++s)
+#pragma unroll
+        for (int t = 0; t < FN; ++t)
+            if (!((xok >> (s * FN + t)) & 1ull)) {
+                xh[s][t] = u32x4{0u, 0u, 0u, 0u};
+                xl[s][t] = u32x4{0u, 0u, 0u, 0u};
+            }
+
+    // ---- the two tensor slabs of an iteration: fragment f = par * cs + s (step s of
+    // j = 2 it + par); wavefront w carries fragments w and w + 8.  Loads are
+    // unconditional (fragments past 2 cs repeat the last one and are not stored; j past
+    // the range repeats its last j, whose weight row is zero).
+    const size_t nku = (size_t)(p.Kt / VEC);
+    int fpar[2], fs[2];
+    bool fval[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int f = w + 8 * h;
+        fval[h] = f < 2 * cs;
+        const int ff = fval[h] ? f : 2 * cs - 1;
+        fpar[h] = ff >= cs ? 1 : 0;
+        fs[h] = ff - fpar[h] * cs;
+    }
+    auto goff = [&](int it, int h) -> size_t {
+        int j = 2 * it + fpar[h];
+        j = j < jn ? j : jn - 1;
+        return ((((size_t)bx * p.J + jbeg + j) * nku + (size_t)(c0 + fs[h]) * 4) * 16) * VEC + (size_t)lane * VEC;
+    };
+    u32x4 rs[P][2], rl[P][2];
+    auto gload = [&](int it, int st) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t o = goff(it, h);
+            rs[st][h] = ld_plain<16>(reinterpret_cast<const AT*>(p.C) + o);
+            if constexpr (X3) rl[st][h] = ld_plain<16>(p.Clo + o);
+        }
+    };
+    auto swrite = [&](int st, int slot) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (fval[h]) {
+                char* d = ring + (size_t)slot * SLOT + (size_t)(fpar[h] * KC + fs[h]) * 1024 + lane * 16;
+                *reinterpret_cast<u32x4*>(d) = rs[st][h];
+                if constexpr (X3) *reinterpret_cast<u32x4*>(d + 2 * KC * 1024) = rl[st][h];
+            }
+    };
+
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        gload(q, q);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    swrite(0, 0);
+    __syncthreads();
+    gload(P, 0);
+    __builtin_amdgcn_sched_barrier(0);
+
+    Acc4 Y[FN];
+#pragma unroll
+    for (int t = 0; t < FN; ++t) Y[t] = Acc4{0, 0, 0, 0};
+
+    auto run = [&](auto nsc) {
+        constexpr int NSC = decltype(nsc)::value;
+        Acc svn[FN];
+        lds_row<FN>(sl + (size_t)(jp < jn ? jp : jn) * NCB + cg * NCW + c16 * FN, svn);
+        // unrolled by P so that every register stage index is a constant (T(q) sits in
+        // stage q % P); iterations past nit (up to a multiple of P) take the zero
+        // j-weight row, so the body has no branches
+        const int nit_pad = (nit + P - 1) / P * P;
+        for (int it0 = 0; it0 < nit_pad; it0 += P) {
+#pragma unroll
+            for (int d = 0; d < P; ++d) {
+                const int it = it0 + d;
+                const int slot = it & 1;
+                Acc sv[FN];
+#pragma unroll
+                for (int t = 0; t < FN; ++t) sv[t] = svn[t];
+                const int jnext = 2 * (it + 1) + jp;
+                lds_row<FN>(sl + (size_t)(jnext < jn ? jnext : jn) * NCB + cg * NCW + c16 * FN, svn);
+                const char* base = ring + (size_t)slot * SLOT + (size_t)jp * KC * 1024 + lane * 16;
+                Acc4 Z[FN];
+#pragma unroll
+                for (int t = 0; t < FN; ++t) Z[t] = Acc4{0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < NSC; ++s) {
+                    // steps past the chunk (only in the rare copies with NSC > cs) read the
+                    // chunk's last step, which holds finite data; their X fragments are zero
+                    const int sr = s < cs ? s : cs - 1;
+                    const u32x4 a = *reinterpret_cast<const u32x4*>(base + (size_t)sr * 1024);
+                    u32x4 al = u32x4{0u, 0u, 0u, 0u};
+                    if constexpr (X3) al = *reinterpret_cast<const u32x4*>(base + (size_t)sr * 1024 + 2 * KC * 1024);
+#pragma unroll
+                    for (int t = 0; t < FN; ++t) mfma_step<MKD>(Z[t], a, al, xh[s][t], xl[s][t]);
+                }
+#pragma unroll
+                for (int t = 0; t < FN; ++t) Y[t] += sv[t] * Z[t];
+                // iteration it + 1's slabs into the other slot (read last in iteration
+                // it - 1), then the barrier that publishes them and frees this slot; the
+                // stores stay after the matrix work (hoisted, they would wait for their
+                // loads early and shorten the prefetch)
+                __builtin_amdgcn_sched_barrier(0);
+                swrite((d + 1) % P, slot ^ 1);
+                __syncthreads();
+                gload(it + 1 + P, (d + 1) % P);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+    // one copy of the loop: a chunk shorter than KC multiplies zero X fragments in its
+    // last steps (a second copy for KC - 1 steps made the compiler drain the ring)
+    run(std::integral_constant<int, KC>{});
+
+    // ---- add the two parities in LDS (fixed order) and write the partial tile
+    __syncthreads();
+    Acc* red = reinterpret_cast<Acc*>(smem);             // [8][FN][4][64]
+#pragma unroll
+    for (int t = 0; t < FN; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((w * FN + t) * 4 + v) * 64 + lane] = Y[t][v];
+    __syncthreads();
+    Acc* out = reinterpret_cast<Acc*>(p.part) + (size_t)(jr * p.nkc + kci) * p.Bpad * p.M;
+    for (int e = threadIdx.x; e < 16 * NCB; e += 512) {
+        const int cb = e >> 4, rr = e & 15;              // block column, local row
+        const int gq = cb / NCW, cl = cb - gq * NCW;     // column group, column within it
+        const int t = cl % FN, cc = cl / FN;
+        const int gg = MKD == MK_F64 ? (rr & 3) : (rr >> 2);
+        const int v = MKD == MK_F64 ? (rr >> 2) : (rr & 3);
+        const int ln = gg * 16 + cc;
+        const Acc sum = red[((gq * FN + t) * 4 + v) * 64 + ln] + red[(((gq + 4) * FN + t) * 4 + v) * 64 + ln];
+        const int row = rowbase + rr, b = b0 + cb;
+        if (row < p.M && b < p.Bpad) out[(size_t)b * p.M + row] = sum;
+    }
+}
+
+template <int MKD>
+static KrsTile krs_tile(int v) {
+    return KrsTab<MKD>::t[v];
+}
+
+static KrsTile krs_tile_mk(int mk, int v) {
+    switch (mk) {
+        case MK_F64: return krs_tile<MK_F64>(v);
+        case MK_F32: return krs_tile<MK_F32>(v);
+        case MK_BF16: return krs_tile<MK_BF16>(v);
+        default: return krs_tile<MK_BF16X3>(v);
+    }
+}
+
+// Same split rules as kr_plan, for 256 concurrent blocks of 8 wavefronts; the LDS holds
+// the two ring slots and the j-weights of a block's j's.
+KrPlan krs_plan(int dt, int M, int J, int Kt, int Bpad, int v, size_t lds_max) {
+    const int mk = mk_of_dt(dt);
+    if (v < 0 || v >= kKrsVariants) v = 0;
+    const KrsTile t = krs_tile_mk(mk, v);
+    KrPlan pl{};
+    pl.v = v;
+    pl.fn = t.fn;
+    pl.kw = t.kc;
+    pl.pf = t.p;
+    const int KS = mk == MK_F64 ? 8 : mk == MK_F32 ? 16 : 32;
+    const size_t accb = mk == MK_F64 ? 8 : 4;
+    const int NCB = 64 * t.fn;
+    const size_t slot = (size_t)2 * t.kc * 1024 * (mk == MK_BF16X3 ? 2 : 1);
+    pl.ksteps = Kt / KS;
+    pl.nkc = (pl.ksteps + t.kc - 1) / t.kc;
+    pl.gx = (M + 15) / 16;
+    pl.gy = (Bpad + NCB - 1) / NCB;
+    const long long base = (long long)pl.gx * pl.gy * pl.nkc;
+    long long jc_max = (long long)((lds_max - 2 * slot) / ((size_t)NCB * accb)) - 1;
+    if (jc_max < 2) jc_max = 2;
+    long long njr_lo = (J + jc_max - 1) / jc_max, njr = njr_lo, best = -1;
+    for (long long n = njr_lo; n <= njr_lo + 256 && n <= J; ++n) {
+        const long long rounds = (base * n + 255) / 256;
+        const long long cost = rounds * ((J + n - 1) / n + 8);
+        if (best < 0 || cost < best) {
+            best = cost;
+            njr = n;
+        }
+    }
+    // j per block: whole groups of P pairs (no padding iterations) when they fit
+    const int jq = 2 * t.p;
+    pl.jc = (int)((J + njr - 1) / njr);
+    if ((pl.jc + jq - 1) / jq * jq <= jc_max) pl.jc = (pl.jc + jq - 1) / jq * jq;
+    else if ((pl.jc + 1) / 2 * 2 <= jc_max) pl.jc = (pl.jc + 1) / 2 * 2;
+    pl.njr = (J + pl.jc - 1) / pl.jc;
+    pl.nsplit = pl.nkc * pl.njr;
+    const size_t s_bytes = (size_t)(pl.jc + 1) * NCB * accb;
+    const size_t r_bytes = (size_t)8 * 256 * t.fn * accb;
+    const size_t need = 2 * slot + s_bytes;
+    pl.lds = need > r_bytes ? need : r_bytes;
+    pl.blocks = (int)((base * pl.njr + 7) / 8 * 8);
+    return pl;
+}
+
+template <int ADT, int MKD, int V>
+static void krs_go_v(const KrArgs& a, const KrPlan& pl, hipStream_t s) {
+    constexpr KrsTile t = KrsTab<MKD>::t[V];
+    hipLaunchKernelGGL((k_krs<ADT, MKD, t.fn, t.kc, t.p>), dim3(pl.blocks), dim3(512), pl.lds, s, a);
+}
+
+template <int ADT, int MKD, int V>
+static hipError_t krs_attr_v(size_t lds) {
+    constexpr KrsTile t = KrsTab<MKD>::t[V];
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_krs<ADT, MKD, t.fn, t.kc, t.p>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int ADT, int MKD>
+static void krs_go(const KrArgs& a, const KrPlan& pl, hipStream_t s) {
+    switch (pl.v) {
+        case 0: krs_go_v<ADT, MKD, 0>(a, pl, s); break;
+        case 1: krs_go_v<ADT, MKD, 1>(a, pl, s); break;
+        case 2: krs_go_v<ADT, MKD, 2>(a, pl, s); break;
+        default: krs_go_v<ADT, MKD, 3>(a, pl, s); break;
+    }
+}
+
+template <int ADT, int MKD>
+static hipError_t krs_attr(size_t lds) {
+    hipError_t e = hipSuccess, q;
+    if ((q = krs_attr_v<ADT, MKD, 0>(lds)) != hipSuccess) e = q;
+    if ((q = krs_attr_v<ADT, MKD, 1>(lds)) != hipSuccess) e = q;
+    if ((q = krs_attr_v<ADT, MKD, 2>(lds)) != hipSuccess) e = q;
+    if ((q = krs_attr_v<ADT, MKD, 3>(lds)) != hipSuccess) e = q;
+    return e;
+}
+
+hipError_t krs_set_lds_limit(size_t lds) {
+    hipError_t e = hipSuccess, q;
+    if ((q = krs_attr<DT_F64, MK_F64>(lds)) != hipSuccess) e = q;
+    if ((q = krs_attr<DT_F32, MK_F32>(lds)) != hipSuccess) e = q;
+    if ((q = krs_attr<DT_BF16, MK_BF16>(lds)) != hipSuccess) e = q;
+    if ((q = krs_attr<DT_BF16X3, MK_BF16X3>(lds)) != hipSuccess) e = q;
+    return e;
+}
+
+void launch_krs_dense(int dt, const KrPlan& pl, const void* Ct, const void* Ct_lo, int N, int Np, int Bpad,
+                      const void* X, const void* Xlo, const void* S, void* part, hipStream_t s) {
+    KrArgs a{};
+    a.C = Ct;
+    a.Clo = (const unsigned short*)Ct_lo;
+    a.X = X;
+    a.Xlo = (const unsigned short*)Xlo;
+    a.S = S;
+    a.part = part;
+    a.M = N;
+    a.J = N;
+    a.Kt = kr_tiled_k(dt, N);
+    a.Kx = Np;
+    a.Bpad = Bpad;
+    a.ksteps = pl.ksteps;
+    a.nkc = pl.nkc;
+    a.jc = pl.jc;
+    a.njr = pl.njr;
+    a.gx = pl.gx;
+    a.gy = pl.gy;
+    switch (dt) {
+        case DT_F64: krs_go<DT_F64, MK_F64>(a, pl, s); break;
+        case DT_F32: krs_go<DT_F32, MK_F32>(a, pl, s); break;
+        case DT_BF16: krs_go<DT_BF16, MK_BF16>(a, pl, s); break;
+        default: krs_go<DT_BF16X3, MK_BF16X3>(a, pl, s); break;
+    }
+}
+
 // ---------------------------------------------------------------- engine choice
 
-int dense_batched_variants() { return kKrVariants + mfma_variants(); }
+// Variants: k_kr (kKrVariants), then k_krs (kKrsVariants), then the LDS-tile kernel.
+int dense_batched_variants() { return kKrVariants + kKrsVariants + mfma_variants(); }
 
 DensePlan dense_batched_plan(int dt, int N, int Np, int Bpad, int variant, size_t lds_max) {
     (void)Np;
     DensePlan d{};
-    if (variant >= kKrVariants) {
+    if (variant >= kKrVariants + kKrsVariants) {
         d.engine = 1;
-        d.m = mfma_dense_plan(dt, N, Np, Bpad, mfma_variant(variant - kKrVariants));
+        d.m = mfma_dense_plan(dt, N, Np, Bpad, mfma_variant(variant - kKrVariants - kKrsVariants));
         d.nsplit = d.m.nsplit;
+    } else if (variant >= kKrVariants) {
+        d.engine = 2;
+        d.k = krs_plan(dt, N, N, kr_tiled_k(dt, N), Bpad, variant - kKrVariants, lds_max);
+        d.nsplit = d.k.nsplit;
     } else {
         d.engine = 0;
         d.k = kr_plan(dt, N, N, kr_tiled_k(dt, N), Bpad, variant, lds_max);
@@ -476,6 +858,7 @@ void launch_dense_batched(int dt, const DensePlan& pl, const void* C, const void
                           const void* Ct_lo, int N, int Np, int Bpad, const void* X, const void* Xlo, const void* S,
                           void* part, hipStream_t s) {
     if (pl.engine == 1) launch_mfma_dense(dt, pl.m, C, Clo, N, Np, Bpad, X, Xlo, S, part, s);
+    else if (pl.engine == 2) launch_krs_dense(dt, pl.k, Ct, Ct_lo, N, Np, Bpad, X, Xlo, S, part, s);
     else launch_kr_dense(dt, pl.k, Ct, Ct_lo, N, Np, Bpad, X, Xlo, S, part, s);
 }
 

@@ -219,7 +219,7 @@ hipError_t kr_set_lds_limit(size_t lds);
 // The batched dense contraction of a context: variants [0, kr_variants()) select the
 // register kernel, the following mfma_variants() the LDS-tile kernel; -1 = default.
 struct DensePlan {
-    int engine;                    // 0 = k_kr, 1 = k_mfma_rows
+    int engine;                    // 0 = k_kr, 1 = k_mfma_rows, 2 = k_krs
     KrPlan k;
     MfmaPlan m;
     int nsplit;
