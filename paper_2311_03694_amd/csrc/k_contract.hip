@@ -189,6 +189,59 @@ __global__ __launch_bounds__(256) void k_cp_scatter1_group(const Scat1Job* __res
     cp_scatter1_body<DT, V, U, MODE>(jb, nullptr, blk, n);
 }
 
+// ============================================================== Helmholtz apply and projections
+
+// With a dense stiffness the step ends by applying Hinv_k to the right-hand side.  For
+// a CP state the same kernel also forms the projections of the new level,
+// s = Bf^T u^{n+1} and t = Cf^T u^{n+1}, from that right-hand side with the operator
+// [Bf|Cf]^T Hinv_k built at context creation (the two products associate:
+// Bf^T (Hinv_k rhs) = (Bf^T Hinv_k) rhs, with the same 2 N R flops as the projection of
+// u^{n+1}).  The next step's scatter then starts at once, and a step is two kernels.
+// Blocks [0, nh) are Helmholtz row blocks, blocks [nh, nh + np) projection row blocks
+// (four rows each).
+template <int DT, bool EVEN>
+__device__ __forceinline__ void helm_proj_body(const HelmJob& jb, long long n, int blk) {
+    if (blk < jb.nh) {
+        helm_gemv_body<EVEN>(jb.a, n, blk);
+        return;
+    }
+    typedef typename Store<DT>::T T;
+    constexpr int V = 16 / (int)sizeof(T);
+    const size_t mstride = (size_t)(bdf_order(n) - 1) * jb.R2 * jb.a.Np;
+    Proj1Job pj{};
+    pj.BCt = reinterpret_cast<const T*>(jb.Mst) + mstride;
+    pj.BCt_lo = jb.Mst_lo ? jb.Mst_lo + mstride : nullptr;
+    pj.N = jb.a.N;
+    pj.Np = jb.a.Np;
+    pj.R2 = jb.R2;
+    pj.u_base = jb.a.rhs;
+    pj.st = jb.a.st;
+    cp_proj1_body<DT, V, 4>(pj, blk - jb.nh);
+}
+
+// One state: nh + np blocks and a last one that closes the previous level and advances
+// the counter.
+template <int DT, bool EVEN>
+__global__ __launch_bounds__(256) void k_helm_proj(HelmJob jb) {
+    if (blockIdx.x == gridDim.x - 1) {
+        close_and_advance(jb.a, *jb.a.step, jb.nh);
+        return;
+    }
+    helm_proj_body<DT, EVEN>(jb, *jb.a.step, blockIdx.x);
+}
+
+// Grouped states: the first block of each job also closes its state's previous level.
+template <int DT>
+__global__ __launch_bounds__(256) void k_helm_proj_group(const HelmJob* __restrict__ jobs, int njobs) {
+    const int p = find_job(jobs, njobs, (int)blockIdx.x);
+    const HelmJob& jb = jobs[p];
+    const int blk = (int)blockIdx.x - jb.blk0;
+    const long long n = *jb.a.step;
+    if (blk == 0) close_and_advance(jb.a, n, jb.nh);
+    if (jb.a.N % 2 == 0) helm_proj_body<DT, true>(jb, n, blk);
+    else helm_proj_body<DT, false>(jb, n, blk);
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <int DT>
@@ -281,6 +334,47 @@ void launch_cp_scatter1_group(int dt, int mode, const Scat1Job* jobs_dev, int nj
                               hipStream_t s) {
     Scat1Job none{};
     scat1_dispatch(dt, mode, none, nullptr, jobs_dev, njobs, blocks, Rpmax, s);
+}
+
+template <int DT>
+static size_t helm_proj_lds(int N, int Np, bool proj) {
+    const size_t h = sizeof(double) * (size_t)N, q = proj ? LdsU<DT>::bytes(Np) : 0;
+    return h > q ? h : q;
+}
+
+template <int DT>
+static void helm_proj_go(const HelmJob& jb, hipStream_t s) {
+    const size_t lds = helm_proj_lds<DT>(jb.a.N, jb.a.Np, jb.np > 0);
+    const unsigned blocks = (unsigned)(jb.nh + jb.np + 1);
+    if (jb.a.N % 2 == 0) hipLaunchKernelGGL((k_helm_proj<DT, true>), dim3(blocks), dim3(256), lds, s, jb);
+    else hipLaunchKernelGGL((k_helm_proj<DT, false>), dim3(blocks), dim3(256), lds, s, jb);
+}
+
+void launch_helm_proj(int dt, const HelmJob& jb, hipStream_t s) {
+    switch (dt) {
+        case DT_F64: helm_proj_go<DT_F64>(jb, s); break;
+        case DT_F32: helm_proj_go<DT_F32>(jb, s); break;
+        case DT_BF16: helm_proj_go<DT_BF16>(jb, s); break;
+        default: helm_proj_go<DT_BF16X3>(jb, s); break;
+    }
+}
+
+template <int DT>
+static void helm_proj_group_go(const HelmJob* jobs, int njobs, int blocks, int Nmax, int Npmax, bool proj,
+                               hipStream_t s) {
+    const size_t lds = helm_proj_lds<DT>(Nmax, Npmax, proj);
+    hipLaunchKernelGGL((k_helm_proj_group<DT>), dim3((unsigned)blocks), dim3(256), lds, s, jobs, njobs);
+}
+
+void launch_helm_proj_group(int dt, const HelmJob* jobs_dev, int njobs, int blocks, int Nmax, int Npmax, int proj,
+                            hipStream_t s) {
+    if (njobs < 1 || blocks < 1) return;
+    switch (dt) {
+        case DT_F64: helm_proj_group_go<DT_F64>(jobs_dev, njobs, blocks, Nmax, Npmax, proj != 0, s); break;
+        case DT_F32: helm_proj_group_go<DT_F32>(jobs_dev, njobs, blocks, Nmax, Npmax, proj != 0, s); break;
+        case DT_BF16: helm_proj_group_go<DT_BF16>(jobs_dev, njobs, blocks, Nmax, Npmax, proj != 0, s); break;
+        default: helm_proj_group_go<DT_BF16X3>(jobs_dev, njobs, blocks, Nmax, Npmax, proj != 0, s); break;
+    }
 }
 
 }  // namespace rom

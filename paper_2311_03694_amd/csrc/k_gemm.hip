@@ -369,6 +369,13 @@ void launch_gemm_scatter_step(int dt, const GemmPlan& pl0, const void* Af, const
     }
 }
 
+// Plain FP64 product Y[b][m] = sum_k A[m][k] X[b][k] (setup work).
+void launch_gemm_f64(const GemmPlan& pl, const double* A, long long lda, const double* X, long long ldx, double* Y,
+                     int M, int K, int Bpad, hipStream_t s) {
+    const GemmArgs a = gemm_args(pl, A, nullptr, lda, X, nullptr, ldx, Y, M, K, Bpad);
+    gemm_go<DT_F64, MK_F64>(a, pl, s);
+}
+
 // Batched Helmholtz apply: U[b][i] = sum_m Hinv_k[i][m] rhs[b][m] (FP64), k from the
 // device step counter; Hinv [3][N][Np], rhs [Bpad][Np].  With step arguments (st) U is
 // u^{n+1}: stored into the state with its energy partials, and the step is closed (one

@@ -128,4 +128,60 @@ __device__ __forceinline__ void close_and_advance(const StepArgs& a, long long n
     }
 }
 
+// ---------------------------------------------------------------- Helmholtz apply rows
+
+// Dense stiffness, one trajectory: u^{n+1}_i = sum_m Hinv_k[i][m] rhs_m, one wavefront
+// per row.  Each lane issues its (up to 8) 16-byte loads of the row before rhs is
+// staged in LDS; rows longer than 1024 elements loop.  Block blk of nblk covers rows
+// 4 blk .. 4 blk + 3.
+template <bool EVEN>
+__device__ __forceinline__ void helm_gemv_body(const StepArgs& a, long long n, int blk) {
+    extern __shared__ __attribute__((aligned(16))) double sm[];
+    double* r = sm;                       // [N]
+    __shared__ double red[4];
+    constexpr int V = EVEN ? 2 : 1, U = 8;
+    typedef typename RawT<8 * V>::T Raw;
+    const int k = bdf_order(n);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int i = blk * 4 + w;
+    const bool live = i < a.N;
+    const double* h = a.hinv + ((size_t)(k - 1) * a.N + (live ? i : 0)) * a.Np;
+    Raw hv[U];
+    int m0 = lane * V;
+    auto issue = [&](int mb) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int m = mb + q * kWave * V;
+            if (live && m < a.N) hv[q] = ld_plain<8 * V>(h + m);
+        }
+    };
+    issue(m0);
+    staged_copy<8, double>(a.N, [&](int m) { return a.rhs[m]; }, [&](int m, double v) { r[m] = v; });
+    __syncthreads();
+    double e = 0.0;
+    if (live) {
+        double s = 0.0;
+        while (m0 < a.N) {
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int m = m0 + q * kWave * V;
+                if (m < a.N) {
+                    const double* hd = reinterpret_cast<const double*>(&hv[q]);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) s += hd[v] * r[m + v];
+                }
+            }
+            m0 += kWave * V * U;
+            if (m0 < a.N) issue(m0);
+        }
+        s = wave_sum(s);
+        if (lane == 0) {
+            write_level(a, n + 1, 0, i, s);
+            e = s * s;
+        }
+    }
+    const double es = block_sum(e, red);
+    if (threadIdx.x == 0) epart_of(a, n + 1)[blk] = es;
+}
+
 }  // namespace rom

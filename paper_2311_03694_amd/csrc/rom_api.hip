@@ -74,6 +74,8 @@ struct rom_ctx_s {
     void *BCt = nullptr, *BCt_lo = nullptr;    // CP [2Rp][Np]: rows Bf^T then Cf^T
     void *Af = nullptr, *Af_lo = nullptr;      // CP [N][Rp]
     void* lam = nullptr;                        // CP [Rp] (FP64 or FP32)
+    // CP with a dense stiffness: [Bf|Cf]^T Hinv_k for k = 1, 2, 3, [3][2Rp][Np]
+    void *Mst = nullptr, *Mst_lo = nullptr;
     double* hdiag = nullptr;                    // [3][N]
     double* hinv = nullptr;                     // [3][N][N]
     // workspaces (shared by every state of the context; one stream serializes use)
@@ -488,6 +490,48 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
         HTRY(hipMemcpyAsync(stage, d->lambda, sizeof(double) * R, hipMemcpyHostToDevice, c->stream));
         launch_cvt_lambda(dt, stage, c->lam, (long long)R, c->stream);
         HTRY(hipGetLastError());
+        if (!c->diagA) {
+            // [Bf|Cf]^T Hinv_k for the one-trajectory step (the projections of u^{n+1}
+            // straight from the right-hand side): FP64 rows of [Bf|Cf]^T, zero padded,
+            // times the symmetric Hinv_k on the matrix cores, then the contraction format
+            const size_t rows2 = 2 * Rp;
+            std::vector<double> bt(rows2 * Np, 0.0);
+            for (size_t n = 0; n < (size_t)N; ++n)
+                for (size_t r = 0; r < R; ++r) {
+                    bt[r * Np + n] = d->Bf[n * R + r];
+                    bt[(Rp + r) * Np + n] = d->Cf[n * R + r];
+                }
+            TRY(dmalloc(&c->Mst, 3 * rows2 * Np * eb + kSlack, &c->bytes, &c->allocs));
+            HTRY(hipMemsetAsync(c->Mst, 0, 3 * rows2 * Np * eb + kSlack, c->stream));
+            if (lo) {
+                TRY(dmalloc(&c->Mst_lo, 3 * rows2 * Np * 2 + kSlack, &c->bytes, &c->allocs));
+                HTRY(hipMemsetAsync(c->Mst_lo, 0, 3 * rows2 * Np * 2 + kSlack, c->stream));
+            }
+            double *bt_d = nullptr, *tmp_d = nullptr;
+            hipError_t e = hipMalloc((void**)&bt_d, sizeof(double) * rows2 * Np);
+            if (e == hipSuccess) e = hipMalloc((void**)&tmp_d, sizeof(double) * rows2 * N);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(bt_d, bt.data(), sizeof(double) * rows2 * Np, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) {
+                const GemmPlan pl = gemm_plan((int)N, (int)rows2, 0);
+                for (int k = 0; k < 3; ++k) {
+                    launch_gemm_f64(pl, c->hinv + (size_t)k * N * Np, (long long)Np, bt_d, (long long)Np, tmp_d,
+                                    (int)N, (int)Np, (int)rows2, c->stream);
+                    launch_cvt_f64_to(dt, tmp_d, (char*)c->Mst + (size_t)k * rows2 * Np * eb,
+                                      lo ? (char*)c->Mst_lo + (size_t)k * rows2 * Np * 2 : nullptr, (long long)rows2,
+                                      (int)N, (int)Np, c->stream);
+                }
+                e = hipGetLastError();
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            }
+            if (bt_d) hipFree(bt_d);
+            if (tmp_d) hipFree(tmp_d);
+            if (e != hipSuccess) {
+                st = fail(ROM_E_DEVICE, "setup of the projection operators failed: %s", hipGetErrorString(e));
+                rom_destroy(c);
+                return st;
+            }
+        }
     }
     HTRY(hipStreamSynchronize(c->stream));
     *out = c;
@@ -507,6 +551,30 @@ static StepArgs step_args(rom_state s, long long n) {
     return a;
 }
 
+// The Helmholtz apply of a one-trajectory state (with the projections of the new level
+// when the context is CP).
+static HelmJob helm_job(rom_ctx c, const StepArgs& a) {
+    HelmJob h{};
+    h.a = a;
+    h.nh = (c->N + 3) / 4;
+    if (!c->dense) {
+        h.Mst = c->Mst;
+        h.Mst_lo = (const unsigned short*)c->Mst_lo;
+        h.R2 = 2 * c->Rp;
+        h.np = (2 * c->Rp + 3) / 4;
+    }
+    h.nblk = h.nh + h.np;
+    return h;
+}
+
+// The projections of level n of a one-trajectory CP state with a dense stiffness (state
+// creation and restart; every step then leaves those of the next level).
+static void seed_projections(rom_ctx c, const StepArgs& a, hipStream_t stream) {
+    if (c->dense || c->diagA || a.B != 1) return;
+    launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N, a.st,
+                    stream);
+}
+
 // Enqueue one BDF3/EXT3 step of state s from level n on `stream`: contraction (dense
 // or CP, single-trajectory or batched kernels), FP64 update and energy; dense
 // stiffness adds the Helmholtz apply.
@@ -522,10 +590,13 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
                               ws + p.part_off, p.nchunk, gemv_tile(c), stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.nchunk, 1, diag, stream);
         } else {
-            launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N,
-                            ws + p.part_off, stream);
-            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, ws + p.part_off, nullptr, &a,
-                               diag ? 1 : 2, stream);
+            // a.st holds the projections of level n: computed here with a diagonal
+            // stiffness, left by the previous step's Helmholtz kernel otherwise
+            if (diag)
+                launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N,
+                                a.st, stream);
+            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, a.st, nullptr, &a, diag ? 1 : 2,
+                               stream);
         }
     } else {
         char* ws = (char*)c->ws;
@@ -540,7 +611,9 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
         }
     }
     if (!c->diagA) {
-        if (s->B == 1) {
+        if (s->B == 1 && !c->dense) {
+            launch_helm_proj(c->dtype, helm_job(c, a), stream);
+        } else if (s->B == 1) {
             launch_helm_apply(a, stream);
         } else {
             launch_gemm_helm(p.ph, c->hinv, c->N, c->Np, p.Bpad, a.rhs, a.step, nullptr, &a, stream);
@@ -800,6 +873,8 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     a.step_next = s->cnt + 1;
     TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.closep, sizeof(int), &s->bytes, &s->allocs));
+    if (!c->dense && batch == 1)
+        TRY(dmalloc(&a.st, 2 * c->Rp * acc_bytes(c->dtype), &s->bytes, &s->allocs));
     if (a.batched) {
         const size_t cells = (size_t)s->Bpad * c->Np;
         TRY(dmalloc(&a.ucv, cells * elem_bytes(c->dtype), &s->bytes, &s->allocs));
@@ -825,6 +900,7 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(reset_counters(s, 0));
     TRY(ensure_elog(s, 1024));
     hipLaunchKernelGGL(k_energy_level, dim3(batch), dim3(256), 0, c->stream, a, 0LL);
+    seed_projections(c, step_args(s, 0), c->stream);
     if (a.batched) launch_prep_ucv(a, a.uring, c->stream);
     TRY(ensure_ws(c, plan_ws(c, batch).total));
     TRY(ensure_scratch(s));
@@ -987,6 +1063,7 @@ extern "C" rom_status rom_state_set(rom_ctx c, rom_state s, const double* u_hist
     if (st != ROM_OK) return st;
     s->h_step = step;
     hipLaunchKernelGGL(k_energy_level, dim3(s->B), dim3(256), 0, c->stream, s->a, (long long)step);
+    seed_projections(c, step_args(s, step), c->stream);
     if (s->a.batched) launch_prep_ucv(s->a, s->a.uring + (size_t)(step % 3) * BN, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1036,7 +1113,7 @@ void enqueue_group(const Group& g, hipStream_t stream, int phase) {
         if (g.dense)
             launch_dense_gemv_group(g.dtype, (const GemvJob*)(g.dev + g.off1), (int)g.gemv.size(), g.b1, g.Npmax,
                                     g.tile, stream);
-        else
+        else if (!g.proj.empty())
             launch_cp_proj1_group(g.dtype, (const Proj1Job*)(g.dev + g.off1), (int)g.proj.size(), g.b1, g.Npmax,
                                   stream);
     } else if (phase == 2) {
@@ -1047,7 +1124,9 @@ void enqueue_group(const Group& g, hipStream_t stream, int phase) {
             launch_cp_scatter1_group(g.dtype, g.diag ? 1 : 2, (const Scat1Job*)(g.dev + g.off2),
                                      (int)g.scat.size(), g.b2, g.Rpmax, stream);
     } else if (phase == 3) {
-        if (!g.diag) launch_helm_group((const HelmJob*)(g.dev + g.off3), (int)g.helm.size(), g.b3, g.Nmax, stream);
+        if (!g.diag)
+            launch_helm_proj_group(g.dtype, (const HelmJob*)(g.dev + g.off3), (int)g.helm.size(), g.b3, g.Nmax,
+                                   g.Npmax, g.dense ? 0 : 1, stream);
     } else {
         launch_close_group((const FinJob*)(g.dev + g.off4), (int)g.fin.size(), stream);
     }
@@ -1117,27 +1196,31 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
             g->b2 += bj.nblk;
             g->bdf.push_back(bj);
         } else {
-            Proj1Job pj{};
-            pj.BCt = c->BCt;
-            pj.BCt_lo = (const unsigned short*)c->BCt_lo;
-            pj.N = c->N;
-            pj.Np = c->Np;
-            pj.R2 = 2 * c->Rp;
-            pj.u_base = sa.uring;
-            pj.stepp = sa.step;
-            pj.slot_stride = c->N;
-            pj.st = scr + p.part_off;
-            pj.blk0 = g->b1;
-            pj.nblk = (2 * c->Rp + 3) / 4;
-            g->b1 += pj.nblk;
-            g->proj.push_back(pj);
+            // with a dense stiffness the projections come from the previous step's
+            // Helmholtz kernel (phase 3)
+            if (diag) {
+                Proj1Job pj{};
+                pj.BCt = c->BCt;
+                pj.BCt_lo = (const unsigned short*)c->BCt_lo;
+                pj.N = c->N;
+                pj.Np = c->Np;
+                pj.R2 = 2 * c->Rp;
+                pj.u_base = sa.uring;
+                pj.stepp = sa.step;
+                pj.slot_stride = c->N;
+                pj.st = sa.st;
+                pj.blk0 = g->b1;
+                pj.nblk = (2 * c->Rp + 3) / 4;
+                g->b1 += pj.nblk;
+                g->proj.push_back(pj);
+            }
             Scat1Job sj{};
             sj.Af = c->Af;
             sj.Af_lo = (const unsigned short*)c->Af_lo;
             sj.lam = c->lam;
             sj.N = c->N;
             sj.Rp = c->Rp;
-            sj.st = scr + p.part_off;
+            sj.st = sa.st;
             sj.a = sa;
             sj.blk0 = g->b2;
             sj.nblk = (c->N + 3) / 4;
@@ -1146,10 +1229,8 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
             if (c->Rp > g->Rpmax) g->Rpmax = c->Rp;
         }
         if (!diag) {
-            HelmJob hj{};
-            hj.a = sa;
+            HelmJob hj = helm_job(c, sa);
             hj.blk0 = g->b3;
-            hj.nblk = (c->N + 3) / 4;
             g->b3 += hj.nblk;
             g->helm.push_back(hj);
         }

@@ -48,6 +48,8 @@ struct StepArgs {
     void* ucv_lo;            // BF16X3 low words
     void* uj;                // [Np][Bpad] j-weights in the accumulation type: FP64 (DT_F64),
                              // else FP32 (the BF16-rounded value for DT_BF16)
+    void* st;                // CP, one trajectory: s = Bf^T u, t = Cf^T u of the newest
+                             // level [2Rp] (accumulation type)
     int Bpad, Np;
     int dtype;               // Dt of the contraction
     int batched;             // 1: write ucv/uj for the batched contraction
@@ -94,9 +96,15 @@ struct BdfJob {            // BDF update from contraction partials, one trajecto
     int nchunk, pb;
     int blk0, nblk;
 };
-struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory
+struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory; with CP
+                           // factors also the projections of the new level (see
+                           // launch_helm_proj)
     StepArgs a;
-    int blk0, nblk;
+    const void* Mst;               // CP: [3][2Rp][Np] [Bf|Cf]^T Hinv_k, contraction format; else null
+    const unsigned short* Mst_lo;  // BF16X3 low words of Mst
+    int R2;                        // 2 Rp
+    int nh, np;                    // row blocks of the Helmholtz part, of the projections (0: none)
+    int blk0, nblk;                // grouped launches: first block, blocks (nh + np)
 };
 struct FinJob {            // closing energy sum of the newest level, one state
     StepArgs a;
@@ -131,7 +139,11 @@ void launch_cp_proj1_group(int dt, const Proj1Job* jobs_dev, int njobs, int bloc
 void launch_cp_scatter1_group(int dt, int mode, const Scat1Job* jobs_dev, int njobs, int blocks, int Rpmax,
                               hipStream_t s);
 void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s);
-void launch_helm_group(const HelmJob* jobs_dev, int njobs, int blocks, int Nmax, hipStream_t s);
+// Dense-stiffness apply of a step with, for CP states (np > 0), the projections of the
+// new level (k_contract.hip); one state, or grouped states (proj: some job has np > 0).
+void launch_helm_proj(int dt, const HelmJob& jb, hipStream_t s);
+void launch_helm_proj_group(int dt, const HelmJob* jobs_dev, int njobs, int blocks, int Nmax, int Npmax, int proj,
+                            hipStream_t s);
 // Closing energy sum of the newest level when it is still pending (after the last step
 // of a sequence; one block per state).
 void launch_close(const StepArgs& a, hipStream_t s);
@@ -243,6 +255,8 @@ void launch_gemm_scatter_step(int dt, const GemmPlan& pl, const void* Af, const 
                               int Bpad, const void* W, const StepArgs& st, int diag, hipStream_t s);
 void launch_gemm_scatter(int dt, const GemmPlan& pl, const void* Af, const void* Af_lo, int N, int Rp, int Bpad,
                          const void* W, void* Y, hipStream_t s);
+void launch_gemm_f64(const GemmPlan& pl, const double* A, long long lda, const double* X, long long ldx, double* Y,
+                     int M, int K, int Bpad, hipStream_t s);
 void launch_gemm_helm(const GemmPlan& pl, const double* hinv, int N, int Np, int Bpad, const double* rhs,
                       const long long* stepp, double* Y, const StepArgs* st, hipStream_t s);
 

@@ -178,16 +178,20 @@ def test_checkpoint_resume_bitwise(torch_gpu):
     assert np.array_equal(Ea, Ec)
 
 
-def test_restart_from_oracle_history(torch_gpu):
-    """rom_state_set with an oracle history continues exactly like the oracle."""
-    _say("restart from oracle history")
-    p = romsynth.make_problem(40, pairs=20, eps=1e-6, cfg=16, dense=True, cp=False)
-    r1 = orc.run(p.N, p.nu, p.dt, p.A, 30, u0=p.u0[0], C=p.C)
-    rom = rg.Rom.from_problem(p, dense=True, dtype="fp64")
+@pytest.mark.parametrize("dense,A", [(True, "diag"), (False, "spd")])
+def test_restart_from_oracle_history(torch_gpu, dense, A):
+    """rom_state_set with an oracle history continues exactly like the oracle (for a CP
+    trajectory with a dense stiffness the restart recomputes the projections of the
+    restart level, which later steps carry from one Helmholtz kernel to the next)."""
+    _say(f"restart from oracle history dense={dense} A={A}")
+    p = romsynth.make_problem(40, pairs=20, eps=1e-6, A=A, cfg=16, dense=dense, cp=not dense)
+    kw = dict(C=p.C) if dense else dict(lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
+    r1 = orc.run(p.N, p.nu, p.dt, p.A, 30, u0=p.u0[0], **kw)
+    rom = rg.Rom.from_problem(p, dense=dense, dtype="fp64")
     s = rom.state(p.u0[0])
     s.set(r1["u_hist"][:, None, :], r1["y_hist"][:, None, :], 30)
     s.step(40)
-    r2 = orc.run(p.N, p.nu, p.dt, p.A, 40, C=p.C, step0=30, uh=r1["u_hist"], yh=r1["y_hist"])
+    r2 = orc.run(p.N, p.nu, p.dt, p.A, 40, step0=30, uh=r1["u_hist"], yh=r1["y_hist"], **kw)
     assert rel(s.u()[0], r2["u_hist"][0]) < 1e-12
 
 
@@ -221,7 +225,8 @@ def test_not_spd_rejected(torch_gpu):
     assert ei.value.status == 1
 
 
-@pytest.mark.parametrize("dense,A,B", [(False, "diag", 1), (True, "spd", 1), (True, "diag", 1), (False, "spd", 3)])
+@pytest.mark.parametrize("dense,A,B", [(False, "diag", 1), (True, "spd", 1), (True, "diag", 1), (False, "spd", 1),
+                                       (False, "spd", 3)])
 def test_step_splits_agree(torch_gpu, dense, A, B):
     """The step counter has two slots and captured chunks are cached per parity of
     their first level: 301 steps at once equal 1 + 130 + 3 + 167 steps (chunks that
