@@ -109,6 +109,17 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
         }
     };
     issue(r0);
+    // the update's history (and diagonal inverse) behind the row loads
+    BdfHist hist{};
+    double hd = 0.0;
+    int k = 0;
+    if constexpr (MODE != 0) {
+        k = bdf_order(n);
+        if (live && lane == 0) {
+            hist = bdf_hist_point(a, n, k, 0, i);
+            if constexpr (MODE == 1) hd = a.hdiag[(size_t)(k - 1) * N + i];
+        }
+    }
     struct Trip { Acc l, a, b; };
     staged_copy<8, Trip>(
         R, [&](int r) { return Trip{lam[r], st[r], st[R + r]}; },
@@ -142,13 +153,12 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
     if constexpr (MODE == 0) {
         if (live && lane == 0) y_out[i] = (double)z;
     } else {
-        const int k = bdf_order(n);
         const BdfCoef c = bdf_coef(k);
         double e = 0.0;
         if (live && lane == 0) {
-            const double rhs = bdf_rhs_point(a, n, c, k, 0, i, (double)z);
+            const double rhs = bdf_rhs_hist(a, n, c, k, 0, i, (double)z, hist);
             if constexpr (MODE == 1) {
-                const double un = rhs * a.hdiag[(size_t)(k - 1) * N + i];
+                const double un = rhs * hd;
                 write_level(a, n + 1, 0, i, un);
                 e = un * un;
             } else {

@@ -7,26 +7,41 @@
 
 namespace rom {
 
-// Store y^n, form the right-hand side of eq. nse_d1 for point (b, i):
-//   rhs = - sum_{q<=k} alpha_q y^{n+1-q} - (1/dt) sum_{q<=k} beta_q u^{n+1-q}.
-__device__ __forceinline__ double bdf_rhs_point(const StepArgs& a, long long n, const BdfCoef& c,
-                                                int k, int b, int i, double y) {
+// History of point (b, i) that the right-hand side of eq. nse_d1 at level n needs:
+// y^{n-1}, y^{n-2} and u^n, u^{n-1}, u^{n-2} (zero beyond the order k).  Kernels whose
+// contraction is long load it first, so that its latency hides behind the contraction.
+struct BdfHist {
+    double y1, y2, u[3];
+};
+__device__ __forceinline__ BdfHist bdf_hist_point(const StepArgs& a, long long n, int k, int b, int i) {
     const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N + i;
-    a.yring[(size_t)slot_of(n) * BN + off] = y;
-    double ylev[3], ulev[3];
-    ylev[0] = y;
-    ylev[1] = k >= 2 ? a.yring[(size_t)slot_of(n - 1) * BN + off] : 0.0;
-    ylev[2] = k >= 3 ? a.yring[(size_t)slot_of(n - 2) * BN + off] : 0.0;
+    BdfHist h;
+    h.y1 = k >= 2 ? a.yring[(size_t)slot_of(n - 1) * BN + off] : 0.0;
+    h.y2 = k >= 3 ? a.yring[(size_t)slot_of(n - 2) * BN + off] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) ulev[q] = q < k ? a.uring[(size_t)slot_of(n - q) * BN + off] : 0.0;
+    for (int q = 0; q < 3; ++q) h.u[q] = q < k ? a.uring[(size_t)slot_of(n - q) * BN + off] : 0.0;
+    return h;
+}
+
+// Store y^n, form the right-hand side of eq. nse_d1 for point (b, i) from its history:
+//   rhs = - sum_{q<=k} alpha_q y^{n+1-q} - (1/dt) sum_{q<=k} beta_q u^{n+1-q}.
+__device__ __forceinline__ double bdf_rhs_hist(const StepArgs& a, long long n, const BdfCoef& c, int k, int b,
+                                               int i, double y, const BdfHist& h) {
+    a.yring[(size_t)slot_of(n) * ((size_t)a.B * a.N) + (size_t)b * a.N + i] = y;
+    const double ylev[3] = {y, h.y1, h.y2};
     double v = 0.0;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
         if (q < k) v -= c.alpha[q] * ylev[q];
 #pragma unroll
     for (int q = 0; q < 3; ++q)
-        if (q < k) v -= (c.beta[q + 1] * a.inv_dt) * ulev[q];
+        if (q < k) v -= (c.beta[q + 1] * a.inv_dt) * h.u[q];
     return v;
+}
+
+__device__ __forceinline__ double bdf_rhs_point(const StepArgs& a, long long n, const BdfCoef& c,
+                                                int k, int b, int i, double y) {
+    return bdf_rhs_hist(a, n, c, k, b, i, y, bdf_hist_point(a, n, k, b, i));
 }
 
 // Coefficient copies for the batched contraction ([Bpad][Np] layout).
