@@ -293,8 +293,8 @@ template <> struct KrTab<MK_F32> {
                                               {4, 8, 3, 512}, {8, 2, 4, 512}, {2, 8, 3, 256}, {1, 8, 4, 256}};
 };
 template <> struct KrTab<MK_BF16> {
-    static constexpr KrTile t[kKrVariants] = {{16, 2, 6, 256}, {16, 2, 6, 512}, {8, 4, 4, 256}, {8, 4, 4, 512},
-                                              {8, 2, 6, 512},  {4, 8, 3, 256},  {2, 8, 4, 256}, {1, 8, 4, 256}};
+    static constexpr KrTile t[kKrVariants] = {{16, 2, 6, 256}, {4, 4, 5, 512}, {8, 4, 4, 256}, {4, 4, 3, 512},
+                                              {8, 2, 6, 512},  {2, 4, 4, 512},  {4, 4, 4, 512}, {1, 8, 4, 256}};
 };
 template <> struct KrTab<MK_BF16X3> {
     static constexpr KrTile t[kKrVariants] = {{8, 2, 4, 256}, {8, 2, 4, 512}, {16, 1, 6, 256}, {4, 4, 4, 256},
