@@ -1,8 +1,9 @@
 // k_contract.hip -- CP advection contraction for one trajectory.
 //
-// CP (Sec. 3.1, eq. tc_ap):  s = Bf^T u, t = Cf^T u (one pass over [Bf | Cf]^T stored
-// [2Rp][Np]), then y = Af (lam .* s .* t) with the Hadamard product formed in LDS by
-// every block of the scatter kernel, which also applies the BDF update to its rows.
+// CP (Sec. 3.1, eq. tc_ap):  w = lam .* s .* t with s = Bf^T u, t = Cf^T u (one pass
+// over [Bf | Cf]^T stored [2Rp][Np]: a wavefront takes rows r and Rp + r and writes w_r),
+// then y = Af w, with w staged in LDS by every block of the scatter kernel, which also
+// applies the BDF update to its rows.
 // Np and Rp round N and R up to multiples of 8; padding rows and columns hold zeros
 // (and zero weights), so they contribute nothing.
 #include "kdot.h"
@@ -12,9 +13,11 @@ namespace rom {
 
 // ============================================================== CP, one trajectory
 
-// Projections: st[r] = sum_k BCt[r][k] u_k for r < 2Rp (rows r < Rp are Bf^T u, rows
-// Rp + r are Cf^T u).  One wavefront per row, four per block; each lane issues its U
-// row loads before u is staged in LDS.
+// Projections and Hadamard product: w[r] = lam_r (sum_k BCt[r][k] u_k)
+// (sum_k BCt[Rp + r][k] u_k) for r < Rp (rows r < Rp are Bf^T, rows Rp + r are Cf^T).
+// One wavefront per row pair, four per block; each lane issues its row loads before u
+// is staged in LDS.  Each projection sums in the same order as a one-row dot product,
+// and w = (lam s) t.
 template <int DT, int V, int U>
 __device__ __forceinline__ void cp_proj1_body(const Proj1Job& jb, int blk) {
     typedef typename Store<DT>::T T;
@@ -28,37 +31,44 @@ __device__ __forceinline__ void cp_proj1_body(const Proj1Job& jb, int blk) {
     L.bind(smem, Np);
     const int lane = threadIdx.x % kWave;
     const int r = blk * 4 + threadIdx.x / kWave;
-    const bool live = r < jb.R2;
+    const bool live = r < jb.Rp;
+    const size_t pair = (size_t)jb.Rp * Np;
     const T* row = reinterpret_cast<const T*>(jb.BCt) + (size_t)(live ? r : 0) * Np;
     const unsigned short* rowlo = X3 ? jb.BCt_lo + (size_t)(live ? r : 0) * Np : nullptr;
-    Raw rv[U], rl[U];
+    Raw rv[2][U], rl[2][U];
     int k0 = lane * V;
     auto issue = [&](int kb) {
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const int k = kb + q * kWave * V;
-            if (live && k < Np) {
-                rv[q] = ld_plain<BYTES>(row + k);
-                if constexpr (X3) rl[q] = ld_plain<BYTES>(rowlo + k);
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int k = kb + q * kWave * V;
+                if (live && k < Np) {
+                    rv[h][q] = ld_plain<BYTES>(row + (h ? pair : 0) + k);
+                    if constexpr (X3) rl[h][q] = ld_plain<BYTES>(rowlo + (h ? pair : 0) + k);
+                }
             }
-        }
     };
     issue(k0);
     L.fill(jb.u_base + (jb.stepp ? (size_t)slot_of(*jb.stepp) * jb.slot_stride : 0), N, Np);
     __syncthreads();
     if (!live) return;
-    Acc z = 0;
+    Acc z[2] = {0, 0};
     while (k0 < Np) {
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int k = k0 + q * kWave * V;
-            if (k < Np) z += dot_vec<DT, V>(rv[q], rl[q], L, k);
+            if (k < Np) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) z[h] += dot_vec<DT, V>(rv[h][q], rl[h][q], L, k);
+            }
         }
         k0 += kWave * V * U;
         if (k0 < Np) issue(k0);
     }
-    z = wave_sum(z);
-    if (lane == 0) reinterpret_cast<Acc*>(jb.st)[r] = z;
+    z[0] = wave_sum(z[0]);
+    z[1] = wave_sum(z[1]);
+    if (lane == 0) reinterpret_cast<Acc*>(jb.w)[r] = reinterpret_cast<const Acc*>(jb.lam)[r] * z[0] * z[1];
 }
 
 template <int DT, int V, int U>
@@ -71,8 +81,8 @@ __global__ __launch_bounds__(256) void k_cp_proj1_group(const Proj1Job* __restri
     cp_proj1_body<DT, V, U>(jobs[p], (int)blockIdx.x - jobs[p].blk0);
 }
 
-// Hadamard-and-scatter: W_r = lam_r s_r t_r in LDS, then y_i = sum_r Af[i][r] W_r, one
-// wavefront per row (row loads issued before W is formed).  MODE 0 writes y (FP64,
+// Scatter: W = lam .* s .* t staged in LDS, then y_i = sum_r Af[i][r] W_r, one
+// wavefront per row (row loads issued before W is staged).  MODE 0 writes y (FP64,
 // to y_out); MODE 1 applies the diagonal-stiffness BDF update with its energy
 // partials; MODE 2 writes the right-hand side for the dense Helmholtz solve.  n is the
 // state's level (MODE 1 and 2).
@@ -89,8 +99,7 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
     __shared__ double red[4];
     const int N = jb.N, R = jb.Rp;
     const StepArgs& a = jb.a;
-    const Acc* __restrict__ lam = reinterpret_cast<const Acc*>(jb.lam);
-    const Acc* __restrict__ st = reinterpret_cast<const Acc*>(jb.st);
+    const Acc* __restrict__ win = reinterpret_cast<const Acc*>(jb.w);
     const int lane = threadIdx.x % kWave;
     const int i = blk * 4 + threadIdx.x / kWave;
     const bool live = i < N;
@@ -120,10 +129,7 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
             if constexpr (MODE == 1) hd = a.hdiag[(size_t)(k - 1) * N + i];
         }
     }
-    struct Trip { Acc l, a, b; };
-    staged_copy<8, Trip>(
-        R, [&](int r) { return Trip{lam[r], st[r], st[R + r]}; },
-        [&](int r, const Trip& t) { W[r] = t.l * t.a * t.b; });
+    staged_copy<8, Acc>(R, [&](int r) { return win[r]; }, [&](int r, Acc v) { W[r] = v; });
     __syncthreads();
     Acc z = 0;
     if (live) {
@@ -203,12 +209,12 @@ __global__ __launch_bounds__(256) void k_cp_scatter1_group(const Scat1Job* __res
 
 // With a dense stiffness the step ends by applying Hinv_k to the right-hand side.  For
 // a CP state the same kernel also forms the projections of the new level,
-// s = Bf^T u^{n+1} and t = Cf^T u^{n+1}, from that right-hand side with the operator
-// [Bf|Cf]^T Hinv_k built at context creation (the two products associate:
-// Bf^T (Hinv_k rhs) = (Bf^T Hinv_k) rhs, with the same 2 N R flops as the projection of
-// u^{n+1}).  The next step's scatter then starts at once, and a step is two kernels.
-// Blocks [0, nh) are Helmholtz row blocks, blocks [nh, nh + np) projection row blocks
-// (four rows each).
+// s = Bf^T u^{n+1} and t = Cf^T u^{n+1}, and w = lam .* s .* t, from that right-hand side
+// with the operator [Bf|Cf]^T Hinv_k built at context creation (the two products
+// associate: Bf^T (Hinv_k rhs) = (Bf^T Hinv_k) rhs, with the same 2 N R flops as the
+// projection of u^{n+1}).  The next step's scatter then starts at once, and a step is
+// two kernels.  Blocks [0, nh) are Helmholtz row blocks, blocks [nh, nh + np)
+// projection blocks (four row pairs each).
 template <int DT, bool EVEN>
 __device__ __forceinline__ void helm_proj_body(const HelmJob& jb, long long n, int blk) {
     if (blk < jb.nh) {
@@ -217,15 +223,16 @@ __device__ __forceinline__ void helm_proj_body(const HelmJob& jb, long long n, i
     }
     typedef typename Store<DT>::T T;
     constexpr int V = 16 / (int)sizeof(T);
-    const size_t mstride = (size_t)(bdf_order(n) - 1) * jb.R2 * jb.a.Np;
+    const size_t mstride = (size_t)(bdf_order(n) - 1) * 2 * jb.Rp * jb.a.Np;
     Proj1Job pj{};
     pj.BCt = reinterpret_cast<const T*>(jb.Mst) + mstride;
     pj.BCt_lo = jb.Mst_lo ? jb.Mst_lo + mstride : nullptr;
+    pj.lam = jb.lam;
     pj.N = jb.a.N;
     pj.Np = jb.a.Np;
-    pj.R2 = jb.R2;
+    pj.Rp = jb.Rp;
     pj.u_base = jb.a.rhs;
-    pj.st = jb.a.st;
+    pj.w = jb.a.st;
     cp_proj1_body<DT, V, 4>(pj, blk - jb.nh);
 }
 
@@ -272,20 +279,21 @@ static void proj1_dispatch(int dt, const Proj1Job& jb, const Proj1Job* jobs, int
     }
 }
 
-int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, int N, int Np, int Rp,
+int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, const void* lam, int N, int Np, int Rp,
                     const double* u_base, const long long* stepp, long long slot_stride,
-                    void* st, hipStream_t s) {
+                    void* w, hipStream_t s) {
     Proj1Job jb{};
     jb.BCt = BCt;
     jb.BCt_lo = (const unsigned short*)BCt_lo;
+    jb.lam = lam;
     jb.N = N;
     jb.Np = Np;
-    jb.R2 = 2 * Rp;
+    jb.Rp = Rp;
     jb.u_base = u_base;
     jb.stepp = stepp;
     jb.slot_stride = slot_stride;
-    jb.st = st;
-    jb.nblk = (2 * Rp + 3) / 4;
+    jb.w = w;
+    jb.nblk = (Rp + 3) / 4;
     proj1_dispatch(dt, jb, nullptr, 0, 0, Np, s);
     return 0;
 }
@@ -324,16 +332,14 @@ static void scat1_dispatch(int dt, int mode, const Scat1Job& jb, double* y, cons
     }
 }
 
-int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, const void* lam, int N,
-                       int Rp, const void* st, double* y_out, const StepArgs* sa, int mode,
-                       hipStream_t s) {
+int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, int N, int Rp, const void* w, double* y_out,
+                       const StepArgs* sa, int mode, hipStream_t s) {
     Scat1Job jb{};
     jb.Af = Af;
     jb.Af_lo = (const unsigned short*)Af_lo;
-    jb.lam = lam;
     jb.N = N;
     jb.Rp = Rp;
-    jb.st = st;
+    jb.w = w;
     if (sa) jb.a = *sa;
     jb.nblk = (N + 3) / 4;
     scat1_dispatch(dt, mode, jb, y_out, nullptr, 0, 0, Rp, s);

@@ -560,19 +560,21 @@ static HelmJob helm_job(rom_ctx c, const StepArgs& a) {
     if (!c->dense) {
         h.Mst = c->Mst;
         h.Mst_lo = (const unsigned short*)c->Mst_lo;
-        h.R2 = 2 * c->Rp;
-        h.np = (2 * c->Rp + 3) / 4;
+        h.lam = c->lam;
+        h.Rp = c->Rp;
+        h.np = (c->Rp + 3) / 4;
     }
     h.nblk = h.nh + h.np;
     return h;
 }
 
-// The projections of level n of a one-trajectory CP state with a dense stiffness (state
-// creation and restart; every step then leaves those of the next level).
+// The Hadamard product of the projections of level n of a one-trajectory CP state with a
+// dense stiffness (state creation and restart; every step then leaves that of the next
+// level).
 static void seed_projections(rom_ctx c, const StepArgs& a, hipStream_t stream) {
     if (c->dense || c->diagA || a.B != 1) return;
-    launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N, a.st,
-                    stream);
+    launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->lam, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N,
+                    a.st, stream);
 }
 
 // Enqueue one BDF3/EXT3 step of state s from level n on `stream`: contraction (dense
@@ -590,13 +592,12 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
                               ws + p.part_off, p.nchunk, gemv_tile(c), stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.nchunk, 1, diag, stream);
         } else {
-            // a.st holds the projections of level n: computed here with a diagonal
+            // a.st holds w = lam .* s .* t of level n: computed here with a diagonal
             // stiffness, left by the previous step's Helmholtz kernel otherwise
             if (diag)
-                launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N,
-                                a.st, stream);
-            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, a.st, nullptr, &a, diag ? 1 : 2,
-                               stream);
+                launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->lam, c->N, c->Np, c->Rp, a.uring, a.step,
+                                (long long)c->N, a.st, stream);
+            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->N, c->Rp, a.st, nullptr, &a, diag ? 1 : 2, stream);
         }
     } else {
         char* ws = (char*)c->ws;
@@ -657,10 +658,10 @@ static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, 
                 launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, u_dev, nullptr, 0, ws + p.part_off, p.nchunk,
                                   gemv_tile(c), c->stream);
             } else {
-                launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->N, c->Np, c->Rp, u_dev, nullptr, 0, ws + p.part_off,
-                                c->stream);
-                launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->lam, c->N, c->Rp, ws + p.part_off, y_dev, nullptr,
-                                   0, c->stream);
+                launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->lam, c->N, c->Np, c->Rp, u_dev, nullptr, 0,
+                                ws + p.part_off, c->stream);
+                launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->N, c->Rp, ws + p.part_off, y_dev, nullptr, 0,
+                                   c->stream);
             }
         } else if (c->dense) {
             launch_dense_batched(c->dtype, p.pd, c->C, c->Clo, c->Ct, c->Ct_lo, c->N, c->Np, p.Bpad, a.ucv, a.ucv_lo,
@@ -874,7 +875,7 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.closep, sizeof(int), &s->bytes, &s->allocs));
     if (!c->dense && batch == 1)
-        TRY(dmalloc(&a.st, 2 * c->Rp * acc_bytes(c->dtype), &s->bytes, &s->allocs));
+        TRY(dmalloc(&a.st, c->Rp * acc_bytes(c->dtype), &s->bytes, &s->allocs));
     if (a.batched) {
         const size_t cells = (size_t)s->Bpad * c->Np;
         TRY(dmalloc(&a.ucv, cells * elem_bytes(c->dtype), &s->bytes, &s->allocs));
@@ -1202,25 +1203,25 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
                 Proj1Job pj{};
                 pj.BCt = c->BCt;
                 pj.BCt_lo = (const unsigned short*)c->BCt_lo;
+                pj.lam = c->lam;
                 pj.N = c->N;
                 pj.Np = c->Np;
-                pj.R2 = 2 * c->Rp;
+                pj.Rp = c->Rp;
                 pj.u_base = sa.uring;
                 pj.stepp = sa.step;
                 pj.slot_stride = c->N;
-                pj.st = sa.st;
+                pj.w = sa.st;
                 pj.blk0 = g->b1;
-                pj.nblk = (2 * c->Rp + 3) / 4;
+                pj.nblk = (c->Rp + 3) / 4;
                 g->b1 += pj.nblk;
                 g->proj.push_back(pj);
             }
             Scat1Job sj{};
             sj.Af = c->Af;
             sj.Af_lo = (const unsigned short*)c->Af_lo;
-            sj.lam = c->lam;
             sj.N = c->N;
             sj.Rp = c->Rp;
-            sj.st = sa.st;
+            sj.w = sa.st;
             sj.a = sa;
             sj.blk0 = g->b2;
             sj.nblk = (c->N + 3) / 4;

@@ -48,8 +48,8 @@ struct StepArgs {
     void* ucv_lo;            // BF16X3 low words
     void* uj;                // [Np][Bpad] j-weights in the accumulation type: FP64 (DT_F64),
                              // else FP32 (the BF16-rounded value for DT_BF16)
-    void* st;                // CP, one trajectory: s = Bf^T u, t = Cf^T u of the newest
-                             // level [2Rp] (accumulation type)
+    void* st;                // CP, one trajectory: w = lam .* (Bf^T u) .* (Cf^T u) of the
+                             // newest level [Rp] (accumulation type)
     int Bpad, Np;
     int dtype;               // Dt of the contraction
     int batched;             // 1: write ucv/uj for the batched contraction
@@ -71,22 +71,22 @@ struct GemvJob {           // dense contraction, one trajectory
     long long chunk_len;
     int blk0, nblk;
 };
-struct Proj1Job {          // CP projections, one trajectory
+struct Proj1Job {          // CP projections and their Hadamard product, one trajectory
     const void* BCt;
     const unsigned short* BCt_lo;
-    int N, Np, R2;
+    const void* lam;
+    int N, Np, Rp;
     const double* u_base;
     const long long* stepp;
     long long slot_stride;
-    void* st;
+    void* w;
     int blk0, nblk;
 };
 struct Scat1Job {          // CP Hadamard-scatter with the fused BDF update
     const void* Af;
     const unsigned short* Af_lo;
-    const void* lam;
     int N, Rp;
-    const void* st;
+    const void* w;                 // lam .* s .* t [Rp]
     StepArgs a;
     int blk0, nblk;
 };
@@ -102,7 +102,8 @@ struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory; w
     StepArgs a;
     const void* Mst;               // CP: [3][2Rp][Np] [Bf|Cf]^T Hinv_k, contraction format; else null
     const unsigned short* Mst_lo;  // BF16X3 low words of Mst
-    int R2;                        // 2 Rp
+    const void* lam;               // CP: lam [Rp] (accumulation type)
+    int Rp;
     int nh, np;                    // row blocks of the Helmholtz part, of the projections (0: none)
     int blk0, nblk;                // grouped launches: first block, blocks (nh + np)
 };
@@ -163,12 +164,11 @@ struct MfmaPlan {
 
 // CP, one trajectory.
 // st [2Rp]: s then t; factors padded to Np / Rp with zeros.
-int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, int N, int Np, int Rp,
+int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, const void* lam, int N, int Np, int Rp,
                     const double* u_base, const long long* stepp, long long slot_stride,
-                    void* st, hipStream_t s);
-int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, const void* lam, int N,
-                       int Rp, const void* st, double* y_out, const StepArgs* sa, int mode,
-                       hipStream_t s);
+                    void* w, hipStream_t s);
+int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, int N, int Rp, const void* w, double* y_out,
+                       const StepArgs* sa, int mode, hipStream_t s);
 
 // BDF update from contraction partials part[c][b][i] (row stride pb trajectories) in
 // the accumulation type (FP64 for DT_F64, FP32 otherwise).  diag = 1: diagonal
