@@ -22,6 +22,8 @@ Also in the one JSON line:
   batched       N = 1000 with B = 16 and 64 trajectories (MFMA kernels), FP32 and BF16
   config2       N = 400, B = 256, the dense Khatri-Rao MFMA GEMM (BF16, BF16x3, FP32)
                 and CP rank 400, with TFLOP/s against the dense MFMA peaks
+  multi         uneven N: one CP trajectory each at N = 100, 200, 400, 700, 1000 stepped
+                together by grouped launches (rom_step_multi) and one after the other
   serving       a bounded Poisson request stream through the continuous-batching loop
   rel_err       GPU trajectories against the FP64 oracle (same operator)
   cpu_baseline  the FP64 oracle (plain C, one thread) on a bounded sample of steps
@@ -59,7 +61,7 @@ def parse():
                     help="target length of the oracle sample (CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no batched/config2/serving)")
-    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "serving"],
+    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "multi", "serving"],
                     help="run one section only (profiling); the JSON line then holds that section")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--calib-copy", action="store_true",
@@ -287,6 +289,36 @@ def main():
                                    "avg_launch_us": c2["dense_bf16"]["contraction_us"],
                                    "algorithmic_flops": 2.0 * 400 ** 3 * 256,
                                    "traffic": _traffic("kr_dense_n400_b256_bf16", "kr")}
+
+    if not args.no_extra and sec in ("all", "multi"):
+        # ---------------- uneven N: grouped launches against the same states one by one
+        Ns = (100, 200, 400, 700, 1000)
+        roms, sts = [], []
+        for i, Nm in enumerate(Ns):
+            pm = romsynth.make_problem(Nm, pairs=Nm, eps=1e-7, nu=5e-4, dt=5e-4, A="spd", cfg=40 + i,
+                                       dense=False, cp=True)
+            rm = rg.Rom.from_problem(pm, dense=False, dtype="fp32", max_batch=1, stream=stream)
+            roms.append(rm)
+            sts.append(rm.state(pm.u0[0]))
+        ch, sh = [r.handle for r in roms], [x.handle for x in sts]
+        nm = 2000
+        rg.rom_step_multi(ch, sh, 20)
+        t_grp = timer(lambda: rg.rom_step_multi(ch, sh, nm))
+        for x in sts:
+            x.step(20)
+        t_sep = timer(lambda: [x.step_async(nm) for x in sts])
+        for x in sts:
+            x.sync()
+        result["multi"] = {"Ns": list(Ns), "R": "2N", "dtype": "fp32", "stiffness": "diag(k^2)+SPD(0.1)",
+                           "grouped_traj_steps_per_s": len(Ns) * nm / t_grp,
+                           "separate_traj_steps_per_s": len(Ns) * nm / t_sep,
+                           "grouped_us_per_step": t_grp / nm * 1e6, "separate_us_per_step": t_sep / nm * 1e6,
+                           "speedup_grouped": t_sep / t_grp}
+        log(f"multi: grouped {len(Ns) * nm / t_grp:.0f}, separate {len(Ns) * nm / t_sep:.0f} traj-steps/s")
+        for x in sts:
+            x.close()
+        for r in roms:
+            r.close()
 
     if not args.no_extra and sec in ("all", "serving"):
         # ---------------- serving: bounded Poisson stream

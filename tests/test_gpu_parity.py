@@ -142,10 +142,11 @@ def test_skew_cp_trajectory(torch_gpu, dt, dense):
     assert np.max(np.abs(E - Eref) / Eref) < TRAJ_TOL[dt]
 
 
-@pytest.mark.parametrize("dt", ["fp64", "fp32"])
+@pytest.mark.parametrize("dt", ["fp64", "fp32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("dense", [True, False])
 def test_spd_stiffness_trajectory(torch_gpu, dt, dense):
-    """Dense SPD stiffness A = diag(k^2) + P: FP64 Helmholtz inverses built on the GPU."""
+    """Dense SPD stiffness A = diag(k^2) + P: FP64 Helmholtz inverses built on the GPU
+    (CP: the projections of each new level through [Bf|Cf]^T Hinv_k in every format)."""
     _say(f"spd stiffness dense={dense} {dt}")
     p = romsynth.make_problem(70, pairs=40, eps=1e-7, nu=5e-4, dt=5e-4, A="spd", nsteps=300,
                               cfg=14, dense=dense, cp=not dense)
