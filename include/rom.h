@@ -134,8 +134,8 @@ rom_status rom_energy(rom_ctx ctx, rom_state st, double *E_host, double *Elog_ho
 /* Checkpoint/resume.  u_hist [3][batch][N] = levels n, n-1, n-2; y_hist [2][batch][N] =
  * C(u)u at levels n-1, n-2; *step = n.  Levels below 0 are zero.  rom_state_set
  * restarts at step n from the given history (the energy log restarts at level n).  A
- * one-trajectory CP state with a dense stiffness carries the projections Bf^T u, Cf^T u
- * from step to step; a restart recomputes those of level n from u^n, so it continues an
+ * one-trajectory CP state with a dense stiffness carries lam .* (Bf^T u) .* (Cf^T u) from
+ * step to step; a restart recomputes it for level n from u^n, so it continues an
  * uninterrupted run to rounding rather than bit for bit.  Both synchronize. */
 rom_status rom_state_get(rom_ctx ctx, rom_state st, double *u_hist, double *y_hist,
                          int64_t *step);
