@@ -9,6 +9,7 @@ from .oracle import (  # noqa: F401
     nonlinear_dense,
     nonlinear_dense_rows,
     nonlinear_cp,
+    nonlinear_cp_skew,
     reconstruct,
     cholesky,
     chol_solve,

@@ -43,6 +43,7 @@ def _load():
     lib.orc_nonlinear_dense.argtypes = [_i64, _d, _d, _d]
     lib.orc_nonlinear_dense_rows.argtypes = [_i64, _d, _d, _i64, ctypes.POINTER(_i64), _d]
     lib.orc_nonlinear_cp.argtypes = [_i64, _i64, _d, _d, _d, _d, _d, _d]
+    lib.orc_nonlinear_cp_skew.argtypes = [_i64, _i64, _d, _d, _d, _d, _d, _d]
     lib.orc_reconstruct.argtypes = [_i64, _i64, _d, _d, _d, _d, _d]
     lib.orc_cholesky.argtypes = [_i64, _d, _d]
     lib.orc_cholesky.restype = ctypes.c_int
@@ -109,6 +110,23 @@ def nonlinear_cp(lam, Af, Bf, Cf, u) -> np.ndarray:
         ub = np.ascontiguousarray(uu[b])
         yb = np.empty(N)
         lib.orc_nonlinear_cp(N, R, _p(lam), _p(Af), _p(Bf), _p(Cf), _p(ub), _p(yb))
+        y[b] = yb
+    return y.reshape(u.shape)
+
+
+def nonlinear_cp_skew(lam, A11, A12, A21, u) -> np.ndarray:
+    """y = C(u)u for the skew-symmetry preserving CP form (Sec. 3.3, eq. skew_abc_struct):
+    factors [A11 A12], [A21 A21], [A12 -A11] with one weight per column pair; A11, A12,
+    A21 are [N][P], lam is [P]."""
+    lib = _load()
+    lam, A11, A12, A21, u = map(_c, (lam, A11, A12, A21, u))
+    N, P = A11.shape
+    uu = u.reshape(-1, N)
+    y = np.empty_like(uu)
+    for b in range(uu.shape[0]):
+        ub = np.ascontiguousarray(uu[b])
+        yb = np.empty(N)
+        lib.orc_nonlinear_cp_skew(N, P, _p(lam), _p(A11), _p(A12), _p(A21), _p(ub), _p(yb))
         y[b] = yb
     return y.reshape(u.shape)
 

@@ -91,6 +91,42 @@ void orc_nonlinear_cp(int64_t N, int64_t R, const double *lam, const double *Af,
     free(t);
 }
 
+/* CP contraction of a decomposition that keeps the partial skew-symmetry
+ * (Sec. 3.3, eq. skew_abc_struct): rank R = 2P with factor matrices
+ *   A^(1) = [A11 A12],  A^(2) = [A21 A21],  A^(3) = [A12 -A11]   (each block N x P)
+ * and one weight per pair of columns.  For pair p write a = A11[:,p], c = A12[:,p],
+ * b = A21[:,p]; its two rank-1 terms of eq. tc_ap give
+ *   y += lam_p (b^T u) (c^T u) a  +  lam_p (b^T u) (-(a^T u)) c,
+ * so with beta_p = b^T u, alpha_p = a^T u, gamma_p = c^T u:
+ *   y_i = sum_p lam_p beta_p (A11[i][p] gamma_p - A12[i][p] alpha_p).   5 N P flops. */
+void orc_nonlinear_cp_skew(int64_t N, int64_t P, const double *lam, const double *A11,
+                           const double *A12, const double *A21, const double *u, double *y)
+{
+    double *al = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    double *be = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    double *ga = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    for (int64_t p = 0; p < P; ++p) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int64_t k = 0; k < N; ++k) {
+            a += A11[k * P + p] * u[k];
+            b += A21[k * P + p] * u[k];
+            c += A12[k * P + p] * u[k];
+        }
+        al[p] = a;
+        be[p] = b;
+        ga[p] = c;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        double acc = 0.0;
+        for (int64_t p = 0; p < P; ++p)
+            acc += lam[p] * be[p] * (A11[i * P + p] * ga[p] - A12[i * P + p] * al[p]);
+        y[i] = acc;
+    }
+    free(al);
+    free(be);
+    free(ga);
+}
+
 /* Kruskal tensor (Sec. 2.3, eq. cpd, with weights):
  *   T[i][j][k] = sum_r lam_r Af[i][r] Bf[j][r] Cf[k][r]. */
 void orc_reconstruct(int64_t N, int64_t R, const double *lam, const double *Af,

@@ -125,6 +125,50 @@ def test_skew_paired_factors_give_skew_tensor(orc):
     assert np.allclose(D, T, rtol=0, atol=1e-14)
 
 
+def _skew_scale(lam, A11, A12, A21, u):
+    """sum over pairs of |lam beta| (|u.a| |gamma| + |u.c| |alpha|): the size of the
+    terms that cancel in u . y."""
+    al, be, ga = A11.T @ u, A21.T @ u, A12.T @ u
+    return float(np.sum(np.abs(lam * be) * (np.abs(u @ A11) * np.abs(ga) + np.abs(u @ A12) * np.abs(al))))
+
+
+def test_cp_skew_contraction(orc):
+    """Sec. 3.3, eq. skew_abc_struct: the pair form of the contraction equals the general
+    CP contraction of the expanded factors [A11 A12], [A21 A21], [A12 -A11] (and the
+    dense contraction of their Kruskal tensor), and u . y vanishes to rounding."""
+    rng = np.random.default_rng(21)
+    for N, P in [(11, 5), (6, 1), (17, 8)]:
+        lam = rng.standard_normal(P)
+        A11, A12, A21 = (rng.standard_normal((N, P)) for _ in range(3))
+        u = rng.standard_normal(N)
+        y = orc.nonlinear_cp_skew(lam, A11, A12, A21, u)
+        Af = np.hstack([A11, A12])
+        Bf = np.hstack([A21, A21])
+        Cf = np.hstack([A12, -A11])
+        lr = np.concatenate([lam, lam])
+        y_cp = orc.nonlinear_cp(lr, Af, Bf, Cf, u)
+        tol = 1e-13 * float(np.abs(lr) @ (np.abs(Bf.T @ u) * np.abs(Cf.T @ u))) * float(np.abs(Af).max())
+        assert np.max(np.abs(y - y_cp)) <= tol
+        y_d = orc.nonlinear_dense(orc.reconstruct(lr, Af, Bf, Cf), u)
+        assert np.max(np.abs(y - y_d)) <= 1e2 * tol
+        assert abs(u @ y) <= 1e-14 * _skew_scale(lam, A11, A12, A21, u)
+        # a sign error in the third factor breaks both the match and the cancellation
+        y_bad = orc.nonlinear_cp(lr, Af, Bf, np.hstack([A12, A11]), u)
+        assert np.max(np.abs(y_bad - y)) > 1e3 * tol
+
+
+def test_cp_skew_interleaved_generator(orc):
+    """The generator's interleaved pairs (columns 2p, 2p+1 = (a, b, c), (c, b, -a)) are
+    the structure of Sec. 3.3 up to a column permutation."""
+    lam, Af, Bf, Cf = romsynth.skew_cp_factors(13, 6, seed=4, cfg=9)
+    assert np.array_equal(Bf[:, 0::2], Bf[:, 1::2])
+    assert np.array_equal(Af[:, 1::2], Cf[:, 0::2]) and np.array_equal(Cf[:, 1::2], -Af[:, 0::2])
+    u = romsynth.initial_u(13, [4], cfg=9)[0]
+    y = orc.nonlinear_cp_skew(lam[0::2], Af[:, 0::2], Af[:, 1::2], Bf[:, 0::2], u)
+    y_cp = orc.nonlinear_cp(lam, Af, Bf, Cf, u)
+    assert np.allclose(y, y_cp, rtol=1e-12, atol=1e-13 * np.abs(y_cp).max())
+
+
 def test_rows_variant_matches_full(orc):
     C = romsynth.dense_rough(10, 4, cfg=5)
     u = romsynth.initial_u(10, [4], cfg=5)[0]
