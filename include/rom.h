@@ -154,15 +154,32 @@ rom_status rom_step_multi(int32_t n, const rom_ctx *ctxs, const rom_state *state
                           int64_t nsteps, int64_t *first_bad_step);
 
 /* Introspection.  what: 0 = device bytes held by the context, 1 = device bytes held by
- * the state, 2 = N, 3 = R (0 if dense), 4 = dtype, 5 = state batch, 6 = state step. */
+ * the state, 2 = N, 3 = R (0 if dense), 4 = dtype, 5 = state batch, 6 = state step,
+ * 7 = skew column-pair layout the one-trajectory CP kernels use (rom_cp_skew_layout's
+ * codes; 0 = general form). */
 rom_status rom_query(rom_ctx ctx, rom_state st, int32_t what, int64_t *value);
 
 /* Kernel tile selection (the autotuner's knob).  kind: 0 = dense single-trajectory
  * streaming contraction, 1 = dense batched MFMA contraction, 2 = CP projections,
- * 3 = CP scatter.  value: an index into that kernel's variant table (see
- * rom_tile_count); -1 restores the built-in heuristic.  Applies to later launches. */
+ * 3 = CP scatter, 4 = pair form of the one-trajectory CP projections (0 = general form,
+ * 1 = pair form, ROM_E_UNSUPPORTED if the factors have no skew column pairs).  value: an
+ * index into that kernel's variant table (see rom_tile_count); -1 restores the built-in
+ * choice (for kind 4: the pair form whenever the factors allow it).  Applies to later
+ * launches. */
 rom_status rom_set_tile(rom_ctx ctx, int32_t kind, int32_t value);
 int32_t rom_tile_count(int32_t kind);
+
+/* Skew column pairs of CP factors (Sec. 3.3, eq. skew_abc_struct), checked exactly on
+ * the host (no device work; callable without a GPU).  Pair p = (c0, c1) must satisfy
+ * lambda[c0] == lambda[c1], Bf[:,c0] == Bf[:,c1], Cf[:,c0] == Af[:,c1] and
+ * Cf[:,c1] == -Af[:,c0].  Returns 1 for c0 = 2p, c1 = 2p + 1 (interleaved pairs), 2 for
+ * c0 = p, c1 = R/2 + p (the paper's blocks [A1 A2], [B1 B1], [A2 -A1]), 0 otherwise
+ * (also for odd R or NULL arrays).  Arrays: host [N][R] factors, lambda [R].
+ * rom_create runs the same check: with pairs, the one-trajectory CP projections read the
+ * P distinct columns of Bf and the R columns of Af (1.5 N R values instead of 2 N R) and
+ * give the same result to the bit. */
+int32_t rom_cp_skew_layout(int32_t N, int32_t R, const double *lambda, const double *Af,
+                           const double *Bf, const double *Cf);
 
 const char *rom_last_error(void);
 

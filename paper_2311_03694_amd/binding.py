@@ -25,7 +25,7 @@ EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_timed", 
            "rom_state_destroy",
            "rom_step", "rom_step_async", "rom_step_sync", "rom_energy", "rom_state_get",
            "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
-           "rom_tile_count", "rom_last_error"]
+           "rom_tile_count", "rom_cp_skew_layout", "rom_last_error"]
 
 _d = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -91,6 +91,8 @@ def lib():
     L.rom_set_tile.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
     L.rom_tile_count.argtypes = [ctypes.c_int32]
     L.rom_tile_count.restype = ctypes.c_int32
+    L.rom_cp_skew_layout.argtypes = [ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _d]
+    L.rom_cp_skew_layout.restype = ctypes.c_int32
     L.rom_last_error.argtypes = []
     L.rom_last_error.restype = ctypes.c_char_p
     for name in ("rom_create", "rom_nonlinear", "rom_nonlinear_timed", "rom_state_create", "rom_step", "rom_step_async",
@@ -257,6 +259,13 @@ def rom_set_tile(ctx: int, kind: int, value: int):
 
 def rom_tile_count(kind: int) -> int:
     return int(lib().rom_tile_count(int(kind)))
+
+
+def rom_cp_skew_layout(lam, Af, Bf, Cf) -> int:
+    """Skew column pairs of CP factors (host only): 0 none, 1 interleaved, 2 blocked."""
+    lam, Af, Bf, Cf = (_host(x) for x in (lam, Af, Bf, Cf))
+    N, R = Af.shape
+    return int(lib().rom_cp_skew_layout(N, R, _ptr(lam), _ptr(Af), _ptr(Bf), _ptr(Cf)))
 
 
 def rom_last_error() -> str:

@@ -71,14 +71,103 @@ __device__ __forceinline__ void cp_proj1_body(const Proj1Job& jb, int blk) {
     if (lane == 0) reinterpret_cast<Acc*>(jb.w)[r] = reinterpret_cast<const Acc*>(jb.lam)[r] * z[0] * z[1];
 }
 
+// The same for factors that keep the partial skew-symmetry (Sec. 3.3, eq.
+// skew_abc_struct): column pair p = (c0, c1) has Bf[:,c1] = Bf[:,c0], Cf[:,c0] = Af[:,c1]
+// and Cf[:,c1] = -Af[:,c0], so with beta = Bf[:,c0]^T u, alpha = Af[:,c0]^T u and
+// gamma = Af[:,c1]^T u the pair's products are w[c0] = lam beta gamma and
+// w[c1] = lam beta (-alpha).  The operator holds the P distinct columns of Bf and the R
+// columns of Af as rows, [P + R][Np]: 1.5 R rows where the general form reads 2 R.  One
+// wavefront per pair (three rows); pair slots past P write the zero padding of w.  Each
+// dot product is computed as in cp_proj1_body.  In FP64 and FP32 the fused multiply-adds
+// round symmetrically, so -alpha is the negated dot product; the packed BF16 dot
+// instruction does not always give dot(-a, u) = -dot(a, u) to the bit, so the BF16
+// formats form -alpha as Af[:,c0]^T (-u) against a second LDS image of -u, which
+// presents it the same signed products as (-a) u.  So w is the general form's to the bit
+// in every format.
+template <int DT, int V, int U>
+__device__ __forceinline__ void cp_proj_skew_body(const Proj1Job& jb, int blk) {
+    typedef typename Store<DT>::T T;
+    typedef typename Store<DT>::Acc Acc;
+    constexpr int BYTES = V * (int)sizeof(T);
+    constexpr bool X3 = (DT == DT_BF16X3);
+    typedef typename RawT<BYTES>::T Raw;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int N = jb.N, Np = jb.Np, P = jb.P, R = jb.R;
+    constexpr bool NEGU = (DT == DT_BF16 || DT == DT_BF16X3);
+    LdsU<DT> L, Ln;                                      // u and (BF16 formats) -u
+    L.bind(smem, Np);
+    Ln.bind(smem + (NEGU ? LdsU<DT>::bytes(Np) : 0), Np);
+    const int lane = threadIdx.x % kWave;
+    const int q = blk * 4 + threadIdx.x / kWave;
+    const bool live = q < P;
+    const int c0 = jb.layout == 1 ? 2 * q : q, c1 = jb.layout == 1 ? 2 * q + 1 : P + q;
+    const size_t rows[3] = {(size_t)(live ? q : 0), (size_t)(live ? P + c0 : 0), (size_t)(live ? P + c1 : 0)};
+    const T* op = reinterpret_cast<const T*>(jb.BCt);
+    Raw rv[3][U], rl[3][U];
+    int k0 = lane * V;
+    auto issue = [&](int kb) {
+#pragma unroll
+        for (int h = 0; h < 3; ++h)
+#pragma unroll
+            for (int qq = 0; qq < U; ++qq) {
+                const int k = kb + qq * kWave * V;
+                if (live && k < Np) {
+                    rv[h][qq] = ld_plain<BYTES>(op + rows[h] * Np + k);
+                    if constexpr (X3) rl[h][qq] = ld_plain<BYTES>(jb.BCt_lo + rows[h] * Np + k);
+                }
+            }
+    };
+    issue(k0);
+    const double* ub = jb.u_base + (jb.stepp ? (size_t)slot_of(*jb.stepp) * jb.slot_stride : 0);
+    L.fill(ub, N, Np);
+    if constexpr (NEGU) Ln.fill(ub, N, Np, -1.0);
+    __syncthreads();
+    Acc* w = reinterpret_cast<Acc*>(jb.w);
+    if (!live) {
+        const int e = R + 2 * (q - P);                  // zero padding of w past R
+        if (lane == 0 && e < jb.Rp) {
+            w[e] = 0;
+            if (e + 1 < jb.Rp) w[e + 1] = 0;
+        }
+        return;
+    }
+    Acc z[3] = {0, 0, 0};                                // beta, -alpha, gamma
+    while (k0 < Np) {
+#pragma unroll
+        for (int qq = 0; qq < U; ++qq) {
+            const int k = k0 + qq * kWave * V;
+            if (k < Np) {
+                z[0] += dot_vec<DT, V>(rv[0][qq], rl[0][qq], L, k);
+                z[1] += dot_vec<DT, V>(rv[1][qq], rl[1][qq], NEGU ? Ln : L, k);
+                z[2] += dot_vec<DT, V>(rv[2][qq], rl[2][qq], L, k);
+            }
+        }
+        k0 += kWave * V * U;
+        if (k0 < Np) issue(k0);
+    }
+#pragma unroll
+    for (int h = 0; h < 3; ++h) z[h] = wave_sum(z[h]);
+    if (lane == 0) {
+        const Acc* lam = reinterpret_cast<const Acc*>(jb.lam);
+        w[c0] = lam[c0] * z[0] * z[2];
+        w[c1] = lam[c1] * z[0] * (NEGU ? z[1] : -z[1]);
+    }
+}
+
+template <int DT, int V, int U>
+__device__ __forceinline__ void cp_proj_any_body(const Proj1Job& jb, int blk) {
+    if (jb.layout) cp_proj_skew_body<DT, V, U>(jb, blk);
+    else cp_proj1_body<DT, V, U>(jb, blk);
+}
+
 template <int DT, int V, int U>
 __global__ __launch_bounds__(256) void k_cp_proj1(Proj1Job jb) {
-    cp_proj1_body<DT, V, U>(jb, blockIdx.x);
+    cp_proj_any_body<DT, V, U>(jb, blockIdx.x);
 }
 template <int DT, int V, int U>
 __global__ __launch_bounds__(256) void k_cp_proj1_group(const Proj1Job* __restrict__ jobs, int njobs) {
     const int p = find_job(jobs, njobs, (int)blockIdx.x);
-    cp_proj1_body<DT, V, U>(jobs[p], (int)blockIdx.x - jobs[p].blk0);
+    cp_proj_any_body<DT, V, U>(jobs[p], (int)blockIdx.x - jobs[p].blk0);
 }
 
 // Scatter: W = lam .* s .* t staged in LDS, then y_i = sum_r Af[i][r] W_r, one
@@ -223,7 +312,8 @@ __device__ __forceinline__ void helm_proj_body(const HelmJob& jb, long long n, i
     }
     typedef typename Store<DT>::T T;
     constexpr int V = 16 / (int)sizeof(T);
-    const size_t mstride = (size_t)(bdf_order(n) - 1) * 2 * jb.Rp * jb.a.Np;
+    const size_t rows = jb.layout ? (size_t)(jb.P + jb.R) : (size_t)2 * jb.Rp;
+    const size_t mstride = (size_t)(bdf_order(n) - 1) * rows * jb.a.Np;
     Proj1Job pj{};
     pj.BCt = reinterpret_cast<const T*>(jb.Mst) + mstride;
     pj.BCt_lo = jb.Mst_lo ? jb.Mst_lo + mstride : nullptr;
@@ -231,9 +321,12 @@ __device__ __forceinline__ void helm_proj_body(const HelmJob& jb, long long n, i
     pj.N = jb.a.N;
     pj.Np = jb.a.Np;
     pj.Rp = jb.Rp;
+    pj.layout = jb.layout;
+    pj.P = jb.P;
+    pj.R = jb.R;
     pj.u_base = jb.a.rhs;
     pj.w = jb.a.st;
-    cp_proj1_body<DT, V, 4>(pj, blk - jb.nh);
+    cp_proj_any_body<DT, V, 4>(pj, blk - jb.nh);
 }
 
 // One state: nh + np blocks and a last one that closes the previous level and advances
@@ -261,10 +354,17 @@ __global__ __launch_bounds__(256) void k_helm_proj_group(const HelmJob* __restri
 
 // ---------------------------------------------------------------- launchers
 
+// LDS of the projection kernels: the image of u, and for the BF16 formats a second one
+// of -u (read by the pair form).
+template <int DT>
+static size_t proj_lds(int Np) {
+    return (DT == DT_BF16 || DT == DT_BF16X3 ? 2 : 1) * LdsU<DT>::bytes(Np);
+}
+
 template <int DT>
 static void proj1_go(const Proj1Job& jb, const Proj1Job* jobs, int njobs, int blocks, int Npmax, hipStream_t s) {
     constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
-    const size_t lds = LdsU<DT>::bytes(Npmax);
+    const size_t lds = proj_lds<DT>(Npmax);
     if (jobs) hipLaunchKernelGGL((k_cp_proj1_group<DT, V, 4>), dim3((unsigned)blocks), dim3(256), lds, s, jobs, njobs);
     else hipLaunchKernelGGL((k_cp_proj1<DT, V, 4>), dim3((unsigned)jb.nblk), dim3(256), lds, s, jb);
 }
@@ -279,8 +379,12 @@ static void proj1_dispatch(int dt, const Proj1Job& jb, const Proj1Job* jobs, int
     }
 }
 
+// Blocks of the projection kernel: four row pairs of [Bf|Cf]^T, or four column pairs
+// of the pair form, per block.
+int proj1_blocks(int Rp, SkewPairs sk) { return sk.layout ? (Rp / 2 + 3) / 4 : (Rp + 3) / 4; }
+
 int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, const void* lam, int N, int Np, int Rp,
-                    const double* u_base, const long long* stepp, long long slot_stride,
+                    SkewPairs sk, const double* u_base, const long long* stepp, long long slot_stride,
                     void* w, hipStream_t s) {
     Proj1Job jb{};
     jb.BCt = BCt;
@@ -289,11 +393,14 @@ int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, const void* lam
     jb.N = N;
     jb.Np = Np;
     jb.Rp = Rp;
+    jb.layout = sk.layout;
+    jb.P = sk.P;
+    jb.R = sk.R;
     jb.u_base = u_base;
     jb.stepp = stepp;
     jb.slot_stride = slot_stride;
     jb.w = w;
-    jb.nblk = (Rp + 3) / 4;
+    jb.nblk = proj1_blocks(Rp, sk);
     proj1_dispatch(dt, jb, nullptr, 0, 0, Np, s);
     return 0;
 }
@@ -354,7 +461,8 @@ void launch_cp_scatter1_group(int dt, int mode, const Scat1Job* jobs_dev, int nj
 
 template <int DT>
 static size_t helm_proj_lds(int N, int Np, bool proj) {
-    const size_t h = sizeof(double) * (size_t)N, q = proj ? LdsU<DT>::bytes(Np) : 0;
+    // projections: images of u and (BF16 formats, pair form) -u
+    const size_t h = sizeof(double) * (size_t)N, q = proj ? proj_lds<DT>(Np) : 0;
     return h > q ? h : q;
 }
 

@@ -41,11 +41,11 @@ template <int DT> struct LdsU {
         }
     }
 
-    // Convert u (FP64, N values) into an image of Np >= N entries, zero beyond N; call
-    // with the whole block, then __syncthreads.
-    __device__ void fill(const double* __restrict__ u, int N, int Np) {
+    // Convert sgn * u (FP64, N values, sgn = +1 or -1) into an image of Np >= N entries,
+    // zero beyond N; call with the whole block, then __syncthreads.
+    __device__ void fill(const double* __restrict__ u, int N, int Np, double sgn = 1.0) {
         staged_copy<8, double>(
-            Np, [&](int q) { return q < N ? u[q] : 0.0; },
+            Np, [&](int q) { return q < N ? sgn * u[q] : 0.0; },
             [&](int q, double v) {
                 if constexpr (DT == DT_F64) {
                     uh[q] = v;

@@ -76,6 +76,12 @@ struct rom_ctx_s {
     void* lam = nullptr;                        // CP [Rp] (FP64 or FP32)
     // CP with a dense stiffness: [Bf|Cf]^T Hinv_k for k = 1, 2, 3, [3][2Rp][Np]
     void *Mst = nullptr, *Mst_lo = nullptr;
+    // CP factors with skew column pairs (skew_layout 1 or 2): the pair form of the
+    // projection operator, [P + R][Np] (the P distinct columns of Bf, then the R columns of
+    // Af, as rows), and with a dense stiffness its product with Hinv_k, [3][P + R][Np]
+    int skew_layout = 0;
+    void *SK = nullptr, *SK_lo = nullptr;
+    void *Msk = nullptr, *Msk_lo = nullptr;
     double* hdiag = nullptr;                    // [3][N]
     double* hinv = nullptr;                     // [3][N][N]
     // workspaces (shared by every state of the context; one stream serializes use)
@@ -83,7 +89,8 @@ struct rom_ctx_s {
     size_t ws_bytes = 0;
     int ws_gen = 0;
     // tiles (-1 = heuristic)
-    int tile[4] = {-1, -1, -1, -1};
+    // tile[4]: CP pair-form kernels (-1 default = on when the factors have skew pairs, 0 off)
+    int tile[5] = {-1, -1, -1, -1, -1};
     size_t lds_max = 65536;                     // dynamic LDS a batched kernel may take
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -289,6 +296,75 @@ static rom_status upload_convert(rom_ctx c, const double* host, size_t rows, int
     return ROM_OK;
 }
 
+// Every operator allocation ends in kSlack zero bytes: the batched kernels' lane vectors
+// may run up to one k-step past the last row (they meet zero weights).
+static constexpr size_t kSlack = 256;
+
+// Column pairs of CP factors that keep the partial skew-symmetry (Sec. 3.3, eq.
+// skew_abc_struct): pair p = (c0, c1) with lam[c0] == lam[c1], Bf[:,c0] == Bf[:,c1],
+// Cf[:,c0] == Af[:,c1] and Cf[:,c1] == -Af[:,c0], exactly.  1: c0 = 2p, c1 = 2p + 1
+// (interleaved pairs); 2: c0 = p, c1 = R/2 + p (the paper's blocks); 0: neither.
+static int skew_layout_of(int N, int R, const double* lam, const double* Af, const double* Bf, const double* Cf) {
+    if (N < 1 || R < 2 || R % 2 != 0 || !lam || !Af || !Bf || !Cf) return 0;
+    const int P = R / 2;
+    for (int layout = 1; layout <= 2; ++layout) {
+        bool ok = true;
+        for (int p = 0; p < P && ok; ++p) {
+            const int c0 = layout == 1 ? 2 * p : p, c1 = layout == 1 ? 2 * p + 1 : P + p;
+            ok = lam[c0] == lam[c1];
+            for (int n = 0; n < N && ok; ++n) {
+                const size_t o = (size_t)n * R;
+                ok = Bf[o + c0] == Bf[o + c1] && Cf[o + c0] == Af[o + c1] && Cf[o + c1] == -Af[o + c0];
+            }
+        }
+        if (ok) return layout;
+    }
+    return 0;
+}
+
+// dst[k] = rows x Hinv_{k+1} for k = 0, 1, 2 ([3][rows][Np] in the contraction format):
+// FP64 rows of length Np (zero padded) times the symmetric Hinv_k on the matrix cores,
+// then one conversion.  Allocates dst (and dst_lo for BF16X3) in the context.
+static rom_status hinv_products(rom_ctx c, const double* host_rows, size_t rows, void** dst, void** dst_lo) {
+    const size_t N = c->N, Np = c->Np, eb = elem_bytes(c->dtype);
+    const size_t rows16 = (rows + 15) / 16 * 16;        // the product's column tiles
+    rom_status st = dmalloc(dst, 3 * rows * Np * eb + kSlack, &c->bytes, &c->allocs);
+    if (st != ROM_OK) return st;
+    HIPCHK(hipMemsetAsync(*dst, 0, 3 * rows * Np * eb + kSlack, c->stream));
+    if (dst_lo) {
+        st = dmalloc(dst_lo, 3 * rows * Np * 2 + kSlack, &c->bytes, &c->allocs);
+        if (st != ROM_OK) return st;
+        HIPCHK(hipMemsetAsync(*dst_lo, 0, 3 * rows * Np * 2 + kSlack, c->stream));
+    }
+    double *x_d = nullptr, *y_d = nullptr;
+    hipError_t e = hipMalloc((void**)&x_d, sizeof(double) * rows16 * Np);
+    if (e == hipSuccess) e = hipMalloc((void**)&y_d, sizeof(double) * rows16 * N);
+    if (e == hipSuccess) e = hipMemsetAsync(x_d, 0, sizeof(double) * rows16 * Np, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(x_d, host_rows, sizeof(double) * rows * Np, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        const GemmPlan pl = gemm_plan((int)N, (int)rows16, 0);
+        for (int k = 0; k < 3; ++k) {
+            launch_gemm_f64(pl, c->hinv + (size_t)k * N * Np, (long long)Np, x_d, (long long)Np, y_d, (int)N,
+                            (int)Np, (int)rows16, c->stream);
+            launch_cvt_f64_to(c->dtype, y_d, (char*)*dst + (size_t)k * rows * Np * eb,
+                              dst_lo ? (char*)*dst_lo + (size_t)k * rows * Np * 2 : nullptr, (long long)rows, (int)N,
+                              (int)Np, c->stream);
+        }
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (x_d) hipFree(x_d);
+    if (y_d) hipFree(y_d);
+    if (e != hipSuccess) return fail(ROM_E_DEVICE, "setup of the projection operators failed: %s", hipGetErrorString(e));
+    return ROM_OK;
+}
+
+extern "C" int32_t rom_cp_skew_layout(int32_t N, int32_t R, const double* lambda, const double* Af, const double* Bf,
+                                      const double* Cf) {
+    return skew_layout_of(N, R, lambda, Af, Bf, Cf);
+}
+
 extern "C" void rom_destroy(rom_ctx c) {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
@@ -439,9 +515,6 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
     const size_t eb = elem_bytes(dt);
     const bool lo = dt == DT_BF16X3;
     const size_t Np = c->Np;
-    // every operator allocation ends in kSlack zero bytes: the batched kernels' lane
-    // vectors may run up to one k-step past the last row (they meet zero weights)
-    const size_t kSlack = 256;
     if (c->dense) {
         const size_t n3 = nn * Np;
         TRY(dmalloc(&c->C, n3 * eb + kSlack, &c->bytes, &c->allocs));
@@ -492,8 +565,7 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
         HTRY(hipGetLastError());
         if (!c->diagA) {
             // [Bf|Cf]^T Hinv_k for the one-trajectory step (the projections of u^{n+1}
-            // straight from the right-hand side): FP64 rows of [Bf|Cf]^T, zero padded,
-            // times the symmetric Hinv_k on the matrix cores, then the contraction format
+            // straight from the right-hand side)
             const size_t rows2 = 2 * Rp;
             std::vector<double> bt(rows2 * Np, 0.0);
             for (size_t n = 0; n < (size_t)N; ++n)
@@ -501,35 +573,37 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
                     bt[r * Np + n] = d->Bf[n * R + r];
                     bt[(Rp + r) * Np + n] = d->Cf[n * R + r];
                 }
-            TRY(dmalloc(&c->Mst, 3 * rows2 * Np * eb + kSlack, &c->bytes, &c->allocs));
-            HTRY(hipMemsetAsync(c->Mst, 0, 3 * rows2 * Np * eb + kSlack, c->stream));
-            if (lo) {
-                TRY(dmalloc(&c->Mst_lo, 3 * rows2 * Np * 2 + kSlack, &c->bytes, &c->allocs));
-                HTRY(hipMemsetAsync(c->Mst_lo, 0, 3 * rows2 * Np * 2 + kSlack, c->stream));
-            }
-            double *bt_d = nullptr, *tmp_d = nullptr;
-            hipError_t e = hipMalloc((void**)&bt_d, sizeof(double) * rows2 * Np);
-            if (e == hipSuccess) e = hipMalloc((void**)&tmp_d, sizeof(double) * rows2 * N);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(bt_d, bt.data(), sizeof(double) * rows2 * Np, hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) {
-                const GemmPlan pl = gemm_plan((int)N, (int)rows2, 0);
-                for (int k = 0; k < 3; ++k) {
-                    launch_gemm_f64(pl, c->hinv + (size_t)k * N * Np, (long long)Np, bt_d, (long long)Np, tmp_d,
-                                    (int)N, (int)Np, (int)rows2, c->stream);
-                    launch_cvt_f64_to(dt, tmp_d, (char*)c->Mst + (size_t)k * rows2 * Np * eb,
-                                      lo ? (char*)c->Mst_lo + (size_t)k * rows2 * Np * 2 : nullptr, (long long)rows2,
-                                      (int)N, (int)Np, c->stream);
-                }
-                e = hipGetLastError();
-                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-            }
-            if (bt_d) hipFree(bt_d);
-            if (tmp_d) hipFree(tmp_d);
-            if (e != hipSuccess) {
-                st = fail(ROM_E_DEVICE, "setup of the projection operators failed: %s", hipGetErrorString(e));
+            st = hinv_products(c, bt.data(), rows2, &c->Mst, lo ? &c->Mst_lo : nullptr);
+            if (st != ROM_OK) {
                 rom_destroy(c);
                 return st;
+            }
+        }
+        // Skew column pairs (Sec. 3.3, eq. skew_abc_struct): the pair form of the
+        // projection operator, rows [Bf[:, c0(p)] for p < P; Af[:, r] for r < R]
+        c->skew_layout = skew_layout_of((int)N, (int)R, d->lambda, d->Af, d->Bf, d->Cf);
+        if (c->skew_layout) {
+            const size_t P = R / 2, rows = P + R;
+            std::vector<double> sk(rows * Np, 0.0);
+            for (size_t p2 = 0; p2 < P; ++p2) {
+                const size_t c0 = c->skew_layout == 1 ? 2 * p2 : p2;
+                for (size_t n = 0; n < (size_t)N; ++n) sk[p2 * Np + n] = d->Bf[n * R + c0];
+            }
+            for (size_t r = 0; r < R; ++r)
+                for (size_t n = 0; n < (size_t)N; ++n) sk[(P + r) * Np + n] = d->Af[n * R + r];
+            TRY(dmalloc(&c->SK, rows * Np * eb + kSlack, &c->bytes, &c->allocs));
+            HTRY(hipMemsetAsync(c->SK, 0, rows * Np * eb + kSlack, c->stream));
+            if (lo) {
+                TRY(dmalloc(&c->SK_lo, rows * Np * 2 + kSlack, &c->bytes, &c->allocs));
+                HTRY(hipMemsetAsync(c->SK_lo, 0, rows * Np * 2 + kSlack, c->stream));
+            }
+            TRY(upload_convert(c, sk.data(), rows, (int)Np, (int)Np, c->SK, c->SK_lo, stage, stage_elems));
+            if (!c->diagA) {
+                st = hinv_products(c, sk.data(), rows, &c->Msk, lo ? &c->Msk_lo : nullptr);
+                if (st != ROM_OK) {
+                    rom_destroy(c);
+                    return st;
+                }
             }
         }
     }
@@ -551,6 +625,20 @@ static StepArgs step_args(rom_state s, long long n) {
     return a;
 }
 
+// The skew column pairs the one-trajectory CP kernels use (layout 0: the general form),
+// and the matching projection operator.
+static SkewPairs skew_of(rom_ctx c) {
+    SkewPairs sk{};
+    if (!c->dense && c->skew_layout && c->tile[4] != 0) {
+        sk.layout = c->skew_layout;
+        sk.P = c->R / 2;
+        sk.R = c->R;
+    }
+    return sk;
+}
+static const void* proj_op(rom_ctx c) { return skew_of(c).layout ? c->SK : c->BCt; }
+static const void* proj_op_lo(rom_ctx c) { return skew_of(c).layout ? c->SK_lo : c->BCt_lo; }
+
 // The Helmholtz apply of a one-trajectory state (with the projections of the new level
 // when the context is CP).
 static HelmJob helm_job(rom_ctx c, const StepArgs& a) {
@@ -558,11 +646,15 @@ static HelmJob helm_job(rom_ctx c, const StepArgs& a) {
     h.a = a;
     h.nh = (c->N + 3) / 4;
     if (!c->dense) {
-        h.Mst = c->Mst;
-        h.Mst_lo = (const unsigned short*)c->Mst_lo;
+        const SkewPairs sk = skew_of(c);
+        h.Mst = sk.layout ? c->Msk : c->Mst;
+        h.Mst_lo = (const unsigned short*)(sk.layout ? c->Msk_lo : c->Mst_lo);
         h.lam = c->lam;
         h.Rp = c->Rp;
-        h.np = (c->Rp + 3) / 4;
+        h.layout = sk.layout;
+        h.P = sk.P;
+        h.R = sk.R;
+        h.np = proj1_blocks(c->Rp, sk);
     }
     h.nblk = h.nh + h.np;
     return h;
@@ -573,8 +665,8 @@ static HelmJob helm_job(rom_ctx c, const StepArgs& a) {
 // level).
 static void seed_projections(rom_ctx c, const StepArgs& a, hipStream_t stream) {
     if (c->dense || c->diagA || a.B != 1) return;
-    launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->lam, c->N, c->Np, c->Rp, a.uring, a.step, (long long)c->N,
-                    a.st, stream);
+    launch_cp_proj1(c->dtype, proj_op(c), proj_op_lo(c), c->lam, c->N, c->Np, c->Rp, skew_of(c), a.uring, a.step,
+                    (long long)c->N, a.st, stream);
 }
 
 // Enqueue one BDF3/EXT3 step of state s from level n on `stream`: contraction (dense
@@ -595,8 +687,8 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
             // a.st holds w = lam .* s .* t of level n: computed here with a diagonal
             // stiffness, left by the previous step's Helmholtz kernel otherwise
             if (diag)
-                launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->lam, c->N, c->Np, c->Rp, a.uring, a.step,
-                                (long long)c->N, a.st, stream);
+                launch_cp_proj1(c->dtype, proj_op(c), proj_op_lo(c), c->lam, c->N, c->Np, c->Rp, skew_of(c),
+                                a.uring, a.step, (long long)c->N, a.st, stream);
             launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->N, c->Rp, a.st, nullptr, &a, diag ? 1 : 2, stream);
         }
     } else {
@@ -658,8 +750,8 @@ static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, 
                 launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, u_dev, nullptr, 0, ws + p.part_off, p.nchunk,
                                   gemv_tile(c), c->stream);
             } else {
-                launch_cp_proj1(c->dtype, c->BCt, c->BCt_lo, c->lam, c->N, c->Np, c->Rp, u_dev, nullptr, 0,
-                                ws + p.part_off, c->stream);
+                launch_cp_proj1(c->dtype, proj_op(c), proj_op_lo(c), c->lam, c->N, c->Np, c->Rp, skew_of(c), u_dev,
+                                nullptr, 0, ws + p.part_off, c->stream);
                 launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->N, c->Rp, ws + p.part_off, y_dev, nullptr, 0,
                                    c->stream);
             }
@@ -1201,18 +1293,22 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
             // Helmholtz kernel (phase 3)
             if (diag) {
                 Proj1Job pj{};
-                pj.BCt = c->BCt;
-                pj.BCt_lo = (const unsigned short*)c->BCt_lo;
+                const SkewPairs sk = skew_of(c);
+                pj.BCt = proj_op(c);
+                pj.BCt_lo = (const unsigned short*)proj_op_lo(c);
                 pj.lam = c->lam;
                 pj.N = c->N;
                 pj.Np = c->Np;
                 pj.Rp = c->Rp;
+                pj.layout = sk.layout;
+                pj.P = sk.P;
+                pj.R = sk.R;
                 pj.u_base = sa.uring;
                 pj.stepp = sa.step;
                 pj.slot_stride = c->N;
                 pj.w = sa.st;
                 pj.blk0 = g->b1;
-                pj.nblk = (c->Rp + 3) / 4;
+                pj.nblk = proj1_blocks(c->Rp, sk);
                 g->b1 += pj.nblk;
                 g->proj.push_back(pj);
             }
@@ -1334,6 +1430,7 @@ extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* v
         case 4: if (!c) break; *value = c->dtype; return ROM_OK;
         case 5: if (!s) break; *value = s->B; return ROM_OK;
         case 6: if (!s) break; *value = s->h_step; return ROM_OK;
+        case 7: if (!c) break; *value = skew_of(c).layout; return ROM_OK;
         default: return fail(ROM_E_INVALID, "unknown query %d", what);
     }
     return fail(ROM_E_INVALID, "query %d needs a %s", what, what == 1 || what >= 5 ? "state" : "context");
@@ -1344,14 +1441,17 @@ extern "C" int32_t rom_tile_count(int32_t kind) {
         case 0: return dense_gemv_variants();
         case 1: return dense_batched_variants();
         case 2: case 3: return gemm_variants() + mfma_variants();
+        case 4: return 2;
         default: return 0;
     }
 }
 
 extern "C" rom_status rom_set_tile(rom_ctx c, int32_t kind, int32_t value) {
     if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
-    if (kind < 0 || kind > 3) return fail(ROM_E_INVALID, "unknown kernel kind %d", kind);
+    if (kind < 0 || kind > 4) return fail(ROM_E_INVALID, "unknown kernel kind %d", kind);
     if (value < -1 || value >= rom_tile_count(kind)) return fail(ROM_E_INVALID, "tile index %d out of range", value);
+    if (kind == 4 && value == 1 && !c->skew_layout)
+        return fail(ROM_E_UNSUPPORTED, "the CP factors have no skew column pairs");
     c->tile[kind] = value;
     c->ws_gen++;   // captured graphs bake tile shapes: force a recapture
     return ROM_OK;

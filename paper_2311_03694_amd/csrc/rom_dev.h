@@ -72,10 +72,11 @@ struct GemvJob {           // dense contraction, one trajectory
     int blk0, nblk;
 };
 struct Proj1Job {          // CP projections and their Hadamard product, one trajectory
-    const void* BCt;
+    const void* BCt;               // layout 0: [Bf|Cf]^T [2Rp][Np]; else the pair form [P + R][Np]
     const unsigned short* BCt_lo;
     const void* lam;
     int N, Np, Rp;
+    int layout, P, R;              // skew column pairs (0 none, 1 interleaved, 2 blocked), R = 2P
     const double* u_base;
     const long long* stepp;
     long long slot_stride;
@@ -104,6 +105,7 @@ struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory; w
     const unsigned short* Mst_lo;  // BF16X3 low words of Mst
     const void* lam;               // CP: lam [Rp] (accumulation type)
     int Rp;
+    int layout, P, R;              // skew column pairs of the factors (Mst in the pair form)
     int nh, np;                    // row blocks of the Helmholtz part, of the projections (0: none)
     int blk0, nblk;                // grouped launches: first block, blocks (nh + np)
 };
@@ -164,9 +166,11 @@ struct MfmaPlan {
 
 // CP, one trajectory.
 // st [2Rp]: s then t; factors padded to Np / Rp with zeros.
+struct SkewPairs { int layout, P, R; };   // layout 0: general factors
 int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, const void* lam, int N, int Np, int Rp,
-                    const double* u_base, const long long* stepp, long long slot_stride,
+                    SkewPairs sk, const double* u_base, const long long* stepp, long long slot_stride,
                     void* w, hipStream_t s);
+int proj1_blocks(int Rp, SkewPairs sk);
 int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, int N, int Rp, const void* w, double* y_out,
                        const StepArgs* sa, int mode, hipStream_t s);
 

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import paper_2311_03694_amd as rg
+import romsynth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -61,3 +62,21 @@ def test_null_handles_rejected():
         rg.rom_query(None, None, 0)
     assert rg.rom_tile_count(0) >= 1
     assert rg.rom_tile_count(99) == 0
+
+
+def test_cp_skew_layout_host_check():
+    """Skew column pairs (Sec. 3.3, eq. skew_abc_struct) are recognised exactly on the
+    host: the generator's interleaved pairs, the paper's blocks, and nothing else."""
+    lam, Af, Bf, Cf = romsynth.skew_cp_factors(9, 5, seed=1, cfg=3)
+    assert rg.rom_cp_skew_layout(lam, Af, Bf, Cf) == 1
+    perm = np.concatenate([np.arange(0, 10, 2), np.arange(1, 10, 2)])     # pairs -> blocks
+    assert rg.rom_cp_skew_layout(lam[perm], Af[:, perm], Bf[:, perm], Cf[:, perm]) == 2
+    Cb = Cf.copy()
+    Cb[4, 3] = np.nextafter(Cb[4, 3], np.inf)                             # one ulp off
+    assert rg.rom_cp_skew_layout(lam, Af, Bf, Cb) == 0
+    lb = lam.copy()
+    lb[1] *= 2.0
+    assert rg.rom_cp_skew_layout(lb, Af, Bf, Cf) == 0
+    assert rg.rom_cp_skew_layout(lam[:9], Af[:, :9], Bf[:, :9], Cf[:, :9]) == 0   # odd rank
+    rng = np.random.default_rng(0)
+    assert rg.rom_cp_skew_layout(*(rng.standard_normal(s) for s in [(6,), (9, 6), (9, 6), (9, 6)])) == 0

@@ -1,0 +1,131 @@
+"""The pair form of the one-trajectory CP projections (Sec. 3.3, eq. skew_abc_struct):
+with skew column pairs the kernels read the P distinct columns of Bf and the R columns
+of Af instead of [Bf|Cf], and every result equals the general form's to the bit (both
+for the evaluation and for trajectories, with a diagonal and a dense stiffness, in
+every format, for the generator's interleaved pairs and the paper's blocks, alone and
+in grouped launches); both match the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2311_03694_amd as rg
+import romsynth
+from helpers import EVAL_TOL, TRAJ_TOL, check_eval, eval_bound_cp, rel
+
+pytestmark = pytest.mark.gpu
+
+DTS = ["fp64", "fp32", "bf16", "bf16x3"]
+KIND_PAIR = 4
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _blocked(p):
+    """The same factors with the pairs as the paper's blocks [A1 A2], [B1 B1], [A2 -A1]."""
+    R = p.Af.shape[1]
+    perm = np.concatenate([np.arange(0, R, 2), np.arange(1, R, 2)])
+    return p.lam[perm].copy(), p.Af[:, perm].copy(), p.Bf[:, perm].copy(), p.Cf[:, perm].copy()
+
+
+def _rom(p, dt, factors=None):
+    lam, Af, Bf, Cf = factors if factors is not None else (p.lam, p.Af, p.Bf, p.Cf)
+    return rg.Rom(p.N, p.nu, p.dt, p.A, lam=lam, Af=Af, Bf=Bf, Cf=Cf, dtype=dt, max_batch=1)
+
+
+def _eval(torch, rom, u):
+    ud = torch.tensor(np.atleast_2d(u), dtype=torch.float64, device="cuda")
+    yd = torch.empty_like(ud)
+    torch.cuda.synchronize()
+    rg.rom_nonlinear(rom.handle, 1, ud, yd)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()[0]
+
+
+def _traj(rom, u0, steps):
+    s = rom.state(u0)
+    s.step(steps)
+    uh, yh, n = s.get()
+    _, Elog = s.energy()
+    s.close()
+    return uh, yh, Elog
+
+
+@pytest.mark.parametrize("layout", ["interleaved", "blocked"])
+@pytest.mark.parametrize("A", ["diag", "spd"])
+@pytest.mark.parametrize("dt", DTS)
+def test_pair_form_equals_general_form(torch_gpu, dt, A, layout):
+    _say(f"pair form {layout} A={A} {dt}")
+    p = romsynth.make_problem(52, pairs=26, eps=1e-6, nu=1e-3, dt=1e-3, A=A, cfg=61, dense=False, cp=True)
+    factors = _blocked(p) if layout == "blocked" else None
+    rom = _rom(p, dt, factors)
+    assert rg.rom_query(rom.handle, None, 7) == (2 if layout == "blocked" else 1)
+    u = p.u0[0]
+    y_pair = _eval(torch_gpu, rom, u)
+    t_pair = _traj(rom, u, 131)
+    rg.rom_set_tile(rom.handle, KIND_PAIR, 0)
+    assert rg.rom_query(rom.handle, None, 7) == 0
+    y_gen = _eval(torch_gpu, rom, u)
+    t_gen = _traj(rom, u, 131)
+    assert np.array_equal(y_pair, y_gen)
+    for a, b in zip(t_pair, t_gen):
+        assert np.array_equal(a, b)
+    # and the oracle, in the pair form of the definition (BF16: on BF16-rounded operands,
+    # whose products the kernels form exactly)
+    lam, Af, Bf, Cf = factors if factors is not None else (p.lam, p.Af, p.Bf, p.Cf)
+    ops = [p.lam[0::2], p.Af[:, 0::2], p.Af[:, 1::2], p.Bf[:, 0::2], u]
+    if dt == "bf16":
+        ops = [orc.round_bf16(a).reshape(np.shape(a)) for a in ops]
+    y_ref = orc.nonlinear_cp_skew(*ops)
+    check_eval(dt, y_pair, y_ref, eval_bound_cp(dt, lam, Af, Bf, Cf, u))
+    ref = orc.run(p.N, p.nu, p.dt, p.A, 131, u0=u, lam=lam, Af=Af, Bf=Bf, Cf=Cf)
+    assert rel(t_pair[0][0][0], ref["u_hist"][0]) < TRAJ_TOL[dt]
+    rom.close()
+
+
+def test_pair_form_off_without_pairs(torch_gpu):
+    _say("general factors: no pair form")
+    p = romsynth.make_problem(40, pairs=20, eps=1e-6, cfg=62, dense=False, cp=True)
+    Cf = p.Cf.copy()
+    Cf[3, 5] += 1e-9
+    rom = _rom(p, "fp32", (p.lam, p.Af, p.Bf, Cf))
+    assert rg.rom_query(rom.handle, None, 7) == 0
+    with pytest.raises(rg.RomError) as ei:
+        rg.rom_set_tile(rom.handle, KIND_PAIR, 1)
+    assert ei.value.status == rg.binding.ROM_E_UNSUPPORTED
+    u = p.u0[0]
+    check_eval("fp32", _eval(torch_gpu, rom, u), orc.nonlinear_cp(p.lam, p.Af, p.Bf, Cf, u),
+               eval_bound_cp("fp32", p.lam, p.Af, p.Bf, Cf, u))
+    rom.close()
+
+
+def test_pair_form_in_grouped_launches(torch_gpu):
+    """rom_step_multi over a pair-form context, a general-form context (the same factors)
+    and a blocked-layout context: each equals its run alone, and the first two agree."""
+    _say("grouped launches with pair-form and general-form contexts")
+    p = romsynth.make_problem(48, pairs=24, eps=1e-6, nu=1e-3, dt=1e-3, A="spd", cfg=63, dense=False, cp=True)
+    roms = [_rom(p, "fp32"), _rom(p, "fp32"), _rom(p, "fp32", _blocked(p))]
+    rg.rom_set_tile(roms[1].handle, KIND_PAIR, 0)
+    u0 = p.u0[0]
+    multi = [r.state(u0) for r in roms]
+    rg.rom_step_multi([r.handle for r in roms], [s.handle for s in multi], 120)
+    for r, s in zip(roms, multi):
+        a = _traj(r, u0, 120)
+        assert np.array_equal(s.get()[0], a[0])
+    assert np.array_equal(multi[0].get()[0], multi[1].get()[0])
+    for s in multi:
+        s.close()
+    for r in roms:
+        r.close()
