@@ -18,7 +18,9 @@ Also in the one JSON line:
   dense / speedup_cp_vs_dense   the G-ROM beside it
   roofline      dense contraction kernel (HBM-bound): algorithmic bytes N^3*4 per launch
                 over its event-timed average duration, against 8 TB/s
-  roofline_cp   CP projections + Hadamard-scatter (3NR*4 bytes per launch)
+  roofline_cp   CP projections + Hadamard-scatter (2.5NR*4 bytes per launch in the pair
+                form of skew-paired factors, 3NR*4 in the general form)
+  cp_general    the same CP-ROM with the general-form projections (kernel knob 4 = 0)
   batched       N = 1000 with B = 16 and 64 trajectories (MFMA kernels), FP32 and BF16
   config2       N = 400, B = 256, the dense Khatri-Rao MFMA GEMM (BF16, BF16x3, FP32)
                 and CP rank 400, with TFLOP/s against the dense MFMA peaks
@@ -182,9 +184,17 @@ def main():
         # ---------------- headline: CP-ROM and dense G-ROM, one trajectory
         log("CP-ROM")
         rom_cp = make(False)
+        cp_form = rg.rom_query(rom_cp.handle, None, 7)       # skew column pairs in use
         s_cp, t_cp = step_rate(rom_cp, p.u0, K, W)
         cp_kernel = kernel_avg(rom_cp, p.u0, args.kernel_reps * 10)
-        log(f"CP {K} steps in {t_cp:.3f}s")
+        log(f"CP {K} steps in {t_cp:.3f}s (pair layout {cp_form})")
+        t_gen = None
+        if cp_form:
+            rg.rom_set_tile(rom_cp.handle, 4, 0)
+            s_gen, t_gen = step_rate(rom_cp, p.u0, K, W)
+            s_gen.close()
+            rg.rom_set_tile(rom_cp.handle, 4, -1)
+            log(f"CP general form {K} steps in {t_gen:.3f}s")
         log("dense G-ROM")
         rom_d = make(True)
         s_d, t_d = step_rate(rom_d, p.u0, Kd, min(W, 20))
@@ -195,7 +205,7 @@ def main():
         cp_rate = K / t_cp
         d_rate = Kd / t_d
         d_bytes = float(N) ** 3 * es
-        cp_bytes = 3.0 * N * R * es
+        cp_bytes = (2.5 if cp_form else 3.0) * N * R * es
         result = {
             "metric": METRIC,
             "value": cp_rate,
@@ -213,12 +223,15 @@ def main():
                        "N": N, "R": R, "batch": 1, "nu": p.nu, "dt": p.dt, "stiffness": "diag(k^2)+SPD(0.1)"},
             "dense": {"value": d_rate, "unit": "trajectory-steps/s", "steps": Kd, "ms_per_step": t_d / Kd * 1e3},
             "speedup_cp_vs_dense": cp_rate / d_rate,
+            "cp_form": "pair form of skew column pairs (Sec. 3.3)" if cp_form else "general",
+            "cp_general": None if t_gen is None else {"value": K / t_gen, "unit": "trajectory-steps/s",
+                                                      "ms_per_step": t_gen / K * 1e3},
             "roofline": {"bound": "hbm", "kernel": "k_dense_gemv (dense contraction, one trajectory)",
                          "achieved": d_bytes / d_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": d_bytes / d_kernel / 1e9 / HBM_PEAK_GBS,
                          "traffic": _traffic(f"dense_gemv_n{N}_{dt}", "dense_gemv"),
                          "avg_launch_us": d_kernel * 1e6, "algorithmic_bytes": d_bytes},
-            "roofline_cp": {"bound": "latency", "kernel": "k_cp_proj1 + k_cp_scatter1",
+            "roofline_cp": {"bound": "latency", "kernel": "k_cp_proj1 + k_cp_scatter1" + (" (pair form)" if cp_form else ""),
                             "achieved": cp_bytes / cp_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": cp_bytes / cp_kernel / 1e9 / HBM_PEAK_GBS,
                             "avg_launch_us": cp_kernel * 1e6, "algorithmic_bytes": cp_bytes},
