@@ -10,6 +10,7 @@ from .oracle import (  # noqa: F401
     nonlinear_dense_rows,
     nonlinear_cp,
     nonlinear_cp_skew,
+    nonlinear_svd,
     reconstruct,
     cholesky,
     chol_solve,

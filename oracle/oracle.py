@@ -44,6 +44,7 @@ def _load():
     lib.orc_nonlinear_dense_rows.argtypes = [_i64, _d, _d, _i64, ctypes.POINTER(_i64), _d]
     lib.orc_nonlinear_cp.argtypes = [_i64, _i64, _d, _d, _d, _d, _d, _d]
     lib.orc_nonlinear_cp_skew.argtypes = [_i64, _i64, _d, _d, _d, _d, _d, _d]
+    lib.orc_nonlinear_svd.argtypes = [_i64, _i64, _d, _d, _d, _d, _d]
     lib.orc_reconstruct.argtypes = [_i64, _i64, _d, _d, _d, _d, _d]
     lib.orc_cholesky.argtypes = [_i64, _d, _d]
     lib.orc_cholesky.restype = ctypes.c_int
@@ -127,6 +128,22 @@ def nonlinear_cp_skew(lam, A11, A12, A21, u) -> np.ndarray:
         ub = np.ascontiguousarray(uu[b])
         yb = np.empty(N)
         lib.orc_nonlinear_cp_skew(N, P, _p(lam), _p(A11), _p(A12), _p(A21), _p(ub), _p(yb))
+        y[b] = yb
+    return y.reshape(u.shape)
+
+
+def nonlinear_svd(U, sigma, V, u) -> np.ndarray:
+    """y = C(u)u for the SVD form (Sec. 4.4): C[i][j][k] ~ sum_r U[j][r] sigma_r V[i][k][r];
+    U [N][R], sigma [R], V [N][N][R]."""
+    lib = _load()
+    U, sigma, V, u = map(_c, (U, sigma, V, u))
+    N, R = U.shape
+    uu = u.reshape(-1, N)
+    y = np.empty_like(uu)
+    for b in range(uu.shape[0]):
+        ub = np.ascontiguousarray(uu[b])
+        yb = np.empty(N)
+        lib.orc_nonlinear_svd(N, R, _p(U), _p(sigma), _p(V), _p(ub), _p(yb))
         y[b] = yb
     return y.reshape(u.shape)
 

@@ -127,6 +127,35 @@ void orc_nonlinear_cp_skew(int64_t N, int64_t P, const double *lam, const double
     free(ga);
 }
 
+/* SVD-ROM contraction (Sec. 4.4): the mode-3 matricization of the tensor is replaced by
+ * its rank-R SVD, C_(3) ~ U_R Sigma_R V_R^T.  In the storage order used here the mode-3
+ * index is the second index j of C[i][j][k] (the advected coefficient), so
+ *   C[i][j][k] ~ sum_r U[j][r] sigma_r V[i][k][r],
+ * with U [N][R] and V [N][N][R] (row (i, k) of V_R), and
+ *   s_r = sum_j U[j][r] u_j,   y_i = sum_r sigma_r s_r (sum_k V[i][k][r] u_k).   2 N^2 R flops. */
+void orc_nonlinear_svd(int64_t N, int64_t R, const double *U, const double *sigma, const double *V,
+                       const double *u, double *y)
+{
+    double *s = (double *)malloc(sizeof(double) * (size_t)(R > 0 ? R : 1));
+    for (int64_t r = 0; r < R; ++r) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < N; ++j)
+            acc += U[j * R + r] * u[j];
+        s[r] = acc;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        double yi = 0.0;
+        for (int64_t r = 0; r < R; ++r) {
+            double vr = 0.0;
+            for (int64_t k = 0; k < N; ++k)
+                vr += V[(i * N + k) * R + r] * u[k];
+            yi += sigma[r] * s[r] * vr;
+        }
+        y[i] = yi;
+    }
+    free(s);
+}
+
 /* Kruskal tensor (Sec. 2.3, eq. cpd, with weights):
  *   T[i][j][k] = sum_r lam_r Af[i][r] Bf[j][r] Cf[k][r]. */
 void orc_reconstruct(int64_t N, int64_t R, const double *lam, const double *Af,

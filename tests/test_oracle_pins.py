@@ -169,6 +169,39 @@ def test_cp_skew_interleaved_generator(orc):
     assert np.allclose(y, y_cp, rtol=1e-12, atol=1e-13 * np.abs(y_cp).max())
 
 
+def test_svd_contraction(orc):
+    """Sec. 4.4: the SVD-ROM contraction equals the dense contraction of its own
+    reconstruction C[i][j][k] = sum_r U[j][r] sigma_r V[i][k][r]; with the full SVD of
+    a tensor's mode-3 matricization (numpy's SVD; the mode-3 index is j here) it equals
+    the dense contraction of the tensor itself; with the index roles swapped it does not."""
+    rng = np.random.default_rng(31)
+    N, R = 9, 4
+    U = rng.standard_normal((N, R))
+    sig = rng.standard_normal(R)
+    V = rng.standard_normal((N, N, R))
+    u = rng.standard_normal(N)
+    T = np.einsum("jr,r,ikr->ijk", U, sig, V)
+    y = orc.nonlinear_svd(U, sig, V, u)
+    y_d = orc.nonlinear_dense(T, u)
+    scale = np.einsum("ijk,j,k->i", np.abs(T), np.abs(u), np.abs(u))
+    assert np.all(np.abs(y - y_d) <= 1e-13 * scale + 1e-300)
+    # full SVD of C_(3): rows j, columns (i, k)
+    C = romsynth.dense_rough(N, 2, cfg=5)
+    M = np.ascontiguousarray(C.transpose(1, 0, 2).reshape(N, N * N))
+    Uf, sf, Vh = np.linalg.svd(M, full_matrices=False)
+    Vf = np.ascontiguousarray(Vh.T.reshape(N, N, N))          # [i][k][r]
+    y_svd = orc.nonlinear_svd(Uf, sf, Vf, u)
+    y_c = orc.nonlinear_dense(C, u)
+    sc = np.einsum("ijk,j,k->i", np.abs(C), np.abs(u), np.abs(u))
+    assert np.all(np.abs(y_svd - y_c) <= 1e-12 * sc.max())
+    # the other unfolding (k as the mode-3 index) is a different operator on a
+    # non-symmetric tensor: the check has teeth
+    M2 = np.ascontiguousarray(C.transpose(2, 0, 1).reshape(N, N * N))
+    U2, s2, Vh2 = np.linalg.svd(M2, full_matrices=False)
+    T2 = np.einsum("jr,r,ikr->ijk", U2, s2, Vh2.T.reshape(N, N, N))
+    assert not np.allclose(T2, C, atol=1e-6)
+
+
 def test_rows_variant_matches_full(orc):
     C = romsynth.dense_rough(10, 4, cfg=5)
     u = romsynth.initial_u(10, [4], cfg=5)[0]
