@@ -90,6 +90,19 @@ typedef struct rom_desc {
  * Errors: ROM_E_INVALID (sizes, nu < 0, dt <= 0, missing operator, non-SPD Helmholtz
  * matrix), ROM_E_NOMEM, ROM_E_DEVICE. */
 rom_status rom_create(const rom_desc *d, rom_ctx *out);
+
+/* The same with the advection tensor in the SVD form of the SVD-ROM (Sec. 4.4): the
+ * mode-3 matricization is replaced by its rank-R SVD, C_(3) ~ U_R Sigma_R V_R^T.  The
+ * mode-3 index is the second index j of C[i][j][k] (the advected coefficient), so
+ *     C[i][j][k] ~ sum_r U[j][r] sigma_r V[i][k][r],
+ *     y_i = sum_r sigma_r (U[:,r]^T u) (sum_k V[i][k][r] u_k)      (2 N^2 R flops).
+ * U host [N][R], sigma host [R], V host [N][N][R] (row (i, k), then r); R >= 1.  d->C,
+ * d->lambda and the CP factors must be NULL (d->R is ignored).  The formats apply as for
+ * the dense tensor (U and V in the contraction format, sigma like the CP weights).  States
+ * hold one trajectory (max_batch must be 1; ROM_E_UNSUPPORTED otherwise, or for N > 4096);
+ * rom_step_multi steps such states one by one.  Errors as rom_create. */
+rom_status rom_create_svd(const rom_desc *d, int32_t R, const double *U, const double *sigma,
+                          const double *V, rom_ctx *out);
 void rom_destroy(rom_ctx ctx);
 
 /* y = C(u)u for `batch` coefficient vectors (Sec. 2.2, eq. Cu; CP form: eq. tc_ap).
@@ -156,7 +169,8 @@ rom_status rom_step_multi(int32_t n, const rom_ctx *ctxs, const rom_state *state
 /* Introspection.  what: 0 = device bytes held by the context, 1 = device bytes held by
  * the state, 2 = N, 3 = R (0 if dense), 4 = dtype, 5 = state batch, 6 = state step,
  * 7 = skew column-pair layout the one-trajectory CP kernels use (rom_cp_skew_layout's
- * codes; 0 = general form). */
+ * codes; 0 = general form), 8 = operator form (0 dense, 1 CP, 2 SVD), 9 = SVD rank
+ * (0 unless SVD). */
 rom_status rom_query(rom_ctx ctx, rom_state st, int32_t what, int64_t *value);
 
 /* Kernel tile selection (the autotuner's knob).  kind: 0 = dense single-trajectory

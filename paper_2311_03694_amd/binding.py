@@ -25,7 +25,7 @@ EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_timed", 
            "rom_state_destroy",
            "rom_step", "rom_step_async", "rom_step_sync", "rom_energy", "rom_state_get",
            "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
-           "rom_tile_count", "rom_cp_skew_layout", "rom_last_error"]
+           "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_last_error"]
 
 _d = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -92,6 +92,8 @@ def lib():
     L.rom_tile_count.argtypes = [ctypes.c_int32]
     L.rom_tile_count.restype = ctypes.c_int32
     L.rom_cp_skew_layout.argtypes = [ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _d]
+    L.rom_create_svd.argtypes = [ctypes.POINTER(rom_desc), ctypes.c_int32, _d, _d, _d, ctypes.POINTER(_vp)]
+    L.rom_create_svd.restype = ctypes.c_int
     L.rom_cp_skew_layout.restype = ctypes.c_int32
     L.rom_last_error.argtypes = []
     L.rom_last_error.restype = ctypes.c_char_p
@@ -140,9 +142,10 @@ def _stream_handle(stream) -> Optional[int]:
 
 # ----------------------------------------------------------------------------- the C calls
 
-def rom_create(N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, dtype="fp32",
+def rom_create(N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, svd=None, dtype="fp32",
                max_batch=1, stream=None) -> int:
-    """Returns the context handle (int).  Host arrays are FP64 numpy-compatible."""
+    """Returns the context handle (int).  Host arrays are FP64 numpy-compatible.  svd:
+    (U [N][R], sigma [R], V [N][N][R]) for the SVD form (rom_create_svd)."""
     L = lib()
     keep = []
 
@@ -160,7 +163,12 @@ def rom_create(N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, dty
                  Af=h(Af), Bf=h(Bf), Cf=h(Cf), dtype=DTYPES[dtype] if isinstance(dtype, str) else int(dtype),
                  max_batch=int(max_batch), stream=_stream_handle(stream))
     out = _vp()
-    _check(L.rom_create(ctypes.byref(d), ctypes.byref(out)))
+    if svd is not None:
+        U, sig, V = svd
+        Rs = int(np.asarray(U).shape[1])
+        _check(L.rom_create_svd(ctypes.byref(d), Rs, h(U), h(sig), h(V), ctypes.byref(out)))
+    else:
+        _check(L.rom_create(ctypes.byref(d), ctypes.byref(out)))
     return out.value
 
 
@@ -277,13 +285,13 @@ def rom_last_error() -> str:
 class Rom:
     """Owning wrapper of a context (rom_create / rom_destroy)."""
 
-    def __init__(self, N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None,
+    def __init__(self, N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, svd=None,
                  dtype="fp32", max_batch=1, stream=None):
         self.N = int(N)
         self.dtype = dtype
         self.max_batch = int(max_batch)
         self.stream = stream
-        self.handle = rom_create(N, nu, dt, A, C=C, lam=lam, Af=Af, Bf=Bf, Cf=Cf, dtype=dtype,
+        self.handle = rom_create(N, nu, dt, A, C=C, lam=lam, Af=Af, Bf=Bf, Cf=Cf, svd=svd, dtype=dtype,
                                  max_batch=max_batch, stream=stream)
 
     @classmethod

@@ -352,6 +352,96 @@ __global__ __launch_bounds__(256) void k_helm_proj_group(const HelmJob* __restri
     else helm_proj_body<DT, false>(jb, n, blk);
 }
 
+// ============================================================== SVD-ROM, one trajectory
+
+// First product of the SVD-ROM (Sec. 4.4): w_r = sigma_r sum_j U[j][r] u_j over the rows
+// of Ut [Rsp][Np] (rows past the rank are zero, so w is zero there).  One wavefront per
+// row, four per block; the second product is the streaming kernel with R weighted slabs.
+struct SvdProj {
+    const void* Ut;
+    const unsigned short* Ut_lo;
+    const void* sigma;
+    int N, Np, Rsp;
+    const double* u_base;
+    const long long* stepp;
+    long long slot_stride;
+    void* w;
+};
+
+template <int DT, int V, int U>
+__global__ __launch_bounds__(256) void k_svd_proj(SvdProj a) {
+    typedef typename Store<DT>::T T;
+    typedef typename Store<DT>::Acc Acc;
+    constexpr int BYTES = V * (int)sizeof(T);
+    constexpr bool X3 = (DT == DT_BF16X3);
+    typedef typename RawT<BYTES>::T Raw;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int N = a.N, Np = a.Np;
+    LdsU<DT> L;
+    L.bind(smem, Np);
+    const int lane = threadIdx.x % kWave;
+    const int r = (int)blockIdx.x * 4 + (int)threadIdx.x / kWave;
+    const bool live = r < a.Rsp;
+    const T* row = reinterpret_cast<const T*>(a.Ut) + (size_t)(live ? r : 0) * Np;
+    const unsigned short* rowlo = X3 ? a.Ut_lo + (size_t)(live ? r : 0) * Np : nullptr;
+    Raw rv[U], rl[U];
+    int k0 = lane * V;
+    auto issue = [&](int kb) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int k = kb + q * kWave * V;
+            if (live && k < Np) {
+                rv[q] = ld_plain<BYTES>(row + k);
+                if constexpr (X3) rl[q] = ld_plain<BYTES>(rowlo + k);
+            }
+        }
+    };
+    issue(k0);
+    L.fill(a.u_base + (a.stepp ? (size_t)slot_of(*a.stepp) * a.slot_stride : 0), N, Np);
+    __syncthreads();
+    if (!live) return;
+    Acc z = 0;
+    while (k0 < Np) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int k = k0 + q * kWave * V;
+            if (k < Np) z += dot_vec<DT, V>(rv[q], rl[q], L, k);
+        }
+        k0 += kWave * V * U;
+        if (k0 < Np) issue(k0);
+    }
+    z = wave_sum(z);
+    if (lane == 0) reinterpret_cast<Acc*>(a.w)[r] = reinterpret_cast<const Acc*>(a.sigma)[r] * z;
+}
+
+template <int DT>
+static void svd_proj_go(const SvdProj& a, hipStream_t s) {
+    constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
+    hipLaunchKernelGGL((k_svd_proj<DT, V, 4>), dim3((unsigned)((a.Rsp + 3) / 4)), dim3(256), LdsU<DT>::bytes(a.Np), s,
+                       a);
+}
+
+void launch_svd_proj(int dt, const void* Ut, const void* Ut_lo, const void* sigma, int N, int Np, int Rs,
+                     const double* u_base, const long long* stepp, long long slot_stride, void* w, hipStream_t s) {
+    SvdProj a{};
+    a.Ut = Ut;
+    a.Ut_lo = (const unsigned short*)Ut_lo;
+    a.sigma = sigma;
+    a.N = N;
+    a.Np = Np;
+    a.Rsp = (Rs + 7) / 8 * 8;
+    a.u_base = u_base;
+    a.stepp = stepp;
+    a.slot_stride = slot_stride;
+    a.w = w;
+    switch (dt) {
+        case DT_F64: svd_proj_go<DT_F64>(a, s); break;
+        case DT_F32: svd_proj_go<DT_F32>(a, s); break;
+        case DT_BF16: svd_proj_go<DT_BF16>(a, s); break;
+        default: svd_proj_go<DT_BF16X3>(a, s); break;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 // LDS of the projection kernels: the image of u, and for the BF16 formats a second one

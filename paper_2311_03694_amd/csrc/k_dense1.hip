@@ -1,6 +1,8 @@
 // k_dense1.hip -- dense advection contraction for one trajectory (Sec. 2.2, eq. Cu;
 // the 2N^3-flop term of the G-ROM):
-//     y_i = sum_j u_j * sum_k C[i][j][k] u_k.
+//     y_i = sum_j u_j * sum_k C[i][j][k] u_k,
+// and, with J slabs of separate weights w, the second product of the SVD-ROM (Sec. 4.4)
+//     y_i = sum_r w_r * sum_k V[i][r][k] u_k   (w_r = sigma_r U[:,r]^T u).
 //
 // The tensor is stored [N][N][Np] with the k index padded by zeros to Np, a multiple
 // of 8.  It is read exactly once per step, so the kernel is a stream over HBM: each row
@@ -30,10 +32,13 @@ __device__ __forceinline__ void dense_gemv_body(const GemvJob& jb, int blk) {
     const T* __restrict__ C = reinterpret_cast<const T*>(jb.C);
     LdsU<DT> L;
     L.bind(smem, Np);
+    // slab weights: u itself (its accumulation-format image), or jb.wj staged behind it
+    Acc* wl = reinterpret_cast<Acc*>(smem + LdsU<DT>::bytes(Np));
+    const Acc* wsrc = jb.wj ? wl : L.uw;
 
     const int i = blk / nchunk;
     const int c = blk - i * nchunk;
-    const long long NN = (long long)N * Np;
+    const long long NN = (long long)jb.J * Np;
     const long long m0 = (long long)c * chunk_len;
     const long long m1 = (m0 + chunk_len < NN) ? m0 + chunk_len : NN;
     const T* row = C + (size_t)i * NN;
@@ -64,13 +69,17 @@ __device__ __forceinline__ void dense_gemv_body(const GemvJob& jb, int blk) {
 
     if (m < m1) issue(m);
     L.fill(jb.u_base + (jb.stepp ? (size_t)slot_of(*jb.stepp) * jb.slot_stride : 0), N, Np);
+    if (jb.wj) {
+        const Acc* wg = reinterpret_cast<const Acc*>(jb.wj);
+        for (int q = threadIdx.x; q < jb.J; q += NT) wl[q] = wg[q];
+    }
     __syncthreads();
 
     Acc acc = 0;
     while (m < m1) {
 #pragma unroll
         for (int q = 0; q < UNR; ++q) {
-            if (m + (long long)q * STEP < m1) acc += L.uw[jj[q]] * dot_vec<DT, V>(r[q], rl[q], L, kk[q]);
+            if (m + (long long)q * STEP < m1) acc += wsrc[jj[q]] * dot_vec<DT, V>(r[q], rl[q], L, kk[q]);
         }
         m += (long long)STEP * UNR;
         if (m < m1) issue(m);
@@ -110,9 +119,9 @@ int dense_gemv_nchunk(int N, GemvTile t) {
     return (int)nchunk;
 }
 
-static long long chunk_len_of(int dt, int N, int Np, int nchunk, GemvTile t) {
+static long long chunk_len_of(int dt, int J, int Np, int nchunk, GemvTile t) {
     const int V = dt == DT_F64 ? 2 : dt == DT_F32 ? 4 : 8;
-    const long long NN = (long long)N * Np;
+    const long long NN = (long long)J * Np;
     const long long step = (long long)t.threads * V;
     // a multiple of threads*V covering the row in nchunk pieces (trailing pieces may be
     // empty; their blocks write a zero partial)
@@ -120,19 +129,22 @@ static long long chunk_len_of(int dt, int N, int Np, int nchunk, GemvTile t) {
     return ((len + step - 1) / step) * step;
 }
 
-GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
-                      const long long* stepp, long long slot_stride, void* part, int nchunk, GemvTile t) {
+GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, int J, const void* wj,
+                      const double* u_base, const long long* stepp, long long slot_stride, void* part, int nchunk,
+                      GemvTile t) {
     GemvJob jb{};
     jb.C = C;
     jb.Clo = (const unsigned short*)Clo;
     jb.N = N;
     jb.Np = Np;
+    jb.J = J;
+    jb.wj = wj;
     jb.u_base = u_base;
     jb.stepp = stepp;
     jb.slot_stride = slot_stride;
     jb.part = part;
     jb.nchunk = nchunk;
-    jb.chunk_len = chunk_len_of(dt, N, Np, nchunk, t);
+    jb.chunk_len = chunk_len_of(dt, J, Np, nchunk, t);
     jb.blk0 = 0;
     jb.nblk = N * nchunk;
     return jb;
@@ -141,7 +153,7 @@ GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, con
 template <int DT, int UNR>
 static void gemv_go(const GemvJob& jb, const GemvJob* jobs, int njobs, int blocks, int Npmax, hipStream_t s) {
     constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
-    const size_t lds = LdsU<DT>::bytes(Npmax);
+    const size_t lds = LdsU<DT>::bytes(Npmax) + (jb.wj ? sizeof(typename Store<DT>::Acc) * (size_t)jb.J : 0);
     if (jobs) hipLaunchKernelGGL((k_dense_gemv_group<DT, V, UNR, 256>), dim3((unsigned)blocks), dim3(256), lds, s, jobs, njobs);
     else hipLaunchKernelGGL((k_dense_gemv<DT, V, UNR, 256>), dim3((unsigned)jb.nblk), dim3(256), lds, s, jb);
 }
@@ -163,10 +175,10 @@ static void gemv_dispatch(int dt, int unr, const GemvJob& jb, const GemvJob* job
     }
 }
 
-int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
-                      const long long* stepp, long long slot_stride, void* part, int nchunk,
+int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, int Np, int J, const void* wj,
+                      const double* u_base, const long long* stepp, long long slot_stride, void* part, int nchunk,
                       GemvTile t, hipStream_t s) {
-    const GemvJob jb = make_gemv_job(dt, C, Clo, N, Np, u_base, stepp, slot_stride, part, nchunk, t);
+    const GemvJob jb = make_gemv_job(dt, C, Clo, N, Np, J, wj, u_base, stepp, slot_stride, part, nchunk, t);
     gemv_dispatch(dt, t.unroll, jb, nullptr, 0, 0, Np, s);
     return 0;
 }

@@ -82,6 +82,11 @@ struct rom_ctx_s {
     int skew_layout = 0;
     void *SK = nullptr, *SK_lo = nullptr;
     void *Msk = nullptr, *Msk_lo = nullptr;
+    // SVD form (svd): Ut [Rsp][Np] (columns of U as rows), sigma [Rsp] (accumulation
+    // type), Vt [N][Rs][Np] (V[i][k][r] as slab r of row i)
+    bool svd = false;
+    int Rs = 0, Rsp = 0;
+    void *Ut = nullptr, *Ut_lo = nullptr, *sig = nullptr, *Vt = nullptr, *Vt_lo = nullptr;
     double* hdiag = nullptr;                    // [3][N]
     double* hinv = nullptr;                     // [3][N][N]
     // workspaces (shared by every state of the context; one stream serializes use)
@@ -204,6 +209,7 @@ struct WsPlan {
     size_t part2_off = 0;           // CP projection partials (B > 1)
     size_t w_off = 0;               // CP Hadamard products W [Bpad][Rp] (B > 1)
     size_t ucv_off = 0, ucvlo_off = 0, usc_off = 0;   // rom_nonlinear operand copies (B > 1)
+    size_t svdw_off = 0;            // SVD form (B = 1): slab weights w [Rsp]
     GemmPlan ph{};                  // B > 1, dense stiffness: FP64 Helmholtz apply
     size_t total = 0;
 };
@@ -215,10 +221,14 @@ WsPlan plan_ws(rom_ctx c, int B) {
     const size_t ab = acc_bytes(c->dtype);
     size_t off = 0;
     if (B == 1) {
-        if (c->dense) {
+        if (c->dense || c->svd) {
             p.nchunk = dense_gemv_nchunk(c->N, gemv_tile(c));
             p.part_off = off;
             off = align256(off + (size_t)p.nchunk * c->N * ab);
+            if (c->svd) {
+                p.svdw_off = off;
+                off = align256(off + (size_t)c->Rsp * ab);
+            }
         } else {
             p.part_off = off;
             off = align256(off + 2 * (size_t)c->Rp * ab);
@@ -374,7 +384,13 @@ extern "C" void rom_destroy(rom_ctx c) {
     delete c;
 }
 
-extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
+// The SVD form handed to rom_create_svd.
+struct SvdDesc {
+    int R;
+    const double *U, *sigma, *V;
+};
+
+static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out) {
     if (!out) return fail(ROM_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!d) return fail(ROM_E_INVALID, "desc is NULL");
@@ -384,7 +400,14 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
     if (!d->A) return fail(ROM_E_INVALID, "stiffness A is NULL");
     if (d->dtype < ROM_FP64 || d->dtype > ROM_BF16X3) return fail(ROM_E_INVALID, "unknown dtype %d", d->dtype);
     if (d->max_batch < 1) return fail(ROM_E_INVALID, "max_batch must be >= 1");
-    if (!d->C) {
+    if (sv) {
+        if (d->C || d->lambda || d->Af || d->Bf || d->Cf)
+            return fail(ROM_E_INVALID, "the SVD form takes no dense tensor or CP factors");
+        if (sv->R < 1) return fail(ROM_E_INVALID, "SVD rank must be >= 1");
+        if (!sv->U || !sv->sigma || !sv->V) return fail(ROM_E_INVALID, "the SVD form needs U, sigma and V");
+        if (d->N > 4096) return fail(ROM_E_UNSUPPORTED, "the SVD form is limited to N <= 4096");
+        if (d->max_batch > 1) return fail(ROM_E_UNSUPPORTED, "the SVD form runs one trajectory per state");
+    } else if (!d->C) {
         if (d->R < 1) return fail(ROM_E_INVALID, "CP rank R must be >= 1 when C is NULL");
         if (!d->lambda || !d->Af || !d->Bf || !d->Cf)
             return fail(ROM_E_INVALID, "CP mode needs lambda, Af, Bf and Cf");
@@ -398,13 +421,14 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
     rom_ctx c = new rom_ctx_s();
     c->N = d->N;
     c->Np = (d->N + 7) / 8 * 8;
-    c->R = d->C ? 0 : d->R;
+    c->R = (d->C || sv) ? 0 : d->R;
     c->Rp = (c->R + 7) / 8 * 8;
     c->dtype = d->dtype;
     c->nu = d->nu;
     c->dt = d->dt;
     c->max_batch = d->max_batch;
     c->dense = d->C != nullptr;
+    c->svd = sv != nullptr;
     c->stream = (hipStream_t)d->stream;
     rom_status st = ROM_OK;
 #define TRY(x)                          \
@@ -515,6 +539,38 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
     const size_t eb = elem_bytes(dt);
     const bool lo = dt == DT_BF16X3;
     const size_t Np = c->Np;
+    if (sv) {
+        // SVD form (Sec. 4.4): Ut rows are the columns of U, Vt[i][r][k] = V[i][k][r]
+        const size_t Rs = (size_t)sv->R, Rsp = (Rs + 7) / 8 * 8;
+        c->Rs = (int)Rs;
+        c->Rsp = (int)Rsp;
+        TRY(dmalloc(&c->Ut, Rsp * Np * eb + kSlack, &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->Ut, 0, Rsp * Np * eb + kSlack, c->stream));
+        TRY(dmalloc(&c->Vt, (size_t)N * Rs * Np * eb + kSlack, &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->Vt, 0, (size_t)N * Rs * Np * eb + kSlack, c->stream));
+        if (lo) {
+            TRY(dmalloc(&c->Ut_lo, Rsp * Np * 2 + kSlack, &c->bytes, &c->allocs));
+            HTRY(hipMemsetAsync(c->Ut_lo, 0, Rsp * Np * 2 + kSlack, c->stream));
+            TRY(dmalloc(&c->Vt_lo, (size_t)N * Rs * Np * 2 + kSlack, &c->bytes, &c->allocs));
+            HTRY(hipMemsetAsync(c->Vt_lo, 0, (size_t)N * Rs * Np * 2 + kSlack, c->stream));
+        }
+        TRY(dmalloc(&c->sig, Rsp * acc_bytes(dt), &c->bytes, &c->allocs));
+        HTRY(hipMemsetAsync(c->sig, 0, Rsp * acc_bytes(dt), c->stream));
+        std::vector<double> t(Rs * (size_t)N);
+        for (size_t n = 0; n < (size_t)N; ++n)
+            for (size_t r = 0; r < Rs; ++r) t[r * N + n] = sv->U[n * Rs + r];
+        TRY(upload_convert(c, t.data(), Rs, (int)N, (int)Np, c->Ut, c->Ut_lo, stage, stage_elems));
+        for (size_t i = 0; i < (size_t)N; ++i) {
+            const double* Vi = sv->V + i * (size_t)N * Rs;           // [k][r] of row i
+            for (size_t k = 0; k < (size_t)N; ++k)
+                for (size_t r = 0; r < Rs; ++r) t[r * N + k] = Vi[k * Rs + r];
+            TRY(upload_convert(c, t.data(), Rs, (int)N, (int)Np, (char*)c->Vt + i * Rs * Np * eb,
+                               lo ? (char*)c->Vt_lo + i * Rs * Np * 2 : nullptr, stage, stage_elems));
+        }
+        HTRY(hipMemcpyAsync(stage, sv->sigma, sizeof(double) * Rs, hipMemcpyHostToDevice, c->stream));
+        launch_cvt_lambda(dt, stage, c->sig, (long long)Rs, c->stream);
+        HTRY(hipGetLastError());
+    } else
     if (c->dense) {
         const size_t n3 = nn * Np;
         TRY(dmalloc(&c->C, n3 * eb + kSlack, &c->bytes, &c->allocs));
@@ -614,6 +670,14 @@ extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) {
     return ROM_OK;
 }
 
+extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) { return create_ctx(d, nullptr, out); }
+
+extern "C" rom_status rom_create_svd(const rom_desc* d, int32_t R, const double* U, const double* sigma,
+                                     const double* V, rom_ctx* out) {
+    const SvdDesc sv{R, U, sigma, V};
+    return create_ctx(d, &sv, out);
+}
+
 // ============================================================== contraction dispatch
 
 // The state's kernel arguments for the step from level n: the counter slot of n's
@@ -664,7 +728,7 @@ static HelmJob helm_job(rom_ctx c, const StepArgs& a) {
 // dense stiffness (state creation and restart; every step then leaves that of the next
 // level).
 static void seed_projections(rom_ctx c, const StepArgs& a, hipStream_t stream) {
-    if (c->dense || c->diagA || a.B != 1) return;
+    if (c->dense || c->svd || c->diagA || a.B != 1) return;
     launch_cp_proj1(c->dtype, proj_op(c), proj_op_lo(c), c->lam, c->N, c->Np, c->Rp, skew_of(c), a.uring, a.step,
                     (long long)c->N, a.st, stream);
 }
@@ -680,8 +744,14 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
     if (s->B == 1) {
         char* ws = (char*)s->scratch;
         if (c->dense) {
-            launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, a.uring, a.step, (long long)c->N,
+            launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, c->N, nullptr, a.uring, a.step, (long long)c->N,
                               ws + p.part_off, p.nchunk, gemv_tile(c), stream);
+            launch_bdf_from_partials(a, accf, ws + p.part_off, p.nchunk, 1, diag, stream);
+        } else if (c->svd) {
+            launch_svd_proj(c->dtype, c->Ut, c->Ut_lo, c->sig, c->N, c->Np, c->Rs, a.uring, a.step, (long long)c->N,
+                            ws + p.svdw_off, stream);
+            launch_dense_gemv(c->dtype, c->Vt, c->Vt_lo, c->N, c->Np, c->Rs, ws + p.svdw_off, a.uring, a.step,
+                              (long long)c->N, ws + p.part_off, p.nchunk, gemv_tile(c), stream);
             launch_bdf_from_partials(a, accf, ws + p.part_off, p.nchunk, 1, diag, stream);
         } else {
             // a.st holds w = lam .* s .* t of level n: computed here with a diagonal
@@ -704,7 +774,7 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
         }
     }
     if (!c->diagA) {
-        if (s->B == 1 && !c->dense) {
+        if (s->B == 1 && !c->dense && !c->svd) {
             launch_helm_proj(c->dtype, helm_job(c, a), stream);
         } else if (s->B == 1) {
             launch_helm_apply(a, stream);
@@ -747,8 +817,13 @@ static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, 
     auto contract = [&]() {
         if (batch == 1) {
             if (c->dense) {
-                launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, u_dev, nullptr, 0, ws + p.part_off, p.nchunk,
-                                  gemv_tile(c), c->stream);
+                launch_dense_gemv(c->dtype, c->C, c->Clo, c->N, c->Np, c->N, nullptr, u_dev, nullptr, 0,
+                                  ws + p.part_off, p.nchunk, gemv_tile(c), c->stream);
+            } else if (c->svd) {
+                launch_svd_proj(c->dtype, c->Ut, c->Ut_lo, c->sig, c->N, c->Np, c->Rs, u_dev, nullptr, 0,
+                                ws + p.svdw_off, c->stream);
+                launch_dense_gemv(c->dtype, c->Vt, c->Vt_lo, c->N, c->Np, c->Rs, ws + p.svdw_off, u_dev, nullptr, 0,
+                                  ws + p.part_off, p.nchunk, gemv_tile(c), c->stream);
             } else {
                 launch_cp_proj1(c->dtype, proj_op(c), proj_op_lo(c), c->lam, c->N, c->Np, c->Rp, skew_of(c), u_dev,
                                 nullptr, 0, ws + p.part_off, c->stream);
@@ -792,7 +867,7 @@ static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, 
         *kernel_us = 1e3 * (double)ms / reps;
     }
     if (batch == 1) {
-        if (c->dense) launch_sum_partials(accf, ws + p.part_off, p.nchunk, 1, 1, c->N, y_dev, c->stream);
+        if (c->dense || c->svd) launch_sum_partials(accf, ws + p.part_off, p.nchunk, 1, 1, c->N, y_dev, c->stream);
     } else {
         launch_sum_partials(accf, ws + p.part_off, c->dense ? p.pd.nsplit : p.ps.nsplit, p.Bpad, batch, c->N, y_dev,
                             c->stream);
@@ -966,7 +1041,7 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     a.step_next = s->cnt + 1;
     TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.closep, sizeof(int), &s->bytes, &s->allocs));
-    if (!c->dense && batch == 1)
+    if (!c->dense && !c->svd && batch == 1)
         TRY(dmalloc(&a.st, c->Rp * acc_bytes(c->dtype), &s->bytes, &s->allocs));
     if (a.batched) {
         const size_t cells = (size_t)s->Bpad * c->Np;
@@ -1254,7 +1329,7 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
     for (int q = 0; q < n; ++q) {
         rom_ctx c = ctxs[q];
         rom_state st = states[q];
-        if (st->B != 1) {
+        if (st->B != 1 || c->svd) {          // batches and SVD-form states step on their own
             if (par == 0) batched.push_back(q);
             continue;
         }
@@ -1274,7 +1349,7 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
         const WsPlan p = plan_ws(c, 1);
         char* scr = (char*)st->scratch;
         if (dense) {
-            GemvJob jb = make_gemv_job(c->dtype, c->C, c->Clo, c->N, c->Np, sa.uring, sa.step, c->N,
+            GemvJob jb = make_gemv_job(c->dtype, c->C, c->Clo, c->N, c->Np, c->N, nullptr, sa.uring, sa.step, c->N,
                                        scr + p.part_off, p.nchunk, gemv_tile(c));
             jb.blk0 = g->b1;
             g->b1 += jb.nblk;
@@ -1431,6 +1506,8 @@ extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* v
         case 5: if (!s) break; *value = s->B; return ROM_OK;
         case 6: if (!s) break; *value = s->h_step; return ROM_OK;
         case 7: if (!c) break; *value = skew_of(c).layout; return ROM_OK;
+        case 8: if (!c) break; *value = c->dense ? 0 : c->svd ? 2 : 1; return ROM_OK;
+        case 9: if (!c) break; *value = c->Rs; return ROM_OK;
         default: return fail(ROM_E_INVALID, "unknown query %d", what);
     }
     return fail(ROM_E_INVALID, "query %d needs a %s", what, what == 1 || what >= 5 ? "state" : "context");

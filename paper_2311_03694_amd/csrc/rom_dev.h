@@ -60,9 +60,11 @@ struct StepArgs {
 // A job is one kernel's work for one (context, state) pair; grouped launches run the
 // jobs of many pairs (uneven N, R) in one grid, job p owning blocks [blk0, blk0+nblk).
 struct GemvJob {           // dense contraction, one trajectory
-    const void* C;
+    const void* C;                 // [N][J][Np]
     const unsigned short* Clo;
     int N, Np;
+    int J;                         // slabs per row: N (dense tensor), or the SVD rank
+    const void* wj;                // slab weights [J] (accumulation type); null: u itself
     const double* u_base;
     const long long* stepp;
     long long slot_stride;
@@ -128,12 +130,16 @@ struct GemvTile { int threads, unroll, chunk_target; };
 int dense_gemv_variants();
 GemvTile dense_gemv_variant(int idx);
 int dense_gemv_nchunk(int N, GemvTile t);
-int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
-                      const long long* stepp, long long slot_stride, void* part, int nchunk,
+int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, int Np, int J, const void* wj,
+                      const double* u_base, const long long* stepp, long long slot_stride, void* part, int nchunk,
                       GemvTile t, hipStream_t s);
+// SVD-ROM first product: w_r = sigma_r U[:,r]^T u over the rows of Ut [Rsp][Np]
+void launch_svd_proj(int dt, const void* Ut, const void* Ut_lo, const void* sigma, int N, int Np, int Rs,
+                     const double* u_base, const long long* stepp, long long slot_stride, void* w, hipStream_t s);
 
-GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, const double* u_base,
-                      const long long* stepp, long long slot_stride, void* part, int nchunk, GemvTile t);
+GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, int J, const void* wj,
+                      const double* u_base, const long long* stepp, long long slot_stride, void* part, int nchunk,
+                      GemvTile t);
 void launch_dense_gemv_group(int dt, const GemvJob* jobs_dev, int njobs, int blocks, int Npmax, GemvTile t,
                              hipStream_t s);
 // grouped single-trajectory CP and BDF kernels; scatter mode 1 = diagonal stiffness

@@ -80,3 +80,26 @@ def test_cp_skew_layout_host_check():
     assert rg.rom_cp_skew_layout(lam[:9], Af[:, :9], Bf[:, :9], Cf[:, :9]) == 0   # odd rank
     rng = np.random.default_rng(0)
     assert rg.rom_cp_skew_layout(*(rng.standard_normal(s) for s in [(6,), (9, 6), (9, 6), (9, 6)])) == 0
+
+
+@pytest.mark.parametrize("kw,status,msg", [
+    (dict(R=0), "ROM_E_INVALID", "SVD rank"),
+    (dict(V=None), "ROM_E_INVALID", "needs U, sigma and V"),
+    (dict(C=True), "ROM_E_INVALID", "takes no dense tensor"),
+    (dict(max_batch=2), "ROM_E_UNSUPPORTED", "one trajectory"),
+])
+def test_create_svd_rejects_invalid(kw, status, msg):
+    """rom_create_svd checks its description before any device work."""
+    N, R = 5, kw.get("R", 3)
+    U = np.ones((N, max(R, 1)))
+    sig = np.ones(max(R, 1))
+    V = None if "V" in kw else np.ones((N, N, max(R, 1)))
+    C = np.zeros((N, N, N)) if kw.get("C") else None
+    A = np.eye(N)
+    d = rg.binding.rom_desc(N=N, R=0, nu=1e-3, dt=1e-3, A=rg.binding._ptr(A),
+                            C=rg.binding._ptr(C), dtype=1, max_batch=kw.get("max_batch", 1))
+    out = ctypes.c_void_p()
+    st = rg.lib().rom_create_svd(ctypes.byref(d), R, rg.binding._ptr(U), rg.binding._ptr(sig),
+                                 rg.binding._ptr(V), ctypes.byref(out))
+    assert st == getattr(rg.binding, status)
+    assert msg in rg.rom_last_error()
