@@ -24,6 +24,8 @@ Also in the one JSON line:
   batched       N = 1000 with B = 16 and 64 trajectories (MFMA kernels), FP32 and BF16
   config2       N = 400, B = 256, the dense Khatri-Rao MFMA GEMM (BF16, BF16x3, FP32)
                 and CP rank 400, with TFLOP/s against the dense MFMA peaks
+  svd           the SVD-ROM (Sec. 4.4) at N = 1000 with SVD ranks 100 and 250 (compression
+                N/R = 10 and 4), FP32, one trajectory: steps/s and the streaming bandwidth
   multi         uneven N: one CP trajectory each at N = 100, 200, 400, 700, 1000 stepped
                 together by grouped launches (rom_step_multi) and one after the other
   serving       a bounded Poisson request stream through the continuous-batching loop
@@ -63,7 +65,7 @@ def parse():
                     help="target length of the oracle sample (CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no batched/config2/serving)")
-    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "multi", "serving"],
+    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "svd", "multi", "serving"],
                     help="run one section only (profiling); the JSON line then holds that section")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--calib-copy", action="store_true",
@@ -302,6 +304,30 @@ def main():
                                    "avg_launch_us": c2["dense_bf16"]["contraction_us"],
                                    "algorithmic_flops": 2.0 * 400 ** 3 * 256,
                                    "traffic": _traffic("kr_dense_n400_b256_bf16", "kr")}
+
+    if not args.no_extra and sec in ("all", "svd"):
+        # ---------------- SVD-ROM: U, sigma, V of the mode-3 matricization (seeded random
+        # factors of the right shapes; the timing does not depend on their values)
+        svd = {}
+        A3 = p.A
+        for Rs in (100, 250):
+            rng = np.random.default_rng(Rs)
+            U = rng.standard_normal((N, Rs)) / np.sqrt(N)
+            sig = 1.0 / (1.0 + np.arange(Rs))
+            V = rng.standard_normal((N, N, Rs)) / N
+            rom_s = rg.Rom(N, p.nu, p.dt, A3, svd=(U, sig, V), dtype="fp32", max_batch=1, stream=stream)
+            del V
+            steps = 2000
+            s_s, t_s = step_rate(rom_s, p.u0, steps, 20)
+            tk = kernel_avg(rom_s, p.u0, 10)
+            vbytes = float(N) * N * Rs * 4
+            svd[f"R{Rs}"] = {"traj_steps_per_s": steps / t_s, "us_per_step": t_s / steps * 1e6,
+                             "contraction_us": tk * 1e6, "compression_N_over_R": N / Rs,
+                             "hbm_frac": vbytes / tk / 1e9 / HBM_PEAK_GBS}
+            log(f"svd R={Rs}: {steps / t_s:.0f} steps/s, contraction {tk * 1e6:.1f} us")
+            s_s.close()
+            rom_s.close()
+        result["svd"] = svd
 
     if not args.no_extra and sec in ("all", "multi"):
         # ---------------- uneven N: grouped launches against the same states one by one
