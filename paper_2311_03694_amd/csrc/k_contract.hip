@@ -1,9 +1,11 @@
 // k_contract.hip -- CP advection contraction for one trajectory.
 //
 // CP (Sec. 3.1, eq. tc_ap):  w = lam .* s .* t with s = Bf^T u, t = Cf^T u (one pass
-// over [Bf | Cf]^T stored [2Rp][Np]: a wavefront takes rows r and Rp + r and writes w_r),
-// then y = Af w, with w staged in LDS by every block of the scatter kernel, which also
-// applies the BDF update to its rows.
+// over [Bf | Cf]^T stored [2Rp][Np]: a wavefront takes rows r and Rp + r and writes w_r;
+// factors with skew column pairs, Sec. 3.3, read the pair form instead), then y = Af w,
+// with w staged in LDS by every block of the scatter kernel, which also applies the BDF
+// update to its rows.  With a dense stiffness the Helmholtz kernel forms the next level's
+// w.  The file also holds the first product of the SVD-ROM (Sec. 4.4).
 // Np and Rp round N and R up to multiples of 8; padding rows and columns hold zeros
 // (and zero weights), so they contribute nothing.
 #include "kdot.h"
