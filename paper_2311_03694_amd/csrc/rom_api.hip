@@ -415,7 +415,21 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out)
     const long long N = d->N;
     if (d->C && N > 4096) return fail(ROM_E_UNSUPPORTED, "dense tensors are limited to N <= 4096");
     if (N > 16384) return fail(ROM_E_UNSUPPORTED, "N > 16384 is not supported");
-    if (!d->C && (long long)d->R * (d->dtype == ROM_FP64 ? 8 : 4) > 65536)
+    // one-trajectory kernels stage u in LDS (64 KB per block): per padded mode 8 bytes
+    // (FP64), 4 (FP32), 6 (BF16: words and weights) or 8 (BF16x3); the CP projections of
+    // the BF16 formats hold a second image of -u, and the SVD slab stream adds R weights
+    {
+        const long long Npl = (N + 7) / 8 * 8;
+        const long long per = d->dtype == ROM_FP64 ? 8 : d->dtype == ROM_FP32 ? 4 : d->dtype == ROM_BF16 ? 6 : 8;
+        const long long acc = d->dtype == ROM_FP64 ? 8 : 4;
+        long long need = per * Npl;
+        if (!d->C && !sv && (d->dtype == ROM_BF16 || d->dtype == ROM_BF16X3)) need *= 2;
+        if (sv) need += acc * (long long)sv->R;
+        if (need > 65536)
+            return fail(ROM_E_UNSUPPORTED, "N = %lld (with this format and rank) exceeds the 64 KB LDS staging of u",
+                        N);
+    }
+    if (!d->C && !sv && (long long)d->R * (d->dtype == ROM_FP64 ? 8 : 4) > 65536)
         return fail(ROM_E_UNSUPPORTED, "CP rank %d exceeds the 64 KB LDS staging of the scatter kernel", d->R);
 
     rom_ctx c = new rom_ctx_s();

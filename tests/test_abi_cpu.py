@@ -103,3 +103,14 @@ def test_create_svd_rejects_invalid(kw, status, msg):
                                  rg.binding._ptr(V), ctypes.byref(out))
     assert st == getattr(rg.binding, status)
     assert msg in rg.rom_last_error()
+
+
+def test_lds_staging_limit_rejected():
+    """One-trajectory kernels stage u in 64 KB of LDS: a BF16 CP context at N = 6000 (two
+    images of 6 bytes per mode) is refused before any device work."""
+    N, R = 6000, 2
+    f = np.ones((N, R))
+    with pytest.raises(rg.RomError) as ei:
+        rg.rom_create(N, 1e-3, 1e-3, np.eye(1), lam=np.ones(R), Af=f, Bf=f, Cf=f, dtype="bf16")
+    assert ei.value.status == rg.binding.ROM_E_UNSUPPORTED
+    assert "LDS staging of u" in str(ei.value)
