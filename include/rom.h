@@ -67,7 +67,8 @@ typedef enum { ROM_FP64 = 0, ROM_FP32 = 1, ROM_BF16 = 2, ROM_BF16X3 = 3 } rom_dt
  *   lambda    host [R] weights; Af, Bf, Cf host [N][R] factors of tensor positions 1,2,3.
  *   dtype     rom_dtype of the contraction.
  *   max_batch largest batch a state of this context may hold (>= 1).
- *   stream    hipStream_t for all work of this context; NULL = the null stream. */
+ *   stream    hipStream_t for all work of this context; NULL = a non-blocking stream the
+ *             context creates and destroys (it does not wait for the null stream). */
 typedef struct rom_desc {
     int32_t N;
     int32_t R;

@@ -303,11 +303,16 @@ class Rom:
                    max_batch=mb, stream=stream)
 
     def nonlinear(self, u_dev, y_dev=None):
+        """y = C(u)u for torch device tensors.  The context works on its own stream, so
+        this waits for torch's current stream before the call (u is ready) and for the
+        device after it (y is ready for torch); rom_nonlinear is the asynchronous form."""
         import torch
         if y_dev is None:
             y_dev = torch.empty_like(u_dev)
         batch = 1 if u_dev.dim() == 1 else u_dev.shape[0]
+        torch.cuda.current_stream().synchronize()
         rom_nonlinear(self.handle, batch, u_dev, y_dev)
+        torch.cuda.synchronize()
         return y_dev
 
     def state(self, u0) -> "RomState":

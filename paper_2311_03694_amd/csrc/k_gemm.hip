@@ -25,6 +25,11 @@
 //    Helmholtz apply.
 //  * FINISH (the batched Helmholtz apply of a step): the outputs are u^{n+1}; they are
 //    stored with their energy partials, and one extra block closes the step.
+//  * SKEW (the CP projections of factors with skew column pairs, Sec. 3.3): A is the pair
+//    form [P + R][Np] (the P distinct columns of Bf, then the columns of Af); a block
+//    takes 16 pairs, each lane three rows (beta, alpha, gamma of its pair), and writes
+//    W[b][c0] = lam beta gamma and W[b][c1] = -lam beta alpha; pairs past P write the
+//    zero padding of W.
 #include "kmfma.h"
 #include "kstep.h"
 
@@ -42,15 +47,18 @@ struct GemmArgs {
     const long long* kstep;        // non-null: A += (BDF order at *kstep - 1) * a_kstride
     long long a_kstride;
     long long pair_off;            // PAIR: elements from a row of A to its partner row
-    const void* lam;               // PAIR: lam [M] (accumulation type)
+    const void* lam;               // PAIR, SKEW: lam (accumulation type)
+    int skew_P, skew_layout;       // SKEW: pairs, layout (1 interleaved, 2 blocked)
+    long long wstride;             // SKEW: row length of W (Rp)
     StepArgs st;                   // UPDATE, RHS: the state of the step (M = N rows)
 };
 
-enum { EPI_PLAIN = 0, EPI_PAIR = 1, EPI_UPDATE = 2, EPI_RHS = 3, EPI_FINISH = 4 };
+enum { EPI_PLAIN = 0, EPI_PAIR = 1, EPI_UPDATE = 2, EPI_RHS = 3, EPI_FINISH = 4, EPI_SKEW = 5 };
 
 template <int ADT, int MKD, int FN, int PF, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     constexpr bool PAIR = (EPI == EPI_PAIR);
+    constexpr bool SKEW = (EPI == EPI_SKEW);
     constexpr bool CLOSE = (EPI == EPI_UPDATE || EPI == EPI_FINISH);   // writes level n+1
     typedef MfmaT<MKD> Tr;
     typedef typename Tr::X XT;
@@ -64,7 +72,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     constexpr bool CVT = (MKD == MK_F32 && ADT != DT_F32);
     constexpr int AV = CVT ? 4 : (int)(16 / sizeof(typename Store<ADT>::T));
     static_assert(AV == VEC, "lane vectors of A and X must cover the same k");
-    constexpr int NA = PAIR ? 2 : 1;                     // A rows per lane (row and partner)
+    constexpr int NA = PAIR ? 2 : SKEW ? 3 : 1;          // A rows per lane (row and partner(s))
     extern __shared__ __attribute__((aligned(16))) char smem[];
     Acc* red = reinterpret_cast<Acc*>(smem);             // [NA][4][FN][4][64]
 
@@ -93,7 +101,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     int r = rowbase + c16;
     r = r < p.M ? r : p.M - 1;
     const size_t kbase = p.kstep ? (size_t)(bdf_order(*p.kstep) - 1) * p.a_kstride : 0;
-    const size_t arow = kbase + (size_t)r * p.lda;
+    size_t arows[NA];
+    if constexpr (SKEW) {
+        const int c0 = p.skew_layout == 1 ? 2 * r : r, c1 = p.skew_layout == 1 ? 2 * r + 1 : p.skew_P + r;
+        arows[0] = kbase + (size_t)r * p.lda;
+        arows[1] = kbase + (size_t)(p.skew_P + c0) * p.lda;
+        arows[2] = kbase + (size_t)(p.skew_P + c1) * p.lda;
+    } else {
+#pragma unroll
+        for (int h = 0; h < NA; ++h) arows[h] = kbase + (size_t)r * p.lda + (h ? (size_t)p.pair_off : 0);
+    }
     size_t xrow[FN];
 #pragma unroll
     for (int t = 0; t < FN; ++t) {
@@ -122,7 +139,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
             k = k < p.K ? k : p.K - VEC;
 #pragma unroll
             for (int h2 = 0; h2 < NA; ++h2) {
-                const size_t ar = arow + (h2 ? (size_t)p.pair_off : 0);
+                const size_t ar = arows[h2];
                 if constexpr (CVT) {
                     const u32x2 h = ld_plain<8>(reinterpret_cast<const unsigned short*>(p.A) + ar + k);
                     u32x2 l = u32x2{0u, 0u};
@@ -205,7 +222,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
             for (int w2 = 1; w2 < 4; ++w2) sum[h] += red[h * RS + ((w2 * FN + t) * 4 + v) * 64 + ln];
         }
         const int row = rowbase + rr, b = b0 + cl;
-        if constexpr (EPI <= EPI_PAIR) {
+        if constexpr (SKEW) {
+            if (b < p.Bpad) {
+                Acc* wrow = out + (size_t)b * p.wstride;
+                if (row < p.skew_P) {
+                    const int c0 = p.skew_layout == 1 ? 2 * row : row;
+                    const int c1 = p.skew_layout == 1 ? 2 * row + 1 : p.skew_P + row;
+                    const Acc* lam = reinterpret_cast<const Acc*>(p.lam);
+                    wrow[c0] = lam[c0] * sum[0] * sum[2];
+                    wrow[c1] = lam[c1] * sum[0] * (-sum[1]);
+                } else {
+                    const long long e = 2LL * row;                // zero padding of W past R = 2P
+                    if (e < p.wstride) wrow[e] = 0;
+                    if (e + 1 < p.wstride) wrow[e + 1] = 0;
+                }
+            }
+        } else if constexpr (EPI <= EPI_PAIR) {
             if (row < p.M && b < p.Bpad) {
                 if constexpr (PAIR) out[(size_t)b * p.M + row] = reinterpret_cast<const Acc*>(p.lam)[row] * sum[0] * sum[1];
                 else out[(size_t)b * p.M + row] = sum[0];
@@ -272,7 +304,8 @@ GemmPlan gemm_plan(int M, int Bpad, int variant) {
 
 template <int ADT, int MKD, int EPI = EPI_PLAIN>
 static void gemm_go(const GemmArgs& a, const GemmPlan& pl, hipStream_t s) {
-    const size_t lds = (size_t)1024 * pl.fn * sizeof(typename MfmaT<MKD>::Acc) * (EPI == EPI_PAIR ? 2 : 1);
+    const size_t lds = (size_t)1024 * pl.fn * sizeof(typename MfmaT<MKD>::Acc) *
+                       (EPI == EPI_PAIR ? 2 : EPI == EPI_SKEW ? 3 : 1);
     if (pl.fn == 4) hipLaunchKernelGGL((k_gemm<ADT, MKD, 4, 4, EPI>), dim3(pl.blocks), dim3(256), lds, s, a);
     else if (pl.fn == 2) hipLaunchKernelGGL((k_gemm<ADT, MKD, 2, 6, EPI>), dim3(pl.blocks), dim3(256), lds, s, a);
     else hipLaunchKernelGGL((k_gemm<ADT, MKD, 1, 8, EPI>), dim3(pl.blocks), dim3(256), lds, s, a);
@@ -327,6 +360,27 @@ void launch_gemm_proj_pair(int dt, const GemmPlan& pl0, const void* BCt, const v
         case DT_F32: gemm_go<DT_F32, MK_F32, EPI_PAIR>(a, pl, s); break;
         case DT_BF16: gemm_go<DT_BF16, MK_BF16, EPI_PAIR>(a, pl, s); break;
         default: gemm_go<DT_BF16X3, MK_BF16X3, EPI_PAIR>(a, pl, s); break;
+    }
+}
+
+// CP projections of factors with skew column pairs and their Hadamard product, from the
+// pair form SK [P + R][Np] (SKEW epilogue): W [Bpad][Rp] in the accumulation type.
+void launch_gemm_proj_skew(int dt, const GemmPlan& pl0, const void* SK, const void* SK_lo, int Np, int P, int layout,
+                           int Rp, int Bpad, const void* X, const void* Xlo, const void* lam, void* W, hipStream_t s) {
+    GemmPlan pl = pl0;
+    pl.gx = (Rp / 2 + 15) / 16;
+    pl.gy = Bpad / (16 * pl.fn);
+    pl.blocks = (pl.gx * pl.gy + 7) / 8 * 8;
+    GemmArgs a = gemm_args(pl, SK, SK_lo, Np, X, Xlo, Np, W, P, Np, Bpad);
+    a.skew_P = P;
+    a.skew_layout = layout;
+    a.wstride = Rp;
+    a.lam = lam;
+    switch (dt) {
+        case DT_F64: gemm_go<DT_F64, MK_F64, EPI_SKEW>(a, pl, s); break;
+        case DT_F32: gemm_go<DT_F32, MK_F32, EPI_SKEW>(a, pl, s); break;
+        case DT_BF16: gemm_go<DT_BF16, MK_BF16, EPI_SKEW>(a, pl, s); break;
+        default: gemm_go<DT_BF16X3, MK_BF16X3, EPI_SKEW>(a, pl, s); break;
     }
 }
 

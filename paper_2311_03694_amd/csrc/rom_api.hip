@@ -142,6 +142,8 @@ static size_t acc_bytes(int dt) { return dt == DT_F64 ? 8 : 4; }
 
 // ============================================================== workspace sizing
 
+static SkewPairs skew_of(rom_ctx c);   // the skew column pairs in use (defined below)
+
 namespace {
 
 GemvTile gemv_tile(rom_ctx c) { return dense_gemv_variant(c->tile[0] < 0 ? 0 : c->tile[0]); }
@@ -182,7 +184,10 @@ void launch_scatter(rom_ctx c, const SkinnyPlan& sp, int Bpad, const void* W, vo
 // return value says so.  Otherwise Y holds the scatter's partial sums.
 bool launch_cp_batched(rom_ctx c, const SkinnyPlan& pp, const SkinnyPlan& ps, int Bpad, int B, const void* X,
                        const void* Xlo, void* P, void* W, void* Y, const StepArgs* sa, hipStream_t s) {
-    if (pp.engine == 0) {
+    const SkewPairs sk = skew_of(c);
+    if (pp.engine == 0 && sk.layout) {
+        launch_gemm_proj_skew(c->dtype, pp.g, c->SK, c->SK_lo, c->Np, sk.P, sk.layout, c->Rp, Bpad, X, Xlo, c->lam, W, s);
+    } else if (pp.engine == 0) {
         launch_gemm_proj_pair(c->dtype, pp.g, c->BCt, c->BCt_lo, c->Np, c->Rp, Bpad, X, Xlo, c->lam, W, s);
     } else {
         launch_proj(c, pp, Bpad, X, Xlo, P, s);

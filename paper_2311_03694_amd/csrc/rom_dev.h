@@ -259,6 +259,8 @@ int gemm_variants();
 GemmPlan gemm_plan(int M, int Bpad, int variant);
 void launch_gemm_proj(int dt, const GemmPlan& pl, const void* BCt, const void* BCt_lo, int Np, int Rp, int Bpad,
                       const void* X, const void* Xlo, void* P, hipStream_t s);
+void launch_gemm_proj_skew(int dt, const GemmPlan& pl0, const void* SK, const void* SK_lo, int Np, int P, int layout,
+                           int Rp, int Bpad, const void* X, const void* Xlo, const void* lam, void* W, hipStream_t s);
 void launch_gemm_proj_pair(int dt, const GemmPlan& pl, const void* BCt, const void* BCt_lo, int Np, int Rp,
                            int Bpad, const void* X, const void* Xlo, const void* lam, void* W, hipStream_t s);
 void launch_gemm_scatter_step(int dt, const GemmPlan& pl, const void* Af, const void* Af_lo, int N, int Rp,

@@ -54,6 +54,15 @@ def _eval(torch, rom, u):
     return yd.cpu().numpy()[0]
 
 
+def _eval_batch(torch, rom, U):
+    ud = torch.tensor(np.atleast_2d(U), dtype=torch.float64, device="cuda")
+    yd = torch.empty_like(ud)
+    torch.cuda.synchronize()
+    rg.rom_nonlinear(rom.handle, ud.shape[0], ud, yd)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
 def _traj(rom, u0, steps):
     s = rom.state(u0)
     s.step(steps)
@@ -129,3 +138,31 @@ def test_pair_form_in_grouped_launches(torch_gpu):
         s.close()
     for r in roms:
         r.close()
+
+
+@pytest.mark.parametrize("layout", ["interleaved", "blocked"])
+@pytest.mark.parametrize("A", ["diag", "spd"])
+@pytest.mark.parametrize("dt", DTS)
+def test_pair_form_batched(torch_gpu, dt, A, layout):
+    """Batches: the projection GEMM in the pair form (three rows per pair) against the
+    general form (rounding differs: tolerance) and against the oracle."""
+    B, steps = 9, 120
+    _say(f"batched pair form {layout} A={A} {dt}")
+    p = romsynth.make_problem(44, pairs=22, eps=1e-6, nu=1e-3, dt=1e-3, A=A, batch=B, cfg=64, dense=False, cp=True)
+    factors = _blocked(p) if layout == "blocked" else (p.lam, p.Af, p.Bf, p.Cf)
+    lam, Af, Bf, Cf = factors
+    rom = rg.Rom(p.N, p.nu, p.dt, p.A, lam=lam, Af=Af, Bf=Bf, Cf=Cf, dtype=dt, max_batch=B)
+    assert rg.rom_query(rom.handle, None, 7) == (2 if layout == "blocked" else 1)
+    Y_pair = _eval_batch(torch_gpu, rom, p.u0)
+    t_pair = _traj(rom, p.u0, steps)
+    rg.rom_set_tile(rom.handle, KIND_PAIR, 0)
+    Y_gen = _eval_batch(torch_gpu, rom, p.u0)
+    t_gen = _traj(rom, p.u0, steps)
+    ops_scale = [eval_bound_cp(dt, lam, Af, Bf, Cf, p.u0[b]) for b in range(B)]
+    for b in range(B):
+        check_eval(dt, Y_pair[b], Y_gen[b], 2.0 * ops_scale[b])
+        assert rel(t_pair[0][0][b], t_gen[0][0][b]) < TRAJ_TOL[dt]
+    for b in (0, 4, 8):
+        ref = orc.run(p.N, p.nu, p.dt, p.A, steps, u0=p.u0[b], lam=lam, Af=Af, Bf=Bf, Cf=Cf)
+        assert rel(t_pair[0][0][b], ref["u_hist"][0]) < TRAJ_TOL[dt], b
+    rom.close()
