@@ -176,11 +176,11 @@ rom_status rom_query(rom_ctx ctx, rom_state st, int32_t what, int64_t *value);
 
 /* Kernel tile selection (the autotuner's knob).  kind: 0 = dense single-trajectory
  * streaming contraction, 1 = dense batched MFMA contraction, 2 = CP projections,
- * 3 = CP scatter, 4 = pair form of the one-trajectory CP projections (0 = general form,
- * 1 = pair form, ROM_E_UNSUPPORTED if the factors have no skew column pairs).  value: an
- * index into that kernel's variant table (see rom_tile_count); -1 restores the built-in
- * choice (for kind 4: the pair form whenever the factors allow it).  Applies to later
- * launches. */
+ * 3 = CP scatter, 4 = pair form of the CP projections (0 = general form, 1 = pair form
+ * for one trajectory and for batches, ROM_E_UNSUPPORTED if the factors have no skew column
+ * pairs).  value: an index into that kernel's variant table (see rom_tile_count); -1
+ * restores the built-in choice (for kind 4: the pair form for one trajectory whenever the
+ * factors allow it, the general form for batches).  Applies to later launches. */
 rom_status rom_set_tile(rom_ctx ctx, int32_t kind, int32_t value);
 int32_t rom_tile_count(int32_t kind);
 

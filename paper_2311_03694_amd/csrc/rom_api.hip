@@ -94,7 +94,8 @@ struct rom_ctx_s {
     size_t ws_bytes = 0;
     int ws_gen = 0;
     // tiles (-1 = heuristic)
-    // tile[4]: CP pair-form kernels (-1 default = on when the factors have skew pairs, 0 off)
+    // tile[4]: CP pair-form kernels (-1 default = on for one trajectory when the factors
+    // have skew pairs, 0 off, 1 on for batches too)
     int tile[5] = {-1, -1, -1, -1, -1};
     size_t lds_max = 65536;                     // dynamic LDS a batched kernel may take
     size_t bytes = 0;
@@ -184,7 +185,10 @@ void launch_scatter(rom_ctx c, const SkinnyPlan& sp, int Bpad, const void* W, vo
 // return value says so.  Otherwise Y holds the scatter's partial sums.
 bool launch_cp_batched(rom_ctx c, const SkinnyPlan& pp, const SkinnyPlan& ps, int Bpad, int B, const void* X,
                        const void* Xlo, void* P, void* W, void* Y, const StepArgs* sa, hipStream_t s) {
-    const SkewPairs sk = skew_of(c);
+    // The pair-form GEMM covers half as many output tiles as the general form, each with
+    // 1.5x the rows: at B <= 64 and R = 2000 it fills fewer CUs and runs 6-10% slower, so
+    // batches take it only when knob 4 asks for it explicitly (value 1).
+    const SkewPairs sk = c->tile[4] == 1 ? skew_of(c) : SkewPairs{};
     if (pp.engine == 0 && sk.layout) {
         launch_gemm_proj_skew(c->dtype, pp.g, c->SK, c->SK_lo, c->Np, sk.P, sk.layout, c->Rp, Bpad, X, Xlo, c->lam, W, s);
     } else if (pp.engine == 0) {

@@ -144,8 +144,8 @@ def test_pair_form_in_grouped_launches(torch_gpu):
 @pytest.mark.parametrize("A", ["diag", "spd"])
 @pytest.mark.parametrize("dt", DTS)
 def test_pair_form_batched(torch_gpu, dt, A, layout):
-    """Batches: the projection GEMM in the pair form (three rows per pair) against the
-    general form (rounding differs: tolerance) and against the oracle."""
+    """Batches: the projection GEMM in the pair form (three rows per pair, knob value 1)
+    against the general form (rounding differs: tolerance) and against the oracle."""
     B, steps = 9, 120
     _say(f"batched pair form {layout} A={A} {dt}")
     p = romsynth.make_problem(44, pairs=22, eps=1e-6, nu=1e-3, dt=1e-3, A=A, batch=B, cfg=64, dense=False, cp=True)
@@ -153,6 +153,7 @@ def test_pair_form_batched(torch_gpu, dt, A, layout):
     lam, Af, Bf, Cf = factors
     rom = rg.Rom(p.N, p.nu, p.dt, p.A, lam=lam, Af=Af, Bf=Bf, Cf=Cf, dtype=dt, max_batch=B)
     assert rg.rom_query(rom.handle, None, 7) == (2 if layout == "blocked" else 1)
+    rg.rom_set_tile(rom.handle, KIND_PAIR, 1)   # batches take the pair form only on request
     Y_pair = _eval_batch(torch_gpu, rom, p.u0)
     t_pair = _traj(rom, p.u0, steps)
     rg.rom_set_tile(rom.handle, KIND_PAIR, 0)
