@@ -15,6 +15,7 @@ from .oracle import (  # noqa: F401
     cholesky,
     chol_solve,
     energy,
+    explicit_full,
     run,
     round_f32,
     round_bf16,

@@ -54,6 +54,11 @@ def _load():
     lib.orc_run.argtypes = [_i64, ctypes.c_double, ctypes.c_double, _d, _d, _i64, _d, _d, _d,
                             _d, _i64, _d, _d, _i64, _d, _d, ctypes.POINTER(_i64)]
     lib.orc_run.restype = ctypes.c_int
+    lib.orc_explicit_full.argtypes = [_i64, _d, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d]
+    lib.orc_run_full.argtypes = [_i64, ctypes.c_double, ctypes.c_double, _d, _d, _d, _i64, _d, _d,
+                                 _d, _d, _d, _d, _d, _d, _i64, _d, _d, _i64, _d, _d,
+                                 ctypes.POINTER(_i64)]
+    lib.orc_run_full.restype = ctypes.c_int
     lib.orc_round_f32.argtypes = [_i64, _d, _d]
     lib.orc_round_bf16.argtypes = [_i64, _d, _d]
     lib.orc_split_bf16x3.argtypes = [_i64, _d, _d, _d]
@@ -182,11 +187,31 @@ def energy(u) -> float:
     return float(lib.orc_energy(u.shape[0], _p(u)))
 
 
+def explicit_full(u, *, C=None, lam=None, Af=None, Bf=None, Cf=None, C1=None, C2=None, c0=None):
+    """g = C(u)u + (C1 + C2) ubar - c0 with ubar = [1, u] (eq. nse_d1, one level);
+    C1, C2 [N][N+1], c0 [N], each optional."""
+    lib = _load()
+    u = _c(u)
+    N = u.shape[0]
+    g = np.empty(N)
+    if C is not None:
+        core = (_p(_c(C)), 0, _p(None), _p(None), _p(None), _p(None))
+    else:
+        lam, Af, Bf, Cf = map(_c, (lam, Af, Bf, Cf))
+        core = (_p(None), Af.shape[1], _p(lam), _p(Af), _p(Bf), _p(Cf))
+    opt = [None if x is None else _c(x) for x in (C1, C2, c0)]
+    lib.orc_explicit_full(N, *core, *[_p(x) for x in opt], _p(u), _p(g))
+    return g
+
+
 def run(N, nu, dt, A, nsteps, *, u0=None, C=None, lam=None, Af=None, Bf=None, Cf=None,
+        M=None, C1=None, C2=None, c0=None, a0=None,
         step0: int = 0, uh=None, yh=None, traj: bool = False) -> dict:
     """Integrate one trajectory for nsteps BDF3/EXT3 steps (with the BDF1/BDF2 ramp).
 
     Either u0 (start at step 0) or the history (step0, uh [3][N], yh [2][N]) is given.
+    M (mass matrix, default the identity) and the zeroth-mode terms C1, C2 [N][N+1],
+    c0, a0 [N] (default zero) select the full form of eq. nse_d1.
     Returns dict(u_hist, y_hist, step, E [nsteps+1], traj [nsteps+1][N] or None,
     status, first_bad).
     """
@@ -211,8 +236,14 @@ def run(N, nu, dt, A, nsteps, *, u0=None, C=None, lam=None, Af=None, Bf=None, Cf
         lam, Af, Bf, Cf = map(_c, (lam, Af, Bf, Cf))
         R = Af.shape[1]
         args = (_p(None), R, _p(lam), _p(Af), _p(Bf), _p(Cf))
-    st = lib.orc_run(N, float(nu), float(dt), _p(A), *args, int(step0), _p(uh), _p(yh),
-                     int(nsteps), _p(E), _p(T), ctypes.byref(fb))
+    full = [None if x is None else _c(x) for x in (M, C1, C2, c0, a0)]
+    if all(x is None for x in full):
+        st = lib.orc_run(N, float(nu), float(dt), _p(A), *args, int(step0), _p(uh), _p(yh),
+                         int(nsteps), _p(E), _p(T), ctypes.byref(fb))
+    else:
+        Mp, C1p, C2p, c0p, a0p = [_p(x) for x in full]
+        st = lib.orc_run_full(N, float(nu), float(dt), _p(A), Mp, *args, C1p, C2p, c0p, a0p,
+                              int(step0), _p(uh), _p(yh), int(nsteps), _p(E), _p(T), ctypes.byref(fb))
     return dict(u_hist=uh, y_hist=yh, step=step0 + nsteps, E=E, traj=T, status=int(st),
                 first_bad=int(fb.value))
 

@@ -16,7 +16,11 @@
  *                 of advecting/advected coefficients.  The contraction is symmetric in
  *                 j and k, so y_i = sum_j sum_k C[i][j][k] u_j u_k  (Sec. 2.2, eq. Cu).
  *   Af,Bf,Cf    = [N][R] CP factors for tensor positions 1, 2, 3; lam = [R] weights.
- *   A           = [N][N] reduced stiffness; the mass matrix is the identity.
+ *   A           = [N][N] reduced stiffness; M = [N][N] reduced mass matrix (NULL: the
+ *                 identity).
+ *   C1, C2      = [N][N+1] zeroth-mode matrices of eq. zeroth_contribution, column 0
+ *                 belonging to the zeroth mode (coefficient 1 in the augmented vector
+ *                 ubar = [1, u_1 .. u_N]); c0, a0 = [N] zeroth-mode vectors.
  *
  * Parity status: every function below is pinned by a CPU test (closed forms,
  * invariants, brute force, library routines); none is "parity unpinned".
@@ -251,27 +255,51 @@ static void bdf_ext(int k, double beta[4], double alpha[3])
     }
 }
 
-/* Time integration of  du/dt = -C(u)u - nu A u  (eq. nse_ode with B = I and the
- * zeroth-mode terms dropped) by the semi-implicit BDFk/EXTk scheme of eq. nse_d1:
+/* Explicit term of eq. nse_d1 at one level (Sec. 2.2):
+ *   g = C(u)u + (C1 + C2) ubar - c0,   ubar = [1, u_1 .. u_N],
+ * with C(u)u the dense contraction if C != NULL, else the CP contraction.  C1, C2, c0
+ * are each optional (NULL: zero). */
+void orc_explicit_full(int64_t N, const double *C, int64_t R, const double *lam, const double *Af,
+                       const double *Bf, const double *Cf, const double *C1, const double *C2,
+                       const double *c0, const double *u, double *g)
+{
+    if (C)
+        orc_nonlinear_dense(N, C, u, g);
+    else
+        orc_nonlinear_cp(N, R, lam, Af, Bf, Cf, u, g);
+    for (int64_t i = 0; i < N; ++i) {
+        double v = 0.0;
+        for (int64_t j = 0; j <= N; ++j) {
+            const double ub = j == 0 ? 1.0 : u[j - 1];
+            const double m = (C1 ? C1[i * (N + 1) + j] : 0.0) + (C2 ? C2[i * (N + 1) + j] : 0.0);
+            v += m * ub;
+        }
+        g[i] += v - (c0 ? c0[i] : 0.0);
+    }
+}
+
+/* Time integration of  M du/dt = -C(ubar)ubar - nu A ubar  (eq. nse_ode; M = I and no
+ * zeroth-mode terms in orc_run) by the semi-implicit BDFk/EXTk scheme of eq. nse_d1:
  *
- *   (beta0/dt I + nu A) u^{n+1} = - sum_{q=1..k} alpha_q y^{n+1-q}
- *                                 - (1/dt) sum_{q=1..k} beta_q u^{n+1-q},
- *   y^m = C(u^m) u^m,
+ *   (beta0/dt M + nu A) u^{n+1} = - sum_{q=1..k} alpha_q g^{n+1-q}
+ *                                 - M (1/dt) sum_{q=1..k} beta_q u^{n+1-q} - nu a0,
+ *   g^m = C(u^m) u^m + (C1 + C2) ubar^m - c0   (orc_explicit_full),
  *
  * with k = min(n+1, 3): the first step is BDF1/EXT1, the second BDF2/EXT2, then
  * BDF3/EXT3.
  *
- * State (in/out): step n, uh = [u^n, u^{n-1}, u^{n-2}] ([3][N]), yh = [y^{n-1},
- * y^{n-2}] ([2][N]); levels that do not exist yet are ignored.  The advection term is
+ * State (in/out): step n, uh = [u^n, u^{n-1}, u^{n-2}] ([3][N]), yh = [g^{n-1},
+ * g^{n-2}] ([2][N]); levels that do not exist yet are ignored.  The advection term is
  * the dense contraction if C != NULL, else the CP contraction.
  * Outputs (optional): E[0..nsteps] = energies of u^{n}..u^{n+nsteps};
  * traj[(s)][N] = u^{n+s}.
  * Returns 0 ok, 1 if a Helmholtz matrix is not SPD, 2 on allocation failure,
  * 4 if a state became non-finite (first_bad = that step index, integration stops). */
-int orc_run(int64_t N, double nu, double dt, const double *A, const double *C, int64_t R,
-            const double *lam, const double *Af, const double *Bf, const double *Cf,
-            int64_t step0, double *uh, double *yh, int64_t nsteps, double *E, double *traj,
-            int64_t *first_bad)
+int orc_run_full(int64_t N, double nu, double dt, const double *A, const double *M,
+                 const double *C, int64_t R, const double *lam, const double *Af,
+                 const double *Bf, const double *Cf, const double *C1, const double *C2,
+                 const double *c0, const double *a0, int64_t step0, double *uh, double *yh,
+                 int64_t nsteps, double *E, double *traj, int64_t *first_bad)
 {
     size_t nn = (size_t)(N * N);
     double *L[3] = {NULL, NULL, NULL};
@@ -305,18 +333,16 @@ int orc_run(int64_t N, double nu, double dt, const double *A, const double *C, i
             }
             for (int64_t i = 0; i < N; ++i)
                 for (int64_t j = 0; j < N; ++j)
-                    H[i * N + j] = nu * A[i * N + j] + (i == j ? beta[0] / dt : 0.0);
+                    H[i * N + j] = nu * A[i * N + j] +
+                                   (beta[0] / dt) * (M ? M[i * N + j] : (i == j ? 1.0 : 0.0));
             if (orc_cholesky(N, H, L[k - 1]) != 0) {
                 status = 1;
                 goto done;
             }
         }
 
-        /* y^n */
-        if (C)
-            orc_nonlinear_dense(N, C, uh, y);
-        else
-            orc_nonlinear_cp(N, R, lam, Af, Bf, Cf, uh, y);
+        /* g^n (the advection term, plus the zeroth-mode terms when given) */
+        orc_explicit_full(N, C, R, lam, Af, Bf, Cf, C1, C2, c0, uh, y);
 
         /* right-hand side: levels n, n-1, n-2 are uh[0..2] and y, yh[0], yh[1] */
         for (int64_t i = 0; i < N; ++i) {
@@ -324,8 +350,19 @@ int orc_run(int64_t N, double nu, double dt, const double *A, const double *C, i
             double v = 0.0;
             for (int q = 1; q <= k; ++q)
                 v -= alpha[q - 1] * ylev[q - 1][i];
-            for (int q = 1; q <= k; ++q)
-                v -= (beta[q] / dt) * uh[(size_t)(q - 1) * N + i];
+            if (M) {
+                for (int64_t j = 0; j < N; ++j) {
+                    double h = 0.0;
+                    for (int q = 1; q <= k; ++q)
+                        h += (beta[q] / dt) * uh[(size_t)(q - 1) * N + j];
+                    v -= M[i * N + j] * h;
+                }
+            } else {
+                for (int q = 1; q <= k; ++q)
+                    v -= (beta[q] / dt) * uh[(size_t)(q - 1) * N + i];
+            }
+            if (a0)
+                v -= nu * a0[i];
             rhs[i] = v;
         }
         orc_chol_solve(N, L[k - 1], rhs, un);
@@ -357,6 +394,16 @@ done:
     free(rhs);
     free(un);
     return status;
+}
+
+/* orc_run_full with the identity mass matrix and no zeroth-mode terms. */
+int orc_run(int64_t N, double nu, double dt, const double *A, const double *C, int64_t R,
+            const double *lam, const double *Af, const double *Bf, const double *Cf,
+            int64_t step0, double *uh, double *yh, int64_t nsteps, double *E, double *traj,
+            int64_t *first_bad)
+{
+    return orc_run_full(N, nu, dt, A, NULL, C, R, lam, Af, Bf, Cf, NULL, NULL, NULL, NULL, step0, uh,
+                        yh, nsteps, E, traj, first_bad);
 }
 
 /* ------------------------------------------------------------------ storage rounding */

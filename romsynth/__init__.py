@@ -12,6 +12,8 @@ from .inputs import (  # noqa: F401
     dense_rough,
     stiffness_diag,
     stiffness_spd,
+    mass_spd,
+    zeroth_terms,
     initial_u,
     make_config,
     make_problem,

@@ -13,8 +13,8 @@ saved there once and memory-mapped on later calls (same seeds give the same file
 
 Random streams come from numpy's PCG64 seeded with SeedSequence([config, stream, seed]);
 stream 0 = factors (or the rough tensor S), 1 = tensor noise, 2 = stiffness perturbation,
-3 = initial coefficients.  The draw order inside a stream is part of the recipe and
-documented next to each draw.
+3 = initial coefficients, 4 = mass matrix and zeroth-mode terms.  The draw order inside a
+stream is part of the recipe and documented next to each draw.
 """
 from __future__ import annotations
 
@@ -28,6 +28,7 @@ STREAM_FACTORS = 0
 STREAM_NOISE = 1
 STREAM_STIFF = 2
 STREAM_U0 = 3
+STREAM_FULL = 4
 
 
 def _rng(cfg: int, stream: int, seed: int) -> np.random.Generator:
@@ -166,6 +167,34 @@ def stiffness_spd(N: int, seed: int = 0, cfg: int = 3, norm: float = 0.1) -> np.
     P = norm * M / np.linalg.norm(M, 2)
     A = stiffness_diag(N) + P
     return 0.5 * (A + A.T)
+
+
+def mass_spd(N: int, seed: int = 0, cfg: int = 3, norm: float = 0.1, diag: bool = False) -> np.ndarray:
+    """Mass matrix M = I + P: P = norm * G G^T / ||G G^T||_2 with G one standard_normal((N, N))
+    from stream 4, or (diag=True) P = norm * diag(v) with v one uniform(N) draw."""
+    g = _rng(cfg, STREAM_FULL, seed)
+    if diag:
+        return np.eye(N) + norm * np.diag(g.uniform(size=N))
+    G = g.standard_normal((N, N))
+    S = G @ G.T
+    M = np.eye(N) + norm * S / np.linalg.norm(S, 2)
+    return 0.5 * (M + M.T)
+
+
+def zeroth_terms(N: int, seed: int = 0, cfg: int = 3, scale: float = 0.1):
+    """Zeroth-mode operators (C1, C2 [N][N+1], c0, a0 [N]), column 0 of C1 and C2 being the
+    zeroth mode.  Draws from stream 4 with seed + 1 in this order: C1, C2 (standard_normal,
+    (N, N+1) each), a0 (standard_normal(N)); entries times scale / sqrt(N + 1).  Column 0 of
+    both matrices is the zeroth mode advecting itself, so c0 is set to column 0 of C1 and
+    column 0 of C2 is set equal to it."""
+    g = _rng(cfg, STREAM_FULL, seed + 1)
+    s = scale / np.sqrt(N + 1.0)
+    C1 = g.standard_normal((N, N + 1)) * s
+    C2 = g.standard_normal((N, N + 1)) * s
+    a0 = g.standard_normal(N) * s
+    c0 = C1[:, 0].copy()
+    C2[:, 0] = c0
+    return C1, C2, c0, a0
 
 
 def initial_u(N: int, seeds, cfg: int = 0) -> np.ndarray:

@@ -366,3 +366,87 @@ def test_bf16x3_split(orc):
     x32 = orc.round_f32(x)
     assert np.all(np.abs(x32 - hi - lo) <= 2.0 ** -16 * np.abs(x32))
     assert np.array_equal(orc.round_bf16(lo), lo)
+
+
+# ---------------------------------------------------------------- full form (zeroth mode, mass)
+
+def test_full_explicit_term_is_augmented_contraction(orc):
+    """Eq. nse_d1's bracket C(u)u + (C1 + C2) ubar - c0 equals the contraction of the full
+    tensor (Sec. 4.2: indices 0..N in both contracted positions) with ubar = [1, u]: C1 is
+    the slice with the zeroth mode advecting, C2 the slice with it advected, and c0 their
+    shared corner, counted twice by (C1 + C2) ubar.  Brute force over the full tensor."""
+    rng = np.random.default_rng(41)
+    N = 7
+    T = rng.standard_normal((N, N + 1, N + 1))
+    u = rng.standard_normal(N)
+    ub = np.concatenate([[1.0], u])
+    want = np.array([sum(T[i, j, k] * ub[j] * ub[k] for j in range(N + 1) for k in range(N + 1))
+                     for i in range(N)])
+    C1, C2, c0 = T[:, 0, :].copy(), T[:, :, 0].copy(), T[:, 0, 0].copy()
+    core = np.ascontiguousarray(T[:, 1:, 1:])
+    g = orc.explicit_full(u, C=core, C1=C1, C2=C2, c0=c0)
+    assert np.max(np.abs(g - want)) <= 1e-13 * np.max(np.abs(want))
+    # the CP core gives the same bracket
+    R = 5
+    lam, Af, Bf, Cf = rng.standard_normal(R), *(rng.standard_normal((N, R)) for _ in range(3))
+    core_cp = np.einsum("r,ir,jr,kr->ijk", lam, Af, Bf, Cf)
+    T2 = T.copy()
+    T2[:, 1:, 1:] = core_cp
+    want2 = np.einsum("ijk,j,k->i", T2, ub, ub)
+    g2 = orc.explicit_full(u, lam=lam, Af=Af, Bf=Bf, Cf=Cf, C1=C1, C2=C2, c0=c0)
+    assert np.max(np.abs(g2 - want2)) <= 1e-12 * np.max(np.abs(want2))
+
+
+def test_full_mass_matrix_change_of_variables(orc):
+    """With M = L L^T and v = L^T u, M du/dt = -g(u) - nu (A u + a0) becomes
+    dv/dt = -L^{-1} g(L^{-T} v) - nu (L^{-1} A L^{-T} v + L^{-1} a0): identity mass, every
+    operator transformed.  BDFk/EXTk are linear in the levels, so the two discrete
+    trajectories agree up to rounding.  Pins M in the Helmholtz matrix and in the history
+    term together, and the zeroth-mode terms under the transformation."""
+    N, nu, dt, steps = 12, 2e-2, 1e-2, 60
+    A = romsynth.stiffness_spd(N, seed=2, cfg=9, norm=1.0)
+    M = romsynth.mass_spd(N, seed=3, cfg=9, norm=0.5)
+    lam, Af, Bf, Cf = romsynth.skew_cp_factors(N, 4, seed=4, cfg=9)
+    C1, C2, c0, a0 = romsynth.zeroth_terms(N, seed=5, cfg=9, scale=0.3)
+    u0 = romsynth.initial_u(N, [6], cfg=9)[0]
+    r1 = orc.run(N, nu, dt, A, steps, u0=u0, lam=lam, Af=Af, Bf=Bf, Cf=Cf, M=M, C1=C1, C2=C2,
+                 c0=c0, a0=a0, traj=True)
+    L = np.linalg.cholesky(M)
+    Li = np.linalg.inv(L)
+
+    def tr(Z):   # zeroth-mode matrix: column 0 maps like a vector, columns 1..N like L^-1 Z L^-T
+        out = np.empty_like(Z)
+        out[:, 0] = Li @ Z[:, 0]
+        out[:, 1:] = Li @ Z[:, 1:] @ Li.T
+        return out
+    r2 = orc.run(N, nu, dt, Li @ A @ Li.T, steps, u0=L.T @ u0, lam=lam, Af=Li @ Af, Bf=Li @ Bf,
+                 Cf=Li @ Cf, C1=tr(C1), C2=tr(C2), c0=Li @ c0, a0=Li @ a0, traj=True)
+    assert r1["status"] == 0 and r2["status"] == 0
+    V = r1["traj"] @ L
+    assert np.max(np.abs(V - r2["traj"])) <= 1e-10 * np.max(np.abs(r2["traj"]))
+    # the identity mass really differs: the untransformed operators give another trajectory
+    r3 = orc.run(N, nu, dt, A, steps, u0=u0, lam=lam, Af=Af, Bf=Bf, Cf=Cf, C1=C1, C2=C2, c0=c0,
+                 a0=a0, traj=True)
+    assert np.max(np.abs(r3["traj"] - r1["traj"])) > 1e-4 * np.max(np.abs(r1["traj"]))
+
+
+def test_full_fixed_point(orc):
+    """Linear full form (zero core tensor): the steady state u* solves
+    (L + nu A) u* = -(f + nu a0), L = (C1 + C2)[:, 1:], f = (C1 + C2)[:, 0] - c0.  BDFk and
+    EXTk reproduce constants exactly (their weights sum to beta0 and to 1), so started at
+    u* every level stays there whatever M is.  u* comes from numpy's solver."""
+    N, nu, dt, steps = 10, 1e-2, 1e-2, 200
+    A = romsynth.stiffness_spd(N, seed=7, cfg=9, norm=1.0)
+    M = romsynth.mass_spd(N, seed=8, cfg=9, norm=0.5)
+    C1, C2, c0, a0 = romsynth.zeroth_terms(N, seed=9, cfg=9, scale=0.3)
+    L = (C1 + C2)[:, 1:]
+    f = (C1 + C2)[:, 0] - c0
+    us = np.linalg.solve(L + nu * A, -(f + nu * a0))
+    r = orc.run(N, nu, dt, A, steps, u0=us, C=np.zeros((N, N, N)), M=M, C1=C1, C2=C2, c0=c0, a0=a0,
+                traj=True)
+    assert r["status"] == 0
+    assert np.max(np.abs(r["traj"] - us)) <= 1e-11 * np.max(np.abs(us))
+    # a sign error in a0 moves the state off u*
+    r2 = orc.run(N, nu, dt, A, steps, u0=us, C=np.zeros((N, N, N)), M=M, C1=C1, C2=C2, c0=c0,
+                 a0=-a0, traj=True)
+    assert np.max(np.abs(r2["traj"][-1] - us)) > 1e-6 * np.max(np.abs(us))
