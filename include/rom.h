@@ -104,6 +104,34 @@ rom_status rom_create(const rom_desc *d, rom_ctx *out);
  * rom_step_multi steps such states one by one.  Errors as rom_create. */
 rom_status rom_create_svd(const rom_desc *d, int32_t R, const double *U, const double *sigma,
                           const double *V, rom_ctx *out);
+
+/* Full form of the reduced system (Sec. 2.2, eqs. nse_ode, nse_d1 and
+ * zeroth_contribution): a mass matrix and the terms of the zeroth mode phi_0, whose
+ * coefficient is 1 in the augmented vector ubar = [1, u_1 .. u_N].  Every pointer is host
+ * FP64, row-major, read during rom_create_full only, and nullable:
+ *   M       [N][N] symmetric positive definite mass matrix; NULL = the identity.
+ *   C1, C2  [N][N+1] zeroth-mode advection matrices, column 0 for phi_0; NULL = zero.
+ *   c0, a0  [N] zeroth-mode advection and stiffness vectors; NULL = zero.
+ * Each step then solves (beta0/dt M + nu A) u^{n+1} = - sum_q alpha_q [C(u)u + (C1 + C2) ubar
+ * - c0]^{n+1-q} - M (1/dt) sum_q beta_q u^{n+1-q} - nu a0, the -c0 removing the phi_0-phi_0
+ * entry that C1 ubar and C2 ubar both contain. */
+typedef struct rom_full_terms {
+    const double *M;
+    const double *C1;
+    const double *C2;
+    const double *c0;
+    const double *a0;
+} rom_full_terms;
+
+/* rom_create with the full form (dense tensor or CP factors; not the SVD form).  States
+ * of the context take one more FP64 kernel per step (the zeroth-mode and mass terms, an
+ * N x 2N GEMV); rom_nonlinear still returns C(u)u alone, and so does the y history of
+ * rom_state_get / rom_state_set (each step recomputes the zeroth-mode and mass terms
+ * from the u history).  Such states step on their own
+ * under rom_step_multi.  Errors as rom_create, plus ROM_E_INVALID for f == NULL or a
+ * non-symmetric M (a non-SPD M shows as a non-SPD Helmholtz matrix) and
+ * ROM_E_UNSUPPORTED for N > 4096. */
+rom_status rom_create_full(const rom_desc *d, const rom_full_terms *f, rom_ctx *out);
 void rom_destroy(rom_ctx ctx);
 
 /* y = C(u)u for `batch` coefficient vectors (Sec. 2.2, eq. Cu; CP form: eq. tc_ap).

@@ -25,7 +25,8 @@ EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_timed", 
            "rom_state_destroy",
            "rom_step", "rom_step_async", "rom_step_sync", "rom_energy", "rom_state_get",
            "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
-           "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_last_error"]
+           "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_create_full",
+           "rom_last_error"]
 
 _d = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -37,6 +38,10 @@ class rom_desc(ctypes.Structure):
                 ("dt", ctypes.c_double), ("A", _d), ("C", _d), ("lambda_", _d), ("Af", _d),
                 ("Bf", _d), ("Cf", _d), ("dtype", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("stream", _vp)]
+
+
+class rom_full_terms(ctypes.Structure):
+    _fields_ = [("M", _d), ("C1", _d), ("C2", _d), ("c0", _d), ("a0", _d)]
 
 
 class RomError(RuntimeError):
@@ -94,6 +99,8 @@ def lib():
     L.rom_cp_skew_layout.argtypes = [ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _d]
     L.rom_create_svd.argtypes = [ctypes.POINTER(rom_desc), ctypes.c_int32, _d, _d, _d, ctypes.POINTER(_vp)]
     L.rom_create_svd.restype = ctypes.c_int
+    L.rom_create_full.argtypes = [ctypes.POINTER(rom_desc), ctypes.POINTER(rom_full_terms), ctypes.POINTER(_vp)]
+    L.rom_create_full.restype = ctypes.c_int
     L.rom_cp_skew_layout.restype = ctypes.c_int32
     L.rom_last_error.argtypes = []
     L.rom_last_error.restype = ctypes.c_char_p
@@ -142,10 +149,11 @@ def _stream_handle(stream) -> Optional[int]:
 
 # ----------------------------------------------------------------------------- the C calls
 
-def rom_create(N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, svd=None, dtype="fp32",
-               max_batch=1, stream=None) -> int:
+def rom_create(N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, svd=None, full=None,
+               dtype="fp32", max_batch=1, stream=None) -> int:
     """Returns the context handle (int).  Host arrays are FP64 numpy-compatible.  svd:
-    (U [N][R], sigma [R], V [N][N][R]) for the SVD form (rom_create_svd)."""
+    (U [N][R], sigma [R], V [N][N][R]) for the SVD form (rom_create_svd).  full: a dict
+    with any of M, C1, C2, c0, a0 for the full form (rom_create_full)."""
     L = lib()
     keep = []
 
@@ -167,6 +175,12 @@ def rom_create(N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, svd
         U, sig, V = svd
         Rs = int(np.asarray(U).shape[1])
         _check(L.rom_create_svd(ctypes.byref(d), Rs, h(U), h(sig), h(V), ctypes.byref(out)))
+    elif full is not None:
+        unknown = set(full) - {"M", "C1", "C2", "c0", "a0"}
+        if unknown:
+            raise ValueError(f"unknown full-form terms {sorted(unknown)}")
+        f = rom_full_terms(**{k: h(full.get(k)) for k in ("M", "C1", "C2", "c0", "a0")})
+        _check(L.rom_create_full(ctypes.byref(d), ctypes.byref(f), ctypes.byref(out)))
     else:
         _check(L.rom_create(ctypes.byref(d), ctypes.byref(out)))
     return out.value
@@ -285,14 +299,14 @@ def rom_last_error() -> str:
 class Rom:
     """Owning wrapper of a context (rom_create / rom_destroy)."""
 
-    def __init__(self, N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, svd=None,
+    def __init__(self, N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, svd=None, full=None,
                  dtype="fp32", max_batch=1, stream=None):
         self.N = int(N)
         self.dtype = dtype
         self.max_batch = int(max_batch)
         self.stream = stream
-        self.handle = rom_create(N, nu, dt, A, C=C, lam=lam, Af=Af, Bf=Bf, Cf=Cf, svd=svd, dtype=dtype,
-                                 max_batch=max_batch, stream=stream)
+        self.handle = rom_create(N, nu, dt, A, C=C, lam=lam, Af=Af, Bf=Bf, Cf=Cf, svd=svd, full=full,
+                                 dtype=dtype, max_batch=max_batch, stream=stream)
 
     @classmethod
     def from_problem(cls, p, *, dense=True, dtype="fp32", max_batch=None, stream=None):

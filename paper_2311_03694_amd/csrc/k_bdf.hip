@@ -193,12 +193,13 @@ void launch_sum_partials(int acc_f64, const void* part, int nchunk, int pb, int 
 
 // ============================================================== Helmholtz setup
 
+// H = nu A + (beta0/dt) M, M the mass matrix (NULL: the identity).
 __global__ void k_build_h(int N, double nu, double diag, const double* __restrict__ A,
-                          double* __restrict__ H) {
+                          const double* __restrict__ M, double* __restrict__ H) {
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (size_t)N * N) return;
     const int i = (int)(q / N), m = (int)(q % N);
-    H[q] = nu * A[q] + (i == m ? diag : 0.0);
+    H[q] = nu * A[q] + diag * (M ? M[q] : (i == m ? 1.0 : 0.0));
 }
 
 // Left-looking Cholesky, column j: one wavefront per row i >= j.
@@ -259,15 +260,16 @@ __global__ void k_gram(int N, int Np, const double* __restrict__ X, double* __re
 }
 
 __global__ void k_hdiag(int N, double nu, double inv_dt, const double* __restrict__ A,
-                        double* __restrict__ hd) {
+                        const double* __restrict__ M, double* __restrict__ hd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double b0[3] = {1.0, 1.5, 11.0 / 6.0};
-    for (int k = 0; k < 3; ++k) hd[(size_t)k * N + i] = 1.0 / (b0[k] * inv_dt + nu * A[(size_t)i * N + i]);
+    const double mi = M ? M[(size_t)i * N + i] : 1.0;
+    for (int k = 0; k < 3; ++k) hd[(size_t)k * N + i] = 1.0 / (b0[k] * inv_dt * mi + nu * A[(size_t)i * N + i]);
 }
 
-int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, double* hinv_dev,
-                     double* work_dev, int* info_dev, hipStream_t s) {
+int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, const double* M_dev,
+                     double* hinv_dev, double* work_dev, int* info_dev, hipStream_t s) {
     // work_dev: 3 N^2 doubles (H, L, X)
     double* H = work_dev;
     double* L = work_dev + (size_t)N * N;
@@ -275,7 +277,7 @@ int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, d
     const double b0[3] = {1.0, 1.5, 11.0 / 6.0};
     const size_t nn = (size_t)N * N;
     for (int k = 0; k < 3; ++k) {
-        hipLaunchKernelGGL(k_build_h, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, nu, b0[k] / dt, A_dev, H);
+        hipLaunchKernelGGL(k_build_h, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, nu, b0[k] / dt, A_dev, M_dev, H);
         hipMemsetAsync(L, 0, nn * sizeof(double), s);
         for (int j = 0; j < N; ++j)
             hipLaunchKernelGGL(k_chol_col, dim3((N - j + 3) / 4), dim3(256), 0, s, N, j, H, L, info_dev);
@@ -286,9 +288,90 @@ int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, d
     return 0;
 }
 
-void helm_setup_diag(int N, double nu, double dt, const double* A_dev, double* hdiag_dev,
+void helm_setup_diag(int N, double nu, double dt, const double* A_dev, const double* M_dev, double* hdiag_dev,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_hdiag, dim3((N + 255) / 256), dim3(256), 0, s, N, nu, 1.0 / dt, A_dev, hdiag_dev);
+    hipLaunchKernelGGL(k_hdiag, dim3((N + 255) / 256), dim3(256), 0, s, N, nu, 1.0 / dt, A_dev, M_dev, hdiag_dev);
+}
+
+// ============================================================== full form (zeroth mode, mass)
+
+// G [N][2 Np] = [L | M - I] with L = (C1 + C2)[:, 1:], zero padding; fz = (C1 + C2)[:, 0]
+// - c0 (the constant of the bracket of eq. nse_d1 at ubar_0 = 1); az = nu a0.  C1, C2 are
+// [N][N+1]; a NULL operator counts as zero (M: the identity).
+__global__ void k_full_setup(int N, int Np, double nu, const double* __restrict__ M, const double* __restrict__ C1,
+                             const double* __restrict__ C2, const double* __restrict__ c0,
+                             const double* __restrict__ a0, double* __restrict__ G, double* __restrict__ fz,
+                             double* __restrict__ az) {
+    const int i = blockIdx.y, m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= 2 * Np) return;
+    const size_t w = (size_t)N + 1;
+    double v = 0.0;
+    if (m < N) {
+        v = (C1 ? C1[(size_t)i * w + 1 + m] : 0.0) + (C2 ? C2[(size_t)i * w + 1 + m] : 0.0);
+    } else if (m >= Np && m - Np < N) {
+        const int j = m - Np;
+        v = M ? M[(size_t)i * N + j] - (i == j ? 1.0 : 0.0) : 0.0;
+    }
+    G[(size_t)i * 2 * Np + m] = v;
+    if (m == 0) {
+        fz[i] = (C1 ? C1[(size_t)i * w] : 0.0) + (C2 ? C2[(size_t)i * w] : 0.0) - (c0 ? c0[i] : 0.0);
+        az[i] = a0 ? nu * a0[i] : 0.0;
+    }
+}
+
+void full_setup(int N, int Np, double nu, const double* M, const double* C1, const double* C2,
+                const double* c0, const double* a0, double* G, double* fz, double* az, hipStream_t s) {
+    hipLaunchKernelGGL(k_full_setup, dim3((2 * Np + 255) / 256, N), dim3(256), 0, s, N, Np, nu, M, C1, C2, c0, a0,
+                       G, fz, az);
+}
+
+// Zeroth-mode and mass terms of the right-hand side of level n (eq. nse_d1), per
+// trajectory b:
+//   zfull = L uhat + (M - I) h + (sum_q alpha_q) fz + az,
+//   uhat = sum_q alpha_q u^{n+1-q},  h = (1/dt) sum_q beta_q u^{n+1-q}
+// (the EXT sum of the linear and constant parts of the bracket, and M minus the identity
+// times the BDF history sum, which the rhs already carries).  Grid (ceil(N/4), B), 256
+// threads: x = [uhat | h] staged in LDS (2 Np doubles), then one wavefront per row of G.
+__global__ __launch_bounds__(256) void k_full_terms(StepArgs a, const double* __restrict__ G,
+                                                    const double* __restrict__ fz,
+                                                    const double* __restrict__ az) {
+    extern __shared__ double xs[];
+    const long long n = *a.step;
+    const int k = bdf_order(n);
+    const BdfCoef c = bdf_coef(k);
+    const int b = blockIdx.y, Np = a.Np;
+    const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N;
+    for (int j = threadIdx.x; j < Np; j += blockDim.x) {
+        double uh = 0.0, h = 0.0;
+        if (j < a.N) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (q < k) {
+                    const double u = a.uring[(size_t)slot_of(n - q) * BN + off + j];
+                    uh += c.alpha[q] * u;
+                    h += (c.beta[q + 1] * a.inv_dt) * u;
+                }
+        }
+        xs[j] = uh;
+        xs[Np + j] = h;
+    }
+    __syncthreads();
+    double sa = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        if (q < k) sa += c.alpha[q];
+    const int lane = threadIdx.x & (kWave - 1), i = blockIdx.x * 4 + (threadIdx.x / kWave);
+    if (i >= a.N) return;
+    const double* g = G + (size_t)i * 2 * Np;
+    double s = 0.0;
+    for (int m = lane; m < 2 * Np; m += kWave) s += g[m] * xs[m];
+    s = wave_sum(s);
+    if (lane == 0) a.zfull[off + i] = s + sa * fz[i] + az[i];
+}
+
+void launch_full_terms(const StepArgs& a, const double* G, const double* fz, const double* az, hipStream_t s) {
+    hipLaunchKernelGGL(k_full_terms, dim3((a.N + 3) / 4, a.B), dim3(256), sizeof(double) * 2 * a.Np, s, a, G, fz,
+                       az);
 }
 
 // ============================================================== storage conversion

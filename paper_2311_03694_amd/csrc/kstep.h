@@ -24,7 +24,8 @@ __device__ __forceinline__ BdfHist bdf_hist_point(const StepArgs& a, long long n
 }
 
 // Store y^n, form the right-hand side of eq. nse_d1 for point (b, i) from its history:
-//   rhs = - sum_{q<=k} alpha_q y^{n+1-q} - (1/dt) sum_{q<=k} beta_q u^{n+1-q}.
+//   rhs = - sum_{q<=k} alpha_q y^{n+1-q} - (1/dt) sum_{q<=k} beta_q u^{n+1-q} [- zfull],
+// zfull carrying the zeroth-mode terms and (M - I) times the history sum (full form).
 __device__ __forceinline__ double bdf_rhs_hist(const StepArgs& a, long long n, const BdfCoef& c, int k, int b,
                                                int i, double y, const BdfHist& h) {
     a.yring[(size_t)slot_of(n) * ((size_t)a.B * a.N) + (size_t)b * a.N + i] = y;
@@ -36,6 +37,7 @@ __device__ __forceinline__ double bdf_rhs_hist(const StepArgs& a, long long n, c
 #pragma unroll
     for (int q = 0; q < 3; ++q)
         if (q < k) v -= (c.beta[q + 1] * a.inv_dt) * h.u[q];
+    if (a.zfull) v -= a.zfull[(size_t)b * a.N + i];
     return v;
 }
 

@@ -89,6 +89,10 @@ struct rom_ctx_s {
     void *Ut = nullptr, *Ut_lo = nullptr, *sig = nullptr, *Vt = nullptr, *Vt_lo = nullptr;
     double* hdiag = nullptr;                    // [3][N]
     double* hinv = nullptr;                     // [3][N][N]
+    // full form of eq. nse_d1 (mass matrix, zeroth-mode terms): G = [L | M - I]
+    // [N][2Np], fz = constant of the bracket, az = nu a0 (FP64)
+    bool full = false;
+    double *Gfull = nullptr, *fz = nullptr, *az = nullptr;
     // workspaces (shared by every state of the context; one stream serializes use)
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -399,7 +403,7 @@ struct SvdDesc {
     const double *U, *sigma, *V;
 };
 
-static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out) {
+static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, const rom_full_terms* fd, rom_ctx* out) {
     if (!out) return fail(ROM_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!d) return fail(ROM_E_INVALID, "desc is NULL");
@@ -423,6 +427,14 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out)
     }
     const long long N = d->N;
     if (d->C && N > 4096) return fail(ROM_E_UNSUPPORTED, "dense tensors are limited to N <= 4096");
+    if (fd && sv) return fail(ROM_E_UNSUPPORTED, "the full form takes the dense tensor or the CP factors");
+    if (fd && (N + 7) / 8 * 8 > 4096)
+        return fail(ROM_E_UNSUPPORTED, "the full form is limited to N <= 4096 (LDS staging of its GEMV)");
+    if (fd && fd->M)
+        for (long long i = 0; i < N; ++i)
+            for (long long m = 0; m < i; ++m)
+                if (fd->M[i * N + m] != fd->M[m * N + i])
+                    return fail(ROM_E_INVALID, "mass matrix M is not symmetric (%lld, %lld)", i, m);
     if (N > 16384) return fail(ROM_E_UNSUPPORTED, "N > 16384 is not supported");
     // one-trajectory kernels stage u in LDS (64 KB per block): per padded mode 8 bytes
     // (FP64), 4 (FP32), 6 (BF16: words and weights) or 8 (BF16x3); the CP projections of
@@ -452,6 +464,7 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out)
     c->max_batch = d->max_batch;
     c->dense = d->C != nullptr;
     c->svd = sv != nullptr;
+    c->full = fd != nullptr;
     c->stream = (hipStream_t)d->stream;
     rom_status st = ROM_OK;
 #define TRY(x)                          \
@@ -492,10 +505,11 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out)
     }
 
     // ---- stiffness: diagonal detection, Helmholtz data
+    const double* Mh = fd ? fd->M : nullptr;   // mass matrix (NULL: the identity)
     bool diag = true;
     for (long long i = 0; i < N && diag; ++i)
         for (long long m = 0; m < N; ++m)
-            if (i != m && d->A[i * N + m] != 0.0) {
+            if (i != m && (d->A[i * N + m] != 0.0 || (Mh && Mh[i * N + m] != 0.0))) {
                 diag = false;
                 break;
             }
@@ -514,13 +528,31 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out)
         ~StageGuard() { if (p) hipFree(p); }
     } guard{stage};
     HTRY(hipMemcpyAsync(stage, d->A, sizeof(double) * nn, hipMemcpyHostToDevice, c->stream));
+    // full form: M, C1, C2, c0, a0 on the device for the Helmholtz matrices and G
+    double* fdev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    struct FullGuard {
+        double** p;
+        ~FullGuard() {
+            for (int q = 0; q < 5; ++q)
+                if (p[q]) hipFree(p[q]);
+        }
+    } fguard{fdev};
+    if (fd) {
+        const double* src[5] = {fd->M, fd->C1, fd->C2, fd->c0, fd->a0};
+        const size_t cnt[5] = {nn, (size_t)N * (N + 1), (size_t)N * (N + 1), (size_t)N, (size_t)N};
+        for (int q = 0; q < 5; ++q) {
+            if (!src[q]) continue;
+            HTRY(hipMalloc((void**)&fdev[q], sizeof(double) * cnt[q]));
+            HTRY(hipMemcpyAsync(fdev[q], src[q], sizeof(double) * cnt[q], hipMemcpyHostToDevice, c->stream));
+        }
+    }
     if (diag) {
         TRY(dmalloc((void**)&c->hdiag, sizeof(double) * 3 * N, &c->bytes, &c->allocs));
-        helm_setup_diag((int)N, d->nu, d->dt, stage, c->hdiag, c->stream);
+        helm_setup_diag((int)N, d->nu, d->dt, stage, fdev[0], c->hdiag, c->stream);
         HTRY(hipGetLastError());
         // SPD check of the three diagonal Helmholtz matrices
         for (long long i = 0; i < N; ++i) {
-            const double h = 1.0 / d->dt + d->nu * d->A[i * N + i];
+            const double h = (Mh ? Mh[i * N + i] : 1.0) / d->dt + d->nu * d->A[i * N + i];
             if (!(h > 0.0)) {
                 st = fail(ROM_E_INVALID, "Helmholtz matrix not positive definite (row %lld)", i);
                 rom_destroy(c);
@@ -536,7 +568,7 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out)
         HTRY(hipMalloc((void**)&work, sizeof(double) * 3 * nn));
         HTRY(hipMalloc((void**)&info, sizeof(int)));
         HTRY(hipMemsetAsync(info, 0, sizeof(int), c->stream));
-        helm_setup_dense((int)N, c->Np, d->nu, d->dt, stage, c->hinv, work, info, c->stream);
+        helm_setup_dense((int)N, c->Np, d->nu, d->dt, stage, fdev[0], c->hinv, work, info, c->stream);
         hipError_t le = hipGetLastError();
         int hinfo = 0;
         hipError_t se = hipStreamSynchronize(c->stream);
@@ -550,10 +582,18 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out)
             return st;
         }
         if (hinfo != 0) {
-            st = fail(ROM_E_INVALID, "Helmholtz matrix (beta0/dt) I + nu A is not positive definite");
+            st = fail(ROM_E_INVALID, "Helmholtz matrix (beta0/dt) M + nu A is not positive definite");
             rom_destroy(c);
             return st;
         }
+    }
+    if (fd) {
+        TRY(dmalloc((void**)&c->Gfull, sizeof(double) * N * 2 * c->Np, &c->bytes, &c->allocs));
+        TRY(dmalloc((void**)&c->fz, sizeof(double) * N, &c->bytes, &c->allocs));
+        TRY(dmalloc((void**)&c->az, sizeof(double) * N, &c->bytes, &c->allocs));
+        full_setup((int)N, c->Np, d->nu, fdev[0], fdev[1], fdev[2], fdev[3], fdev[4], c->Gfull, c->fz, c->az,
+                   c->stream);
+        HTRY(hipGetLastError());
     }
     HTRY(hipStreamSynchronize(c->stream));
 
@@ -693,12 +733,19 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, rom_ctx* out)
     return ROM_OK;
 }
 
-extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) { return create_ctx(d, nullptr, out); }
+extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) { return create_ctx(d, nullptr, nullptr, out); }
+extern "C" rom_status rom_create_full(const rom_desc* d, const rom_full_terms* f, rom_ctx* out) {
+    if (!f) {
+        if (out) *out = nullptr;
+        return fail(ROM_E_INVALID, "full terms are NULL");
+    }
+    return create_ctx(d, nullptr, f, out);
+}
 
 extern "C" rom_status rom_create_svd(const rom_desc* d, int32_t R, const double* U, const double* sigma,
                                      const double* V, rom_ctx* out) {
     const SvdDesc sv{R, U, sigma, V};
-    return create_ctx(d, &sv, out);
+    return create_ctx(d, &sv, nullptr, out);
 }
 
 // ============================================================== contraction dispatch
@@ -764,6 +811,7 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
     const WsPlan p = plan_ws(c, s->B);
     const int accf = acc_f64(c->dtype);
     const int diag = c->diagA ? 1 : 0;
+    if (c->full) launch_full_terms(a, c->Gfull, c->fz, c->az, stream);
     if (s->B == 1) {
         char* ws = (char*)s->scratch;
         if (c->dense) {
@@ -1066,6 +1114,7 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(dmalloc((void**)&a.closep, sizeof(int), &s->bytes, &s->allocs));
     if (!c->dense && !c->svd && batch == 1)
         TRY(dmalloc(&a.st, c->Rp * acc_bytes(c->dtype), &s->bytes, &s->allocs));
+    if (c->full) TRY(dmalloc((void**)&a.zfull, sizeof(double) * BN, &s->bytes, &s->allocs));
     if (a.batched) {
         const size_t cells = (size_t)s->Bpad * c->Np;
         TRY(dmalloc(&a.ucv, cells * elem_bytes(c->dtype), &s->bytes, &s->allocs));
@@ -1352,7 +1401,7 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
     for (int q = 0; q < n; ++q) {
         rom_ctx c = ctxs[q];
         rom_state st = states[q];
-        if (st->B != 1 || c->svd) {          // batches and SVD-form states step on their own
+        if (st->B != 1 || c->svd || c->full) {   // batches, SVD- and full-form states step on their own
             if (par == 0) batched.push_back(q);
             continue;
         }

@@ -40,7 +40,9 @@ struct StepArgs {
     int* ecount;             // [2] partials per trajectory of a level, same parity slots
     int enmax;               // capacity per trajectory (at least any update kernel's blocks)
     const double* hdiag;     // [3][N] 1/(beta0_k/dt + nu A_ii) (diagonal stiffness)
-    const double* hinv;      // [3][N][Np] (beta0_k/dt I + nu A)^-1, row pitch Np (dense stiffness)
+    const double* hinv;      // [3][N][Np] (beta0_k/dt M + nu A)^-1, row pitch Np (dense stiffness)
+    double* zfull;           // full form: [B][N] zeroth-mode and mass terms of the level's
+                             // right-hand side (k_full_terms); NULL otherwise
     // coefficient copies in the contraction's number format for the batched kernels,
     // laid out [Bpad][Np] (padding rows and columns stay zero); written by the update
     // of each step
@@ -194,10 +196,16 @@ void launch_sum_partials(int acc_f64, const void* part, int nchunk, int pb, int 
                          double* y, hipStream_t s);
 
 // Helmholtz setup on the device: H = (beta0/dt) I + nu A, Cholesky, inverse.
-int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, double* hinv_dev,
-                     double* work_dev, int* info_dev, hipStream_t s);
-void helm_setup_diag(int N, double nu, double dt, const double* A_dev, double* hdiag_dev,
+int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, const double* M_dev,
+                     double* hinv_dev, double* work_dev, int* info_dev, hipStream_t s);
+void helm_setup_diag(int N, double nu, double dt, const double* A_dev, const double* M_dev, double* hdiag_dev,
                      hipStream_t s);
+// Full form of eq. nse_d1 (k_bdf.hip).  Setup: G = [L | M - I] [N][2 Np] with
+// L = (C1 + C2)[:, 1:], fz = (C1 + C2)[:, 0] - c0, az = nu a0 (each input nullable: zero,
+// M: the identity).  Per step: zfull of the level from the step counter.
+void full_setup(int N, int Np, double nu, const double* M, const double* C1, const double* C2,
+                const double* c0, const double* a0, double* G, double* fz, double* az, hipStream_t s);
+void launch_full_terms(const StepArgs& a, const double* G, const double* fz, const double* az, hipStream_t s);
 
 // Batched contraction launchers (k_mfma.hip).  Partials are [nsplit][Bpad][M] in the
 // accumulation type (FP64 for DT_F64, FP32 otherwise).

@@ -114,3 +114,29 @@ def test_lds_staging_limit_rejected():
         rg.rom_create(N, 1e-3, 1e-3, np.eye(1), lam=np.ones(R), Af=f, Bf=f, Cf=f, dtype="bf16")
     assert ei.value.status == rg.binding.ROM_E_UNSUPPORTED
     assert "LDS staging of u" in str(ei.value)
+
+
+@pytest.mark.parametrize("case,status,msg", [
+    ("null_terms", "ROM_E_INVALID", "full terms are NULL"),
+    ("asymmetric_mass", "ROM_E_INVALID", "not symmetric"),
+    ("too_large", "ROM_E_UNSUPPORTED", "N <= 4096"),
+])
+def test_create_full_rejects_invalid(case, status, msg):
+    """rom_create_full checks its terms before any device work."""
+    N = 4100 if case == "too_large" else 6
+    R = 1
+    A = np.eye(N)
+    lam, Af = np.ones(R), np.ones((N, R))
+    d = rg.binding.rom_desc(N=N, R=R, nu=1e-3, dt=1e-3, A=rg.binding._ptr(A), lambda_=rg.binding._ptr(lam),
+                            Af=rg.binding._ptr(Af), Bf=rg.binding._ptr(Af), Cf=rg.binding._ptr(Af),
+                            dtype=1, max_batch=1)
+    M = np.eye(N) if N < 100 else None
+    if case == "asymmetric_mass":
+        M[2, 1] = 0.25
+    f = rg.binding.rom_full_terms(M=rg.binding._ptr(M))
+    out = ctypes.c_void_p()
+    fp = None if case == "null_terms" else ctypes.byref(f)
+    st = rg.lib().rom_create_full(ctypes.byref(d), fp, ctypes.byref(out))
+    assert st == getattr(rg.binding, status)
+    assert msg in rg.rom_last_error()
+    assert out.value is None
