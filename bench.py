@@ -26,6 +26,8 @@ Also in the one JSON line:
                 and CP rank 400, with TFLOP/s against the dense MFMA peaks
   svd           the SVD-ROM (Sec. 4.4) at N = 1000 with SVD ranks 100 and 250 (compression
                 N/R = 10 and 4), FP32, one trajectory: steps/s and the streaming bandwidth
+  full          the full form of the reduced system (dense SPD mass matrix, zeroth-mode
+                terms) at the headline size, CP rank 2000 FP32, against the plain step
   multi         uneven N: one CP trajectory each at N = 100, 200, 400, 700, 1000 stepped
                 together by grouped launches (rom_step_multi) and one after the other
   serving       a bounded Poisson request stream through the continuous-batching loop
@@ -65,7 +67,7 @@ def parse():
                     help="target length of the oracle sample (CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no batched/config2/serving)")
-    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "svd", "multi", "serving"],
+    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "svd", "full", "multi", "serving"],
                     help="run one section only (profiling); the JSON line then holds that section")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--calib-copy", action="store_true",
@@ -328,6 +330,36 @@ def main():
             s_s.close()
             rom_s.close()
         result["svd"] = svd
+
+    if not args.no_extra and sec in ("all", "full"):
+        # ---------------- full form of the reduced system at the headline size: dense SPD
+        # mass matrix and zeroth-mode terms beside the CP rank-2000 contraction; plain and
+        # full contexts stepped in alternation on the same stream
+        C1, C2, c0, a0 = romsynth.zeroth_terms(N, seed=1, cfg=3, scale=0.1)
+        full_terms = dict(M=romsynth.mass_spd(N, seed=2, cfg=3, norm=0.1), C1=C1, C2=C2, c0=c0, a0=a0)
+        core = dict(lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
+        rom_f = rg.Rom(N, p.nu, p.dt, p.A, **core, full=full_terms, dtype="fp32", max_batch=1, stream=stream)
+        rom_p = rg.Rom(N, p.nu, p.dt, p.A, **core, dtype="fp32", max_batch=1, stream=stream)
+        for r in (rom_f, rom_p):
+            tune.apply(r, 1, dense=False, R=R, table=tiles)
+        s_f, s_p = rom_f.state(p.u0), rom_p.state(p.u0)
+        s_f.step(200)
+        s_p.step(200)
+        nf, tf, tp = 4000, [], []
+        for _ in range(3):
+            tf.append(timer(lambda: s_f.step_async(nf)))
+            s_f.sync()
+            tp.append(timer(lambda: s_p.step_async(nf)))
+            s_p.sync()
+        t_f, t_p = min(tf) / nf, min(tp) / nf
+        Np = (N + 7) // 8 * 8
+        result["full"] = {"traj_steps_per_s": 1.0 / t_f, "us_per_step": t_f * 1e6, "plain_us_per_step": t_p * 1e6,
+                          "extra_us_per_step": (t_f - t_p) * 1e6, "terms_bytes_per_step": 16.0 * N * Np,
+                          "config": "N=1000, CP rank 2000 FP32, SPD stiffness, dense SPD mass matrix, "
+                                    "zeroth-mode C1, C2, c0, a0 (FP64)"}
+        log(f"full form: {1.0 / t_f:.0f} steps/s ({t_f * 1e6:.2f} us/step; plain {t_p * 1e6:.2f})")
+        for x in (s_f, s_p, rom_f, rom_p):
+            x.close()
 
     if not args.no_extra and sec in ("all", "multi"):
         # ---------------- uneven N: grouped launches against the same states one by one

@@ -331,47 +331,94 @@ void full_setup(int N, int Np, double nu, const double* M, const double* C1, con
 //   uhat = sum_q alpha_q u^{n+1-q},  h = (1/dt) sum_q beta_q u^{n+1-q}
 // (the EXT sum of the linear and constant parts of the bracket, and M minus the identity
 // times the BDF history sum, which the rhs already carries).  Grid (ceil(N/4), B), 256
-// threads: x = [uhat | h] staged in LDS (2 Np doubles), then one wavefront per row of G.
+// threads, one wavefront per row of G (2 Np doubles, read as 16-byte pairs in chunks of
+// 16 per lane, a whole row up to N = 1024).  The first chunk of G and the history loads of
+// the staging (up to 1024 coefficients per pass) are all issued before any of them is
+// used, so the kernel waits for one round trip to memory instead of one per loop pass.
+constexpr int kFullRows = 4, kFullChunk = 16, kFullStage = 4;
 __global__ __launch_bounds__(256) void k_full_terms(StepArgs a, const double* __restrict__ G,
                                                     const double* __restrict__ fz,
                                                     const double* __restrict__ az) {
-    extern __shared__ double xs[];
+    extern __shared__ double2 xs2[];
+    double* xs = reinterpret_cast<double*>(xs2);
+    const int b = blockIdx.y, Np = a.Np;
+    const int lane = threadIdx.x & (kWave - 1), i = blockIdx.x * kFullRows + (threadIdx.x / kWave);
+    const bool active = i < a.N;
+    // row i of G as Np pairs (Np is a multiple of 8, rows 16-byte aligned)
+    const double2* g2 = reinterpret_cast<const double2*>(G + (size_t)(active ? i : 0) * 2 * Np);
+    double2 gv[kFullChunk];
+#pragma unroll
+    for (int u = 0; u < kFullChunk; ++u) {
+        const int m = lane + u * kWave;
+        gv[u] = (active && m < Np) ? g2[m] : make_double2(0.0, 0.0);
+    }
     const long long n = *a.step;
     const int k = bdf_order(n);
     const BdfCoef c = bdf_coef(k);
-    const int b = blockIdx.y, Np = a.Np;
     const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N;
-    for (int j = threadIdx.x; j < Np; j += blockDim.x) {
-        double uh = 0.0, h = 0.0;
-        if (j < a.N) {
+    const double* lev[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) lev[q] = a.uring + (size_t)slot_of(n - q) * BN + off;
+    for (int j0 = 0; j0 < Np; j0 += kFullStage * (int)blockDim.x) {
+        double uv[3][kFullStage];
+#pragma unroll
+        for (int e = 0; e < kFullStage; ++e) {
+            const int j = j0 + e * (int)blockDim.x + (int)threadIdx.x;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) uv[q][e] = (q < k && j < a.N) ? lev[q][j] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < kFullStage; ++e) {
+            const int j = j0 + e * (int)blockDim.x + (int)threadIdx.x;
+            double uh = 0.0, h = 0.0;
 #pragma unroll
             for (int q = 0; q < 3; ++q)
                 if (q < k) {
-                    const double u = a.uring[(size_t)slot_of(n - q) * BN + off + j];
-                    uh += c.alpha[q] * u;
-                    h += (c.beta[q + 1] * a.inv_dt) * u;
+                    uh += c.alpha[q] * uv[q][e];
+                    h += (c.beta[q + 1] * a.inv_dt) * uv[q][e];
                 }
+            if (j < Np) {
+                xs[j] = uh;
+                xs[Np + j] = h;
+            }
         }
-        xs[j] = uh;
-        xs[Np + j] = h;
     }
     __syncthreads();
+    if (!active) return;
     double sa = 0.0;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
         if (q < k) sa += c.alpha[q];
-    const int lane = threadIdx.x & (kWave - 1), i = blockIdx.x * 4 + (threadIdx.x / kWave);
-    if (i >= a.N) return;
-    const double* g = G + (size_t)i * 2 * Np;
-    double s = 0.0;
-    for (int m = lane; m < 2 * Np; m += kWave) s += g[m] * xs[m];
-    s = wave_sum(s);
+    double acc[kFullChunk];
+#pragma unroll
+    for (int u = 0; u < kFullChunk; ++u) acc[u] = 0.0;
+    for (int base = 0; base < Np; base += kFullChunk * kWave) {
+        if (base > 0) {
+#pragma unroll
+            for (int u = 0; u < kFullChunk; ++u) {
+                const int m = base + lane + u * kWave;
+                gv[u] = m < Np ? g2[m] : make_double2(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFullChunk; ++u) {
+            const int m = base + lane + u * kWave;
+            if (m < Np) {
+                const double2 x = xs2[m];
+                acc[u] += gv[u].x * x.x + gv[u].y * x.y;
+            }
+        }
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < kFullChunk; ++u) t += acc[u];
+    const double s = wave_sum(t);
     if (lane == 0) a.zfull[off + i] = s + sa * fz[i] + az[i];
 }
 
 void launch_full_terms(const StepArgs& a, const double* G, const double* fz, const double* az, hipStream_t s) {
-    hipLaunchKernelGGL(k_full_terms, dim3((a.N + 3) / 4, a.B), dim3(256), sizeof(double) * 2 * a.Np, s, a, G, fz,
-                       az);
+    hipLaunchKernelGGL(k_full_terms, dim3((a.N + kFullRows - 1) / kFullRows, a.B), dim3(256),
+                       sizeof(double) * 2 * a.Np, s, a, G, fz, az);
 }
 
 // ============================================================== storage conversion

@@ -141,3 +141,28 @@ def test_full_in_grouped_launches(torch_gpu):
         x.close()
     rf.close()
     rc.close()
+
+
+@pytest.mark.slow
+def test_full_headline_size(torch_gpu):
+    """The benchmark's full-form workload (N = 1000, CP rank 2000 FP32, SPD stiffness, dense
+    SPD mass matrix, zeroth-mode terms; tile table applied as the benchmark does): 30 steps
+    and every energy against the oracle."""
+    from paper_2311_03694_amd import tune
+    _say("full form N=1000 CP rank 2000 fp32, 30 steps")
+    p = romsynth.make_config(3, R=2000, batch=1, dense=False)
+    N, steps = p.N, 30
+    C1, C2, c0, a0 = romsynth.zeroth_terms(N, seed=1, cfg=3, scale=0.1)
+    full = dict(M=romsynth.mass_spd(N, seed=2, cfg=3, norm=0.1), C1=C1, C2=C2, c0=c0, a0=a0)
+    rom = _rom(p, "cp", full, "fp32", 1)
+    tune.apply(rom, 1, dense=False, R=2000)
+    s = rom.state(p.u0[0])
+    s.step(steps)
+    uh, _, n = s.get()
+    _, Elog = s.energy()
+    ref = _ref(p, "cp", full, steps, p.u0[0])
+    assert ref["status"] == 0 and n == steps
+    assert rel(uh[0][0], ref["u_hist"][0]) < TRAJ_TOL["fp32"]
+    assert float(np.max(np.abs(Elog.reshape(-1) - ref["E"]) / ref["E"])) < TRAJ_TOL["fp32"]
+    s.close()
+    rom.close()
