@@ -166,3 +166,31 @@ def test_full_headline_size(torch_gpu):
     assert float(np.max(np.abs(Elog.reshape(-1) - ref["E"]) / ref["E"])) < TRAJ_TOL["fp32"]
     s.close()
     rom.close()
+
+
+@pytest.mark.parametrize("A", ["diag", "spd"])
+@pytest.mark.parametrize("form", ["dense", "cp"])
+def test_full_restart(torch_gpu, form, A):
+    """A checkpoint of a full-form state (rom_state_get: the u levels and the y levels,
+    which hold C(u)u alone) restored into a new state continues like the uninterrupted
+    run: each step recomputes the zeroth-mode and mass terms from the u levels.  Both
+    against the oracle's uninterrupted full-form run."""
+    N, n1, n2 = 40, 30, 40
+    _say(f"full form restart {form} A={A}")
+    p = romsynth.make_problem(N, pairs=20, eps=1e-6, A=A, cfg=85, dense=form == "dense", cp=form == "cp")
+    full = _terms(N, "dense", 85)
+    rom = _rom(p, form, full, "fp64", 1)
+    s1 = rom.state(p.u0[0])
+    s1.step(n1)
+    uh, yh, n = s1.get()
+    assert n == n1
+    s2 = rom.state(p.u0[0])
+    s2.set(uh, yh, n1)
+    s2.step(n2)
+    s1.step(n2)
+    ref = _ref(p, form, full, n1 + n2, p.u0[0])
+    assert ref["status"] == 0
+    assert rel(s2.get()[0][0][0], ref["u_hist"][0]) < TRAJ_TOL["fp64"]
+    assert rel(s2.get()[0][0][0], s1.get()[0][0][0]) < 1e-13
+    for x in (s1, s2, rom):
+        x.close()
