@@ -360,6 +360,28 @@ def main():
         log(f"full form: {1.0 / t_f:.0f} steps/s ({t_f * 1e6:.2f} us/step; plain {t_p * 1e6:.2f})")
         for x in (s_f, s_p, rom_f, rom_p):
             x.close()
+        # 64 trajectories: the terms as one FP64 product X G^T per step
+        Bf = 64
+        u0b = romsynth.initial_u(N, range(Bf), cfg=3)
+        rom_f = rg.Rom(N, p.nu, p.dt, p.A, **core, full=full_terms, dtype="fp32", max_batch=Bf, stream=stream)
+        rom_p = rg.Rom(N, p.nu, p.dt, p.A, **core, dtype="fp32", max_batch=Bf, stream=stream)
+        for r in (rom_f, rom_p):
+            tune.apply(r, Bf, dense=False, R=R, table=tiles)
+        s_f, s_p = rom_f.state(u0b), rom_p.state(u0b)
+        s_f.step(20)
+        s_p.step(20)
+        nb, tf, tp = 1000, [], []
+        for _ in range(3):
+            tf.append(timer(lambda: s_f.step_async(nb)))
+            s_f.sync()
+            tp.append(timer(lambda: s_p.step_async(nb)))
+            s_p.sync()
+        t_f, t_p = min(tf) / nb, min(tp) / nb
+        result["full"]["B64"] = {"traj_steps_per_s": Bf / t_f, "us_per_step": t_f * 1e6,
+                                 "plain_us_per_step": t_p * 1e6}
+        log(f"full form B={Bf}: {Bf / t_f:.0f} traj-steps/s ({t_f * 1e6:.2f} us/step; plain {t_p * 1e6:.2f})")
+        for x in (s_f, s_p, rom_f, rom_p):
+            x.close()
 
     if not args.no_extra and sec in ("all", "multi"):
         # ---------------- uneven N: grouped launches against the same states one by one

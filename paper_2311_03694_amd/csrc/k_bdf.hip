@@ -327,18 +327,16 @@ void full_setup(int N, int Np, double nu, const double* M, const double* C1, con
 
 // Zeroth-mode and mass terms of the right-hand side of level n (eq. nse_d1), per
 // trajectory b:
-//   zfull = L uhat + (M - I) h + (sum_q alpha_q) fz + az,
+//   zfull = L uhat + (M - I) h,
 //   uhat = sum_q alpha_q u^{n+1-q},  h = (1/dt) sum_q beta_q u^{n+1-q}
-// (the EXT sum of the linear and constant parts of the bracket, and M minus the identity
-// times the BDF history sum, which the rhs already carries).  Grid (ceil(N/4), B), 256
+// (the EXT sum of the linear part of the bracket, and M minus the identity times the BDF
+// history sum, which the rhs already carries; the constants are added with the rhs).  Grid (ceil(N/4), B), 256
 // threads, one wavefront per row of G (2 Np doubles, read as 16-byte pairs in chunks of
 // 16 per lane, a whole row up to N = 1024).  The first chunk of G and the history loads of
 // the staging (up to 1024 coefficients per pass) are all issued before any of them is
 // used, so the kernel waits for one round trip to memory instead of one per loop pass.
 constexpr int kFullRows = 4, kFullChunk = 16, kFullStage = 4;
-__global__ __launch_bounds__(256) void k_full_terms(StepArgs a, const double* __restrict__ G,
-                                                    const double* __restrict__ fz,
-                                                    const double* __restrict__ az) {
+__global__ __launch_bounds__(256) void k_full_terms(StepArgs a, const double* __restrict__ G) {
     extern __shared__ double2 xs2[];
     double* xs = reinterpret_cast<double*>(xs2);
     const int b = blockIdx.y, Np = a.Np;
@@ -385,10 +383,6 @@ __global__ __launch_bounds__(256) void k_full_terms(StepArgs a, const double* __
     }
     __syncthreads();
     if (!active) return;
-    double sa = 0.0;
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-        if (q < k) sa += c.alpha[q];
     double acc[kFullChunk];
 #pragma unroll
     for (int u = 0; u < kFullChunk; ++u) acc[u] = 0.0;
@@ -413,12 +407,39 @@ __global__ __launch_bounds__(256) void k_full_terms(StepArgs a, const double* __
 #pragma unroll
     for (int u = 0; u < kFullChunk; ++u) t += acc[u];
     const double s = wave_sum(t);
-    if (lane == 0) a.zfull[off + i] = s + sa * fz[i] + az[i];
+    if (lane == 0) a.zfull[off + i] = s;
 }
 
-void launch_full_terms(const StepArgs& a, const double* G, const double* fz, const double* az, hipStream_t s) {
+void launch_full_terms(const StepArgs& a, const double* G, hipStream_t s) {
     hipLaunchKernelGGL(k_full_terms, dim3((a.N + kFullRows - 1) / kFullRows, a.B), dim3(256),
-                       sizeof(double) * 2 * a.Np, s, a, G, fz, az);
+                       sizeof(double) * 2 * a.Np, s, a, G);
+}
+
+// X[b] = [uhat_b | h_b] of level n for b < B (row pitch 2 Np; entries j >= N and rows
+// b >= B are never written and stay zero): the operand of the batched zfull = X G^T,
+// which reads G once for the whole batch.
+__global__ __launch_bounds__(256) void k_full_x(StepArgs a, double* __restrict__ X) {
+    const int b = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.N) return;
+    const long long n = *a.step;
+    const int k = bdf_order(n);
+    const BdfCoef c = bdf_coef(k);
+    const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N;
+    double uh = 0.0, h = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        if (q < k) {
+            const double u = a.uring[(size_t)slot_of(n - q) * BN + off + j];
+            uh += c.alpha[q] * u;
+            h += (c.beta[q + 1] * a.inv_dt) * u;
+        }
+    double* xr = X + (size_t)b * 2 * a.Np;
+    xr[j] = uh;
+    xr[a.Np + j] = h;
+}
+
+void launch_full_x(const StepArgs& a, double* X, hipStream_t s) {
+    hipLaunchKernelGGL(k_full_x, dim3((a.N + 255) / 256, a.B), dim3(256), 0, s, a, X);
 }
 
 // ============================================================== storage conversion

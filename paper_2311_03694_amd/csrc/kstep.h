@@ -24,8 +24,10 @@ __device__ __forceinline__ BdfHist bdf_hist_point(const StepArgs& a, long long n
 }
 
 // Store y^n, form the right-hand side of eq. nse_d1 for point (b, i) from its history:
-//   rhs = - sum_{q<=k} alpha_q y^{n+1-q} - (1/dt) sum_{q<=k} beta_q u^{n+1-q} [- zfull],
-// zfull carrying the zeroth-mode terms and (M - I) times the history sum (full form).
+//   rhs = - sum_{q<=k} alpha_q y^{n+1-q} - (1/dt) sum_{q<=k} beta_q u^{n+1-q}
+//         [- zfull - (sum_q alpha_q) fz - nu a0],
+// zfull = L uhat + (M - I) h carrying the zeroth-mode linear terms under the EXT sum and
+// the mass matrix minus the identity times the history sum (full form).
 __device__ __forceinline__ double bdf_rhs_hist(const StepArgs& a, long long n, const BdfCoef& c, int k, int b,
                                                int i, double y, const BdfHist& h) {
     a.yring[(size_t)slot_of(n) * ((size_t)a.B * a.N) + (size_t)b * a.N + i] = y;
@@ -37,7 +39,13 @@ __device__ __forceinline__ double bdf_rhs_hist(const StepArgs& a, long long n, c
 #pragma unroll
     for (int q = 0; q < 3; ++q)
         if (q < k) v -= (c.beta[q + 1] * a.inv_dt) * h.u[q];
-    if (a.zfull) v -= a.zfull[(size_t)b * a.N + i];
+    if (a.zfull) {
+        double sa = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (q < k) sa += c.alpha[q];
+        v -= a.zfull[(size_t)b * a.N + i] + (sa * a.fz[i] + a.az[i]);
+    }
     return v;
 }
 

@@ -116,6 +116,7 @@ struct rom_state_s {
     // projections), so several states of one context can be stepped in one grouped launch
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    double* xfull = nullptr;            // full form, batches: [Bpad][2Np] operand of X G^T
     int sgen = 0;                       // bumped when scratch or the energy log moves
     long long* cnt = nullptr;           // the two slots of the device step counter
     // captured chunks of steps, one per parity of the first level (the kernels of a
@@ -811,7 +812,15 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
     const WsPlan p = plan_ws(c, s->B);
     const int accf = acc_f64(c->dtype);
     const int diag = c->diagA ? 1 : 0;
-    if (c->full) launch_full_terms(a, c->Gfull, c->fz, c->az, stream);
+    if (c->full) {
+        if (s->B == 1) {
+            launch_full_terms(a, c->Gfull, stream);
+        } else {
+            launch_full_x(a, s->xfull, stream);
+            launch_gemm_f64(gemm_plan(c->N, s->Bpad, 0), c->Gfull, 2LL * c->Np, s->xfull, 2LL * c->Np, a.zfull,
+                            c->N, 2 * c->Np, s->Bpad, stream);
+        }
+    }
     if (s->B == 1) {
         char* ws = (char*)s->scratch;
         if (c->dense) {
@@ -1114,7 +1123,21 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(dmalloc((void**)&a.closep, sizeof(int), &s->bytes, &s->allocs));
     if (!c->dense && !c->svd && batch == 1)
         TRY(dmalloc(&a.st, c->Rp * acc_bytes(c->dtype), &s->bytes, &s->allocs));
-    if (c->full) TRY(dmalloc((void**)&a.zfull, sizeof(double) * BN, &s->bytes, &s->allocs));
+    if (c->full) {
+        // zfull takes Bpad rows (the batched product writes its padding rows); X of the
+        // batched product starts zero and only its live entries are ever written
+        TRY(dmalloc((void**)&a.zfull, sizeof(double) * s->Bpad * N, &s->bytes, &s->allocs));
+        a.fz = c->fz;
+        a.az = c->az;
+        if (batch > 1) {
+            const size_t xb = sizeof(double) * s->Bpad * 2 * c->Np;
+            TRY(dmalloc((void**)&s->xfull, xb, &s->bytes, &s->allocs));
+            if (hipMemsetAsync(s->xfull, 0, xb, c->stream) != hipSuccess) {
+                rom_state_destroy(s);
+                return fail(ROM_E_DEVICE, "clearing the full-form operand failed");
+            }
+        }
+    }
     if (a.batched) {
         const size_t cells = (size_t)s->Bpad * c->Np;
         TRY(dmalloc(&a.ucv, cells * elem_bytes(c->dtype), &s->bytes, &s->allocs));

@@ -41,8 +41,10 @@ struct StepArgs {
     int enmax;               // capacity per trajectory (at least any update kernel's blocks)
     const double* hdiag;     // [3][N] 1/(beta0_k/dt + nu A_ii) (diagonal stiffness)
     const double* hinv;      // [3][N][Np] (beta0_k/dt M + nu A)^-1, row pitch Np (dense stiffness)
-    double* zfull;           // full form: [B][N] zeroth-mode and mass terms of the level's
-                             // right-hand side (k_full_terms); NULL otherwise
+    double* zfull;           // full form: [Bpad][N] G x of the level's right-hand side
+                             // (zeroth-mode linear terms and M - I); NULL otherwise
+    const double* fz;        // full form: [N] constant of the bracket, (C1 + C2)[:, 0] - c0
+    const double* az;        // full form: [N] nu a0
     // coefficient copies in the contraction's number format for the batched kernels,
     // laid out [Bpad][Np] (padding rows and columns stay zero); written by the update
     // of each step
@@ -205,7 +207,10 @@ void helm_setup_diag(int N, double nu, double dt, const double* A_dev, const dou
 // M: the identity).  Per step: zfull of the level from the step counter.
 void full_setup(int N, int Np, double nu, const double* M, const double* C1, const double* C2,
                 const double* c0, const double* a0, double* G, double* fz, double* az, hipStream_t s);
-void launch_full_terms(const StepArgs& a, const double* G, const double* fz, const double* az, hipStream_t s);
+void launch_full_terms(const StepArgs& a, const double* G, hipStream_t s);
+// Batches: X [Bpad][2 Np] = [uhat | h] per trajectory (padding stays zero), the operand
+// of zfull = X G^T (launch_gemm_f64).
+void launch_full_x(const StepArgs& a, double* X, hipStream_t s);
 
 // Batched contraction launchers (k_mfma.hip).  Partials are [nsplit][Bpad][M] in the
 // accumulation type (FP64 for DT_F64, FP32 otherwise).
