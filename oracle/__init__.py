@@ -21,3 +21,4 @@ from .oracle import (  # noqa: F401
     round_bf16,
     split_bf16x3,
 )
+from . import als  # noqa: F401,E402

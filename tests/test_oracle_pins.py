@@ -450,3 +450,58 @@ def test_full_fixed_point(orc):
     r2 = orc.run(N, nu, dt, A, steps, u0=us, C=np.zeros((N, N, N)), M=M, C1=C1, C2=C2, c0=c0,
                  a0=-a0, traj=True)
     assert np.max(np.abs(r2["traj"][-1] - us)) > 1e-6 * np.max(np.abs(us))
+
+
+# ---------------------------------------------------------------- CP-ALS (Sec. 2.3)
+
+def _als_problem(N, R, seed):
+    rng = np.random.default_rng(seed)
+    T = [rng.standard_normal((N, R)) for _ in range(3)]
+    X = np.einsum("ir,jr,kr->ijk", *T) + 1e-3 * rng.standard_normal((N, N, N))
+    F0 = [rng.standard_normal((N, R)) for _ in range(3)]
+    return X, T, F0
+
+
+def test_als_update_is_least_squares(orc):
+    """Each update of eq. cp_als is the least-squares solution of its subproblem: numpy's
+    lstsq on the unfolded problem (X_(n) against the Khatri-Rao product of the two fixed
+    factors) gives the same factor.  A transposed operand or a wrong unfolding fails."""
+    N, R = 7, 3
+    X, _, F = _als_problem(N, R, 3)
+    A1, A2, A3 = F
+    KR = np.einsum("jr,kr->jkr", A2, A3).reshape(N * N, R)          # rows (j, k)
+    want1 = np.linalg.lstsq(KR, X.reshape(N, N * N).T, rcond=None)[0].T
+    (B1, B2, B3), _ = orc.als.cp_als(X, A1, A2, A3, 1)
+    assert np.max(np.abs(B1 - want1)) <= 1e-9 * np.max(np.abs(want1))
+    KR2 = np.einsum("ir,kr->ikr", B1, A3).reshape(N * N, R)          # rows (i, k)
+    X2 = X.transpose(1, 0, 2).reshape(N, N * N)
+    want2 = np.linalg.lstsq(KR2, X2.T, rcond=None)[0].T
+    assert np.max(np.abs(B2 - want2)) <= 1e-9 * np.max(np.abs(want2))
+    KR3 = np.einsum("ir,jr->ijr", B1, B2).reshape(N * N, R)          # rows (i, j)
+    X3 = X.transpose(2, 0, 1).reshape(N, N * N)
+    want3 = np.linalg.lstsq(KR3, X3.T, rcond=None)[0].T
+    assert np.max(np.abs(B3 - want3)) <= 1e-9 * np.max(np.abs(want3))
+
+
+def test_als_exact_factors_fixed_point(orc):
+    """A tensor of exact CP rank R: its own factors minimise every subproblem, so a sweep
+    returns them (up to rounding) with residual ~0."""
+    N, R = 8, 3
+    rng = np.random.default_rng(4)
+    T = [rng.standard_normal((N, R)) for _ in range(3)]
+    X = np.einsum("ir,jr,kr->ijk", *T)
+    F, res = orc.als.cp_als(X, *T, 2)
+    for a, b in zip(F, T):
+        assert np.max(np.abs(a - b)) <= 1e-10 * np.max(np.abs(b))
+    assert res[-1] < 1e-12
+
+
+def test_als_residual_never_grows(orc):
+    """Every subproblem is minimised exactly, so the fit residual of eq. cp_nls does not
+    increase from sweep to sweep; from a random start it falls well below its start."""
+    N, R = 9, 4
+    X, _, F0 = _als_problem(N, R, 5)
+    r0 = orc.als.residual(X, F0)
+    _, res = orc.als.cp_als(X, *F0, 40)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(res, res[1:]))
+    assert res[-1] < 0.5 * min(r0, 1.0)
