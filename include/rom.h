@@ -134,6 +134,23 @@ typedef struct rom_full_terms {
 rom_status rom_create_full(const rom_desc *d, const rom_full_terms *f, rom_ctx *out);
 void rom_destroy(rom_ctx ctx);
 
+/* CP-ALS (Sec. 2.3, eqs. cp_nls and cp_als): `sweeps` sweeps of alternating least squares
+ * fitting [[A1, A2, A3]] (CP weights one) to a dense tensor.  Each sweep solves the three
+ * subproblems in turn, each through its normal equations, e.g. for the first factor
+ *   A1 <- M1 V1^{-1},  M1[i][r] = sum_jk C[i][j][k] A2[j][r] A3[k][r],
+ *   V1 = (A2^T A2) .* (A3^T A3),
+ * V inverted by Cholesky factorisation in FP64 on the device.
+ *   C        device FP64 [N][N][N], C[i][j][k] (position 1 = i, as rom_desc.C); read only.
+ *   A1..A3   device FP64 [N][R] factors for positions 1, 2, 3: the initial guess on entry
+ *            (the caller chooses it), the fitted factors on return.
+ *   stream   hipStream_t or NULL (the null stream).  Synchronizes; allocates and frees
+ *            its own workspace (about 4 R^2 + 2 N R doubles).
+ * Errors: ROM_E_INVALID (N or R outside [1, 4096], sweeps < 0, NULL pointers, or a
+ * normal matrix that is not positive definite: rank-deficient factors; the factors then
+ * hold non-finite values), ROM_E_NOMEM, ROM_E_DEVICE.  sweeps = 0 does nothing. */
+rom_status rom_cp_als(int32_t N, int32_t R, const double *C, double *A1, double *A2, double *A3,
+                      int32_t sweeps, void *stream);
+
 /* y = C(u)u for `batch` coefficient vectors (Sec. 2.2, eq. Cu; CP form: eq. tc_ap).
  * u_dev, y_dev: device FP64 [batch][N], caller-owned; 1 <= batch <= max_batch.
  * The contraction runs in the context's dtype; y is returned in FP64.  Asynchronous. */

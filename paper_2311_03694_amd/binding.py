@@ -25,7 +25,7 @@ EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_timed", 
            "rom_state_destroy",
            "rom_step", "rom_step_async", "rom_step_sync", "rom_energy", "rom_state_get",
            "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
-           "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_create_full",
+           "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_create_full", "rom_cp_als",
            "rom_last_error"]
 
 _d = ctypes.POINTER(ctypes.c_double)
@@ -101,6 +101,8 @@ def lib():
     L.rom_create_svd.restype = ctypes.c_int
     L.rom_create_full.argtypes = [ctypes.POINTER(rom_desc), ctypes.POINTER(rom_full_terms), ctypes.POINTER(_vp)]
     L.rom_create_full.restype = ctypes.c_int
+    L.rom_cp_als.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp]
+    L.rom_cp_als.restype = ctypes.c_int
     L.rom_cp_skew_layout.restype = ctypes.c_int32
     L.rom_last_error.argtypes = []
     L.rom_last_error.restype = ctypes.c_char_p
@@ -184,6 +186,12 @@ def rom_create(N, nu, dt, A, *, C=None, lam=None, Af=None, Bf=None, Cf=None, svd
     else:
         _check(L.rom_create(ctypes.byref(d), ctypes.byref(out)))
     return out.value
+
+
+def rom_cp_als(N, R, C_dev, A1_dev, A2_dev, A3_dev, sweeps, stream=None):
+    """CP-ALS sweeps on device FP64 tensors (C [N][N][N], factors [N][R], updated in place)."""
+    _check(lib().rom_cp_als(int(N), int(R), _dev_ptr(C_dev), _dev_ptr(A1_dev), _dev_ptr(A2_dev),
+                            _dev_ptr(A3_dev), int(sweeps), _stream_handle(stream)))
 
 
 def rom_destroy(ctx: int):

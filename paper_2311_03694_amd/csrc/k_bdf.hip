@@ -8,6 +8,7 @@
 //   * storage conversions of the operators (round to nearest even).
 #include <climits>
 
+#include "als.h"
 #include "kstep.h"
 
 namespace rom {
@@ -286,6 +287,14 @@ int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, c
                            hinv_dev + (size_t)k * N * Np);
     }
     return 0;
+}
+
+void spd_inverse(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s) {
+    hipMemsetAsync(L, 0, (size_t)n * n * sizeof(double), s);
+    for (int j = 0; j < n; ++j)
+        hipLaunchKernelGGL(k_chol_col, dim3((n - j + 3) / 4), dim3(256), 0, s, n, j, H, L, info);
+    hipLaunchKernelGGL(k_trinv_col, dim3(n), dim3(64), sizeof(double) * n, s, n, L, X);
+    hipLaunchKernelGGL(k_gram, dim3((n + 255) / 256, n), dim3(256), 0, s, n, np, X, Hinv);
 }
 
 void helm_setup_diag(int N, double nu, double dt, const double* A_dev, const double* M_dev, double* hdiag_dev,

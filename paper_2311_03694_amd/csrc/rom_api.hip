@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "rom.h"
+#include "als.h"
 #include "rom_dev.h"
 
 using namespace rom;
@@ -735,6 +736,62 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, const rom_ful
 }
 
 extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) { return create_ctx(d, nullptr, nullptr, out); }
+extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* A1, double* A2, double* A3,
+                                  int32_t sweeps, void* stream) {
+    if (N < 1 || N > 4096) return fail(ROM_E_INVALID, "N must be in [1, 4096] (got %d)", N);
+    if (R < 1 || R > 4096) return fail(ROM_E_INVALID, "R must be in [1, 4096] (got %d)", R);
+    if (sweeps < 0) return fail(ROM_E_INVALID, "sweeps must be >= 0");
+    if (!C || !A1 || !A2 || !A3) return fail(ROM_E_INVALID, "a tensor or factor pointer is NULL");
+    if (sweeps == 0) return ROM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)N, r = (size_t)R, rp = (r + 7) / 8 * 8, npad = (n + 15) / 16 * 16;
+    // V, its Cholesky factor and inverse factor [R][R]; Vinv [R][Rp] and the right-hand
+    // side Mb [Npad][Rp] with zero padding (the product's K = Rp); the product Yb [Npad][R]
+    const size_t sizes[6] = {r * r, r * r, r * r, r * rp, npad * rp, npad * r};
+    double* buf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int* info = nullptr;
+    struct Guard {
+        double** b;
+        int** info;
+        ~Guard() {
+            for (int q = 0; q < 6; ++q)
+                if (b[q]) hipFree(b[q]);
+            if (*info) hipFree(*info);
+        }
+    } guard{buf, &info};
+    for (int q = 0; q < 6; ++q) {
+        const hipError_t e = hipMalloc((void**)&buf[q], sizeof(double) * sizes[q]);
+        if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? ROM_E_NOMEM : ROM_E_DEVICE, "CP-ALS workspace: %s",
+                                         hipGetErrorString(e));
+    }
+    if (hipMalloc((void**)&info, sizeof(int)) != hipSuccess) return fail(ROM_E_NOMEM, "CP-ALS workspace");
+    double *V = buf[0], *L = buf[1], *X = buf[2], *Vinv = buf[3], *Mb = buf[4], *Yb = buf[5];
+    if (hipMemsetAsync(Vinv, 0, sizeof(double) * sizes[3], s) != hipSuccess ||
+        hipMemsetAsync(Mb, 0, sizeof(double) * sizes[4], s) != hipSuccess ||
+        hipMemsetAsync(info, 0, sizeof(int), s) != hipSuccess)
+        return fail(ROM_E_DEVICE, "CP-ALS workspace clear failed");
+    double* F[3] = {A1, A2, A3};
+    const GemmPlan pl = gemm_plan(R, (int)npad, 0);
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int mode = 0; mode < 3; ++mode) {
+            const int a = mode == 0 ? 1 : 0, b = mode == 2 ? 1 : 2;
+            launch_gram_hadamard(N, R, F[a], F[b], V, s);
+            launch_mttkrp(mode, N, R, C, F[0], F[1], F[2], Mb, (int)rp, s);
+            spd_inverse(R, (int)rp, V, L, X, Vinv, info, s);
+            // F[mode][i][m] = sum_k Vinv[m][k] Mb[i][k]  (V symmetric)
+            launch_gemm_f64(pl, Vinv, (long long)rp, Mb, (long long)rp, Yb, R, (int)rp, (int)npad, s);
+            if (hipMemcpyAsync(F[mode], Yb, sizeof(double) * n * r, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(ROM_E_DEVICE, "CP-ALS factor copy failed");
+        }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int hinfo = 0;
+    if (e == hipSuccess) e = hipMemcpy(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(ROM_E_DEVICE, "CP-ALS failed: %s", hipGetErrorString(e));
+    if (hinfo) return fail(ROM_E_INVALID, "CP-ALS normal equations not positive definite (rank-deficient factors)");
+    return ROM_OK;
+}
+
 extern "C" rom_status rom_create_full(const rom_desc* d, const rom_full_terms* f, rom_ctx* out) {
     if (!f) {
         if (out) *out = nullptr;

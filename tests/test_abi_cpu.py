@@ -140,3 +140,22 @@ def test_create_full_rejects_invalid(case, status, msg):
     assert st == getattr(rg.binding, status)
     assert msg in rg.rom_last_error()
     assert out.value is None
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((0, 3, 1), "N must be"),
+    ((5, 0, 1), "R must be"),
+    ((5, 3, -1), "sweeps must be"),
+])
+def test_cp_als_rejects_invalid(args, msg):
+    """rom_cp_als checks its sizes before any device work."""
+    N, R, sweeps = args
+    st = rg.lib().rom_cp_als(N, R, 1, 1, 1, 1, sweeps, None)
+    assert st == rg.binding.ROM_E_INVALID
+    assert msg in rg.rom_last_error()
+
+
+def test_cp_als_rejects_null():
+    st = rg.lib().rom_cp_als(5, 3, None, 1, 1, 1, 1, None)
+    assert st == rg.binding.ROM_E_INVALID
+    assert "NULL" in rg.rom_last_error()

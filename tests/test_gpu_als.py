@@ -1,0 +1,80 @@
+"""CP-ALS on the GPU (Sec. 2.3, eq. cp_als) against the oracle's sweeps from the same
+initial factors: ragged sizes (N and R not multiples of the kernels' tiles), one and
+several sweeps, the fitted residual, and the rank-deficient error."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2311_03694_amd as rg
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _problem(N, R, seed, noise=1e-3):
+    rng = np.random.default_rng(seed)
+    T = [rng.standard_normal((N, R)) for _ in range(3)]
+    X = np.einsum("ir,jr,kr->ijk", *T) + noise * rng.standard_normal((N, N, N))
+    F0 = [rng.standard_normal((N, R)) for _ in range(3)]
+    return X, F0
+
+
+def _gpu_als(torch, X, F0, sweeps):
+    N, R = F0[0].shape
+    Xd = torch.tensor(X, dtype=torch.float64, device="cuda").contiguous()
+    Fd = [torch.tensor(A, dtype=torch.float64, device="cuda").contiguous() for A in F0]
+    torch.cuda.synchronize()
+    rg.rom_cp_als(N, R, Xd, *Fd, sweeps)
+    torch.cuda.synchronize()
+    return [A.cpu().numpy() for A in Fd]
+
+
+@pytest.mark.parametrize("N,R,sweeps", [(7, 3, 1), (23, 5, 1), (23, 5, 6), (40, 19, 3), (33, 260, 1)])
+def test_als_matches_oracle(torch_gpu, N, R, sweeps):
+    _say(f"cp-als N={N} R={R} sweeps={sweeps}")
+    X, F0 = _problem(N, R, 10 + N + R)
+    G = _gpu_als(torch_gpu, X, F0, sweeps)
+    F, res = orc.als.cp_als(X, *F0, sweeps)
+    for a, b in zip(G, F):
+        assert np.max(np.abs(a - b)) <= 1e-8 * np.max(np.abs(b)), float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    assert abs(orc.als.residual(X, G) - res[-1]) <= 1e-8 * max(res[-1], 1e-12)
+
+
+def test_als_fits_low_rank(torch_gpu):
+    """From a random start, 60 GPU sweeps bring a noisy rank-4 tensor to the noise level."""
+    _say("cp-als fit N=16 R=4 sweeps=60")
+    X, F0 = _problem(16, 4, 77, noise=1e-6)
+    G = _gpu_als(torch_gpu, X, F0, 60)
+    assert orc.als.residual(X, G) < 1e-4
+
+
+def test_als_rank_deficient_reported(torch_gpu):
+    """A zero column in the two factors held fixed makes the normal matrix's first pivot
+    exactly zero: the call reports it instead of returning silently."""
+    _say("cp-als rank-deficient factors")
+    X, F0 = _problem(10, 3, 5)
+    F0[1][:, 0] = 0.0
+    F0[2][:, 0] = 0.0
+    with pytest.raises(rg.RomError):
+        _gpu_als(torch_gpu, X, F0, 1)
+
+
+def test_als_zero_sweeps_noop(torch_gpu):
+    X, F0 = _problem(9, 2, 6)
+    G = _gpu_als(torch_gpu, X, F0, 0)
+    for a, b in zip(G, F0):
+        assert np.array_equal(a, b)
