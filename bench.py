@@ -28,6 +28,7 @@ Also in the one JSON line:
                 N/R = 10 and 4), FP32, one trajectory: steps/s and the streaming bandwidth
   full          the full form of the reduced system (dense SPD mass matrix, zeroth-mode
                 terms) at the headline size, CP rank 2000 FP32, against the plain step
+  als           CP-ALS sweeps (rom_cp_als) at N = 200, R = 400, FP64: ms per sweep
   multi         uneven N: one CP trajectory each at N = 100, 200, 400, 700, 1000 stepped
                 together by grouped launches (rom_step_multi) and one after the other
   serving       a bounded Poisson request stream through the continuous-batching loop
@@ -67,7 +68,7 @@ def parse():
                     help="target length of the oracle sample (CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no batched/config2/serving)")
-    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "svd", "full", "multi", "serving"],
+    ap.add_argument("--section", default="all", choices=["all", "headline", "batched", "config2", "svd", "full", "als", "multi", "serving"],
                     help="run one section only (profiling); the JSON line then holds that section")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--calib-copy", action="store_true",
@@ -382,6 +383,22 @@ def main():
         log(f"full form B={Bf}: {Bf / t_f:.0f} traj-steps/s ({t_f * 1e6:.2f} us/step; plain {t_p * 1e6:.2f})")
         for x in (s_f, s_p, rom_f, rom_p):
             x.close()
+
+    if not args.no_extra and sec in ("all", "als"):
+        # ---------------- CP-ALS (offline fit of the CP factors): N = 200, R = 400, FP64,
+        # seeded random tensor and initial factors (the timing does not depend on values)
+        Na, Ra = 200, 400
+        rng = np.random.default_rng(2)
+        Xd = torch.tensor(rng.standard_normal((Na, Na, Na)), dtype=torch.float64, device=dev)
+        Fd = [torch.tensor(rng.standard_normal((Na, Ra)), dtype=torch.float64, device=dev) for _ in range(3)]
+        rg.rom_cp_als(Na, Ra, Xd, *Fd, 1, stream=stream)
+        nsw = 3
+        t_als = timer(lambda: rg.rom_cp_als(Na, Ra, Xd, *Fd, nsw, stream=stream)) / nsw
+        fl = 3 * 2.0 * Na ** 3 * Ra
+        result["als"] = {"N": Na, "R": Ra, "ms_per_sweep": t_als * 1e3,
+                         "mttkrp_flops_per_sweep": fl, "sweep_tflops": fl / t_als / 1e12}
+        log(f"cp-als N={Na} R={Ra}: {t_als * 1e3:.2f} ms per sweep")
+        del Xd, Fd
 
     if not args.no_extra and sec in ("all", "multi"):
         # ---------------- uneven N: grouped launches against the same states one by one
