@@ -4,12 +4,14 @@
 
 namespace rom {
 
-// M[p][r] (row pitch ldm) = sum_{q,t} X(p, q, t) Fq[q][r] Ft[t][r], the right-hand side of
-// subproblem `mode` (0, 1, 2) of eq. cp_als, for the dense tensor C [N][N][N] (C[i][j][k])
-// and factors F0, F1, F2 [N][R]: mode 0 contracts j and k with F1, F2; mode 1 contracts
-// i and k with F0, F2; mode 2 contracts i and j with F0, F1.
-void launch_mttkrp(int mode, int N, int R, const double* C, const double* F0, const double* F1, const double* F2,
-                   double* M, int ldm, hipStream_t s);
+// Unfolding of C [N][N][N] into U [N^2][np] (zero padding past column N): layout 0 rows
+// (i, j) and columns k, layout 1 rows (i, k) and columns j.
+void launch_als_unfold(int N, int np, int layout, const double* C, double* U, hipStream_t s);
+// Ft [R][np] = F^T for F [N][R], zero padding.
+void launch_als_transpose(int N, int R, int np, const double* F, double* Ft, hipStream_t s);
+// M[p][r] (pitch ldm) = sum_q T[row][r] F[q][r] with row = p N + q (keep_first) or q N + p.
+void launch_als_reduce(int N, int R, int keep_first, const double* T, const double* F, double* M, int ldm,
+                       hipStream_t s);
 // V[r][s] = (Fa^T Fa)[r][s] * (Fb^T Fb)[r][s], [R][R], factors [N][R].
 void launch_gram_hadamard(int N, int R, const double* Fa, const double* Fb, double* V, hipStream_t s);
 // Hinv [n][np] = H^{-1} for SPD H [n][n] by Cholesky (L), the inverse factor (X) and its

@@ -289,8 +289,9 @@ int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, c
     return 0;
 }
 
+// Only the lower triangle of L is written and read (k_chol_col, k_trinv_col), so L needs
+// no clearing and the sequence can be captured into a graph.
 void spd_inverse(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s) {
-    hipMemsetAsync(L, 0, (size_t)n * n * sizeof(double), s);
     for (int j = 0; j < n; ++j)
         hipLaunchKernelGGL(k_chol_col, dim3((n - j + 3) / 4), dim3(256), 0, s, n, j, H, L, info);
     hipLaunchKernelGGL(k_trinv_col, dim3(n), dim3(64), sizeof(double) * n, s, n, L, X);

@@ -745,46 +745,98 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
     if (sweeps == 0) return ROM_OK;
     hipStream_t s = (hipStream_t)stream;
     const size_t n = (size_t)N, r = (size_t)R, rp = (r + 7) / 8 * 8, npad = (n + 15) / 16 * 16;
+    const size_t np = (n + 7) / 8 * 8, n2pad = (n * n + 15) / 16 * 16;
     // V, its Cholesky factor and inverse factor [R][R]; Vinv [R][Rp] and the right-hand
-    // side Mb [Npad][Rp] with zero padding (the product's K = Rp); the product Yb [Npad][R]
-    const size_t sizes[6] = {r * r, r * r, r * r, r * rp, npad * rp, npad * r};
-    double* buf[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // side Mb [Npad][Rp] with zero padding (the product's K = Rp); the product Yb [Npad][R];
+    // the two unfoldings of C [N^2 padded][Np], a transposed factor [R][Np] and the
+    // tensor-factor product T [N^2 padded][R]
+    constexpr int kBufs = 10;
+    const size_t sizes[kBufs] = {r * r, r * r, r * r, r * rp, npad * rp, npad * r, n2pad * np, n2pad * np, r * np,
+                                 n2pad * r};
+    double* buf[kBufs] = {};
     int* info = nullptr;
     struct Guard {
         double** b;
         int** info;
         ~Guard() {
-            for (int q = 0; q < 6; ++q)
+            for (int q = 0; q < kBufs; ++q)
                 if (b[q]) hipFree(b[q]);
             if (*info) hipFree(*info);
         }
     } guard{buf, &info};
-    for (int q = 0; q < 6; ++q) {
+    for (int q = 0; q < kBufs; ++q) {
         const hipError_t e = hipMalloc((void**)&buf[q], sizeof(double) * sizes[q]);
         if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? ROM_E_NOMEM : ROM_E_DEVICE, "CP-ALS workspace: %s",
                                          hipGetErrorString(e));
     }
     if (hipMalloc((void**)&info, sizeof(int)) != hipSuccess) return fail(ROM_E_NOMEM, "CP-ALS workspace");
     double *V = buf[0], *L = buf[1], *X = buf[2], *Vinv = buf[3], *Mb = buf[4], *Yb = buf[5];
+    double *U0 = buf[6], *U1 = buf[7], *Ft = buf[8], *T = buf[9];
     if (hipMemsetAsync(Vinv, 0, sizeof(double) * sizes[3], s) != hipSuccess ||
         hipMemsetAsync(Mb, 0, sizeof(double) * sizes[4], s) != hipSuccess ||
+        hipMemsetAsync(U0, 0, sizeof(double) * sizes[6], s) != hipSuccess ||
+        hipMemsetAsync(U1, 0, sizeof(double) * sizes[7], s) != hipSuccess ||
         hipMemsetAsync(info, 0, sizeof(int), s) != hipSuccess)
         return fail(ROM_E_DEVICE, "CP-ALS workspace clear failed");
+    launch_als_unfold(N, (int)np, 0, C, U0, s);     // rows (i, j), columns k
+    launch_als_unfold(N, (int)np, 1, C, U1, s);     // rows (i, k), columns j
+    // one sweep (about 3 R + 30 launches) is captured once into a graph on a stream of
+    // this call, ordered after the caller's stream, and replayed `sweeps` times
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphGuard {
+        hipStream_t* cs;
+        hipEvent_t* ev;
+        hipGraph_t* g;
+        hipGraphExec_t* ge;
+        ~GraphGuard() {
+            if (*ge) hipGraphExecDestroy(*ge);
+            if (*g) hipGraphDestroy(*g);
+            if (*cs) {
+                hipStreamSynchronize(*cs);
+                hipStreamDestroy(*cs);
+            }
+            if (*ev) hipEventDestroy(*ev);
+        }
+    } gguard{&cs, &ev, &graph, &gexec};
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess ||
+        hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
+        return fail(ROM_E_DEVICE, "CP-ALS stream setup failed");
     double* F[3] = {A1, A2, A3};
-    const GemmPlan pl = gemm_plan(R, (int)npad, 0);
-    for (int sw = 0; sw < sweeps; ++sw)
-        for (int mode = 0; mode < 3; ++mode) {
+    const GemmPlan pl = gemm_plan(R, (int)npad, 0), plt = gemm_plan(R, (int)n2pad, 0);
+    // T[row][m] = sum_c Ft[m][c] U[row][c]: the unfolding times one factor
+    auto tensor_times = [&](const double* Uf, const double* Fk) {
+        launch_als_transpose(N, R, (int)np, Fk, Ft, s);
+        launch_gemm_f64(plt, Ft, (long long)np, Uf, (long long)np, T, R, (int)np, (int)n2pad, s);
+    };
+    s = cs;   // every launch below (tensor_times included) goes to the capture stream
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(ROM_E_DEVICE, "CP-ALS graph capture failed to start");
+    bool copy_ok = true;
+    for (int mode = 0; mode < 3; ++mode) {
             const int a = mode == 0 ? 1 : 0, b = mode == 2 ? 1 : 2;
             launch_gram_hadamard(N, R, F[a], F[b], V, s);
-            launch_mttkrp(mode, N, R, C, F[0], F[1], F[2], Mb, (int)rp, s);
+            // right-hand side: modes 1 and 2 share T = C x_k A3 (A3 is fixed until mode 3);
+            // mode 3 uses C x_j A2 over rows (i, k)
+            if (mode == 0) tensor_times(U0, F[2]);
+            if (mode == 2) tensor_times(U1, F[1]);
+            if (mode == 0) launch_als_reduce(N, R, 1, T, F[1], Mb, (int)rp, s);       // sum_j T[(i,j)] A2[j]
+            else launch_als_reduce(N, R, 0, T, F[0], Mb, (int)rp, s);                 // sum_i T[(i,.)] A1[i]
             spd_inverse(R, (int)rp, V, L, X, Vinv, info, s);
             // F[mode][i][m] = sum_k Vinv[m][k] Mb[i][k]  (V symmetric)
             launch_gemm_f64(pl, Vinv, (long long)rp, Mb, (long long)rp, Yb, R, (int)rp, (int)npad, s);
             if (hipMemcpyAsync(F[mode], Yb, sizeof(double) * n * r, hipMemcpyDeviceToDevice, s) != hipSuccess)
-                return fail(ROM_E_DEVICE, "CP-ALS factor copy failed");
-        }
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+                copy_ok = false;
+    }
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess && !copy_ok) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    for (int sw = 0; sw < sweeps && e == hipSuccess; ++sw) e = hipGraphLaunch(gexec, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
     int hinfo = 0;
     if (e == hipSuccess) e = hipMemcpy(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(ROM_E_DEVICE, "CP-ALS failed: %s", hipGetErrorString(e));
