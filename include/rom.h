@@ -143,8 +143,10 @@ void rom_destroy(rom_ctx ctx);
  *   C        device FP64 [N][N][N], C[i][j][k] (position 1 = i, as rom_desc.C); read only.
  *   A1..A3   device FP64 [N][R] factors for positions 1, 2, 3: the initial guess on entry
  *            (the caller chooses it), the fitted factors on return.
- *   stream   hipStream_t or NULL (the null stream).  Synchronizes; allocates and frees
- *            its own workspace (about 4 R^2 + 2 N R doubles).
+ *   stream   hipStream_t or NULL (the null stream); the sweeps themselves run on a stream
+ *            of the call's own, ordered after it.  Synchronizes; allocates and frees its own
+ *            workspace: two padded unfoldings of C and their product with a factor, about
+ *            2 N^3 + N^2 R + 4 R^2 doubles (ROM_E_NOMEM when that does not fit).
  * Errors: ROM_E_INVALID (N or R outside [1, 4096], sweeps < 0, NULL pointers, or a
  * normal matrix that is not positive definite: rank-deficient factors; the factors then
  * hold non-finite values), ROM_E_NOMEM, ROM_E_DEVICE.  sweeps = 0 does nothing. */
