@@ -51,11 +51,11 @@ def _rom(p, form, full, dt, B):
 
 @pytest.mark.parametrize("mass", ["identity", "diag", "dense"])
 @pytest.mark.parametrize("A", ["diag", "spd"])
-@pytest.mark.parametrize("dt", ["fp64", "fp32"])
+@pytest.mark.parametrize("dt", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("form", ["dense", "cp"])
 def test_full_trajectory(torch_gpu, form, dt, A, mass):
     """One trajectory, 150 steps (N = 44: a ragged tail), coefficients and every energy
-    against the oracle."""
+    against the oracle (the terms themselves are FP64 in every format)."""
     N, steps = 44, 150
     _say(f"full form {form} {dt} A={A} M={mass}")
     p = romsynth.make_problem(N, pairs=22, eps=1e-6, A=A, cfg=81, dense=form == "dense", cp=form == "cp")
