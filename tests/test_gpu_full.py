@@ -77,16 +77,18 @@ def test_full_trajectory(torch_gpu, form, dt, A, mass):
     rom.close()
 
 
+@pytest.mark.parametrize("A,mass", [("spd", "dense"), ("diag", "diag")])
 @pytest.mark.parametrize("dt", ["fp64", "fp32"])
 @pytest.mark.parametrize("form", ["dense", "cp"])
-def test_full_batched(torch_gpu, form, dt):
-    """Five trajectories through the batched kernels with a dense mass matrix and an SPD
-    stiffness; each against its own oracle run."""
+def test_full_batched(torch_gpu, form, dt, A, mass):
+    """Five trajectories through the batched kernels, with a dense mass matrix and an SPD
+    stiffness (Helmholtz product) or both diagonal (the update in the contraction's
+    epilogue); each against its own oracle run."""
     N, B, steps = 40, 5, 120
-    _say(f"full form batched {form} {dt} B={B}")
-    p = romsynth.make_problem(N, pairs=20, eps=1e-6, A="spd", batch=B, cfg=82, dense=form == "dense",
+    _say(f"full form batched {form} {dt} B={B} A={A} M={mass}")
+    p = romsynth.make_problem(N, pairs=20, eps=1e-6, A=A, batch=B, cfg=82, dense=form == "dense",
                               cp=form == "cp")
-    full = _terms(N, "dense", 82)
+    full = _terms(N, mass, 82)
     rom = _rom(p, form, full, dt, B)
     s = rom.state(p.u0)
     s.step(steps)
