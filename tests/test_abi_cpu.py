@@ -159,3 +159,19 @@ def test_cp_als_rejects_null():
     st = rg.lib().rom_cp_als(5, 3, None, 1, 1, 1, 1, None)
     assert st == rg.binding.ROM_E_INVALID
     assert "NULL" in rg.rom_last_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without librom.so every call raises: there is no CPU fallback."""
+    monkeypatch.setattr(rg.binding, "_lib", None)
+    monkeypatch.setattr(rg.binding, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "librom.so"))
+    with pytest.raises(RuntimeError, match="librom.so not found"):
+        rg.binding.lib()
+    with pytest.raises(RuntimeError, match="librom.so not found"):
+        rg.rom_last_error()
+
+
+def test_full_terms_layout_matches_header():
+    # rom_full_terms: five pointers M, C1, C2, c0, a0 (LP64)
+    assert ctypes.sizeof(rg.binding.rom_full_terms) == 5 * 8
+    assert rg.binding.rom_full_terms.a0.offset == 32
