@@ -340,13 +340,14 @@ void full_setup(int N, int Np, double nu, const double* M, const double* C1, con
 //   zfull = L uhat + (M - I) h,
 //   uhat = sum_q alpha_q u^{n+1-q},  h = (1/dt) sum_q beta_q u^{n+1-q}
 // (the EXT sum of the linear part of the bracket, and M minus the identity times the BDF
-// history sum, which the rhs already carries; the constants are added with the rhs).  Grid (ceil(N/4), B), 256
-// threads, one wavefront per row of G (2 Np doubles, read as 16-byte pairs in chunks of
-// 16 per lane, a whole row up to N = 1024).  The first chunk of G and the history loads of
-// the staging (up to 1024 coefficients per pass) are all issued before any of them is
-// used, so the kernel waits for one round trip to memory instead of one per loop pass.
-constexpr int kFullRows = 4, kFullChunk = 16, kFullStage = 4;
-__global__ __launch_bounds__(256) void k_full_terms(StepArgs a, const double* __restrict__ G) {
+// history sum, which the rhs already carries; the constants are added with the rhs).
+// Grid (ceil(N/8), B), 512 threads, one wavefront per row of G (2 Np doubles, read as
+// 16-byte pairs in chunks of 16 per lane, a whole row up to N = 1024).  The first chunk of
+// G and the history loads of the staging (up to 1024 coefficients per pass) are all issued
+// before any of them is used, so the kernel waits for one round trip to memory instead of
+// one per loop pass; eight rows per block share one staging of the history.
+constexpr int kFullRows = 8, kFullChunk = 16, kFullStage = 2;
+__global__ __launch_bounds__(512) void k_full_terms(StepArgs a, const double* __restrict__ G) {
     extern __shared__ double2 xs2[];
     double* xs = reinterpret_cast<double*>(xs2);
     const int b = blockIdx.y, Np = a.Np;
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(256) void k_full_terms(StepArgs a, const double* __
 }
 
 void launch_full_terms(const StepArgs& a, const double* G, hipStream_t s) {
-    hipLaunchKernelGGL(k_full_terms, dim3((a.N + kFullRows - 1) / kFullRows, a.B), dim3(256),
+    hipLaunchKernelGGL(k_full_terms, dim3((a.N + kFullRows - 1) / kFullRows, a.B), dim3(kFullRows * kWave),
                        sizeof(double) * 2 * a.Np, s, a, G);
 }
 
