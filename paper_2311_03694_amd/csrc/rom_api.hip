@@ -53,7 +53,10 @@ extern "C" const char* rom_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
-constexpr int kGraphChunk = 64;   // steps per captured graph
+// Steps are replayed from captured graphs of 1, 2, 4, ..., 64 steps (a binary ladder),
+// so a call of any length is a handful of graph launches.
+constexpr int kGraphSizes = 7;
+constexpr int kGraphChunk = 1 << (kGraphSizes - 1);   // the longest chunk
 
 struct DevBuf {
     void* p = nullptr;
@@ -120,10 +123,11 @@ struct rom_state_s {
     double* xfull = nullptr;            // full form, batches: [Bpad][2Np] operand of X G^T
     int sgen = 0;                       // bumped when scratch or the energy log moves
     long long* cnt = nullptr;           // the two slots of the device step counter
-    // captured chunks of steps, one per parity of the first level (the kernels of a
-    // step take the counter slots of its level's parity)
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-    int graph_gen[2] = {-1, -1}, graph_sgen[2] = {-1, -1};
+    // captured chunks of 2^q steps, one per parity of the first level (the kernels of a
+    // step take the counter slots of its level's parity); the whole ladder is captured
+    // at once and is valid while the workspace and scratch generations hold
+    hipGraphExec_t graph[2][kGraphSizes] = {};
+    int graph_gen = -1, graph_sgen = -1;
     bool pending = false;
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -1181,8 +1185,9 @@ int energy_slots(rom_ctx c, int B) { return B > 1 ? (c->N + 15) / 16 : (c->N + 3
 extern "C" void rom_state_destroy(rom_state s) {
     if (!s) return;
     if (s->ctx && s->ctx->stream) hipStreamSynchronize(s->ctx->stream);
-    for (auto g : s->graph)
-        if (g) hipGraphExecDestroy(g);
+    for (auto& row : s->graph)
+        for (auto g : row)
+            if (g) hipGraphExecDestroy(g);
     for (void* p : s->allocs) hipFree(p);
     if (s->a.elog) hipFree(s->a.elog);
     if (s->scratch) hipFree(s->scratch);
@@ -1295,52 +1300,65 @@ static rom_status prepare(rom_ctx c, rom_state s, int64_t nsteps) {
     return ensure_elog(s, s->h_step + nsteps + 1);
 }
 
+// Capture `len` steps of state s starting at a level of parity `par` into *gx.
+static rom_status capture_chunk(rom_ctx c, rom_state s, int par, int len, hipGraphExec_t* gx) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    rom_status cst = ROM_OK;
+    for (int q = 0; q < len && cst == ROM_OK; ++q) cst = enqueue_step(c, s, c->stream, par + q);
+    hipError_t ee = hipStreamEndCapture(c->stream, &g);
+    if (cst != ROM_OK) {
+        if (g) hipGraphDestroy(g);
+        return cst;
+    }
+    if (ee != hipSuccess) return fail(ROM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ee));
+    hipError_t ie = hipGraphInstantiate(gx, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        *gx = nullptr;
+        return fail(ROM_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+    }
+    return ROM_OK;
+}
+
+// The ladder of captured chunks of state s, (re)captured when the workspace or the
+// state's scratch has moved since.
+static rom_status ensure_ladder(rom_ctx c, rom_state s) {
+    if (s->graph_gen == c->ws_gen && s->graph_sgen == s->sgen) return ROM_OK;
+    for (auto& row : s->graph)
+        for (auto& g : row)
+            if (g) {
+                hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    s->graph_gen = s->graph_sgen = -1;
+    for (int par = 0; par < 2; ++par)
+        for (int q = 0; q < kGraphSizes; ++q) TRYS(capture_chunk(c, s, par, 1 << q, &s->graph[par][q]));
+    s->graph_gen = c->ws_gen;
+    s->graph_sgen = s->sgen;
+    return ROM_OK;
+}
+
 static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
     rom_status st = prepare(c, s, nsteps);
     if (st != ROM_OK) return st;
+    if (nsteps == 0) return ROM_OK;
+    TRYS(ensure_ladder(c, s));
     const long long n0 = s->h_step;
     long long n = n0;
     int64_t left = nsteps;
-    if (left >= 2 * kGraphChunk) {
-        // kGraphChunk is even, so every launch of the chunk starts at n0's parity
-        const int par = (int)(n0 & 1);
-        hipGraphExec_t& gx = s->graph[par];
-        if (!gx || s->graph_gen[par] != c->ws_gen || s->graph_sgen[par] != s->sgen) {
-            if (gx) {
-                hipGraphExecDestroy(gx);
-                gx = nullptr;
-            }
-            hipGraph_t g = nullptr;
-            HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            rom_status cst = ROM_OK;
-            for (int q = 0; q < kGraphChunk && cst == ROM_OK; ++q) cst = enqueue_step(c, s, c->stream, n0 + q);
-            hipError_t ee = hipStreamEndCapture(c->stream, &g);
-            if (cst != ROM_OK) {
-                if (g) hipGraphDestroy(g);
-                return cst;
-            }
-            if (ee != hipSuccess) return fail(ROM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ee));
-            hipError_t ie = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
-            if (ie != hipSuccess) {
-                gx = nullptr;
-                return fail(ROM_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
-            }
-            s->graph_gen[par] = c->ws_gen;
-            s->graph_sgen[par] = s->sgen;
+    // longest chunks first (even lengths keep the parity), then the binary digits of
+    // what is left
+    for (; left >= kGraphChunk; left -= kGraphChunk, n += kGraphChunk)
+        HIPCHK(hipGraphLaunch(s->graph[n & 1][kGraphSizes - 1], c->stream));
+    for (int q = kGraphSizes - 2; q >= 0; --q)
+        if (left & (1LL << q)) {
+            HIPCHK(hipGraphLaunch(s->graph[n & 1][q], c->stream));
+            n += 1LL << q;
+            left -= 1LL << q;
         }
-        while (left >= kGraphChunk) {
-            HIPCHK(hipGraphLaunch(gx, c->stream));
-            left -= kGraphChunk;
-            n += kGraphChunk;
-        }
-    }
-    for (; left > 0; --left, ++n) {
-        st = enqueue_step(c, s, c->stream, n);
-        if (st != ROM_OK) return st;
-    }
     // every update kernel closes the level before its own; the newest one is closed here
-    if (nsteps > 0) launch_close(step_args(s, n0 + nsteps), c->stream);
+    launch_close(step_args(s, n0 + nsteps), c->stream);
     HIPCHK(hipGetLastError());
     s->h_step += nsteps;
     s->pending = true;

@@ -15,6 +15,9 @@ from .inputs import (  # noqa: F401
     mass_spd,
     zeroth_terms,
     initial_u,
+    integer_dense,
+    integer_cp_factors,
+    integer_u,
     make_config,
     make_problem,
     truncate_cp,

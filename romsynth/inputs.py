@@ -204,6 +204,49 @@ def initial_u(N: int, seeds, cfg: int = 0) -> np.ndarray:
     return np.stack(rows, axis=0)
 
 
+# ----------------------------------------------------------------------------- small integers
+
+def integer_dense(N: int, seed: int = 0, cfg: int = 50, vmax: int = 1) -> np.ndarray:
+    """Skew tensor of small integers: C = S - S^(13) with S[i][j][k] uniform in
+    {-vmax, ..., vmax} (one integers((N, N, N)) draw), so |C| <= 2 vmax."""
+    S = _rng(cfg, STREAM_FACTORS, seed).integers(-vmax, vmax + 1, size=(N, N, N)).astype(np.float64)
+    return S - S.transpose(2, 1, 0)
+
+
+def integer_cp_factors(N: int, R: int, seed: int = 0, cfg: int = 51, vmax: int = 1, skew: bool = True):
+    """CP factors of small integers.  skew=True: R/2 column pairs laid out like
+    skew_cp_factors (columns (lam_p; a_p, b_p, c_p) and (lam_p; c_p, b_p, -a_p)), so the
+    pair form applies; skew=False: independent columns.  Entries uniform in
+    {-vmax, ..., vmax}, weights in {1, 2}.  Draw order: a, b, c as integers((N, P)) (P =
+    R/2, or R columns each when skew=False), then the weights as integers(P) (or R)."""
+    rng = _rng(cfg, STREAM_FACTORS, seed)
+    cols = R // 2 if skew else R
+    a, b, c = (rng.integers(-vmax, vmax + 1, size=(N, cols)).astype(np.float64) for _ in range(3))
+    w = rng.integers(1, 3, size=cols).astype(np.float64)
+    if not skew:
+        return w, a, b, c
+    lam = np.empty(R)
+    Af = np.empty((N, R))
+    Bf = np.empty((N, R))
+    Cf = np.empty((N, R))
+    lam[0::2] = w
+    lam[1::2] = w
+    Af[:, 0::2] = a
+    Af[:, 1::2] = c
+    Bf[:, 0::2] = b
+    Bf[:, 1::2] = b
+    Cf[:, 0::2] = c
+    Cf[:, 1::2] = -a
+    return lam, Af, Bf, Cf
+
+
+def integer_u(N: int, seeds, cfg: int = 52, vmax: int = 2) -> np.ndarray:
+    """Rows of small integer coefficients in {-vmax, ..., vmax}, one integers(N) draw per
+    seed from stream 3."""
+    return np.stack([_rng(cfg, STREAM_U0, int(s)).integers(-vmax, vmax + 1, size=N).astype(np.float64)
+                     for s in seeds], axis=0)
+
+
 # ----------------------------------------------------------------------------- named workloads
 
 CONFIGS = {
