@@ -158,6 +158,18 @@ rom_status rom_cp_als(int32_t N, int32_t R, const double *C, double *A1, double 
  * The contraction runs in the context's dtype; y is returned in FP64.  Asynchronous. */
 rom_status rom_nonlinear(rom_ctx ctx, int32_t batch, const double *u_dev, double *y_dev);
 
+/* rom_nonlinear for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same kernels and
+ * results as rom_nonlinear, but the workspace (partial sums, CP projections, operand
+ * copies) is a fixed 32 MiB array that the library's code object holds on each GPU until
+ * the process ends, instead of the context's workspace; the call allocates and frees
+ * nothing and launches only kernels (the workspace it uses is cleared by a kernel, no
+ * memset).  Every call on one GPU shares that array: calls that overlap in time on one
+ * GPU (several streams, several threads) race and must be ordered by the caller.
+ * Errors as rom_nonlinear, plus ROM_E_UNSUPPORTED when the evaluation's workspace
+ * exceeds the 32 MiB (large batches of large N; rom_nonlinear has no such limit). */
+rom_status rom_nonlinear_noalloc(rom_ctx ctx, int32_t batch, const double *u_dev, double *y_dev);
+
 /* Measurement entry point: y = C(u)u exactly as rom_nonlinear computes it, but with the
  * contraction kernels (dense: the stream or MFMA contraction; CP: projections, Hadamard
  * product and scatter) captured `reps` >= 1 times into a HIP graph, launched once to warm

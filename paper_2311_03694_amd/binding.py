@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "ROM_OK", 1: "ROM_E_INVALID", 2: "ROM_E_NOMEM", 3: "ROM_E_DEV
                 4: "ROM_E_NONFINITE", 5: "ROM_E_UNSUPPORTED"}
 
 # every symbol declared in include/rom.h
-EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_timed", "rom_state_create",
+EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_noalloc", "rom_nonlinear_timed",
+           "rom_state_create",
            "rom_state_destroy",
            "rom_step", "rom_step_async", "rom_step_sync", "rom_energy", "rom_state_get",
            "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
@@ -79,6 +80,7 @@ def lib():
     L.rom_destroy.argtypes = [_vp]
     L.rom_destroy.restype = None
     L.rom_nonlinear.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+    L.rom_nonlinear_noalloc.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
     L.rom_nonlinear_timed.argtypes = [_vp, ctypes.c_int32, _vp, _vp, ctypes.c_int32, _d]
     L.rom_state_create.argtypes = [_vp, ctypes.c_int32, _d, ctypes.POINTER(_vp)]
     L.rom_state_destroy.argtypes = [_vp]
@@ -106,7 +108,7 @@ def lib():
     L.rom_cp_skew_layout.restype = ctypes.c_int32
     L.rom_last_error.argtypes = []
     L.rom_last_error.restype = ctypes.c_char_p
-    for name in ("rom_create", "rom_nonlinear", "rom_nonlinear_timed", "rom_state_create", "rom_step", "rom_step_async",
+    for name in ("rom_create", "rom_nonlinear", "rom_nonlinear_noalloc", "rom_nonlinear_timed", "rom_state_create", "rom_step", "rom_step_async",
                  "rom_step_sync", "rom_energy", "rom_state_get", "rom_state_set", "rom_state_u",
                  "rom_step_multi", "rom_query", "rom_set_tile"):
         getattr(L, name).restype = ctypes.c_int
@@ -200,6 +202,11 @@ def rom_destroy(ctx: int):
 
 def rom_nonlinear(ctx: int, batch: int, u_dev, y_dev):
     _check(lib().rom_nonlinear(ctx, int(batch), _dev_ptr(u_dev), _dev_ptr(y_dev)))
+
+
+def rom_nonlinear_noalloc(ctx: int, batch: int, u_dev, y_dev):
+    """rom_nonlinear with the library's fixed device scratch instead of an allocated workspace."""
+    _check(lib().rom_nonlinear_noalloc(ctx, int(batch), _dev_ptr(u_dev), _dev_ptr(y_dev)))
 
 
 def rom_nonlinear_timed(ctx: int, batch: int, u_dev, y_dev, reps: int) -> float:

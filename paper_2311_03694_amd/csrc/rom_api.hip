@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "rom.h"
@@ -67,6 +68,7 @@ struct DevBuf {
 
 struct rom_ctx_s {
     int N = 0, Np = 0, R = 0, Rp = 0, dtype = 0, max_batch = 1;
+    int device = 0;                             // the GPU current at creation
     double nu = 0, dt = 0;
     bool dense = true, diagA = true;
     hipStream_t stream = nullptr;
@@ -216,6 +218,21 @@ bool launch_cp_batched(rom_ctx c, const SkinnyPlan& pp, const SkinnyPlan& ps, in
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Zero `bytes` (a multiple of 16) of device memory with a kernel (unlike a memset node,
+// safe inside a caller's graph capture).
+__global__ void k_zero16(u32x4* p, size_t n) {
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+        p[q] = z;
+}
+void launch_zero_fill(void* p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_zero16, dim3((unsigned)blocks), dim3(256), 0, s, (u32x4*)p, n);
+}
 
 // Contraction workspace of a batch of B (shared by the states of a context and by
 // rom_nonlinear): layout and launch plans.
@@ -497,6 +514,7 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, const rom_ful
     {
         int dev = 0, lds = 0;
         HTRY(hipGetDevice(&dev));
+        c->device = dev;
         HTRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         size_t want = lds > 122880 ? 122880 : (size_t)lds;
         if (want > 65536 && kr_set_lds_limit(want) != hipSuccess) {
@@ -984,14 +1002,25 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
 // contraction is captured `reps` times into a HIP graph, launched once to warm up and
 // once between two events; *kernel_us is the average per repetition.
 static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, double* y_dev, int reps,
-                                 double* kernel_us) {
+                                 double* kernel_us, char* ws_given = nullptr, size_t ws_given_bytes = 0) {
     if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
     if (batch < 1 || batch > c->max_batch) return fail(ROM_E_INVALID, "batch %d outside [1, %d]", batch, c->max_batch);
     if (!u_dev || !y_dev) return fail(ROM_E_INVALID, "u_dev / y_dev is NULL");
     const WsPlan p = plan_ws(c, batch);
-    rom_status st = ensure_ws(c, p.total);
-    if (st != ROM_OK) return st;
-    char* ws = (char*)c->ws;
+    char* ws = ws_given;
+    if (ws) {
+        // a caller-chosen workspace: it must hold the plan, and what the kernels may
+        // read beyond the regions they write (lane vectors run up to one k-step past
+        // the last row) must be zero, as a fresh workspace is
+        if (p.total > ws_given_bytes)
+            return fail(ROM_E_UNSUPPORTED, "the evaluation needs %zu bytes of workspace, more than the %zu available",
+                        p.total, ws_given_bytes);
+        launch_zero_fill(ws, p.total, c->stream);
+    } else {
+        rom_status st = ensure_ws(c, p.total);
+        if (st != ROM_OK) return st;
+        ws = (char*)c->ws;
+    }
     const int accf = acc_f64(c->dtype);
     StepArgs a{};
     if (batch > 1) {
@@ -1067,6 +1096,53 @@ static rom_status nonlinear_impl(rom_ctx c, int32_t batch, const double* u_dev, 
     }
     HIPCHK(hipGetLastError());
     return ROM_OK;
+}
+
+// ============================================================== scratch-free evaluation
+//
+// rom_nonlinear_noalloc runs rom_nonlinear's kernels with their workspace in `scratch`,
+// one array per GPU that the code object brings along (held until the process ends),
+// instead of the context's allocated workspace.  Host code never passes the array's
+// name to a kernel: the device address of each GPU's copy is looked up once per GPU
+// with hipGetSymbolAddress and kept in g_scratch_dev.
+
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this GPU's `scratch` (looked up on the first call with `dev`
+// current; the caller's current device is restored).
+rom_status scratch_of(int dev, void** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return fail(ROM_E_UNSUPPORTED, "device %d outside [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            return fail(ROM_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return ROM_OK;
+}
+
+}  // namespace
+
+extern "C" rom_status rom_nonlinear_noalloc(rom_ctx c, int32_t batch, const double* u_dev, double* y_dev) {
+    if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
+    void* ws = nullptr;
+    TRYS(scratch_of(c->device, &ws));
+    return nonlinear_impl(c, batch, u_dev, y_dev, 1, nullptr, (char*)ws, kStaticScratchBytes);
 }
 
 extern "C" rom_status rom_nonlinear(rom_ctx c, int32_t batch, const double* u_dev, double* y_dev) {
