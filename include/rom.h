@@ -189,10 +189,20 @@ void rom_state_destroy(rom_state st);
 
 /* Advance every trajectory of the state by nsteps BDFk/EXTk steps (eq. nse_d1 with
  * the 1-2-3 start-up ramp) and log the energy E = |u|^2/2 after each step.  Runs on the
- * context's stream, in graph-captured chunks; synchronizes once at the end to read the
- * health flag.  Returns ROM_E_NONFINITE if any trajectory became non-finite, with the
+ * context's stream as replays of captured graphs (see rom_step_prepare); synchronizes
+ * once at the end to read the health flag.  Returns ROM_E_NONFINITE if any trajectory became non-finite, with the
  * first such step number in *first_bad_step (nullable; -1 if none). */
 rom_status rom_step(rom_ctx ctx, rom_state st, int64_t nsteps, int64_t *first_bad_step);
+
+/* Capture, without running any step, the HIP graphs that a later rom_step or
+ * rom_step_async of nsteps replays, and move them to the device.  A call of nsteps
+ * replays (nsteps - 1) / 64 graphs of 64 steps and one graph of the remaining 1..64 steps
+ * ending with the step close; graphs depend on the parity of the first level only, and
+ * both parities are prepared, so other steps may run in between.  A length is otherwise
+ * captured the first time it is stepped.  Graphs are dropped when the energy log or a
+ * workspace moves (it grows by doubling): the energy log is sized here for nsteps more
+ * steps from the current level.  Synchronizes.  Errors as rom_step_async. */
+rom_status rom_step_prepare(rom_ctx ctx, rom_state st, int64_t nsteps);
 
 /* Enqueue nsteps without the final synchronization; rom_step_sync later waits and
  * reports the health flag exactly as rom_step does. */

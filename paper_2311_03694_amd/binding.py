@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "ROM_OK", 1: "ROM_E_INVALID", 2: "ROM_E_NOMEM", 3: "ROM_E_DEV
 EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_noalloc", "rom_nonlinear_timed",
            "rom_state_create",
            "rom_state_destroy",
-           "rom_step", "rom_step_async", "rom_step_sync", "rom_energy", "rom_state_get",
+           "rom_step", "rom_step_async", "rom_step_sync", "rom_step_prepare", "rom_energy", "rom_state_get",
            "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
            "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_create_full", "rom_cp_als",
            "rom_last_error"]
@@ -87,6 +87,7 @@ def lib():
     L.rom_state_destroy.restype = None
     L.rom_step.argtypes = [_vp, _vp, ctypes.c_int64, _i64p]
     L.rom_step_async.argtypes = [_vp, _vp, ctypes.c_int64]
+    L.rom_step_prepare.argtypes = [_vp, _vp, ctypes.c_int64]
     L.rom_step_sync.argtypes = [_vp, _vp, _i64p]
     L.rom_energy.argtypes = [_vp, _vp, _d, _d]
     L.rom_state_get.argtypes = [_vp, _vp, _d, _d, _i64p]
@@ -109,7 +110,7 @@ def lib():
     L.rom_last_error.argtypes = []
     L.rom_last_error.restype = ctypes.c_char_p
     for name in ("rom_create", "rom_nonlinear", "rom_nonlinear_noalloc", "rom_nonlinear_timed", "rom_state_create", "rom_step", "rom_step_async",
-                 "rom_step_sync", "rom_energy", "rom_state_get", "rom_state_set", "rom_state_u",
+                 "rom_step_sync", "rom_step_prepare", "rom_energy", "rom_state_get", "rom_state_set", "rom_state_u",
                  "rom_step_multi", "rom_query", "rom_set_tile"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -238,6 +239,10 @@ def rom_step(ctx: int, st: int, nsteps: int) -> None:
 
 def rom_step_async(ctx: int, st: int, nsteps: int) -> None:
     _check(lib().rom_step_async(ctx, st, int(nsteps)))
+
+
+def rom_step_prepare(ctx: int, st: int, nsteps: int) -> None:
+    _check(lib().rom_step_prepare(ctx, st, int(nsteps)))
 
 
 def rom_step_sync(ctx: int, st: int) -> None:
@@ -374,6 +379,9 @@ class RomState:
 
     def step_async(self, nsteps: int):
         rom_step_async(self.rom.handle, self.handle, nsteps)
+
+    def prepare(self, nsteps: int):
+        rom_step_prepare(self.rom.handle, self.handle, nsteps)
 
     def sync(self):
         rom_step_sync(self.rom.handle, self.handle)

@@ -54,10 +54,10 @@ extern "C" const char* rom_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
-// Steps are replayed from captured graphs of 1, 2, 4, ..., 64 steps (a binary ladder),
-// so a call of any length is a handful of graph launches.
-constexpr int kGraphSizes = 7;
-constexpr int kGraphChunk = 1 << (kGraphSizes - 1);   // the longest chunk
+// Steps are replayed from captured graphs: a call of n steps is (n - 1) / 64 launches of a
+// 64-step graph and one graph of the remaining 1..64 steps that ends with the closing
+// kernel, so a call of up to 64 steps is a single graph launch.
+constexpr int kGraphChunk = 64;
 
 struct DevBuf {
     void* p = nullptr;
@@ -125,10 +125,10 @@ struct rom_state_s {
     double* xfull = nullptr;            // full form, batches: [Bpad][2Np] operand of X G^T
     int sgen = 0;                       // bumped when scratch or the energy log moves
     long long* cnt = nullptr;           // the two slots of the device step counter
-    // captured chunks of 2^q steps, one per parity of the first level (the kernels of a
-    // step take the counter slots of its level's parity); the whole ladder is captured
-    // at once and is valid while the workspace and scratch generations hold
-    hipGraphExec_t graph[2][kGraphSizes] = {};
+    // captured chunks of len = 1..64 steps, per parity of the first level (the kernels of
+    // a step take the counter slots of its level's parity), without [0] and with [1] the
+    // closing kernel at the end; valid while the workspace and scratch generations hold
+    hipGraphExec_t graph[2][2][kGraphChunk + 1] = {};
     int graph_gen = -1, graph_sgen = -1;
     bool pending = false;
     size_t bytes = 0;
@@ -1261,9 +1261,10 @@ int energy_slots(rom_ctx c, int B) { return B > 1 ? (c->N + 15) / 16 : (c->N + 3
 extern "C" void rom_state_destroy(rom_state s) {
     if (!s) return;
     if (s->ctx && s->ctx->stream) hipStreamSynchronize(s->ctx->stream);
-    for (auto& row : s->graph)
-        for (auto g : row)
-            if (g) hipGraphExecDestroy(g);
+    for (auto& par : s->graph)
+        for (auto& row : par)
+            for (auto g : row)
+                if (g) hipGraphExecDestroy(g);
     for (void* p : s->allocs) hipFree(p);
     if (s->a.elog) hipFree(s->a.elog);
     if (s->scratch) hipFree(s->scratch);
@@ -1376,12 +1377,14 @@ static rom_status prepare(rom_ctx c, rom_state s, int64_t nsteps) {
     return ensure_elog(s, s->h_step + nsteps + 1);
 }
 
-// Capture `len` steps of state s starting at a level of parity `par` into *gx.
-static rom_status capture_chunk(rom_ctx c, rom_state s, int par, int len, hipGraphExec_t* gx) {
+// Capture `len` steps of state s starting at a level of parity `par` into *gx, with the
+// closing kernel of the newest level at the end when `close` is set.
+static rom_status capture_chunk(rom_ctx c, rom_state s, int par, int len, int close, hipGraphExec_t* gx) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     rom_status cst = ROM_OK;
     for (int q = 0; q < len && cst == ROM_OK; ++q) cst = enqueue_step(c, s, c->stream, par + q);
+    if (cst == ROM_OK && close) launch_close(step_args(s, par + len), c->stream);
     hipError_t ee = hipStreamEndCapture(c->stream, &g);
     if (cst != ROM_OK) {
         if (g) hipGraphDestroy(g);
@@ -1394,24 +1397,53 @@ static rom_status capture_chunk(rom_ctx c, rom_state s, int par, int len, hipGra
         *gx = nullptr;
         return fail(ROM_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
     }
+    // move the executable graph to the device now rather than at its first launch
+    ie = hipGraphUpload(*gx, c->stream);
+    if (ie != hipSuccess) return fail(ROM_E_DEVICE, "graph upload failed: %s", hipGetErrorString(ie));
     return ROM_OK;
 }
 
-// The ladder of captured chunks of state s, (re)captured when the workspace or the
-// state's scratch has moved since.
-static rom_status ensure_ladder(rom_ctx c, rom_state s) {
-    if (s->graph_gen == c->ws_gen && s->graph_sgen == s->sgen) return ROM_OK;
-    for (auto& row : s->graph)
-        for (auto& g : row)
-            if (g) {
-                hipGraphExecDestroy(g);
-                g = nullptr;
-            }
-    s->graph_gen = s->graph_sgen = -1;
-    for (int par = 0; par < 2; ++par)
-        for (int q = 0; q < kGraphSizes; ++q) TRYS(capture_chunk(c, s, par, 1 << q, &s->graph[par][q]));
-    s->graph_gen = c->ws_gen;
-    s->graph_sgen = s->sgen;
+// The graph of `len` steps from a level of parity `par` (captured on first use; every
+// cached graph is dropped when the workspace or the state's scratch has moved).
+static rom_status chunk_graph(rom_ctx c, rom_state s, int par, int len, int close, hipGraphExec_t* out) {
+    if (s->graph_gen != c->ws_gen || s->graph_sgen != s->sgen) {
+        for (auto& pr : s->graph)
+            for (auto& row : pr)
+                for (auto& g : row)
+                    if (g) {
+                        hipGraphExecDestroy(g);
+                        g = nullptr;
+                    }
+        s->graph_gen = c->ws_gen;
+        s->graph_sgen = s->sgen;
+    }
+    hipGraphExec_t& gx = s->graph[par][close][len];
+    if (!gx) TRYS(capture_chunk(c, s, par, len, close, &gx));
+    *out = gx;
+    return ROM_OK;
+}
+
+// Walk the graphs of a call of nsteps from level n0: launch them, or (launch = false)
+// only make sure they are captured.
+static rom_status walk_graphs(rom_ctx c, rom_state s, long long n0, int64_t nsteps, bool launch) {
+    long long n = n0;
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int len = left > kGraphChunk ? kGraphChunk : (int)left;
+        const int close = left <= kGraphChunk ? 1 : 0;
+        hipGraphExec_t gx = nullptr;
+        TRYS(chunk_graph(c, s, (int)(n & 1), len, close, &gx));
+        if (launch) HIPCHK(hipGraphLaunch(gx, c->stream));
+        else if (len == kGraphChunk && !close) {
+            // the 64-step graph repeats from the same parity: one capture serves them all
+            const int64_t reps = (left - 1) / kGraphChunk;
+            n += reps * kGraphChunk;
+            left -= reps * kGraphChunk;
+            continue;
+        }
+        n += len;
+        left -= len;
+    }
     return ROM_OK;
 }
 
@@ -1419,25 +1451,24 @@ static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
     rom_status st = prepare(c, s, nsteps);
     if (st != ROM_OK) return st;
     if (nsteps == 0) return ROM_OK;
-    TRYS(ensure_ladder(c, s));
-    const long long n0 = s->h_step;
-    long long n = n0;
-    int64_t left = nsteps;
-    // longest chunks first (even lengths keep the parity), then the binary digits of
-    // what is left
-    for (; left >= kGraphChunk; left -= kGraphChunk, n += kGraphChunk)
-        HIPCHK(hipGraphLaunch(s->graph[n & 1][kGraphSizes - 1], c->stream));
-    for (int q = kGraphSizes - 2; q >= 0; --q)
-        if (left & (1LL << q)) {
-            HIPCHK(hipGraphLaunch(s->graph[n & 1][q], c->stream));
-            n += 1LL << q;
-            left -= 1LL << q;
-        }
-    // every update kernel closes the level before its own; the newest one is closed here
-    launch_close(step_args(s, n0 + nsteps), c->stream);
+    // every update kernel closes the level before its own; the graph of the last chunk
+    // closes the newest one
+    TRYS(walk_graphs(c, s, s->h_step, nsteps, true));
     HIPCHK(hipGetLastError());
     s->h_step += nsteps;
     s->pending = true;
+    return ROM_OK;
+}
+
+extern "C" rom_status rom_step_prepare(rom_ctx c, rom_state s, int64_t nsteps) {
+    if (!c || !s || s->ctx != c) return fail(ROM_E_INVALID, "bad ctx/state");
+    if (nsteps < 0) return fail(ROM_E_INVALID, "nsteps < 0");
+    TRYS(prepare(c, s, nsteps));
+    // the graphs depend on the parity of the first level only: both parities are
+    // captured, so steps of any count may come between this call and the prepared one
+    TRYS(walk_graphs(c, s, s->h_step, nsteps, false));
+    TRYS(walk_graphs(c, s, s->h_step + 1, nsteps, false));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return ROM_OK;
 }
 

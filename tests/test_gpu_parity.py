@@ -262,3 +262,27 @@ def test_graph_and_eager_agree(torch_gpu):
     for _ in range(300):
         b.step(1)
     assert np.array_equal(a.get()[0], b.get()[0])
+
+
+def test_prepare_runs_no_step(torch_gpu):
+    """rom_step_prepare captures graphs without stepping; a prepared call of 20 steps and
+    calls of other lengths (one graph, a 64-step graph plus the rest) give the same
+    trajectory as an unprepared one, to the bit."""
+    _say("prepare")
+    p = romsynth.make_problem(40, pairs=20, eps=1e-6, A="spd", cfg=24, dense=False)
+    rom = rg.Rom.from_problem(p, dense=False, dtype="fp32")
+    a = rom.state(p.u0[0])
+    a.step(3)
+    u3 = a.get()
+    a.prepare(20)
+    a.prepare(150)
+    assert a.step_count == 3
+    ub = a.get()
+    assert all(np.array_equal(x, y) for x, y in zip(u3[:2], ub[:2]))
+    a.step(20)
+    a.step(150)
+    b = rom.state(p.u0[0])
+    for k in (3, 20, 64, 86):
+        b.step(k)
+    assert np.array_equal(a.get()[0], b.get()[0])
+    assert np.array_equal(a.energy()[1], b.energy()[1])
