@@ -20,5 +20,8 @@ from .oracle import (  # noqa: F401
     round_f32,
     round_bf16,
     split_bf16x3,
+    set_threads,
+    get_threads,
+    threads,
 )
 from . import als  # noqa: F401,E402

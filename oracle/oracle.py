@@ -26,7 +26,7 @@ def lib_path() -> str:
 
 def build() -> str:
     """Compile rom_oracle.c with gcc: strict IEEE FP64 (no contraction into FMA)."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
            "-std=c99", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
@@ -62,8 +62,35 @@ def _load():
     lib.orc_round_f32.argtypes = [_i64, _d, _d]
     lib.orc_round_bf16.argtypes = [_i64, _d, _d]
     lib.orc_split_bf16x3.argtypes = [_i64, _d, _d, _d]
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_threads.restype = ctypes.c_int
+    lib.orc_get_threads.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def set_threads(n: int) -> int:
+    """Host threads for the oracle's row loops (results identical for any count); returns
+    the previous count."""
+    return int(_load().orc_set_threads(int(n)))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
+
+
+class threads:
+    """Context manager: `with oracle.threads(n): ...` runs the oracle's row loops on n threads."""
+
+    def __init__(self, n: int):
+        self.n = int(n)
+
+    def __enter__(self):
+        self.old = set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.old)
 
 
 def _c(a) -> np.ndarray:

@@ -8,8 +8,11 @@
  * leg of the benchmark load this file's library.  The product path never links,
  * calls or includes it, and it shares no code with the HIP sources.
  *
- * Every routine is a single-threaded loop nest written in the order of the
- * definition it cites, in IEEE FP64 (built with -ffp-contract=off, no fast-math).
+ * Every routine is a loop nest written in the order of the definition it cites, in IEEE
+ * FP64 (built with -ffp-contract=off, no fast-math).  Loops over independent output rows
+ * may be shared among host threads (OpenMP, orc_set_threads; one thread unless asked):
+ * each row is still summed by one thread in the written order, so the results are the
+ * same to the bit for any thread count.
  *
  * Storage (row-major, 0-based):
  *   C[i][j][k]  = the paper's C_{i k j} with output row i; the pair (j, k) is the pair
@@ -26,9 +29,24 @@
  * invariants, brute force, library routines); none is "parity unpinned".
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* ------------------------------------------------------------------ threads */
+
+static int g_threads = 1;
+
+/* Host threads for the row loops (>= 1); returns the previous count. */
+int orc_set_threads(int n)
+{
+    int old = g_threads;
+    g_threads = n < 1 ? 1 : n;
+    return old;
+}
+
+int orc_get_threads(void) { return g_threads; }
 
 /* ------------------------------------------------------------------ contractions */
 
@@ -36,6 +54,7 @@
  *   y_i = sum_{j} u_j * ( sum_{k} C[i][j][k] * u_k ),  2 N^3 flops. */
 void orc_nonlinear_dense(int64_t N, const double *C, const double *u, double *y)
 {
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int64_t i = 0; i < N; ++i) {
         double s = 0.0;
         for (int64_t j = 0; j < N; ++j) {
@@ -54,6 +73,7 @@ void orc_nonlinear_dense(int64_t N, const double *C, const double *u, double *y)
 void orc_nonlinear_dense_rows(int64_t N, const double *C, const double *u,
                               int64_t nrows, const int64_t *rows, double *y_out)
 {
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int64_t q = 0; q < nrows; ++q) {
         int64_t i = rows[q];
         double s = 0.0;
@@ -76,6 +96,7 @@ void orc_nonlinear_cp(int64_t N, int64_t R, const double *lam, const double *Af,
 {
     double *s = (double *)malloc(sizeof(double) * (size_t)(R > 0 ? R : 1));
     double *t = (double *)malloc(sizeof(double) * (size_t)(R > 0 ? R : 1));
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int64_t r = 0; r < R; ++r) {
         double sr = 0.0, tr = 0.0;
         for (int64_t k = 0; k < N; ++k)
@@ -85,6 +106,7 @@ void orc_nonlinear_cp(int64_t N, int64_t R, const double *lam, const double *Af,
         s[r] = sr;
         t[r] = tr;
     }
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int64_t i = 0; i < N; ++i) {
         double acc = 0.0;
         for (int64_t r = 0; r < R; ++r)
@@ -147,6 +169,7 @@ void orc_nonlinear_svd(int64_t N, int64_t R, const double *U, const double *sigm
             acc += U[j * R + r] * u[j];
         s[r] = acc;
     }
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int64_t i = 0; i < N; ++i) {
         double yi = 0.0;
         for (int64_t r = 0; r < R; ++r) {

@@ -9,6 +9,9 @@ import numpy as np
 #    compared with the oracle on BF16-rounded operands (its products are exact, so only
 #    the FP32 accumulation remains), the other formats with the exact operator.
 TRAJ_TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-5, "bf16": 1e-3}
+# The energy E = |u|^2 / 2 has the relative error dE/E = 2 u.du / |u|^2 <= 2 |du| / |u| to
+# first order, so a trajectory within TRAJ_TOL of the oracle has its energies within twice it.
+ENERGY_TOL = {k: 2.0 * v for k, v in TRAJ_TOL.items()}
 EVAL_TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-5, "bf16": 1e-5}
 
 U32 = 2.0 ** -24

@@ -16,7 +16,7 @@ import pytest
 import oracle as orc
 import paper_2311_03694_amd as rg
 import romsynth
-from helpers import EPS_OP, EVAL_TOL, TRAJ_TOL, U_ACC, check_eval, eval_bound_cp, rel
+from helpers import TRAJ_TOL, bound_cp, bound_dense, check_elem, g_dense, rel
 from paper_2311_03694_amd import tune
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -64,19 +64,10 @@ def _abs_rows(C, u, rows):
     return np.array([au @ (np.abs(np.asarray(C[i])) @ au) for i in rows])
 
 
-def _check_rows(dt, y, y_ref, yabs, N):
-    """Norm-wise over the sampled rows: the operand error EPS_OP plus the accumulation
-    bound 4 N u of N^2-term sums, relative to sum |terms| (as eval_bound_dense)."""
-    bound = float(np.linalg.norm(yabs) * (EPS_OP[dt] + 4.0 * N * U_ACC[dt]))
-    check_eval(dt, y, y_ref, bound)
-
-
-def _check_rows_bf16(y, y_ref_exact, yabs, N):
-    """Elementwise: each product carries three BF16 roundings (2^-9 relative each) and
-    the FP32 sum of N^2 terms at most N^2 2^-24 relative to sum |terms|."""
-    g = (1 + 2.0 ** -8) ** 3 - 1 + N * N * 2.0 ** -24
-    err = np.abs(np.asarray(y) - np.asarray(y_ref_exact))
-    assert np.all(err <= g * yabs + 1e-300), float(np.max(err / (g * yabs + 1e-300)))
+def _check_rows(dt, y, y_ref, yabs, N, what=""):
+    """Row by row: the rounding bound g_dense (operand conversions, products and the
+    accumulation bound of N^2-term sums) times sum_jk |C_ijk| |u_j| |u_k| of each row."""
+    check_elem(y, y_ref, g_dense(dt, N) * yabs, what)
 
 
 def _nonlinear(torch, rom, U):
@@ -97,8 +88,8 @@ def test_config3_cp_fp32(torch_gpu, cfg3):
     tune.apply(rom, 1, dense=False, R=p.Af.shape[1])
     u = p.u0[0]
     y = _nonlinear(torch_gpu, rom, u)[0]
-    check_eval("fp32", y, orc.nonlinear_cp(p.lam, p.Af, p.Bf, p.Cf, u),
-               eval_bound_cp("fp32", p.lam, p.Af, p.Bf, p.Cf, u))
+    check_elem(y, orc.nonlinear_cp(p.lam, p.Af, p.Bf, p.Cf, u), bound_cp("fp32", p.lam, p.Af, p.Bf, p.Cf, u),
+               "N=1000 CP evaluation")
     s = rom.state(p.u0)
     s.step(40)
     uh, _, n = s.get()
@@ -113,22 +104,29 @@ def test_config3_cp_fp32(torch_gpu, cfg3):
 
 def test_config3_dense_fp32(torch_gpu, cfg3):
     """Headline workload, dense G-ROM (the streaming contraction over 1e9 entries):
-    sampled rows of one evaluation, and the first two steps."""
+    sampled rows of one evaluation; then three steps, every level against the oracle,
+    and the sampled rows of the y levels the steps computed (y^1, y^2) against the
+    oracle at the GPU's own u^1, u^2."""
     p = cfg3
-    _say("N=1000 dense FP32: sampled rows and 2 steps")
+    _say("N=1000 dense FP32: sampled rows and 3 steps")
     rom = rg.Rom.from_problem(p, dense=True, dtype="fp32", max_batch=1)
     tune.apply(rom, 1, dense=True)
     u = p.u0[0]
     rows = _rows(p.N)
     y = _nonlinear(torch_gpu, rom, u)[0]
-    _check_rows("fp32", y[rows], orc.nonlinear_dense_rows(p.C, u, rows), _abs_rows(p.C, u, rows), p.N)
+    _check_rows("fp32", y[rows], orc.nonlinear_dense_rows(p.C, u, rows), _abs_rows(p.C, u, rows), p.N, "evaluation")
     s = rom.state(p.u0)
-    s.step(2)
-    uh, _, n = s.get()
-    ref = orc.run(p.N, p.nu, p.dt, p.A, 2, u0=u, C=p.C)
-    assert ref["status"] == 0 and n == 2
-    assert rel(uh[0][0], ref["u_hist"][0]) < TRAJ_TOL["fp32"]
-    assert rel(uh[1][0], ref["u_hist"][1]) < TRAJ_TOL["fp32"]
+    s.step(3)
+    uh, yh, n = s.get()
+    with orc.threads(16):
+        ref = orc.run(p.N, p.nu, p.dt, p.A, 3, u0=u, C=p.C, traj=True)
+    assert ref["status"] == 0 and n == 3
+    for q in range(3):
+        assert rel(uh[q][0], ref["traj"][3 - q]) < TRAJ_TOL["fp32"], q
+    for q in range(2):
+        ul = uh[q + 1][0]
+        _check_rows("fp32", yh[q][0][rows], orc.nonlinear_dense_rows(p.C, ul, rows), _abs_rows(p.C, ul, rows), p.N,
+                    f"y level {2 - q}")
     s.close()
     rom.close()
 
@@ -149,10 +147,7 @@ def test_config3_batched_dense(torch_gpu, cfg3, dt):
         _say(f"  trajectory {b}")
         y_ref = orc.nonlinear_dense_rows(p.C, U[b], rows)
         yabs = _abs_rows(p.C, U[b], rows)
-        if dt == "bf16":
-            _check_rows_bf16(Y[b][rows], y_ref, yabs, p.N)
-        else:
-            _check_rows(dt, Y[b][rows], y_ref, yabs, p.N)
+        _check_rows(dt, Y[b][rows], y_ref, yabs, p.N, f"trajectory {b}")
     rom.close()
 
 
@@ -170,15 +165,10 @@ def test_config2_batched_dense(torch_gpu, cfg2, dt):
         Cr = orc.round_bf16(p.C).reshape(p.C.shape)
     for b in (0, 1, 127, 128, 200, 255):
         if dt == "bf16":
+            # BF16 against the oracle on BF16-rounded operands: only the accumulation remains
             ur = orc.round_bf16(p.u0[b])
-            y_ref = orc.nonlinear_dense(Cr, ur)
-            bound = float(np.linalg.norm(np.einsum("ijk,j,k->i", np.abs(Cr), np.abs(ur), np.abs(ur)))
-                          * 4.0 * p.N * U_ACC[dt])
-        else:
-            y_ref = orc.nonlinear_dense(p.C, p.u0[b])
-            rows = np.arange(p.N)
-            bound = float(np.linalg.norm(_abs_rows(p.C, p.u0[b], rows)) * (EPS_OP[dt] + 4.0 * p.N * U_ACC[dt]))
-        check_eval(dt, Y[b], y_ref, bound)
+            check_elem(Y[b], orc.nonlinear_dense(Cr, ur), bound_dense(dt, Cr, ur, rounded=True), f"trajectory {b}")
+        check_elem(Y[b], orc.nonlinear_dense(p.C, p.u0[b]), bound_dense(dt, p.C, p.u0[b]), f"trajectory {b}")
     rom.close()
 
 
@@ -193,8 +183,8 @@ def test_config2_batched_cp(torch_gpu, cfg2):
     Y = _nonlinear(torch_gpu, rom, p.u0)
     sample = (0, 1, 127, 128, 200, 255)
     for b in sample:
-        check_eval("fp32", Y[b], orc.nonlinear_cp(p.lam, p.Af, p.Bf, p.Cf, p.u0[b]),
-                   eval_bound_cp("fp32", p.lam, p.Af, p.Bf, p.Cf, p.u0[b]))
+        check_elem(Y[b], orc.nonlinear_cp(p.lam, p.Af, p.Bf, p.Cf, p.u0[b]),
+                   bound_cp("fp32", p.lam, p.Af, p.Bf, p.Cf, p.u0[b]), f"trajectory {b}")
     s = rom.state(p.u0)
     s.step(30)
     uh, _, n = s.get()
