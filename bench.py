@@ -32,8 +32,12 @@ Also in the one JSON line:
   multi         uneven N: one CP trajectory each at N = 100, 200, 400, 700, 1000 stepped
                 together by grouped launches (rom_step_multi) and one after the other
   serving       a bounded Poisson request stream through the continuous-batching loop
-  rel_err       GPU trajectories against the FP64 oracle (same operator)
-  cpu_baseline  the FP64 oracle (plain C, one thread) on a bounded sample of steps
+  model_error   the CP-ROM's distance from the G-ROM (Sec. 4.1: errors relative to the
+                G-ROM) at CP ranks 500, 1000, 2000 over 1000 steps, GPU FP32 trajectories
+  rel_err       every section: sampled GPU trajectories against the FP64 oracle of the
+                same operator (the oracle leg runs after all GPU timing)
+  cpu_baseline  the FP64 oracle (plain C) on a bounded sample of steps, on all host cores
+                of the GPU machine's share (results identical to one thread) and on one
 """
 from __future__ import annotations
 
@@ -124,6 +128,62 @@ class Timer:
         return e0.elapsed_time(e1) / 1e3
 
 
+ORC_THREADS = max(1, min(16, os.cpu_count() or 1))     # the host share of one GPU
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+class Checks:
+    """GPU results kept for the oracle leg: each entry names a section, the operator, the
+    initial coefficients, the number of steps and the GPU's final coefficients (and
+    energy log)."""
+
+    def __init__(self):
+        self.items = []
+
+    def add(self, section, label, prob, ops, u0, nsteps, u_gpu, E_gpu=None, full=None, dtype="fp32"):
+        self.items.append(dict(section=section, label=label, N=prob[0], nu=prob[1], dt=prob[2], A=prob[3],
+                               ops=ops, u0=np.array(u0, dtype=np.float64), nsteps=int(nsteps),
+                               u_gpu=np.array(u_gpu, dtype=np.float64),
+                               E_gpu=None if E_gpu is None else np.array(E_gpu, dtype=np.float64),
+                               full=full, dtype=dtype))
+
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-5, "bf16": 1e-3}
+
+
+def run_checks(checks, orc, log):
+    """The oracle leg of the accuracy report: {section: {label: errors}}.  Oracle runs of
+    the same operator, start and length are shared."""
+    out = {}
+    cache = {}
+    for c in checks.items:
+        key = (id(c["ops"]), id(c["full"]), c["u0"].tobytes(), c["nsteps"])
+        if key not in cache:
+            t = time.perf_counter()
+            with orc.threads(ORC_THREADS):
+                r = orc.run(c["N"], c["nu"], c["dt"], c["A"], c["nsteps"], u0=c["u0"], **c["ops"], **(c["full"] or {}))
+            cache[key] = r
+            log(f"oracle: {c['section']} {c['label']} ({c['nsteps']} steps, {time.perf_counter() - t:.1f}s)")
+        r = cache[key]
+        ref = r["u_hist"][0]
+        e = dict(steps=c["nsteps"], traj=float(np.linalg.norm(c["u_gpu"] - ref) / np.linalg.norm(ref)),
+                 tol=TOL[c["dtype"]])
+        if c["E_gpu"] is not None:
+            e["energy"] = float(np.max(np.abs(c["E_gpu"] - r["E"]) / r["E"]))
+        out.setdefault(c["section"], {})[c["label"]] = e
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -183,8 +243,10 @@ def main():
         return rg.rom_nonlinear_timed(rom.handle, B, ud, yd, reps) * 1e-6
 
     sec = args.section
-    if sec not in ("all", "headline"):
-        args.no_cpu = True
+    checks = Checks()
+    prob = (N, p.nu, p.dt, p.A)
+    ops_dense = dict(C=p.C)
+    ops_cp = dict(lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
     result = {"metric": METRIC, "value": None, "unit": "trajectory-steps/s", "n_gpus": 1,
               "section": sec}
     if sec in ("all", "headline"):
@@ -212,7 +274,41 @@ def main():
         cp_rate = K / t_cp
         d_rate = Kd / t_d
         d_bytes = float(N) ** 3 * es
+        # one CP step with a dense stiffness: the scatter reads Af [N][R]; the Helmholtz
+        # kernel reads Hinv_k [N][N] (FP64) and the projection operator [B|C]^T Hinv_k,
+        # 1.5R rows in the pair form (2R in the general form) of N values
+        cp_step_bytes = N * R * es + 8.0 * N * N + (1.5 if cp_form else 2.0) * R * N * es
         cp_bytes = (2.5 if cp_form else 3.0) * N * R * es
+        s_chk = rom_d.state(p.u0)
+        s_chk.step(3)
+        checks.add("headline", "dense", prob, ops_dense, p.u0[0], 3, s_chk.u(), E_gpu=s_chk.energy()[1][:, 0], dtype=dt)
+        s_chk.close()
+        # the CP-ROM's distance from the G-ROM (Sec. 4.1): GPU trajectories, u every 100th
+        # level over 1000 steps, CP ranks 500, 1000, 2000 against the dense tensor
+        log("model error: CP ranks 500, 1000, 2000 against the dense G-ROM, 1000 steps")
+        marks = list(range(100, 1001, 100))
+
+        def traj_marks(rom):
+            st = rom.state(p.u0)
+            out, done = [], 0
+            for m in marks:
+                st.step(m - done)
+                done = m
+                out.append(st.u().copy())
+            st.close()
+            return np.stack(out)
+
+        U_dense = traj_marks(rom_d)
+        model = {}
+        for Rm in (500, 1000, 2000):
+            ops_m = dict(zip(("lam", "Af", "Bf", "Cf"), romsynth.truncate_cp(p.lam, p.Af, p.Bf, p.Cf, Rm)))
+            rom_m = rg.Rom(N, p.nu, p.dt, p.A, **ops_m, dtype=dt, stream=stream)
+            Um = traj_marks(rom_m)
+            rom_m.close()
+            model[f"R{Rm}"] = {"max_rel_to_grom": float(np.max(np.linalg.norm(Um - U_dense, axis=1) /
+                                                                np.linalg.norm(U_dense, axis=1))),
+                               "compression_N2_over_3R": N * N / (3.0 * Rm),
+                               "compression_skew_2N2_over_3R": 2.0 * N * N / (3.0 * Rm)}
         result = {
             "metric": METRIC,
             "value": cp_rate,
@@ -238,10 +334,16 @@ def main():
                          "frac": d_bytes / d_kernel / 1e9 / HBM_PEAK_GBS,
                          "traffic": _traffic(f"dense_gemv_n{N}_{dt}", "dense_gemv"),
                          "avg_launch_us": d_kernel * 1e6, "algorithmic_bytes": d_bytes},
-            "roofline_cp": {"bound": "latency", "kernel": "k_cp_proj1 + k_cp_scatter1" + (" (pair form)" if cp_form else ""),
-                            "achieved": cp_bytes / cp_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": cp_bytes / cp_kernel / 1e9 / HBM_PEAK_GBS,
-                            "avg_launch_us": cp_kernel * 1e6, "algorithmic_bytes": cp_bytes},
+            "roofline_cp": {"bound": "hbm", "kernel": "one CP step: k_cp_scatter1 (right-hand side) + k_helm_proj "
+                                                      "(Helmholtz apply and next projections)"
+                                                      + (", pair form" if cp_form else ""),
+                            "achieved": cp_step_bytes / (t_cp / K) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": cp_step_bytes / (t_cp / K) / 1e9 / HBM_PEAK_GBS,
+                            "avg_step_us": t_cp / K * 1e6, "algorithmic_bytes": cp_step_bytes},
+            "cp_evaluation": {"kernel": "k_cp_proj1 + k_cp_scatter1 (rom_nonlinear)", "avg_launch_us": cp_kernel * 1e6,
+                              "algorithmic_bytes": cp_bytes, "hbm_frac": cp_bytes / cp_kernel / 1e9 / HBM_PEAK_GBS},
+            "model_error": dict(model, steps=1000, note="max over every 100th level of |u_cp - u_dense| / "
+                                                        "|u_dense|, FP32 GPU trajectories"),
         }
         s_cp.close()
         s_d.close()
@@ -265,6 +367,15 @@ def main():
                     s, t = step_rate(rom, u0, steps, 5)
                     name = "dense" if dense else "cp"
                     entry[name] = {"traj_steps_per_s": steps * B / t, "us_per_step": t / steps * 1e6}
+                    s.close()
+                    # accuracy: a fresh batch, sampled trajectories against the oracle
+                    nchk = 3 if dense else 200
+                    s = rom.state(u0)
+                    s.step(nchk)
+                    ug = s.get()[0][0]
+                    ops = ops_dense if dense else ops_cp
+                    for b in (0, B - 1):
+                        checks.add("batched", f"B{B}_{bdt}_{name}_traj{b}", prob, ops, u0[b], nchk, ug[b], dtype=bdt)
                     if dense:
                         tk = kernel_avg(rom, u0, 10)
                         fl = 2.0 * N ** 3 * B
@@ -284,6 +395,9 @@ def main():
         # ---------------- config 2: N = 400, B = 256
         log("config 2 (N=400, B=256)")
         p2 = romsynth.make_config(2, R=400)
+        prob2 = (p2.N, p2.nu, p2.dt, p2.A)
+        ops2d = dict(C=p2.C)
+        ops2c = dict(lam=p2.lam, Af=p2.Af, Bf=p2.Bf, Cf=p2.Cf)
         c2 = {}
         for bdt in ("bf16", "bf16x3", "fp32"):
             rom = rg.Rom.from_problem(p2, dense=True, dtype=bdt, max_batch=256, stream=stream)
@@ -295,11 +409,20 @@ def main():
                                   "contraction_us": tk * 1e6, "tflops": fl / tk / 1e12,
                                   "mfma_frac": fl / tk / 1e12 / MFMA_PEAK_TFLOPS[bdt]}
             s.close()
+            s = rom.state(p2.u0)
+            s.step(20)
+            ug = s.get()[0][0]
+            for b in (0, 255):
+                checks.add("config2", f"dense_{bdt}_traj{b}", prob2, ops2d, p2.u0[b], 20, ug[b], dtype=bdt)
+            s.close()
             rom.close()
         rom = rg.Rom.from_problem(p2, dense=False, dtype="fp32", max_batch=256, stream=stream)
         tune.apply(rom, 256, dense=False, R=400, table=tiles)
         s, t = step_rate(rom, p2.u0, 500, 20)
         c2["cp_fp32_R400"] = {"traj_steps_per_s": 500 * 256 / t, "us_per_step": t / 500 * 1e6}
+        ug = s.get()[0][0]
+        for b in (0, 255):
+            checks.add("config2", f"cp_fp32_R400_traj{b}", prob2, ops2c, p2.u0[b], 520, ug[b])
         s.close()
         rom.close()
         result["config2"] = c2
@@ -321,7 +444,6 @@ def main():
             sig = 1.0 / (1.0 + np.arange(Rs))
             V = rng.standard_normal((N, N, Rs)) / N
             rom_s = rg.Rom(N, p.nu, p.dt, A3, svd=(U, sig, V), dtype="fp32", max_batch=1, stream=stream)
-            del V
             steps = 2000
             s_s, t_s = step_rate(rom_s, p.u0, steps, 20)
             tk = kernel_avg(rom_s, p.u0, 10)
@@ -330,6 +452,10 @@ def main():
                              "contraction_us": tk * 1e6, "compression_N_over_R": N / Rs,
                              "hbm_frac": vbytes / tk / 1e9 / HBM_PEAK_GBS}
             log(f"svd R={Rs}: {steps / t_s:.0f} steps/s, contraction {tk * 1e6:.1f} us")
+            s_s.close()
+            s_s = rom_s.state(p.u0)
+            s_s.step(5)
+            checks.add("svd", f"R{Rs}", prob, dict(U=U, sigma=sig, V=V), p.u0[0], 5, s_s.u())
             s_s.close()
             rom_s.close()
         result["svd"] = svd
@@ -361,7 +487,12 @@ def main():
                           "config": "N=1000, CP rank 2000 FP32, SPD stiffness, dense SPD mass matrix, "
                                     "zeroth-mode C1, C2, c0, a0 (FP64)"}
         log(f"full form: {1.0 / t_f:.0f} steps/s ({t_f * 1e6:.2f} us/step; plain {t_p * 1e6:.2f})")
-        for x in (s_f, s_p, rom_f, rom_p):
+        for x in (s_f, s_p):
+            x.close()
+        s_f = rom_f.state(p.u0)
+        s_f.step(200)
+        checks.add("full", "B1", prob, core, p.u0[0], 200, s_f.u(), E_gpu=s_f.energy()[1][:, 0], full=full_terms)
+        for x in (s_f, rom_f, rom_p):
             x.close()
         # 64 trajectories: the terms as one FP64 product X G^T per step
         Bf = 64
@@ -383,7 +514,14 @@ def main():
         result["full"]["B64"] = {"traj_steps_per_s": Bf / t_f, "us_per_step": t_f * 1e6,
                                  "plain_us_per_step": t_p * 1e6}
         log(f"full form B={Bf}: {Bf / t_f:.0f} traj-steps/s ({t_f * 1e6:.2f} us/step; plain {t_p * 1e6:.2f})")
-        for x in (s_f, s_p, rom_f, rom_p):
+        for x in (s_f, s_p):
+            x.close()
+        s_f = rom_f.state(u0b)
+        s_f.step(50)
+        ug = s_f.get()[0][0]
+        for b in (0, Bf - 1):
+            checks.add("full", f"B{Bf}_traj{b}", prob, core, u0b[b], 50, ug[b], full=full_terms)
+        for x in (s_f, rom_f, rom_p):
             x.close()
 
     if not args.no_extra and sec in ("all", "als"):
@@ -405,11 +543,12 @@ def main():
     if not args.no_extra and sec in ("all", "multi"):
         # ---------------- uneven N: grouped launches against the same states one by one
         Ns = (100, 200, 400, 700, 1000)
-        roms, sts = [], []
+        roms, sts, pms = [], [], []
         for i, Nm in enumerate(Ns):
             pm = romsynth.make_problem(Nm, pairs=Nm, eps=1e-7, nu=5e-4, dt=5e-4, A="spd", cfg=40 + i,
                                        dense=False, cp=True)
             rm = rg.Rom.from_problem(pm, dense=False, dtype="fp32", max_batch=1, stream=stream)
+            pms.append(pm)
             roms.append(rm)
             sts.append(rm.state(pm.u0[0]))
         ch, sh = [r.handle for r in roms], [x.handle for x in sts]
@@ -428,6 +567,12 @@ def main():
                            "speedup_grouped": t_sep / t_grp}
         log(f"multi: grouped {len(Ns) * nm / t_grp:.0f}, separate {len(Ns) * nm / t_sep:.0f} traj-steps/s")
         for x in sts:
+            x.close()
+        sts = [rm.state(pm.u0[0]) for rm, pm in zip(roms, pms)]
+        rg.rom_step_multi([r.handle for r in roms], [x.handle for x in sts], 200)
+        for Nm, pm, x in zip(Ns, pms, sts):
+            checks.add("multi", f"N{Nm}", (pm.N, pm.nu, pm.dt, pm.A), dict(lam=pm.lam, Af=pm.Af, Bf=pm.Bf, Cf=pm.Cf),
+                       pm.u0[0], 200, x.u())
             x.close()
         for r in roms:
             r.close()
@@ -451,36 +596,54 @@ def main():
                                       "operator creation")
         srv.close()
 
-    # ---------------- accuracy and CPU baseline (oracle, FP64, one thread)
+    # ---------------- oracle leg (after all GPU timing): accuracy of every section, and the
+    # CPU baseline (the FP64 oracle on the host cores of the GPU machine's share, and on one)
     if not args.no_cpu:
         import oracle as orc
-        t1 = time.perf_counter()
-        orc.run(N, p.nu, p.dt, p.A, 20, u0=p.u0[0], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
-        per = max((time.perf_counter() - t1) / 20, 1e-6)
-        n_cpu = int(max(100, min(20000, args.cpu_seconds / per)))
-        t1 = time.perf_counter()
-        r_cp = orc.run(N, p.nu, p.dt, p.A, n_cpu, u0=p.u0[0], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
-        t_cpu = time.perf_counter() - t1
-        sg = rom_cp.state(p.u0)
-        sg.step(n_cpu)
-        ug = sg.get()[0][0][0]
-        Eg = sg.energy()[1][:, 0]
-        err_cp = float(np.linalg.norm(ug - r_cp["u_hist"][0]) / np.linalg.norm(r_cp["u_hist"][0]))
-        errE_cp = float(np.max(np.abs(Eg - r_cp["E"]) / r_cp["E"]))
-        nd = 3
-        t2 = time.perf_counter()
-        r_d = orc.run(N, p.nu, p.dt, p.A, nd, u0=p.u0[0], C=p.C)
-        t_cpu_d = time.perf_counter() - t2
-        sd = rom_d.state(p.u0)
-        sd.step(nd)
-        err_d = float(np.linalg.norm(sd.get()[0][0][0] - r_d["u_hist"][0]) / np.linalg.norm(r_d["u_hist"][0]))
-        result["rel_err"] = {"cp_traj": err_cp, "cp_energy": errE_cp, "cp_steps": n_cpu,
-                             "dense_traj": err_d, "dense_steps": nd, "tol": 1e-5}
-        result["cpu_baseline"] = {
-            "value": n_cpu / t_cpu, "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_cpu} CP-ROM steps (N=1000, R={R}, FP64, one thread, incl. one-time Cholesky); "
-                      f"dense G-ROM: {nd} steps at {nd / t_cpu_d:.3f} steps/s",
-            "dense_value": nd / t_cpu_d}
+        if sec in ("all", "headline"):
+            orc.set_threads(1)
+            t1 = time.perf_counter()
+            orc.run(N, p.nu, p.dt, p.A, 20, u0=p.u0[0], **ops_cp)
+            per = max((time.perf_counter() - t1) / 20, 1e-6)
+            n_cpu = int(max(100, min(20000, args.cpu_seconds / per)))
+            log(f"oracle CPU baseline: {n_cpu} CP steps, one thread and {ORC_THREADS}")
+            t1 = time.perf_counter()
+            r1 = orc.run(N, p.nu, p.dt, p.A, n_cpu, u0=p.u0[0], **ops_cp)
+            t_one = time.perf_counter() - t1
+            with orc.threads(ORC_THREADS):
+                t1 = time.perf_counter()
+                rm_ = orc.run(N, p.nu, p.dt, p.A, n_cpu, u0=p.u0[0], **ops_cp)
+                t_all = time.perf_counter() - t1
+            assert np.array_equal(r1["u_hist"], rm_["u_hist"])
+            nd = 3
+            t2 = time.perf_counter()
+            orc.run(N, p.nu, p.dt, p.A, nd, u0=p.u0[0], C=p.C)
+            t_d1 = time.perf_counter() - t2
+            with orc.threads(ORC_THREADS):
+                t2 = time.perf_counter()
+                orc.run(N, p.nu, p.dt, p.A, nd, u0=p.u0[0], C=p.C)
+                t_dm = time.perf_counter() - t2
+            rom_chk = make(False)
+            sg = rom_chk.state(p.u0)
+            sg.step(n_cpu)
+            checks.add("headline", "cp", prob, ops_cp, p.u0[0], n_cpu, sg.u(), E_gpu=sg.energy()[1][:, 0], dtype=dt)
+            sg.close()
+            rom_chk.close()
+            result["cpu_baseline"] = {
+                "value": n_cpu / t_all, "unit": "trajectory-steps/s", "cores": ORC_THREADS, "kind": "oracle",
+                "sample": f"{n_cpu} CP-ROM steps (N=1000, R={R}, FP64, incl. its one-time Cholesky) on "
+                          f"{ORC_THREADS} host threads (row loops; results identical to one thread); dense G-ROM: "
+                          f"{nd} steps",
+                "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
+                "single_thread_value": n_cpu / t_one,
+                "dense_value": nd / t_dm, "dense_single_thread_value": nd / t_d1}
+        errs = run_checks(checks, orc, log)
+        worst = {}
+        for secname, entries in errs.items():
+            tgt = result.setdefault(secname, {}) if secname != "headline" else result
+            tgt.setdefault("rel_err", {}).update(entries)
+            worst[secname] = max(v["traj"] / v["tol"] for v in entries.values())
+        result["rel_err_worst_over_tol"] = worst
     print(json.dumps(result), flush=True)
 
 

@@ -54,6 +54,9 @@ def _load():
     lib.orc_run.argtypes = [_i64, ctypes.c_double, ctypes.c_double, _d, _d, _i64, _d, _d, _d,
                             _d, _i64, _d, _d, _i64, _d, _d, ctypes.POINTER(_i64)]
     lib.orc_run.restype = ctypes.c_int
+    lib.orc_run_svd.argtypes = [_i64, ctypes.c_double, ctypes.c_double, _d, _i64, _d, _d, _d, _i64, _d, _d,
+                                _i64, _d, _d, ctypes.POINTER(_i64)]
+    lib.orc_run_svd.restype = ctypes.c_int
     lib.orc_explicit_full.argtypes = [_i64, _d, _i64, _d, _d, _d, _d, _d, _d, _d, _d, _d]
     lib.orc_run_full.argtypes = [_i64, ctypes.c_double, ctypes.c_double, _d, _d, _d, _i64, _d, _d,
                                  _d, _d, _d, _d, _d, _d, _i64, _d, _d, _i64, _d, _d,
@@ -232,11 +235,13 @@ def explicit_full(u, *, C=None, lam=None, Af=None, Bf=None, Cf=None, C1=None, C2
 
 
 def run(N, nu, dt, A, nsteps, *, u0=None, C=None, lam=None, Af=None, Bf=None, Cf=None,
-        M=None, C1=None, C2=None, c0=None, a0=None,
+        M=None, C1=None, C2=None, c0=None, a0=None, U=None, sigma=None, V=None,
         step0: int = 0, uh=None, yh=None, traj: bool = False) -> dict:
     """Integrate one trajectory for nsteps BDF3/EXT3 steps (with the BDF1/BDF2 ramp).
 
     Either u0 (start at step 0) or the history (step0, uh [3][N], yh [2][N]) is given.
+    The advection term is the dense tensor C, the CP factors, or the SVD form (U [N][Rs],
+    sigma [Rs], V [N][N][Rs]; identity mass matrix, no zeroth-mode terms).
     M (mass matrix, default the identity) and the zeroth-mode terms C1, C2 [N][N+1],
     c0, a0 [N] (default zero) select the full form of eq. nse_d1.
     Returns dict(u_hist, y_hist, step, E [nsteps+1], traj [nsteps+1][N] or None,
@@ -253,6 +258,12 @@ def run(N, nu, dt, A, nsteps, *, u0=None, C=None, lam=None, Af=None, Bf=None, Cf
     E = np.empty(nsteps + 1)
     T = np.empty((nsteps + 1, N)) if traj else None
     fb = _i64(-1)
+    if U is not None:
+        U, sigma, V = map(_c, (U, sigma, V))
+        st = lib.orc_run_svd(N, float(nu), float(dt), _p(A), U.shape[1], _p(U), _p(sigma), _p(V), int(step0),
+                             _p(uh), _p(yh), int(nsteps), _p(E), _p(T), ctypes.byref(fb))
+        return dict(u_hist=uh, y_hist=yh, step=step0 + nsteps, E=E, traj=T, status=int(st),
+                    first_bad=int(fb.value))
     if C is not None:
         C = np.asarray(C)
         if not (C.dtype == np.float64 and C.flags.c_contiguous):

@@ -278,18 +278,33 @@ static void bdf_ext(int k, double beta[4], double alpha[3])
     }
 }
 
+/* The advection operator of a run: the dense tensor (C), the CP factors (R, lam, Af, Bf,
+ * Cf) or the SVD form of the SVD-ROM (Rs, U, sigma, V), in that order of precedence. */
+typedef struct {
+    const double *C;
+    int64_t R;
+    const double *lam, *Af, *Bf, *Cf;
+    int64_t Rs;
+    const double *U, *sigma, *V;
+} orc_adv;
+
+static void advection(int64_t N, const orc_adv *op, const double *u, double *y)
+{
+    if (op->C)
+        orc_nonlinear_dense(N, op->C, u, y);
+    else if (op->U)
+        orc_nonlinear_svd(N, op->Rs, op->U, op->sigma, op->V, u, y);
+    else
+        orc_nonlinear_cp(N, op->R, op->lam, op->Af, op->Bf, op->Cf, u, y);
+}
+
 /* Explicit term of eq. nse_d1 at one level (Sec. 2.2):
  *   g = C(u)u + (C1 + C2) ubar - c0,   ubar = [1, u_1 .. u_N],
- * with C(u)u the dense contraction if C != NULL, else the CP contraction.  C1, C2, c0
- * are each optional (NULL: zero). */
-void orc_explicit_full(int64_t N, const double *C, int64_t R, const double *lam, const double *Af,
-                       const double *Bf, const double *Cf, const double *C1, const double *C2,
-                       const double *c0, const double *u, double *g)
+ * C1, C2, c0 each optional (NULL: zero). */
+static void explicit_full(int64_t N, const orc_adv *op, const double *C1, const double *C2,
+                          const double *c0, const double *u, double *g)
 {
-    if (C)
-        orc_nonlinear_dense(N, C, u, g);
-    else
-        orc_nonlinear_cp(N, R, lam, Af, Bf, Cf, u, g);
+    advection(N, op, u, g);
     for (int64_t i = 0; i < N; ++i) {
         double v = 0.0;
         for (int64_t j = 0; j <= N; ++j) {
@@ -299,6 +314,15 @@ void orc_explicit_full(int64_t N, const double *C, int64_t R, const double *lam,
         }
         g[i] += v - (c0 ? c0[i] : 0.0);
     }
+}
+
+/* The same with C(u)u the dense contraction if C != NULL, else the CP contraction. */
+void orc_explicit_full(int64_t N, const double *C, int64_t R, const double *lam, const double *Af,
+                       const double *Bf, const double *Cf, const double *C1, const double *C2,
+                       const double *c0, const double *u, double *g)
+{
+    const orc_adv op = {C, R, lam, Af, Bf, Cf, 0, NULL, NULL, NULL};
+    explicit_full(N, &op, C1, C2, c0, u, g);
 }
 
 /* Time integration of  M du/dt = -C(ubar)ubar - nu A ubar  (eq. nse_ode; M = I and no
@@ -318,11 +342,10 @@ void orc_explicit_full(int64_t N, const double *C, int64_t R, const double *lam,
  * traj[(s)][N] = u^{n+s}.
  * Returns 0 ok, 1 if a Helmholtz matrix is not SPD, 2 on allocation failure,
  * 4 if a state became non-finite (first_bad = that step index, integration stops). */
-int orc_run_full(int64_t N, double nu, double dt, const double *A, const double *M,
-                 const double *C, int64_t R, const double *lam, const double *Af,
-                 const double *Bf, const double *Cf, const double *C1, const double *C2,
-                 const double *c0, const double *a0, int64_t step0, double *uh, double *yh,
-                 int64_t nsteps, double *E, double *traj, int64_t *first_bad)
+static int run_core(int64_t N, double nu, double dt, const double *A, const double *M,
+                    const orc_adv *op, const double *C1, const double *C2,
+                    const double *c0, const double *a0, int64_t step0, double *uh, double *yh,
+                    int64_t nsteps, double *E, double *traj, int64_t *first_bad)
 {
     size_t nn = (size_t)(N * N);
     double *L[3] = {NULL, NULL, NULL};
@@ -365,7 +388,7 @@ int orc_run_full(int64_t N, double nu, double dt, const double *A, const double 
         }
 
         /* g^n (the advection term, plus the zeroth-mode terms when given) */
-        orc_explicit_full(N, C, R, lam, Af, Bf, Cf, C1, C2, c0, uh, y);
+        explicit_full(N, op, C1, C2, c0, uh, y);
 
         /* right-hand side: levels n, n-1, n-2 are uh[0..2] and y, yh[0], yh[1] */
         for (int64_t i = 0; i < N; ++i) {
@@ -419,6 +442,17 @@ done:
     return status;
 }
 
+/* The run with the dense tensor (C != NULL) or the CP factors as the advection term. */
+int orc_run_full(int64_t N, double nu, double dt, const double *A, const double *M,
+                 const double *C, int64_t R, const double *lam, const double *Af,
+                 const double *Bf, const double *Cf, const double *C1, const double *C2,
+                 const double *c0, const double *a0, int64_t step0, double *uh, double *yh,
+                 int64_t nsteps, double *E, double *traj, int64_t *first_bad)
+{
+    const orc_adv op = {C, R, lam, Af, Bf, Cf, 0, NULL, NULL, NULL};
+    return run_core(N, nu, dt, A, M, &op, C1, C2, c0, a0, step0, uh, yh, nsteps, E, traj, first_bad);
+}
+
 /* orc_run_full with the identity mass matrix and no zeroth-mode terms. */
 int orc_run(int64_t N, double nu, double dt, const double *A, const double *C, int64_t R,
             const double *lam, const double *Af, const double *Bf, const double *Cf,
@@ -427,6 +461,17 @@ int orc_run(int64_t N, double nu, double dt, const double *A, const double *C, i
 {
     return orc_run_full(N, nu, dt, A, NULL, C, R, lam, Af, Bf, Cf, NULL, NULL, NULL, NULL, step0, uh,
                         yh, nsteps, E, traj, first_bad);
+}
+
+/* orc_run with the SVD form of the SVD-ROM (Sec. 4.4, orc_nonlinear_svd) as the advection
+ * term: U [N][Rs], sigma [Rs], V [N][N][Rs]. */
+int orc_run_svd(int64_t N, double nu, double dt, const double *A, int64_t Rs, const double *U,
+                const double *sigma, const double *V, int64_t step0, double *uh, double *yh,
+                int64_t nsteps, double *E, double *traj, int64_t *first_bad)
+{
+    const orc_adv op = {NULL, 0, NULL, NULL, NULL, NULL, Rs, U, sigma, V};
+    return run_core(N, nu, dt, A, NULL, &op, NULL, NULL, NULL, NULL, step0, uh, yh, nsteps, E, traj,
+                    first_bad);
 }
 
 /* ------------------------------------------------------------------ storage rounding */

@@ -505,3 +505,47 @@ def test_als_residual_never_grows(orc):
     _, res = orc.als.cp_als(X, *F0, 40)
     assert all(b <= a * (1 + 1e-12) for a, b in zip(res, res[1:]))
     assert res[-1] < 0.5 * min(r0, 1.0)
+
+
+def test_run_svd_form_equals_reconstructed_dense(orc):
+    """The stepper with the SVD form (Sec. 4.4) as its advection term follows the stepper
+    with the dense tensor that form reconstructs, C[i][j][k] = sum_r U[j][r] s_r V[i][k][r]."""
+    N, R = 12, 5
+    rng = np.random.default_rng(7)
+    U = rng.standard_normal((N, R)) / np.sqrt(N)
+    sig = 1.0 / (1.0 + np.arange(R))
+    V = rng.standard_normal((N, N, R)) / N
+    T = np.einsum("jr,r,ikr->ijk", U, sig, V)
+    A = romsynth.stiffness_spd(N, 1, cfg=9)
+    u0 = romsynth.initial_u(N, [2], cfg=9)[0]
+    a = orc.run(N, 1e-2, 1e-2, A, 30, u0=u0, U=U, sigma=sig, V=V, traj=True)
+    b = orc.run(N, 1e-2, 1e-2, A, 30, u0=u0, C=T, traj=True)
+    assert a["status"] == b["status"] == 0
+    assert np.max(np.abs(a["traj"] - b["traj"])) <= 1e-13 * np.max(np.abs(b["traj"]))
+    assert np.max(np.abs(a["E"] - b["E"]) / b["E"]) <= 1e-13
+
+
+def test_threads_give_identical_results(orc):
+    """The oracle's row loops on several host threads give the one-thread results to the
+    bit (dense, CP, SVD forms; evaluations and runs)."""
+    N, pairs = 40, 12
+    C = romsynth.dense_from_skew_cp(N, pairs, 1e-6, seed=1, cfg=8)
+    lam, Af, Bf, Cf = romsynth.skew_cp_factors(N, pairs, seed=1, cfg=8)
+    rng = np.random.default_rng(8)
+    U = rng.standard_normal((N, 6))
+    sig = np.ones(6)
+    V = rng.standard_normal((N, N, 6)) / N
+    A = romsynth.stiffness_spd(N, 2, cfg=8)
+    u0 = romsynth.initial_u(N, [1], cfg=8)[0]
+    kinds = [dict(C=C), dict(lam=lam, Af=Af, Bf=Bf, Cf=Cf), dict(U=U, sigma=sig, V=V)]
+    one = [orc.run(N, 1e-3, 1e-3, A, 25, u0=u0, traj=True, **k) for k in kinds]
+    ev1 = [orc.nonlinear_dense(C, u0), orc.nonlinear_cp(lam, Af, Bf, Cf, u0), orc.nonlinear_svd(U, sig, V, u0)]
+    with orc.threads(4):
+        assert orc.get_threads() == 4
+        many = [orc.run(N, 1e-3, 1e-3, A, 25, u0=u0, traj=True, **k) for k in kinds]
+        ev4 = [orc.nonlinear_dense(C, u0), orc.nonlinear_cp(lam, Af, Bf, Cf, u0), orc.nonlinear_svd(U, sig, V, u0)]
+    assert orc.get_threads() == 1
+    for a, b in zip(one, many):
+        assert np.array_equal(a["traj"], b["traj"]) and np.array_equal(a["E"], b["E"])
+    for a, b in zip(ev1, ev4):
+        assert np.array_equal(a, b)
