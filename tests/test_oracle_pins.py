@@ -549,3 +549,75 @@ def test_threads_give_identical_results(orc):
         assert np.array_equal(a["traj"], b["traj"]) and np.array_equal(a["E"], b["E"])
     for a, b in zip(ev1, ev4):
         assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ ALS-skew (Sec. 3.3)
+
+def _skew_problem(N, P, seed, noise):
+    rng = np.random.default_rng(seed)
+    a, c, b = (rng.standard_normal((N, P)) for _ in range(3))
+    from oracle import als
+    X = np.einsum("ir,jr,kr->ijk", *als.skew_factors(a, c, b))
+    if noise:
+        G = rng.standard_normal((N, N, N))
+        X = X + noise * 0.5 * (G - G.transpose(2, 1, 0))
+    return X, (a, c, b), rng
+
+
+def test_als_skew_structure_and_fixed_point(orc):
+    """Sec. 3.3, eq. skew_abc_struct: the structured factors give a tensor skew in positions
+    1 and 3, and exact structured factors are a fixed point of ALS-skew (with a planted
+    sign error in the third factor the fixed point is lost)."""
+    X, (a, c, b), _ = _skew_problem(11, 3, 1, 0.0)
+    assert np.max(np.abs(X + X.transpose(2, 1, 0))) <= 1e-13 * np.max(np.abs(X))
+    (A11, A12, B1), res = orc.als.als_skew(X, a, c, b, sweeps=3, subiters=2)
+    assert max(res) < 1e-12
+    for u, v in ((A11, a), (A12, c), (B1, b)):
+        assert np.max(np.abs(u - v)) <= 1e-10 * np.max(np.abs(v))
+    Xbad = np.einsum("ir,jr,kr->ijk", np.hstack([a, c]), np.hstack([b, b]), np.hstack([c, a]))
+    assert np.max(np.abs(Xbad + Xbad.transpose(2, 1, 0))) > 1e-3 * np.max(np.abs(Xbad))
+
+
+def test_als_skew_updates_are_least_squares(orc):
+    """Each ALS-skew update solves its linear least-squares problem (numpy's lstsq on the
+    unfolded system): the tied second factor B1 over the P columns of vec(a_p c_p^T -
+    c_p a_p^T), and the subiteration's first factor over the Khatri-Rao columns with the
+    third factor held fixed (eq. cp_als_quad).  For a skew tensor the untied ALS update of
+    the second factor has equal halves, i.e. equals the tied one."""
+    N, P = 9, 3
+    X, _, rng = _skew_problem(N, P, 2, 0.3)
+    a, c, b = (rng.standard_normal((N, P)) for _ in range(3))
+    als = orc.als
+    # tied second factor
+    (_, _, B1), _ = als.als_skew(X, a, c, b, sweeps=1, subiters=0)
+    Z = (np.einsum("ip,kp->ikp", a, c) - np.einsum("ip,kp->ikp", c, a)).reshape(N * N, P)
+    X2 = X.transpose(1, 0, 2).reshape(N, N * N)                       # rows j, columns (i, k)
+    B1_ls = np.linalg.lstsq(Z, X2.T, rcond=None)[0].T
+    assert np.max(np.abs(B1 - B1_ls)) <= 1e-10 * np.max(np.abs(B1_ls))
+    F = als.skew_factors(a, c, b)
+    A2u = np.linalg.solve(als.normal_matrix(F, 1), als.mttkrp(X, F, 1).T).T
+    assert np.max(np.abs(A2u[:, :P] - A2u[:, P:])) <= 1e-10 * np.max(np.abs(A2u))
+    assert np.max(np.abs(A2u[:, :P] - B1_ls)) <= 1e-10 * np.max(np.abs(B1_ls))
+    # one subiteration without momentum: the least-squares first factor with A3 fixed
+    (A11, A12, B1b), _ = als.als_skew(X, a, c, b, sweeps=1, subiters=1, momentum=0.0)
+    F = als.skew_factors(a, c, B1b)
+    KR = np.einsum("jr,kr->jkr", F[1], F[2]).reshape(N * N, 2 * P)    # rows (j, k)
+    A1_ls = np.linalg.lstsq(KR, X.reshape(N, N * N).T, rcond=None)[0].T
+    assert np.max(np.abs(np.hstack([A11, A12]) - A1_ls)) <= 1e-9 * np.max(np.abs(A1_ls))
+    # with momentum m the new first factor lies between the old one and that solution
+    (A11m, A12m, _), _ = als.als_skew(X, a, c, b, sweeps=1, subiters=1, momentum=0.25)
+    assert np.allclose(np.hstack([A11m, A12m]), 0.25 * np.hstack([a, c]) + 0.75 * A1_ls, rtol=0, atol=1e-9)
+
+
+def test_als_skew_fit_residual(orc):
+    """From a random start on a noisy rank-6 skew tensor (3 pairs): the residual of eq.
+    cp_nls does not grow from sweep to sweep (seeded case) and reaches the noise level; the
+    fitted Kruskal tensor stays skew in positions 1 and 3."""
+    N, P = 14, 3
+    X, _, rng = _skew_problem(N, P, 3, 1e-3)
+    init = [rng.standard_normal((N, P)) for _ in range(3)]
+    (A11, A12, B1), res = orc.als.als_skew(X, *init, sweeps=60, subiters=3)
+    assert all(r1 <= r0 * (1 + 1e-12) for r0, r1 in zip(res, res[1:])), res
+    assert res[-1] < 1e-2
+    T = np.einsum("ir,jr,kr->ijk", *orc.als.skew_factors(A11, A12, B1))
+    assert np.max(np.abs(T + T.transpose(2, 1, 0))) <= 1e-12 * np.max(np.abs(T))
