@@ -28,7 +28,8 @@ Also in the one JSON line:
                 N/R = 10 and 4), FP32, one trajectory: steps/s and the streaming bandwidth
   full          the full form of the reduced system (dense SPD mass matrix, zeroth-mode
                 terms) at the headline size, CP rank 2000 FP32, against the plain step
-  als           CP-ALS sweeps (rom_cp_als) at N = 200, R = 400, FP64: ms per sweep
+  als           CP-ALS sweeps (rom_cp_als) at N = 200, R = 400, FP64: ms per sweep; ALS-skew
+                (rom_cp_als_skew) with 200 column pairs and 3 subiterations
   multi         uneven N: one CP trajectory each at N = 100, 200, 400, 700, 1000 stepped
                 together by grouped launches (rom_step_multi) and one after the other
   serving       a bounded Poisson request stream through the continuous-batching loop
@@ -149,6 +150,11 @@ class Checks:
 
     def __init__(self):
         self.items = []
+        self.fns = []
+
+    def add_fn(self, section, fn):
+        """A check the oracle leg evaluates by calling fn(oracle) -> {label: errors}."""
+        self.fns.append((section, fn))
 
     def add(self, section, label, prob, ops, u0, nsteps, u_gpu, E_gpu=None, full=None, dtype="fp32"):
         self.items.append(dict(section=section, label=label, N=prob[0], nu=prob[1], dt=prob[2], A=prob[3],
@@ -181,6 +187,8 @@ def run_checks(checks, orc, log):
         if c["E_gpu"] is not None:
             e["energy"] = float(np.max(np.abs(c["E_gpu"] - r["E"]) / r["E"]))
         out.setdefault(c["section"], {})[c["label"]] = e
+    for section, fn in checks.fns:
+        out.setdefault(section, {}).update(fn(orc))
     return out
 
 
@@ -294,7 +302,7 @@ def main():
             for m in marks:
                 st.step(m - done)
                 done = m
-                out.append(st.u().copy())
+                out.append(st.u()[0].copy())
             st.close()
             return np.stack(out)
 
@@ -538,7 +546,39 @@ def main():
         result["als"] = {"N": Na, "R": Ra, "ms_per_sweep": t_als * 1e3,
                          "mttkrp_flops_per_sweep": fl, "sweep_tflops": fl / t_als / 1e12}
         log(f"cp-als N={Na} R={Ra}: {t_als * 1e3:.2f} ms per sweep")
-        del Xd, Fd
+        # ALS-skew at the same size: P = 200 column pairs (R = 400), 3 subiterations per
+        # sweep (one tied solve and three momentum subiterations), on a skew tensor
+        Pa, sub = Ra // 2, 3
+        Xs = Xd - Xd.permute(2, 1, 0)
+        Fs = [torch.tensor(rng.standard_normal((Na, Pa)), dtype=torch.float64, device=dev) for _ in range(3)]
+        rg.rom_cp_als_skew(Na, Pa, Xs, *Fs, 1, sub, stream=stream)
+        t_sk = timer(lambda: rg.rom_cp_als_skew(Na, Pa, Xs, *Fs, nsw, sub, stream=stream)) / nsw
+        fl_sk = (1 + sub - 1) * 2.0 * Na ** 3 * Ra
+        result["als"]["skew"] = {"P": Pa, "subiters": sub, "momentum": 0.5, "ms_per_sweep": t_sk * 1e3,
+                                 "tensor_product_flops_per_sweep": fl_sk}
+        log(f"als-skew N={Na} P={Pa} subiters={sub}: {t_sk * 1e3:.2f} ms per sweep")
+        del Xd, Fd, Xs, Fs
+        # accuracy (oracle leg): 2 sweeps of each at N = 40, R = 24 from seeded factors
+        rng = np.random.default_rng(4)
+        Xc = rng.standard_normal((40, 40, 40))
+        Xc = Xc - Xc.transpose(2, 1, 0)
+        F0 = [rng.standard_normal((40, 24)) for _ in range(3)]
+        S0 = [rng.standard_normal((40, 12)) for _ in range(3)]
+        Xcd = torch.tensor(Xc, dtype=torch.float64, device=dev)
+        Fg = [torch.tensor(a, dtype=torch.float64, device=dev) for a in F0]
+        Sg = [torch.tensor(a, dtype=torch.float64, device=dev) for a in S0]
+        rg.rom_cp_als(40, 24, Xcd, *Fg, 2, stream=stream)
+        rg.rom_cp_als_skew(40, 12, Xcd, *Sg, 2, sub, stream=stream)
+        Fg = [a.cpu().numpy() for a in Fg]
+        Sg = [a.cpu().numpy() for a in Sg]
+
+        def als_err(orc, X=Xc, F0=F0, S0=S0, Fg=Fg, Sg=Sg):
+            F, _ = orc.als.cp_als(X, *F0, 2)
+            Fs_, _ = orc.als.als_skew(X, *S0, sweeps=2, subiters=sub)
+            rel = lambda G, R_: max(float(np.max(np.abs(g - r)) / np.max(np.abs(r))) for g, r in zip(G, R_))
+            return {"cp_als_N40_R24_2sweeps": {"factors": rel(Fg, F), "tol": 1e-8},
+                    "als_skew_N40_P12_2sweeps": {"factors": rel(Sg, Fs_), "tol": 1e-8}}
+        checks.add_fn("als", als_err)
 
     if not args.no_extra and sec in ("all", "multi"):
         # ---------------- uneven N: grouped launches against the same states one by one
@@ -642,7 +682,7 @@ def main():
         for secname, entries in errs.items():
             tgt = result.setdefault(secname, {}) if secname != "headline" else result
             tgt.setdefault("rel_err", {}).update(entries)
-            worst[secname] = max(v["traj"] / v["tol"] for v in entries.values())
+            worst[secname] = max(v.get("traj", v.get("factors", 0.0)) / v["tol"] for v in entries.values())
         result["rel_err_worst_over_tol"] = worst
     print(json.dumps(result), flush=True)
 

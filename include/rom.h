@@ -153,6 +153,26 @@ void rom_destroy(rom_ctx ctx);
 rom_status rom_cp_als(int32_t N, int32_t R, const double *C, double *A1, double *A2, double *A3,
                       int32_t sweeps, void *stream);
 
+/* ALS-skew (Sec. 3.3, eqs. skew_abc_struct and cp_als_quad): `sweeps` sweeps fitting the
+ * skew-symmetry preserving CP structure with P column pairs (rank R = 2P, weights one)
+ *   A1 = [A11 A12],  A2 = [B1 B1],  A3 = [A12 -A11]
+ * to a dense tensor (for a tensor skew in positions 1 and 3, C[i][j][k] = -C[k][j][i]).
+ * Each sweep updates B1 by least squares with the two halves of A2 tied (the ALS update
+ * of the second factor), then runs `subiters` subiterations on the first factor: the
+ * least-squares solution A1_next with A3 held fixed, the momentum update
+ * A1 <- momentum A1 + (1 - momentum) A1_next, and A3 tied again.  The paper fixes neither
+ * the momentum nor the subiteration count (1/2 averages as the Babylonian square-root
+ * iteration the paper cites does).  Normal equations as in rom_cp_als, FP64 on the device.
+ *   C             device FP64 [N][N][N] (as rom_cp_als); read only.
+ *   A11, A12, B1  device FP64 [N][P]: the initial blocks on entry, the fitted ones on return.
+ *   stream        as rom_cp_als.  Synchronizes; allocates and frees its own workspace
+ *                 (about N^3 + 2 N^2 P doubles).
+ * Errors: ROM_E_INVALID (N outside [1, 4096], P outside [1, 2048], sweeps or subiters < 0,
+ * momentum outside [0, 1), NULL pointers, or a normal matrix that is not positive
+ * definite), ROM_E_NOMEM, ROM_E_DEVICE.  sweeps = 0 does nothing. */
+rom_status rom_cp_als_skew(int32_t N, int32_t P, const double *C, double *A11, double *A12, double *B1,
+                           int32_t sweeps, int32_t subiters, double momentum, void *stream);
+
 /* y = C(u)u for `batch` coefficient vectors (Sec. 2.2, eq. Cu; CP form: eq. tc_ap).
  * u_dev, y_dev: device FP64 [batch][N], caller-owned; 1 <= batch <= max_batch.
  * The contraction runs in the context's dtype; y is returned in FP64.  Asynchronous. */

@@ -26,7 +26,7 @@ EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_noalloc"
            "rom_state_destroy",
            "rom_step", "rom_step_async", "rom_step_sync", "rom_step_prepare", "rom_energy", "rom_state_get",
            "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
-           "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_create_full", "rom_cp_als",
+           "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_create_full", "rom_cp_als", "rom_cp_als_skew",
            "rom_last_error"]
 
 _d = ctypes.POINTER(ctypes.c_double)
@@ -106,6 +106,9 @@ def lib():
     L.rom_create_full.restype = ctypes.c_int
     L.rom_cp_als.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp]
     L.rom_cp_als.restype = ctypes.c_int
+    L.rom_cp_als_skew.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_double, _vp]
+    L.rom_cp_als_skew.restype = ctypes.c_int
     L.rom_cp_skew_layout.restype = ctypes.c_int32
     L.rom_last_error.argtypes = []
     L.rom_last_error.restype = ctypes.c_char_p
@@ -195,6 +198,13 @@ def rom_cp_als(N, R, C_dev, A1_dev, A2_dev, A3_dev, sweeps, stream=None):
     """CP-ALS sweeps on device FP64 tensors (C [N][N][N], factors [N][R], updated in place)."""
     _check(lib().rom_cp_als(int(N), int(R), _dev_ptr(C_dev), _dev_ptr(A1_dev), _dev_ptr(A2_dev),
                             _dev_ptr(A3_dev), int(sweeps), _stream_handle(stream)))
+
+
+def rom_cp_als_skew(N, P, C_dev, A11_dev, A12_dev, B1_dev, sweeps, subiters, momentum=0.5, stream=None):
+    """ALS-skew sweeps on device FP64 tensors (C [N][N][N]; blocks [N][P], updated in place)."""
+    _check(lib().rom_cp_als_skew(int(N), int(P), _dev_ptr(C_dev), _dev_ptr(A11_dev), _dev_ptr(A12_dev),
+                                 _dev_ptr(B1_dev), int(sweeps), int(subiters), float(momentum),
+                                 _stream_handle(stream)))
 
 
 def rom_destroy(ctx: int):

@@ -14,6 +14,17 @@ void launch_als_reduce(int N, int R, int keep_first, const double* T, const doub
                        hipStream_t s);
 // V[r][s] = (Fa^T Fa)[r][s] * (Fb^T Fb)[r][s], [R][R], factors [N][R].
 void launch_gram_hadamard(int N, int R, const double* Fa, const double* Fb, double* V, hipStream_t s);
+// ALS-skew (Sec. 3.3): A1 = [A11 A12], A2 = [B1 B1], A3 = [A12 -A11] ([N][2P]) from the
+// blocks [N][P]; the tied normal equations Vt = S^T V S [P][P], Mt = M S (S = [I; I]); B1
+// and A2 from the tied solve Y; the momentum update of A1 from the subiteration's solution
+// Y, with the blocks and A3 tied again.
+void launch_skew_assemble(int N, int P, const double* A11, const double* A12, const double* B1, double* A1,
+                          double* A2, double* A3, hipStream_t s);
+void launch_skew_tie(int N, int P, const double* V, double* Vt, const double* M, int ldm, double* Mt, int ldt,
+                     hipStream_t s);
+void launch_skew_set_b(int N, int P, const double* Y, int ldy, double* B1, double* A2, hipStream_t s);
+void launch_skew_momentum(int N, int P, double mom, const double* Y, int ldy, double* A1, double* A3, double* A11,
+                          double* A12, hipStream_t s);
 // Hinv [n][np] = H^{-1} for SPD H [n][n] by Cholesky (L), the inverse factor (X) and its
 // Gram product; columns past n of Hinv are left as they are.  *info becomes 1 if a pivot
 // is not positive.

@@ -92,4 +92,97 @@ void launch_gram_hadamard(int N, int R, const double* Fa, const double* Fb, doub
     hipLaunchKernelGGL(k_gram_hadamard, dim3((R + 255) / 256, R), dim3(256), 0, s, N, R, Fa, Fb, V);
 }
 
+// ---------------------------------------------------------------- ALS-skew (Sec. 3.3)
+//
+// Factors of the skew-symmetry preserving structure (eq. skew_abc_struct) with P column
+// pairs, R = 2P: A1 = [A11 A12], A2 = [B1 B1], A3 = [A12 -A11], each [N][R].
+
+// The three full factors from the blocks A11, A12, B1 [N][P].
+__global__ void k_skew_assemble(int N, int P, const double* __restrict__ A11, const double* __restrict__ A12,
+                                const double* __restrict__ B1, double* __restrict__ A1, double* __restrict__ A2,
+                                double* __restrict__ A3) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)N * P) return;
+    const int i = (int)(q / P), p = (int)(q % P);
+    const size_t o = (size_t)i * 2 * P;
+    const double a = A11[q], c = A12[q], b = B1[q];
+    A1[o + p] = a;
+    A1[o + P + p] = c;
+    A2[o + p] = b;
+    A2[o + P + p] = b;
+    A3[o + p] = c;
+    A3[o + P + p] = -a;
+}
+
+void launch_skew_assemble(int N, int P, const double* A11, const double* A12, const double* B1, double* A1,
+                          double* A2, double* A3, hipStream_t s) {
+    const long long n = (long long)N * P;
+    hipLaunchKernelGGL(k_skew_assemble, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, P, A11, A12, B1, A1,
+                       A2, A3);
+}
+
+// The normal equations of the tied second factor A2 = B1 S, S = [I; I]:
+// Vt = S^T V S [P][P] from V [R][R], and Mt = M S [npad][ldt] from M [N][ldm].
+__global__ void k_skew_tie(int N, int P, const double* __restrict__ V, double* __restrict__ Vt,
+                           const double* __restrict__ M, int ldm, double* __restrict__ Mt, int ldt) {
+    const int row = blockIdx.y, p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int R = 2 * P;
+    if (row < P) {
+        const double* v0 = V + (size_t)row * R;
+        const double* v1 = V + (size_t)(P + row) * R;
+        Vt[(size_t)row * P + p] = (v0[p] + v0[P + p]) + (v1[p] + v1[P + p]);
+    }
+    if (row < N) Mt[(size_t)row * ldt + p] = M[(size_t)row * ldm + p] + M[(size_t)row * ldm + P + p];
+}
+
+void launch_skew_tie(int N, int P, const double* V, double* Vt, const double* M, int ldm, double* Mt, int ldt,
+                     hipStream_t s) {
+    const int rows = N > P ? N : P;
+    hipLaunchKernelGGL(k_skew_tie, dim3((P + 255) / 256, rows), dim3(256), 0, s, N, P, V, Vt, M, ldm, Mt, ldt);
+}
+
+// B1 from the tied solve Y [..][ldy] (first P columns), and A2 = [B1 B1].
+__global__ void k_skew_set_b(int N, int P, const double* __restrict__ Y, int ldy, double* __restrict__ B1,
+                             double* __restrict__ A2) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)N * P) return;
+    const int i = (int)(q / P), p = (int)(q % P);
+    const double b = Y[(size_t)i * ldy + p];
+    B1[q] = b;
+    A2[(size_t)i * 2 * P + p] = b;
+    A2[(size_t)i * 2 * P + P + p] = b;
+}
+
+void launch_skew_set_b(int N, int P, const double* Y, int ldy, double* B1, double* A2, hipStream_t s) {
+    const long long n = (long long)N * P;
+    hipLaunchKernelGGL(k_skew_set_b, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, P, Y, ldy, B1, A2);
+}
+
+// Momentum update of the first factor from the subiteration's solution Y [..][ldy]:
+// A1 <- mom A1 + (1 - mom) Y, the blocks A11, A12 written out, and A3 = [A12 -A11].
+__global__ void k_skew_momentum(int N, int P, double mom, const double* __restrict__ Y, int ldy,
+                                double* __restrict__ A1, double* __restrict__ A3, double* __restrict__ A11,
+                                double* __restrict__ A12) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)N * P) return;
+    const int i = (int)(q / P), p = (int)(q % P);
+    const size_t o = (size_t)i * 2 * P;
+    const double a = mom * A1[o + p] + (1.0 - mom) * Y[(size_t)i * ldy + p];
+    const double c = mom * A1[o + P + p] + (1.0 - mom) * Y[(size_t)i * ldy + P + p];
+    A1[o + p] = a;
+    A1[o + P + p] = c;
+    A3[o + p] = c;
+    A3[o + P + p] = -a;
+    A11[q] = a;
+    A12[q] = c;
+}
+
+void launch_skew_momentum(int N, int P, double mom, const double* Y, int ldy, double* A1, double* A3, double* A11,
+                          double* A12, hipStream_t s) {
+    const long long n = (long long)N * P;
+    hipLaunchKernelGGL(k_skew_momentum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, P, mom, Y, ldy, A1, A3,
+                       A11, A12);
+}
+
 }  // namespace rom

@@ -229,6 +229,142 @@ __global__ __launch_bounds__(256) void k_chol_col(int N, int j, const double* __
     }
 }
 
+// Blocked right-looking Cholesky of an SPD matrix in place: L starts as (the lower
+// triangle of) H and ends as its factor, H = L L^T.  Panel after panel of kCholNb
+// columns: k_chol_panel factors the panel's diagonal block (already updated by the panels
+// before) in LDS and solves the rows below it, L21 = A21 L11^{-T}; k_chol_update subtracts
+// L21 L21^T from the trailing lower triangle.  Only the lower triangle is read or written.
+constexpr int kCholNb = 32;
+constexpr int kCholRows = 256;          // panel rows solved per block (one per thread)
+
+__global__ void k_tril_copy(int n, const double* __restrict__ H, double* __restrict__ L) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long long)n * n) return;
+    const int i = (int)(q / n), m = (int)(q % n);
+    if (m <= i) L[q] = H[q];
+}
+
+// Load the diagonal block of panel j0 (b x b, already updated by the panels before) into
+// D and factor it there (whole block); `report` raises *info on a non-positive pivot.
+__device__ void chol_diag_block(int n, int j0, int b, const double* __restrict__ L, double (*D)[kCholNb + 1],
+                                int* info, bool report) {
+    const int t = threadIdx.x;
+    for (int q = t; q < b * b; q += blockDim.x) {
+        const int r = q / b, c = q % b;
+        D[r][c] = c <= r ? L[(size_t)(j0 + r) * n + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    // column c, then the rank-1 update of the columns after it
+    for (int c = 0; c < b; ++c) {
+        const double piv = D[c][c];
+        __syncthreads();
+        const double dcc = sqrt(piv);
+        if (t == 0 && report && !(piv > 0.0)) atomicMax(info, 1);
+        for (int r = c + 1 + t; r < b; r += blockDim.x) D[r][c] /= dcc;
+        __syncthreads();
+        if (t == 0) D[c][c] = dcc;
+        for (int q = t; q < b * b; q += blockDim.x) {
+            const int r = q / b, s2 = q % b;
+            if (s2 > c && s2 <= r) D[r][s2] -= D[r][c] * D[s2][c];
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void chol_store_diag(int n, int j0, int b, double* __restrict__ L, const double (*D)[kCholNb + 1]) {
+    for (int q = threadIdx.x; q < b * b; q += blockDim.x) {
+        const int r = q / b, c = q % b;
+        if (c <= r) L[(size_t)(j0 + r) * n + j0 + c] = D[r][c];
+    }
+}
+
+// Panel j0: every block factors the diagonal block for itself (none writes it: other
+// blocks may still be reading it) and solves its rows below it, x L11^T = a, by forward
+// substitution, one row per thread.  With no rows below (one block) it stores the factor.
+__global__ __launch_bounds__(256) void k_chol_panel(int n, int j0, double* __restrict__ L, int* info) {
+    __shared__ double D[kCholNb][kCholNb + 1];
+    const int b = n - j0 < kCholNb ? n - j0 : kCholNb;
+    const int t = threadIdx.x;
+    chol_diag_block(n, j0, b, L, D, info, blockIdx.x == 0);
+    if (n - j0 - b == 0) {
+        chol_store_diag(n, j0, b, L, D);
+        return;
+    }
+    const int i = j0 + b + blockIdx.x * kCholRows + t;
+    if (t < kCholRows && i < n) {
+        double x[kCholNb];
+        double* row = L + (size_t)i * n + j0;
+#pragma unroll
+        for (int c = 0; c < kCholNb; ++c)
+            if (c < b) x[c] = row[c];
+#pragma unroll
+        for (int c = 0; c < kCholNb; ++c) {
+            if (c < b) {
+                double v = x[c];
+#pragma unroll
+                for (int m = 0; m < kCholNb; ++m)
+                    if (m < c) v -= x[m] * D[c][m];
+                x[c] = v / D[c][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kCholNb; ++c)
+            if (c < b) row[c] = x[c];
+    }
+}
+
+// Trailing update of the lower triangle: L[i][k] -= sum_{m < b} L[i][j0 + m] L[k][j0 + m]
+// for j0 + b <= k <= i < n, one 16 x 16 tile per block (tiles on or below the diagonal);
+// one more block factors panel j0's diagonal block again and stores it (the panel kernel,
+// whose blocks all read it, has finished).
+__global__ __launch_bounds__(256) void k_chol_update(int n, int j0, int b, int ntiles, double* __restrict__ L) {
+    __shared__ double Pi[16][kCholNb + 1], Pk[16][kCholNb + 1];
+    const int q = blockIdx.x;
+    if (q == ntiles) {
+        __shared__ double D[kCholNb][kCholNb + 1];
+        chol_diag_block(n, j0, b, L, D, nullptr, false);
+        chol_store_diag(n, j0, b, L, D);
+        return;
+    }
+    // tile (ti, tk), tk <= ti, from the linear block index q = ti (ti + 1) / 2 + tk
+    int ti = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= q) ++ti;
+    while (ti * (ti + 1) / 2 > q) --ti;
+    const int tk = q - ti * (ti + 1) / 2;
+    const int base = j0 + b;
+    const int i0 = base + ti * 16, k0 = base + tk * 16;
+    const int t = threadIdx.x;
+    for (int e = t; e < 16 * kCholNb; e += blockDim.x) {
+        const int r = e / kCholNb, m = e % kCholNb;
+        Pi[r][m] = (i0 + r < n && m < b) ? L[(size_t)(i0 + r) * n + j0 + m] : 0.0;
+        Pk[r][m] = (k0 + r < n && m < b) ? L[(size_t)(k0 + r) * n + j0 + m] : 0.0;
+    }
+    __syncthreads();
+    const int r = t / 16, c = t % 16;
+    const int i = i0 + r, k = k0 + c;
+    if (i < n && k <= i) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < kCholNb; ++m) s += Pi[r][m] * Pk[c][m];
+        L[(size_t)i * n + k] -= s;
+    }
+}
+
+void chol_blocked(int n, const double* H, double* L, int* info, hipStream_t s) {
+    const long long nn = (long long)n * n;
+    hipLaunchKernelGGL(k_tril_copy, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, n, H, L);
+    for (int j0 = 0; j0 < n; j0 += kCholNb) {
+        const int b = n - j0 < kCholNb ? n - j0 : kCholNb;
+        const int below = n - j0 - b;
+        hipLaunchKernelGGL(k_chol_panel, dim3(below > 0 ? (below + kCholRows - 1) / kCholRows : 1), dim3(256), 0, s,
+                           n, j0, L, info);
+        if (below > 0) {
+            const int tiles = (below + 15) / 16, ntiles = tiles * (tiles + 1) / 2;
+            hipLaunchKernelGGL(k_chol_update, dim3(ntiles + 1), dim3(256), 0, s, n, j0, b, ntiles, L);
+        }
+    }
+}
+
 // X = L^{-1} column by column (one wavefront per column c, values kept in LDS):
 //   X_cc = 1/L_cc,  X_rc = -(sum_{c<=m<r} L_rm X_mc) / L_rr  for r > c.
 __global__ __launch_bounds__(64) void k_trinv_col(int N, const double* __restrict__ L,
@@ -280,8 +416,7 @@ int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, c
     for (int k = 0; k < 3; ++k) {
         hipLaunchKernelGGL(k_build_h, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, nu, b0[k] / dt, A_dev, M_dev, H);
         hipMemsetAsync(L, 0, nn * sizeof(double), s);
-        for (int j = 0; j < N; ++j)
-            hipLaunchKernelGGL(k_chol_col, dim3((N - j + 3) / 4), dim3(256), 0, s, N, j, H, L, info_dev);
+        chol_blocked(N, H, L, info_dev, s);
         hipLaunchKernelGGL(k_trinv_col, dim3(N), dim3(64), sizeof(double) * N, s, N, L, X);
         hipLaunchKernelGGL(k_gram, dim3((N + 255) / 256, N), dim3(256), 0, s, N, Np, X,
                            hinv_dev + (size_t)k * N * Np);
@@ -289,11 +424,10 @@ int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, c
     return 0;
 }
 
-// Only the lower triangle of L is written and read (k_chol_col, k_trinv_col), so L needs
+// Only the lower triangle of L is written and read (chol_blocked, k_trinv_col), so L needs
 // no clearing and the sequence can be captured into a graph.
 void spd_inverse(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s) {
-    for (int j = 0; j < n; ++j)
-        hipLaunchKernelGGL(k_chol_col, dim3((n - j + 3) / 4), dim3(256), 0, s, n, j, H, L, info);
+    chol_blocked(n, H, L, info, s);
     hipLaunchKernelGGL(k_trinv_col, dim3(n), dim3(64), sizeof(double) * n, s, n, L, X);
     hipLaunchKernelGGL(k_gram, dim3((n + 255) / 256, n), dim3(256), 0, s, n, np, X, Hinv);
 }

@@ -866,6 +866,118 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
     return ROM_OK;
 }
 
+extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, double* A11, double* A12, double* B1,
+                                       int32_t sweeps, int32_t subiters, double momentum, void* stream) {
+    if (N < 1 || N > 4096) return fail(ROM_E_INVALID, "N must be in [1, 4096] (got %d)", N);
+    if (P < 1 || P > 2048) return fail(ROM_E_INVALID, "P must be in [1, 2048] (got %d)", P);
+    if (sweeps < 0 || subiters < 0) return fail(ROM_E_INVALID, "sweeps and subiters must be >= 0");
+    if (!(momentum >= 0.0 && momentum < 1.0)) return fail(ROM_E_INVALID, "momentum must be in [0, 1)");
+    if (!C || !A11 || !A12 || !B1) return fail(ROM_E_INVALID, "a tensor or factor pointer is NULL");
+    if (sweeps == 0) return ROM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int R = 2 * P;
+    const size_t n = (size_t)N, r = (size_t)R, rp = (r + 7) / 8 * 8, p = (size_t)P, pp = (p + 7) / 8 * 8;
+    const size_t npad = (n + 15) / 16 * 16, np = (n + 7) / 8 * 8, n2pad = (n * n + 15) / 16 * 16;
+    // factors A1, A2, A3 [N][R]; the untied normal system V, L, X [R][R], Vinv [R][Rp],
+    // right-hand side Mb [Npad][Rp], solution Yb [Npad][R]; the tied system Vt, Lt, Xt
+    // [P][P], Vtinv [P][Pp], Mt [Npad][Pp], Yt [Npad][P]; the unfolding U0 [N^2 padded][Np],
+    // a transposed factor Ft [R][Np] and the product T [N^2 padded][R]
+    constexpr int kBufs = 17;
+    const size_t sizes[kBufs] = {n * r, n * r, n * r, r * r, r * r, r * r, r * rp, npad * rp, npad * r,
+                                 p * p, p * p, p * p, p * pp, npad * pp, npad * p, n2pad * np, r * np};
+    const size_t tsize = n2pad * r;
+    double* buf[kBufs + 1] = {};
+    int* info = nullptr;
+    struct Guard {
+        double** b;
+        int** info;
+        ~Guard() {
+            for (int q = 0; q <= kBufs; ++q)
+                if (b[q]) hipFree(b[q]);
+            if (*info) hipFree(*info);
+        }
+    } guard{buf, &info};
+    for (int q = 0; q <= kBufs; ++q) {
+        const hipError_t e = hipMalloc((void**)&buf[q], sizeof(double) * (q < kBufs ? sizes[q] : tsize));
+        if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? ROM_E_NOMEM : ROM_E_DEVICE, "ALS-skew workspace: %s",
+                                         hipGetErrorString(e));
+    }
+    if (hipMalloc((void**)&info, sizeof(int)) != hipSuccess) return fail(ROM_E_NOMEM, "ALS-skew workspace");
+    double *A1 = buf[0], *A2 = buf[1], *A3 = buf[2], *V = buf[3], *L = buf[4], *X = buf[5], *Vinv = buf[6];
+    double *Mb = buf[7], *Yb = buf[8], *Vt = buf[9], *Lt = buf[10], *Xt = buf[11], *Vtinv = buf[12], *Mt = buf[13];
+    double *Yt = buf[14], *U0 = buf[15], *Ft = buf[16], *T = buf[17];
+    if (hipMemsetAsync(Vinv, 0, sizeof(double) * sizes[6], s) != hipSuccess ||
+        hipMemsetAsync(Mb, 0, sizeof(double) * sizes[7], s) != hipSuccess ||
+        hipMemsetAsync(Vtinv, 0, sizeof(double) * sizes[12], s) != hipSuccess ||
+        hipMemsetAsync(Mt, 0, sizeof(double) * sizes[13], s) != hipSuccess ||
+        hipMemsetAsync(U0, 0, sizeof(double) * sizes[15], s) != hipSuccess ||
+        hipMemsetAsync(info, 0, sizeof(int), s) != hipSuccess)
+        return fail(ROM_E_DEVICE, "ALS-skew workspace clear failed");
+    launch_als_unfold(N, (int)np, 0, C, U0, s);     // rows (i, j), columns k
+    launch_skew_assemble(N, P, A11, A12, B1, A1, A2, A3, s);
+    hipStream_t cs = nullptr;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphGuard {
+        hipStream_t* cs;
+        hipEvent_t* ev;
+        hipGraph_t* g;
+        hipGraphExec_t* ge;
+        ~GraphGuard() {
+            if (*ge) hipGraphExecDestroy(*ge);
+            if (*g) hipGraphDestroy(*g);
+            if (*cs) {
+                hipStreamSynchronize(*cs);
+                hipStreamDestroy(*cs);
+            }
+            if (*ev) hipEventDestroy(*ev);
+        }
+    } gguard{&cs, &ev, &graph, &gexec};
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess ||
+        hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
+        return fail(ROM_E_DEVICE, "ALS-skew stream setup failed");
+    const GemmPlan plt = gemm_plan(R, (int)n2pad, 0), plr = gemm_plan(R, (int)npad, 0),
+                   plp = gemm_plan(P, (int)npad, 0);
+    s = cs;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(ROM_E_DEVICE, "ALS-skew graph capture failed to start");
+    // T[(i, j)][m] = sum_k C[i][j][k] A3[k][m]: the unfolding times the third factor
+    auto tensor_times_a3 = [&]() {
+        launch_als_transpose(N, R, (int)np, A3, Ft, s);
+        launch_gemm_f64(plt, Ft, (long long)np, U0, (long long)np, T, R, (int)np, (int)n2pad, s);
+    };
+    // one sweep: the tied second factor (least squares with A2 = B1 [I I]), then the
+    // subiterations of the first factor with A3 fixed, each followed by the momentum
+    // update and A3 = [A12 -A11]
+    launch_gram_hadamard(N, R, A1, A3, V, s);
+    tensor_times_a3();
+    launch_als_reduce(N, R, 0, T, A1, Mb, (int)rp, s);                 // sum_i T[(i, j)] A1[i]
+    launch_skew_tie(N, P, V, Vt, Mb, (int)rp, Mt, (int)pp, s);
+    spd_inverse(P, (int)pp, Vt, Lt, Xt, Vtinv, info, s);
+    launch_gemm_f64(plp, Vtinv, (long long)pp, Mt, (long long)pp, Yt, P, (int)pp, (int)npad, s);
+    launch_skew_set_b(N, P, Yt, P, B1, A2, s);
+    for (int it = 0; it < subiters; ++it) {
+        launch_gram_hadamard(N, R, A2, A3, V, s);
+        if (it > 0) tensor_times_a3();                                 // A3 moved with A1
+        launch_als_reduce(N, R, 1, T, A2, Mb, (int)rp, s);             // sum_j T[(i, j)] A2[j]
+        spd_inverse(R, (int)rp, V, L, X, Vinv, info, s);
+        launch_gemm_f64(plr, Vinv, (long long)rp, Mb, (long long)rp, Yb, R, (int)rp, (int)npad, s);
+        launch_skew_momentum(N, P, momentum, Yb, R, A1, A3, A11, A12, s);
+    }
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    for (int sw = 0; sw < sweeps && e == hipSuccess; ++sw) e = hipGraphLaunch(gexec, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
+    int hinfo = 0;
+    if (e == hipSuccess) e = hipMemcpy(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(ROM_E_DEVICE, "ALS-skew failed: %s", hipGetErrorString(e));
+    if (hinfo) return fail(ROM_E_INVALID, "ALS-skew normal equations not positive definite (rank-deficient factors)");
+    return ROM_OK;
+}
+
 extern "C" rom_status rom_create_full(const rom_desc* d, const rom_full_terms* f, rom_ctx* out) {
     if (!f) {
         if (out) *out = nullptr;

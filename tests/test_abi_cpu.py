@@ -175,3 +175,15 @@ def test_full_terms_layout_matches_header():
     # rom_full_terms: five pointers M, C1, C2, c0, a0 (LP64)
     assert ctypes.sizeof(rg.binding.rom_full_terms) == 5 * 8
     assert rg.binding.rom_full_terms.a0.offset == 32
+
+
+def test_als_skew_rejects_arguments():
+    """rom_cp_als_skew checks its arguments before touching a device."""
+    L = rg.lib()
+    for args, msg in [((0, 2, None, None, None, None, 1, 1, 0.5, None), b"N must be"),
+                      ((4, 0, None, None, None, None, 1, 1, 0.5, None), b"P must be"),
+                      ((4, 2, None, None, None, None, 1, -1, 0.5, None), b"subiters"),
+                      ((4, 2, None, None, None, None, 1, 1, 1.0, None), b"momentum"),
+                      ((4, 2, None, None, None, None, 1, 1, 0.5, None), b"NULL")]:
+        assert L.rom_cp_als_skew(*args) == rg.binding.ROM_E_INVALID
+        assert msg in L.rom_last_error()

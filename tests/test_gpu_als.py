@@ -78,3 +78,61 @@ def test_als_zero_sweeps_noop(torch_gpu):
     G = _gpu_als(torch_gpu, X, F0, 0)
     for a, b in zip(G, F0):
         assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ ALS-skew (Sec. 3.3)
+
+def _skew_problem(N, P, seed, noise=1e-3):
+    rng = np.random.default_rng(seed)
+    a, c, b = (rng.standard_normal((N, P)) for _ in range(3))
+    X = np.einsum("ir,jr,kr->ijk", *orc.als.skew_factors(a, c, b))
+    G = rng.standard_normal((N, N, N))
+    X = X + noise * 0.5 * (G - G.transpose(2, 1, 0))
+    init = [rng.standard_normal((N, P)) for _ in range(3)]
+    return X, init
+
+
+def _gpu_als_skew(torch, X, init, sweeps, subiters, momentum=0.5):
+    N, P = init[0].shape
+    Xd = torch.tensor(X, dtype=torch.float64, device="cuda").contiguous()
+    Fd = [torch.tensor(A, dtype=torch.float64, device="cuda").contiguous() for A in init]
+    torch.cuda.synchronize()
+    rg.rom_cp_als_skew(N, P, Xd, *Fd, sweeps, subiters, momentum)
+    torch.cuda.synchronize()
+    return [A.cpu().numpy() for A in Fd]
+
+
+@pytest.mark.parametrize("N,P,sweeps,subiters,mom", [(7, 2, 1, 1, 0.5), (23, 5, 1, 2, 0.5), (23, 5, 4, 3, 0.5),
+                                                     (40, 19, 2, 2, 0.25), (33, 130, 1, 1, 0.5), (17, 4, 3, 0, 0.5),
+                                                     (50, 40, 2, 5, 0.0)])
+def test_als_skew_matches_oracle(torch_gpu, N, P, sweeps, subiters, mom):
+    _say(f"als-skew N={N} P={P} sweeps={sweeps} subiters={subiters} momentum={mom}")
+    X, init = _skew_problem(N, P, 30 + N + P)
+    G = _gpu_als_skew(torch_gpu, X, init, sweeps, subiters, mom)
+    F, res = orc.als.als_skew(X, *init, sweeps=sweeps, subiters=subiters, momentum=mom)
+    for a, b in zip(G, F):
+        assert np.max(np.abs(a - b)) <= 1e-8 * np.max(np.abs(b)), float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    rg_res = orc.als.residual(X, orc.als.skew_factors(*G))
+    assert abs(rg_res - res[-1]) <= 1e-8 * max(res[-1], 1e-12)
+
+
+def test_als_skew_fits_and_stays_skew(torch_gpu):
+    """From a random start, 60 GPU sweeps (3 subiterations, momentum 1/2) bring a noisy
+    rank-6 skew tensor to the noise level, and the fit is skew in positions 1 and 3."""
+    _say("als-skew fit N=14 P=3 sweeps=60")
+    X, init = _skew_problem(14, 3, 1003, noise=1e-4)
+    G = _gpu_als_skew(torch_gpu, X, init, 60, 3)
+    T = np.einsum("ir,jr,kr->ijk", *orc.als.skew_factors(*G))
+    assert np.max(np.abs(T + T.transpose(2, 1, 0))) <= 1e-12 * np.max(np.abs(T))
+    assert orc.als.residual(X, orc.als.skew_factors(*G)) < 1e-2
+
+
+def test_als_skew_exact_fixed_point(torch_gpu):
+    _say("als-skew fixed point")
+    rng = np.random.default_rng(11)
+    N, P = 20, 4
+    a, c, b = (rng.standard_normal((N, P)) for _ in range(3))
+    X = np.einsum("ir,jr,kr->ijk", *orc.als.skew_factors(a, c, b))
+    G = _gpu_als_skew(torch_gpu, X, [a, c, b], 3, 2)
+    for u, v in zip(G, (a, c, b)):
+        assert np.max(np.abs(u - v)) <= 1e-9 * np.max(np.abs(v))
