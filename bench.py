@@ -30,8 +30,9 @@ Also in the one JSON line:
                 terms) at the headline size, CP rank 2000 FP32, against the plain step
   als           CP-ALS sweeps (rom_cp_als) at N = 200, R = 400, FP64: ms per sweep; ALS-skew
                 (rom_cp_als_skew) with 200 column pairs and 3 subiterations
-  multi         uneven N: one CP trajectory each at N = 100, 200, 400, 700, 1000 stepped
-                together by grouped launches (rom_step_multi) and one after the other
+  multi         uneven N and mixed formats: CP states at N = 100..1000 in FP32, BF16X3 and
+                BF16 with SPD or diagonal stiffness, a dense state and a batch of 16, stepped
+                together (rom_step_multi) and one after the other
   serving       a bounded Poisson request stream through the continuous-batching loop
   model_error   the CP-ROM's distance from the G-ROM (Sec. 4.1: errors relative to the
                 G-ROM) at CP ranks 500, 1000, 2000 over 1000 steps, GPU FP32 trajectories
@@ -581,38 +582,52 @@ def main():
         checks.add_fn("als", als_err)
 
     if not args.no_extra and sec in ("all", "multi"):
-        # ---------------- uneven N: grouped launches against the same states one by one
-        Ns = (100, 200, 400, 700, 1000)
+        # ---------------- uneven N and mixed formats: grouped launches against the same
+        # states one by one.  One-trajectory CP states at N = 100..1000 (R = 2N) in FP32,
+        # BF16X3 and BF16 with SPD or diagonal stiffness, a dense FP32 state, and a batch
+        # of 16 CP FP32 trajectories at N = 400
+        specs = [(100, "cp", "fp32", "spd", 1), (200, "cp", "bf16x3", "diag", 1), (400, "cp", "fp32", "spd", 1),
+                 (700, "cp", "bf16", "spd", 1), (1000, "cp", "fp32", "spd", 1), (200, "dense", "fp32", "diag", 1),
+                 (400, "cp", "fp32", "spd", 16)]
         roms, sts, pms = [], [], []
-        for i, Nm in enumerate(Ns):
-            pm = romsynth.make_problem(Nm, pairs=Nm, eps=1e-7, nu=5e-4, dt=5e-4, A="spd", cfg=40 + i,
-                                       dense=False, cp=True)
-            rm = rg.Rom.from_problem(pm, dense=False, dtype="fp32", max_batch=1, stream=stream)
+        for i_, (Nm, kind, mdt, A_kind, Bm) in enumerate(specs):
+            pm = romsynth.make_problem(Nm, pairs=Nm, eps=1e-7, nu=5e-4, dt=5e-4, A=A_kind, cfg=40 + i_, batch=Bm,
+                                       dense=kind == "dense", cp=kind == "cp")
+            rm = rg.Rom.from_problem(pm, dense=kind == "dense", dtype=mdt, max_batch=Bm, stream=stream)
+            if Bm > 1:
+                tune.apply(rm, Bm, dense=False, R=2 * Nm, table=tiles)
             pms.append(pm)
             roms.append(rm)
-            sts.append(rm.state(pm.u0[0]))
+            sts.append(rm.state(pm.u0))
         ch, sh = [r.handle for r in roms], [x.handle for x in sts]
+        ntraj = sum(x[4] for x in specs)
         nm = 2000
         rg.rom_step_multi(ch, sh, 20)
+        rg.rom_step_multi(ch, sh, nm)                    # tables and graphs of this call length
         t_grp = timer(lambda: rg.rom_step_multi(ch, sh, nm))
         for x in sts:
+            x.prepare(nm)
             x.step(20)
         t_sep = timer(lambda: [x.step_async(nm) for x in sts])
         for x in sts:
             x.sync()
-        result["multi"] = {"Ns": list(Ns), "R": "2N", "dtype": "fp32", "stiffness": "diag(k^2)+SPD(0.1)",
-                           "grouped_traj_steps_per_s": len(Ns) * nm / t_grp,
-                           "separate_traj_steps_per_s": len(Ns) * nm / t_sep,
+        result["multi"] = {"pairs": [dict(N=a, form=b, dtype=c, stiffness=d, batch=e) for a, b, c, d, e in specs],
+                           "R": "2N", "trajectories": ntraj,
+                           "grouped_traj_steps_per_s": ntraj * nm / t_grp,
+                           "separate_traj_steps_per_s": ntraj * nm / t_sep,
                            "grouped_us_per_step": t_grp / nm * 1e6, "separate_us_per_step": t_sep / nm * 1e6,
                            "speedup_grouped": t_sep / t_grp}
-        log(f"multi: grouped {len(Ns) * nm / t_grp:.0f}, separate {len(Ns) * nm / t_sep:.0f} traj-steps/s")
+        log(f"multi: grouped {ntraj * nm / t_grp:.0f}, separate {ntraj * nm / t_sep:.0f} traj-steps/s")
         for x in sts:
             x.close()
-        sts = [rm.state(pm.u0[0]) for rm, pm in zip(roms, pms)]
+        sts = [rm.state(pm.u0) for rm, pm in zip(roms, pms)]
         rg.rom_step_multi([r.handle for r in roms], [x.handle for x in sts], 200)
-        for Nm, pm, x in zip(Ns, pms, sts):
-            checks.add("multi", f"N{Nm}", (pm.N, pm.nu, pm.dt, pm.A), dict(lam=pm.lam, Af=pm.Af, Bf=pm.Bf, Cf=pm.Cf),
-                       pm.u0[0], 200, x.u())
+        for (Nm, kind, mdt, A_kind, Bm), pm, x in zip(specs, pms, sts):
+            ops = dict(C=pm.C) if kind == "dense" else dict(lam=pm.lam, Af=pm.Af, Bf=pm.Bf, Cf=pm.Cf)
+            ug = x.get()[0][0]
+            for b in sorted({0, Bm - 1}):
+                checks.add("multi", f"N{Nm}_{kind}_{mdt}_{A_kind}_B{Bm}_traj{b}", (pm.N, pm.nu, pm.dt, pm.A), ops,
+                           pm.u0[b], 200, ug[b], dtype=mdt)
             x.close()
         for r in roms:
             r.close()

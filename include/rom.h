@@ -248,11 +248,17 @@ rom_status rom_state_set(rom_ctx ctx, rom_state st, const double *u_hist,
 /* Copy the current coefficients u^n [batch][N] into caller device memory.  Async. */
 rom_status rom_state_u(rom_ctx ctx, rom_state st, double *u_dev);
 
-/* Several (context, state) pairs of possibly different N, R and dtype advanced
- * together: each step of all pairs is issued as one fused launch per kernel phase over
- * a device work table, on the stream of ctxs[0], so trajectories of uneven size share
- * the device.  nsteps applies to every pair.  Results equal those of rom_step on each
- * pair alone within the dtype's tolerance.  Synchronizes at the end. */
+/* Several (context, state) pairs advanced together by nsteps steps each, on the stream
+ * of ctxs[0].  The one-trajectory states, whatever their N, CP rank, format, stiffness
+ * kind (diagonal or dense) and operator form (dense, CP general or pair form, SVD, full
+ * form), share at most four launches per step, one per phase of the step, each over a
+ * device work table of all their jobs; batches (B > 1) run their own kernels inside the
+ * same captured steps.  A state's results equal those of rom_step on it alone, to the bit.
+ * The work tables and captured graphs of a set of pairs are built on its first call and
+ * reused by later calls with the same pairs in the same order and level parities (they
+ * are dropped when a member is destroyed).  Synchronizes at the end.  Returns
+ * ROM_E_NONFINITE with the earliest non-finite level over all pairs; rom_query(what = 10)
+ * tells which states failed. */
 rom_status rom_step_multi(int32_t n, const rom_ctx *ctxs, const rom_state *states,
                           int64_t nsteps, int64_t *first_bad_step);
 
@@ -260,7 +266,8 @@ rom_status rom_step_multi(int32_t n, const rom_ctx *ctxs, const rom_state *state
  * the state, 2 = N, 3 = R (0 if dense), 4 = dtype, 5 = state batch, 6 = state step,
  * 7 = skew column-pair layout the one-trajectory CP kernels use (rom_cp_skew_layout's
  * codes; 0 = general form), 8 = operator form (0 dense, 1 CP, 2 SVD), 9 = SVD rank
- * (0 unless SVD). */
+ * (0 unless SVD), 10 = the state's first non-finite level, -1 if none (synchronizes with
+ * the context's stream; lets a caller of rom_step_multi find which states failed). */
 rom_status rom_query(rom_ctx ctx, rom_state st, int32_t what, int64_t *value);
 
 /* Kernel tile selection (the autotuner's knob).  kind: 0 = dense single-trajectory

@@ -9,52 +9,11 @@
 #include <climits>
 
 #include "als.h"
-#include "kstep.h"
+#include "kbody.h"
 
 namespace rom {
 
 // ============================================================== update kernels
-
-// y^n from contraction partials part[c][b][i] (summed over c in order), then either
-// the diagonal-stiffness update u^{n+1} = rhs / H_ii with its energy partials, or the
-// right-hand side for the dense solve.  Block (bx, b) covers rows 256 bx .. 256 bx + 255
-// of trajectory b (nbx blocks per trajectory).
-template <class ACC, bool DIAG>
-__device__ __forceinline__ void bdf_partials_body(const StepArgs& a, long long n, const ACC* __restrict__ part,
-                                                  int nchunk, int pbstride, int bx, int b, int nbx) {
-    __shared__ double red[4];
-    const int k = bdf_order(n);
-    const BdfCoef c = bdf_coef(k);
-    const int i = bx * blockDim.x + threadIdx.x;
-    double e = 0.0;
-    if (i < a.N) {
-        // partial sums added in chunk order; loads issued 8 at a time
-        double y = 0.0;
-        const size_t cs = (size_t)pbstride * a.N;
-        const ACC* pp = part + (size_t)b * a.N + i;
-        int q = 0;
-        for (; q + 8 <= nchunk; q += 8) {
-            ACC v[8];
-#pragma unroll
-            for (int e2 = 0; e2 < 8; ++e2) v[e2] = pp[(size_t)(q + e2) * cs];
-#pragma unroll
-            for (int e2 = 0; e2 < 8; ++e2) y += (double)v[e2];
-        }
-        for (; q < nchunk; ++q) y += (double)pp[(size_t)q * cs];
-        const double rhs = bdf_rhs_point(a, n, c, k, b, i, y);
-        if (DIAG) {
-            const double un = rhs * a.hdiag[(size_t)(k - 1) * a.N + i];
-            write_level(a, n + 1, b, i, un);
-            e = un * un;
-        } else {
-            a.rhs[(size_t)b * a.Np + i] = rhs;
-        }
-    }
-    if (DIAG) {
-        const double s = block_sum(e, red);
-        if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * a.enmax + bx] = s;
-    }
-}
 
 // Grid (nbx, B) for the right-hand side; with DIAG (the update kernel) one more row
 // whose block 0 closes the previous level and advances the counter (the rest of that
@@ -71,20 +30,6 @@ __global__ __launch_bounds__(256) void k_bdf_partials(StepArgs a, const ACC* __r
     } else {
         bdf_partials_body<ACC, false>(a, *a.step, part, nchunk, pbstride, blockIdx.x, blockIdx.y, gridDim.x);
     }
-}
-
-// Grouped states (one trajectory each); with DIAG the first block of each job also
-// closes its state's previous level and advances its counter.
-template <class ACC, bool DIAG>
-__global__ __launch_bounds__(256) void k_bdf_group(const BdfJob* __restrict__ jobs, int njobs) {
-    const int p = find_job(jobs, njobs, (int)blockIdx.x);
-    const BdfJob& jb = jobs[p];
-    const int blk = (int)blockIdx.x - jb.blk0;
-    const long long n = *jb.a.step;
-    if constexpr (DIAG) {
-        if (blk == 0) close_and_advance(jb.a, n, jb.nblk);
-    }
-    bdf_partials_body<ACC, DIAG>(jb.a, n, reinterpret_cast<const ACC*>(jb.part), jb.nchunk, jb.pb, blk, 0, jb.nblk);
 }
 
 // ceil(N/4) row blocks plus a last block that closes the previous level and advances
@@ -164,15 +109,6 @@ void launch_close_group(const FinJob* jobs_dev, int njobs, hipStream_t s) {
     if (njobs > 0) hipLaunchKernelGGL(k_close_group, dim3((unsigned)njobs), dim3(256), 0, s, jobs_dev);
 }
 
-void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s) {
-    if (acc_f64) {
-        if (diag) hipLaunchKernelGGL((k_bdf_group<double, true>), dim3(blocks), dim3(256), 0, s, jobs_dev, njobs);
-        else hipLaunchKernelGGL((k_bdf_group<double, false>), dim3(blocks), dim3(256), 0, s, jobs_dev, njobs);
-    } else {
-        if (diag) hipLaunchKernelGGL((k_bdf_group<float, true>), dim3(blocks), dim3(256), 0, s, jobs_dev, njobs);
-        else hipLaunchKernelGGL((k_bdf_group<float, false>), dim3(blocks), dim3(256), 0, s, jobs_dev, njobs);
-    }
-}
 
 void launch_helm_apply(const StepArgs& a, hipStream_t s) {
     const size_t lds = sizeof(double) * a.N;
@@ -469,90 +405,9 @@ void full_setup(int N, int Np, double nu, const double* M, const double* C1, con
                        G, fz, az);
 }
 
-// Zeroth-mode and mass terms of the right-hand side of level n (eq. nse_d1), per
-// trajectory b:
-//   zfull = L uhat + (M - I) h,
-//   uhat = sum_q alpha_q u^{n+1-q},  h = (1/dt) sum_q beta_q u^{n+1-q}
-// (the EXT sum of the linear part of the bracket, and M minus the identity times the BDF
-// history sum, which the rhs already carries; the constants are added with the rhs).
-// Grid (ceil(N/8), B), 512 threads, one wavefront per row of G (2 Np doubles, read as
-// 16-byte pairs in chunks of 16 per lane, a whole row up to N = 1024).  The first chunk of
-// G and the history loads of the staging (up to 1024 coefficients per pass) are all issued
-// before any of them is used, so the kernel waits for one round trip to memory instead of
-// one per loop pass; eight rows per block share one staging of the history.
-constexpr int kFullRows = 8, kFullChunk = 16, kFullStage = 2;
+// One state: grid (ceil(N/8), B), 512 threads.
 __global__ __launch_bounds__(512) void k_full_terms(StepArgs a, const double* __restrict__ G) {
-    extern __shared__ double2 xs2[];
-    double* xs = reinterpret_cast<double*>(xs2);
-    const int b = blockIdx.y, Np = a.Np;
-    const int lane = threadIdx.x & (kWave - 1), i = blockIdx.x * kFullRows + (threadIdx.x / kWave);
-    const bool active = i < a.N;
-    // row i of G as Np pairs (Np is a multiple of 8, rows 16-byte aligned)
-    const double2* g2 = reinterpret_cast<const double2*>(G + (size_t)(active ? i : 0) * 2 * Np);
-    double2 gv[kFullChunk];
-#pragma unroll
-    for (int u = 0; u < kFullChunk; ++u) {
-        const int m = lane + u * kWave;
-        gv[u] = (active && m < Np) ? g2[m] : make_double2(0.0, 0.0);
-    }
-    const long long n = *a.step;
-    const int k = bdf_order(n);
-    const BdfCoef c = bdf_coef(k);
-    const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N;
-    const double* lev[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) lev[q] = a.uring + (size_t)slot_of(n - q) * BN + off;
-    for (int j0 = 0; j0 < Np; j0 += kFullStage * (int)blockDim.x) {
-        double uv[3][kFullStage];
-#pragma unroll
-        for (int e = 0; e < kFullStage; ++e) {
-            const int j = j0 + e * (int)blockDim.x + (int)threadIdx.x;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) uv[q][e] = (q < k && j < a.N) ? lev[q][j] : 0.0;
-        }
-#pragma unroll
-        for (int e = 0; e < kFullStage; ++e) {
-            const int j = j0 + e * (int)blockDim.x + (int)threadIdx.x;
-            double uh = 0.0, h = 0.0;
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                if (q < k) {
-                    uh += c.alpha[q] * uv[q][e];
-                    h += (c.beta[q + 1] * a.inv_dt) * uv[q][e];
-                }
-            if (j < Np) {
-                xs[j] = uh;
-                xs[Np + j] = h;
-            }
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-    double acc[kFullChunk];
-#pragma unroll
-    for (int u = 0; u < kFullChunk; ++u) acc[u] = 0.0;
-    for (int base = 0; base < Np; base += kFullChunk * kWave) {
-        if (base > 0) {
-#pragma unroll
-            for (int u = 0; u < kFullChunk; ++u) {
-                const int m = base + lane + u * kWave;
-                gv[u] = m < Np ? g2[m] : make_double2(0.0, 0.0);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kFullChunk; ++u) {
-            const int m = base + lane + u * kWave;
-            if (m < Np) {
-                const double2 x = xs2[m];
-                acc[u] += gv[u].x * x.x + gv[u].y * x.y;
-            }
-        }
-    }
-    double t = 0.0;
-#pragma unroll
-    for (int u = 0; u < kFullChunk; ++u) t += acc[u];
-    const double s = wave_sum(t);
-    if (lane == 0) a.zfull[off + i] = s;
+    full_terms_body(a, G, (int)blockIdx.x, (int)blockIdx.y);
 }
 
 void launch_full_terms(const StepArgs& a, const double* G, hipStream_t s) {

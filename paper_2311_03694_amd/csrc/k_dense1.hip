@@ -14,91 +14,13 @@
 // u_j.  BF16 pairs use the packed dot2 instruction.  Blocks write one partial sum each
 // (FP32, or FP64 for the FP64 format); the BDF update adds them in a fixed order, so
 // results are deterministic.
-#include "kdot.h"
+#include "kbody.h"
 
 namespace rom {
 
 template <int DT, int V, int UNR, int NT>
-__device__ __forceinline__ void dense_gemv_body(const GemvJob& jb, int blk) {
-    typedef typename Store<DT>::T T;
-    typedef typename Store<DT>::Acc Acc;
-    typedef typename RawT<V * (int)sizeof(T)>::T Raw;
-    constexpr int BYTES = V * (int)sizeof(T);
-    constexpr bool X3 = (DT == DT_BF16X3);
-    extern __shared__ __attribute__((aligned(16))) char smem[];
-    __shared__ Acc red[NT / kWave];
-    const int N = jb.N, Np = jb.Np, nchunk = jb.nchunk;
-    const long long chunk_len = jb.chunk_len;
-    const T* __restrict__ C = reinterpret_cast<const T*>(jb.C);
-    LdsU<DT> L;
-    L.bind(smem, Np);
-    // slab weights: u itself (its accumulation-format image), or jb.wj staged behind it
-    Acc* wl = reinterpret_cast<Acc*>(smem + LdsU<DT>::bytes(Np));
-    const Acc* wsrc = jb.wj ? wl : L.uw;
-
-    const int i = blk / nchunk;
-    const int c = blk - i * nchunk;
-    const long long NN = (long long)jb.J * Np;
-    const long long m0 = (long long)c * chunk_len;
-    const long long m1 = (m0 + chunk_len < NN) ? m0 + chunk_len : NN;
-    const T* row = C + (size_t)i * NN;
-    const unsigned short* rowlo = X3 ? jb.Clo + (size_t)i * NN : nullptr;
-
-    constexpr int STEP = NT * V;
-    const int dj = STEP / Np, dk = STEP - (STEP / Np) * Np;
-    long long m = m0 + (long long)threadIdx.x * V;
-    int j = (int)(m / Np), k = (int)(m - (long long)j * Np);
-
-    Raw r[UNR], rl[UNR];
-    int jj[UNR], kk[UNR];
-    auto issue = [&](long long mb) {
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) {
-            const long long mq = mb + (long long)q * STEP;
-            jj[q] = j;
-            kk[q] = k;
-            if (mq < m1) {
-                r[q] = ld_stream<BYTES>(row + mq);
-                if constexpr (X3) rl[q] = ld_stream<BYTES>(rowlo + mq);
-            }
-            k += dk;
-            j += dj;
-            if (k >= Np) { k -= Np; ++j; }
-        }
-    };
-
-    if (m < m1) issue(m);
-    L.fill(jb.u_base + (jb.stepp ? (size_t)slot_of(*jb.stepp) * jb.slot_stride : 0), N, Np);
-    if (jb.wj) {
-        const Acc* wg = reinterpret_cast<const Acc*>(jb.wj);
-        for (int q = threadIdx.x; q < jb.J; q += NT) wl[q] = wg[q];
-    }
-    __syncthreads();
-
-    Acc acc = 0;
-    while (m < m1) {
-#pragma unroll
-        for (int q = 0; q < UNR; ++q) {
-            if (m + (long long)q * STEP < m1) acc += wsrc[jj[q]] * dot_vec<DT, V>(r[q], rl[q], L, kk[q]);
-        }
-        m += (long long)STEP * UNR;
-        if (m < m1) issue(m);
-    }
-    const Acc s = block_sum(acc, red);
-    if (threadIdx.x == 0) reinterpret_cast<Acc*>(jb.part)[(size_t)c * N + i] = s;
-}
-
-template <int DT, int V, int UNR, int NT>
 __global__ __launch_bounds__(NT) void k_dense_gemv(GemvJob jb) {
     dense_gemv_body<DT, V, UNR, NT>(jb, blockIdx.x);
-}
-
-// Several contractions of different N in one launch: block q runs block
-// q - jobs[p].blk0 of the job p whose block range holds q.
-template <int DT, int V, int UNR, int NT>
-__global__ __launch_bounds__(NT) void k_dense_gemv_group(const GemvJob* __restrict__ jobs, int njobs) {
-    const int p = find_job(jobs, njobs, (int)blockIdx.x);
-    dense_gemv_body<DT, V, UNR, NT>(jobs[p], (int)blockIdx.x - jobs[p].blk0);
 }
 
 static const GemvTile kGemvTiles[] = {
@@ -151,27 +73,25 @@ GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, int
 }
 
 template <int DT, int UNR>
-static void gemv_go(const GemvJob& jb, const GemvJob* jobs, int njobs, int blocks, int Npmax, hipStream_t s) {
+static void gemv_go(const GemvJob& jb, hipStream_t s) {
     constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
-    const size_t lds = LdsU<DT>::bytes(Npmax) + (jb.wj ? sizeof(typename Store<DT>::Acc) * (size_t)jb.J : 0);
-    if (jobs) hipLaunchKernelGGL((k_dense_gemv_group<DT, V, UNR, 256>), dim3((unsigned)blocks), dim3(256), lds, s, jobs, njobs);
-    else hipLaunchKernelGGL((k_dense_gemv<DT, V, UNR, 256>), dim3((unsigned)jb.nblk), dim3(256), lds, s, jb);
+    const size_t lds = LdsU<DT>::bytes(jb.Np) + (jb.wj ? sizeof(typename Store<DT>::Acc) * (size_t)jb.J : 0);
+    hipLaunchKernelGGL((k_dense_gemv<DT, V, UNR, 256>), dim3((unsigned)jb.nblk), dim3(256), lds, s, jb);
 }
 
 template <int DT>
-static void gemv_dt(int unr, const GemvJob& jb, const GemvJob* jobs, int njobs, int blocks, int Npmax, hipStream_t s) {
-    if (unr == 2) gemv_go<DT, 2>(jb, jobs, njobs, blocks, Npmax, s);
-    else if (unr == 8) gemv_go<DT, 8>(jb, jobs, njobs, blocks, Npmax, s);
-    else gemv_go<DT, 4>(jb, jobs, njobs, blocks, Npmax, s);
+static void gemv_dt(int unr, const GemvJob& jb, hipStream_t s) {
+    if (unr == 2) gemv_go<DT, 2>(jb, s);
+    else if (unr == 8) gemv_go<DT, 8>(jb, s);
+    else gemv_go<DT, 4>(jb, s);
 }
 
-static void gemv_dispatch(int dt, int unr, const GemvJob& jb, const GemvJob* jobs, int njobs, int blocks, int Npmax,
-                          hipStream_t s) {
+static void gemv_dispatch(int dt, int unr, const GemvJob& jb, hipStream_t s) {
     switch (dt) {
-        case DT_F64: gemv_dt<DT_F64>(unr, jb, jobs, njobs, blocks, Npmax, s); break;
-        case DT_F32: gemv_dt<DT_F32>(unr, jb, jobs, njobs, blocks, Npmax, s); break;
-        case DT_BF16: gemv_dt<DT_BF16>(unr, jb, jobs, njobs, blocks, Npmax, s); break;
-        default: gemv_dt<DT_BF16X3>(unr, jb, jobs, njobs, blocks, Npmax, s); break;
+        case DT_F64: gemv_dt<DT_F64>(unr, jb, s); break;
+        case DT_F32: gemv_dt<DT_F32>(unr, jb, s); break;
+        case DT_BF16: gemv_dt<DT_BF16>(unr, jb, s); break;
+        default: gemv_dt<DT_BF16X3>(unr, jb, s); break;
     }
 }
 
@@ -179,14 +99,8 @@ int launch_dense_gemv(int dt, const void* C, const void* Clo, int N, int Np, int
                       const double* u_base, const long long* stepp, long long slot_stride, void* part, int nchunk,
                       GemvTile t, hipStream_t s) {
     const GemvJob jb = make_gemv_job(dt, C, Clo, N, Np, J, wj, u_base, stepp, slot_stride, part, nchunk, t);
-    gemv_dispatch(dt, t.unroll, jb, nullptr, 0, 0, Np, s);
+    gemv_dispatch(dt, t.unroll, jb, s);
     return 0;
-}
-
-void launch_dense_gemv_group(int dt, const GemvJob* jobs_dev, int njobs, int blocks, int Npmax, GemvTile t,
-                             hipStream_t s) {
-    GemvJob none{};
-    gemv_dispatch(dt, t.unroll, none, jobs_dev, njobs, blocks, Npmax, s);
 }
 
 }  // namespace rom

@@ -411,8 +411,11 @@ extern "C" int32_t rom_cp_skew_layout(int32_t N, int32_t R, const double* lambda
     return skew_layout_of(N, R, lambda, Af, Bf, Cf);
 }
 
+static void forget_plans_of(const void* obj);
+
 extern "C" void rom_destroy(rom_ctx c) {
     if (!c) return;
+    forget_plans_of(c);
     if (c->stream) hipStreamSynchronize(c->stream);
     for (void* p : c->allocs) hipFree(p);
     if (c->ws) hipFree(c->ws);
@@ -1372,6 +1375,7 @@ int energy_slots(rom_ctx c, int B) { return B > 1 ? (c->N + 15) / 16 : (c->N + 3
 
 extern "C" void rom_state_destroy(rom_state s) {
     if (!s) return;
+    forget_plans_of(s);
     if (s->ctx && s->ctx->stream) hipStreamSynchronize(s->ctx->stream);
     for (auto& par : s->graph)
         for (auto& row : par)
@@ -1688,57 +1692,278 @@ extern "C" rom_status rom_state_u(rom_ctx c, rom_state s, double* u_dev) {
 }
 
 // ============================================================== uneven-N batching
+//
+// rom_step_multi advances many (context, state) pairs together.  Every one-trajectory
+// state contributes jobs to four mixed launches per step (k_multi.hip): phase 0 full-form
+// terms and SVD first products, phase 1 dense / SVD slab streams and CP projections,
+// phase 2 BDF updates and CP scatters, phase 3 Helmholtz applies (with the next CP
+// projections), whatever the mix of N, R, formats, stiffness kinds and operator forms.
+// Batches (B > 1) run their own kernels (enqueue_step) inside the same captured steps.
+// The job tables of a set of pairs (one per parity of the step index: a state's kernels
+// take the counter slots of its level's parity) are built and uploaded once and cached
+// with their captured graphs; a plan is dropped when one of its states or contexts is
+// destroyed, or rebuilt when a workspace, scratch or energy log has moved.
 
 namespace {
 
-// Single-trajectory pairs that share a kernel family: dense/CP, number format, and
-// diagonal or dense stiffness.  Each phase of a step is one grouped launch over the
-// job table of the group.
-struct Group {
-    int dense = 0, dtype = 0, diag = 0;
-    std::vector<GemvJob> gemv;
-    std::vector<Proj1Job> proj;
-    std::vector<Scat1Job> scat;
-    std::vector<BdfJob> bdf;
-    std::vector<HelmJob> helm;
-    std::vector<FinJob> fin;               // closing energy sum after the last step, per state
-    int b1 = 0, b2 = 0, b3 = 0;            // blocks of phase 1, 2, 3
-    int Npmax = 8, Rpmax = 8, Nmax = 1;
-    GemvTile tile{};
-    char* dev = nullptr;                   // device copies of the job tables
-    size_t off1 = 0, off2 = 0, off3 = 0, off4 = 0;
+constexpr int kMixPhases = 4;
+
+struct MultiPlan {
+    std::vector<rom_ctx> ctxs;
+    std::vector<rom_state> states;
+    std::vector<int> wsgen, sgen;
+    std::vector<char> par;                  // level parity of each state at the plan's start
+    std::vector<int> batched;               // pairs stepped by their own kernels
+    char* dev = nullptr;                    // the job tables
+    size_t off[2][kMixPhases] = {};
+    int njobs[2][kMixPhases] = {}, blocks[2][kMixPhases] = {};
+    size_t lds[2][kMixPhases] = {};
+    size_t fin_off[2] = {};                 // closing jobs after an even / odd number of steps
+    int nfin = 0;
+    // graphs of len steps (index len) from the plan's start parities, without [0] and with
+    // [1] the closing kernels at the end
+    hipGraphExec_t graph[2][kGraphChunk + 1] = {};
+    hipStream_t stream = nullptr;
+
+    ~MultiPlan() {
+        for (auto& row : graph)
+            for (auto g : row)
+                if (g) hipGraphExecDestroy(g);
+        if (dev) {
+            if (stream) hipStreamSynchronize(stream);
+            hipFree(dev);
+        }
+    }
 };
 
-template <class J>
-size_t put(std::vector<char>& blob, const std::vector<J>& v) {
-    size_t off = (blob.size() + 255) & ~(size_t)255;
-    blob.resize(off + sizeof(J) * v.size());
-    if (!v.empty()) memcpy(blob.data() + off, v.data(), sizeof(J) * v.size());
-    return off;
+constexpr size_t kMaxPlans = 8;
+std::mutex g_plan_mu;
+std::vector<MultiPlan*> g_plans;            // most recently used last
+
+// Drop every plan that refers to `obj` (a context or a state about to be destroyed).
+void forget_plans(const void* obj) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (size_t q = 0; q < g_plans.size();) {
+        MultiPlan* pl = g_plans[q];
+        bool hit = false;
+        for (size_t r = 0; r < pl->states.size() && !hit; ++r)
+            hit = (const void*)pl->states[r] == obj || (const void*)pl->ctxs[r] == obj;
+        if (hit) {
+            delete pl;
+            g_plans.erase(g_plans.begin() + (long)q);
+        } else {
+            ++q;
+        }
+    }
 }
 
-void enqueue_group(const Group& g, hipStream_t stream, int phase) {
-    if (phase == 1) {
-        if (g.dense)
-            launch_dense_gemv_group(g.dtype, (const GemvJob*)(g.dev + g.off1), (int)g.gemv.size(), g.b1, g.Npmax,
-                                    g.tile, stream);
-        else if (!g.proj.empty())
-            launch_cp_proj1_group(g.dtype, (const Proj1Job*)(g.dev + g.off1), (int)g.proj.size(), g.b1, g.Npmax,
-                                  stream);
-    } else if (phase == 2) {
-        if (g.dense)
-            launch_bdf_group(acc_f64(g.dtype), g.diag, (const BdfJob*)(g.dev + g.off2), (int)g.bdf.size(), g.b2,
-                             stream);
-        else
-            launch_cp_scatter1_group(g.dtype, g.diag ? 1 : 2, (const Scat1Job*)(g.dev + g.off2),
-                                     (int)g.scat.size(), g.b2, g.Rpmax, stream);
-    } else if (phase == 3) {
-        if (!g.diag)
-            launch_helm_proj_group(g.dtype, (const HelmJob*)(g.dev + g.off3), (int)g.helm.size(), g.b3, g.Nmax,
-                                   g.Npmax, g.dense ? 0 : 1, stream);
-    } else {
-        launch_close_group((const FinJob*)(g.dev + g.off4), (int)g.fin.size(), stream);
+bool plan_matches(const MultiPlan* pl, int n, const rom_ctx* ctxs, const rom_state* states) {
+    if ((int)pl->states.size() != n || pl->stream != ctxs[0]->stream) return false;
+    for (int q = 0; q < n; ++q)
+        if (pl->ctxs[q] != ctxs[q] || pl->states[q] != states[q] || pl->wsgen[q] != ctxs[q]->ws_gen ||
+            pl->sgen[q] != states[q]->sgen || pl->par[q] != (char)(states[q]->h_step & 1))
+            return false;
+    return true;
+}
+
+// The mixed jobs of one-trajectory pair (c, st) for the step from level `lev`, by phase.
+void pair_jobs(rom_ctx c, rom_state st, long long lev, std::vector<MixJob> (&ph)[kMixPhases]) {
+    const StepArgs sa = step_args(st, lev);
+    const WsPlan p = plan_ws(c, 1);
+    char* scr = (char*)st->scratch;
+    const int diag = c->diagA ? 1 : 0;
+    auto add = [&](int phase, MixJob jb) {
+        jb.dtype = c->dtype;
+        jb.nblk = mix_job_blocks(jb);
+        ph[phase].push_back(jb);
+    };
+    if (c->full) {
+        MixJob jb{};
+        jb.kind = MIX_FULL;
+        jb.f.a = sa;
+        jb.f.G = c->Gfull;
+        add(0, jb);
     }
+    if (c->dense || c->svd) {
+        const void* wj = nullptr;
+        if (c->svd) {
+            MixJob jv{};
+            jv.kind = MIX_SVDP;
+            jv.v.Ut = c->Ut;
+            jv.v.Ut_lo = (const unsigned short*)c->Ut_lo;
+            jv.v.sigma = c->sig;
+            jv.v.N = c->N;
+            jv.v.Np = c->Np;
+            jv.v.Rsp = c->Rsp;
+            jv.v.u_base = sa.uring;
+            jv.v.stepp = sa.step;
+            jv.v.slot_stride = c->N;
+            jv.v.w = scr + p.svdw_off;
+            wj = jv.v.w;
+            add(0, jv);
+        }
+        MixJob jg{};
+        jg.kind = MIX_GEMV;
+        jg.g = c->svd ? make_gemv_job(c->dtype, c->Vt, c->Vt_lo, c->N, c->Np, c->Rs, wj, sa.uring, sa.step, c->N,
+                                      scr + p.part_off, p.nchunk, gemv_tile(c))
+                      : make_gemv_job(c->dtype, c->C, c->Clo, c->N, c->Np, c->N, nullptr, sa.uring, sa.step, c->N,
+                                      scr + p.part_off, p.nchunk, gemv_tile(c));
+        add(1, jg);
+        MixJob jb{};
+        jb.kind = MIX_BDF;
+        jb.mode = diag;
+        jb.b.a = sa;
+        jb.b.part = scr + p.part_off;
+        jb.b.nchunk = p.nchunk;
+        jb.b.pb = 1;
+        jb.b.nblk = (c->N + 255) / 256;
+        add(2, jb);
+    } else {
+        // with a dense stiffness the projections come from the previous step's Helmholtz
+        // kernel (phase 3)
+        if (diag) {
+            MixJob jp{};
+            jp.kind = MIX_PROJ;
+            const SkewPairs sk = skew_of(c);
+            jp.p.BCt = proj_op(c);
+            jp.p.BCt_lo = (const unsigned short*)proj_op_lo(c);
+            jp.p.lam = c->lam;
+            jp.p.N = c->N;
+            jp.p.Np = c->Np;
+            jp.p.Rp = c->Rp;
+            jp.p.layout = sk.layout;
+            jp.p.P = sk.P;
+            jp.p.R = sk.R;
+            jp.p.u_base = sa.uring;
+            jp.p.stepp = sa.step;
+            jp.p.slot_stride = c->N;
+            jp.p.w = sa.st;
+            jp.p.nblk = proj1_blocks(c->Rp, sk);
+            add(1, jp);
+        }
+        MixJob js{};
+        js.kind = MIX_SCAT;
+        js.mode = diag ? 1 : 2;
+        js.s.Af = c->Af;
+        js.s.Af_lo = (const unsigned short*)c->Af_lo;
+        js.s.N = c->N;
+        js.s.Rp = c->Rp;
+        js.s.w = sa.st;
+        js.s.a = sa;
+        js.s.nblk = (c->N + 3) / 4;
+        add(2, js);
+    }
+    if (!diag) {
+        MixJob jh{};
+        jh.kind = MIX_HELM;
+        jh.h = helm_job(c, sa);
+        if (c->dense || c->svd) {
+            jh.h.np = 0;
+            jh.h.Mst = nullptr;
+        }
+        add(3, jh);
+    }
+}
+
+// Build and upload the job tables of a set of pairs from their current levels.
+rom_status build_plan(MultiPlan* pl, int n, const rom_ctx* ctxs, const rom_state* states) {
+    pl->stream = ctxs[0]->stream;
+    std::vector<MixJob> ph[2][kMixPhases];
+    std::vector<FinJob> fin[2];
+    for (int q = 0; q < n; ++q) {
+        rom_ctx c = ctxs[q];
+        rom_state st = states[q];
+        pl->ctxs.push_back(c);
+        pl->states.push_back(st);
+        pl->wsgen.push_back(c->ws_gen);
+        pl->sgen.push_back(st->sgen);
+        pl->par.push_back((char)(st->h_step & 1));
+        if (st->B != 1) {
+            pl->batched.push_back(q);
+            continue;
+        }
+        for (int k = 0; k < 2; ++k) {
+            pair_jobs(c, st, st->h_step + k, ph[k]);
+            FinJob fj{};
+            fj.a = step_args(st, st->h_step + k);      // counter slots of the last level's parity
+            fin[k].push_back(fj);
+        }
+    }
+    // blob: tables per parity and phase (block ranges assigned in order), then the
+    // closing jobs
+    std::vector<char> blob;
+    auto put_bytes = [&](const void* src, size_t bytes) {
+        const size_t o = (blob.size() + 255) & ~(size_t)255;
+        blob.resize(o + bytes);
+        if (bytes) memcpy(blob.data() + o, src, bytes);
+        return o;
+    };
+    for (int k = 0; k < 2; ++k)
+        for (int f = 0; f < kMixPhases; ++f) {
+            int b = 0;
+            size_t lds = 0;
+            for (auto& jb : ph[k][f]) {
+                jb.blk0 = b;
+                b += jb.nblk;
+                const size_t l = mix_job_lds(jb);
+                if (l > lds) lds = l;
+            }
+            pl->off[k][f] = put_bytes(ph[k][f].data(), sizeof(MixJob) * ph[k][f].size());
+            pl->njobs[k][f] = (int)ph[k][f].size();
+            pl->blocks[k][f] = b;
+            pl->lds[k][f] = lds;
+        }
+    for (int k = 0; k < 2; ++k) pl->fin_off[k] = put_bytes(fin[k].data(), sizeof(FinJob) * fin[k].size());
+    pl->nfin = (int)fin[0].size();
+    if (!blob.empty()) {
+        HIPCHK(hipMalloc((void**)&pl->dev, blob.size()));
+        HIPCHK(hipMemcpy(pl->dev, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    }
+    return ROM_OK;
+}
+
+// Step k of a call (levels h_step + k of every pair).
+rom_status multi_enqueue_step(MultiPlan* pl, int64_t k) {
+    hipStream_t stream = pl->stream;
+    const int par = (int)(k & 1);
+    for (int f = 0; f < kMixPhases; ++f)
+        launch_mix((const MixJob*)(pl->dev + pl->off[par][f]), pl->njobs[par][f], pl->blocks[par][f], pl->lds[par][f],
+                   stream);
+    for (int q : pl->batched) TRYS(enqueue_step(pl->ctxs[q], pl->states[q], stream, pl->states[q]->h_step + k));
+    HIPCHK(hipGetLastError());
+    return ROM_OK;
+}
+
+void multi_enqueue_close(MultiPlan* pl, int64_t nsteps) {
+    launch_close_group((const FinJob*)(pl->dev + pl->fin_off[nsteps & 1]), pl->nfin, pl->stream);
+    for (int q : pl->batched) launch_close(step_args(pl->states[q], pl->states[q]->h_step + nsteps), pl->stream);
+}
+
+rom_status multi_graph(MultiPlan* pl, int len, int close, hipGraphExec_t* out) {
+    hipGraphExec_t& gx = pl->graph[close][len];
+    if (!gx) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+        rom_status cst = ROM_OK;
+        for (int k = 0; k < len && cst == ROM_OK; ++k) cst = multi_enqueue_step(pl, k);
+        if (cst == ROM_OK && close) multi_enqueue_close(pl, len);
+        hipError_t ee = hipStreamEndCapture(pl->stream, &g);
+        if (cst != ROM_OK) {
+            if (g) hipGraphDestroy(g);
+            return cst;
+        }
+        if (ee != hipSuccess) return fail(ROM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ee));
+        hipError_t ie = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            gx = nullptr;
+            return fail(ROM_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+        }
+        ie = hipGraphUpload(gx, pl->stream);
+        if (ie != hipSuccess) return fail(ROM_E_DEVICE, "graph upload failed: %s", hipGetErrorString(ie));
+    }
+    *out = gx;
+    return ROM_OK;
 }
 
 }  // namespace
@@ -1762,163 +1987,44 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
     }
     if (nsteps == 0) return ROM_OK;
 
-    // ---- job tables, one set per parity of the step index k (pair q's level is
-    // h_step + k, and its kernels take the counter slots of that level's parity)
-    std::vector<Group> groups[2];
-    std::vector<int> batched;
-    for (int par = 0; par < 2; ++par)
-    for (int q = 0; q < n; ++q) {
-        rom_ctx c = ctxs[q];
-        rom_state st = states[q];
-        if (st->B != 1 || c->svd || c->full) {   // batches, SVD- and full-form states step on their own
-            if (par == 0) batched.push_back(q);
-            continue;
+    // the cached plan of this set of pairs (most recently used last), or a new one
+    std::unique_lock<std::mutex> lk(g_plan_mu);
+    MultiPlan* pl = nullptr;
+    for (size_t q = 0; q < g_plans.size(); ++q)
+        if (plan_matches(g_plans[q], n, ctxs, states)) {
+            pl = g_plans[q];
+            g_plans.erase(g_plans.begin() + (long)q);
+            break;
         }
-        const StepArgs sa = step_args(st, st->h_step + par);
-        const int dense = c->dense ? 1 : 0, diag = c->diagA ? 1 : 0;
-        Group* g = nullptr;
-        for (auto& x : groups[par])
-            if (x.dense == dense && x.dtype == c->dtype && x.diag == diag) g = &x;
-        if (!g) {
-            groups[par].emplace_back();
-            g = &groups[par].back();
-            g->dense = dense;
-            g->dtype = c->dtype;
-            g->diag = diag;
-            g->tile = gemv_tile(c);
+    if (!pl) {
+        pl = new MultiPlan();
+        rom_status bs = build_plan(pl, n, ctxs, states);
+        if (bs != ROM_OK) {
+            delete pl;
+            return bs;
         }
-        const WsPlan p = plan_ws(c, 1);
-        char* scr = (char*)st->scratch;
-        if (dense) {
-            GemvJob jb = make_gemv_job(c->dtype, c->C, c->Clo, c->N, c->Np, c->N, nullptr, sa.uring, sa.step, c->N,
-                                       scr + p.part_off, p.nchunk, gemv_tile(c));
-            jb.blk0 = g->b1;
-            g->b1 += jb.nblk;
-            g->gemv.push_back(jb);
-            BdfJob bj{};
-            bj.a = sa;
-            bj.part = scr + p.part_off;
-            bj.nchunk = p.nchunk;
-            bj.pb = 1;
-            bj.blk0 = g->b2;
-            bj.nblk = (c->N + 255) / 256;
-            g->b2 += bj.nblk;
-            g->bdf.push_back(bj);
-        } else {
-            // with a dense stiffness the projections come from the previous step's
-            // Helmholtz kernel (phase 3)
-            if (diag) {
-                Proj1Job pj{};
-                const SkewPairs sk = skew_of(c);
-                pj.BCt = proj_op(c);
-                pj.BCt_lo = (const unsigned short*)proj_op_lo(c);
-                pj.lam = c->lam;
-                pj.N = c->N;
-                pj.Np = c->Np;
-                pj.Rp = c->Rp;
-                pj.layout = sk.layout;
-                pj.P = sk.P;
-                pj.R = sk.R;
-                pj.u_base = sa.uring;
-                pj.stepp = sa.step;
-                pj.slot_stride = c->N;
-                pj.w = sa.st;
-                pj.blk0 = g->b1;
-                pj.nblk = proj1_blocks(c->Rp, sk);
-                g->b1 += pj.nblk;
-                g->proj.push_back(pj);
-            }
-            Scat1Job sj{};
-            sj.Af = c->Af;
-            sj.Af_lo = (const unsigned short*)c->Af_lo;
-            sj.N = c->N;
-            sj.Rp = c->Rp;
-            sj.w = sa.st;
-            sj.a = sa;
-            sj.blk0 = g->b2;
-            sj.nblk = (c->N + 3) / 4;
-            g->b2 += sj.nblk;
-            g->scat.push_back(sj);
-            if (c->Rp > g->Rpmax) g->Rpmax = c->Rp;
+        if (g_plans.size() >= kMaxPlans) {
+            delete g_plans.front();
+            g_plans.erase(g_plans.begin());
         }
-        if (!diag) {
-            HelmJob hj = helm_job(c, sa);
-            hj.blk0 = g->b3;
-            g->b3 += hj.nblk;
-            g->helm.push_back(hj);
-        }
-        // the update kernel (phase 2 with a diagonal stiffness, else phase 3) advances
-        // the step and closes the previous level; phase 4, after the last step, closes
-        // the newest one
-        FinJob fj{};
-        fj.a = sa;
-        g->fin.push_back(fj);
-        if (c->Np > g->Npmax) g->Npmax = c->Np;
-        if (c->N > g->Nmax) g->Nmax = c->N;
     }
-    char* dev[2] = {nullptr, nullptr};
-    for (int par = 0; par < 2; ++par) {
-        std::vector<char> blob;
-        for (auto& g : groups[par]) {
-            g.off1 = g.dense ? put(blob, g.gemv) : put(blob, g.proj);
-            g.off2 = g.dense ? put(blob, g.bdf) : put(blob, g.scat);
-            g.off3 = put(blob, g.helm);
-            g.off4 = put(blob, g.fin);
-        }
-        if (!blob.empty()) {
-            hipError_t e = hipMalloc((void**)&dev[par], blob.size());
-            if (e == hipSuccess) e = hipMemcpy(dev[par], blob.data(), blob.size(), hipMemcpyHostToDevice);
-            if (e != hipSuccess) {
-                for (char* d : dev)
-                    if (d) hipFree(d);
-                return fail(ROM_E_DEVICE, "job table upload failed: %s", hipGetErrorString(e));
-            }
-        }
-        for (auto& g : groups[par]) g.dev = dev[par];
-    }
+    g_plans.push_back(pl);
 
-    // step k of this call (levels h_step + k)
-    auto enqueue_all = [&](int64_t k) -> rom_status {
-        for (int phase = 1; phase <= 3; ++phase)
-            for (const auto& g : groups[k & 1]) enqueue_group(g, stream, phase);
-        for (int q : batched) {
-            rom_status st = enqueue_step(ctxs[q], states[q], stream, states[q]->h_step + k);
-            if (st != ROM_OK) return st;
-        }
-        HIPCHK(hipGetLastError());
-        return ROM_OK;
-    };
-
+    // (nsteps - 1) / 64 replays of the 64-step graph, then one graph of the rest with the
+    // closing kernels
     rom_status status = ROM_OK;
-    int64_t left = nsteps, k = 0;
-    hipGraphExec_t gx = nullptr;
-    if (left >= 2 * kGraphChunk) {
-        hipGraph_t gr = nullptr;
-        hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            for (int q = 0; q < kGraphChunk && status == ROM_OK; ++q) status = enqueue_all(q);
-            e = hipStreamEndCapture(stream, &gr);
-            if (status == ROM_OK && e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
-            if (gr) hipGraphDestroy(gr);
-        }
-        if (status == ROM_OK && e != hipSuccess) status = fail(ROM_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-        while (status == ROM_OK && left >= kGraphChunk) {
-            e = hipGraphLaunch(gx, stream);
-            if (e != hipSuccess) status = fail(ROM_E_DEVICE, "graph launch failed: %s", hipGetErrorString(e));
-            left -= kGraphChunk;
-            k += kGraphChunk;
-        }
+    int64_t left = nsteps;
+    while (status == ROM_OK && left > 0) {
+        const int len = left > kGraphChunk ? kGraphChunk : (int)left;
+        const int close = left <= kGraphChunk ? 1 : 0;
+        hipGraphExec_t gx = nullptr;
+        status = multi_graph(pl, len, close, &gx);
+        if (status == ROM_OK && hipGraphLaunch(gx, stream) != hipSuccess)
+            status = fail(ROM_E_DEVICE, "graph launch failed");
+        left -= len;
     }
-    for (; status == ROM_OK && left > 0; --left, ++k) status = enqueue_all(k);
-    if (status == ROM_OK) {
-        // the newest level of every state is still to be closed
-        for (const auto& g : groups[nsteps & 1]) enqueue_group(g, stream, 4);
-        for (int q : batched) launch_close(step_args(states[q], states[q]->h_step + nsteps), stream);
-    }
+    lk.unlock();
     hipError_t se = hipStreamSynchronize(stream);
-    if (gx) hipGraphExecDestroy(gx);
-    for (char* d : dev)
-        if (d) hipFree(d);
     if (status != ROM_OK) return status;
     if (se != hipSuccess) return fail(ROM_E_DEVICE, "rom_step_multi: %s", hipGetErrorString(se));
     long long worst = LLONG_MAX;
@@ -1936,6 +2042,8 @@ extern "C" rom_status rom_step_multi(int32_t n, const rom_ctx* ctxs, const rom_s
     return ROM_OK;
 }
 
+static void forget_plans_of(const void* obj) { forget_plans(obj); }
+
 extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* value) {
     if (!value) return fail(ROM_E_INVALID, "value is NULL");
     switch (what) {
@@ -1949,9 +2057,18 @@ extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* v
         case 7: if (!c) break; *value = skew_of(c).layout; return ROM_OK;
         case 8: if (!c) break; *value = c->dense ? 0 : c->svd ? 2 : 1; return ROM_OK;
         case 9: if (!c) break; *value = c->Rs; return ROM_OK;
+        case 10: {
+            if (!s) break;
+            long long bad = LLONG_MAX;
+            HIPCHK(hipStreamSynchronize(s->ctx->stream));
+            HIPCHK(hipMemcpy(&bad, s->a.bad, sizeof(long long), hipMemcpyDeviceToHost));
+            *value = bad == LLONG_MAX ? -1 : (int64_t)bad;
+            return ROM_OK;
+        }
         default: return fail(ROM_E_INVALID, "unknown query %d", what);
     }
-    return fail(ROM_E_INVALID, "query %d needs a %s", what, what == 1 || what >= 5 ? "state" : "context");
+    return fail(ROM_E_INVALID, "query %d needs a %s", what,
+                what == 1 || (what >= 5 && what <= 6) || what == 10 ? "state" : "context");
 }
 
 extern "C" int32_t rom_tile_count(int32_t kind) {

@@ -115,9 +115,51 @@ struct HelmJob {           // dense-stiffness Helmholtz apply, one trajectory; w
     int nh, np;                    // row blocks of the Helmholtz part, of the projections (0: none)
     int blk0, nblk;                // grouped launches: first block, blocks (nh + np)
 };
+struct SvdProj {           // SVD form, first product: w_r = sigma_r U[:,r]^T u, one trajectory
+    const void* Ut;                // [Rsp][Np] columns of U as rows
+    const unsigned short* Ut_lo;
+    const void* sigma;             // [Rsp] (accumulation type)
+    int N, Np, Rsp;
+    const double* u_base;
+    const long long* stepp;
+    long long slot_stride;
+    void* w;                       // [Rsp] (accumulation type)
+};
+struct FullJob {           // full form: zeroth-mode and mass terms of a level, one trajectory
+    StepArgs a;
+    const double* G;               // [N][2 Np]
+};
 struct FinJob {            // closing energy sum of the newest level, one state
     StepArgs a;
 };
+
+// A job of a mixed launch over a heterogeneous work table (rom_step_multi): one phase of
+// one one-trajectory state, of any kind and number format.  A step is at most four such
+// launches, whatever the mix of N, R, formats, stiffness kinds and operator forms:
+//   phase 0: full-form terms (MIX_FULL), SVD first products (MIX_SVDP)
+//   phase 1: dense / SVD slab streams (MIX_GEMV), CP projections, diagonal stiffness (MIX_PROJ)
+//   phase 2: BDF update or right-hand side from partials (MIX_BDF), CP scatter (MIX_SCAT)
+//   phase 3: Helmholtz apply, with the next projections for CP states (MIX_HELM)
+enum MixKind { MIX_GEMV = 0, MIX_PROJ = 1, MIX_BDF = 2, MIX_SCAT = 3, MIX_HELM = 4, MIX_SVDP = 5, MIX_FULL = 6 };
+struct MixJob {
+    int kind, dtype;
+    int mode;                      // MIX_BDF: 1 = diagonal-stiffness update; MIX_SCAT: scatter mode 1 or 2
+    int blk0, nblk;
+    union {
+        GemvJob g;
+        Proj1Job p;
+        BdfJob b;
+        Scat1Job s;
+        HelmJob h;
+        SvdProj v;
+        FullJob f;
+    };
+};
+// Blocks and dynamic LDS bytes a mixed job needs; the launch over a table (jobs sorted by
+// blk0, `blocks` in total, `lds` the largest need).
+int mix_job_blocks(const MixJob& jb);
+size_t mix_job_lds(const MixJob& jb);
+void launch_mix(const MixJob* jobs_dev, int njobs, int blocks, size_t lds, hipStream_t s);
 
 // ---------------------------------------------------------------- launchers (k_*.hip)
 
@@ -144,19 +186,9 @@ void launch_svd_proj(int dt, const void* Ut, const void* Ut_lo, const void* sigm
 GemvJob make_gemv_job(int dt, const void* C, const void* Clo, int N, int Np, int J, const void* wj,
                       const double* u_base, const long long* stepp, long long slot_stride, void* part, int nchunk,
                       GemvTile t);
-void launch_dense_gemv_group(int dt, const GemvJob* jobs_dev, int njobs, int blocks, int Npmax, GemvTile t,
-                             hipStream_t s);
-// grouped single-trajectory CP and BDF kernels; scatter mode 1 = diagonal stiffness
-// (update fused), 2 = dense stiffness (right-hand side); bdf diag likewise
-void launch_cp_proj1_group(int dt, const Proj1Job* jobs_dev, int njobs, int blocks, int Npmax, hipStream_t s);
-void launch_cp_scatter1_group(int dt, int mode, const Scat1Job* jobs_dev, int njobs, int blocks, int Rpmax,
-                              hipStream_t s);
-void launch_bdf_group(int acc_f64, int diag, const BdfJob* jobs_dev, int njobs, int blocks, hipStream_t s);
 // Dense-stiffness apply of a step with, for CP states (np > 0), the projections of the
-// new level (k_contract.hip); one state, or grouped states (proj: some job has np > 0).
+// new level (k_contract.hip), one state.
 void launch_helm_proj(int dt, const HelmJob& jb, hipStream_t s);
-void launch_helm_proj_group(int dt, const HelmJob* jobs_dev, int njobs, int blocks, int Nmax, int Npmax, int proj,
-                            hipStream_t s);
 // Closing energy sum of the newest level when it is still pending (after the last step
 // of a sequence; one block per state).
 void launch_close(const StepArgs& a, hipStream_t s);

@@ -125,3 +125,89 @@ def test_multi_mixed_level_parities(torch_gpu):
         assert nm == na == 132, (q, nm, na)
         assert np.array_equal(um, ua), q
         assert np.array_equal(multi[q].energy()[1], a.energy()[1]), q
+
+
+def _svd_rom(N, R, seed, dt):
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((N, R)) / np.sqrt(N)
+    sig = 1.0 / (1.0 + np.arange(R))
+    V = rng.standard_normal((N, N, R)) / N
+    A = romsynth.stiffness_spd(N, seed, cfg=63)
+    return rg.Rom(N, 1e-3, 1e-3, A, svd=(U, sig, V), dtype=dt), romsynth.initial_u(N, [seed], cfg=63)
+
+
+def _full_rom(N, pairs, seed, dt, A_kind, dense):
+    p = romsynth.make_problem(N, pairs=pairs, eps=1e-6, nu=1e-3, dt=1e-3, A=A_kind, cfg=64 + seed,
+                              dense=dense, cp=not dense)
+    C1, C2, c0, a0 = romsynth.zeroth_terms(N, seed=seed, cfg=64, scale=0.1)
+    full = dict(M=romsynth.mass_spd(N, seed=seed, cfg=64, norm=0.1), C1=C1, C2=C2, c0=c0, a0=a0)
+    ops = dict(C=p.C) if dense else dict(lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf)
+    return rg.Rom(N, p.nu, p.dt, p.A, **ops, full=full, dtype=dt), p.u0
+
+
+def test_multi_all_forms_equal_alone(torch_gpu):
+    """One work table over every one-trajectory form: dense and CP (general and pair form)
+    with diagonal and SPD stiffness in four formats, SVD states and full-form states (dense
+    and CP), plus a batch; then a second call on the same set (the cached tables and
+    graphs): each state equals rom_step alone over both calls, to the bit."""
+    pairs = []
+    specs = [(41, 20, True, "fp64", "spd"), (53, 25, False, "bf16", "spd"), (29, 15, False, "bf16x3", "diag"),
+             (70, 35, True, "bf16", "diag"), (45, 20, False, "fp32", "diag")]
+    for q, (N, pr, dense, dt, A) in enumerate(specs):
+        p = romsynth.make_problem(N, pairs=pr, eps=1e-6, nu=1e-3, dt=1e-3, A=A, cfg=70 + q, dense=dense, cp=not dense)
+        r = rg.Rom.from_problem(p, dense=dense, dtype=dt)
+        if q == 4:
+            rg.rom_set_tile(r.handle, 4, 0)                      # general form of skew-paired factors
+        pairs.append((r, p.u0))
+    pairs.append(_svd_rom(48, 9, 1, "fp32"))
+    pairs.append(_svd_rom(33, 5, 2, "bf16x3"))
+    pairs.append(_full_rom(37, 18, 3, "fp32", "spd", False))
+    pairs.append(_full_rom(31, 15, 4, "fp64", "diag", True))
+    pb = romsynth.make_problem(24, pairs=12, eps=1e-6, A="spd", batch=3, cfg=79, dense=False)
+    pairs.append((rg.Rom.from_problem(pb, dense=False, dtype="fp32", max_batch=3), pb.u0))
+    multi = [r.state(u0) for r, u0 in pairs]
+    ctxs = [r.handle for r, _ in pairs]
+    _say(f"rom_step_multi over {len(pairs)} pairs of every form: 150 then 37 steps")
+    rg.rom_step_multi(ctxs, [s.handle for s in multi], 150)
+    rg.rom_step_multi(ctxs, [s.handle for s in multi], 37)
+    for q, ((r, u0), sm) in enumerate(zip(pairs, multi)):
+        a = r.state(u0)
+        a.step(187)
+        assert np.array_equal(sm.get()[0], a.get()[0]), q
+        assert np.array_equal(sm.energy()[1], a.energy()[1]), q
+        a.close()
+
+
+def test_multi_reports_the_failing_state(torch_gpu):
+    """A non-finite trajectory in a set: rom_step_multi reports it, and the per-state query
+    names that state only; the other states' results are those of stepping alone."""
+    p0, r0 = _build(SPECS[0], 90)
+    p1, r1 = _build(SPECS[3], 91)
+    bad_u0 = p1.u0.copy()
+    bad_u0[0, 5] = np.nan
+    s0, s1 = r0.state(p0.u0), r1.state(bad_u0)
+    _say("rom_step_multi with one non-finite state")
+    with pytest.raises(rg.NonFinite) as ei:
+        rg.rom_step_multi([r0.handle, r1.handle], [s0.handle, s1.handle], 20)
+    assert ei.value.first_bad == 0
+    assert rg.rom_query(r0.handle, s0.handle, 10) == -1
+    assert rg.rom_query(r1.handle, s1.handle, 10) == 0
+    a = r0.state(p0.u0)
+    a.step(20)
+    assert np.array_equal(s0.get()[0], a.get()[0])
+
+
+def test_multi_plan_dropped_with_its_states(torch_gpu):
+    """A cached set whose state is destroyed is not reused: a new state (possibly at the same
+    address) in the same position steps correctly."""
+    p, r = _build(SPECS[0], 92)
+    p2, r2 = _build(SPECS[3], 93)
+    for rnd in range(3):
+        _say(f"round {rnd}: new states, same contexts")
+        s, s2 = r.state(p.u0), r2.state(p2.u0)
+        rg.rom_step_multi([r.handle, r2.handle], [s.handle, s2.handle], 70)
+        a = r.state(p.u0)
+        a.step(70)
+        assert np.array_equal(s.get()[0], a.get()[0])
+        for x in (s, s2, a):
+            x.close()
