@@ -245,6 +245,20 @@ rom_status rom_state_get(rom_ctx ctx, rom_state st, double *u_hist, double *y_hi
 rom_status rom_state_set(rom_ctx ctx, rom_state st, const double *u_hist,
                          const double *y_hist, int64_t step);
 
+/* Continuous batching: replace trajectory b (0 <= b < batch) of a state by another one at
+ * the state's current level n, leaving the other trajectories as they are.  u_hist [3][N]
+ * holds the new trajectory's u at levels n, n-1, n-2 and y_hist [2][N] its C(u)u at
+ * levels n-1, n-2 (host FP64), as rom_state_set takes for a whole state; E^n of trajectory
+ * b is logged from u_hist[0].  A trajectory that has taken its own start-up steps (BDF1
+ * and BDF2 from its level 0) joins a state at n >= 2 and continues with BDF3, as from its
+ * own level 2; zeros make an idle slot (it stays zero).  clear_health != 0 also clears
+ * the state's non-finite flag (for a caller that replaced every failed trajectory; see
+ * rom_query what = 10 and rom_energy).  Every form and format (a full-form state
+ * recomputes its zeroth-mode and mass terms from the u history; a one-trajectory CP state
+ * with a dense stiffness recomputes the projections of level n).  Synchronizes. */
+rom_status rom_state_set_slot(rom_ctx ctx, rom_state st, int32_t b, const double *u_hist, const double *y_hist,
+                              int32_t clear_health);
+
 /* Copy the current coefficients u^n [batch][N] into caller device memory.  Async. */
 rom_status rom_state_u(rom_ctx ctx, rom_state st, double *u_dev);
 

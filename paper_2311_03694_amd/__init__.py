@@ -7,6 +7,6 @@ package holds its sources (csrc/), its build script and a thin ctypes binding.
 from .binding import (  # noqa: F401
     DTYPES, EXPORTS, LIB_PATH, NonFinite, Rom, RomError, RomState, lib, rom_create, rom_destroy,
     rom_energy, rom_last_error, rom_nonlinear, rom_nonlinear_noalloc, rom_nonlinear_timed, rom_query, rom_set_tile, rom_state_create,
-    rom_state_destroy, rom_state_get, rom_state_set, rom_state_u, rom_step, rom_step_async,
+    rom_state_destroy, rom_state_get, rom_state_set, rom_state_set_slot, rom_state_u, rom_step, rom_step_async,
     rom_step_multi, rom_step_prepare, rom_step_sync, rom_tile_count, rom_cp_skew_layout, rom_cp_als, rom_cp_als_skew,
 )

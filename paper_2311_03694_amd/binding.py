@@ -25,7 +25,7 @@ EXPORTS = ["rom_create", "rom_destroy", "rom_nonlinear", "rom_nonlinear_noalloc"
            "rom_state_create",
            "rom_state_destroy",
            "rom_step", "rom_step_async", "rom_step_sync", "rom_step_prepare", "rom_energy", "rom_state_get",
-           "rom_state_set", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
+           "rom_state_set", "rom_state_set_slot", "rom_state_u", "rom_step_multi", "rom_query", "rom_set_tile",
            "rom_tile_count", "rom_cp_skew_layout", "rom_create_svd", "rom_create_full", "rom_cp_als", "rom_cp_als_skew",
            "rom_last_error"]
 
@@ -93,6 +93,8 @@ def lib():
     L.rom_state_get.argtypes = [_vp, _vp, _d, _d, _i64p]
     L.rom_state_set.argtypes = [_vp, _vp, _d, _d, ctypes.c_int64]
     L.rom_state_u.argtypes = [_vp, _vp, _vp]
+    L.rom_state_set_slot.argtypes = [_vp, _vp, ctypes.c_int32, _d, _d, ctypes.c_int32]
+    L.rom_state_set_slot.restype = ctypes.c_int
     L.rom_step_multi.argtypes = [ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.c_int64, _i64p]
     L.rom_query.argtypes = [_vp, _vp, ctypes.c_int32, _i64p]
@@ -292,6 +294,12 @@ def rom_state_set(ctx: int, st: int, u_hist, y_hist, step: int):
     _check(lib().rom_state_set(ctx, st, _ptr(uh), _ptr(yh), int(step)))
 
 
+def rom_state_set_slot(ctx: int, st: int, b: int, u_hist, y_hist, clear_health: bool = False):
+    uh = _host(u_hist)
+    yh = _host(y_hist)
+    _check(lib().rom_state_set_slot(ctx, st, int(b), _ptr(uh), _ptr(yh), 1 if clear_health else 0))
+
+
 def rom_state_u(ctx: int, st: int, u_dev):
     _check(lib().rom_state_u(ctx, st, _dev_ptr(u_dev)))
 
@@ -404,6 +412,9 @@ class RomState:
 
     def set(self, u_hist, y_hist, step):
         rom_state_set(self.rom.handle, self.handle, u_hist, y_hist, step)
+
+    def set_slot(self, b, u_hist, y_hist, clear_health=False):
+        rom_state_set_slot(self.rom.handle, self.handle, b, u_hist, y_hist, clear_health)
 
     @property
     def step_count(self) -> int:

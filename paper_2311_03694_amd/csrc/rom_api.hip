@@ -14,6 +14,7 @@
 #include "rom.h"
 #include "als.h"
 #include "rom_dev.h"
+#include "kstep.h"
 
 using namespace rom;
 
@@ -123,6 +124,7 @@ struct rom_state_s {
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     double* xfull = nullptr;            // full form, batches: [Bpad][2Np] operand of X G^T
+    double* slot_stage = nullptr;       // rom_state_set_slot: [5][N] staging of one history
     int sgen = 0;                       // bumped when scratch or the energy log moves
     long long* cnt = nullptr;           // the two slots of the device step counter
     // captured chunks of len = 1..64 steps, per parity of the first level (the kernels of
@@ -1384,6 +1386,7 @@ extern "C" void rom_state_destroy(rom_state s) {
     for (void* p : s->allocs) hipFree(p);
     if (s->a.elog) hipFree(s->a.elog);
     if (s->scratch) hipFree(s->scratch);
+    if (s->slot_stage) hipFree(s->slot_stage);
     delete s;
 }
 
@@ -1679,6 +1682,61 @@ extern "C" rom_status rom_state_set(rom_ctx c, rom_state s, const double* u_hist
     seed_projections(c, step_args(s, step), c->stream);
     if (s->a.batched) launch_prep_ucv(s->a, s->a.uring + (size_t)(step % 3) * BN, c->stream);
     HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ROM_OK;
+}
+
+namespace {
+
+// Trajectory b of a state at level n from h [5][N] (u^n, u^{n-1}, u^{n-2}, y^{n-1},
+// y^{n-2}; levels below 0 skipped): the rings, the batched operand copies of level n, and
+// E^n in the energy log.  One block.
+__global__ __launch_bounds__(256) void k_set_slot(StepArgs a, long long n, int b, const double* __restrict__ h) {
+    __shared__ double red[4];
+    const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N;
+    double e = 0.0;
+    for (int i = threadIdx.x; i < a.N; i += blockDim.x) {
+        for (int q = 0; q < 3; ++q)
+            if (n - q >= 0) a.uring[(size_t)slot_of(n - q) * BN + off + i] = h[(size_t)q * a.N + i];
+        for (int q = 0; q < 2; ++q)
+            if (n - 1 - q >= 0) a.yring[(size_t)slot_of(n - 1 - q) * BN + off + i] = h[(size_t)(3 + q) * a.N + i];
+        const double u = h[i];
+        if (a.batched) write_ucv(a, b, i, u);
+        e += u * u;
+    }
+    const double sum = block_sum(e, red);
+    if (threadIdx.x == 0 && n < a.elog_cap) a.elog[(size_t)n * a.B + b] = 0.5 * sum;
+}
+
+}  // namespace
+
+extern "C" rom_status rom_state_set_slot(rom_ctx c, rom_state s, int32_t b, const double* u_hist,
+                                         const double* y_hist, int32_t clear_health) {
+    if (!c || !s || s->ctx != c) return fail(ROM_E_INVALID, "bad ctx/state");
+    if (b < 0 || b >= s->B) return fail(ROM_E_INVALID, "slot %d outside [0, %d)", b, s->B);
+    if (!u_hist || !y_hist) return fail(ROM_E_INVALID, "u_hist / y_hist is NULL");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const size_t N = c->N;
+    if (!s->slot_stage) {
+        const hipError_t e = hipMalloc((void**)&s->slot_stage, sizeof(double) * 5 * N);
+        if (e != hipSuccess) {
+            s->slot_stage = nullptr;
+            return fail(ROM_E_NOMEM, "slot staging hipMalloc failed: %s", hipGetErrorString(e));
+        }
+        s->bytes += sizeof(double) * 5 * N;
+    }
+    HIPCHK(hipMemcpy(s->slot_stage, u_hist, sizeof(double) * 3 * N, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s->slot_stage + 3 * N, y_hist, sizeof(double) * 2 * N, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_set_slot, dim3(1), dim3(256), 0, c->stream, s->a, (long long)s->h_step, (int)b,
+                       (const double*)s->slot_stage);
+    // a one-trajectory CP state with a dense stiffness carries the projections of its
+    // level from step to step: form them from the new u^n
+    seed_projections(c, step_args(s, s->h_step), c->stream);
+    HIPCHK(hipGetLastError());
+    if (clear_health) {
+        const long long none = LLONG_MAX;
+        HIPCHK(hipMemcpyAsync(s->a.bad, &none, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     return ROM_OK;
 }

@@ -1,9 +1,9 @@
 """Scheduling logic of the serving loop on the host, with a fake device backend
-(deterministic step-time model, byte accounting)."""
+(deterministic step-time model, byte accounting, failure injection)."""
 import numpy as np
 import pytest
 
-from paper_2311_03694_amd.serve import Request, Server, op_key, poisson_requests, summarize
+from paper_2311_03694_amd.serve import RAMP, Request, Server, at_rate, op_key, poisson_requests, summarize
 
 
 class Clock:
@@ -17,66 +17,108 @@ class Clock:
         self.t += max(dt, 0.0)
 
 
-class FakeBackend:
-    """Operators cost N^2 bytes, states N bytes; a chunk of n steps over the active pairs
-    costs n * (1e-6 + 1e-9 * sum N) seconds of virtual time."""
+class FakePool:
+    def __init__(self, key, slots):
+        self.key = key
+        self.occ = [None] * slots          # request id per slot
+        self.bad = [False] * slots
+        self.steps = 0
 
-    def __init__(self, clock):
+
+class FakeBackend:
+    """Operators cost N^2 bytes, pools N * slots bytes plus their steps / 100 (a growing
+    energy log); a chunk of n steps costs n * (1e-6 + 1e-9 * sum N * slots) seconds of
+    virtual time.  Requests in `fail` become non-finite after that many steps."""
+
+    def __init__(self, clock, slots=4, fail=None):
         self.clock = clock
-        self.created = []
-        self.destroyed = []
+        self.pool_slots = slots
+        self.fail = fail or {}
+        self.created, self.destroyed = [], []
         self.live = 0
         self.peak = 0
         self.steps = {}
+        self.pools = []
+
+    def _add(self, n):
+        self.live += n
+        self.peak = max(self.peak, self.live)
 
     def estimate_op_bytes(self, key):
         return key[0] ** 2
 
-    def estimate_state_bytes(self, key):
-        return key[0]
-
     def create_op(self, key):
         self.created.append(key)
-        self.live += key[0] ** 2
-        self.peak = max(self.peak, self.live)
+        self._add(key[0] ** 2)
         return ("op", key), key[0] ** 2
 
     def destroy_op(self, op):
         self.destroyed.append(op[1])
         self.live -= op[1][0] ** 2
 
-    def create_state(self, op, r):
-        self.steps[r.rid] = 0
-        self.live += r.N
-        self.peak = max(self.peak, self.live)
-        return ("st", r), r.N
+    def estimate_pool_bytes(self, key):
+        return key[0] * self.pool_slots + 100
 
-    def destroy_state(self, st):
-        self.live -= st[1].N
+    def create_pool(self, op):
+        p = FakePool(op[1], self.pool_slots)
+        self.pools.append(p)
+        self._add(op[1][0] * self.pool_slots)
+        return p, op[1][0] * self.pool_slots
 
-    def step(self, pairs, n):
-        self.clock.t += n * (1e-6 + 1e-9 * sum(st[1].N for _, st in pairs))
-        for _, st in pairs:
-            self.steps[st[1].rid] += n
+    def destroy_pool(self, pool):
+        self.live -= self.pool_bytes(pool)
 
-    def result(self, st):
-        return np.full(3, float(self.steps[st[1].rid])), float(st[1].rid)
+    def pool_bytes(self, pool):
+        return pool.key[0] * self.pool_slots + pool.steps // 100
+
+    def start(self, op, r):
+        self.steps[r.rid] = min(RAMP, r.nsteps)
+        if r.nsteps <= RAMP:
+            return None, (np.full(3, float(self.steps[r.rid])), float(r.rid))
+        return r.rid, None
+
+    def set_slot(self, pool, slot, hist, clear_health=False):
+        pool.occ[slot] = hist
+        pool.bad[slot] = False
+
+    def step(self, pools, n):
+        self.clock.t += n * (1e-6 + 1e-9 * sum(p.key[0] * self.pool_slots for p in pools))
+        ok = True
+        for p in pools:
+            old = p.steps
+            p.steps += n
+            self.live += p.steps // 100 - old // 100
+            self.peak = max(self.peak, self.live)
+            for b, rid in enumerate(p.occ):
+                if rid is None:
+                    continue
+                self.steps[rid] += n
+                if rid in self.fail and self.steps[rid] >= self.fail[rid]:
+                    p.bad[b] = True
+                    ok = False
+        return ok
+
+    def slot_finite(self, pool):
+        return ~np.array(pool.bad)
+
+    def slot_results(self, pool, slots):
+        return {b: (np.full(3, float(self.steps[pool.occ[b]])), float(pool.occ[b])) for b in slots}
 
 
-def _run(reqs, budget, slots=64, chunk=50):
+def _run(reqs, budget, slots=64, chunk=50, pool_slots=4, fail=None):
     clk = Clock()
-    be = FakeBackend(clk)
+    be = FakeBackend(clk, pool_slots, fail)
     srv = Server(be, budget, max_slots=slots, chunk=chunk, clock=clk, sleep=clk.sleep)
     recs = srv.run(reqs)
     return srv, be, recs, clk
 
 
 def test_every_request_runs_its_steps():
-    reqs = poisson_requests(200, rate=2000.0, Ns=(10, 20, 40), steps_range=(10, 1000), rng_seed=3)
+    reqs = poisson_requests(200, rate=2000.0, Ns=(10, 20, 40), steps_range=(1, 1000), rng_seed=3)
     srv, be, recs, clk = _run(reqs, budget=10 ** 6)
     assert len(recs) == len(reqs)
     for r, rec in zip(reqs, recs):
-        assert rec.rid == r.rid
+        assert rec.rid == r.rid and rec.error is None
         assert be.steps[r.rid] == r.nsteps           # exactly nsteps, never more
         assert rec.u[0] == r.nsteps
         assert r.arrival <= rec.admitted <= rec.done
@@ -85,38 +127,82 @@ def test_every_request_runs_its_steps():
     assert s["latency_p50_s"] == pytest.approx(np.percentile(lat, 50))
     assert s["latency_p99_s"] == pytest.approx(np.percentile(lat, 99))
     assert s["trajectory_steps"] == sum(r.nsteps for r in reqs)
+    assert any(r.nsteps <= RAMP for r in reqs)        # requests done in their start-up steps
 
 
 def test_budget_is_respected_and_operators_shared():
     reqs = [Request(i, 0.0, N=30 if i % 2 else 20, seed=0, kind="cp", dtype="fp32", nsteps=100, u0_seed=i)
             for i in range(40)]
-    budget = 30 ** 2 + 20 ** 2 + 40 * 30
+    budget = 30 ** 2 + 20 ** 2 + 2 * (30 + 20) * 4 + 400
     srv, be, recs, _ = _run(reqs, budget)
     assert be.peak <= budget
+    assert srv.peak_used <= budget
     assert sorted(set(be.created)) == sorted({op_key(r) for r in reqs})
     assert len(be.created) == 2                        # each operator built once, then shared
+    assert all(rec.error is None for rec in recs)
+
+
+def test_pool_bytes_reread_after_chunks():
+    """Pools grow with the steps (their energy logs): the server's accounting follows the
+    backend's byte counts, so the budget holds as the logs grow."""
+    reqs = [Request(i, 0.0, 20, 0, "cp", "fp32", 5000, i) for i in range(8)]
+    srv, be, recs, _ = _run(reqs, budget=10 ** 6)
+    assert srv.used == sum(be.pool_bytes(p.handle) for plist in srv.pools.values() for p in plist) + \
+        sum(v[1] for v in srv.ops.values())
+    assert srv.peak_used >= be.pool_bytes(be.pools[0])
 
 
 def test_eviction_makes_room():
     # two operators that do not fit together: the second waits until the first is
     # unreferenced, then replaces it
     reqs = [Request(0, 0.0, 100, 0, "dense", "fp32", 300, 0), Request(1, 0.0, 90, 0, "dense", "fp32", 100, 1)]
-    srv, be, recs, _ = _run(reqs, budget=100 ** 2 + 200)
-    assert be.peak <= 100 ** 2 + 200
+    budget = 100 ** 2 + 100 * 4 + 200
+    srv, be, recs, _ = _run(reqs, budget=budget)
+    assert be.peak <= budget
     assert be.destroyed == [(100, 0, "dense", "fp32")]
     assert recs[1].admitted >= recs[0].done
 
 
 def test_continuous_batching_admits_mid_flight():
     # a long request is running when a short one arrives: the short one joins the
-    # running batch and finishes first
+    # running pool and finishes first
     reqs = [Request(0, 0.0, 20, 0, "cp", "fp32", 5000, 0), Request(1, 1e-3, 20, 0, "cp", "fp32", 100, 1)]
     srv, be, recs, _ = _run(reqs, budget=10 ** 6, chunk=100)
     assert recs[1].admitted < recs[0].done
     assert recs[1].done < recs[0].done
     assert max(srv.batches) == 2
+    assert len(be.pools) == 1                          # one pool, two slots
 
 
-def test_oversized_request_rejected():
-    with pytest.raises(ValueError):
-        _run([Request(0, 0.0, 100, 0, "dense", "fp32", 10, 0)], budget=100)
+def test_more_requests_than_slots_open_pools():
+    reqs = [Request(i, 0.0, 20, 0, "cp", "fp32", 300, i) for i in range(10)]
+    srv, be, recs, _ = _run(reqs, budget=10 ** 6, pool_slots=4)
+    assert len(be.pools) == 3
+    assert all(rec.error is None and be.steps[rec.rid] == 300 for rec in recs)
+
+
+def test_oversized_request_rejected_others_run():
+    reqs = [Request(0, 0.0, 100, 0, "dense", "fp32", 10, 0), Request(1, 0.0, 5, 0, "cp", "fp32", 30, 1)]
+    srv, be, recs, _ = _run(reqs, budget=200)
+    assert recs[0].error and "rejected" in recs[0].error
+    assert recs[1].error is None and be.steps[1] == 30
+
+
+def test_failed_trajectory_ends_only_its_request():
+    """A trajectory that becomes non-finite ends its own request with an error; its slot
+    is cleared and reused, and the requests sharing its pool complete."""
+    reqs = [Request(i, 0.0, 20, 0, "cp", "fp32", 400, i) for i in range(6)]
+    srv, be, recs, _ = _run(reqs, budget=10 ** 6, chunk=50, fail={2: 120})
+    assert recs[2].error and "non-finite" in recs[2].error
+    for q in (0, 1, 3, 4, 5):
+        assert recs[q].error is None and be.steps[q] == 400
+    s = summarize(recs, 1.0)
+    assert s["failed"] == 1 and s["completed"] == 5
+
+
+def test_at_rate_keeps_order():
+    reqs = poisson_requests(50, rate=10.0, rng_seed=1)
+    slow = at_rate(reqs, 1.0, rng_seed=2)
+    assert [r.rid for r in slow] == [r.rid for r in reqs]
+    assert all(b.arrival > a.arrival for a, b in zip(slow, slow[1:]))
+    assert slow[-1].arrival > reqs[-1].arrival
