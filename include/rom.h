@@ -127,8 +127,10 @@ typedef struct rom_full_terms {
  * of the context take one more FP64 kernel per step (the zeroth-mode and mass terms, an
  * N x 2N GEMV); rom_nonlinear still returns C(u)u alone, and so does the y history of
  * rom_state_get / rom_state_set (each step recomputes the zeroth-mode and mass terms
- * from the u history).  Such states step on their own
- * under rom_step_multi.  Errors as rom_create, plus ROM_E_INVALID for f == NULL or a
+ * from the u history).  The energy logged for such states stays |u|^2/2 (the coefficient
+ * norm that the plain form logs), not u^T M u/2: it is the quantity the blow-up check
+ * and the oracle compare, and it bounds u^T M u/2 within the extreme eigenvalues of M.
+ * Errors as rom_create, plus ROM_E_INVALID for f == NULL or a
  * non-symmetric M (a non-SPD M shows as a non-SPD Helmholtz matrix) and
  * ROM_E_UNSUPPORTED for N > 4096. */
 rom_status rom_create_full(const rom_desc *d, const rom_full_terms *f, rom_ctx *out);

@@ -480,6 +480,20 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, const rom_ful
     }
     if (!d->C && !sv && (long long)d->R * (d->dtype == ROM_FP64 ? 8 : 4) > 65536)
         return fail(ROM_E_UNSUPPORTED, "CP rank %d exceeds the 64 KB LDS staging of the scatter kernel", d->R);
+    // stiffness (and mass matrix): diagonal, or dense; a dense one is solved through an
+    // explicit inverse whose setup and apply stage N doubles in LDS (and the CP projections
+    // of a one-trajectory state stage the right-hand side), so N is limited
+    bool diag = true;
+    {
+        const double* Mh = fd ? fd->M : nullptr;
+        for (long long i = 0; i < N && diag; ++i)
+            for (long long m = 0; m < N; ++m)
+                if (i != m && (d->A[i * N + m] != 0.0 || (Mh && Mh[i * N + m] != 0.0))) {
+                    diag = false;
+                    break;
+                }
+    }
+    if (!diag && N > 4096) return fail(ROM_E_UNSUPPORTED, "a non-diagonal stiffness is limited to N <= 4096");
 
     rom_ctx c = new rom_ctx_s();
     c->N = d->N;
@@ -533,21 +547,9 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, const rom_ful
         c->own_stream = true;
     }
 
-    // ---- stiffness: diagonal detection, Helmholtz data
+    // ---- stiffness: Helmholtz data
     const double* Mh = fd ? fd->M : nullptr;   // mass matrix (NULL: the identity)
-    bool diag = true;
-    for (long long i = 0; i < N && diag; ++i)
-        for (long long m = 0; m < N; ++m)
-            if (i != m && (d->A[i * N + m] != 0.0 || (Mh && Mh[i * N + m] != 0.0))) {
-                diag = false;
-                break;
-            }
     c->diagA = diag;
-    if (!diag && N > 4096) {
-        st = fail(ROM_E_UNSUPPORTED, "a non-diagonal stiffness is limited to N <= 4096");
-        rom_destroy(c);
-        return st;
-    }
     const size_t stage_elems = (size_t)1 << 25;   // 256 MB of FP64 per upload chunk
     double* stage = nullptr;
     const size_t nn = (size_t)N * N;

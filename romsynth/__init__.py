@@ -12,6 +12,7 @@ from .inputs import (  # noqa: F401
     dense_rough,
     stiffness_diag,
     stiffness_spd,
+    stiffness_graded,
     mass_spd,
     zeroth_terms,
     initial_u,

@@ -169,6 +169,17 @@ def stiffness_spd(N: int, seed: int = 0, cfg: int = 3, norm: float = 0.1) -> np.
     return 0.5 * (A + A.T)
 
 
+def stiffness_graded(N: int, lo: float, hi: float, seed: int = 0, cfg: int = 3) -> np.ndarray:
+    """Dense SPD stiffness with eigenvalues log-spaced over [lo, hi] in a random orthonormal
+    basis: A = Q diag(lam) Q^T, Q from the QR factorisation of one standard_normal((N, N))
+    draw from stream 2, then symmetrized."""
+    G = _rng(cfg, STREAM_STIFF, seed).standard_normal((N, N))
+    Q, _ = np.linalg.qr(G)
+    lam = np.logspace(np.log10(lo), np.log10(hi), N)
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T)
+
+
 def mass_spd(N: int, seed: int = 0, cfg: int = 3, norm: float = 0.1, diag: bool = False) -> np.ndarray:
     """Mass matrix M = I + P: P = norm * G G^T / ||G G^T||_2 with G one standard_normal((N, N))
     from stream 4, or (diag=True) P = norm * diag(v) with v one uniform(N) draw."""

@@ -187,3 +187,17 @@ def test_als_skew_rejects_arguments():
                       ((4, 2, None, None, None, None, 1, 1, 0.5, None), b"NULL")]:
         assert L.rom_cp_als_skew(*args) == rg.binding.ROM_E_INVALID
         assert msg in L.rom_last_error()
+
+
+def test_dense_stiffness_size_limit_refused_on_host():
+    """A non-diagonal stiffness is solved through an explicit inverse that stages N doubles
+    in LDS: N > 4096 is refused before any device work (here N = 8200 with CP factors in
+    FP32, whose own LDS staging of u would still fit)."""
+    N, R = 8200, 2
+    A = np.zeros((N, N))
+    A[0, 1] = A[1, 0] = 0.5
+    f = np.zeros((N, R))
+    with pytest.raises(rg.RomError) as ei:
+        rg.rom_create(N, 1e-3, 1e-3, A, lam=np.ones(R), Af=f, Bf=f, Cf=f, dtype="fp32")
+    assert ei.value.status == rg.binding.ROM_E_UNSUPPORTED
+    assert "non-diagonal stiffness" in str(ei.value)

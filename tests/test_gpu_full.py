@@ -11,7 +11,7 @@ import pytest
 import oracle as orc
 import paper_2311_03694_amd as rg
 import romsynth
-from helpers import TRAJ_TOL, rel
+from helpers import TRAJ_TOL, rel, traj_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -196,3 +196,30 @@ def test_full_restart(torch_gpu, form, A):
     assert rel(s2.get()[0][0][0], s1.get()[0][0][0]) < 1e-13
     for x in (s1, s2, rom):
         x.close()
+
+
+@pytest.mark.parametrize("dt", ["fp64", "fp32"])
+def test_full_form_ragged_large_n(torch_gpu, dt):
+    """N = 1100 (padded to 1104 > 1024): the full-form terms kernel stages the history in
+    more than one pass and walks each row of G in more than one chunk.  CP rank 120, SPD
+    stiffness, dense SPD mass matrix, zeroth-mode terms; every level of 25 steps against
+    the oracle."""
+    import romsynth as syn
+    N = 1100
+    _say(f"full form N={N} {dt}")
+    p = syn.make_problem(N, pairs=60, eps=1e-7, nu=5e-4, dt=5e-4, A="spd", cfg=31, dense=False)
+    C1, C2, c0, a0 = syn.zeroth_terms(N, seed=2, cfg=31, scale=0.1)
+    full = dict(M=syn.mass_spd(N, seed=3, cfg=31, norm=0.1), C1=C1, C2=C2, c0=c0, a0=a0)
+    rom = rg.Rom(N, p.nu, p.dt, p.A, lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf, full=full, dtype=dt)
+    st = rom.state(p.u0[0])
+    lv = [p.u0[0].copy()]
+    for _ in range(25):
+        st.step(1)
+        lv.append(st.u()[0].copy())
+    ref = orc.run(N, p.nu, p.dt, p.A, 25, u0=p.u0[0], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf, traj=True, **full)
+    assert ref["status"] == 0
+    err = traj_rel(lv, ref["traj"])
+    _say(f"  max level error {err:.2e}")
+    assert err < TRAJ_TOL[dt], err
+    E = st.energy()[1][:, 0]
+    assert np.max(np.abs(E - ref["E"]) / ref["E"]) < 2 * TRAJ_TOL[dt]
