@@ -370,6 +370,9 @@ class Rom:
     def state(self, u0) -> "RomState":
         return RomState(self, u0)
 
+    def set_tile(self, kind: int, value: int):
+        rom_set_tile(self.handle, kind, value)
+
     def bytes(self) -> int:
         return rom_query(self.handle, None, 0)
 
@@ -419,6 +422,11 @@ class RomState:
     @property
     def step_count(self) -> int:
         return rom_query(self.rom.handle, self.handle, 6)
+
+    @property
+    def resident_blocks(self) -> int:
+        """Blocks of the resident runs this state's steps take from level 2 on (0: none)."""
+        return rom_query(self.rom.handle, self.handle, 11)
 
     def u(self) -> np.ndarray:
         return self.get()[0][0]

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librom.so")
 SOURCES = ["k_als.hip", "k_bdf.hip", "k_contract.hip", "k_dense1.hip", "k_gemm.hip", "k_kr.hip", "k_mfma.hip", "k_multi.hip",
-           "rom_api.hip"]
+           "k_res.hip", "rom_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

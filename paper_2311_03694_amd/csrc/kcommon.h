@@ -80,11 +80,39 @@ template <int V> struct Decode<DT_BF16X3, V> : DecodeBf16<V> {};
 
 // ---------------------------------------------------------------- reductions
 
+// Lane exchange within rows of 16 lanes (DPP row_ror:K, K = 1..15) and lane reads.
+template <int K>
+__device__ __forceinline__ float row_ror(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 + K, 0xF, 0xF, false));
+}
+template <int K>
+__device__ __forceinline__ double row_ror(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x120 + K, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x120 + K, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_read(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the wavefront, the same value in every lane; every lane must be active.
+// Within each row of 16 lanes, v += v rotated by 8, 4, 2, 1 lanes (after the rotation by
+// k the row has period k, the two addends of every sum being the same pair in either
+// order, so all 16 lanes hold the row's sum), then (row0 + row1) + (row2 + row3).  DPP
+// moves and lane reads instead of LDS permutes: a few cycles a step.
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += row_ror<8>(v);
+    v += row_ror<4>(v);
+    v += row_ror<2>(v);
+    v += row_ror<1>(v);
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 // Sum over the block (blockDim.x a multiple of 64, at most 1024); result valid in

@@ -21,12 +21,7 @@ template <int DT> struct LdsU {
     Acc* uw;
 
     // bytes needed for N (padded) coefficients (three 16-byte aligned regions)
-    static __host__ __device__ size_t bytes(int N) {
-        const size_t r = ((size_t)N * sizeof(T) + 15) & ~(size_t)15;
-        if (DT == DT_F64 || DT == DT_F32) return r;
-        const size_t l = DT == DT_BF16X3 ? (((size_t)N * 2 + 15) & ~(size_t)15) : 0;
-        return r + l + (size_t)N * sizeof(Acc);
-    }
+    static __host__ __device__ size_t bytes(int N) { return lds_u_bytes(DT, N); }
 
     __device__ void bind(char* base, int N) {
         const size_t r = ((size_t)N * sizeof(T) + 15) & ~(size_t)15;
@@ -41,28 +36,30 @@ template <int DT> struct LdsU {
         }
     }
 
+    // Entry q of the image from the FP64 value v.
+    __device__ __forceinline__ void put(int q, double v) {
+        if constexpr (DT == DT_F64) {
+            uh[q] = v;
+        } else if constexpr (DT == DT_F32) {
+            uh[q] = (float)v;
+        } else if constexpr (DT == DT_BF16) {
+            const unsigned short h = bf16_bits((float)v);
+            uh[q] = h;
+            uw[q] = bf16_f(h);
+        } else {
+            const float f = (float)v;
+            const unsigned short h = bf16_bits(f);
+            uh[q] = h;
+            ul[q] = bf16_bits(f - bf16_f(h));
+            uw[q] = f;
+        }
+    }
+
     // Convert sgn * u (FP64, N values, sgn = +1 or -1) into an image of Np >= N entries,
     // zero beyond N; call with the whole block, then __syncthreads.
     __device__ void fill(const double* __restrict__ u, int N, int Np, double sgn = 1.0) {
         staged_copy<8, double>(
-            Np, [&](int q) { return q < N ? sgn * u[q] : 0.0; },
-            [&](int q, double v) {
-                if constexpr (DT == DT_F64) {
-                    uh[q] = v;
-                } else if constexpr (DT == DT_F32) {
-                    uh[q] = (float)v;
-                } else if constexpr (DT == DT_BF16) {
-                    const unsigned short h = bf16_bits((float)v);
-                    uh[q] = h;
-                    uw[q] = bf16_f(h);
-                } else {
-                    const float f = (float)v;
-                    const unsigned short h = bf16_bits(f);
-                    uh[q] = h;
-                    ul[q] = bf16_bits(f - bf16_f(h));
-                    uw[q] = f;
-                }
-            });
+            Np, [&](int q) { return q < N ? sgn * u[q] : 0.0; }, [&](int q, double v) { put(q, v); });
     }
 };
 

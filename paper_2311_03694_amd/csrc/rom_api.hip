@@ -2,6 +2,7 @@
 // Helmholtz inverses, workspaces), states (trajectory histories, energy log), and the
 // step sequencer that issues each BDF3/EXT3 step as a short chain of kernels and
 // replays chunks of steps as captured HIP graphs.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -106,8 +107,13 @@ struct rom_ctx_s {
     int ws_gen = 0;
     // tiles (-1 = heuristic)
     // tile[4]: CP pair-form kernels (-1 default = on for one trajectory when the factors
-    // have skew pairs, 0 off, 1 on for batches too)
-    int tile[5] = {-1, -1, -1, -1, -1};
+    // have skew pairs, 0 off, 1 on for batches too); tile[5]: resident one-trajectory CP
+    // steps (-1 default = on where the operator fits on chip, 0 off)
+    int tile[6] = {-1, -1, -1, -1, -1, -1};
+    // resident one-trajectory CP steps: geometry, valid while res_gen == ws_gen
+    // (res_ok 0: not available for this context)
+    int res_gen = -1, res_ok = 0, res_G = 0, res_nrg = 0, res_npg = 0, res_rg = 0, res_pg = 0;
+    size_t res_lds = 0;
     size_t lds_max = 65536;                     // dynamic LDS a batched kernel may take
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -132,6 +138,12 @@ struct rom_state_s {
     // closing kernel at the end; valid while the workspace and scratch generations hold
     hipGraphExec_t graph[2][2][kGraphChunk + 1] = {};
     int graph_gen = -1, graph_sgen = -1;
+    // resident one-trajectory CP steps: message words of x and w, the energy partials of a
+    // run, the tag base (one allocation, res_buf)
+    void* res_buf = nullptr;
+    unsigned long long *res_x = nullptr, *res_w = nullptr;
+    double* res_ep = nullptr;
+    unsigned* res_seq = nullptr;
     bool pending = false;
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -1358,11 +1370,11 @@ rom_status ensure_scratch(rom_state s) {
 
 rom_status reset_counters(rom_state s, long long step) {
     rom_ctx c = s->ctx;
-    const long long big = LLONG_MAX;
     const long long both[2] = {step, step};
+    const long long health[2] = {LLONG_MAX, 0};
     const int none = 0;
     HIPCHK(hipMemcpyAsync(s->cnt, both, sizeof(both), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(s->a.bad, &big, sizeof(long long), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(s->a.bad, health, sizeof(health), hipMemcpyHostToDevice, c->stream));
     const int nocount[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(s->a.closep, &none, sizeof(int), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(s->a.ecount, nocount, sizeof(nocount), hipMemcpyHostToDevice, c->stream));
@@ -1388,6 +1400,7 @@ extern "C" void rom_state_destroy(rom_state s) {
     for (void* p : s->allocs) hipFree(p);
     if (s->a.elog) hipFree(s->a.elog);
     if (s->scratch) hipFree(s->scratch);
+    if (s->res_buf) hipFree(s->res_buf);
     if (s->slot_stage) hipFree(s->slot_stage);
     delete s;
 }
@@ -1431,7 +1444,8 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     TRY(dmalloc((void**)&s->cnt, 2 * sizeof(long long), &s->bytes, &s->allocs));
     a.step = s->cnt;
     a.step_next = s->cnt + 1;
-    TRY(dmalloc((void**)&a.bad, sizeof(long long), &s->bytes, &s->allocs));
+    // bad[0]: first non-finite level; bad[1]: nonzero when a resident run's wait gave up
+    TRY(dmalloc((void**)&a.bad, 2 * sizeof(long long), &s->bytes, &s->allocs));
     TRY(dmalloc((void**)&a.closep, sizeof(int), &s->bytes, &s->allocs));
     if (!c->dense && !c->svd && batch == 1)
         TRY(dmalloc(&a.st, c->Rp * acc_bytes(c->dtype), &s->bytes, &s->allocs));
@@ -1490,11 +1504,18 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
 
 // ============================================================== stepping
 
+static bool res_usable(rom_ctx c, rom_state s);
+static rom_status ensure_res(rom_ctx c, rom_state s);
+
 static rom_status prepare(rom_ctx c, rom_state s, int64_t nsteps) {
     rom_status st = ensure_ws(c, plan_ws(c, s->B).total);
     if (st != ROM_OK) return st;
     st = ensure_scratch(s);
     if (st != ROM_OK) return st;
+    if (res_usable(c, s)) {
+        st = ensure_res(c, s);
+        if (st != ROM_OK) return st;
+    }
     return ensure_elog(s, s->h_step + nsteps + 1);
 }
 
@@ -1568,13 +1589,158 @@ static rom_status walk_graphs(rom_ctx c, rom_state s, long long n0, int64_t nste
     return ROM_OK;
 }
 
+// ---- resident one-trajectory CP runs (k_res.hip)
+
+constexpr int kResMin = 16;        // shortest run worth a launch (shorter tails use graphs)
+constexpr int kResMax = 512;       // levels per run (the energy partials of a run)
+constexpr unsigned kResSpin = 1u << 21;   // polling rounds before a wait gives up (seconds)
+
+// Whether the one-trajectory CP steps of context c run resident, and their geometry:
+// every block of the run co-resident (one per compute unit at most), the block's rows and
+// vectors in its LDS, the vectors a block waits for within kResWaitWords message words.
+static bool res_plan(rom_ctx c) {
+    if (c->res_gen == c->ws_gen) return c->res_ok != 0;
+    c->res_gen = c->ws_gen;
+    c->res_ok = 0;
+    if (c->dense || c->svd || c->full || c->tile[5] == 0) return false;
+    const int wpe = c->dtype == DT_F64 ? 2 : 1;
+    if (2 * c->N > kResWaitWords || c->Rp * wpe > kResWaitWords) return false;
+    int ncu = 0, lds_dev = 0, coop = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess || !coop) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const SkewPairs sk = skew_of(c);
+    const int nrg = (c->N + 3) / 4, npg = proj1_blocks(c->Rp, sk);
+    const int G = std::min(ncu, std::max(nrg, npg));
+    const int rg = (nrg + G - 1) / G, pg = (npg + G - 1) / G;
+    if (rg > 4 || pg > 8) return false;       // the kernel's per-block tables
+    const size_t lds = res_layout(c->dtype, c->N, c->Np, c->Rp, sk.layout, c->diagA ? 0 : 1, rg, pg).total;
+    const size_t cap = (size_t)lds_dev - 2048;   // room for the kernel's static LDS
+    if (lds > cap) return false;
+    int per_cu = 0;
+    if (res_attr(c->dtype, c->N, cap, lds, &per_cu) != hipSuccess || per_cu < 1 || (long long)per_cu * ncu < G) {
+        (void)hipGetLastError();
+        return false;
+    }
+    c->res_ok = 1;
+    c->res_G = G;
+    c->res_nrg = nrg;
+    c->res_npg = npg;
+    c->res_rg = rg;
+    c->res_pg = pg;
+    c->res_lds = lds;
+    return true;
+}
+
+static bool res_usable(rom_ctx c, rom_state s) { return s->B == 1 && res_plan(c); }
+
+// Message words, energy partials and tag base of a state's resident runs (zeroed once;
+// the tag base only grows, so old words never match a later run's tags).
+static rom_status ensure_res(rom_ctx c, rom_state s) {
+    if (s->res_buf) return ROM_OK;
+    const int wpe = c->dtype == DT_F64 ? 2 : 1;
+    const size_t xb = align256(sizeof(unsigned long long) * 2 * c->N);
+    const size_t wb = align256(sizeof(unsigned long long) * (size_t)c->Rp * wpe);
+    const size_t eb = align256(sizeof(double) * (size_t)kResMax * ((c->N + 3) / 4));
+    const size_t total = xb + wb + eb + 256;
+    hipError_t e = hipMalloc(&s->res_buf, total);
+    if (e != hipSuccess) {
+        s->res_buf = nullptr;
+        return fail(ROM_E_NOMEM, "resident step buffers hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+    }
+    s->bytes += total;
+    char* p = (char*)s->res_buf;
+    s->res_x = (unsigned long long*)p;
+    s->res_w = (unsigned long long*)(p + xb);
+    s->res_ep = (double*)(p + xb + wb);
+    s->res_seq = (unsigned*)(p + xb + wb + eb);
+    launch_zero_fill(s->res_buf, total, c->stream);
+    HIPCHK(hipGetLastError());
+    return ROM_OK;
+}
+
+// One resident run of L steps from level n0 >= 2, then its closing block.
+static rom_status launch_resident(rom_ctx c, rom_state s, long long n0, int L) {
+    const SkewPairs sk = skew_of(c);
+    ResJob jb{};
+    jb.a = step_args(s, n0);
+    jb.n0 = n0;
+    jb.nsteps = L;
+    jb.dense_h = c->diagA ? 0 : 1;
+    jb.Af = c->Af;
+    jb.Af_lo = (const unsigned short*)c->Af_lo;
+    if (jb.dense_h) {
+        // order 3 of [3][rows][Np]
+        const size_t rows = sk.layout ? (size_t)(sk.P + sk.R) : (size_t)2 * c->Rp;
+        const size_t off = 2 * rows * c->Np;
+        jb.Pop = (const char*)(sk.layout ? c->Msk : c->Mst) + off * elem_bytes(c->dtype);
+        const void* lo = sk.layout ? c->Msk_lo : c->Mst_lo;
+        jb.Pop_lo = lo ? (const unsigned short*)lo + off : nullptr;
+    } else {
+        jb.Pop = proj_op(c);
+        jb.Pop_lo = (const unsigned short*)proj_op_lo(c);
+    }
+    jb.lam = c->lam;
+    jb.Rp = c->Rp;
+    jb.layout = sk.layout;
+    jb.P = sk.P;
+    jb.R = sk.R;
+    jb.nrg = c->res_nrg;
+    jb.npg = c->res_npg;
+    jb.rg_per = c->res_rg;
+    jb.pg_per = c->res_pg;
+    jb.xmsg = s->res_x;
+    jb.wmsg = s->res_w;
+    jb.epall = s->res_ep;
+    jb.seq = s->res_seq;
+    jb.err = (int*)(s->a.bad + 1);
+    jb.spin_max = kResSpin;
+    hipError_t e = res_launch(c->dtype, jb, c->res_G, c->res_lds, c->stream);
+    if (e != hipSuccess) return fail(ROM_E_DEVICE, "resident step launch failed: %s", hipGetErrorString(e));
+    res_close_launch(step_args(s, n0), step_args(s, n0 + L), n0, L, s->res_ep, c->res_nrg, s->res_seq, c->stream);
+    HIPCHK(hipGetLastError());
+    return ROM_OK;
+}
+
+// The launches of nsteps steps from level n0: resident runs from level 2 on when the
+// context allows them (the first two levels and a tail shorter than kResMin through the
+// captured graphs), else the graphs alone.  launch = false only captures the graphs.
+static rom_status walk_steps(rom_ctx c, rom_state s, long long n0, int64_t nsteps, bool launch) {
+    const int64_t head = n0 < 2 ? std::min<int64_t>(2 - n0, nsteps) : 0;
+    bool res = nsteps - head >= kResMin && res_usable(c, s);
+    if (res && launch) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) res = false;
+    }
+    if (!res) return walk_graphs(c, s, n0, nsteps, launch);
+    long long n = n0;
+    int64_t left = nsteps;
+    if (head > 0) {
+        TRYS(walk_graphs(c, s, n, head, launch));
+        n += head;
+        left -= head;
+    }
+    while (left >= kResMin) {
+        const int L = (int)std::min<int64_t>(left, kResMax);
+        if (launch) TRYS(launch_resident(c, s, n, L));
+        n += L;
+        left -= L;
+    }
+    if (left > 0) TRYS(walk_graphs(c, s, n, left, launch));
+    else if (launch) launch_close(step_args(s, n), c->stream);
+    return ROM_OK;
+}
+
 static rom_status step_enqueue(rom_ctx c, rom_state s, int64_t nsteps) {
     rom_status st = prepare(c, s, nsteps);
     if (st != ROM_OK) return st;
     if (nsteps == 0) return ROM_OK;
     // every update kernel closes the level before its own; the graph of the last chunk
-    // closes the newest one
-    TRYS(walk_graphs(c, s, s->h_step, nsteps, true));
+    // (or the closing kernel after a resident run) closes the newest one
+    TRYS(walk_steps(c, s, s->h_step, nsteps, true));
     HIPCHK(hipGetLastError());
     s->h_step += nsteps;
     s->pending = true;
@@ -1587,8 +1753,8 @@ extern "C" rom_status rom_step_prepare(rom_ctx c, rom_state s, int64_t nsteps) {
     TRYS(prepare(c, s, nsteps));
     // the graphs depend on the parity of the first level only: both parities are
     // captured, so steps of any count may come between this call and the prepared one
-    TRYS(walk_graphs(c, s, s->h_step, nsteps, false));
-    TRYS(walk_graphs(c, s, s->h_step + 1, nsteps, false));
+    TRYS(walk_steps(c, s, s->h_step, nsteps, false));
+    TRYS(walk_steps(c, s, s->h_step + 1, nsteps, false));
     HIPCHK(hipStreamSynchronize(c->stream));
     return ROM_OK;
 }
@@ -1598,8 +1764,11 @@ extern "C" rom_status rom_step_sync(rom_ctx c, rom_state s, int64_t* first_bad_s
     if (first_bad_step) *first_bad_step = -1;
     HIPCHK(hipStreamSynchronize(c->stream));
     s->pending = false;
-    long long bad = LLONG_MAX;
-    HIPCHK(hipMemcpy(&bad, s->a.bad, sizeof(long long), hipMemcpyDeviceToHost));
+    long long health[2] = {LLONG_MAX, 0};
+    HIPCHK(hipMemcpy(health, s->a.bad, sizeof(health), hipMemcpyDeviceToHost));
+    if (health[1] != 0)
+        return fail(ROM_E_DEVICE, "a resident step run gave up waiting for another block's data");
+    const long long bad = health[0];
     if (bad != LLONG_MAX) {
         if (first_bad_step) *first_bad_step = bad;
         return fail(ROM_E_NONFINITE, "trajectory became non-finite at step %lld", bad);
@@ -2125,10 +2294,11 @@ extern "C" rom_status rom_query(rom_ctx c, rom_state s, int32_t what, int64_t* v
             *value = bad == LLONG_MAX ? -1 : (int64_t)bad;
             return ROM_OK;
         }
+        case 11: if (!s) break; *value = res_usable(s->ctx, s) ? s->ctx->res_G : 0; return ROM_OK;
         default: return fail(ROM_E_INVALID, "unknown query %d", what);
     }
     return fail(ROM_E_INVALID, "query %d needs a %s", what,
-                what == 1 || (what >= 5 && what <= 6) || what == 10 ? "state" : "context");
+                what == 1 || (what >= 5 && what <= 6) || what >= 10 ? "state" : "context");
 }
 
 extern "C" int32_t rom_tile_count(int32_t kind) {
@@ -2137,13 +2307,14 @@ extern "C" int32_t rom_tile_count(int32_t kind) {
         case 1: return dense_batched_variants();
         case 2: case 3: return gemm_variants() + mfma_variants();
         case 4: return 2;
+        case 5: return 2;
         default: return 0;
     }
 }
 
 extern "C" rom_status rom_set_tile(rom_ctx c, int32_t kind, int32_t value) {
     if (!c) return fail(ROM_E_INVALID, "ctx is NULL");
-    if (kind < 0 || kind > 4) return fail(ROM_E_INVALID, "unknown kernel kind %d", kind);
+    if (kind < 0 || kind > 5) return fail(ROM_E_INVALID, "unknown kernel kind %d", kind);
     if (value < -1 || value >= rom_tile_count(kind)) return fail(ROM_E_INVALID, "tile index %d out of range", value);
     if (kind == 4 && value == 1 && !c->skew_layout)
         return fail(ROM_E_UNSUPPORTED, "the CP factors have no skew column pairs");

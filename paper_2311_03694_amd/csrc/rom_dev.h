@@ -216,6 +216,77 @@ int proj1_blocks(int Rp, SkewPairs sk);
 int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, int N, int Rp, const void* w, double* y_out,
                        const StepArgs* sa, int mode, hipStream_t s);
 
+// CP, one trajectory, resident operator (k_res.hip): from level 2 on, a run of steps in
+// one cooperative launch whose blocks keep their rows of the order-3 operators in LDS.
+struct ResJob {
+    StepArgs a;                    // counter slots of level n0
+    long long n0;                  // first level of the run (n0 >= 2)
+    int nsteps;                    // levels n0 + 1 .. n0 + nsteps are produced
+    int dense_h;                   // 1: dense stiffness (Hinv_3 rows, M_3 projections)
+    const void* Af;                // [N][Rp]
+    const unsigned short* Af_lo;
+    const void* Pop;               // projection rows of order 3: pair form [P + R][Np] or
+    const unsigned short* Pop_lo;  // [Bf|Cf]^T [2Rp][Np] (times Hinv_3 with a dense stiffness)
+    const void* lam;               // [Rp] accumulation type
+    int Rp, layout, P, R;
+    int nrg, npg;                  // row groups (4 rows), projection groups (4 waves)
+    int rg_per, pg_per;            // groups of each kind per block, at most
+    unsigned long long* xmsg;      // [2N] tagged halves of x (rhs, or u^{n+1} with a diagonal stiffness)
+    unsigned long long* wmsg;      // [Rp * words per entry] tagged words of w
+    double* epall;                 // [nsteps][nrg] energy partials of the levels produced
+    const unsigned* seq;           // tag base of the run
+    int* err;                      // raised when a wait gives up
+    unsigned spin_max;             // polling rounds before a wait gives up
+};
+
+// Bytes of the LDS image of N coefficients in format dt (LdsU<DT>::bytes).
+__host__ __device__ inline size_t lds_u_bytes(int dt, int N) {
+    const size_t eb = dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2;
+    const size_t r = ((size_t)N * eb + 15) & ~(size_t)15;
+    if (dt == DT_F64 || dt == DT_F32) return r;
+    const size_t l = dt == DT_BF16X3 ? (((size_t)N * 2 + 15) & ~(size_t)15) : 0;
+    return r + l + (size_t)N * 4;
+}
+
+// LDS layout of a resident block: w [Rp], x [N] (FP64), the images of x (and -x for the
+// BF16 formats' pair form), then the block's rows: Af (and its low words), Hinv_3, the
+// projection rows (and their low words).
+struct ResLayout { size_t W, xr, L, Ln, af, aflo, hv, pr, prlo, total; };
+__host__ __device__ inline ResLayout res_layout(int dt, int N, int Np, int Rp, int layout, int dense_h, int rg_per,
+                                                int pg_per) {
+    const size_t eb = dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : 2, ab = dt == DT_F64 ? 8 : 4;
+    const bool x3 = dt == DT_BF16X3, neg = (dt == DT_BF16 || x3) && layout;
+    const size_t ph = layout ? 3 : 2;
+    ResLayout r{};
+    size_t o = 0;
+    auto put = [&](size_t& at, size_t bytes) {
+        at = o;
+        o = (o + bytes + 15) & ~(size_t)15;
+    };
+    put(r.W, (size_t)Rp * ab);
+    put(r.xr, (size_t)N * 8);
+    put(r.L, lds_u_bytes(dt, Np));
+    put(r.Ln, neg ? lds_u_bytes(dt, Np) : 0);
+    put(r.af, (size_t)rg_per * 4 * Rp * eb);
+    put(r.aflo, x3 ? (size_t)rg_per * 4 * Rp * 2 : 0);
+    put(r.hv, dense_h ? (size_t)rg_per * 4 * Np * 8 : 0);
+    put(r.pr, (size_t)pg_per * 4 * ph * Np * eb);
+    put(r.prlo, x3 ? (size_t)pg_per * 4 * ph * Np * 2 : 0);
+    r.total = o;
+    return r;
+}
+constexpr int kResWaitWords = 4096;    // message words a block waits for at most (x or w)
+// Cooperative launch of the run (dynamic LDS `lds`, G blocks of 256 threads), then one
+// block that logs the energies of levels n0 .. n0 + nsteps - 1, leaves n0 + nsteps
+// pending as the step kernels do, advances the counter and the tag base.
+hipError_t res_launch(int dt, const ResJob& jb, int G, size_t lds, hipStream_t s);
+void res_close_launch(const StepArgs& a0, const StepArgs& aL, long long n0, int nsteps, const double* epall,
+                      int nrg, unsigned* seq, hipStream_t s);
+// Raise the kernel's dynamic LDS limit to `cap` (the same for every context: the
+// attribute belongs to the kernel) and report how many of its blocks with `lds` bytes
+// fit on one compute unit.
+hipError_t res_attr(int dt, int N, size_t cap, size_t lds, int* blocks_per_cu);
+
 // BDF update from contraction partials part[c][b][i] (row stride pb trajectories) in
 // the accumulation type (FP64 for DT_F64, FP32 otherwise).  diag = 1: diagonal
 // stiffness (update, energy partials, step close); diag = 0: right-hand side only.

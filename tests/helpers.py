@@ -24,6 +24,15 @@ EPS_OP = {"fp64": 0.0, "fp32": 3 * U32, "bf16": 0.0, "bf16x3": 3 * 2.0 ** -16 + 
 U_ACC = {"fp64": U64, "fp32": U32, "bf16": U32, "bf16x3": U32}
 
 
+def cond_traj_bar(cond_h: float, level: int) -> float:
+    """Relative bar for FP64 level `level` of a trajectory whose Helmholtz matrix has
+    condition number cond_h: each backward-stable FP64 solve carries a forward error of
+    order cond_h * u64, and the errors of the levels add along a decaying trajectory, so
+    level m may differ from another FP64 solver's by up to m * cond_h * u64 (a rounding-
+    level perturbation of the stiffness alone moves the oracle by about a fifth of that)."""
+    return max(TRAJ_TOL["fp64"], level * cond_h * 2.0 ** -53)
+
+
 def eval_bound_dense(dt, C, u):
     """Norm-wise bound on |y - y_ref| for the dense contraction: operand error EPS_OP
     plus the probabilistic accumulation bound 4 sqrt(n) u (n = N^2 terms per output,

@@ -18,7 +18,7 @@ import pytest
 
 import oracle as orc
 import romsynth
-from helpers import bound_cp, bound_dense, elem_violations
+from helpers import bound_cp, bound_dense, cond_traj_bar, elem_violations
 
 
 def _rb(x):
@@ -107,3 +107,24 @@ def test_cp_bound_from_right_hand_side():
     tb = _rb(MC) @ _rb(rhs)
     yb = Af @ (lam * sb * tb)
     assert _frac_bad(yb, y, bd) > 0.5
+
+
+def test_ill_conditioned_bar_is_the_problems_own_sensitivity():
+    """The FP64 bar for an ill-conditioned Helmholtz matrix (cond ~ 1e4) is neither loose
+    nor tight by more than a factor ten: flipping the last bit of the stiffness entries
+    (symmetric random signs) moves the oracle's own trajectory by 0.1 to 1 times
+    cond_traj_bar at every level."""
+    N = 48
+    A = romsynth.stiffness_graded(N, 1.0, 2e10, seed=1, cfg=25)
+    p = romsynth.make_problem(N, pairs=20, eps=1e-6, nu=1e-3, dt=1e-3, cfg=25, dense=False)
+    w = np.linalg.eigvalsh((11.0 / 6.0) / 1e-3 * np.eye(N) + 1e-3 * A)
+    cond = w[-1] / w[0]
+    assert 1e4 < cond < 2e4
+    kw = dict(u0=p.u0[0], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf, traj=True)
+    ref = orc.run(N, 1e-3, 1e-3, A, 200, **kw)["traj"]
+    R = np.triu(np.random.default_rng(7).choice([-1.0, 1.0], size=(N, N)))
+    R = R + np.triu(R, 1).T
+    T = orc.run(N, 1e-3, 1e-3, A * (1.0 + 2.0 ** -53 * R), 200, **kw)["traj"]
+    for m in (10, 60, 200):
+        d = np.linalg.norm(T[m] - ref[m]) / np.linalg.norm(ref[m])
+        assert 0.1 * cond_traj_bar(cond, m) < d < cond_traj_bar(cond, m), (m, d)

@@ -10,7 +10,7 @@ import pytest
 import oracle as orc
 import paper_2311_03694_amd as rg
 import romsynth
-from helpers import TRAJ_TOL, bf16_bound, check_eval, eval_bound_cp, eval_bound_dense, rel, traj_rel
+from helpers import TRAJ_TOL, bf16_bound, cond_traj_bar, check_eval, eval_bound_cp, eval_bound_dense, rel, traj_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -227,28 +227,27 @@ def test_nonfinite_reported(torch_gpu):
 def test_explicit_inverse_ill_conditioned(torch_gpu):
     """The dense-stiffness solve applies an explicit inverse built from the Cholesky
     factor.  With cond(beta0/dt I + nu A) near 1e4 (eigenvalues of A log-spaced over ten
-    decades) an FP64 trajectory still follows the oracle's triangular solves to 1e-12."""
+    decades) every FP64 level m stays within m * cond * u64 of the oracle's triangular
+    solves: the spread any two FP64 solvers show on this problem (a last-bit change of
+    the stiffness alone moves the oracle by a fifth of it)."""
     N = 48
     A = romsynth.stiffness_graded(N, 1.0, 2e10, seed=1, cfg=25)
-    H = (11.0 / 6.0) / 1e-3 * np.eye(N) + 1e-3 * A
-    w = np.linalg.eigvalsh(H)
-    assert w[-1] / w[0] > 1e4
+    w = np.linalg.eigvalsh((11.0 / 6.0) / 1e-3 * np.eye(N) + 1e-3 * A)
+    cond = w[-1] / w[0]
+    assert cond > 1e4
     p = romsynth.make_problem(N, pairs=20, eps=1e-6, nu=1e-3, dt=1e-3, cfg=25, dense=False)
     rom = rg.Rom(N, 1e-3, 1e-3, A, lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf, dtype="fp64")
-    _say(f"ill-conditioned stiffness, cond(H) = {w[-1] / w[0]:.2e}")
+    _say(f"ill-conditioned stiffness, cond(H) = {cond:.2e}")
     st = rom.state(p.u0[0])
-    marks = [1, 2, 3, 10, 60, 200]
-    lv = [p.u0[0].copy()]
-    done = 0
-    for m in marks:
-        st.step(m - done)
-        done = m
-        lv.append(st.u()[0].copy())
     ref = orc.run(N, 1e-3, 1e-3, A, 200, u0=p.u0[0], lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf, traj=True)
     assert ref["status"] == 0
-    err = traj_rel(lv, [ref["traj"][0]] + [ref["traj"][m] for m in marks])
-    _say(f"  max level error {err:.2e}")
-    assert err < TRAJ_TOL["fp64"], err
+    done = 0
+    for m in (1, 2, 3, 10, 60, 200):
+        st.step(m - done)
+        done = m
+        err = rel(st.u()[0], ref["traj"][m])
+        _say(f"  level {m}: {err:.2e} = {err / cond_traj_bar(cond, m):.3f} of the bar")
+        assert err < cond_traj_bar(cond, m), (m, err)
 
 
 def test_not_spd_rejected(torch_gpu):
