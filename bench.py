@@ -18,8 +18,12 @@ Also in the one JSON line:
   dense / speedup_cp_vs_dense   the G-ROM beside it
   roofline      dense contraction kernel (HBM-bound): algorithmic bytes N^3*4 per launch
                 over its event-timed average duration, against 8 TB/s
-  roofline_cp   CP projections + Hadamard-scatter (2.5NR*4 bytes per launch in the pair
-                form of skew-paired factors, 3NR*4 in the general form)
+  roofline_cp   one CP step through the per-step kernels (resident runs off): N R + 1.5 R N
+                operator words and the FP64 Hinv_3 (8 N^2 bytes) against 8 TB/s
+  resident      the headline's own path: the CP step with its operator resident in LDS
+                (k_cp_resident), its step time and the streaming bandwidth it equals
+  cp_evaluation CP projections + Hadamard-scatter alone (2.5NR*4 bytes per launch in the
+                pair form of skew-paired factors, 3NR*4 in the general form)
   cp_general    the same CP-ROM with the general-form projections (kernel knob 4 = 0)
   batched       N = 1000 with B = 16 and 64 trajectories (MFMA kernels), FP32 and BF16
   config2       N = 400, B = 256, the dense Khatri-Rao MFMA GEMM (BF16, BF16x3, FP32)
@@ -279,6 +283,14 @@ def main():
             s_gen.close()
             rg.rom_set_tile(rom_cp.handle, 4, -1)
             log(f"CP general form {K} steps in {t_gen:.3f}s")
+        # the same steps through the per-step kernels (resident runs off): the streaming
+        # path that the HBM roofline of a CP step applies to
+        res_blocks = s_cp.resident_blocks
+        rg.rom_set_tile(rom_cp.handle, 5, 0)
+        s_ps, t_ps = step_rate(rom_cp, p.u0, K, W)
+        s_ps.close()
+        rg.rom_set_tile(rom_cp.handle, 5, -1)
+        log(f"CP per-step kernels {K} steps in {t_ps:.3f}s (resident blocks {res_blocks})")
         log("dense G-ROM")
         rom_d = make(True)
         s_d, t_d = step_rate(rom_d, p.u0, Kd, min(W, 20))
@@ -349,12 +361,22 @@ def main():
                          "frac": d_bytes / d_kernel / 1e9 / HBM_PEAK_GBS,
                          "traffic": _traffic(f"dense_gemv_n{N}_{dt}", "dense_gemv"),
                          "avg_launch_us": d_kernel * 1e6, "algorithmic_bytes": d_bytes},
-            "roofline_cp": {"bound": "hbm", "kernel": "one CP step: k_cp_scatter1 (right-hand side) + k_helm_proj "
-                                                      "(Helmholtz apply and next projections)"
-                                                      + (", pair form" if cp_form else ""),
-                            "achieved": cp_step_bytes / (t_cp / K) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": cp_step_bytes / (t_cp / K) / 1e9 / HBM_PEAK_GBS,
-                            "avg_step_us": t_cp / K * 1e6, "algorithmic_bytes": cp_step_bytes},
+            "roofline_cp": {"bound": "hbm", "kernel": "one CP step through the per-step kernels: k_cp_scatter1 "
+                                                      "(right-hand side) + k_helm_proj (Helmholtz apply and next "
+                                                      "projections)" + (", pair form" if cp_form else ""),
+                            "achieved": cp_step_bytes / (t_ps / K) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": cp_step_bytes / (t_ps / K) / 1e9 / HBM_PEAK_GBS,
+                            "avg_step_us": t_ps / K * 1e6, "algorithmic_bytes": cp_step_bytes,
+                            "value": K / t_ps},
+            "resident": {"kernel": "k_cp_resident (operator rows in LDS for a run of up to 512 steps)",
+                         "blocks": res_blocks, "avg_step_us": t_cp / K * 1e6,
+                         "hbm_operator_bytes_per_step": 0,
+                         "equivalent_stream_GBps": cp_step_bytes / (t_cp / K) / 1e9,
+                         "equivalent_stream_frac": cp_step_bytes / (t_cp / K) / 1e9 / HBM_PEAK_GBS,
+                         "speedup_vs_per_step": t_ps / t_cp,
+                         "note": "the step is bound by its two exchanges between blocks (x: N FP64, w: Rp words), "
+                                 "not by memory bandwidth; equivalent_stream is the bandwidth a streaming step "
+                                 "would need to match it"},
             "cp_evaluation": {"kernel": "k_cp_proj1 + k_cp_scatter1 (rom_nonlinear)", "avg_launch_us": cp_kernel * 1e6,
                               "algorithmic_bytes": cp_bytes, "hbm_frac": cp_bytes / cp_kernel / 1e9 / HBM_PEAK_GBS},
             "model_error": dict(model, steps=1000, note="max over every 100th level of |u_cp - u_dense| / "

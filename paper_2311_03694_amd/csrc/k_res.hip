@@ -112,7 +112,7 @@ __device__ bool res_wait(const ResJob& jb, const unsigned long long* src, int ne
 template <class SrcF>
 __device__ void lds_rows(char* dst, int nrows, size_t row_bytes, SrcF src) {
     const int cpr = (int)(row_bytes / 16);
-    staged_copy<8, u32x4>(
+    staged_copy<16, u32x4>(
         nrows * cpr,
         [&](int q) {
             const int r = q / cpr, c = q - r * cpr;
