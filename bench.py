@@ -87,6 +87,8 @@ def parse():
                     help="requests of the serving stream (config 4 has 10,000)")
     ap.add_argument("--serving-max-steps", type=int, default=10000,
                     help="largest step count of a serving request (config 4: 100,000)")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="step CP states through the per-step kernels only (counter runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -240,7 +242,10 @@ def main():
         del a, b2
 
     def make(dense, dtype=dt, batch=1):
-        return rg.Rom.from_problem(p, dense=dense, dtype=dtype, max_batch=batch, stream=stream)
+        rom = rg.Rom.from_problem(p, dense=dense, dtype=dtype, max_batch=batch, stream=stream)
+        if args.no_resident and not dense:
+            rom.set_tile(5, 0)
+        return rom
 
     def step_rate(rom, u0, nsteps, warm):
         s = rom.state(u0)
@@ -289,7 +294,7 @@ def main():
         rg.rom_set_tile(rom_cp.handle, 5, 0)
         s_ps, t_ps = step_rate(rom_cp, p.u0, K, W)
         s_ps.close()
-        rg.rom_set_tile(rom_cp.handle, 5, -1)
+        rg.rom_set_tile(rom_cp.handle, 5, 0 if args.no_resident else -1)
         log(f"CP per-step kernels {K} steps in {t_ps:.3f}s (resident blocks {res_blocks})")
         log("dense G-ROM")
         rom_d = make(True)
@@ -330,6 +335,8 @@ def main():
         for Rm in (500, 1000, 2000):
             ops_m = dict(zip(("lam", "Af", "Bf", "Cf"), romsynth.truncate_cp(p.lam, p.Af, p.Bf, p.Cf, Rm)))
             rom_m = rg.Rom(N, p.nu, p.dt, p.A, **ops_m, dtype=dt, stream=stream)
+            if args.no_resident:
+                rom_m.set_tile(5, 0)
             Um = traj_marks(rom_m)
             rom_m.close()
             model[f"R{Rm}"] = {"max_rel_to_grom": float(np.max(np.linalg.norm(Um - U_dense, axis=1) /
