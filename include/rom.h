@@ -283,16 +283,30 @@ rom_status rom_step_multi(int32_t n, const rom_ctx *ctxs, const rom_state *state
  * 7 = skew column-pair layout the one-trajectory CP kernels use (rom_cp_skew_layout's
  * codes; 0 = general form), 8 = operator form (0 dense, 1 CP, 2 SVD), 9 = SVD rank
  * (0 unless SVD), 10 = the state's first non-finite level, -1 if none (synchronizes with
- * the context's stream; lets a caller of rom_step_multi find which states failed). */
+ * the context's stream; lets a caller of rom_step_multi find which states failed),
+ * 11 = blocks of the resident runs the state's steps take from level 2 on (0: none; see
+ * rom_set_tile kind 5). */
 rom_status rom_query(rom_ctx ctx, rom_state st, int32_t what, int64_t *value);
 
 /* Kernel tile selection (the autotuner's knob).  kind: 0 = dense single-trajectory
  * streaming contraction, 1 = dense batched MFMA contraction, 2 = CP projections,
  * 3 = CP scatter, 4 = pair form of the CP projections (0 = general form, 1 = pair form
  * for one trajectory and for batches, ROM_E_UNSUPPORTED if the factors have no skew column
- * pairs).  value: an index into that kernel's variant table (see rom_tile_count); -1
- * restores the built-in choice (for kind 4: the pair form for one trajectory whenever the
- * factors allow it, the general form for batches).  Applies to later launches. */
+ * pairs), 5 = resident runs of one-trajectory CP steps (0 = off: every step through the
+ * per-step kernels; 1 or -1 = on where the operator fits on chip).  value: an index into
+ * that kernel's variant table (see rom_tile_count); -1 restores the built-in choice (for
+ * kind 4: the pair form for one trajectory whenever the factors allow it, the general
+ * form for batches).  Applies to later launches.
+ *
+ * Resident runs: from level 2 on, a one-trajectory CP state (not the full form) takes runs
+ * of 16 to 512 steps in one cooperative launch whose blocks, one per compute unit at most,
+ * keep their rows of Af, the projection operator and (dense stiffness) Hinv_3 in LDS, and
+ * pass the right-hand side and w = lam .* s .* t between them as tagged messages.  They
+ * apply when 2N <= 4096, Rp (FP64: 2 Rp) <= 4096 and the rows fit the device's LDS; the
+ * results equal the per-step kernels' to the bit.  A wait for another block's data that
+ * does not end within a bounded number of polling rounds (seconds) makes rom_step_sync
+ * return ROM_E_DEVICE.  A run is not captured into graphs (a capturing stream takes the
+ * per-step kernels). */
 rom_status rom_set_tile(rom_ctx ctx, int32_t kind, int32_t value);
 int32_t rom_tile_count(int32_t kind);
 

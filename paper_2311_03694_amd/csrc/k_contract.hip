@@ -20,16 +20,16 @@ __global__ __launch_bounds__(256) void k_cp_proj1(Proj1Job jb) {
 }
 // MODE 1 (the update kernel) runs one block more than there are row blocks: the last
 // one closes the previous level and advances the counter.
-template <int DT, int V, int U, int MODE>
+template <int DT, int V, int U, int MODE, bool FULL>
 __global__ __launch_bounds__(256) void k_cp_scatter1(Scat1Job jb, double* y_out) {
     if constexpr (MODE == 1) {
         if (blockIdx.x == gridDim.x - 1) {
             close_and_advance(jb.a, *jb.a.step, (int)gridDim.x - 1);
             return;
         }
-        cp_scatter1_body<DT, V, U, MODE>(jb, y_out, blockIdx.x, *jb.a.step);
+        cp_scatter1_body<DT, V, U, MODE, FULL>(jb, y_out, blockIdx.x, *jb.a.step);
     } else {
-        cp_scatter1_body<DT, V, U, MODE>(jb, y_out, blockIdx.x, MODE == 0 ? 0LL : *jb.a.step);
+        cp_scatter1_body<DT, V, U, MODE, FULL>(jb, y_out, blockIdx.x, MODE == 0 ? 0LL : *jb.a.step);
     }
 }
 // ============================================================== Helmholtz apply and projections
@@ -135,8 +135,15 @@ template <int DT, int MODE>
 static void scat1_go(const Scat1Job& jb, double* y, hipStream_t s) {
     typedef typename Store<DT>::Acc Acc;
     constexpr int V = 16 / (int)sizeof(typename Store<DT>::T);
-    hipLaunchKernelGGL((k_cp_scatter1<DT, V, 8, MODE>), dim3((unsigned)jb.nblk + (MODE == 1 ? 1u : 0u)), dim3(256),
-                       sizeof(Acc) * jb.Rp, s, jb, y);
+    const dim3 grid((unsigned)jb.nblk + (MODE == 1 ? 1u : 0u));
+    const size_t w_lds = sizeof(Acc) * jb.Rp;
+    if (MODE != 0 && jb.G) {
+        // W, then [uhat; h] (2 Np doubles) 16-byte aligned behind it
+        const size_t lds = ((w_lds + 15) & ~(size_t)15) + sizeof(double) * 2 * jb.a.Np;
+        hipLaunchKernelGGL((k_cp_scatter1<DT, V, 8, MODE, MODE != 0>), grid, dim3(256), lds, s, jb, y);
+    } else {
+        hipLaunchKernelGGL((k_cp_scatter1<DT, V, 8, MODE, false>), grid, dim3(256), w_lds, s, jb, y);
+    }
 }
 
 template <int DT>
@@ -156,8 +163,9 @@ static void scat1_dispatch(int dt, int mode, const Scat1Job& jb, double* y, hipS
 }
 
 int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, int N, int Rp, const void* w, double* y_out,
-                       const StepArgs* sa, int mode, hipStream_t s) {
+                       const StepArgs* sa, int mode, hipStream_t s, const double* G) {
     Scat1Job jb{};
+    jb.G = G;
     jb.Af = Af;
     jb.Af_lo = (const unsigned short*)Af_lo;
     jb.N = N;

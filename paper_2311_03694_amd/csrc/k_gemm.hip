@@ -44,6 +44,7 @@ struct GemmArgs {
     int M, K, Bpad;
     long long lda, ldx;
     int gx, gy;                    // row tiles, column tiles
+    int ksplit;                    // PLAIN: K ranges, one partial product each (Y + split * M * Bpad)
     const long long* kstep;        // non-null: A += (BDF order at *kstep - 1) * a_kstride
     long long a_kstride;
     long long pair_off;            // PAIR: elements from a row of A to its partner row
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     Acc* red = reinterpret_cast<Acc*>(smem);             // [NA][4][FN][4][64]
 
-    const int nwork = p.gx * p.gy + (CLOSE ? 1 : 0);
+    const int nks = EPI == EPI_PLAIN ? p.ksplit : 1;
+    const int nwork = p.gx * p.gy * nks + (CLOSE ? 1 : 0);
     const int per = (nwork + 7) / 8;
     const int wi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (wi >= nwork) return;
@@ -87,15 +89,21 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
         }
     }
     const long long n = EPI >= EPI_UPDATE ? *p.st.step : 0;
-    const int by = wi % p.gy, bx = wi / p.gy;
+    // the K ranges of one tile are consecutive work items (one XCD, shared X rows)
+    const int ks = wi % nks, tile = wi / nks;
+    const int by = tile % p.gy, bx = tile / p.gy;
 
     const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int rowbase = bx * 16, b0 = by * 16 * FN;
-    const int ksteps = (p.K + KS - 1) / KS;
+    // this block's K steps [kb, kb + kn), split over the 4 wavefronts
+    const int ksteps_all = (p.K + KS - 1) / KS;
+    const int kper = (ksteps_all + nks - 1) / nks;
+    const int kb = ks * kper;
+    const int ksteps = kb < ksteps_all ? (ksteps_all - kb < kper ? ksteps_all - kb : kper) : 0;
     const int wsb = ksteps / 4, wse = ksteps - wsb * 4;
     const int ns = wsb + (w < wse ? 1 : 0);
-    const int s0 = w * wsb + (w < wse ? w : wse);
+    const int s0 = kb + w * wsb + (w < wse ? w : wse);
 
     // the lane's row (rows past M are clamped for loads and never stored) and columns
     int r = rowbase + c16;
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) red[h * RS + ((w * FN + t) * 4 + v) * 64 + lane] = Z[h][t][v];
     __syncthreads();
-    Acc* out = reinterpret_cast<Acc*>(p.Y);
+    Acc* out = reinterpret_cast<Acc*>(p.Y) + (size_t)ks * p.M * p.Bpad;
     for (int e = threadIdx.x; e < 256 * FN; e += 256) {
         const int cl = e >> 4, rr = e & 15;              // local column, local row
         const int t = cl >> 4, cc = cl & 15;
@@ -299,6 +307,21 @@ GemmPlan gemm_plan(int M, int Bpad, int variant) {
     pl.gx = (M + 15) / 16;
     pl.gy = Bpad / (16 * pl.fn);
     pl.blocks = (pl.gx * pl.gy + 7) / 8 * 8;
+    pl.ksplit = 1;
+    return pl;
+}
+
+// K ranges only where the output tiles leave compute units idle: about one block per
+// compute unit (more blocks only add per-block prologues and reductions), each wavefront
+// keeping at least 4 K steps (8 FP64 values a step), at most 8 ranges.
+GemmPlan gemm_plan_splitk(int M, int K, int Bpad) {
+    GemmPlan pl = gemm_plan(M, Bpad, 1);
+    const int tiles = pl.gx * pl.gy, ksteps = (K + 7) / 8;
+    int ks = 256 / tiles;
+    ks = ks < 1 ? 1 : ks > 8 ? 8 : ks;
+    while (ks > 1 && ksteps / ks < 16) --ks;
+    pl.ksplit = ks;
+    pl.blocks = (tiles * ks + 7) / 8 * 8;
     return pl;
 }
 
@@ -326,6 +349,7 @@ static GemmArgs gemm_args(const GemmPlan& pl, const void* A, const void* Alo, lo
     a.ldx = ldx;
     a.gx = pl.gx;
     a.gy = pl.gy;
+    a.ksplit = pl.ksplit > 0 ? pl.ksplit : 1;
     return a;
 }
 

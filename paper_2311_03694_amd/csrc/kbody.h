@@ -86,6 +86,156 @@ __device__ __forceinline__ void dense_gemv_body(const GemvJob& jb, int blk) {
 }
 
 
+// ============================================================== full form terms
+
+// Zeroth-mode and mass terms of the right-hand side of level n (eq. nse_d1), per
+// trajectory b:
+//   zfull = L uhat + (M - I) h,
+//   uhat = sum_q alpha_q u^{n+1-q},  h = (1/dt) sum_q beta_q u^{n+1-q}
+// (the EXT sum of the linear part of the bracket, and M minus the identity times the BDF
+// history sum, which the rhs already carries; the constants are added with the rhs).
+// Block blk of trajectory b (blockDim.x / 64 rows per block), one wavefront per row of G (2 Np doubles, read as
+// 16-byte pairs in chunks of 16 per lane, a whole row up to N = 1024).  The first chunk of
+// G and the history loads of the staging (up to 1024 coefficients per pass) are all issued
+// before any of them is used, so the kernel waits for one round trip to memory instead of
+// one per loop pass; eight rows per block share one staging of the history.
+constexpr int kFullRows = 8, kFullChunk = 16, kFullStage = 2;
+
+// The pieces of a row's term, shared by the terms kernel and the fused CP scatter so both
+// sum in one order.  First chunk of row g2 (Np pairs) into gv, zero past Np or for an
+// inactive row.
+__device__ __forceinline__ void full_issue(const double2* __restrict__ g2, bool active, int lane, int Np,
+                                           double2 (&gv)[kFullChunk]) {
+#pragma unroll
+    for (int u = 0; u < kFullChunk; ++u) {
+        const int m = lane + u * kWave;
+        gv[u] = (active && m < Np) ? g2[m] : make_double2(0.0, 0.0);
+    }
+}
+
+// Element j of [uhat; h] from the element's history u[q] = u^{n-q}_j (q < k).
+__device__ __forceinline__ void full_x_elem(const BdfCoef& c, int k, double inv_dt, const double (&u)[3], double& uh,
+                                            double& h) {
+    uh = 0.0;
+    h = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        if (q < k) {
+            uh += c.alpha[q] * u[q];
+            h += (c.beta[q + 1] * inv_dt) * u[q];
+        }
+}
+
+// Whole block: xs[0, Np) = uhat and xs[Np, 2 Np) = h of trajectory b at level n (zero past
+// N); the caller synchronizes before reading.
+__device__ __forceinline__ void full_stage_x(const StepArgs& a, long long n, int b, double* __restrict__ xs) {
+    const int Np = a.Np, k = bdf_order(n);
+    const BdfCoef c = bdf_coef(k);
+    const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N;
+    const double* lev[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) lev[q] = a.uring + (size_t)slot_of(n - q) * BN + off;
+    for (int j0 = 0; j0 < Np; j0 += kFullStage * (int)blockDim.x) {
+        double uv[3][kFullStage];
+#pragma unroll
+        for (int e = 0; e < kFullStage; ++e) {
+            const int j = j0 + e * (int)blockDim.x + (int)threadIdx.x;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) uv[q][e] = (q < k && j < a.N) ? lev[q][j] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < kFullStage; ++e) {
+            const int j = j0 + e * (int)blockDim.x + (int)threadIdx.x;
+            const double u3[3] = {uv[0][e], uv[1][e], uv[2][e]};
+            double uh, h;
+            full_x_elem(c, k, a.inv_dt, u3, uh, h);
+            if (j < Np) {
+                xs[j] = uh;
+                xs[Np + j] = h;
+            }
+        }
+    }
+}
+
+// The same staging in two halves for a block of 256 threads and Np <= 1024: the history
+// loads (issued with the caller's other loads), then the elements into xs.
+constexpr int kFullRegJ = 4;
+struct FullHist { double u[3][kFullRegJ]; };
+__device__ __forceinline__ void full_load_hist(const StepArgs& a, long long n, FullHist& fh) {
+    const int k = bdf_order(n);
+    const size_t BN = (size_t)a.B * a.N;
+#pragma unroll
+    for (int e = 0; e < kFullRegJ; ++e) {
+        const int j = e * 256 + (int)threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            fh.u[q][e] = (q < k && j < a.N) ? a.uring[(size_t)slot_of(n - q) * BN + j] : 0.0;
+    }
+}
+__device__ __forceinline__ void full_store_x(const StepArgs& a, long long n, const FullHist& fh, double* __restrict__ xs) {
+    const int Np = a.Np, k = bdf_order(n);
+    const BdfCoef c = bdf_coef(k);
+#pragma unroll
+    for (int e = 0; e < kFullRegJ; ++e) {
+        const int j = e * 256 + (int)threadIdx.x;
+        const double u3[3] = {fh.u[0][e], fh.u[1][e], fh.u[2][e]};
+        double uh, h;
+        full_x_elem(c, k, a.inv_dt, u3, uh, h);
+        if (j < Np) {
+            xs[j] = uh;
+            xs[Np + j] = h;
+        }
+    }
+}
+
+// The lane's part of row g2 . xs2 (chunks after the first loaded here), summed over its
+// chunks in order; wave_sum of it is the row's term.
+__device__ __forceinline__ double full_dot(const double2* __restrict__ g2, int lane, int Np,
+                                           double2 (&gv)[kFullChunk], const double2* xs2) {
+    double acc[kFullChunk];
+#pragma unroll
+    for (int u = 0; u < kFullChunk; ++u) acc[u] = 0.0;
+    for (int base = 0; base < Np; base += kFullChunk * kWave) {
+        if (base > 0) {
+#pragma unroll
+            for (int u = 0; u < kFullChunk; ++u) {
+                const int m = base + lane + u * kWave;
+                gv[u] = m < Np ? g2[m] : make_double2(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kFullChunk; ++u) {
+            const int m = base + lane + u * kWave;
+            if (m < Np) {
+                const double2 x = xs2[m];
+                acc[u] += gv[u].x * x.x + gv[u].y * x.y;
+            }
+        }
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < kFullChunk; ++u) t += acc[u];
+    return t;
+}
+
+__device__ __forceinline__ void full_terms_body(const StepArgs& a, const double* __restrict__ G, int blk, int b) {
+    extern __shared__ double2 xs2[];
+    double* xs = reinterpret_cast<double*>(xs2);
+    const int Np = a.Np;
+    const int lane = threadIdx.x & (kWave - 1), i = blk * ((int)blockDim.x / kWave) + (threadIdx.x / kWave);
+    const bool active = i < a.N;
+    // row i of G as Np pairs (Np is a multiple of 8, rows 16-byte aligned)
+    const double2* g2 = reinterpret_cast<const double2*>(G + (size_t)(active ? i : 0) * 2 * Np);
+    double2 gv[kFullChunk];
+    full_issue(g2, active, lane, Np, gv);
+    full_stage_x(a, *a.step, b, xs);
+    __syncthreads();
+    if (!active) return;
+    const double s = wave_sum(full_dot(g2, lane, Np, gv, xs2));
+    if (lane == 0) a.zfull[(size_t)b * a.N + i] = s;
+}
+
+
 // ============================================================== CP, one trajectory
 
 // Projections and Hadamard product: w[r] = lam_r (sum_k BCt[r][k] u_k)
@@ -239,8 +389,11 @@ __device__ __forceinline__ void cp_proj_any_body(const Proj1Job& jb, int blk) {
 // wavefront per row (row loads issued before W is staged).  MODE 0 writes y (FP64,
 // to y_out); MODE 1 applies the diagonal-stiffness BDF update with its energy
 // partials; MODE 2 writes the right-hand side for the dense Helmholtz solve.  n is the
-// state's level (MODE 1 and 2).
-template <int DT, int V, int U, int MODE>
+// state's level (MODE 1 and 2).  FULL (MODE 1 and 2, full form): the block also stages
+// the level's [uhat; h] behind W and each wavefront forms its row's term G_i . x (the
+// terms kernel's pieces, in its order) for the right-hand side, so a full-form step
+// needs no kernel of its own for the terms.
+template <int DT, int V, int U, int MODE, bool FULL = false>
 __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __restrict__ y_out, int blk,
                                                  long long n) {
     typedef typename Store<DT>::T T;
@@ -272,6 +425,16 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
         }
     };
     issue(r0);
+    // full form: the first chunk of the row of G, behind the row loads
+    const double2* g2 = nullptr;
+    double2 gv[FULL ? kFullChunk : 1];
+    FullHist fh;
+    const bool full_regs = FULL && a.Np <= kFullRegJ * 256;      // block of 256 threads
+    if constexpr (FULL) {
+        g2 = reinterpret_cast<const double2*>(jb.G + (size_t)(live ? i : 0) * 2 * a.Np);
+        full_issue(g2, live, lane, a.Np, gv);
+        if (full_regs) full_load_hist(a, n, fh);
+    }
     // the update's history (and diagonal inverse) behind the row loads
     BdfHist hist{};
     double hd = 0.0;
@@ -284,6 +447,11 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
         }
     }
     staged_copy<8, Acc>(R, [&](int r) { return win[r]; }, [&](int r, Acc v) { W[r] = v; });
+    double* xs = reinterpret_cast<double*>(smem + ((sizeof(Acc) * (size_t)R + 15) & ~(size_t)15));
+    if constexpr (FULL) {
+        if (full_regs) full_store_x(a, n, fh, xs);
+        else full_stage_x(a, n, 0, xs);
+    }
     __syncthreads();
     Acc z = 0;
     if (live) {
@@ -310,13 +478,17 @@ __device__ __forceinline__ void cp_scatter1_body(const Scat1Job& jb, double* __r
         }
         z = wave_sum(z);
     }
+    double zf = 0.0;
+    if constexpr (FULL) {
+        if (live) zf = wave_sum(full_dot(g2, lane, a.Np, gv, reinterpret_cast<const double2*>(xs)));
+    }
     if constexpr (MODE == 0) {
         if (live && lane == 0) y_out[i] = (double)z;
     } else {
         const BdfCoef c = bdf_coef(k);
         double e = 0.0;
         if (live && lane == 0) {
-            const double rhs = bdf_rhs_hist(a, n, c, k, 0, i, (double)z, hist);
+            const double rhs = bdf_rhs_hist<FULL>(a, n, c, k, 0, i, (double)z, hist, zf);
             if constexpr (MODE == 1) {
                 const double un = rhs * hd;
                 write_level(a, n + 1, 0, i, un);
@@ -460,95 +632,6 @@ __device__ __forceinline__ void bdf_partials_body(const StepArgs& a, long long n
         const double s = block_sum(e, red);
         if (threadIdx.x == 0) epart_of(a, n + 1)[(size_t)b * a.enmax + bx] = s;
     }
-}
-
-
-// ============================================================== full form terms
-
-// Zeroth-mode and mass terms of the right-hand side of level n (eq. nse_d1), per
-// trajectory b:
-//   zfull = L uhat + (M - I) h,
-//   uhat = sum_q alpha_q u^{n+1-q},  h = (1/dt) sum_q beta_q u^{n+1-q}
-// (the EXT sum of the linear part of the bracket, and M minus the identity times the BDF
-// history sum, which the rhs already carries; the constants are added with the rhs).
-// Block blk of trajectory b (blockDim.x / 64 rows per block), one wavefront per row of G (2 Np doubles, read as
-// 16-byte pairs in chunks of 16 per lane, a whole row up to N = 1024).  The first chunk of
-// G and the history loads of the staging (up to 1024 coefficients per pass) are all issued
-// before any of them is used, so the kernel waits for one round trip to memory instead of
-// one per loop pass; eight rows per block share one staging of the history.
-constexpr int kFullRows = 8, kFullChunk = 16, kFullStage = 2;
-__device__ __forceinline__ void full_terms_body(const StepArgs& a, const double* __restrict__ G, int blk, int b) {
-    extern __shared__ double2 xs2[];
-    double* xs = reinterpret_cast<double*>(xs2);
-    const int Np = a.Np;
-    const int lane = threadIdx.x & (kWave - 1), i = blk * ((int)blockDim.x / kWave) + (threadIdx.x / kWave);
-    const bool active = i < a.N;
-    // row i of G as Np pairs (Np is a multiple of 8, rows 16-byte aligned)
-    const double2* g2 = reinterpret_cast<const double2*>(G + (size_t)(active ? i : 0) * 2 * Np);
-    double2 gv[kFullChunk];
-#pragma unroll
-    for (int u = 0; u < kFullChunk; ++u) {
-        const int m = lane + u * kWave;
-        gv[u] = (active && m < Np) ? g2[m] : make_double2(0.0, 0.0);
-    }
-    const long long n = *a.step;
-    const int k = bdf_order(n);
-    const BdfCoef c = bdf_coef(k);
-    const size_t BN = (size_t)a.B * a.N, off = (size_t)b * a.N;
-    const double* lev[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) lev[q] = a.uring + (size_t)slot_of(n - q) * BN + off;
-    for (int j0 = 0; j0 < Np; j0 += kFullStage * (int)blockDim.x) {
-        double uv[3][kFullStage];
-#pragma unroll
-        for (int e = 0; e < kFullStage; ++e) {
-            const int j = j0 + e * (int)blockDim.x + (int)threadIdx.x;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) uv[q][e] = (q < k && j < a.N) ? lev[q][j] : 0.0;
-        }
-#pragma unroll
-        for (int e = 0; e < kFullStage; ++e) {
-            const int j = j0 + e * (int)blockDim.x + (int)threadIdx.x;
-            double uh = 0.0, h = 0.0;
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                if (q < k) {
-                    uh += c.alpha[q] * uv[q][e];
-                    h += (c.beta[q + 1] * a.inv_dt) * uv[q][e];
-                }
-            if (j < Np) {
-                xs[j] = uh;
-                xs[Np + j] = h;
-            }
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-    double acc[kFullChunk];
-#pragma unroll
-    for (int u = 0; u < kFullChunk; ++u) acc[u] = 0.0;
-    for (int base = 0; base < Np; base += kFullChunk * kWave) {
-        if (base > 0) {
-#pragma unroll
-            for (int u = 0; u < kFullChunk; ++u) {
-                const int m = base + lane + u * kWave;
-                gv[u] = m < Np ? g2[m] : make_double2(0.0, 0.0);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kFullChunk; ++u) {
-            const int m = base + lane + u * kWave;
-            if (m < Np) {
-                const double2 x = xs2[m];
-                acc[u] += gv[u].x * x.x + gv[u].y * x.y;
-            }
-        }
-    }
-    double t = 0.0;
-#pragma unroll
-    for (int u = 0; u < kFullChunk; ++u) t += acc[u];
-    const double s = wave_sum(t);
-    if (lane == 0) a.zfull[off + i] = s;
 }
 
 

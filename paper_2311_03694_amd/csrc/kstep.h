@@ -28,8 +28,11 @@ __device__ __forceinline__ BdfHist bdf_hist_point(const StepArgs& a, long long n
 //         [- zfull - (sum_q alpha_q) fz - nu a0],
 // zfull = L uhat + (M - I) h carrying the zeroth-mode linear terms under the EXT sum and
 // the mass matrix minus the identity times the history sum (full form).
+// ZF: the caller formed the full form's G x of point (b, i) itself (zf_given); else it is
+// read from a.zfull (summed over its partial products).
+template <bool ZF = false>
 __device__ __forceinline__ double bdf_rhs_hist(const StepArgs& a, long long n, const BdfCoef& c, int k, int b,
-                                               int i, double y, const BdfHist& h) {
+                                               int i, double y, const BdfHist& h, double zf_given = 0.0) {
     a.yring[(size_t)slot_of(n) * ((size_t)a.B * a.N) + (size_t)b * a.N + i] = y;
     const double ylev[3] = {y, h.y1, h.y2};
     double v = 0.0;
@@ -44,7 +47,13 @@ __device__ __forceinline__ double bdf_rhs_hist(const StepArgs& a, long long n, c
 #pragma unroll
         for (int q = 0; q < 3; ++q)
             if (q < k) sa += c.alpha[q];
-        v -= a.zfull[(size_t)b * a.N + i] + (sa * a.fz[i] + a.az[i]);
+        double zf = zf_given;
+        if constexpr (!ZF) {
+            const size_t off = (size_t)b * a.N + i;
+            zf = a.zfull[off];
+            for (int q = 1; q < a.zsplit; ++q) zf += a.zfull[(size_t)q * a.zstride + off];
+        }
+        v -= zf + (sa * a.fz[i] + a.az[i]);
     }
     return v;
 }

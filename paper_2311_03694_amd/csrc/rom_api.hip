@@ -1074,12 +1074,14 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
     const WsPlan p = plan_ws(c, s->B);
     const int accf = acc_f64(c->dtype);
     const int diag = c->diagA ? 1 : 0;
+    // the full form's terms: the one-trajectory CP scatter forms them itself
+    const bool fused_terms = c->full && s->B == 1 && !c->dense && !c->svd;
     if (c->full) {
         if (s->B == 1) {
-            launch_full_terms(a, c->Gfull, stream);
+            if (!fused_terms) launch_full_terms(a, c->Gfull, stream);
         } else {
             launch_full_x(a, s->xfull, stream);
-            launch_gemm_f64(gemm_plan(c->N, s->Bpad, 0), c->Gfull, 2LL * c->Np, s->xfull, 2LL * c->Np, a.zfull,
+            launch_gemm_f64(gemm_plan_splitk(c->N, 2 * c->Np, s->Bpad), c->Gfull, 2LL * c->Np, s->xfull, 2LL * c->Np, a.zfull,
                             c->N, 2 * c->Np, s->Bpad, stream);
         }
     }
@@ -1101,7 +1103,8 @@ static rom_status enqueue_step(rom_ctx c, rom_state s, hipStream_t stream, long 
             if (diag)
                 launch_cp_proj1(c->dtype, proj_op(c), proj_op_lo(c), c->lam, c->N, c->Np, c->Rp, skew_of(c),
                                 a.uring, a.step, (long long)c->N, a.st, stream);
-            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->N, c->Rp, a.st, nullptr, &a, diag ? 1 : 2, stream);
+            launch_cp_scatter1(c->dtype, c->Af, c->Af_lo, c->N, c->Rp, a.st, nullptr, &a, diag ? 1 : 2, stream,
+                               fused_terms ? c->Gfull : nullptr);
         }
     } else {
         char* ws = (char*)c->ws;
@@ -1452,7 +1455,10 @@ extern "C" rom_status rom_state_create(rom_ctx c, int32_t batch, const double* u
     if (c->full) {
         // zfull takes Bpad rows (the batched product writes its padding rows); X of the
         // batched product starts zero and only its live entries are ever written
-        TRY(dmalloc((void**)&a.zfull, sizeof(double) * s->Bpad * N, &s->bytes, &s->allocs));
+        // batches: one partial product of X G^T per K range of the split product
+        a.zsplit = batch > 1 ? gemm_plan_splitk(c->N, 2 * c->Np, s->Bpad).ksplit : 1;
+        a.zstride = (long long)s->Bpad * N;
+        TRY(dmalloc((void**)&a.zfull, sizeof(double) * a.zsplit * s->Bpad * N, &s->bytes, &s->allocs));
         a.fz = c->fz;
         a.az = c->az;
         if (batch > 1) {

@@ -41,8 +41,11 @@ struct StepArgs {
     int enmax;               // capacity per trajectory (at least any update kernel's blocks)
     const double* hdiag;     // [3][N] 1/(beta0_k/dt + nu A_ii) (diagonal stiffness)
     const double* hinv;      // [3][N][Np] (beta0_k/dt M + nu A)^-1, row pitch Np (dense stiffness)
-    double* zfull;           // full form: [Bpad][N] G x of the level's right-hand side
-                             // (zeroth-mode linear terms and M - I); NULL otherwise
+    double* zfull;           // full form: [zsplit][Bpad][N] G x of the level's right-hand
+                             // side (zeroth-mode linear terms and M - I), summed over the
+                             // zsplit partial products in order; NULL otherwise
+    int zsplit;              // partial products of zfull (1 for one trajectory)
+    long long zstride;       // doubles from one partial product to the next
     const double* fz;        // full form: [N] constant of the bracket, (C1 + C2)[:, 0] - c0
     const double* az;        // full form: [N] nu a0
     // coefficient copies in the contraction's number format for the batched kernels,
@@ -95,6 +98,8 @@ struct Scat1Job {          // CP Hadamard-scatter with the fused BDF update
     int N, Rp;
     const void* w;                 // lam .* s .* t [Rp]
     StepArgs a;
+    const double* G;               // full form: G = [L | M - I] [N][2 Np], whose terms the
+                                   // scatter forms itself (null: none, or read from a.zfull)
     int blk0, nblk;
 };
 struct BdfJob {            // BDF update from contraction partials, one trajectory
@@ -214,7 +219,7 @@ int launch_cp_proj1(int dt, const void* BCt, const void* BCt_lo, const void* lam
                     void* w, hipStream_t s);
 int proj1_blocks(int Rp, SkewPairs sk);
 int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, int N, int Rp, const void* w, double* y_out,
-                       const StepArgs* sa, int mode, hipStream_t s);
+                       const StepArgs* sa, int mode, hipStream_t s, const double* G = nullptr);
 
 // CP, one trajectory, resident operator (k_res.hip): from level 2 on, a run of steps in
 // one cooperative launch whose blocks keep their rows of the order-3 operators in LDS.
@@ -370,9 +375,12 @@ void launch_dense_batched(int dt, const DensePlan& pl, const void* C, const void
 
 // Skinny products of the batched path (k_gemm.hip): one block per output tile over the
 // whole contracted index; outputs in the partials layout with a single split.
-struct GemmPlan { int fn, gx, gy, blocks; };
+struct GemmPlan { int fn, gx, gy, blocks, ksplit; };
 int gemm_variants();
 GemmPlan gemm_plan(int M, int Bpad, int variant);
+// The plan of an FP64 product over K whose short column side leaves the device
+// underfilled: K split into ksplit ranges, one partial product each.
+GemmPlan gemm_plan_splitk(int M, int K, int Bpad);
 void launch_gemm_proj(int dt, const GemmPlan& pl, const void* BCt, const void* BCt_lo, int Np, int Rp, int Bpad,
                       const void* X, const void* Xlo, void* P, hipStream_t s);
 void launch_gemm_proj_skew(int dt, const GemmPlan& pl0, const void* SK, const void* SK_lo, int Np, int P, int layout,
