@@ -689,8 +689,9 @@ def main():
         create_s = time.perf_counter() - t1
         log(f"serving: {len(srv.ops)} operators created in {create_s:.1f}s")
         sat = [_dc.replace(r, arrival=0.0) for r in reqs]
+        prog = lambda d, n, t: log(f"serving: {d}/{n} requests done after {t:.0f}s")
         t1 = time.perf_counter()
-        recs = srv.run(sat)
+        recs = srv.run(sat, progress=prog)
         wall = time.perf_counter() - t1
         s_sat = summarize(recs, wall)
         lam_sat = s_sat["completed"] / wall
@@ -699,7 +700,7 @@ def main():
         for f in (0.5, 0.8, 0.95):
             rq = at_rate(reqs, f * lam_sat, rng_seed=int(100 * f))
             t1 = time.perf_counter()
-            rr = srv.run(rq)
+            rr = srv.run(rq, progress=prog)
             w = time.perf_counter() - t1
             rates[f"{f:.2f}"] = dict(summarize(rr, w), offered_req_per_s=f * lam_sat)
             log(f"serving at {f:.2f} of saturation: p50 {rates[f'{f:.2f}']['latency_p50_s']:.2f}s "

@@ -29,5 +29,8 @@ void launch_skew_momentum(int N, int P, double mom, const double* Y, int ldy, do
 // Gram product; columns past n of Hinv are left as they are.  *info becomes 1 if a pivot
 // is not positive.
 void spd_inverse(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s);
+// The same inverse by blocked Gauss-Jordan sweeps, one kernel per 32-column panel, with L
+// and X as the two buffers the panels alternate between (each n x n).
+void spd_inverse_gj(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s);
 
 }  // namespace rom

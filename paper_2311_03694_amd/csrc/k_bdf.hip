@@ -368,6 +368,118 @@ void spd_inverse(int n, int np, const double* H, double* L, double* X, double* H
     hipLaunchKernelGGL(k_gram, dim3((n + 255) / 256, n), dim3(256), 0, s, n, np, X, Hinv);
 }
 
+// Blocked Gauss-Jordan inverse of an SPD matrix (no pivoting: the pivot blocks of an SPD
+// matrix are Schur complements of SPD matrices, so SPD themselves).  Panel K (kGjNb columns
+// from k0, b of them) maps the matrix out of place:
+//   A'_KK = P^-1,  A'_KJ = P^-1 A_KJ,  A'_IK = -A_IK P^-1,  A'_IJ = A_IJ - A_IK P^-1 A_KJ,
+// P = A_KK; after every panel the matrix is A^-1.  Two kernels per panel: k_gj_pivot (one
+// block, one thread per entry) inverts P by scalar sweeps of the same formulas and stores
+// it as the K x K tile of the result; k_gj_panel (one block per other 32 x 32 tile) reads
+// it there and forms its tile from the old matrix, which is only read, so no block waits
+// for another.  k_gj_pivot raises *info on a non-positive pivot.
+constexpr int kGjNb = 32;
+
+__global__ __launch_bounds__(1024) void k_gj_pivot(int n, int k0, const double* __restrict__ src, int sp,
+                                                   double* __restrict__ dst, int dp, int* info) {
+    __shared__ double P[kGjNb][kGjNb + 1];
+    const int b = n - k0 < kGjNb ? n - k0 : kGjNb;
+    const int r = threadIdx.x / kGjNb, cc = threadIdx.x % kGjNb;
+    const bool in = r < b && cc < b;
+    P[r][cc] = in ? src[(size_t)(k0 + r) * sp + k0 + cc] : 0.0;
+    __syncthreads();
+    for (int c = 0; c < b; ++c) {
+        const double p = P[c][c];
+        if (threadIdx.x == 0 && !(p > 0.0)) atomicMax(info, 1);
+        const double ip = 1.0 / p;
+        double v = 0.0;
+        if (in) {
+            if (r == c && cc == c) v = ip;
+            else if (r == c) v = P[c][cc] * ip;
+            else if (cc == c) v = -P[r][c] * ip;
+            else v = P[r][cc] - P[r][c] * (P[c][cc] * ip);
+        }
+        __syncthreads();
+        if (in) P[r][cc] = v;
+        __syncthreads();
+    }
+    if (in) dst[(size_t)(k0 + r) * dp + k0 + cc] = P[r][cc];
+}
+
+__global__ __launch_bounds__(256) void k_gj_panel(int n, int k0, const double* __restrict__ src, int sp,
+                                                  double* __restrict__ dst, int dp) {
+    __shared__ double Pi[kGjNb][kGjNb + 1], Aik[kGjNb][kGjNb + 1], Rkj[kGjNb][kGjNb + 1];
+    const int b = n - k0 < kGjNb ? n - k0 : kGjNb;
+    const int i0 = blockIdx.y * kGjNb, j0 = blockIdx.x * kGjNb;
+    const bool ik = i0 == k0, jk = j0 == k0;          // tiles are aligned with the panels
+    if (ik && jk) return;                              // the pivot kernel's tile
+    const int bi = n - i0 < kGjNb ? n - i0 : kGjNb, bj = n - j0 < kGjNb ? n - j0 : kGjNb;
+    const int t = threadIdx.x;
+    for (int q = t; q < kGjNb * kGjNb; q += blockDim.x) {
+        const int r = q / kGjNb, c = q % kGjNb;
+        Pi[r][c] = (r < b && c < b) ? dst[(size_t)(k0 + r) * dp + k0 + c] : 0.0;
+        Aik[r][c] = (r < bi && c < b) ? src[(size_t)(i0 + r) * sp + k0 + c] : 0.0;
+        Rkj[r][c] = (r < b && c < bj) ? src[(size_t)(k0 + r) * sp + j0 + c] : 0.0;   // A_KJ for now
+    }
+    __syncthreads();
+    double out[4];
+    if (!jk) {
+        // R = P^-1 A_KJ (the K rows' result, and the factor of every tile off the panel)
+        double rv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int q = t + e * 256, r = q / kGjNb, c = q % kGjNb;
+            double v = 0.0;
+            if (r < b && c < bj)
+                for (int m = 0; m < b; ++m) v += Pi[r][m] * Rkj[m][c];
+            rv[e] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int q = t + e * 256;
+            Rkj[q / kGjNb][q % kGjNb] = rv[e];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int q = t + e * 256, r = q / kGjNb, c = q % kGjNb;
+        double v = 0.0;
+        if (r < bi && c < bj) {
+            if (ik) {
+                v = Rkj[r][c];
+            } else if (jk) {
+                for (int m = 0; m < b; ++m) v -= Aik[r][m] * Pi[m][c];
+            } else {
+                v = src[(size_t)(i0 + r) * sp + j0 + c];
+                for (int m = 0; m < b; ++m) v -= Aik[r][m] * Rkj[m][c];
+            }
+        }
+        out[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int q = t + e * 256, r = q / kGjNb, c = q % kGjNb;
+        if (r < bi && c < bj) dst[(size_t)(i0 + r) * dp + j0 + c] = out[e];
+    }
+}
+
+void spd_inverse_gj(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s) {
+    const int nb = (n + kGjNb - 1) / kGjNb;
+    const dim3 grid((unsigned)nb, (unsigned)nb);
+    const double* src = H;
+    int sp = n;
+    for (int q = 0; q < nb; ++q) {
+        const bool last = q == nb - 1;
+        double* dst = last ? Hinv : (q % 2 == 0 ? L : X);
+        const int dp = last ? np : n;
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGjNb * kGjNb), 0, s, n, q * kGjNb, src, sp, dst, dp, info);
+        if (nb > 1) hipLaunchKernelGGL(k_gj_panel, grid, dim3(256), 0, s, n, q * kGjNb, src, sp, dst, dp);
+        src = dst;
+        sp = dp;
+    }
+}
+
 void helm_setup_diag(int N, double nu, double dt, const double* A_dev, const double* M_dev, double* hdiag_dev,
                      hipStream_t s) {
     hipLaunchKernelGGL(k_hdiag, dim3((N + 255) / 256), dim3(256), 0, s, N, nu, 1.0 / dt, A_dev, M_dev, hdiag_dev);

@@ -866,7 +866,7 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
             if (mode == 2) tensor_times(U1, F[1]);
             if (mode == 0) launch_als_reduce(N, R, 1, T, F[1], Mb, (int)rp, s);       // sum_j T[(i,j)] A2[j]
             else launch_als_reduce(N, R, 0, T, F[0], Mb, (int)rp, s);                 // sum_i T[(i,.)] A1[i]
-            spd_inverse(R, (int)rp, V, L, X, Vinv, info, s);
+            spd_inverse_gj(R, (int)rp, V, L, X, Vinv, info, s);
             // F[mode][i][m] = sum_k Vinv[m][k] Mb[i][k]  (V symmetric)
             launch_gemm_f64(pl, Vinv, (long long)rp, Mb, (long long)rp, Yb, R, (int)rp, (int)npad, s);
             if (hipMemcpyAsync(F[mode], Yb, sizeof(double) * n * r, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -974,14 +974,14 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
     tensor_times_a3();
     launch_als_reduce(N, R, 0, T, A1, Mb, (int)rp, s);                 // sum_i T[(i, j)] A1[i]
     launch_skew_tie(N, P, V, Vt, Mb, (int)rp, Mt, (int)pp, s);
-    spd_inverse(P, (int)pp, Vt, Lt, Xt, Vtinv, info, s);
+    spd_inverse_gj(P, (int)pp, Vt, Lt, Xt, Vtinv, info, s);
     launch_gemm_f64(plp, Vtinv, (long long)pp, Mt, (long long)pp, Yt, P, (int)pp, (int)npad, s);
     launch_skew_set_b(N, P, Yt, P, B1, A2, s);
     for (int it = 0; it < subiters; ++it) {
         launch_gram_hadamard(N, R, A2, A3, V, s);
         if (it > 0) tensor_times_a3();                                 // A3 moved with A1
         launch_als_reduce(N, R, 1, T, A2, Mb, (int)rp, s);             // sum_j T[(i, j)] A2[j]
-        spd_inverse(R, (int)rp, V, L, X, Vinv, info, s);
+        spd_inverse_gj(R, (int)rp, V, L, X, Vinv, info, s);
         launch_gemm_f64(plr, Vinv, (long long)rp, Mb, (long long)rp, Yb, R, (int)rp, (int)npad, s);
         launch_skew_momentum(N, P, momentum, Yb, R, A1, A3, A11, A12, s);
     }

@@ -290,7 +290,9 @@ class Server:
         self.peak_used = max(self.peak_used, self.used)
         return pool
 
-    def run(self, requests: List[Request]) -> List[Record]:
+    def run(self, requests: List[Request], progress=None, progress_every: float = 30.0) -> List[Record]:
+        """progress(done, total, seconds), if given, is called about every
+        `progress_every` seconds of the run."""
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         qi = 0
         waiting: List[Request] = []
@@ -298,14 +300,20 @@ class Server:
         records: Dict[int, Record] = {}
         t0 = self.clock()
         now = lambda: self.clock() - t0
+        ndone = [0]
+        next_report = progress_every
 
         def finish(rec, u=None, energy=None, error=None):
             rec.done = now()
             rec.u, rec.energy, rec.error = u, energy, error
+            ndone[0] += 1
 
         try:
             while qi < len(pending) or waiting or active:
                 t = now()
+                if progress is not None and t >= next_report:
+                    progress(ndone[0], len(pending), t)
+                    next_report = t + progress_every
                 while qi < len(pending) and pending[qi].arrival <= t:
                     waiting.append(pending[qi])
                     qi += 1
