@@ -141,7 +141,8 @@ void rom_destroy(rom_ctx ctx);
  * subproblems in turn, each through its normal equations, e.g. for the first factor
  *   A1 <- M1 V1^{-1},  M1[i][r] = sum_jk C[i][j][k] A2[j][r] A3[k][r],
  *   V1 = (A2^T A2) .* (A3^T A3),
- * V inverted by Cholesky factorisation in FP64 on the device.
+ * V inverted in FP64 on the device by blocked Gauss-Jordan elimination without pivoting
+ * (every pivot block of an SPD matrix is SPD).
  *   C        device FP64 [N][N][N], C[i][j][k] (position 1 = i, as rom_desc.C); read only.
  *   A1..A3   device FP64 [N][R] factors for positions 1, 2, 3: the initial guess on entry
  *            (the caller chooses it), the fitted factors on return.

@@ -25,12 +25,10 @@ void launch_skew_tie(int N, int P, const double* V, double* Vt, const double* M,
 void launch_skew_set_b(int N, int P, const double* Y, int ldy, double* B1, double* A2, hipStream_t s);
 void launch_skew_momentum(int N, int P, double mom, const double* Y, int ldy, double* A1, double* A3, double* A11,
                           double* A12, hipStream_t s);
-// Hinv [n][np] = H^{-1} for SPD H [n][n] by Cholesky (L), the inverse factor (X) and its
-// Gram product; columns past n of Hinv are left as they are.  *info becomes 1 if a pivot
-// is not positive.
-void spd_inverse(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s);
-// The same inverse by blocked Gauss-Jordan sweeps, one kernel per 32-column panel, with L
-// and X as the two buffers the panels alternate between (each n x n).
+// Hinv [n][np] = H^{-1} for SPD H [n][n] by blocked Gauss-Jordan sweeps, one kernel per
+// 32-column panel, with L and X as the two buffers the panels alternate between (each
+// n x n); columns past n of Hinv are left as they are.  *info becomes 1 if a pivot is not
+// positive.
 void spd_inverse_gj(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s);
 
 }  // namespace rom

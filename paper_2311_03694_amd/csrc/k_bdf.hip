@@ -139,32 +139,6 @@ __global__ void k_build_h(int N, double nu, double diag, const double* __restric
     H[q] = nu * A[q] + diag * (M ? M[q] : (i == m ? 1.0 : 0.0));
 }
 
-// Left-looking Cholesky, column j: one wavefront per row i >= j.
-//   L_jj = sqrt(H_jj - sum_{m<j} L_jm^2),  L_ij = (H_ij - sum_{m<j} L_im L_jm) / L_jj.
-__global__ __launch_bounds__(256) void k_chol_col(int N, int j, const double* __restrict__ H,
-                                                  double* __restrict__ L, int* info) {
-    const int lane = threadIdx.x % kWave;
-    const int i = j + blockIdx.x * 4 + threadIdx.x / kWave;
-    if (i >= N) return;
-    const double* Lj = L + (size_t)j * N;
-    const double* Li = L + (size_t)i * N;
-    double d = 0.0, s = 0.0;
-    for (int m = lane; m < j; m += kWave) {
-        d += Lj[m] * Lj[m];
-        s += Li[m] * Lj[m];
-    }
-    d = wave_sum(d);
-    s = wave_sum(s);
-    const double piv = H[(size_t)j * N + j] - d;
-    if (lane == 0) {
-        if (!(piv > 0.0)) {
-            if (i == j) atomicMax(info, 1);
-        }
-        const double ljj = sqrt(piv);
-        L[(size_t)i * N + j] = (i == j) ? ljj : (H[(size_t)i * N + j] - s) / ljj;
-    }
-}
-
 // Blocked right-looking Cholesky of an SPD matrix in place: L starts as (the lower
 // triangle of) H and ends as its factor, H = L L^T.  Panel after panel of kCholNb
 // columns: k_chol_panel factors the panel's diagonal block (already updated by the panels
@@ -360,107 +334,175 @@ int helm_setup_dense(int N, int Np, double nu, double dt, const double* A_dev, c
     return 0;
 }
 
-// Only the lower triangle of L is written and read (chol_blocked, k_trinv_col), so L needs
-// no clearing and the sequence can be captured into a graph.
-void spd_inverse(int n, int np, const double* H, double* L, double* X, double* Hinv, int* info, hipStream_t s) {
-    chol_blocked(n, H, L, info, s);
-    hipLaunchKernelGGL(k_trinv_col, dim3(n), dim3(64), sizeof(double) * n, s, n, L, X);
-    hipLaunchKernelGGL(k_gram, dim3((n + 255) / 256, n), dim3(256), 0, s, n, np, X, Hinv);
-}
-
 // Blocked Gauss-Jordan inverse of an SPD matrix (no pivoting: the pivot blocks of an SPD
 // matrix are Schur complements of SPD matrices, so SPD themselves).  Panel K (kGjNb columns
 // from k0, b of them) maps the matrix out of place:
 //   A'_KK = P^-1,  A'_KJ = P^-1 A_KJ,  A'_IK = -A_IK P^-1,  A'_IJ = A_IJ - A_IK P^-1 A_KJ,
-// P = A_KK; after every panel the matrix is A^-1.  Two kernels per panel: k_gj_pivot (one
-// block, one thread per entry) inverts P by scalar sweeps of the same formulas and stores
-// it as the K x K tile of the result; k_gj_panel (one block per other 32 x 32 tile) reads
-// it there and forms its tile from the old matrix, which is only read, so no block waits
-// for another.  k_gj_pivot raises *info on a non-positive pivot.
+// P = A_KK; after every panel the matrix is A^-1.  One kernel per panel, one block per
+// 32 x 32 tile of the result.  Every block inverts P itself, by sweeps of the same
+// formulas over its 2 x 2 diagonal blocks in registers (thread t holds column t % 32 of
+// rows 4 (t / 32) .. +3; the pivot rows and columns go through LDS, one barrier per
+// sweep) while its tile operands are in flight; then the block's four waves form the
+// tile's 16 x 16 quarters with FP64 MFMA.  The old matrix is only read, so no block waits
+// for another.  The block of tile (K, K) raises *info on a pivot block that is not
+// positive definite.
 constexpr int kGjNb = 32;
 
-__global__ __launch_bounds__(1024) void k_gj_pivot(int n, int k0, const double* __restrict__ src, int sp,
-                                                   double* __restrict__ dst, int dp, int* info) {
-    __shared__ double P[kGjNb][kGjNb + 1];
-    const int b = n - k0 < kGjNb ? n - k0 : kGjNb;
-    const int r = threadIdx.x / kGjNb, cc = threadIdx.x % kGjNb;
-    const bool in = r < b && cc < b;
-    P[r][cc] = in ? src[(size_t)(k0 + r) * sp + k0 + cc] : 0.0;
-    __syncthreads();
-    for (int c = 0; c < b; ++c) {
-        const double p = P[c][c];
-        if (threadIdx.x == 0 && !(p > 0.0)) atomicMax(info, 1);
-        const double ip = 1.0 / p;
-        double v = 0.0;
-        if (in) {
-            if (r == c && cc == c) v = ip;
-            else if (r == c) v = P[c][cc] * ip;
-            else if (cc == c) v = -P[r][c] * ip;
-            else v = P[r][cc] - P[r][c] * (P[c][cc] * ip);
-        }
-        __syncthreads();
-        if (in) P[r][cc] = v;
-        __syncthreads();
+namespace {
+
+// acc += A[ra.., 0..31] B[0..31, cb..] for a 16 x 16 quarter (wave-wide; LDS operands of
+// pitch kGjNb + 1).  Lane l feeds row / column l % 16 and k group l / 16.
+__device__ __forceinline__ void gj_quarter(f64x4& acc, const double (*A)[kGjNb + 1], int ra,
+                                           const double (*B)[kGjNb + 1], int cb, double sa) {
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int s = 0; s < kGjNb / 4; ++s) {
+        const int k = 4 * s + lane / 16;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sa * A[ra + lane % 16][k], B[k][cb + lane % 16], acc, 0, 0, 0);
     }
-    if (in) dst[(size_t)(k0 + r) * dp + k0 + cc] = P[r][cc];
 }
 
-__global__ __launch_bounds__(256) void k_gj_panel(int n, int k0, const double* __restrict__ src, int sp,
-                                                  double* __restrict__ dst, int dp) {
-    __shared__ double Pi[kGjNb][kGjNb + 1], Aik[kGjNb][kGjNb + 1], Rkj[kGjNb][kGjNb + 1];
+// 1 / d for a positive normal d: the hardware reciprocal refined by two Newton steps
+// (r <- r + r (1 - d r)), within an ulp; five dependent operations where the IEEE division
+// takes eleven, on the pivot chain of the sweeps below.
+__device__ __forceinline__ double gj_recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_gj_step(int n, int k0, const double* __restrict__ src, int sp,
+                                                 double* __restrict__ dst, int dp, int* info) {
+    __shared__ double Pi[kGjNb][kGjNb + 1], Aik[kGjNb][kGjNb + 1], Akj[kGjNb][kGjNb + 1], Rkj[kGjNb][kGjNb + 1];
+    __shared__ __attribute__((aligned(16))) double rowb[2][2][kGjNb], colb[2][2][kGjNb];
     const int b = n - k0 < kGjNb ? n - k0 : kGjNb;
     const int i0 = blockIdx.y * kGjNb, j0 = blockIdx.x * kGjNb;
     const bool ik = i0 == k0, jk = j0 == k0;          // tiles are aligned with the panels
-    if (ik && jk) return;                              // the pivot kernel's tile
     const int bi = n - i0 < kGjNb ? n - i0 : kGjNb, bj = n - j0 < kGjNb ? n - j0 : kGjNb;
-    const int t = threadIdx.x;
-    for (int q = t; q < kGjNb * kGjNb; q += blockDim.x) {
-        const int r = q / kGjNb, c = q % kGjNb;
-        Pi[r][c] = (r < b && c < b) ? dst[(size_t)(k0 + r) * dp + k0 + c] : 0.0;
-        Aik[r][c] = (r < bi && c < b) ? src[(size_t)(i0 + r) * sp + k0 + c] : 0.0;
-        Rkj[r][c] = (r < b && c < bj) ? src[(size_t)(k0 + r) * sp + j0 + c] : 0.0;   // A_KJ for now
+    const int t = threadIdx.x, cc = t % kGjNb, rg = t / kGjNb;
+    const int w = t / kWave, lane = t % kWave;
+    const int rq = (w / 2) * 16, cq = (w % 2) * 16;    // this wave's quarter of the tile
+
+    // P, extended by the identity beyond b (pivots of 1 with zero rows and columns: their
+    // sweeps change nothing, so every block sweeps all kGjNb of them).  The tile operands
+    // (zero beyond the tile) stay in registers until the sweeps are done.  Every load is
+    // issued (addresses clamped into the matrix) and its value selected afterwards, so the
+    // sweeps wait for P's loads alone.
+    const int nm = n - 1;
+    auto at = [&](int r, int c) { return src[(size_t)(r < nm ? r : nm) * sp + (c < nm ? c : nm)]; };
+    double x[4], aik[4], akj[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = at(k0 + 4 * rg + e, k0 + cc);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int q = t + e * 256, r = q / kGjNb, c = q % kGjNb;
+        aik[e] = at(i0 + r, k0 + c);
+        akj[e] = at(k0 + r, j0 + c);
+    }
+    f64x4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = at(i0 + rq + lane / 16 + 4 * v, j0 + cq + lane % 16);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = 4 * rg + e;
+        x[e] = (r < b && cc < b) ? x[e] : (r == cc ? 1.0 : 0.0);
+    }
+
+    // P -> P^-1 by the same map with 2 x 2 pivot blocks Q (SPD as principal blocks of the
+    // Schur complements), pivots c0 = 2s, c1 = 2s + 1: rows c0, c1 become Q^-1 (rows c0, c1),
+    // columns c0, c1 become -(columns c0, c1) Q^-1, the pivot block Q^-1, the rest
+    // x - (columns c0, c1) Q^-1 (rows c0, c1).  Rows and columns c0, c1 pass through LDS
+    // (double buffered: one barrier per pivot block).
+    bool bad = false;
+#pragma unroll
+    for (int st = 0; st < kGjNb / 2; ++st) {
+        const int c0 = 2 * st;
+        double (*rb)[kGjNb] = rowb[st & 1];
+        double (*cb)[kGjNb] = colb[st & 1];
+        if (rg == st / 2) {
+            rb[0][cc] = x[2 * (st % 2)];
+            rb[1][cc] = x[2 * (st % 2) + 1];
+        }
+        if ((cc & ~1) == c0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cb[cc - c0][4 * rg + e] = x[e];
+        }
+        __syncthreads();
+        // every LDS read of the sweep at once (one LDS latency per pivot block)
+        const double p00 = rb[0][c0], p01 = rb[0][c0 + 1], p10 = rb[1][c0], p11 = rb[1][c0 + 1];
+        const double a0 = rb[0][cc], a1 = rb[1][cc];
+        double u0[4], u1[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            u0[e] = cb[0][4 * rg + e];
+            u1[e] = cb[1][4 * rg + e];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const double det = p00 * p11 - p01 * p10;
+        bad |= !(p00 > 0.0) || !(det > 0.0);
+        const double id = gj_recip(det);
+        const double q00 = p11 * id, q01 = -p01 * id, q10 = -p10 * id, q11 = p00 * id;
+        const double g0 = q00 * a0 + q01 * a1, g1 = q10 * a0 + q11 * a1;    // (Q^-1 rows)[., cc]
+        const bool incol = (cc & ~1) == c0;
+        const double qc0 = (cc & 1) ? q01 : q00, qc1 = (cc & 1) ? q11 : q10;  // column cc - c0 of Q^-1
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            double v = x[e] - (u0[e] * g0 + u1[e] * g1);
+            v = incol ? -(u0[e] * qc0 + u1[e] * qc1) : v;
+            if (e / 2 == st % 2) {
+                // rows c0 + e % 2 of the pivot block's row pair
+                const double gr = (e % 2) ? g1 : g0;
+                const double qr = (e % 2) ? ((cc & 1) ? q11 : q10) : ((cc & 1) ? q01 : q00);
+                v = rg == st / 2 ? (incol ? qr : gr) : v;
+            }
+            x[e] = v;
+        }
+    }
+    if (ik && jk) {
+        if (t == 0 && bad) atomicMax(info, 1);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 4 * rg + e;
+            if (r < b && cc < b) dst[(size_t)(k0 + r) * dp + k0 + cc] = x[e];
+        }
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int q = t + e * 256, r = q / kGjNb, c = q % kGjNb;
+        Pi[4 * rg + e][cc] = x[e];
+        Aik[r][c] = (!ik && r < bi && c < b) ? aik[e] : 0.0;
+        Akj[r][c] = (!jk && r < b && c < bj) ? akj[e] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = rq + lane / 16 + 4 * v, c = cq + lane % 16;
+        acc[v] = (!ik && !jk && r < bi && c < bj) ? acc[v] : 0.0;
     }
     __syncthreads();
-    double out[4];
-    if (!jk) {
-        // R = P^-1 A_KJ (the K rows' result, and the factor of every tile off the panel)
-        double rv[4];
+
+    if (ik) {
+        gj_quarter(acc, Pi, rq, Akj, cq, 1.0);                  // P^-1 A_KJ
+    } else if (jk) {
+        gj_quarter(acc, Aik, rq, Pi, cq, -1.0);                 // -A_IK P^-1
+    } else {
+        f64x4 rk = {0.0, 0.0, 0.0, 0.0};
+        gj_quarter(rk, Pi, rq, Akj, cq, 1.0);                   // R = P^-1 A_KJ
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int q = t + e * 256, r = q / kGjNb, c = q % kGjNb;
-            double v = 0.0;
-            if (r < b && c < bj)
-                for (int m = 0; m < b; ++m) v += Pi[r][m] * Rkj[m][c];
-            rv[e] = v;
-        }
+        for (int v = 0; v < 4; ++v) Rkj[rq + lane / 16 + 4 * v][cq + lane % 16] = rk[v];
         __syncthreads();
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int q = t + e * 256;
-            Rkj[q / kGjNb][q % kGjNb] = rv[e];
-        }
-        __syncthreads();
+        gj_quarter(acc, Aik, rq, Rkj, cq, -1.0);                // A_IJ - A_IK R
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int q = t + e * 256, r = q / kGjNb, c = q % kGjNb;
-        double v = 0.0;
-        if (r < bi && c < bj) {
-            if (ik) {
-                v = Rkj[r][c];
-            } else if (jk) {
-                for (int m = 0; m < b; ++m) v -= Aik[r][m] * Pi[m][c];
-            } else {
-                v = src[(size_t)(i0 + r) * sp + j0 + c];
-                for (int m = 0; m < b; ++m) v -= Aik[r][m] * Rkj[m][c];
-            }
-        }
-        out[e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int q = t + e * 256, r = q / kGjNb, c = q % kGjNb;
-        if (r < bi && c < bj) dst[(size_t)(i0 + r) * dp + j0 + c] = out[e];
+    for (int v = 0; v < 4; ++v) {
+        const int r = rq + lane / 16 + 4 * v, c = cq + lane % 16;
+        if (r < bi && c < bj) dst[(size_t)(i0 + r) * dp + j0 + c] = acc[v];
     }
 }
 
@@ -473,8 +515,7 @@ void spd_inverse_gj(int n, int np, const double* H, double* L, double* X, double
         const bool last = q == nb - 1;
         double* dst = last ? Hinv : (q % 2 == 0 ? L : X);
         const int dp = last ? np : n;
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kGjNb * kGjNb), 0, s, n, q * kGjNb, src, sp, dst, dp, info);
-        if (nb > 1) hipLaunchKernelGGL(k_gj_panel, grid, dim3(256), 0, s, n, q * kGjNb, src, sp, dst, dp);
+        hipLaunchKernelGGL(k_gj_step, grid, dim3(256), 0, s, n, q * kGjNb, src, sp, dst, dp, info);
         src = dst;
         sp = dp;
     }
