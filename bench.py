@@ -577,24 +577,33 @@ def main():
         rng = np.random.default_rng(2)
         Xd = torch.tensor(rng.standard_normal((Na, Na, Na)), dtype=torch.float64, device=dev)
         Fd = [torch.tensor(rng.standard_normal((Na, Ra)), dtype=torch.float64, device=dev) for _ in range(3)]
+        # a call allocates its workspace, unfolds the tensor and captures one sweep into a
+        # graph before replaying it: per sweep = the difference of a 12-sweep and a 2-sweep
+        # call over 10; the rest of a call is its set-up
         rg.rom_cp_als(Na, Ra, Xd, *Fd, 1, stream=stream)
-        nsw = 3
-        t_als = timer(lambda: rg.rom_cp_als(Na, Ra, Xd, *Fd, nsw, stream=stream)) / nsw
+
+        def per_sweep(call):
+            t2, t12 = timer(lambda: call(2)), timer(lambda: call(12))
+            per = (t12 - t2) / 10
+            return per, t2 - 2 * per
+
+        t_als, set_als = per_sweep(lambda k: rg.rom_cp_als(Na, Ra, Xd, *Fd, k, stream=stream))
         fl = 3 * 2.0 * Na ** 3 * Ra
-        result["als"] = {"N": Na, "R": Ra, "ms_per_sweep": t_als * 1e3,
+        result["als"] = {"N": Na, "R": Ra, "ms_per_sweep": t_als * 1e3, "call_setup_ms": set_als * 1e3,
                          "mttkrp_flops_per_sweep": fl, "sweep_tflops": fl / t_als / 1e12}
-        log(f"cp-als N={Na} R={Ra}: {t_als * 1e3:.2f} ms per sweep")
+        log(f"cp-als N={Na} R={Ra}: {t_als * 1e3:.2f} ms per sweep, {set_als * 1e3:.2f} ms set-up per call")
         # ALS-skew at the same size: P = 200 column pairs (R = 400), 3 subiterations per
         # sweep (one tied solve and three momentum subiterations), on a skew tensor
         Pa, sub = Ra // 2, 3
         Xs = Xd - Xd.permute(2, 1, 0)
         Fs = [torch.tensor(rng.standard_normal((Na, Pa)), dtype=torch.float64, device=dev) for _ in range(3)]
         rg.rom_cp_als_skew(Na, Pa, Xs, *Fs, 1, sub, stream=stream)
-        t_sk = timer(lambda: rg.rom_cp_als_skew(Na, Pa, Xs, *Fs, nsw, sub, stream=stream)) / nsw
+        t_sk, set_sk = per_sweep(lambda k: rg.rom_cp_als_skew(Na, Pa, Xs, *Fs, k, sub, stream=stream))
         fl_sk = (1 + sub - 1) * 2.0 * Na ** 3 * Ra
         result["als"]["skew"] = {"P": Pa, "subiters": sub, "momentum": 0.5, "ms_per_sweep": t_sk * 1e3,
-                                 "tensor_product_flops_per_sweep": fl_sk}
-        log(f"als-skew N={Na} P={Pa} subiters={sub}: {t_sk * 1e3:.2f} ms per sweep")
+                                 "call_setup_ms": set_sk * 1e3, "tensor_product_flops_per_sweep": fl_sk}
+        log(f"als-skew N={Na} P={Pa} subiters={sub}: {t_sk * 1e3:.2f} ms per sweep, {set_sk * 1e3:.2f} ms set-up "
+            f"per call")
         del Xd, Fd, Xs, Fs
         # accuracy (oracle leg): 2 sweeps of each at N = 40, R = 24 from seeded factors
         rng = np.random.default_rng(4)

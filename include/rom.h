@@ -307,7 +307,9 @@ rom_status rom_query(rom_ctx ctx, rom_state st, int32_t what, int64_t *value);
  * results equal the per-step kernels' to the bit.  A wait for another block's data that
  * does not end within a bounded number of polling rounds (seconds) makes rom_step_sync
  * return ROM_E_DEVICE.  A run is not captured into graphs (a capturing stream takes the
- * per-step kernels). */
+ * per-step kernels).  When the runtime refuses the cooperative launch (for instance while
+ * another process on the GPU holds the device's resource for such launches), the context
+ * takes the per-step kernels from then on, with the same results. */
 rom_status rom_set_tile(rom_ctx ctx, int32_t kind, int32_t value);
 int32_t rom_tile_count(int32_t kind);
 

@@ -111,8 +111,10 @@ struct rom_ctx_s {
     // steps (-1 default = on where the operator fits on chip, 0 off)
     int tile[6] = {-1, -1, -1, -1, -1, -1};
     // resident one-trajectory CP steps: geometry, valid while res_gen == ws_gen
-    // (res_ok 0: not available for this context)
+    // (res_ok 0: not available for this context; res_refused: the runtime refused a
+    // cooperative launch, e.g. while another process holds the device's resource for them)
     int res_gen = -1, res_ok = 0, res_G = 0, res_nrg = 0, res_npg = 0, res_rg = 0, res_pg = 0;
+    bool res_refused = false;
     size_t res_lds = 0;
     size_t lds_max = 65536;                     // dynamic LDS a batched kernel may take
     size_t bytes = 0;
@@ -777,6 +779,29 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, const rom_ful
 }
 
 extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) { return create_ctx(d, nullptr, nullptr, out); }
+// The tensor-factor product of the ALS sweeps on the one-pass MFMA kernel when its X tile
+// fits in 64 KB of LDS (two blocks per compute unit, one staging its tile while the other
+// multiplies: 8% less per sweep than one block with a 64-column tile at N = 200, R = 400;
+// the allowance is set here, before any capture), else on the skinny GEMM.  The transposed
+// factor it reads gets kWideSlack zeroed elements past its end.
+constexpr size_t kWideSlack = 16;
+constexpr int kWideLds = 65536;
+struct WideProduct {
+    MfmaPlan pl;
+    bool ok;
+};
+static WideProduct wide_product(int M, int Kp, int Bpad) {
+    int dev = 0, lds = 0;
+    WideProduct w{};
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return w;
+    w.pl = mfma_wide_plan(M, Kp, Bpad, (size_t)std::min(lds, kWideLds));
+    w.ok = mfma_wide_ready(w.pl);
+    if (!w.ok) (void)hipGetLastError();        // a refused allowance is not the call's error
+    return w;
+}
+
 extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* A1, double* A2, double* A3,
                                   int32_t sweeps, void* stream) {
     if (N < 1 || N > 4096) return fail(ROM_E_INVALID, "N must be in [1, 4096] (got %d)", N);
@@ -787,13 +812,13 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
     hipStream_t s = (hipStream_t)stream;
     const size_t n = (size_t)N, r = (size_t)R, rp = (r + 7) / 8 * 8, npad = (n + 15) / 16 * 16;
     const size_t np = (n + 7) / 8 * 8, n2pad = (n * n + 15) / 16 * 16;
-    // V, its Cholesky factor and inverse factor [R][R]; Vinv [R][Rp] and the right-hand
+    // V and the two panel buffers of its inverse [R][R]; Vinv [R][Rp] and the right-hand
     // side Mb [Npad][Rp] with zero padding (the product's K = Rp); the product Yb [Npad][R];
     // the two unfoldings of C [N^2 padded][Np], a transposed factor [R][Np] and the
     // tensor-factor product T [N^2 padded][R]
     constexpr int kBufs = 10;
-    const size_t sizes[kBufs] = {r * r, r * r, r * r, r * rp, npad * rp, npad * r, n2pad * np, n2pad * np, r * np,
-                                 n2pad * r};
+    const size_t sizes[kBufs] = {r * r, r * r, r * r, r * rp, npad * rp, npad * r, n2pad * np, n2pad * np,
+                                 r * np + kWideSlack, n2pad * r};
     double* buf[kBufs] = {};
     int* info = nullptr;
     struct Guard {
@@ -817,6 +842,7 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
         hipMemsetAsync(Mb, 0, sizeof(double) * sizes[4], s) != hipSuccess ||
         hipMemsetAsync(U0, 0, sizeof(double) * sizes[6], s) != hipSuccess ||
         hipMemsetAsync(U1, 0, sizeof(double) * sizes[7], s) != hipSuccess ||
+        hipMemsetAsync(Ft, 0, sizeof(double) * sizes[8], s) != hipSuccess ||
         hipMemsetAsync(info, 0, sizeof(int), s) != hipSuccess)
         return fail(ROM_E_DEVICE, "CP-ALS workspace clear failed");
     launch_als_unfold(N, (int)np, 0, C, U0, s);     // rows (i, j), columns k
@@ -848,10 +874,12 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
         return fail(ROM_E_DEVICE, "CP-ALS stream setup failed");
     double* F[3] = {A1, A2, A3};
     const GemmPlan pl = gemm_plan(R, (int)npad, 0), plt = gemm_plan(R, (int)n2pad, 0);
+    const WideProduct wide = wide_product(R, (int)np, (int)n2pad);
     // T[row][m] = sum_c Ft[m][c] U[row][c]: the unfolding times one factor
     auto tensor_times = [&](const double* Uf, const double* Fk) {
         launch_als_transpose(N, R, (int)np, Fk, Ft, s);
-        launch_gemm_f64(plt, Ft, (long long)np, Uf, (long long)np, T, R, (int)np, (int)n2pad, s);
+        if (wide.ok) launch_mfma_wide(wide.pl, Ft, R, (int)np, Uf, (int)n2pad, T, s);
+        else launch_gemm_f64(plt, Ft, (long long)np, Uf, (long long)np, T, R, (int)np, (int)n2pad, s);
     };
     s = cs;   // every launch below (tensor_times included) goes to the capture stream
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -903,7 +931,7 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
     // a transposed factor Ft [R][Np] and the product T [N^2 padded][R]
     constexpr int kBufs = 17;
     const size_t sizes[kBufs] = {n * r, n * r, n * r, r * r, r * r, r * r, r * rp, npad * rp, npad * r,
-                                 p * p, p * p, p * p, p * pp, npad * pp, npad * p, n2pad * np, r * np};
+                                 p * p, p * p, p * p, p * pp, npad * pp, npad * p, n2pad * np, r * np + kWideSlack};
     const size_t tsize = n2pad * r;
     double* buf[kBufs + 1] = {};
     int* info = nullptr;
@@ -930,6 +958,7 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
         hipMemsetAsync(Vtinv, 0, sizeof(double) * sizes[12], s) != hipSuccess ||
         hipMemsetAsync(Mt, 0, sizeof(double) * sizes[13], s) != hipSuccess ||
         hipMemsetAsync(U0, 0, sizeof(double) * sizes[15], s) != hipSuccess ||
+        hipMemsetAsync(Ft, 0, sizeof(double) * sizes[16], s) != hipSuccess ||
         hipMemsetAsync(info, 0, sizeof(int), s) != hipSuccess)
         return fail(ROM_E_DEVICE, "ALS-skew workspace clear failed");
     launch_als_unfold(N, (int)np, 0, C, U0, s);     // rows (i, j), columns k
@@ -959,13 +988,15 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
         return fail(ROM_E_DEVICE, "ALS-skew stream setup failed");
     const GemmPlan plt = gemm_plan(R, (int)n2pad, 0), plr = gemm_plan(R, (int)npad, 0),
                    plp = gemm_plan(P, (int)npad, 0);
+    const WideProduct wide = wide_product(R, (int)np, (int)n2pad);
     s = cs;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(ROM_E_DEVICE, "ALS-skew graph capture failed to start");
     // T[(i, j)][m] = sum_k C[i][j][k] A3[k][m]: the unfolding times the third factor
     auto tensor_times_a3 = [&]() {
         launch_als_transpose(N, R, (int)np, A3, Ft, s);
-        launch_gemm_f64(plt, Ft, (long long)np, U0, (long long)np, T, R, (int)np, (int)n2pad, s);
+        if (wide.ok) launch_mfma_wide(wide.pl, Ft, R, (int)np, U0, (int)n2pad, T, s);
+        else launch_gemm_f64(plt, Ft, (long long)np, U0, (long long)np, T, R, (int)np, (int)n2pad, s);
     };
     // one sweep: the tied second factor (least squares with A2 = B1 [I I]), then the
     // subiterations of the first factor with A3 fixed, each followed by the momentum
@@ -1605,6 +1636,7 @@ constexpr unsigned kResSpin = 1u << 21;   // polling rounds before a wait gives 
 // every block of the run co-resident (one per compute unit at most), the block's rows and
 // vectors in its LDS, the vectors a block waits for within kResWaitWords message words.
 static bool res_plan(rom_ctx c) {
+    if (c->res_refused) return false;
     if (c->res_gen == c->ws_gen) return c->res_ok != 0;
     c->res_gen = c->ws_gen;
     c->res_ok = 0;
@@ -1668,8 +1700,11 @@ static rom_status ensure_res(rom_ctx c, rom_state s) {
     return ROM_OK;
 }
 
-// One resident run of L steps from level n0 >= 2, then its closing block.
-static rom_status launch_resident(rom_ctx c, rom_state s, long long n0, int L) {
+// One resident run of L steps from level n0 >= 2, then its closing block.  Returns
+// *refused = true (and ROM_OK) when the runtime refuses the cooperative launch: nothing was
+// enqueued, and the context takes the per-step kernels from then on.
+static rom_status launch_resident(rom_ctx c, rom_state s, long long n0, int L, bool* refused) {
+    *refused = false;
     const SkewPairs sk = skew_of(c);
     ResJob jb{};
     jb.a = step_args(s, n0);
@@ -1705,7 +1740,12 @@ static rom_status launch_resident(rom_ctx c, rom_state s, long long n0, int L) {
     jb.err = (int*)(s->a.bad + 1);
     jb.spin_max = kResSpin;
     hipError_t e = res_launch(c->dtype, jb, c->res_G, c->res_lds, c->stream);
-    if (e != hipSuccess) return fail(ROM_E_DEVICE, "resident step launch failed: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->res_refused = true;
+        *refused = true;
+        return ROM_OK;
+    }
     res_close_launch(step_args(s, n0), step_args(s, n0 + L), n0, L, s->res_ep, c->res_nrg, s->res_seq, c->stream);
     HIPCHK(hipGetLastError());
     return ROM_OK;
@@ -1731,7 +1771,11 @@ static rom_status walk_steps(rom_ctx c, rom_state s, long long n0, int64_t nstep
     }
     while (left >= kResMin) {
         const int L = (int)std::min<int64_t>(left, kResMax);
-        if (launch) TRYS(launch_resident(c, s, n, L));
+        if (launch) {
+            bool refused = false;
+            TRYS(launch_resident(c, s, n, L, &refused));
+            if (refused) break;                      // the rest through the graphs
+        }
         n += L;
         left -= L;
     }

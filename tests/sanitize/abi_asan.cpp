@@ -204,7 +204,8 @@ void gpu_checks() {
         for (int b = 0; b < cs.batch; ++b) u0.insert(u0.end(), p.u0.begin(), p.u0.end());
         const auto e1 = stepped(ctx, u0, cs.batch, {70});
         const auto e2 = stepped(ctx, u0, cs.batch, {9, 61});
-        check(e1.size() == e2.size() && std::memcmp(e1.data(), e2.data(), e1.size() * sizeof(double)) == 0,
+        check(!e1.empty() && e1.size() == e2.size() &&
+                  std::memcmp(e1.data(), e2.data(), e1.size() * sizeof(double)) == 0,
               "step splits agree");
         // evaluation through both entry points
         double *ud = nullptr, *y1 = nullptr, *y2 = nullptr;
@@ -261,7 +262,8 @@ void gpu_checks() {
     for (size_t q = 0; q < ms.size(); ++q) {
         std::vector<double> E(41);
         check(rom_energy(mc[q], ms[q], nullptr, E.data()) == ROM_OK, "energy");
-        check(std::memcmp(E.data(), alone[q].data(), sizeof(double) * 41) == 0, "multi equals alone");
+        check(alone[q].size() == 41 && std::memcmp(E.data(), alone[q].data(), sizeof(double) * 41) == 0,
+              "multi equals alone");
     }
     rom_state_destroy(ms.back());   // drops the set's tables; the rest steps on
     ms.pop_back();

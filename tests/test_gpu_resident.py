@@ -140,3 +140,41 @@ def test_resident_first_bad_level(torch_gpu):
     with pytest.raises(rg.NonFinite) as ei:
         s.step(400)
     assert ei.value.first_bad == r["first_bad"]
+
+
+def test_resident_in_a_second_process(torch_gpu, tmp_path):
+    """This process takes a resident run first; then a child process steps the same
+    problem.  The runtime may refuse the child's cooperative launch while this process
+    holds the device's resource for such launches: the child's steps must then go through
+    the per-step kernels, and either way its levels equal the per-step kernels' to the bit."""
+    import os
+    import subprocess
+    _say("resident run here, then the same steps in a child process")
+    p = romsynth.make_problem(64, pairs=40, eps=1e-6, nu=1e-3, dt=1e-3, A="spd", cfg=93, dense=False)
+    res, ref = _pair(p, "fp32", True)
+    a, b = res.state(p.u0[0]), ref.state(p.u0[0])
+    assert a.resident_blocks > 0
+    a.step(100)
+    b.step(100)
+    _same(a, b, "this process")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = tmp_path / "child.npz"
+    code = f"""
+import sys
+sys.path.insert(0, {root!r})
+import numpy as np, romsynth, paper_2311_03694_amd as rg
+p = romsynth.make_problem(64, pairs=40, eps=1e-6, nu=1e-3, dt=1e-3, A="spd", cfg=93, dense=False)
+rom = rg.Rom(p.N, p.nu, p.dt, p.A, lam=p.lam, Af=p.Af, Bf=p.Bf, Cf=p.Cf, dtype="fp32")
+st = rom.state(p.u0[0])
+st.step(100)
+u, y, n = st.get()
+np.savez({str(out)!r}, u=u, y=y, E=st.energy()[1], n=n)
+print("child done", flush=True)
+"""
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
+    got = np.load(out)
+    ub, yb, nb = b.get()
+    assert int(got["n"]) == nb
+    assert np.array_equal(got["u"], ub) and np.array_equal(got["y"], yb)
+    assert np.array_equal(got["E"], b.energy()[1])
