@@ -802,6 +802,52 @@ static WideProduct wide_product(int M, int Kp, int Bpad) {
     return w;
 }
 
+// Streams and graph of an ALS call: the capture stream cs (ordered after the caller's
+// stream), a side stream for the SPD inverses, and one fork / join event pair per update
+// of a sweep.  fork(q) makes the side stream wait for cs; join_mark(q) records the side
+// stream's work; join(q) makes cs wait for it.  The side stream joins the capture through
+// the fork and leaves it through the join, so the graph holds the inverse as a branch.
+struct SweepStreams {
+    static constexpr int kPairs = 8;
+    hipStream_t cs = nullptr, side = nullptr;
+    hipEvent_t start = nullptr, evf[kPairs] = {}, evj[kPairs] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool init(hipStream_t caller) {
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess)
+            return false;
+        for (int q = 0; q < kPairs; ++q)
+            if (hipEventCreateWithFlags(&evf[q], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&evj[q], hipEventDisableTiming) != hipSuccess)
+                return false;
+        return hipEventRecord(start, caller) == hipSuccess && hipStreamWaitEvent(cs, start, 0) == hipSuccess;
+    }
+    bool fork(int q) {
+        return q < kPairs && hipEventRecord(evf[q], cs) == hipSuccess && hipStreamWaitEvent(side, evf[q], 0) == hipSuccess;
+    }
+    bool join_mark(int q) { return q < kPairs && hipEventRecord(evj[q], side) == hipSuccess; }
+    bool join(int q) { return q < kPairs && hipStreamWaitEvent(cs, evj[q], 0) == hipSuccess; }
+    ~SweepStreams() {
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (graph) hipGraphDestroy(graph);
+        if (cs) {
+            hipStreamSynchronize(cs);
+            hipStreamDestroy(cs);
+        }
+        if (side) {
+            hipStreamSynchronize(side);
+            hipStreamDestroy(side);
+        }
+        if (start) hipEventDestroy(start);
+        for (int q = 0; q < kPairs; ++q) {
+            if (evf[q]) hipEventDestroy(evf[q]);
+            if (evj[q]) hipEventDestroy(evj[q]);
+        }
+    }
+};
+
 extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* A1, double* A2, double* A3,
                                   int32_t sweeps, void* stream) {
     if (N < 1 || N > 4096) return fail(ROM_E_INVALID, "N must be in [1, 4096] (got %d)", N);
@@ -847,31 +893,15 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
         return fail(ROM_E_DEVICE, "CP-ALS workspace clear failed");
     launch_als_unfold(N, (int)np, 0, C, U0, s);     // rows (i, j), columns k
     launch_als_unfold(N, (int)np, 1, C, U1, s);     // rows (i, k), columns j
-    // one sweep (about 3 R + 30 launches) is captured once into a graph on a stream of
-    // this call, ordered after the caller's stream, and replayed `sweeps` times
-    hipStream_t cs = nullptr;
-    hipEvent_t ev = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    struct GraphGuard {
-        hipStream_t* cs;
-        hipEvent_t* ev;
-        hipGraph_t* g;
-        hipGraphExec_t* ge;
-        ~GraphGuard() {
-            if (*ge) hipGraphExecDestroy(*ge);
-            if (*g) hipGraphDestroy(*g);
-            if (*cs) {
-                hipStreamSynchronize(*cs);
-                hipStreamDestroy(*cs);
-            }
-            if (*ev) hipEventDestroy(*ev);
-        }
-    } gguard{&cs, &ev, &graph, &gexec};
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess ||
-        hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
-        return fail(ROM_E_DEVICE, "CP-ALS stream setup failed");
+    // one sweep (about 3 R / 16 + 30 launches) is captured once into a graph on a stream of
+    // this call, ordered after the caller's stream, and replayed `sweeps` times; each
+    // inverse runs on a side stream beside the right-hand side of its update (a branch of
+    // the graph)
+    SweepStreams ss;
+    if (!ss.init(s)) return fail(ROM_E_DEVICE, "CP-ALS stream setup failed");
+    hipStream_t cs = ss.cs;
+    hipGraph_t& graph = ss.graph;
+    hipGraphExec_t& gexec = ss.gexec;
     double* F[3] = {A1, A2, A3};
     const GemmPlan pl = gemm_plan(R, (int)npad, 0), plt = gemm_plan(R, (int)n2pad, 0);
     const WideProduct wide = wide_product(R, (int)np, (int)n2pad);
@@ -888,13 +918,16 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
     for (int mode = 0; mode < 3; ++mode) {
             const int a = mode == 0 ? 1 : 0, b = mode == 2 ? 1 : 2;
             launch_gram_hadamard(N, R, F[a], F[b], V, s);
+            copy_ok = ss.fork(mode) && copy_ok;
+            spd_inverse_gj(R, (int)rp, V, L, X, Vinv, info, ss.side);
+            copy_ok = ss.join_mark(mode) && copy_ok;
             // right-hand side: modes 1 and 2 share T = C x_k A3 (A3 is fixed until mode 3);
             // mode 3 uses C x_j A2 over rows (i, k)
             if (mode == 0) tensor_times(U0, F[2]);
             if (mode == 2) tensor_times(U1, F[1]);
             if (mode == 0) launch_als_reduce(N, R, 1, T, F[1], Mb, (int)rp, s);       // sum_j T[(i,j)] A2[j]
             else launch_als_reduce(N, R, 0, T, F[0], Mb, (int)rp, s);                 // sum_i T[(i,.)] A1[i]
-            spd_inverse_gj(R, (int)rp, V, L, X, Vinv, info, s);
+            copy_ok = ss.join(mode) && copy_ok;
             // F[mode][i][m] = sum_k Vinv[m][k] Mb[i][k]  (V symmetric)
             launch_gemm_f64(pl, Vinv, (long long)rp, Mb, (long long)rp, Yb, R, (int)rp, (int)npad, s);
             if (hipMemcpyAsync(F[mode], Yb, sizeof(double) * n * r, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -963,29 +996,11 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
         return fail(ROM_E_DEVICE, "ALS-skew workspace clear failed");
     launch_als_unfold(N, (int)np, 0, C, U0, s);     // rows (i, j), columns k
     launch_skew_assemble(N, P, A11, A12, B1, A1, A2, A3, s);
-    hipStream_t cs = nullptr;
-    hipEvent_t ev = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    struct GraphGuard {
-        hipStream_t* cs;
-        hipEvent_t* ev;
-        hipGraph_t* g;
-        hipGraphExec_t* ge;
-        ~GraphGuard() {
-            if (*ge) hipGraphExecDestroy(*ge);
-            if (*g) hipGraphDestroy(*g);
-            if (*cs) {
-                hipStreamSynchronize(*cs);
-                hipStreamDestroy(*cs);
-            }
-            if (*ev) hipEventDestroy(*ev);
-        }
-    } gguard{&cs, &ev, &graph, &gexec};
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, s) != hipSuccess ||
-        hipStreamWaitEvent(cs, ev, 0) != hipSuccess)
-        return fail(ROM_E_DEVICE, "ALS-skew stream setup failed");
+    SweepStreams ss;
+    if (!ss.init(s)) return fail(ROM_E_DEVICE, "ALS-skew stream setup failed");
+    hipStream_t cs = ss.cs;
+    hipGraph_t& graph = ss.graph;
+    hipGraphExec_t& gexec = ss.gexec;
     const GemmPlan plt = gemm_plan(R, (int)n2pad, 0), plr = gemm_plan(R, (int)npad, 0),
                    plp = gemm_plan(P, (int)npad, 0);
     const WideProduct wide = wide_product(R, (int)np, (int)n2pad);
@@ -1008,15 +1023,22 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
     spd_inverse_gj(P, (int)pp, Vt, Lt, Xt, Vtinv, info, s);
     launch_gemm_f64(plp, Vtinv, (long long)pp, Mt, (long long)pp, Yt, P, (int)pp, (int)npad, s);
     launch_skew_set_b(N, P, Yt, P, B1, A2, s);
+    bool cap_ok = true;
     for (int it = 0; it < subiters; ++it) {
         launch_gram_hadamard(N, R, A2, A3, V, s);
+        // the inverse on the side stream, beside the right-hand side
+        const int q = it % SweepStreams::kPairs;
+        cap_ok = ss.fork(q) && cap_ok;
+        spd_inverse_gj(R, (int)rp, V, L, X, Vinv, info, ss.side);
+        cap_ok = ss.join_mark(q) && cap_ok;
         if (it > 0) tensor_times_a3();                                 // A3 moved with A1
         launch_als_reduce(N, R, 1, T, A2, Mb, (int)rp, s);             // sum_j T[(i, j)] A2[j]
-        spd_inverse_gj(R, (int)rp, V, L, X, Vinv, info, s);
+        cap_ok = ss.join(q) && cap_ok;
         launch_gemm_f64(plr, Vinv, (long long)rp, Mb, (long long)rp, Yb, R, (int)rp, (int)npad, s);
         launch_skew_momentum(N, P, momentum, Yb, R, A1, A3, A11, A12, s);
     }
     hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess && !cap_ok) e = hipErrorInvalidValue;
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
     for (int sw = 0; sw < sweeps && e == hipSuccess; ++sw) e = hipGraphLaunch(gexec, cs);
