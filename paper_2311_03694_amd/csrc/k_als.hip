@@ -49,24 +49,28 @@ void launch_als_transpose(int N, int R, int np, const double* F, double* Ft, hip
 }
 
 // M[p][r] (pitch ldm) = sum_q T[row(p, q)][r] F[q][r], row = p N + q (first index
-// kept) or q N + p (second index kept); thread r, block row p.
+// kept) or q N + p (second index kept); thread r, block row p.  T is streamed once (N^2 R
+// values): eight rows are loaded before they are used, into eight partial sums added in a
+// fixed order.
 __global__ __launch_bounds__(256) void k_als_reduce(int N, int R, int keep_first, const double* __restrict__ T,
                                                     const double* __restrict__ F, double* __restrict__ M, int ldm) {
     const int p = blockIdx.y, r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
-    double a0 = 0.0, a1 = 0.0;
+    auto row = [&](int q) { return keep_first ? (size_t)p * N + q : (size_t)q * N + p; };
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int q = 0;
-    for (; q + 1 < N; q += 2) {
-        const size_t r0 = keep_first ? (size_t)p * N + q : (size_t)q * N + p;
-        const size_t r1 = keep_first ? (size_t)p * N + q + 1 : (size_t)(q + 1) * N + p;
-        a0 += T[r0 * R + r] * F[(size_t)q * R + r];
-        a1 += T[r1 * R + r] * F[(size_t)(q + 1) * R + r];
+    for (; q + 8 <= N; q += 8) {
+        double t[8], f[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            t[e] = T[row(q + e) * R + r];
+            f[e] = F[(size_t)(q + e) * R + r];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] += t[e] * f[e];
     }
-    if (q < N) {
-        const size_t r0 = keep_first ? (size_t)p * N + q : (size_t)q * N + p;
-        a0 += T[r0 * R + r] * F[(size_t)q * R + r];
-    }
-    M[(size_t)p * ldm + r] = a0 + a1;
+    for (; q < N; ++q) acc[0] += T[row(q) * R + r] * F[(size_t)q * R + r];
+    M[(size_t)p * ldm + r] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
 void launch_als_reduce(int N, int R, int keep_first, const double* T, const double* F, double* M, int ldm,
@@ -74,22 +78,49 @@ void launch_als_reduce(int N, int R, int keep_first, const double* T, const doub
     hipLaunchKernelGGL(k_als_reduce, dim3((R + 255) / 256, N), dim3(256), 0, s, N, R, keep_first, T, F, M, ldm);
 }
 
-// Block row r, thread column s: both Gram entries over the N factor rows.
-__global__ __launch_bounds__(256) void k_gram_hadamard(int N, int R, const double* __restrict__ Fa,
+// V = (Fa^T Fa) .* (Fb^T Fb) [R][R] on FP64 MFMA: a block per 32 x 32 tile of V, eight
+// waves: wave w forms quarter w % 4 (rows r0, columns c0) over the factor rows of issues
+// s = w / 4, w / 4 + 2, ... (two halves of the contracted range, added in LDS).  Lane l
+// feeds row / column l % 16 and factor row k = 4 s + l / 16 of issue s, its operands read
+// straight from the factors (16 consecutive values of one factor row per 16 lanes); rows
+// past N give zeros and columns past R are clamped for the loads and not stored.
+__global__ __launch_bounds__(512) void k_gram_hadamard(int N, int R, const double* __restrict__ Fa,
                                                        const double* __restrict__ Fb, double* __restrict__ V) {
-    const int r = blockIdx.y, c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= R) return;
-    double ga = 0.0, gb = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const size_t o = (size_t)i * R;
-        ga += Fa[o + r] * Fa[o + c];
-        gb += Fb[o + r] * Fb[o + c];
+    __shared__ f64x4 part[4][kWave][2];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, qd = w % 4, half = w / 4;
+    const int r0 = blockIdx.y * 32 + (qd / 2) * 16, c0 = blockIdx.x * 32 + (qd % 2) * 16;
+    const int rr = min(r0 + lane % 16, R - 1), cc = min(c0 + lane % 16, R - 1);
+    f64x4 ga = {0.0, 0.0, 0.0, 0.0}, gb = {0.0, 0.0, 0.0, 0.0};
+    const int steps = (N + 3) / 4;
+#pragma unroll 8
+    for (int st = half; st < steps; st += 2) {
+        const int k = 4 * st + lane / 16;
+        const bool in = k < N;
+        const size_t o = (size_t)(in ? k : 0) * R;
+        const double ar = in ? Fa[o + rr] : 0.0, ac = in ? Fa[o + cc] : 0.0;
+        const double br = in ? Fb[o + rr] : 0.0, bc = in ? Fb[o + cc] : 0.0;
+        ga = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ac, ga, 0, 0, 0);
+        gb = __builtin_amdgcn_mfma_f64_16x16x4f64(br, bc, gb, 0, 0, 0);
     }
-    V[(size_t)r * R + c] = ga * gb;
+    if (half == 1) {
+        part[qd][lane][0] = ga;
+        part[qd][lane][1] = gb;
+    }
+    __syncthreads();
+    if (half == 1) return;
+    ga += part[qd][lane][0];
+    gb += part[qd][lane][1];
+    // accumulator element v of lane l: row l / 16 + 4 v, column l % 16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = r0 + lane / 16 + 4 * v, c = c0 + lane % 16;
+        if (r < R && c < R) V[(size_t)r * R + c] = ga[v] * gb[v];
+    }
 }
 
 void launch_gram_hadamard(int N, int R, const double* Fa, const double* Fb, double* V, hipStream_t s) {
-    hipLaunchKernelGGL(k_gram_hadamard, dim3((R + 255) / 256, R), dim3(256), 0, s, N, R, Fa, Fb, V);
+    const unsigned t = (unsigned)((R + 31) / 32);
+    hipLaunchKernelGGL(k_gram_hadamard, dim3(t, t), dim3(512), 0, s, N, R, Fa, Fb, V);
 }
 
 // ---------------------------------------------------------------- ALS-skew (Sec. 3.3)
