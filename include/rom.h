@@ -300,16 +300,19 @@ rom_status rom_query(rom_ctx ctx, rom_state st, int32_t what, int64_t *value);
  * form for batches).  Applies to later launches.
  *
  * Resident runs: from level 2 on, a one-trajectory CP state (not the full form) takes runs
- * of 16 to 512 steps in one cooperative launch whose blocks, one per compute unit at most,
- * keep their rows of Af, the projection operator and (dense stiffness) Hinv_3 in LDS, and
- * pass the right-hand side and w = lam .* s .* t between them as tagged messages.  They
+ * of 16 to 512 steps in one launch whose blocks, one per compute unit at most, keep their
+ * rows of Af, the projection operator and (dense stiffness) Hinv_3 in LDS, and pass the
+ * right-hand side and w = lam .* s .* t between them as tagged messages.  Every block of a
+ * run must be on the device at once: the library orders the runs of a process across
+ * streams (a run waits for the previous run on another stream), and a device shared with
+ * another kernel that waits for all of its own blocks may delay a run until that kernel
+ * ends.  They
  * apply when 2N <= 4096, Rp (FP64: 2 Rp) <= 4096 and the rows fit the device's LDS; the
  * results equal the per-step kernels' to the bit.  A wait for another block's data that
  * does not end within a bounded number of polling rounds (seconds) makes rom_step_sync
  * return ROM_E_DEVICE.  A run is not captured into graphs (a capturing stream takes the
- * per-step kernels).  When the runtime refuses the cooperative launch (for instance while
- * another process on the GPU holds the device's resource for such launches), the context
- * takes the per-step kernels from then on, with the same results. */
+ * per-step kernels).  When the runtime refuses a run's launch, the context takes the
+ * per-step kernels from then on, with the same results. */
 rom_status rom_set_tile(rom_ctx ctx, int32_t kind, int32_t value);
 int32_t rom_tile_count(int32_t kind);
 

@@ -5,9 +5,10 @@
 // Af for the Hadamard-scatter, the projection rows (the pair form of Sec. 3.3 or
 // [Bf|Cf]^T; with a dense stiffness their products with Hinv_3) and, with a dense
 // stiffness, the rows of Hinv_3.  The per-step kernels stream those rows from memory
-// twice a step.  Here one block per compute unit, all co-resident (cooperative launch),
-// copies its share of the rows into LDS once and then runs a whole sequence of steps on
-// them: a step reads no operator bytes from memory.
+// twice a step.  Here one block per compute unit at most, all on the device at once (an
+// otherwise idle device places every block of such a launch; the host orders the runs of
+// one process across streams), copies its share of the rows into LDS once and then runs a
+// whole sequence of steps on them: a step reads no operator bytes from memory.
 //
 // Between blocks only two vectors move per step: x (the right-hand side, N FP64 values;
 // with a diagonal stiffness u^{n+1}) and w = lam .* s .* t (Rp values).  They travel as
@@ -109,17 +110,26 @@ __device__ bool res_wait(const ResJob& jb, const unsigned long long* src, int ne
 
 // Whole block: copy nrows rows of row_bytes (a multiple of 16) to dst (rows
 // back to back); src(r) is row r's address, or null for a row past the operator (zeros).
+// nrows rows of row_bytes (a multiple of 16) into LDS at dst, a row whose src(r) is null as
+// zeros.  16-byte direct loads from memory into LDS (no registers in between), all of the
+// block's loads in flight at once: a wave's 64 lanes fill 1 KB of consecutive LDS per
+// load.  The caller waits for them (lds_rows_done) before any wave reads the rows.
 template <class SrcF>
 __device__ void lds_rows(char* dst, int nrows, size_t row_bytes, SrcF src) {
-    const int cpr = (int)(row_bytes / 16);
-    staged_copy<16, u32x4>(
-        nrows * cpr,
-        [&](int q) {
-            const int r = q / cpr, c = q - r * cpr;
-            const char* s = src(r);
-            return s ? *reinterpret_cast<const u32x4*>(s + (size_t)c * 16) : u32x4{0u, 0u, 0u, 0u};
-        },
-        [&](int q, u32x4 v) { *reinterpret_cast<u32x4*>(dst + (size_t)q * 16) = v; });
+    const int cpr = (int)(row_bytes / 16), n = nrows * cpr;
+    const int lane = threadIdx.x % kWave;
+    for (int base = (int)(threadIdx.x - lane); base < n; base += (int)blockDim.x) {   // wave-uniform
+        const int q = base + lane, r = q / cpr, c = q - r * cpr;
+        const char* s = q < n ? src(r) : nullptr;
+        if (s) __builtin_amdgcn_global_load_lds(s + (size_t)c * 16, dst + (size_t)base * 16, 16, 0, 0);
+        else if (q < n) *reinterpret_cast<u32x4*>(dst + (size_t)q * 16) = u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
+// The direct loads of lds_rows have landed (this wave's), then every wave's (barrier).
+__device__ __forceinline__ void lds_rows_done() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
 }
 
 // Groups g = b, b + G, ... below n owned by block b.
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(kNT) void k_cp_resident(ResJob jb) {
             });
         }
     }
-    __syncthreads();
+    lds_rows_done();
 
     const unsigned seq0 = *jb.seq;
     const BdfCoef cf = bdf_coef(3);
@@ -504,7 +514,8 @@ __global__ __launch_bounds__(kNT) void k_cp_resident(ResJob jb) {
 // the parity slots the step kernels use, advances the counter and moves the tag base
 // past the run's tags.  256 threads a block.
 __global__ __launch_bounds__(kNT) void k_res_close(StepArgs a0, StepArgs aL, long long n0, int nsteps,
-                                                   const double* __restrict__ epall, int nrg, unsigned* seq) {
+                                                   const double* __restrict__ epall, int nrg, unsigned* seq,
+                                                   int close_last) {
     __shared__ double cred[4];
     const int j = blockIdx.x;
     if (j + 1 < nsteps) {
@@ -532,16 +543,22 @@ __global__ __launch_bounds__(kNT) void k_res_close(StepArgs a0, StepArgs aL, lon
         *aL.step = nl;
         *seq += 2u * (unsigned)nsteps + 2u;
     }
+    if (close_last) {
+        // the run ends a sequence of steps: its last level is closed here, as a closing
+        // kernel would close it
+        __syncthreads();
+        close_level(aL, nl);
+        __syncthreads();
+        if (threadIdx.x == 0) *aL.closep = 0;
+    }
 }
 
 namespace {
 
 template <int DT, bool EVEN>
 hipError_t res_go(const ResJob& jb, int G, size_t lds, hipStream_t s) {
-    ResJob arg = jb;
-    void* args[] = {&arg};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_cp_resident<DT, EVEN>), dim3((unsigned)G),
-                                      dim3(kNT), args, (unsigned)lds, s);
+    hipLaunchKernelGGL((k_cp_resident<DT, EVEN>), dim3((unsigned)G), dim3(kNT), (unsigned)lds, s, jb);
+    return hipGetLastError();
 }
 
 template <int DT, bool EVEN>
@@ -580,8 +597,9 @@ hipError_t res_attr(int dt, int N, size_t cap, size_t lds, int* per_cu) {
 }
 
 void res_close_launch(const StepArgs& a0, const StepArgs& aL, long long n0, int nsteps, const double* epall,
-                      int nrg, unsigned* seq, hipStream_t s) {
-    hipLaunchKernelGGL(k_res_close, dim3((unsigned)nsteps), dim3(kNT), 0, s, a0, aL, n0, nsteps, epall, nrg, seq);
+                      int nrg, unsigned* seq, bool close_last, hipStream_t s) {
+    hipLaunchKernelGGL(k_res_close, dim3((unsigned)nsteps), dim3(kNT), 0, s, a0, aL, n0, nsteps, epall, nrg, seq,
+                       close_last ? 1 : 0);
 }
 
 }  // namespace rom

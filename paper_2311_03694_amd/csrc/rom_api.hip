@@ -111,8 +111,8 @@ struct rom_ctx_s {
     // steps (-1 default = on where the operator fits on chip, 0 off)
     int tile[6] = {-1, -1, -1, -1, -1, -1};
     // resident one-trajectory CP steps: geometry, valid while res_gen == ws_gen
-    // (res_ok 0: not available for this context; res_refused: the runtime refused a
-    // cooperative launch, e.g. while another process holds the device's resource for them)
+    // (res_ok 0: not available for this context; res_refused: the runtime refused a run's
+    // launch)
     int res_gen = -1, res_ok = 0, res_G = 0, res_nrg = 0, res_npg = 0, res_rg = 0, res_pg = 0;
     bool res_refused = false;
     size_t res_lds = 0;
@@ -429,9 +429,20 @@ extern "C" int32_t rom_cp_skew_layout(int32_t N, int32_t R, const double* lambda
 
 static void forget_plans_of(const void* obj);
 
+// The order of resident runs across streams (one record per device).
+constexpr int kResDevices = 16;
+struct ResOrder {
+    std::mutex mu;
+    hipEvent_t ev = nullptr;
+    hipStream_t last = nullptr;     // stream of the latest run
+};
+static ResOrder& res_order(int device);
+static void res_forget_stream(int device, hipStream_t s);
+
 extern "C" void rom_destroy(rom_ctx c) {
     if (!c) return;
     forget_plans_of(c);
+    res_forget_stream(c->device, c->stream);
     if (c->stream) hipStreamSynchronize(c->stream);
     for (void* p : c->allocs) hipFree(p);
     if (c->ws) hipFree(c->ws);
@@ -1665,10 +1676,9 @@ static bool res_plan(rom_ctx c) {
     if (c->dense || c->svd || c->full || c->tile[5] == 0) return false;
     const int wpe = c->dtype == DT_F64 ? 2 : 1;
     if (2 * c->N > kResWaitWords || c->Rp * wpe > kResWaitWords) return false;
-    int ncu = 0, lds_dev = 0, coop = 0;
+    int ncu = 0, lds_dev = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
-        hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess ||
-        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess || !coop) {
+        hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
@@ -1722,10 +1732,28 @@ static rom_status ensure_res(rom_ctx c, rom_state s) {
     return ROM_OK;
 }
 
+// A resident run needs every one of its blocks on the device at once (they wait for each
+// other's messages).  It is an ordinary launch of at most one block per compute unit, which
+// an otherwise idle device places at once; two runs overlapping on two streams could each
+// hold part of the device, so the runs of this process are ordered across streams: a run on
+// another stream than the previous run's first waits for all work enqueued on that stream
+// (an event recorded there when the stream changes; none while runs stay on one stream).
+// Any other wait that does not end within the kernel's polling bound raises its error flag.
+static ResOrder& res_order(int device) {
+    static ResOrder ord[kResDevices];
+    return ord[(unsigned)device % kResDevices];
+}
+
+static void res_forget_stream(int device, hipStream_t s) {
+    ResOrder& ord = res_order(device);
+    std::lock_guard<std::mutex> lk(ord.mu);
+    if (ord.last == s) ord.last = nullptr;
+}
+
 // One resident run of L steps from level n0 >= 2, then its closing block.  Returns
-// *refused = true (and ROM_OK) when the runtime refuses the cooperative launch: nothing was
-// enqueued, and the context takes the per-step kernels from then on.
-static rom_status launch_resident(rom_ctx c, rom_state s, long long n0, int L, bool* refused) {
+// *refused = true (and ROM_OK) when the runtime refuses the launch: nothing was enqueued,
+// and the context takes the per-step kernels from then on.
+static rom_status launch_resident(rom_ctx c, rom_state s, long long n0, int L, bool close_last, bool* refused) {
     *refused = false;
     const SkewPairs sk = skew_of(c);
     ResJob jb{};
@@ -1761,6 +1789,13 @@ static rom_status launch_resident(rom_ctx c, rom_state s, long long n0, int L, b
     jb.seq = s->res_seq;
     jb.err = (int*)(s->a.bad + 1);
     jb.spin_max = kResSpin;
+    ResOrder& ord = res_order(c->device);
+    std::lock_guard<std::mutex> lk(ord.mu);
+    if (ord.last && ord.last != c->stream) {
+        if (!ord.ev) HIPCHK(hipEventCreateWithFlags(&ord.ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ord.ev, ord.last));
+        HIPCHK(hipStreamWaitEvent(c->stream, ord.ev, 0));
+    }
     hipError_t e = res_launch(c->dtype, jb, c->res_G, c->res_lds, c->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -1768,7 +1803,9 @@ static rom_status launch_resident(rom_ctx c, rom_state s, long long n0, int L, b
         *refused = true;
         return ROM_OK;
     }
-    res_close_launch(step_args(s, n0), step_args(s, n0 + L), n0, L, s->res_ep, c->res_nrg, s->res_seq, c->stream);
+    ord.last = c->stream;
+    res_close_launch(step_args(s, n0), step_args(s, n0 + L), n0, L, s->res_ep, c->res_nrg, s->res_seq, close_last,
+                     c->stream);
     HIPCHK(hipGetLastError());
     return ROM_OK;
 }
@@ -1795,14 +1832,13 @@ static rom_status walk_steps(rom_ctx c, rom_state s, long long n0, int64_t nstep
         const int L = (int)std::min<int64_t>(left, kResMax);
         if (launch) {
             bool refused = false;
-            TRYS(launch_resident(c, s, n, L, &refused));
+            TRYS(launch_resident(c, s, n, L, left == L, &refused));   // the last run closes its last level
             if (refused) break;                      // the rest through the graphs
         }
         n += L;
         left -= L;
     }
     if (left > 0) TRYS(walk_graphs(c, s, n, left, launch));
-    else if (launch) launch_close(step_args(s, n), c->stream);
     return ROM_OK;
 }
 

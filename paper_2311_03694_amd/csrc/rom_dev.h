@@ -230,7 +230,8 @@ int launch_cp_scatter1(int dt, const void* Af, const void* Af_lo, int N, int Rp,
                        const StepArgs* sa, int mode, hipStream_t s, const double* G = nullptr);
 
 // CP, one trajectory, resident operator (k_res.hip): from level 2 on, a run of steps in
-// one cooperative launch whose blocks keep their rows of the order-3 operators in LDS.
+// one launch (one block per compute unit at most) whose blocks keep their rows of the
+// order-3 operators in LDS.
 struct ResJob {
     StepArgs a;                    // counter slots of level n0
     long long n0;                  // first level of the run (n0 >= 2)
@@ -289,12 +290,13 @@ __host__ __device__ inline ResLayout res_layout(int dt, int N, int Np, int Rp, i
     return r;
 }
 constexpr int kResWaitWords = 4096;    // message words a block waits for at most (x or w)
-// Cooperative launch of the run (dynamic LDS `lds`, G blocks of 256 threads), then one
-// block that logs the energies of levels n0 .. n0 + nsteps - 1, leaves n0 + nsteps
-// pending as the step kernels do, advances the counter and the tag base.
+// Launch of the run (dynamic LDS `lds`, G blocks of 256 threads, all resident at once),
+// then the closing kernel: it logs the energies of levels n0 .. n0 + nsteps - 1, leaves
+// n0 + nsteps pending as the step kernels do (or, with close_last, the run ending a
+// sequence of steps, closes it too), and advances the counter and the tag base.
 hipError_t res_launch(int dt, const ResJob& jb, int G, size_t lds, hipStream_t s);
 void res_close_launch(const StepArgs& a0, const StepArgs& aL, long long n0, int nsteps, const double* epall,
-                      int nrg, unsigned* seq, hipStream_t s);
+                      int nrg, unsigned* seq, bool close_last, hipStream_t s);
 // Raise the kernel's dynamic LDS limit to `cap` (the same for every context: the
 // attribute belongs to the kernel) and report how many of its blocks with `lds` bytes
 // fit on one compute unit.

@@ -178,3 +178,32 @@ print("child done", flush=True)
     assert int(got["n"]) == nb
     assert np.array_equal(got["u"], ub) and np.array_equal(got["y"], yb)
     assert np.array_equal(got["E"], b.energy()[1])
+
+
+def test_resident_runs_on_two_streams(torch_gpu):
+    """Two contexts on two streams whose resident runs are enqueued interleaved and
+    asynchronously: the library orders the runs across the streams (each run needs the
+    whole device), so both sequences finish and equal the per-step kernels to the bit."""
+    torch = torch_gpu
+    _say("resident runs of two contexts on two streams, interleaved")
+    p = romsynth.make_problem(130, pairs=70, eps=1e-6, nu=1e-3, dt=1e-3, A="spd", cfg=95, dense=False)
+    q = romsynth.make_problem(97, pairs=40, eps=1e-6, nu=1e-3, dt=1e-3, A="diag", cfg=96, dense=False)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    roms = [rg.Rom(x.N, x.nu, x.dt, x.A, lam=x.lam, Af=x.Af, Bf=x.Bf, Cf=x.Cf, dtype="fp32", stream=st)
+            for x, st in zip((p, q), streams)]
+    states = [r.state(x.u0[0]) for r, x in zip(roms, (p, q))]
+    for st in states:
+        assert st.resident_blocks > 0
+        st.step(2)
+    for _ in range(3):
+        for st in states:
+            st.step_async(300)
+    for st in states:
+        st.sync()
+    for x in (p, q):
+        ref = rg.Rom(x.N, x.nu, x.dt, x.A, lam=x.lam, Af=x.Af, Bf=x.Bf, Cf=x.Cf, dtype="fp32")
+        ref.set_tile(RESIDENT, 0)
+        b = ref.state(x.u0[0])
+        b.step(902)
+        a = states[0 if x is p else 1]
+        _same(a, b, f"N={x.N} on its own stream")
