@@ -691,7 +691,7 @@ def main():
         log(f"serving: {nreq} requests, steps 1e3..{smax}")
         reqs = poisson_requests(nreq, rate=1.0, Ns=(100, 200, 400, 700, 1000), dense_frac=0.5,
                                 dtypes=("fp32", "bf16x3"), steps_range=(1000, smax), seeds=(0, 1), rng_seed=7)
-        be = RomBackend(stream=stream, pool_slots=16)
+        be = RomBackend(pool_slots=16)             # each operator's context on a stream of its own
         srv = Server(be, hbm_budget=200 << 30, max_slots=256, chunk=500)
         t1 = time.perf_counter()
         srv.warm(sorted({op_key(r) for r in reqs}))

@@ -13,9 +13,14 @@ contraction format.  The loop
     BDF2) alone on a one-trajectory state of its operator, then its history is written
     into a free slot of a pool that is past its own start-up (rom_state_set_slot) and it
     continues with BDF3 there, at the pool's level;
-  * advances every pool with an occupied slot by one chunk of steps with a single
-    rom_step_multi call (continuous batching: requests join and leave at chunk
-    boundaries while others keep running);
+  * advances the pools with an occupied slot in rounds (continuous batching: requests
+    join and leave at round boundaries while others keep running).  With a backend that
+    steps pools concurrently (RomBackend: each operator's context on a stream of its own,
+    every pool's steps enqueued asynchronously, then all of them awaited), each pool takes
+    its own number of steps in a round, more for a pool whose step is cheaper (up to
+    `max_ratio` chunks, by the backend's step-time estimate), so that the pools of small
+    operators are not held to the pace of the largest one; otherwise every pool takes one
+    chunk in a single rom_step_multi call;
   * retires finished requests (their slot's coefficients and energy), and failed ones: a
     non-finite trajectory ends its own request with an error and its slot is cleared;
     the other requests continue.  A request whose operator and pool cannot fit the budget
@@ -181,6 +186,29 @@ class RomBackend:
             return False
         return True
 
+    def step_pools(self, items) -> List[object]:
+        """Advance each pool by its own number of steps, all enqueued before any is awaited
+        (pools of different operators run on their contexts' streams side by side); the
+        pools in which a trajectory became non-finite."""
+        for pool, n in items:
+            pool.step_async(n)
+        bad = []
+        for pool, _ in items:
+            try:
+                pool.sync()
+            except self.rg.NonFinite:
+                bad.append(pool)
+        return bad
+
+    def estimate_step_seconds(self, key) -> float:
+        """Time of one step of a pool of `key`: the operator bytes a step streams (the dense
+        tensor once for all slots, or the CP factors and projection operators, and the FP64
+        Helmholtz inverse) at 5 TB/s, plus 20 us of latency."""
+        N, _seed, kind, dtype = key
+        eb = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x3": 4}[dtype]
+        nbytes = N ** 3 * eb if kind == "dense" else 3 * N * (2 * N) * eb
+        return 2e-5 + (nbytes + 8 * N * N) / 5e12
+
     def slot_finite(self, pool) -> np.ndarray:
         E, _ = pool.energy(log=False)
         return np.isfinite(E)
@@ -206,8 +234,9 @@ class Server:
 
     def __init__(self, backend, hbm_budget: int, max_slots: int = 256, chunk: int = 256,
                  pool_slots: Optional[int] = None, clock: Optional[Callable[[], float]] = None,
-                 sleep: Optional[Callable[[float], None]] = None):
+                 sleep: Optional[Callable[[float], None]] = None, max_ratio: int = 32):
         self.be = backend
+        self.max_ratio = int(max_ratio)
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.chunk = int(chunk)
@@ -261,6 +290,20 @@ class Server:
         self.used += nbytes
         self.peak_used = max(self.peak_used, self.used)
         return True
+
+    def _round(self, stepped) -> Dict[int, int]:
+        """Steps of each pool in this round: the pool with the costliest step takes at most
+        one chunk, a pool whose step is k times cheaper up to k chunks (at most max_ratio),
+        and no pool more than its occupants' fewest remaining steps."""
+        est = getattr(self.be, "estimate_step_seconds", None)
+        cost = {id(p): (est(key) if est else 1.0) for key, p in stepped}
+        worst = max(cost.values())
+        out = {}
+        for key, p in stepped:
+            ratio = max(1, min(self.max_ratio, int(worst / cost[id(p)])))
+            left = min(a[0].nsteps - a[4] for a in p.occupant.values())
+            out[id(p)] = min(self.chunk * ratio, left)
+        return out
 
     def warm(self, keys):
         """Create the operators of `keys` ahead of the run (those that fit the budget)."""
@@ -353,14 +396,19 @@ class Server:
                     if waiting:
                         raise RuntimeError("a waiting request can never be admitted")
                     break
-                n = min(self.chunk, min(a[0].nsteps - a[4] for a in active))
                 self.batches.append(len(active))
-                stepped = []
-                for plist in self.pools.values():
-                    stepped += [p for p in plist if p.occupant]
-                failed = not self.be.step([p.handle for p in stepped], n)
+                keyed = [(key, p) for key, plist in self.pools.items() for p in plist if p.occupant]
+                stepped = [p for _, p in keyed]
+                step_pools = getattr(self.be, "step_pools", None)
+                if step_pools is not None:
+                    counts = self._round(keyed)
+                    failed = bool(step_pools([(p.handle, counts[id(p)]) for p in stepped]))
+                else:
+                    n = min(self.chunk, min(a[0].nsteps - a[4] for a in active))
+                    counts = {id(p): n for p in stepped}
+                    failed = not self.be.step([p.handle for p in stepped], n)
                 for a in active:
-                    a[4] += n
+                    a[4] += counts[id(a[2])]
                 retire = []
                 if failed:
                     # end the requests whose trajectories became non-finite, clear their slots
