@@ -9,6 +9,17 @@ namespace rom {
 void launch_als_unfold(int N, int np, int layout, const double* C, double* U, hipStream_t s);
 // Ft [R][np] = F^T for F [N][R], zero padding.
 void launch_als_transpose(int N, int R, int np, const double* F, double* Ft, hipStream_t s);
+// T [Bn][R] = U Ft^T in FP64 for U [Bn][np] and Ft [R][np] (np a multiple of 8, Ft with at
+// least 8 readable elements past its end): the plan stages 32 (else 16) rows of U per block
+// in at most lds_cap bytes of LDS; ok is false when neither fits or the allowance is refused.
+struct AlsProductPlan {
+    int kc, kcp, nbt;
+    size_t lds;
+    bool ok;
+};
+AlsProductPlan als_product_plan(int np, int lds_cap);
+void launch_als_product(const AlsProductPlan& pl, int R, int np, long long Bn, const double* U, const double* Ft,
+                        double* T, hipStream_t s);
 // M[p][r] (pitch ldm) = sum_q T[row][r] F[q][r] with row = p N + q (keep_first) or q N + p.
 void launch_als_reduce(int N, int R, int keep_first, const double* T, const double* F, double* M, int ldm,
                        hipStream_t s);

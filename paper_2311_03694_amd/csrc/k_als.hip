@@ -4,6 +4,8 @@
 // reduction with the other) and their normal matrices (elementwise products of factor
 // Grams).  The normal equations are solved by the SPD inverse of k_bdf.hip and an FP64
 // MFMA product (k_gemm.hip).
+#include <algorithm>
+
 #include "als.h"
 #include "kcommon.h"
 
@@ -46,6 +48,153 @@ __global__ __launch_bounds__(256) void k_als_transpose(int N, int R, int np, con
 void launch_als_transpose(int N, int R, int np, const double* F, double* Ft, hipStream_t s) {
     const long long total = (long long)R * np;
     hipLaunchKernelGGL(k_als_transpose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, N, R, np, F, Ft);
+}
+
+// T[b][m] = sum_k U[b][k] Ft[m][k] in FP64: the unfolding times one factor, T [Bn][R].
+// A block stages 16 NBT rows of U [Bn][np] in LDS (zeros past np, up to kc = np rounded up
+// to 16, and past Bn; an odd number of 16-byte units per row, so the fragment reads meet
+// no bank conflicts) and forms those rows of T for every m: its four wavefronts take the
+// 16 x 16 tiles (b-tile t % NBT, m-tile t / NBT) for t = w, w + 4, ..., up to four at a
+// time.  A wavefront's U fragment of a step is shared by its tiles; the factor fragments
+// stream from global memory (the factor stays in L2) two steps ahead.  Lane l feeds row
+// l % 16 and the k group l / 16 of a 16-k step, two consecutive k per half-step in both
+// operands; accumulator element v of lane l is row b = l / 16 + 4 v and column
+// m = l % 16.  Rows of Ft past R are clamped for the loads and not stored; k in
+// [np, kc) meets the LDS zeros (the factor rows are finite and the last one has
+// zeroed slack past its end).
+template <int G>
+__device__ __forceinline__ void als_product_round(const double* xs, int kcp, int nsteps, const double* __restrict__ Ft,
+                                                  int np, int R, int mt0, int dm, int bt, long long b0, long long Bn,
+                                                  double* __restrict__ T) {
+    const int lane = threadIdx.x % kWave, g = lane >> 4, c16 = lane & 15;
+    size_t off[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const int m = min((mt0 + i * dm) * 16 + c16, R - 1);
+        off[i] = (size_t)m * np + 4 * g;
+    }
+    const double* xrow = xs + (size_t)(bt * 16 + c16) * kcp + 4 * g;
+    f64x4 acc[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // two-step ring of factor fragments; loads past the last step reload it
+    double2 ring[2][G][2];
+    auto issue = [&](int slot, int st) {
+        st = min(st, nsteps - 1);
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) ring[slot][i][h] = *reinterpret_cast<const double2*>(Ft + off[i] + 16 * st + 2 * h);
+    };
+    auto consume = [&](int slot, int st) {
+        double2 a[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) a[h] = *reinterpret_cast<const double2*>(xrow + 16 * st + 2 * h);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h].x, ring[slot][i][h].x, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h].y, ring[slot][i][h].y, acc[i], 0, 0, 0);
+            }
+    };
+    issue(0, 0);
+    issue(1, 1);
+    int st = 0;
+    for (; st + 2 <= nsteps; st += 2) {
+        consume(0, st);
+        issue(0, st + 2);
+        consume(1, st + 1);
+        issue(1, st + 3);
+    }
+    if (st < nsteps) consume(0, st);
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const int m = (mt0 + i * dm) * 16 + c16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const long long b = b0 + bt * 16 + g + 4 * v;
+            if (b < Bn && m < R) T[b * R + m] = acc[i][v];
+        }
+    }
+}
+
+template <int NBT>
+__global__ __launch_bounds__(256) void k_als_product(int R, int np, int kc, int kcp, long long Bn,
+                                                     const double* __restrict__ U, const double* __restrict__ Ft,
+                                                     double* __restrict__ T) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    double* xs = reinterpret_cast<double*>(smem);
+    const long long b0 = (long long)blockIdx.x * (16 * NBT);
+    const int vr = kc / 2;      // 16-byte vectors per staged row
+    staged_copy<4, double2>(
+        16 * NBT * vr,
+        [&](int q) {
+            const int r = q / vr, k = (q - r * vr) * 2;
+            double2 v = {0.0, 0.0};
+            if (b0 + r < Bn && k < np) v = *reinterpret_cast<const double2*>(U + (size_t)(b0 + r) * np + k);
+            return v;
+        },
+        [&](int q, const double2& v) {
+            const int r = q / vr, k = (q - r * vr) * 2;
+            *reinterpret_cast<double2*>(xs + (size_t)r * kcp + k) = v;
+        });
+    __syncthreads();
+    const int w = threadIdx.x / kWave, nmt = (R + 15) / 16, bt = w % NBT, dm = 4 / NBT;
+    const int nsteps = kc / 16;
+    int mt0 = w / NBT;
+    int left = mt0 < nmt ? (nmt - mt0 + dm - 1) / dm : 0;
+    // rounds of at most four tiles, as even as possible (13 tiles as 4, 3, 3, 3), so no
+    // round is left with a single accumulator chain
+    for (int rounds = (left + 3) / 4; rounds > 0; --rounds) {
+        const int gsz = (left + rounds - 1) / rounds;
+        if (gsz == 4) als_product_round<4>(xs, kcp, nsteps, Ft, np, R, mt0, dm, bt, b0, Bn, T);
+        else if (gsz == 3) als_product_round<3>(xs, kcp, nsteps, Ft, np, R, mt0, dm, bt, b0, Bn, T);
+        else if (gsz == 2) als_product_round<2>(xs, kcp, nsteps, Ft, np, R, mt0, dm, bt, b0, Bn, T);
+        else als_product_round<1>(xs, kcp, nsteps, Ft, np, R, mt0, dm, bt, b0, Bn, T);
+        left -= gsz;
+        mt0 += gsz * dm;
+    }
+}
+
+// Each block reserves at least kProductLdsFloor bytes of LDS: two blocks then fill at most
+// 128 KB of a compute unit's 160 KB, which leaves room for a block of the SPD inverse
+// (k_gj_step, 35 KB) that runs beside the product on a side stream; at three blocks per
+// compute unit the inverse's panels wait for product blocks to retire (measured at
+// N = 200, R = 400: 4-7% slower sweeps, and the product itself no faster).
+constexpr size_t kProductLdsFloor = 57344;
+
+AlsProductPlan als_product_plan(int np, int lds_cap) {
+    AlsProductPlan pl{};
+    pl.kc = (np + 15) / 16 * 16;
+    int units = pl.kc / 2;                  // 16-byte units of a staged row
+    if (units % 2 == 0) units += 1;
+    pl.kcp = units * 2;
+    for (int nbt = 2; nbt >= 1; --nbt) {
+        const size_t lds = (size_t)nbt * 16 * pl.kcp * sizeof(double);
+        if (lds <= (size_t)lds_cap) {
+            pl.nbt = nbt;
+            pl.lds = std::max(lds, std::min(kProductLdsFloor, (size_t)lds_cap));
+            break;
+        }
+    }
+    if (pl.nbt == 2)
+        pl.ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_als_product<2>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds) == hipSuccess;
+    else if (pl.nbt == 1)
+        pl.ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_als_product<1>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds) == hipSuccess;
+    if (!pl.ok) (void)hipGetLastError();    // a refused allowance is not the caller's error
+    return pl;
+}
+
+void launch_als_product(const AlsProductPlan& pl, int R, int np, long long Bn, const double* U, const double* Ft,
+                        double* T, hipStream_t s) {
+    const unsigned blocks = (unsigned)((Bn + 16 * pl.nbt - 1) / (16 * pl.nbt));
+    if (pl.nbt == 2)
+        hipLaunchKernelGGL(k_als_product<2>, dim3(blocks), dim3(256), pl.lds, s, R, np, pl.kc, pl.kcp, Bn, U, Ft, T);
+    else
+        hipLaunchKernelGGL(k_als_product<1>, dim3(blocks), dim3(256), pl.lds, s, R, np, pl.kc, pl.kcp, Bn, U, Ft, T);
 }
 
 // M[p][r] (pitch ldm) = sum_q T[row(p, q)][r] F[q][r], row = p N + q (first index

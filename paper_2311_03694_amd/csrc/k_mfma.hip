@@ -426,53 +426,6 @@ void launch_mfma_helm(const MfmaPlan& pl, const double* hinv, int N, int Np, int
     go_tile<DT_F64, MK_F64, false>(a, pl, s);
 }
 
-// The CP-ALS tensor-factor product Y[b][m] = sum_k A[m][k] X[b][k] in FP64, whose column
-// side is long (M = R rows of a transposed factor, Bpad = N^2 rows of an unfolding): the
-// whole contracted range is one k-chunk, so every block writes its tile of Y directly, and
-// each block holds an X tile of up to 64 columns in LDS (up to the device's LDS per block).
-MfmaPlan mfma_wide_plan(int M, int Kp, int Bpad, size_t lds_cap) {
-    MfmaPlan pl{};
-    pl.mw = 32;
-    pl.bt = 64;
-    while (pl.bt > 16 && Bpad % pl.bt != 0) pl.bt /= 2;
-    const int KS = mk_ks(MK_F64);
-    pl.kc = (Kp + KS - 1) / KS * KS;
-    pl.nkc = pl.jc = pl.njr = pl.nsplit = 1;
-    int units = ((pl.kc + KS) * 8 + 15) / 16;
-    if (units % 2 == 0) units += 1;
-    pl.kcp = units * 2;
-    pl.lds = (size_t)pl.bt * pl.kcp * 8;
-    while (pl.bt > 16 && pl.lds > lds_cap) {
-        pl.bt /= 2;
-        pl.lds = (size_t)pl.bt * pl.kcp * 8;
-    }
-    pl.grid_x = (M + 4 * pl.mw - 1) / (4 * pl.mw);
-    pl.grid_y = Bpad / pl.bt;
-    pl.blocks = (pl.grid_x * pl.grid_y + 7) / 8 * 8;
-    if (pl.lds > lds_cap) pl.blocks = 0;      // does not fit: the caller takes another kernel
-    return pl;
-}
-
-template <int BT>
-static bool wide_allow(int lds) {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mfma_rows<DT_F64, MK_F64, 32, BT, false, false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds) == hipSuccess &&
-           hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mfma_rows<DT_F64, MK_F64, 32, BT, false, true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds) == hipSuccess;
-}
-
-bool mfma_wide_ready(const MfmaPlan& pl) {
-    if (pl.blocks == 0) return false;
-    return pl.bt == 64 ? wide_allow<64>((int)pl.lds) : pl.bt == 32 ? wide_allow<32>((int)pl.lds)
-                                                                    : wide_allow<16>((int)pl.lds);
-}
-
-void launch_mfma_wide(const MfmaPlan& pl, const double* A, int M, int Kp, const double* X, int Bpad, double* Y,
-                      hipStream_t s) {
-    const MfmaArgs a = fill_args(pl, A, nullptr, X, nullptr, nullptr, Y, Kp, 0, M, 1, Kp, Bpad, 0);
-    go_tile<DT_F64, MK_F64, false>(a, pl, s);
-}
-
 void launch_hadamard(int dt, const void* P, int nz, int Bpad, int B, int Rp, const void* lam, void* W,
                      hipStream_t s) {
     dim3 grid((Rp + 255) / 256, Bpad);

@@ -790,28 +790,12 @@ static rom_status create_ctx(const rom_desc* d, const SvdDesc* sv, const rom_ful
 }
 
 extern "C" rom_status rom_create(const rom_desc* d, rom_ctx* out) { return create_ctx(d, nullptr, nullptr, out); }
-// The tensor-factor product of the ALS sweeps on the one-pass MFMA kernel when its X tile
-// fits in 64 KB of LDS (two blocks per compute unit, one staging its tile while the other
-// multiplies: 8% less per sweep than one block with a 64-column tile at N = 200, R = 400;
-// the allowance is set here, before any capture), else on the skinny GEMM.  The transposed
-// factor it reads gets kWideSlack zeroed elements past its end.
-constexpr size_t kWideSlack = 16;
-constexpr int kWideLds = 65536;
-struct WideProduct {
-    MfmaPlan pl;
-    bool ok;
-};
-static WideProduct wide_product(int M, int Kp, int Bpad) {
-    int dev = 0, lds = 0;
-    WideProduct w{};
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return w;
-    w.pl = mfma_wide_plan(M, Kp, Bpad, (size_t)std::min(lds, kWideLds));
-    w.ok = mfma_wide_ready(w.pl);
-    if (!w.ok) (void)hipGetLastError();        // a refused allowance is not the call's error
-    return w;
-}
+// The tensor-factor product of the ALS sweeps on its own FP64 MFMA kernel (k_als.hip)
+// when 16 or 32 rows of the unfolding fit in 64 KB of LDS (N up to 496; the allowance is
+// set here, before any capture), else on the skinny GEMM.  The transposed factor it reads
+// gets kProductSlack zeroed elements past its end.
+constexpr size_t kProductSlack = 16;
+constexpr int kProductLds = 65536;
 
 // Streams and graph of an ALS call: the capture stream cs (ordered after the caller's
 // stream), a side stream for the SPD inverses, and one fork / join event pair per update
@@ -875,7 +859,7 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
     // tensor-factor product T [N^2 padded][R]
     constexpr int kBufs = 10;
     const size_t sizes[kBufs] = {r * r, r * r, r * r, r * rp, npad * rp, npad * r, n2pad * np, n2pad * np,
-                                 r * np + kWideSlack, n2pad * r};
+                                 r * np + kProductSlack, n2pad * r};
     double* buf[kBufs] = {};
     int* info = nullptr;
     struct Guard {
@@ -915,11 +899,11 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
     hipGraphExec_t& gexec = ss.gexec;
     double* F[3] = {A1, A2, A3};
     const GemmPlan pl = gemm_plan(R, (int)npad, 0), plt = gemm_plan(R, (int)n2pad, 0);
-    const WideProduct wide = wide_product(R, (int)np, (int)n2pad);
+    const AlsProductPlan prod = als_product_plan((int)np, kProductLds);
     // T[row][m] = sum_c Ft[m][c] U[row][c]: the unfolding times one factor
     auto tensor_times = [&](const double* Uf, const double* Fk) {
         launch_als_transpose(N, R, (int)np, Fk, Ft, s);
-        if (wide.ok) launch_mfma_wide(wide.pl, Ft, R, (int)np, Uf, (int)n2pad, T, s);
+        if (prod.ok) launch_als_product(prod, R, (int)np, (long long)n2pad, Uf, Ft, T, s);
         else launch_gemm_f64(plt, Ft, (long long)np, Uf, (long long)np, T, R, (int)np, (int)n2pad, s);
     };
     s = cs;   // every launch below (tensor_times included) goes to the capture stream
@@ -975,7 +959,7 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
     // a transposed factor Ft [R][Np] and the product T [N^2 padded][R]
     constexpr int kBufs = 17;
     const size_t sizes[kBufs] = {n * r, n * r, n * r, r * r, r * r, r * r, r * rp, npad * rp, npad * r,
-                                 p * p, p * p, p * p, p * pp, npad * pp, npad * p, n2pad * np, r * np + kWideSlack};
+                                 p * p, p * p, p * p, p * pp, npad * pp, npad * p, n2pad * np, r * np + kProductSlack};
     const size_t tsize = n2pad * r;
     double* buf[kBufs + 1] = {};
     int* info = nullptr;
@@ -1014,14 +998,14 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
     hipGraphExec_t& gexec = ss.gexec;
     const GemmPlan plt = gemm_plan(R, (int)n2pad, 0), plr = gemm_plan(R, (int)npad, 0),
                    plp = gemm_plan(P, (int)npad, 0);
-    const WideProduct wide = wide_product(R, (int)np, (int)n2pad);
+    const AlsProductPlan prod = als_product_plan((int)np, kProductLds);
     s = cs;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(ROM_E_DEVICE, "ALS-skew graph capture failed to start");
     // T[(i, j)][m] = sum_k C[i][j][k] A3[k][m]: the unfolding times the third factor
     auto tensor_times_a3 = [&]() {
         launch_als_transpose(N, R, (int)np, A3, Ft, s);
-        if (wide.ok) launch_mfma_wide(wide.pl, Ft, R, (int)np, U0, (int)n2pad, T, s);
+        if (prod.ok) launch_als_product(prod, R, (int)np, (long long)n2pad, U0, Ft, T, s);
         else launch_gemm_f64(plt, Ft, (long long)np, U0, (long long)np, T, R, (int)np, (int)n2pad, s);
     };
     // one sweep: the tied second factor (least squares with A2 = B1 [I I]), then the

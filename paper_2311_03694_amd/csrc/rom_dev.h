@@ -211,14 +211,6 @@ struct MfmaPlan {
     int grid_x, grid_y, blocks;
 };
 
-// FP64 product with a long column side in one pass (the CP-ALS tensor-factor product):
-// Y[b][m] = sum_k A[m][k] X[b][k], A [M][Kp] (readable 16 elements past its end), X
-// [Bpad][Kp], Y [Bpad][M].  blocks == 0 in the plan: the X tile does not fit lds_cap.
-MfmaPlan mfma_wide_plan(int M, int Kp, int Bpad, size_t lds_cap);
-bool mfma_wide_ready(const MfmaPlan& pl);      // allows the plan's LDS (before capture)
-void launch_mfma_wide(const MfmaPlan& pl, const double* A, int M, int Kp, const double* X, int Bpad, double* Y,
-                      hipStream_t s);
-
 // CP, one trajectory.
 // st [2Rp]: s then t; factors padded to Np / Rp with zeros.
 struct SkewPairs { int layout, P, R; };   // layout 0: general factors
