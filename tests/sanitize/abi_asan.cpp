@@ -306,5 +306,6 @@ int main() {
         return 1;
     }
     std::printf("abi sanitizer run: all checks hold\n");
+    std::fflush(stdout);     // before the runtimes' own teardown at exit
     return 0;
 }
