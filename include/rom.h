@@ -232,7 +232,9 @@ rom_status rom_step_prepare(rom_ctx ctx, rom_state st, int64_t nsteps);
 rom_status rom_step_async(rom_ctx ctx, rom_state st, int64_t nsteps);
 rom_status rom_step_sync(rom_ctx ctx, rom_state st, int64_t *first_bad_step);
 
-/* Energies (eq. ene_fluc, first quantity, with identity mass matrix).  Synchronizes.
+/* Energies (eq. ene_fluc, first quantity, with identity mass matrix): 1/2 |u|^2 per level,
+ * also for a full-form state, whose mass matrix M the log does not weight (it is the
+ * quantity the non-finite check and the oracle's log use).  Synchronizes.
  * E_host [batch] (nullable): energy of the current level of each trajectory.
  * Elog_host (nullable): [steps+1][batch], level 0..steps of the state's step counter. */
 rom_status rom_energy(rom_ctx ctx, rom_state st, double *E_host, double *Elog_host);
