@@ -44,8 +44,10 @@ def _gpu_als(torch, X, F0, sweeps):
 
 
 # N = 33, 17, 50: the product's last block of unfolding rows is half empty; R = 260: the
-# last 16-column tile of T is ragged; N = 250: the product stages 16 rows per block
-@pytest.mark.parametrize("N,R,sweeps", [(7, 3, 1), (23, 5, 1), (23, 5, 6), (40, 19, 3), (33, 260, 1), (250, 6, 1)])
+# last 16-column tile of T is ragged; N = 250: the product stages 16 rows per block;
+# N = 500: 16 rows no longer fit its LDS, and the product runs on the skinny GEMM
+@pytest.mark.parametrize("N,R,sweeps", [(7, 3, 1), (23, 5, 1), (23, 5, 6), (40, 19, 3), (33, 260, 1), (250, 6, 1),
+                                        (500, 3, 1)])
 def test_als_matches_oracle(torch_gpu, N, R, sweeps):
     _say(f"cp-als N={N} R={R} sweeps={sweeps}")
     X, F0 = _problem(N, R, 10 + N + R)
