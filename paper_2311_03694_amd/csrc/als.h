@@ -26,7 +26,8 @@ void launch_als_reduce(int N, int R, int keep_first, const double* T, const doub
 // V[r][s] = (Fa^T Fa)[r][s] * (Fb^T Fb)[r][s], [R][R], factors [N][R].
 void launch_gram_hadamard(int N, int R, const double* Fa, const double* Fb, double* V, hipStream_t s);
 // ALS-skew (Sec. 3.3): A1 = [A11 A12], A2 = [B1 B1], A3 = [A12 -A11] ([N][2P]) from the
-// blocks [N][P]; the tied normal equations Vt = S^T V S [P][P], Mt = M S (S = [I; I]); B1
+// blocks [N][P]; the tied normal equations Vt = S^T V S [P][P], Mt = M S (S = [I; I]; a
+// NULL V or M skips that part); B1
 // and A2 from the tied solve Y; the momentum update of A1 from the subiteration's solution
 // Y, with the blocks and A3 tied again.
 void launch_skew_assemble(int N, int P, const double* A11, const double* A12, const double* B1, double* A1,

@@ -302,18 +302,19 @@ void launch_skew_assemble(int N, int P, const double* A11, const double* A12, co
 }
 
 // The normal equations of the tied second factor A2 = B1 S, S = [I; I]:
-// Vt = S^T V S [P][P] from V [R][R], and Mt = M S [npad][ldt] from M [N][ldm].
+// Vt = S^T V S [P][P] from V [R][R], and Mt = M S [npad][ldt] from M [N][ldm]; a NULL V
+// or M skips its part (the inverse of Vt can then start before M exists).
 __global__ void k_skew_tie(int N, int P, const double* __restrict__ V, double* __restrict__ Vt,
                            const double* __restrict__ M, int ldm, double* __restrict__ Mt, int ldt) {
     const int row = blockIdx.y, p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const int R = 2 * P;
-    if (row < P) {
+    if (row < P && V) {
         const double* v0 = V + (size_t)row * R;
         const double* v1 = V + (size_t)(P + row) * R;
         Vt[(size_t)row * P + p] = (v0[p] + v0[P + p]) + (v1[p] + v1[P + p]);
     }
-    if (row < N) Mt[(size_t)row * ldt + p] = M[(size_t)row * ldm + p] + M[(size_t)row * ldm + P + p];
+    if (row < N && M) Mt[(size_t)row * ldt + p] = M[(size_t)row * ldm + p] + M[(size_t)row * ldm + P + p];
 }
 
 void launch_skew_tie(int N, int P, const double* V, double* Vt, const double* M, int ldm, double* Mt, int ldt,

@@ -798,12 +798,13 @@ constexpr size_t kProductSlack = 16;
 constexpr int kProductLds = 65536;
 
 // Streams and graph of an ALS call: the capture stream cs (ordered after the caller's
-// stream), a side stream for the SPD inverses, and one fork / join event pair per update
-// of a sweep.  fork(q) makes the side stream wait for cs; join_mark(q) records the side
+// stream), a side stream for the SPD inverses, and one fork / join event pair per inverse
+// of a sweep (kPairs - 1 for ALS-skew's subiterations, taken in turn, and the last for
+// its tied system).  fork(q) makes the side stream wait for cs; join_mark(q) records the side
 // stream's work; join(q) makes cs wait for it.  The side stream joins the capture through
 // the fork and leaves it through the join, so the graph holds the inverse as a branch.
 struct SweepStreams {
-    static constexpr int kPairs = 8;
+    static constexpr int kPairs = 9;
     hipStream_t cs = nullptr, side = nullptr;
     hipEvent_t start = nullptr, evf[kPairs] = {}, evj[kPairs] = {};
     hipGraph_t graph = nullptr;
@@ -1011,18 +1012,24 @@ extern "C" rom_status rom_cp_als_skew(int32_t N, int32_t P, const double* C, dou
     // one sweep: the tied second factor (least squares with A2 = B1 [I I]), then the
     // subiterations of the first factor with A3 fixed, each followed by the momentum
     // update and A3 = [A12 -A11]
+    bool cap_ok = true;
     launch_gram_hadamard(N, R, A1, A3, V, s);
+    // the tied system's inverse on the side stream, beside the product and the reduction
+    const int qt = SweepStreams::kPairs - 1;
+    launch_skew_tie(N, P, V, Vt, nullptr, (int)rp, Mt, (int)pp, s);   // Vt
+    cap_ok = ss.fork(qt) && cap_ok;
+    spd_inverse_gj(P, (int)pp, Vt, Lt, Xt, Vtinv, info, ss.side);
+    cap_ok = ss.join_mark(qt) && cap_ok;
     tensor_times_a3();
     launch_als_reduce(N, R, 0, T, A1, Mb, (int)rp, s);                 // sum_i T[(i, j)] A1[i]
-    launch_skew_tie(N, P, V, Vt, Mb, (int)rp, Mt, (int)pp, s);
-    spd_inverse_gj(P, (int)pp, Vt, Lt, Xt, Vtinv, info, s);
+    launch_skew_tie(N, P, nullptr, Vt, Mb, (int)rp, Mt, (int)pp, s);  // Mt
+    cap_ok = ss.join(qt) && cap_ok;
     launch_gemm_f64(plp, Vtinv, (long long)pp, Mt, (long long)pp, Yt, P, (int)pp, (int)npad, s);
     launch_skew_set_b(N, P, Yt, P, B1, A2, s);
-    bool cap_ok = true;
     for (int it = 0; it < subiters; ++it) {
         launch_gram_hadamard(N, R, A2, A3, V, s);
         // the inverse on the side stream, beside the right-hand side
-        const int q = it % SweepStreams::kPairs;
+        const int q = it % (SweepStreams::kPairs - 1);
         cap_ok = ss.fork(q) && cap_ok;
         spd_inverse_gj(R, (int)rp, V, L, X, Vinv, info, ss.side);
         cap_ok = ss.join_mark(q) && cap_ok;
