@@ -45,7 +45,7 @@ Also in the one JSON line:
   rel_err       every section: sampled GPU trajectories against the FP64 oracle of the
                 same operator (the oracle leg runs after all GPU timing)
   cpu_baseline  the FP64 oracle (plain C) on a bounded sample of steps, on all host cores
-                of the GPU machine's share (results identical to one thread) and on one
+                of one GPU's host share (results identical to one thread) and on one
 """
 from __future__ import annotations
 
@@ -208,7 +208,7 @@ def run_checks(checks, orc, log):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+        print(f"bench.py measures one GPU only: this library has no multi-GPU path "
               f"(requested --gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
@@ -736,7 +736,7 @@ def main():
         srv.close()
 
     # ---------------- oracle leg (after all GPU timing): accuracy of every section, and the
-    # CPU baseline (the FP64 oracle on the host cores of the GPU machine's share, and on one)
+    # CPU baseline (the FP64 oracle on the host cores of one GPU's share, and on one)
     if not args.no_cpu:
         import oracle as orc
         if sec in ("all", "headline"):

@@ -42,7 +42,7 @@ typedef enum {
     ROM_E_NOMEM = 2,       /* device or host allocation failed                           */
     ROM_E_DEVICE = 3,      /* a HIP runtime call failed                                  */
     ROM_E_NONFINITE = 4,   /* a trajectory produced Inf/NaN (Sec. 4.3's unstable ROMs)   */
-    ROM_E_UNSUPPORTED = 5  /* valid request this build does not implement                */
+    ROM_E_UNSUPPORTED = 5  /* valid request this library does not implement              */
 } rom_status;
 
 /* Arithmetic of the advection contraction.  The state update, the Helmholtz solve and
