@@ -227,22 +227,25 @@ void launch_als_reduce(int N, int R, int keep_first, const double* T, const doub
     hipLaunchKernelGGL(k_als_reduce, dim3((R + 255) / 256, N), dim3(256), 0, s, N, R, keep_first, T, F, M, ldm);
 }
 
-// V = (Fa^T Fa) .* (Fb^T Fb) [R][R] on FP64 MFMA: a block per 32 x 32 tile of V, eight
+// V = (Fa^T Fa) .* (Fb^T Fb) [R][R] on FP64 MFMA: a block per 32 x 32 tile of V, sixteen
 // waves: wave w forms quarter w % 4 (rows r0, columns c0) over the factor rows of issues
-// s = w / 4, w / 4 + 2, ... (two halves of the contracted range, added in LDS).  Lane l
-// feeds row / column l % 16 and factor row k = 4 s + l / 16 of issue s, its operands read
-// straight from the factors (16 consecutive values of one factor row per 16 lanes); rows
-// past N give zeros and columns past R are clamped for the loads and not stored.
-__global__ __launch_bounds__(512) void k_gram_hadamard(int N, int R, const double* __restrict__ Fa,
-                                                       const double* __restrict__ Fb, double* __restrict__ V) {
-    __shared__ f64x4 part[4][kWave][2];
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, qd = w % 4, half = w / 4;
+// s = w / 4, w / 4 + 4, ... (four parts of the contracted range, added in LDS in a fixed
+// order).  Lane l feeds row / column l % 16 and factor row k = 4 s + l / 16 of issue s, its
+// operands read straight from the factors (16 consecutive values of one factor row per 16
+// lanes); rows past N give zeros and columns past R are clamped for the loads and not
+// stored.
+constexpr int kGramParts = 4;
+__global__ __launch_bounds__(256 * kGramParts) void k_gram_hadamard(int N, int R, const double* __restrict__ Fa,
+                                                                   const double* __restrict__ Fb,
+                                                                   double* __restrict__ V) {
+    __shared__ f64x4 part[kGramParts - 1][4][kWave][2];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave, qd = w % 4, kp = w / 4;
     const int r0 = blockIdx.y * 32 + (qd / 2) * 16, c0 = blockIdx.x * 32 + (qd % 2) * 16;
     const int rr = min(r0 + lane % 16, R - 1), cc = min(c0 + lane % 16, R - 1);
     f64x4 ga = {0.0, 0.0, 0.0, 0.0}, gb = {0.0, 0.0, 0.0, 0.0};
     const int steps = (N + 3) / 4;
-#pragma unroll 8
-    for (int st = half; st < steps; st += 2) {
+#pragma unroll 4
+    for (int st = kp; st < steps; st += kGramParts) {
         const int k = 4 * st + lane / 16;
         const bool in = k < N;
         const size_t o = (size_t)(in ? k : 0) * R;
@@ -251,14 +254,17 @@ __global__ __launch_bounds__(512) void k_gram_hadamard(int N, int R, const doubl
         ga = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ac, ga, 0, 0, 0);
         gb = __builtin_amdgcn_mfma_f64_16x16x4f64(br, bc, gb, 0, 0, 0);
     }
-    if (half == 1) {
-        part[qd][lane][0] = ga;
-        part[qd][lane][1] = gb;
+    if (kp > 0) {
+        part[kp - 1][qd][lane][0] = ga;
+        part[kp - 1][qd][lane][1] = gb;
     }
     __syncthreads();
-    if (half == 1) return;
-    ga += part[qd][lane][0];
-    gb += part[qd][lane][1];
+    if (kp > 0) return;
+#pragma unroll
+    for (int q = 0; q < kGramParts - 1; ++q) {
+        ga += part[q][qd][lane][0];
+        gb += part[q][qd][lane][1];
+    }
     // accumulator element v of lane l: row l / 16 + 4 v, column l % 16
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(512) void k_gram_hadamard(int N, int R, const doubl
 
 void launch_gram_hadamard(int N, int R, const double* Fa, const double* Fb, double* V, hipStream_t s) {
     const unsigned t = (unsigned)((R + 31) / 32);
-    hipLaunchKernelGGL(k_gram_hadamard, dim3(t, t), dim3(512), 0, s, N, R, Fa, Fb, V);
+    hipLaunchKernelGGL(k_gram_hadamard, dim3(t, t), dim3(256 * kGramParts), 0, s, N, R, Fa, Fb, V);
 }
 
 // ---------------------------------------------------------------- ALS-skew (Sec. 3.3)
