@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "rom_dev.h"
+
 namespace rom {
 
 // Unfolding of C [N][N][N] into U [N^2][np] (zero padding past column N): layout 0 rows
@@ -37,6 +39,10 @@ void launch_skew_tie(int N, int P, const double* V, double* Vt, const double* M,
 void launch_skew_set_b(int N, int P, const double* Y, int ldy, double* B1, double* A2, hipStream_t s);
 void launch_skew_momentum(int N, int P, double mom, const double* Y, int ldy, double* A1, double* A3, double* A11,
                           double* A12, hipStream_t s);
+// launch_gemm_f64 (Y[b][m] = sum_k A[m][k] X[b][k]) storing only the first `rows` of the
+// Bpad rows b of Y, so that Y can be an unpadded [rows][M] array (the ALS factor updates).
+void launch_gemm_f64_rows(const GemmPlan& pl, const double* A, long long lda, const double* X, long long ldx,
+                          double* Y, int M, int K, int Bpad, int rows, hipStream_t s);
 // Hinv [n][np] = H^{-1} for SPD H [n][n] by blocked Gauss-Jordan sweeps, one kernel per
 // 32-column panel, with L and X as the two buffers the panels alternate between (each
 // n x n); columns past n of Hinv are left as they are.  *info becomes 1 if a pivot is not

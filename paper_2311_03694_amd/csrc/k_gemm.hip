@@ -30,6 +30,7 @@
 //    takes 16 pairs, each lane three rows (beta, alpha, gamma of its pair), and writes
 //    W[b][c0] = lam beta gamma and W[b][c1] = -lam beta alpha; pairs past P write the
 //    zero padding of W.
+#include "als.h"
 #include "kmfma.h"
 #include "kstep.h"
 
@@ -45,6 +46,7 @@ struct GemmArgs {
     long long lda, ldx;
     int gx, gy;                    // row tiles, column tiles
     int ksplit;                    // PLAIN: K ranges, one partial product each (Y + split * M * Bpad)
+    int bstore;                    // PLAIN, PAIR: columns b of Y stored (0: all Bpad)
     const long long* kstep;        // non-null: A += (BDF order at *kstep - 1) * a_kstride
     long long a_kstride;
     long long pair_off;            // PAIR: elements from a row of A to its partner row
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
                 }
             }
         } else if constexpr (EPI <= EPI_PAIR) {
-            if (row < p.M && b < p.Bpad) {
+            if (row < p.M && b < (p.bstore > 0 ? p.bstore : p.Bpad)) {
                 if constexpr (PAIR) out[(size_t)b * p.M + row] = reinterpret_cast<const Acc*>(p.lam)[row] * sum[0] * sum[1];
                 else out[(size_t)b * p.M + row] = sum[0];
             }
@@ -453,6 +455,13 @@ void launch_gemm_scatter_step(int dt, const GemmPlan& pl0, const void* Af, const
 void launch_gemm_f64(const GemmPlan& pl, const double* A, long long lda, const double* X, long long ldx, double* Y,
                      int M, int K, int Bpad, hipStream_t s) {
     const GemmArgs a = gemm_args(pl, A, nullptr, lda, X, nullptr, ldx, Y, M, K, Bpad);
+    gemm_go<DT_F64, MK_F64>(a, pl, s);
+}
+
+void launch_gemm_f64_rows(const GemmPlan& pl, const double* A, long long lda, const double* X, long long ldx,
+                          double* Y, int M, int K, int Bpad, int rows, hipStream_t s) {
+    GemmArgs a = gemm_args(pl, A, nullptr, lda, X, nullptr, ldx, Y, M, K, Bpad);
+    a.bstore = rows;
     gemm_go<DT_F64, MK_F64>(a, pl, s);
 }
 

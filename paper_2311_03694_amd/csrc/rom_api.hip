@@ -855,11 +855,11 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
     const size_t n = (size_t)N, r = (size_t)R, rp = (r + 7) / 8 * 8, npad = (n + 15) / 16 * 16;
     const size_t np = (n + 7) / 8 * 8, n2pad = (n * n + 15) / 16 * 16;
     // V and the two panel buffers of its inverse [R][R]; Vinv [R][Rp] and the right-hand
-    // side Mb [Npad][Rp] with zero padding (the product's K = Rp); the product Yb [Npad][R];
-    // the two unfoldings of C [N^2 padded][Np], a transposed factor [R][Np] and the
-    // tensor-factor product T [N^2 padded][R]
-    constexpr int kBufs = 10;
-    const size_t sizes[kBufs] = {r * r, r * r, r * r, r * rp, npad * rp, npad * r, n2pad * np, n2pad * np,
+    // side Mb [Npad][Rp] with zero padding (the product's K = Rp; the product M V^-1 is
+    // written straight into the factor's N rows); the two unfoldings of C [N^2 padded][Np],
+    // a transposed factor [R][Np] and the tensor-factor product T [N^2 padded][R]
+    constexpr int kBufs = 9;
+    const size_t sizes[kBufs] = {r * r, r * r, r * r, r * rp, npad * rp, n2pad * np, n2pad * np,
                                  r * np + kProductSlack, n2pad * r};
     double* buf[kBufs] = {};
     int* info = nullptr;
@@ -878,13 +878,13 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
                                          hipGetErrorString(e));
     }
     if (hipMalloc((void**)&info, sizeof(int)) != hipSuccess) return fail(ROM_E_NOMEM, "CP-ALS workspace");
-    double *V = buf[0], *L = buf[1], *X = buf[2], *Vinv = buf[3], *Mb = buf[4], *Yb = buf[5];
-    double *U0 = buf[6], *U1 = buf[7], *Ft = buf[8], *T = buf[9];
+    double *V = buf[0], *L = buf[1], *X = buf[2], *Vinv = buf[3], *Mb = buf[4];
+    double *U0 = buf[5], *U1 = buf[6], *Ft = buf[7], *T = buf[8];
     if (hipMemsetAsync(Vinv, 0, sizeof(double) * sizes[3], s) != hipSuccess ||
         hipMemsetAsync(Mb, 0, sizeof(double) * sizes[4], s) != hipSuccess ||
-        hipMemsetAsync(U0, 0, sizeof(double) * sizes[6], s) != hipSuccess ||
-        hipMemsetAsync(U1, 0, sizeof(double) * sizes[7], s) != hipSuccess ||
-        hipMemsetAsync(Ft, 0, sizeof(double) * sizes[8], s) != hipSuccess ||
+        hipMemsetAsync(U0, 0, sizeof(double) * sizes[5], s) != hipSuccess ||
+        hipMemsetAsync(U1, 0, sizeof(double) * sizes[6], s) != hipSuccess ||
+        hipMemsetAsync(Ft, 0, sizeof(double) * sizes[7], s) != hipSuccess ||
         hipMemsetAsync(info, 0, sizeof(int), s) != hipSuccess)
         return fail(ROM_E_DEVICE, "CP-ALS workspace clear failed");
     launch_als_unfold(N, (int)np, 0, C, U0, s);     // rows (i, j), columns k
@@ -910,27 +910,25 @@ extern "C" rom_status rom_cp_als(int32_t N, int32_t R, const double* C, double* 
     s = cs;   // every launch below (tensor_times included) goes to the capture stream
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(ROM_E_DEVICE, "CP-ALS graph capture failed to start");
-    bool copy_ok = true;
+    bool cap_ok = true;
     for (int mode = 0; mode < 3; ++mode) {
             const int a = mode == 0 ? 1 : 0, b = mode == 2 ? 1 : 2;
             launch_gram_hadamard(N, R, F[a], F[b], V, s);
-            copy_ok = ss.fork(mode) && copy_ok;
+            cap_ok = ss.fork(mode) && cap_ok;
             spd_inverse_gj(R, (int)rp, V, L, X, Vinv, info, ss.side);
-            copy_ok = ss.join_mark(mode) && copy_ok;
+            cap_ok = ss.join_mark(mode) && cap_ok;
             // right-hand side: modes 1 and 2 share T = C x_k A3 (A3 is fixed until mode 3);
             // mode 3 uses C x_j A2 over rows (i, k)
             if (mode == 0) tensor_times(U0, F[2]);
             if (mode == 2) tensor_times(U1, F[1]);
             if (mode == 0) launch_als_reduce(N, R, 1, T, F[1], Mb, (int)rp, s);       // sum_j T[(i,j)] A2[j]
             else launch_als_reduce(N, R, 0, T, F[0], Mb, (int)rp, s);                 // sum_i T[(i,.)] A1[i]
-            copy_ok = ss.join(mode) && copy_ok;
+            cap_ok = ss.join(mode) && cap_ok;
             // F[mode][i][m] = sum_k Vinv[m][k] Mb[i][k]  (V symmetric)
-            launch_gemm_f64(pl, Vinv, (long long)rp, Mb, (long long)rp, Yb, R, (int)rp, (int)npad, s);
-            if (hipMemcpyAsync(F[mode], Yb, sizeof(double) * n * r, hipMemcpyDeviceToDevice, s) != hipSuccess)
-                copy_ok = false;
+            launch_gemm_f64_rows(pl, Vinv, (long long)rp, Mb, (long long)rp, F[mode], R, (int)rp, (int)npad, N, s);
     }
     hipError_t e = hipStreamEndCapture(cs, &graph);
-    if (e == hipSuccess && !copy_ok) e = hipErrorInvalidValue;
+    if (e == hipSuccess && !cap_ok) e = hipErrorInvalidValue;
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
     for (int sw = 0; sw < sweeps && e == hipSuccess; ++sw) e = hipGraphLaunch(gexec, cs);
